@@ -1,0 +1,465 @@
+"""Pins for the CPU oracle: each checks it against something other than itself.
+
+* hand-solved instances (tests/golden/hand_examples.json, each with its
+  derivation and the paper passage it rests on);
+* brute-force enumeration of active sets on tiny instances;
+* the optimality (KKT) conditions of the Lagrangian in Section 2.1;
+* the textbook sort-based simplex projection as the special case
+  D = I, b = 1, l = 0, u = inf of (CQK) (Section 1);
+* an independent library QP solver (scipy SLSQP) on small instances;
+* closed forms: the unbounded case of eq. (CQKlambda0), constant vectors,
+  translation invariance of the simplex projection;
+* the invariants the paper proves: lam_J >= lam* (Section 2.2), Theorem 1
+  (monotone simplex Newton), Lemma 1 (lam* <= 0 for the l1 ball);
+* central finite differences for the vector-Jacobian products.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import cqk_oracle as O
+from paper_2603_15910_amd import workloads as W
+
+
+def _arr(v):
+    return np.array([float(t) if not isinstance(t, str) else float(t) for t in v])
+
+
+# ---------------------------------------------------------------------------
+# Hand-solved instances
+# ---------------------------------------------------------------------------
+def test_golden_cqk(golden):
+    for ex in golden["cqk"]:
+        args = [_arr(ex[k]) for k in "dabl"] + [_arr(ex["u"])]
+        res = O.solve_cqk(*args, ex["r"])
+        if ex.get("status") == "INFEASIBLE":
+            assert res.status == O.INFEASIBLE, ex["name"]
+            continue
+        assert res.status == O.OK, ex["name"]
+        np.testing.assert_allclose(res.x, ex["x"], rtol=0, atol=1e-14, err_msg=ex["name"])
+        assert res.unique == ex["unique"], ex["name"]
+        if ex["lam"] is not None:
+            assert abs(res.lam - ex["lam"]) <= 1e-14, ex["name"]
+
+
+def test_golden_simplex_l1_vjp(golden):
+    for ex in golden["simplex"]:
+        x, lam = O.project_simplex(ex["y"], ex["r"])
+        np.testing.assert_allclose(x, ex["x"], atol=1e-15, err_msg=ex["name"])
+        assert abs(lam - ex["lam"]) <= 1e-15
+    for ex in golden["l1"]:
+        x, lam = O.project_l1(ex["y"], ex["radius"])
+        np.testing.assert_allclose(x, ex["x"], atol=1e-15, err_msg=ex["name"])
+        assert abs(lam - ex["lam"]) <= 1e-15
+    for ex in golden["vjp"]:
+        gy, gr = O.simplex_vjp(ex["x"], ex["g"])
+        np.testing.assert_allclose(gy, ex["grad_y"], atol=1e-15)
+        assert abs(gr - ex["grad_r"]) <= 1e-15
+
+
+def test_golden_alg2_traces(golden):
+    for ex in golden["alg2"]:
+        lam, J = O.condat_lambda0(ex["y"], ex["r"])
+        assert abs(lam - ex["lam"]) <= 1e-14, ex["name"]
+        assert sorted(J) == ex["J"], ex["name"]
+
+
+def test_golden_bruteforce_agrees(golden):
+    for ex in golden["cqk"]:
+        if ex.get("status"):
+            assert O.solve_bruteforce(*[_arr(ex[k]) for k in "dablu"], ex["r"]) is None
+            continue
+        x, _ = O.solve_bruteforce(*[_arr(ex[k]) for k in "dablu"], ex["r"])
+        np.testing.assert_allclose(x, ex["x"], atol=1e-12, err_msg=ex["name"])
+
+
+# ---------------------------------------------------------------------------
+# Random tiny instances against brute force
+# ---------------------------------------------------------------------------
+def _tiny_instance(rng, n, kind):
+    d = rng.uniform(0.5, 3.0, n)
+    a = rng.uniform(-3.0, 3.0, n)
+    b = rng.uniform(0.5, 3.0, n)
+    l = rng.uniform(-2.0, 0.5, n)
+    u = l + rng.uniform(0.0, 2.0, n)
+    if kind == "int":
+        # small integers: ties between breakpoints, l == u, plateaus
+        d = rng.integers(1, 3, n).astype(float)
+        a = rng.integers(-3, 4, n).astype(float)
+        b = rng.integers(1, 3, n).astype(float)
+        l = rng.integers(-2, 1, n).astype(float)
+        u = l + rng.integers(0, 3, n).astype(float)
+    if kind == "inf":
+        mask = rng.random(n) < 0.3
+        l[mask] = -np.inf
+        mask = rng.random(n) < 0.3
+        u[mask] = np.inf
+    lo = -np.inf if np.any(np.isinf(l)) else float(np.dot(b, l))
+    hi = np.inf if np.any(np.isinf(u)) else float(np.dot(b, u))
+    lo_f = lo if math.isfinite(lo) else float(np.dot(b, np.where(np.isfinite(l), l, -5)))
+    hi_f = hi if math.isfinite(hi) else float(np.dot(b, np.where(np.isfinite(u), u, 5)))
+    if kind == "int":
+        r = float(rng.integers(int(math.floor(lo_f)), int(math.ceil(hi_f)) + 1))
+        r = min(max(r, lo), hi)
+    else:
+        r = float(rng.uniform(lo_f, hi_f))
+    return d, a, b, l, u, r
+
+
+@pytest.mark.parametrize("kind", ["real", "int", "inf"])
+def test_sort_solver_equals_bruteforce(kind):
+    rng = np.random.default_rng({"real": 1, "int": 2, "inf": 3}[kind])
+    count = 0
+    for trial in range(250):
+        n = int(rng.integers(1, 7))
+        d, a, b, l, u, r = _tiny_instance(rng, n, kind)
+        res = O.solve_cqk(d, a, b, l, u, r)
+        bf = O.solve_bruteforce(d, a, b, l, u, r)
+        if bf is None:
+            assert res.status == O.INFEASIBLE, (trial, d, a, b, l, u, r)
+            continue
+        assert res.status == O.OK, (trial, res.status)
+        np.testing.assert_allclose(res.x, bf[0], rtol=0, atol=1e-9, err_msg=str(trial))
+        count += 1
+    assert count > 150
+
+
+def test_bruteforce_n10_few():
+    rng = np.random.default_rng(11)
+    for _ in range(3):
+        d, a, b, l, u, r = _tiny_instance(rng, 9, "real")
+        res = O.solve_cqk(d, a, b, l, u, r)
+        x, _ = O.solve_bruteforce(d, a, b, l, u, r)
+        np.testing.assert_allclose(res.x, x, atol=1e-9)
+
+
+def test_sort_solver_matches_scipy_qp():
+    opt = pytest.importorskip("scipy.optimize")
+    rng = np.random.default_rng(5)
+    for _ in range(8):
+        n = 6
+        d, a, b, l, u, r = _tiny_instance(rng, n, "real")
+        res = O.solve_cqk(d, a, b, l, u, r)
+        sol = opt.minimize(lambda x: 0.5 * np.dot(d * x, x) - np.dot(a, x),
+                           x0=np.clip(np.zeros(n), l, u),
+                           jac=lambda x: d * x - a,
+                           bounds=list(zip(l, u)),
+                           constraints=[{"type": "eq", "fun": lambda x: np.dot(b, x) - r,
+                                         "jac": lambda x: b}],
+                           method="SLSQP", options={"ftol": 1e-14, "maxiter": 500})
+        assert sol.success
+        np.testing.assert_allclose(res.x, sol.x, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# KKT and closed forms at larger n
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("gen,n", [("uniform", 1000), ("uniform", 100000),
+                                   ("correlated", 20000), ("paper_unc", 5000),
+                                   ("paper_weak", 5000), ("paper_cor", 5000)])
+def test_sort_solver_kkt(gen, n):
+    inst = {"uniform": lambda: W.cqk_uniform(n, 1),
+            "correlated": lambda: W.cqk_correlated(n, 2),
+            "paper_unc": lambda: W.cqk_paper(n, 3, "uncorrelated"),
+            "paper_weak": lambda: W.cqk_paper(n, 4, "weak"),
+            "paper_cor": lambda: W.cqk_paper(n, 5, "correlated")}[gen]()
+    res = O.solve_cqk(inst["d"], inst["a"], inst["b"], inst["l"], inst["u"], inst["r"])
+    assert res.status == O.OK
+    k = O.kkt_residuals(res.x, res.lam, inst["d"], inst["a"], inst["b"], inst["l"], inst["u"], inst["r"])
+    assert k["bound"] == 0.0
+    assert k["feas_rel"] < 1e-14, k
+    assert k["stat_rel"] < 1e-13, k
+
+
+def test_unbounded_is_lambda0_formula():
+    rng = np.random.default_rng(8)
+    n = 500
+    d = rng.uniform(1, 10, n)
+    a = rng.uniform(-10, 10, n)
+    b = rng.uniform(1, 10, n)
+    l = np.full(n, -np.inf)
+    u = np.full(n, np.inf)
+    r = 17.0
+    res = O.solve_cqk(d, a, b, l, u, r)
+    s = math.fsum(b * a / d)
+    q = math.fsum(b * b / d)
+    lam = (r - s) / q
+    assert abs(res.lam - lam) <= 1e-13 * abs(lam)
+    np.testing.assert_allclose(res.x, (a + lam * b) / d, rtol=1e-13)
+
+
+def test_sort_solver_on_simplex_equals_textbook():
+    for dist in ("normal", "uniform", "normal_small"):
+        y = W.simplex_input(20000, 3, dist, np.float64)
+        n = y.size
+        res = O.solve_cqk(np.ones(n), y, np.ones(n), np.zeros(n), np.full(n, np.inf), 1.0)
+        x, lam = O.project_simplex(y, 1.0)
+        np.testing.assert_allclose(res.x, x, rtol=0, atol=1e-13)
+        assert abs(res.lam - lam) <= 1e-13 * max(1.0, abs(lam))
+
+
+def test_infeasible_and_invalid():
+    n = 4
+    one = np.ones(n)
+    assert O.solve_cqk(one, one, one, np.zeros(n), one, 4.5).status == O.INFEASIBLE
+    assert O.solve_cqk(one, one, one, np.zeros(n), one, -0.1).status == O.INFEASIBLE
+    assert O.solve_cqk(one, one, one, np.zeros(n), one, 4.0).status == O.OK
+    bad_d = one.copy(); bad_d[1] = 0
+    assert O.solve_cqk(bad_d, one, one, np.zeros(n), one, 1).status == O.INVALID_ARG
+    bad_b = one.copy(); bad_b[2] = -1
+    assert O.solve_cqk(one, one, bad_b, np.zeros(n), one, 1).status == O.INVALID_ARG
+    bad_l = np.zeros(n); bad_l[0] = 2
+    assert O.solve_cqk(one, one, one, bad_l, one, 1).status == O.INVALID_ARG
+    nan_a = one.copy(); nan_a[3] = np.nan
+    assert O.solve_cqk(one, nan_a, one, np.zeros(n), one, 1).status == O.INVALID_ARG
+    assert O.solve_cqk(one, one, one, np.zeros(n), one, np.inf).status == O.INVALID_ARG
+    e = np.zeros(0)
+    assert O.solve_cqk(e, e, e, e, e, 0.0).status == O.OK
+    assert O.solve_cqk(e, e, e, e, e, 1.0).status == O.INFEASIBLE
+
+
+# ---------------------------------------------------------------------------
+# Simplex / l1
+# ---------------------------------------------------------------------------
+def test_simplex_closed_forms():
+    rng = np.random.default_rng(4)
+    assert O.project_simplex([3.7], 2.0)[0][0] == 2.0
+    y = rng.dirichlet(np.ones(50)) * 3.0
+    x, lam = O.project_simplex(y, 3.0)
+    np.testing.assert_allclose(x, y, atol=1e-14)
+    assert abs(lam) < 1e-14
+    y = rng.standard_normal(300)
+    x1, _ = O.project_simplex(y, 1.0)
+    x2, _ = O.project_simplex(y + 5.25, 1.0)
+    np.testing.assert_allclose(x1, x2, atol=1e-13)
+    perm = rng.permutation(300)
+    x3, _ = O.project_simplex(y[perm], 1.0)
+    np.testing.assert_allclose(x3, x1[perm], atol=0)
+    x0, _ = O.project_simplex(y, 0.0)
+    assert np.all(x0 == 0)
+
+
+def test_simplex_is_projection():
+    """Variational inequality of a Euclidean projection onto a convex set:
+    (y - x)^T (z - x) <= 0 for every z in the simplex."""
+    rng = np.random.default_rng(9)
+    y = rng.standard_normal(64)
+    x, _ = O.project_simplex(y, 1.0)
+    assert abs(x.sum() - 1) < 1e-14 and np.all(x >= 0)
+    for _ in range(200):
+        z = rng.dirichlet(np.full(64, 0.3))
+        assert np.dot(y - x, z - x) <= 1e-12
+
+
+def test_l1_properties():
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal(5000)
+    x, lam = O.project_l1(y, 10.0)
+    assert lam <= 0                                     # Lemma 1
+    assert abs(np.abs(x).sum() - 10.0) < 1e-11
+    assert np.all(np.sign(x)[x != 0] == np.sign(y)[x != 0])
+    np.testing.assert_allclose(x, np.sign(y) * np.maximum(np.abs(y) + lam, 0), atol=1e-14)
+    y0 = y.copy(); y0[:100] = 0.0
+    x0, _ = O.project_l1(y0, 10.0)
+    assert np.all(x0[:100] == 0)
+    xin, lin = O.project_l1(y * 1e-5, 10.0)
+    np.testing.assert_array_equal(xin, y * 1e-5)
+    assert lin == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 2 and eq. (lambdaJ)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dist", ["normal", "uniform", "normal_small"])
+def test_condat_lambda0_invariants(dist):
+    y = W.simplex_input(4000, 21, dist, np.float64)
+    x, lam_star = O.project_simplex(y, 1.0)
+    lam0, J = O.condat_lambda0(y, 1.0)
+    assert abs(lam0 - O.lambda_J(y, 1.0, J)) <= 1e-12 * max(1, abs(lam0))
+    assert lam0 >= lam_star - 1e-13
+    fixed = np.setdiff1d(np.arange(y.size), J)
+    assert np.all(x[fixed] == 0)
+    # chunked runs (the parallel form of Section 4): every chunk's J is a
+    # valid J, and so is their union
+    for chunk in (7, 64, 333):
+        Ju = []
+        for s in range(0, y.size, chunk):
+            lc, Jc = O.condat_lambda0(y, 1.0, I=range(s, min(s + chunk, y.size)))
+            assert lc >= lam_star - 1e-13
+            assert np.all(x[np.setdiff1d(np.arange(s, min(s + chunk, y.size)), Jc)] == 0)
+            Ju += Jc
+        assert O.lambda_J(y, 1.0, Ju) >= lam_star - 1e-13
+
+
+def test_condat_lambda0_l1():
+    y = W.simplex_input(3000, 22, "normal", np.float64)
+    y[::10] = 0.0
+    x, lam_star = O.project_l1(y, 1.0)
+    lam0, J = O.condat_lambda0(y, 1.0, l1=True)
+    assert lam0 >= lam_star - 1e-13
+    assert all(y[j] != 0 for j in J)
+    fixed = np.setdiff1d(np.arange(y.size), J)
+    assert np.all(x[fixed] == 0)
+
+
+def test_lambda_J_on_optimal_support_is_lambda_star():
+    for dist in ("normal", "uniform"):
+        y = W.simplex_input(5000, 23, dist, np.float64)
+        x, lam_star = O.project_simplex(y, 1.0)
+        S = np.nonzero(x > 0)[0]
+        assert abs(O.lambda_J(y, 1.0, S) - lam_star) <= 1e-13 * max(1, abs(lam_star))
+
+
+def test_slopes_match_one_sided_differences():
+    inst = W.cqk_uniform(2000, 17)
+    args = [inst[k] for k in "dablu"]
+    lbar, ubar = O.breakpoints(*args)
+    bps = np.sort(np.concatenate([lbar, ubar]))
+    for lam in (-3.0, -0.7, 0.0, 0.4, 2.5):
+        gap = np.min(np.abs(bps - lam))
+        h = 0.25 * gap
+        sp, sm = O.phi_slopes(lam, *args)
+        fp = (O.phi(lam + h, *args) - O.phi(lam, *args)) / h
+        fm = (O.phi(lam, *args) - O.phi(lam - h, *args)) / h
+        assert abs(sp - fp) <= 1e-6 * max(1, sp)
+        assert abs(sm - fm) <= 1e-6 * max(1, sm)
+    # at a breakpoint the two sides differ by that index's b^2/d
+    i = 5
+    lam = float(lbar[i])
+    sp, sm = O.phi_slopes(lam, *args)
+    w = inst["b"][i] ** 2 / inst["d"][i]
+    assert abs((sp - sm) - w) <= 1e-9 * max(1, sp)
+
+
+def test_lambda_J_upper_bound_random_sets():
+    rng = np.random.default_rng(12)
+    y = rng.standard_normal(200)
+    _, lam_star = O.project_simplex(y, 1.0)
+    for _ in range(300):
+        J = rng.choice(200, size=int(rng.integers(1, 200)), replace=False)
+        assert O.lambda_J(y, 1.0, J) >= lam_star - 1e-13
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 4 (Theorem 1) and Algorithm 1
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("dist", ["normal", "uniform", "normal_small"])
+@pytest.mark.parametrize("start", ["zero", "formula", "condat"])
+def test_newton_simplex_theorem1(dist, start):
+    y = W.simplex_input(20000, 31, dist, np.float64)
+    x_ref, lam_star = O.project_simplex(y, 1.0)
+    lam0 = {"zero": 0.0, "formula": (1.0 - y.sum()) / y.size,
+            "condat": O.condat_lambda0(y, 1.0)[0]}[start]
+    lam, tr = O.newton_simplex(y, 1.0, lam0)
+    lams = [t["lam"] for t in tr]
+    for k in range(1, len(tr) - 1):
+        assert tr[k]["phi"] > 1.0                      # item 4
+        assert tr[k]["cminus"] > 0                     # item 4
+        assert lams[k + 1] <= lams[k]                  # item 3
+        assert lams[k + 1] >= lam_star - 1e-12         # item 3
+    x = np.maximum(y + lam, 0)
+    np.testing.assert_allclose(x, x_ref, atol=1e-12)
+    assert len(tr) < 40
+    # every step from k >= 1 lands on lam_J of the current free set
+    # (eq. (lambdaJ) applied to J_k = {y + lam_k > 0})
+    for k in range(1, len(tr) - 1):
+        Jk = np.nonzero(y + lams[k] > 0)[0]
+        assert abs(lams[k + 1] - O.lambda_J(y, 1.0, Jk)) <= 1e-12 * max(1, abs(lams[k + 1]))
+
+
+@pytest.mark.parametrize("gen", ["uniform", "correlated", "paper_unc"])
+def test_newton_cqk_converges_to_sort_solution(gen):
+    n = 20000
+    inst = {"uniform": W.cqk_uniform, "correlated": W.cqk_correlated,
+            "paper_unc": lambda n, s: W.cqk_paper(n, s, "uncorrelated")}[gen](n, 41)
+    args = [inst[k] for k in "dablu"]
+    ref = O.solve_cqk(*args, inst["r"])
+    st, lam, tr = O.newton_cqk(*args, inst["r"], lam0=0.0)
+    assert st == O.OK
+    x = O.x_of_lambda(lam, *args)
+    scale = max(np.max(np.abs(ref.x)), np.max(np.abs(inst["a"] / inst["d"])))
+    assert np.max(np.abs(x - ref.x)) <= 1e-10 * scale
+    assert len(tr) <= 15
+    # the bracket always contains lam*
+    for t in tr:
+        assert t["lo"] <= ref.lam + 1e-12 and t["hi"] >= ref.lam - 1e-12
+
+
+def test_newton_cqk_breakpoint_and_infeasible():
+    # All variables start clamped at lam = 0 so both slopes are zero and the
+    # breakpoint branch of Algorithm 1 is taken.
+    d = np.ones(3); a = np.array([-5.0, -6.0, -7.0]); b = np.ones(3)
+    l = np.zeros(3); u = np.ones(3)
+    st, lam, tr = O.newton_cqk(d, a, b, l, u, 1.5, lam0=0.0)
+    assert st == O.OK
+    assert tr[0].get("kind") == "breakpoint"
+    np.testing.assert_allclose(O.x_of_lambda(lam, d, a, b, l, u), O.solve_cqk(d, a, b, l, u, 1.5).x,
+                               atol=1e-12)
+    st, _, _ = O.newton_cqk(d, a, b, l, u, 3.5, lam0=0.0)
+    assert st == O.INFEASIBLE
+
+
+# ---------------------------------------------------------------------------
+# Vector-Jacobian products against finite differences
+# ---------------------------------------------------------------------------
+def test_simplex_vjp_finite_differences():
+    rng = np.random.default_rng(13)
+    for trial in range(6):
+        n = int(rng.integers(5, 60))
+        y = 3.0 * rng.standard_normal(n)
+        x, lam = O.project_simplex(y, 1.0)
+        if np.min(np.abs(y + lam)) < 1e-4:
+            continue
+        g = rng.standard_normal(n)
+        gy, gr = O.simplex_vjp(x, g)
+        h = 1e-6
+        fd = np.empty(n)
+        for i in range(n):
+            e = np.zeros(n); e[i] = h
+            fd[i] = (np.dot(g, O.project_simplex(y + e, 1.0)[0])
+                     - np.dot(g, O.project_simplex(y - e, 1.0)[0])) / (2 * h)
+        np.testing.assert_allclose(gy, fd, atol=1e-8 * max(1, np.max(np.abs(g))))
+        fdr = (np.dot(g, O.project_simplex(y, 1.0 + h)[0])
+               - np.dot(g, O.project_simplex(y, 1.0 - h)[0])) / (2 * h)
+        assert abs(gr - fdr) <= 1e-8 * max(1, np.max(np.abs(g)))
+
+
+def test_cqk_vjp_finite_differences():
+    rng = np.random.default_rng(14)
+    inst = W.cqk_uniform(40, 15)
+    d, a, b, l, u, r = (inst[k] for k in "dablu") if False else (inst["d"], inst["a"], inst["b"], inst["l"], inst["u"], inst["r"])
+    res = O.solve_cqk(d, a, b, l, u, r)
+    g = rng.standard_normal(40)
+    ga, gr = O.cqk_vjp(res.x, g, d, b, l, u)
+    h = 1e-6
+    fd = np.empty(40)
+    for i in range(40):
+        e = np.zeros(40); e[i] = h
+        fd[i] = (np.dot(g, O.solve_cqk(d, a + e, b, l, u, r).x)
+                 - np.dot(g, O.solve_cqk(d, a - e, b, l, u, r).x)) / (2 * h)
+    np.testing.assert_allclose(ga, fd, atol=1e-7)
+    fdr = (np.dot(g, O.solve_cqk(d, a, b, l, u, r + h).x)
+           - np.dot(g, O.solve_cqk(d, a, b, l, u, r - h).x)) / (2 * h)
+    assert abs(gr - fdr) < 1e-7
+
+
+def test_vjp_simplex_matches_cqk_vjp_special_case():
+    rng = np.random.default_rng(16)
+    y = rng.standard_normal(100)
+    x, _ = O.project_simplex(y, 1.0)
+    g = rng.standard_normal(100)
+    n = 100
+    ga1, gr1 = O.simplex_vjp(x, g)
+    ga2, gr2 = O.cqk_vjp(x, g, np.ones(n), np.ones(n), np.zeros(n), np.full(n, np.inf))
+    np.testing.assert_allclose(ga1, ga2, atol=1e-14)
+    assert abs(gr1 - gr2) < 1e-14
+
+
+def test_batched_rowwise():
+    off, y = W.batched_simplex_input(20, 4, 300, 3, dtype=np.float64)
+    x, lam = O.project_simplex_batched(y, off, 1.0)
+    for s in range(20):
+        xs, ls = O.project_simplex(y[off[s]:off[s + 1]], 1.0)
+        np.testing.assert_array_equal(x[off[s]:off[s + 1]], xs)
+        assert lam[s] == ls
