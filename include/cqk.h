@@ -1,0 +1,198 @@
+/*
+ * cqk.h -- C ABI of libcqk, an MI355X (gfx950) library for the continuous
+ * quadratic knapsack problem and its simplex / l1-ball special cases.
+ *
+ * Problem (Secchin & Silva, "Parallel Newton methods for the continuous
+ * quadratic knapsack problem", Section 1, eq. (CQK)):
+ *
+ *     min_x 1/2 x^T D x - a^T x   s.t.  b^T x = r,  l <= x <= u,
+ *
+ * with D = diag(d), d_i > 0, b_i > 0 (the paper assumes b > 0 throughout),
+ * l_i <= u_i; bounds may be -inf / +inf.  The solver is the semismooth Newton
+ * method on the dual equation phi(lam) = b^T x(lam) = r (Section 2.1,
+ * eq. (xopt), eq. (opt), eq. (phideriv), Algorithm 1), with variable fixing
+ * (Section 2.2) done as compaction of the indices the Newton bracket has
+ * resolved, and the stopping criteria of Section 5.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is a DEVICE pointer owned by the caller, contiguous,
+ *   with element i at ptr[i], 16-byte aligned (INVALID_ARG otherwise; the
+ *   kernels use 16-byte vector loads).  Outputs must not alias inputs.
+ * - Work is enqueued on the context's HIP stream (cqk_create / cqk_set_stream)
+ *   and is ordered with the caller's other work on that stream.
+ * - Errors are returned as cqk_status; nothing aborts or throws across the
+ *   ABI.  Host-side argument errors return before anything is enqueued.
+ * - With opts->sync != 0 (the default) the call waits for the result and
+ *   fills *info.  Outputs are then final.
+ * - On any status other than CQK_OK and CQK_NOT_CONVERGED the contents of the
+ *   output array are unspecified.  CQK_NOT_CONVERGED writes x(lam_last).
+ * - The context owns a device workspace that grows on demand (hipMalloc) and
+ *   is reused between calls; cqk_reserve() grows it ahead of time.
+ * - A context is not thread safe; use one context per host thread.
+ */
+#ifndef CQK_H
+#define CQK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum cqk_status {
+  CQK_OK = 0,
+  CQK_INFEASIBLE = 1,     /* r outside [b^T l, b^T u] (Algorithm 1 exits) */
+  CQK_INVALID_ARG = 2,    /* bad argument or input data (see each call) */
+  CQK_NOT_CONVERGED = 3,  /* max_iter reached; x = x(lam_last) written */
+  CQK_DEVICE_ERROR = 4,   /* a HIP runtime call failed */
+  CQK_NO_MEMORY = 5       /* workspace allocation failed */
+} cqk_status;
+
+/* Initial multiplier (Section 2.1 eq. (CQKlambda0); Section 3.1 Alg. 2). */
+typedef enum cqk_lambda0_mode {
+  CQK_LAMBDA0_ZERO = 0,     /* lam_0 = 0 */
+  CQK_LAMBDA0_FORMULA = 1,  /* lam_0 = (r - s)/q over all indices, eq. (CQKlambda0) */
+  CQK_LAMBDA0_CONDAT = 2,   /* simplex / l1 only: Algorithm 2 run per thread
+                               chunk, merged by eq. (lambdaJ) (Section 4) */
+  CQK_LAMBDA0_USER = 3      /* lam_0 = opts->lambda0_user */
+} cqk_lambda0_mode;
+
+typedef enum cqk_compaction {
+  CQK_COMPACT_OFF = 0,      /* every pass reads all n indices (the paper's GPU form) */
+  CQK_COMPACT_AUTO = 1,     /* compact when the predicted survivors are
+                               <= compact_theta times the current set */
+  CQK_COMPACT_ALWAYS = 2    /* compact whenever the bracket resolves an index */
+} cqk_compaction;
+
+typedef enum cqk_accum {
+  CQK_ACCUM_DEFAULT = 0,    /* f64 inputs: f64; f32 inputs: f64 */
+  CQK_ACCUM_F32 = 1,        /* f32 inputs only: f32 values and sums, integer counts */
+  CQK_ACCUM_F64 = 2
+} cqk_accum;
+
+typedef struct cqk_opts {
+  int32_t lambda0_mode;     /* cqk_lambda0_mode; default ZERO (CONDAT for simplex/l1) */
+  double lambda0_user;      /* used with CQK_LAMBDA0_USER */
+  int32_t max_iter;         /* Newton iterations (evaluations of phi); default 100 */
+  double tol;               /* <= 0: eps^(3/4) of the working type (Section 5) */
+  int32_t compaction;       /* cqk_compaction; default AUTO */
+  double compact_theta;     /* <= 0: library default */
+  int32_t accum;            /* cqk_accum */
+  int32_t sync;             /* 1 (default): wait and fill *info */
+  int32_t trace;            /* 1: record one cqk_trace_rec per pass */
+  int32_t timing;           /* 1: time every pass kernel with HIP events */
+} cqk_opts;
+
+typedef struct cqk_info {
+  int32_t status;           /* cqk_status of the solve */
+  int32_t iterations;       /* evaluations of phi (Newton iterations) */
+  int32_t passes;           /* kernel passes over the data, incl. breakpoint passes */
+  int32_t stop_reason;      /* 0 none, 1/2/3 = stopping criterion of Section 5,
+                               4 = exact stop (phi(lam) = r or free set fixed),
+                               5 = trivial case (empty, r = 0, inside l1 ball) */
+  double lambda;            /* multiplier x was evaluated at */
+  double lambda0;           /* initial multiplier actually used */
+  double residual;          /* |b^T x - r| of the returned x (device sum) */
+  double abs_bx;            /* sum_i |b_i x_i| of the returned x */
+  int64_t n_free;           /* #{l_i < x_i < u_i} (simplex: #{x_i > 0}) */
+  int64_t n_after_init;     /* simplex/l1 with CONDAT: survivors of Alg. 2 */
+  double pass_bytes;        /* algorithmic bytes of the Newton/init passes */
+  double pass_ms;           /* their summed kernel time (opts.timing = 1) */
+  double finalize_bytes;    /* algorithmic bytes of the x-writing pass */
+  double finalize_ms;       /* its kernel time (opts.timing = 1) */
+} cqk_info;
+
+/* One record per kernel pass (opts.trace = 1). */
+typedef struct cqk_trace_rec {
+  int32_t iter;             /* Newton iteration the pass belongs to */
+  int32_t kind;             /* 0 init, 1 evaluate phi, 2 breakpoint search,
+                               3 Newton step taken, 4 secant, 5 breakpoint step */
+  int32_t compacted;        /* 1 if this pass wrote a compacted set */
+  int32_t source;           /* 0 original arrays, 1/2 compacted buffers */
+  double lam;               /* multiplier evaluated by the pass */
+  double phi;               /* phi(lam) */
+  double slope;             /* slope used for the step (phi'_+ or phi'_-) */
+  double lo, hi;            /* Newton bracket after the pass */
+  int64_t n_in;             /* indices read by the pass */
+  int64_t n_out;            /* indices written (compaction survivors) */
+} cqk_trace_rec;
+
+typedef struct cqk_ctx cqk_ctx;
+
+/* Create a context bound to `hip_stream` (a hipStream_t; NULL = the null
+ * stream) on the current HIP device.  Returns CQK_DEVICE_ERROR if no device
+ * is usable. */
+cqk_status cqk_create(cqk_ctx** ctx, void* hip_stream);
+void cqk_destroy(cqk_ctx* ctx);
+cqk_status cqk_set_stream(cqk_ctx* ctx, void* hip_stream);
+/* Grow the workspace for solves of up to max_n indices and batched calls of
+ * up to max_seg rows. */
+cqk_status cqk_reserve(cqk_ctx* ctx, int64_t max_n, int32_t max_seg);
+const char* cqk_status_string(int32_t status);
+void cqk_default_opts(cqk_opts* opts);
+/* Copy up to `cap` trace records of the last call into host memory `out`;
+ * *count receives the number recorded. */
+cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count);
+
+/* General CQK (Section 1 eq. (CQK), Algorithm 1).
+ * d, a, b, l, u: n inputs each; x: n outputs.  r: right-hand side.
+ * INVALID_ARG: n < 0, a null pointer with n > 0, non-finite r, or (found on
+ * the device in the first pass) d_i <= 0, b_i <= 0, l_i > u_i, l_i = +inf,
+ * u_i = -inf, or a NaN / infinite value in d, a, b.
+ * INFEASIBLE: r outside [b^T l, b^T u].  n = 0: OK iff r = 0. */
+cqk_status cqk_solve_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                         const double* b, const double* l, const double* u, double r,
+                         double* x, const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_solve_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                         const float* b, const float* l, const float* u, double r,
+                         float* x, const cqk_opts* opts, cqk_info* info);
+
+/* Projection onto the r-simplex {x >= 0, sum x = r} (Section 1 (proj_Delta),
+ * Section 3 Algorithm 4 with Algorithm 2 as the start).
+ * y: n inputs; x: n outputs.  INVALID_ARG: n < 0, null pointers, r < 0 or
+ * non-finite, a NaN/inf in y (device check); n = 0 with r > 0 is INFEASIBLE;
+ * r = 0 gives x = 0. */
+cqk_status cqk_project_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r,
+                                   float* x, const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r,
+                                   double* x, const cqk_opts* opts, cqk_info* info);
+
+/* Projection onto the l1 ball {x : sum |x_i| <= radius} (Section 3.2,
+ * Lemma 1): x = y if y is inside, else sgn(y) * P_Delta(|y|).  Same errors
+ * as the simplex call, with `radius` for r. */
+cqk_status cqk_project_l1_f32(cqk_ctx* ctx, int64_t n, const float* y, double radius,
+                              float* x, const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_l1_f64(cqk_ctx* ctx, int64_t n, const double* y, double radius,
+                              double* x, const cqk_opts* opts, cqk_info* info);
+
+/* Many simplex projections in one launch: row s is y[offsets[s] ..
+ * offsets[s+1]) (Section 3 Algorithms 2 and 4 applied per row).
+ * offsets: int64[nseg+1] DEVICE array, non-decreasing, offsets[0] = 0.
+ * r: DEVICE float64[nseg] radii, or NULL to use r_scalar for every row.
+ * lambda_out: optional DEVICE float64[nseg], the row multipliers.
+ * nfree_out: optional DEVICE int32[nseg], #{x_i > 0} per row.
+ * INVALID_ARG: nseg < 0, null y/x/offsets with nseg > 0, r_scalar < 0 or
+ * non-finite (when r is NULL); on the device, a row radius < 0 or NaN marks
+ * that row's lambda_out as NaN and its x as 0 and sets the call status.
+ * An empty row with r > 0 is infeasible and is reported the same way. */
+cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                           const float* y, const double* r, double r_scalar,
+                                           float* x, double* lambda_out, int32_t* nfree_out,
+                                           const cqk_opts* opts, cqk_info* info);
+
+/* Vector-Jacobian product of the batched simplex projection w.r.t. y and r
+ * on each row's support S = {x_i > 0} (derived from eq. (lambdaJ)):
+ *   grad_y_i = [i in S] (g_i - mean_S g),   grad_r[s] = mean_S g.
+ * x: forward output, g: upstream gradient, grad_y: output (same layout);
+ * grad_r: optional DEVICE float64[nseg]. */
+cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
+                                                    const int64_t* offsets, const float* x,
+                                                    const float* g, float* grad_y,
+                                                    double* grad_r, const cqk_opts* opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CQK_H */

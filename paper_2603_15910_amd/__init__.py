@@ -1,7 +1,367 @@
 """MI355X-native CQK / simplex / l1 projection library (HIP, gfx950).
 
 The compute path lives in the HIP shared library ``libcqk.so`` (built from
-``csrc/``); this package is a thin ctypes binding over its C ABI.  The library
-is loaded on first use and a missing build raises an error: there is no CPU
-fallback.
+``csrc/`` by ``paper_2603_15910_amd.build``).  This package is a thin binding
+over its C ABI (``include/cqk.h``):
+
+* the C entry points under their own names (``cqk_solve_f64`` ...), taking
+  integer device pointers, exactly as declared in the header;
+* ``Context`` and module-level helpers that take torch tensors on the GPU and
+  pass ``data_ptr()`` and torch's current HIP stream;
+* ``SimplexProjection``, a ``torch.autograd.Function`` whose forward and
+  backward are the batched HIP kernels.
+
+The library is loaded on first use; a missing build raises
+``CqkLibraryMissing``.  There is no CPU fallback.
 """
+from __future__ import annotations
+
+import ctypes as C
+import threading
+
+from . import _lib as L
+from ._lib import (CQK_DEVICE_ERROR, CQK_INFEASIBLE, CQK_INVALID_ARG, CQK_NO_MEMORY,
+                   CQK_NOT_CONVERGED, CQK_OK, STATUS_NAMES, CqkLibraryMissing, cqk_info,
+                   cqk_opts, cqk_trace_rec)
+
+__all__ = [
+    "CQK_OK", "CQK_INFEASIBLE", "CQK_INVALID_ARG", "CQK_NOT_CONVERGED", "CQK_DEVICE_ERROR",
+    "CQK_NO_MEMORY", "CqkError", "CqkLibraryMissing", "Context", "solve", "project_simplex",
+    "project_l1", "project_simplex_batched", "project_simplex_batched_backward",
+    "SimplexProjection", "lib",
+]
+
+
+def lib():
+    return L.load()
+
+
+class CqkError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}")
+
+
+# ---------------------------------------------------------------------------
+# The C entry points under their own names (pointer-level marshalling only)
+# ---------------------------------------------------------------------------
+def cqk_create(stream: int = 0) -> int:
+    h = C.c_void_p()
+    st = lib().cqk_create(C.byref(h), C.c_void_p(stream))
+    if st != CQK_OK:
+        raise CqkError(st, "cqk_create")
+    return h.value
+
+
+def cqk_destroy(ctx: int) -> None:
+    lib().cqk_destroy(C.c_void_p(ctx))
+
+
+def cqk_set_stream(ctx: int, stream: int) -> int:
+    return lib().cqk_set_stream(C.c_void_p(ctx), C.c_void_p(stream))
+
+
+def cqk_reserve(ctx: int, max_n: int, max_seg: int) -> int:
+    return lib().cqk_reserve(C.c_void_p(ctx), max_n, max_seg)
+
+
+def cqk_status_string(status: int) -> str:
+    return lib().cqk_status_string(status).decode()
+
+
+def cqk_default_opts() -> cqk_opts:
+    o = cqk_opts()
+    lib().cqk_default_opts(C.byref(o))
+    return o
+
+
+def cqk_last_trace(ctx: int, cap: int = 512):
+    buf = (cqk_trace_rec * cap)()
+    cnt = C.c_int32(0)
+    lib().cqk_last_trace(C.c_void_p(ctx), buf, cap, C.byref(cnt))
+    return [buf[i].as_dict() for i in range(min(cap, cnt.value))]
+
+
+def _call(name, *args):
+    return getattr(lib(), name)(*args)
+
+
+def cqk_solve_f64(ctx, n, d, a, b, l, u, r, x, opts=None, info=None):
+    return _call("cqk_solve_f64", C.c_void_p(ctx), n, d, a, b, l, u, r, x,
+                 C.byref(opts) if opts is not None else None,
+                 C.byref(info) if info is not None else None)
+
+
+def cqk_solve_f32(ctx, n, d, a, b, l, u, r, x, opts=None, info=None):
+    return _call("cqk_solve_f32", C.c_void_p(ctx), n, d, a, b, l, u, r, x,
+                 C.byref(opts) if opts is not None else None,
+                 C.byref(info) if info is not None else None)
+
+
+def _proj(name, ctx, n, y, r, x, opts, info):
+    return _call(name, C.c_void_p(ctx), n, y, r, x,
+                 C.byref(opts) if opts is not None else None,
+                 C.byref(info) if info is not None else None)
+
+
+def cqk_project_simplex_f32(ctx, n, y, r, x, opts=None, info=None):
+    return _proj("cqk_project_simplex_f32", ctx, n, y, r, x, opts, info)
+
+
+def cqk_project_simplex_f64(ctx, n, y, r, x, opts=None, info=None):
+    return _proj("cqk_project_simplex_f64", ctx, n, y, r, x, opts, info)
+
+
+def cqk_project_l1_f32(ctx, n, y, radius, x, opts=None, info=None):
+    return _proj("cqk_project_l1_f32", ctx, n, y, radius, x, opts, info)
+
+
+def cqk_project_l1_f64(ctx, n, y, radius, x, opts=None, info=None):
+    return _proj("cqk_project_l1_f64", ctx, n, y, radius, x, opts, info)
+
+
+def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out=None,
+                                    nfree_out=None, opts=None, info=None):
+    return _call("cqk_project_simplex_batched_f32", C.c_void_p(ctx), nseg, offsets, y, r,
+                 r_scalar, x, lambda_out, nfree_out,
+                 C.byref(opts) if opts is not None else None,
+                 C.byref(info) if info is not None else None)
+
+
+def cqk_project_simplex_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, grad_r=None,
+                                             opts=None):
+    return _call("cqk_project_simplex_batched_backward_f32", C.c_void_p(ctx), nseg, offsets, x,
+                 g, grad_y, grad_r, C.byref(opts) if opts is not None else None)
+
+
+# ---------------------------------------------------------------------------
+# torch-tensor helpers
+# ---------------------------------------------------------------------------
+def make_opts(lambda0=None, lambda0_user=0.0, max_iter=100, tol=0.0, compaction="auto",
+              theta=0.0, accum="default", trace=False, timing=False, simplex=False):
+    o = cqk_default_opts()
+    if lambda0 is None:
+        lambda0 = "condat" if simplex else "zero"
+    o.lambda0_mode = L.LAMBDA0[lambda0]
+    o.lambda0_user = float(lambda0_user)
+    o.max_iter = int(max_iter)
+    o.tol = float(tol)
+    o.compaction = L.COMPACTION[compaction]
+    o.compact_theta = float(theta)
+    o.accum = L.ACCUM[accum]
+    o.sync = 1
+    o.trace = 1 if trace else 0
+    o.timing = 1 if timing else 0
+    return o
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, dtype, name):
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous() or t.data_ptr() % 16:
+        raise ValueError(f"{name} must be contiguous and 16-byte aligned")
+    return t.data_ptr()
+
+
+class Context:
+    """One libcqk context (workspace + state) on one GPU."""
+
+    def __init__(self, device=None):
+        torch = _torch()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        with torch.cuda.device(self.device):
+            self.handle = cqk_create(torch.cuda.current_stream(self.device).cuda_stream)
+        self.last_info = None
+
+    def close(self):
+        if self.handle:
+            cqk_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _bind_stream(self):
+        torch = _torch()
+        cqk_set_stream(self.handle, torch.cuda.current_stream(self.device).cuda_stream)
+
+    def reserve(self, max_n, max_seg=0):
+        st = cqk_reserve(self.handle, int(max_n), int(max_seg))
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_reserve")
+
+    def trace(self):
+        return cqk_last_trace(self.handle)
+
+    def solve(self, d, a, b, l, u, r, out=None, check=True, **kw):
+        torch = _torch()
+        dt = d.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("solve takes float64 or float32 tensors")
+        n = d.numel()
+        x = out if out is not None else torch.empty_like(d)
+        ptrs = [_dev_ptr(t, dt, nm) for t, nm in zip((d, a, b, l, u, x), "dablux")]
+        opts = make_opts(**kw)
+        info = cqk_info()
+        self._bind_stream()
+        fn = cqk_solve_f64 if dt == torch.float64 else cqk_solve_f32
+        st = fn(self.handle, n, *ptrs[:5], float(r), ptrs[5], opts, info)
+        self.last_info = info.as_dict()
+        if check and st not in (CQK_OK,):
+            raise CqkError(st, "cqk_solve")
+        return x, self.last_info
+
+    def _project(self, name64, name32, y, r, out, check, kw):
+        torch = _torch()
+        x = out if out is not None else torch.empty_like(y)
+        dt = y.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("projection takes float64 or float32 tensors")
+        py = _dev_ptr(y, dt, "y")
+        px = _dev_ptr(x, dt, "x")
+        opts = make_opts(simplex=True, **kw)
+        info = cqk_info()
+        self._bind_stream()
+        fn = name64 if dt == torch.float64 else name32
+        st = fn(self.handle, y.numel(), py, float(r), px, opts, info)
+        self.last_info = info.as_dict()
+        if check and st != CQK_OK:
+            raise CqkError(st, fn.__name__)
+        return x, self.last_info
+
+    def project_simplex(self, y, r=1.0, out=None, check=True, **kw):
+        return self._project(cqk_project_simplex_f64, cqk_project_simplex_f32, y, r, out, check, kw)
+
+    def project_l1(self, y, radius=1.0, out=None, check=True, **kw):
+        return self._project(cqk_project_l1_f64, cqk_project_l1_f32, y, radius, out, check, kw)
+
+    def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
+                                nfree_out=None, check=True, **kw):
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        x = out if out is not None else torch.empty_like(y)
+        py = _dev_ptr(y, torch.float32, "y")
+        px = _dev_ptr(x, torch.float32, "x")
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        if torch.is_tensor(r):
+            pr, rs = _dev_ptr(r, torch.float64, "r"), 0.0
+        else:
+            pr, rs = None, float(r)
+        pl = _dev_ptr(lambda_out, torch.float64, "lambda_out") if lambda_out is not None else None
+        pn = _dev_ptr(nfree_out, torch.int32, "nfree_out") if nfree_out is not None else None
+        opts = make_opts(simplex=True, **kw)
+        info = cqk_info()
+        self._bind_stream()
+        st = cqk_project_simplex_batched_f32(self.handle, nseg, po, py, pr, rs, px, pl, pn,
+                                             opts, info)
+        self.last_info = info.as_dict()
+        if check and st != CQK_OK:
+            raise CqkError(st, "cqk_project_simplex_batched_f32")
+        return x, self.last_info
+
+    def project_simplex_batched_backward(self, x, g, offsets, grad_y=None, grad_r=None,
+                                         check=True, **kw):
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        gy = grad_y if grad_y is not None else torch.empty_like(g)
+        px = _dev_ptr(x, torch.float32, "x")
+        pg = _dev_ptr(g, torch.float32, "g")
+        pgy = _dev_ptr(gy, torch.float32, "grad_y")
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        pgr = _dev_ptr(grad_r, torch.float64, "grad_r") if grad_r is not None else None
+        opts = make_opts(simplex=True, **kw)
+        self._bind_stream()
+        st = cqk_project_simplex_batched_backward_f32(self.handle, nseg, po, px, pg, pgy, pgr,
+                                                      opts)
+        if check and st != CQK_OK:
+            raise CqkError(st, "cqk_project_simplex_batched_backward_f32")
+        return gy
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def default_context(device=None) -> Context:
+    torch = _torch()
+    idx = torch.cuda.current_device() if device is None else torch.device(device).index or 0
+    key = (threading.get_ident(), idx)
+    with _ctx_lock:
+        if key not in _contexts:
+            _contexts[key] = Context(idx)
+        return _contexts[key]
+
+
+def solve(d, a, b, l, u, r, **kw):
+    return default_context(d.device).solve(d, a, b, l, u, r, **kw)
+
+
+def project_simplex(y, r=1.0, **kw):
+    return default_context(y.device).project_simplex(y, r, **kw)
+
+
+def project_l1(y, radius=1.0, **kw):
+    return default_context(y.device).project_l1(y, radius, **kw)
+
+
+def project_simplex_batched(y, offsets, r=1.0, **kw):
+    return default_context(y.device).project_simplex_batched(y, offsets, r, **kw)
+
+
+def project_simplex_batched_backward(x, g, offsets, **kw):
+    return default_context(x.device).project_simplex_batched_backward(x, g, offsets, **kw)
+
+
+def _autograd_cls():
+    torch = _torch()
+
+    class _SimplexProjection(torch.autograd.Function):
+        """Batched simplex projection with a hand-written HIP backward.
+
+        forward(y, offsets, r): y float32 [N], offsets int64 [nseg+1] (GPU),
+        r a float or a float64 GPU tensor [nseg].  backward returns
+        (grad_y, None, grad_r) with grad_r per row, summed when r was a
+        Python number."""
+
+        @staticmethod
+        def forward(ctx, y, offsets, r):
+            x, _ = project_simplex_batched(y.contiguous(), offsets, r)
+            ctx.save_for_backward(x, offsets)
+            ctx.r_is_tensor = torch.is_tensor(r)
+            return x
+
+        @staticmethod
+        def backward(ctx, g):
+            x, offsets = ctx.saved_tensors
+            nseg = offsets.numel() - 1
+            grad_r = torch.empty(nseg, dtype=torch.float64, device=x.device)
+            gy = project_simplex_batched_backward(x, g.contiguous().float(), offsets,
+                                                  grad_r=grad_r)
+            gr = grad_r if ctx.r_is_tensor else None
+            return gy, None, gr
+
+    return _SimplexProjection
+
+
+class _Lazy:
+    _cls = None
+
+    def __getattr__(self, item):
+        if _Lazy._cls is None:
+            _Lazy._cls = _autograd_cls()
+        return getattr(_Lazy._cls, item)
+
+
+SimplexProjection = _Lazy()

@@ -1,0 +1,292 @@
+// extern "C" entry points of libcqk: argument checks, context and workspace
+// management, dispatch to the kernel launchers.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
+#include "../../include/cqk.h"
+#include "cqk_internal.h"
+
+namespace cqk {
+
+cqk_status hip_ok(hipError_t e) { return e == hipSuccess ? CQK_OK : CQK_DEVICE_ERROR; }
+
+cqk_status ensure_buffer(DeviceBuf& b, size_t bytes) {
+  if (bytes <= b.bytes && b.ptr) return CQK_OK;
+  if (b.ptr) {
+    if (hipFree(b.ptr) != hipSuccess) return CQK_DEVICE_ERROR;
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = bytes < 4096 ? 4096 : bytes;
+  void* p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return CQK_NO_MEMORY;
+  }
+  b.ptr = p;
+  b.bytes = want;
+  return CQK_OK;
+}
+
+cqk_status ensure_events(cqk_ctx* ctx, size_t count) {
+  while (ctx->events.size() < count) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return CQK_DEVICE_ERROR;
+    ctx->events.push_back(e);
+  }
+  return CQK_OK;
+}
+
+void fill_default_opts(cqk_opts* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->lambda0_mode = CQK_LAMBDA0_ZERO;
+  o->lambda0_user = 0.0;
+  o->max_iter = 100;
+  o->tol = 0.0;
+  o->compaction = CQK_COMPACT_AUTO;
+  o->compact_theta = 0.0;
+  o->accum = CQK_ACCUM_DEFAULT;
+  o->sync = 1;
+  o->trace = 0;
+  o->timing = 0;
+}
+
+}  // namespace cqk
+
+using namespace cqk;
+
+namespace {
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+cqk_status check_opts(const cqk_opts* in, cqk_opts* out, bool simplex) {
+  if (in) {
+    *out = *in;
+  } else {
+    fill_default_opts(out);
+    if (simplex) out->lambda0_mode = CQK_LAMBDA0_CONDAT;
+  }
+  if (out->max_iter <= 0 || out->max_iter > 200) return CQK_INVALID_ARG;
+  if (out->lambda0_mode < 0 || out->lambda0_mode > 3) return CQK_INVALID_ARG;
+  if (!simplex && out->lambda0_mode == CQK_LAMBDA0_CONDAT) return CQK_INVALID_ARG;
+  if (out->lambda0_mode == CQK_LAMBDA0_USER && !std::isfinite(out->lambda0_user))
+    return CQK_INVALID_ARG;
+  if (out->compaction < 0 || out->compaction > 2) return CQK_INVALID_ARG;
+  if (!(out->compact_theta <= 1.0) || std::isnan(out->tol)) return CQK_INVALID_ARG;
+  if (out->accum < 0 || out->accum > 2) return CQK_INVALID_ARG;
+  return CQK_OK;
+}
+
+void info_trivial(cqk_info* info, int status, double lam) {
+  if (!info) return;
+  std::memset(info, 0, sizeof(*info));
+  info->status = status;
+  info->lambda = lam;
+  info->stop_reason = 5;
+}
+
+template <typename T>
+cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T* b, const T* l,
+                        const T* u, double r, T* x, const cqk_opts* opts, cqk_info* info) {
+  if (!ctx || n < 0 || !std::isfinite(r)) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, false);
+  if (st != CQK_OK) return st;
+  if (n == 0) {
+    const int s = (r == 0.0) ? CQK_OK : CQK_INFEASIBLE;
+    info_trivial(info, s, 0.0);
+    return (cqk_status)s;
+  }
+  if (!d || !a || !b || !l || !u || !x) return CQK_INVALID_ARG;
+  if (!aligned16(d) || !aligned16(a) || !aligned16(b) || !aligned16(l) || !aligned16(u) ||
+      !aligned16(x))
+    return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_info tmp;
+  cqk_info* inf = info ? info : &tmp;
+  if constexpr (sizeof(T) == 8)
+    st = run_general_f64(ctx, n, d, a, b, l, u, r, x, o, inf);
+  else
+    st = run_general_f32(ctx, n, d, a, b, l, u, r, x, o, inf);
+  if (st != CQK_OK) return st;
+  return (cqk_status)inf->status;
+}
+
+template <typename T>
+cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, double r, T* x, bool l1,
+                          const cqk_opts* opts, cqk_info* info) {
+  if (!ctx || n < 0 || !std::isfinite(r) || r < 0.0) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, true);
+  if (st != CQK_OK) return st;
+  if (n == 0) {
+    const int s = (r == 0.0 || l1) ? CQK_OK : CQK_INFEASIBLE;
+    info_trivial(info, s, 0.0);
+    return (cqk_status)s;
+  }
+  if (!y || !x) return CQK_INVALID_ARG;
+  if (!aligned16(y) || !aligned16(x)) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_info tmp;
+  cqk_info* inf = info ? info : &tmp;
+  if constexpr (sizeof(T) == 8)
+    st = run_simplex_f64(ctx, n, y, r, x, l1, o, inf);
+  else
+    st = run_simplex_f32(ctx, n, y, r, x, l1, o, inf);
+  if (st != CQK_OK) return st;
+  return (cqk_status)inf->status;
+}
+
+}  // namespace
+
+extern "C" {
+
+cqk_status cqk_create(cqk_ctx** out, void* hip_stream) {
+  if (!out) return CQK_INVALID_ARG;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_ctx* ctx = new (std::nothrow) cqk_ctx();
+  if (!ctx) return CQK_NO_MEMORY;
+  ctx->device = dev;
+  ctx->stream = (hipStream_t)hip_stream;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    ctx->num_cus = prop.multiProcessorCount;
+  ctx->host_pinned_bytes = 64 * 1024;
+  if (hipHostMalloc(&ctx->host_pinned, ctx->host_pinned_bytes, hipHostMallocDefault) !=
+      hipSuccess) {
+    delete ctx;
+    return CQK_NO_MEMORY;
+  }
+  *out = ctx;
+  return CQK_OK;
+}
+
+void cqk_destroy(cqk_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  else hipDeviceSynchronize();
+  if (ctx->ws.ptr) hipFree(ctx->ws.ptr);
+  if (ctx->state.ptr) hipFree(ctx->state.ptr);
+  if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
+  for (hipEvent_t e : ctx->events) hipEventDestroy(e);
+  delete ctx;
+}
+
+cqk_status cqk_set_stream(cqk_ctx* ctx, void* hip_stream) {
+  if (!ctx) return CQK_INVALID_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return CQK_OK;
+}
+
+cqk_status cqk_reserve(cqk_ctx* ctx, int64_t max_n, int32_t max_seg) {
+  if (!ctx || max_n < 0 || max_seg < 0) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  // compaction buffers dominate: 2 x 4 doubles per index, plus slack for
+  // per-block padding and partial records
+  const size_t want = (size_t)max_n * 64 + (size_t)max_seg * 64 + (4u << 20);
+  cqk_status st = ensure_buffer(ctx->ws, want);
+  if (st != CQK_OK) return st;
+  return ensure_buffer(ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
+}
+
+const char* cqk_status_string(int32_t s) {
+  switch (s) {
+    case CQK_OK: return "CQK_OK";
+    case CQK_INFEASIBLE: return "CQK_INFEASIBLE";
+    case CQK_INVALID_ARG: return "CQK_INVALID_ARG";
+    case CQK_NOT_CONVERGED: return "CQK_NOT_CONVERGED";
+    case CQK_DEVICE_ERROR: return "CQK_DEVICE_ERROR";
+    case CQK_NO_MEMORY: return "CQK_NO_MEMORY";
+    default: return "CQK_UNKNOWN_STATUS";
+  }
+}
+
+void cqk_default_opts(cqk_opts* opts) {
+  if (opts) fill_default_opts(opts);
+}
+
+cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count) {
+  if (!ctx || cap < 0 || (cap > 0 && !out)) return CQK_INVALID_ARG;
+  const int32_t have = (int32_t)ctx->last_trace.size();
+  const int32_t k = cap < have ? cap : have;
+  for (int32_t i = 0; i < k; ++i) out[i] = ctx->last_trace[i];
+  if (count) *count = have;
+  return CQK_OK;
+}
+
+cqk_status cqk_solve_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                         const double* b, const double* l, const double* u, double r, double* x,
+                         const cqk_opts* opts, cqk_info* info) {
+  return solve_common<double>(ctx, n, d, a, b, l, u, r, x, opts, info);
+}
+
+cqk_status cqk_solve_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                         const float* b, const float* l, const float* u, double r, float* x,
+                         const cqk_opts* opts, cqk_info* info) {
+  return solve_common<float>(ctx, n, d, a, b, l, u, r, x, opts, info);
+}
+
+cqk_status cqk_project_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x,
+                                   const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<float>(ctx, n, y, r, x, false, opts, info);
+}
+
+cqk_status cqk_project_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r,
+                                   double* x, const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<double>(ctx, n, y, r, x, false, opts, info);
+}
+
+cqk_status cqk_project_l1_f32(cqk_ctx* ctx, int64_t n, const float* y, double radius, float* x,
+                              const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<float>(ctx, n, y, radius, x, true, opts, info);
+}
+
+cqk_status cqk_project_l1_f64(cqk_ctx* ctx, int64_t n, const double* y, double radius,
+                              double* x, const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<double>(ctx, n, y, radius, x, true, opts, info);
+}
+
+cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                           const float* y, const double* r, double r_scalar,
+                                           float* x, double* lambda_out, int32_t* nfree_out,
+                                           const cqk_opts* opts, cqk_info* info) {
+  if (!ctx || nseg < 0) return CQK_INVALID_ARG;
+  if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, true);
+  if (st != CQK_OK) return st;
+  if (nseg == 0) {
+    info_trivial(info, CQK_OK, 0.0);
+    return CQK_OK;
+  }
+  if (!offsets || !y || !x) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_info tmp;
+  cqk_info* inf = info ? info : &tmp;
+  st = run_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, o, inf);
+  if (st != CQK_OK) return st;
+  return (cqk_status)inf->status;
+}
+
+cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
+                                                    const int64_t* offsets, const float* x,
+                                                    const float* g, float* grad_y,
+                                                    double* grad_r, const cqk_opts* opts) {
+  if (!ctx || nseg < 0) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, true);
+  if (st != CQK_OK) return st;
+  if (nseg == 0) return CQK_OK;
+  if (!offsets || !x || !g || !grad_y) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return run_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, grad_r, o);
+}
+
+}  // extern "C"

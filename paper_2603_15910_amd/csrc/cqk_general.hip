@@ -1,0 +1,746 @@
+// General CQK: semismooth Newton on the dual equation phi(lam) = r.
+//
+// Paper: Section 2.1 (eq. (xopt), eq. (opt), eq. (phideriv), Algorithm 1,
+// eq. (CQKlambda0)), Section 2.2 (variable fixing), Section 4 (the pass is a
+// map over indices followed by a reduction), Section 5 (stopping criteria).
+//
+// Every pass works on the per-index form
+//     g_i(lam) = b_i x_i(lam) = min(max(c_i + lam s_i, b_i l_i), b_i u_i),
+//     c_i = b_i a_i / d_i,  s_i = b_i^2 / d_i,
+// which is eq. (xopt) multiplied by b_i > 0.  phi(lam) = sum_i g_i(lam); the
+// one-sided slopes of eq. (phideriv) sum s_i over b l <= c + lam s < b u and
+// b l < c + lam s <= b u.
+//
+// Kernels:
+//   gen_iter_kernel     one pass over the current index set + the scalar
+//                       Algorithm 1 update in the last block to finish;
+//   gen_lambda0_kernel  eq. (CQKlambda0) over all indices, with input checks;
+//   gen_finalize_kernel x(lam*) over all n indices (eq. (xopt)), b^T x.
+//
+// Compaction.  Once the Newton bracket [lo, hi] is known, an index whose
+// bound is active on the whole bracket (c + hi s <= b l, or c + lo s >= b u)
+// has the same value at every later iterate; so does an index that is free on
+// the whole bracket, whose contribution is the line c + lam s.  Such indices
+// are dropped from the pass (their contributions kept as a few scalars) and
+// the survivors are written, in the per-index form above, to a ping-pong
+// buffer: block b always owns the same region, so no grid-wide scan is needed
+// and the layout is deterministic.  In exact arithmetic the values of phi and
+// its slopes are unchanged; this is the fixing of Section 2.2 applied through
+// the bracket, plus the free-side analogue.
+#include <algorithm>
+#include <cmath>
+
+#include "cqk_device.h"
+#include "cqk_internal.h"
+
+namespace cqk {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kUnroll = 2;
+
+// Partial record: NSUM sums, then one min (BR) and one max (BL).
+enum {
+  P_P = 0,     // sum g_i(lam)
+  P_A,         // sum |g_i(lam)|
+  P_QP,        // phi'_+ part
+  P_QM,        // phi'_- part
+  P_DF,        // bounds of indices fixed in this pass
+  P_DAF,       // |bounds| of indices fixed in this pass
+  P_DC0,       // c of indices found free on the bracket
+  P_DC1,       // s of those
+  P_DA0,       // sgn * c of those
+  P_DA1,       // sgn * s of those
+  P_NIN,       // indices read
+  P_NOUT,      // indices written
+  P_PREDLO,    // survivors if lo moves to lam
+  P_PREDHI,    // survivors if hi moves to lam
+  P_BAD,       // indices failing the input checks
+  NSUM
+};
+constexpr int NPART = NSUM + 2;
+
+struct GenArgs {
+  const void* d;
+  const void* a;
+  const void* b;
+  const void* l;
+  const void* u;
+  void* x;
+  int64_t n;
+  int64_t chunk;
+  double* buf[2][4];
+  int32_t* cnt[2];
+  double* partials;
+  GenState* st;
+  cqk_trace_rec* trace;
+};
+
+struct Acc {
+  double s[NSUM];
+  double br, bl;
+};
+
+__device__ __forceinline__ void acc_init(Acc& a) {
+#pragma unroll
+  for (int i = 0; i < NSUM; ++i) a.s[i] = 0.0;
+  a.br = inf_d();
+  a.bl = -inf_d();
+}
+
+// Per-index form of the original data (eq. (xopt) times b), with the input
+// checks of Section 5.
+__device__ __forceinline__ void to_form(double d, double a, double b, double l, double u,
+                                        double& c, double& s, double& bl, double& bu,
+                                        double& bad) {
+  const double inv = 1.0 / d;
+  c = (b * a) * inv;
+  s = (b * b) * inv;
+  bl = b * l;
+  bu = b * u;
+  const bool ok = (d > 0.0) && (d < inf_d()) && (b > 0.0) && (b < inf_d()) &&
+                  (fabs(a) < inf_d()) && (l <= u) && (l < inf_d()) && (u > -inf_d());
+  bad += ok ? 0.0 : 1.0;
+}
+
+// One index of an evaluation pass.  Returns true if the index survives
+// compaction (always true when not compacting).
+template <bool COMPACT>
+__device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double bl, double bu,
+                                           double lam, double lo, double hi) {
+  const double f = fma(s, lam, c);
+  const double g = fmin(fmax(f, bl), bu);
+  acc.s[P_P] += g;
+  acc.s[P_A] += fabs(g);
+  const bool ge_l = f >= bl, gt_l = f > bl, lt_u = f < bu, le_u = f <= bu;
+  acc.s[P_QP] += (ge_l && lt_u) ? s : 0.0;
+  acc.s[P_QM] += (gt_l && le_u) ? s : 0.0;
+  acc.s[P_NIN] += 1.0;
+  const double fl = fma(s, lo, c);
+  const double fh = fma(s, hi, c);
+  const bool fix_l = fh <= bl;
+  const bool fix_u = fl >= bu;
+  // resolved under the two brackets the update can produce
+  const bool res_lo_lam = (f <= bl) || fix_u || ((fl >= bl) && le_u && (fl >= 0.0 || f <= 0.0));
+  const bool res_lam_hi = fix_l || (f >= bu) || (ge_l && (fh <= bu) && (f >= 0.0 || fh <= 0.0));
+  acc.s[P_PREDHI] += res_lo_lam ? 0.0 : 1.0;
+  acc.s[P_PREDLO] += res_lam_hi ? 0.0 : 1.0;
+  if (!COMPACT) return true;
+  if (fix_l) {
+    acc.s[P_DF] += bl;
+    acc.s[P_DAF] += fabs(bl);
+    return false;
+  }
+  if (fix_u) {
+    acc.s[P_DF] += bu;
+    acc.s[P_DAF] += fabs(bu);
+    return false;
+  }
+  if ((fl >= bl) && (fh <= bu) && (fl >= 0.0 || fh <= 0.0)) {
+    const double sg = (fl >= 0.0) ? 1.0 : -1.0;
+    acc.s[P_DC0] += c;
+    acc.s[P_DC1] += s;
+    acc.s[P_DA0] += sg * c;
+    acc.s[P_DA1] += sg * s;
+    return false;
+  }
+  return true;
+}
+
+// Closest breakpoints around lam (Algorithm 1, breakpoint steps).
+__device__ __forceinline__ void bkpt_index(Acc& acc, double c, double s, double bl, double bu,
+                                           double lam) {
+  const double lb = (bl - c) / s;
+  const double ub = (bu - c) / s;
+  if (lb > lam) acc.br = fmin(acc.br, lb);
+  if (ub < lam) acc.bl = fmax(acc.bl, ub);
+}
+
+// Sources: the caller's arrays or a compacted region.
+template <typename TIn>
+struct SrcOrig {
+  static constexpr int V = VecWidth<TIn>::value;
+  const TIn *d, *a, *b, *l, *u;
+  __device__ __forceinline__ void load(int64_t i, int64_t n, double* c, double* s, double* bl,
+                                       double* bu, double& bad) const {
+    double vd[V], va[V], vb[V], vl[V], vu[V];
+    Vec<TIn, V>::load(d, i, n, 1.0, vd);
+    Vec<TIn, V>::load(a, i, n, 0.0, va);
+    Vec<TIn, V>::load(b, i, n, 1.0, vb);
+    Vec<TIn, V>::load(l, i, n, 0.0, vl);
+    Vec<TIn, V>::load(u, i, n, 0.0, vu);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      double tb = 0.0;
+      to_form(vd[k], va[k], vb[k], vl[k], vu[k], c[k], s[k], bl[k], bu[k], tb);
+      if (i + k < n) bad += tb;
+    }
+  }
+};
+
+struct SrcForm {
+  static constexpr int V = 2;
+  const double *c, *s, *bl, *bu;
+  __device__ __forceinline__ void load(int64_t i, int64_t n, double* oc, double* os, double* obl,
+                                       double* obu, double&) const {
+    Vec<double, 2>::load(c, i, n, 0.0, oc);
+    Vec<double, 2>::load(s, i, n, 1.0, os);
+    Vec<double, 2>::load(bl, i, n, 0.0, obl);
+    Vec<double, 2>::load(bu, i, n, 0.0, obu);
+  }
+};
+
+template <typename Src, bool COMPACT>
+__device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, double hi,
+                          double* const* out, int32_t* out_cnt, Acc& acc, int* lds_i) {
+  constexpr int V = Src::V;
+  constexpr int E = kUnroll * V;
+  constexpr int64_t TILE = (int64_t)kBlock * E;
+  int64_t written = 0;
+  for (int64_t base = 0; base < count; base += TILE) {
+    double c[E], s[E], bl[E], bu[E];
+    bool keep[E];
+#pragma unroll
+    for (int w = 0; w < kUnroll; ++w) {
+      const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+      src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = w * V + k;
+        keep[e] = false;
+        if (i + k < count) keep[e] = eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi);
+      }
+    }
+    if (COMPACT) {
+      int nk = 0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) nk += keep[e] ? 1 : 0;
+      int total;
+      const int off = block_excl_scan<kBlock>(nk, lds_i, &total);
+      int64_t pos = written + off;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (keep[e]) {
+          out[0][pos] = c[e];
+          out[1][pos] = s[e];
+          out[2][pos] = bl[e];
+          out[3][pos] = bu[e];
+          ++pos;
+        }
+      }
+      written += total;
+    }
+  }
+  if (COMPACT && threadIdx.x == 0) {
+    *out_cnt = (int32_t)written;
+    acc.s[P_NOUT] += (double)written;
+  }
+}
+
+template <typename Src>
+__device__ void bkpt_pass(const Src& src, int64_t count, double lam, Acc& acc) {
+  constexpr int V = Src::V;
+  constexpr int E = kUnroll * V;
+  constexpr int64_t TILE = (int64_t)kBlock * E;
+  for (int64_t base = 0; base < count; base += TILE) {
+    double c[E], s[E], bl[E], bu[E];
+#pragma unroll
+    for (int w = 0; w < kUnroll; ++w) {
+      const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+      double dummy = 0.0;
+      src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], dummy);
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = w * V + k;
+        if (i + k < count) bkpt_index(acc, c[e], s[e], bl[e], bu[e], lam);
+      }
+    }
+  }
+}
+
+__device__ void trace_push(GenState* st, cqk_trace_rec* tr, int kind, int compacted, int source,
+                           double lam, double phi, double slope, int64_t nin, int64_t nout) {
+  if (st->ntrace < st->trace_cap) {
+    cqk_trace_rec& t = tr[st->ntrace];
+    t.iter = st->iter;
+    t.kind = kind;
+    t.compacted = compacted;
+    t.source = source;
+    t.lam = lam;
+    t.phi = phi;
+    t.slope = slope;
+    t.lo = st->lo;
+    t.hi = st->hi;
+    t.n_in = nin;
+    t.n_out = nout;
+  }
+  st->ntrace += 1;
+}
+
+__device__ void finish(GenState* st, double lamf, int reason) {
+  st->status = CQK_OK;
+  st->lam_final = lamf;
+  st->stop_reason = reason;
+}
+
+__device__ void advance(GenState* st, double next) {
+  st->lam_prev = st->lam;
+  st->lam = next;
+  st->mode = kModeEval;
+  if (st->iter >= st->max_iter) {
+    st->status = CQK_NOT_CONVERGED;
+    st->lam_final = st->lam_prev;
+  }
+}
+
+// The scalar part of Algorithm 1, run by one thread after an evaluation pass.
+__device__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
+  const double lam = st->lam;
+  const bool compacted = st->compact_next != 0;
+  const int source = st->src;
+  st->passes += 1;
+  if (t[P_BAD] > 0.0) {
+    st->status = CQK_INVALID_ARG;
+    return;
+  }
+  const double phi = (st->F + st->C0) + (lam * st->C1 + t[P_P]);
+  const double A = (st->AF + st->A0) + (lam * st->A1 + t[P_A]);
+  const double Qp = st->C1 + t[P_QP];
+  const double Qm = st->C1 + t[P_QM];
+  if (compacted) {
+    st->F += t[P_DF];
+    st->AF += t[P_DAF];
+    st->C0 += t[P_DC0];
+    st->C1 += t[P_DC1];
+    st->A0 += t[P_DA0];
+    st->A1 += t[P_DA1];
+    st->src = (source == 1) ? 2 : 1;
+    st->n_src = (int64_t)t[P_NOUT];
+  } else {
+    st->n_src = (int64_t)t[P_NIN];
+  }
+  st->compact_next = 0;
+  const double r = st->r, tol = st->tol;
+  const double res = phi - r;
+  double lo = st->lo, hi = st->hi;
+  if (res < 0.0) {
+    lo = lam;
+    st->phi_lo = phi;
+  } else if (res > 0.0) {
+    hi = lam;
+    st->phi_hi = phi;
+  }
+  st->lo = lo;
+  st->hi = hi;
+  const double slope = (res < 0.0) ? Qp : Qm;
+  trace_push(st, tr, 1, compacted ? 1 : 0, source, lam, phi, slope, (int64_t)t[P_NIN],
+             compacted ? (int64_t)t[P_NOUT] : 0);
+  st->iter += 1;
+  // Section 5 criterion 1 (and the exact stop of Algorithm 1)
+  if (res == 0.0) return finish(st, lam, 4);
+  if (fabs(res) < tol * (A + fabs(r))) return finish(st, lam, 1);
+  // compaction decision for the next evaluation pass
+  if (st->compaction != CQK_COMPACT_OFF) {
+    const double pred = (res < 0.0) ? t[P_PREDLO] : t[P_PREDHI];
+    const double ncur = (double)st->n_src;
+    st->compact_next = (st->compaction == CQK_COMPACT_ALWAYS) ? (pred < ncur)
+                                                              : (pred <= st->theta * ncur);
+  }
+  // criterion 3
+  if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, lam, 3);
+  double next;
+  bool secant = false;
+  if (slope > 0.0) {
+    const double step = res / slope;
+    if (fabs(step) < tol) return finish(st, fmin(fmax(lam - step, lo), hi), 2);  // criterion 2
+    next = lam - step;
+    secant = (res < 0.0) ? !(next < hi) : !(next > lo);
+  } else {
+    // slope zero: the closest breakpoint in the needed direction
+    st->mode = (res < 0.0) ? kModeBreakRight : kModeBreakLeft;
+    return;
+  }
+  if (secant) {
+    next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+  }
+  if (next == lam) return finish(st, lam, 2);  // criterion 2, lam_{k-1} = lam_k
+  advance(st, next);
+}
+
+__device__ void update_after_bkpt(GenState* st, const double* t, cqk_trace_rec* tr) {
+  st->passes += 1;
+  const bool right = st->mode == kModeBreakRight;
+  const double bp = right ? t[NSUM] : t[NSUM + 1];
+  trace_push(st, tr, 2, 0, st->src, st->lam, bp, 0.0, (int64_t)st->n_src, 0);
+  if (!(fabs(bp) < inf_d())) {
+    st->status = CQK_INFEASIBLE;
+    return;
+  }
+  const double lo = st->lo, hi = st->hi;
+  double next = bp;
+  if (!(next > lo && next < hi)) {
+    if (fabs(lo) < inf_d() && fabs(hi) < inf_d()) {
+      next = lo - (st->phi_lo - st->r) * (hi - lo) / (st->phi_hi - st->phi_lo);
+      if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    }
+  }
+  advance(st, next);
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const int mode = st->mode;
+  const int src = st->src;
+  const bool compact = (mode == kModeEval) && (st->compact_next != 0);
+  const double lam = st->lam, lo = st->lo, hi = st->hi;
+  const int64_t off = (int64_t)blockIdx.x * A.chunk;
+
+  __shared__ double lds[NPART * (kBlock / kWave)];
+  __shared__ double tot[NPART];
+  __shared__ int lds_i[kBlock / kWave + 1];
+
+  Acc acc;
+  acc_init(acc);
+  if (src == 0) {
+    SrcOrig<TIn> s{(const TIn*)A.d + off, (const TIn*)A.a + off, (const TIn*)A.b + off,
+                   (const TIn*)A.l + off, (const TIn*)A.u + off};
+    const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
+    if (mode != kModeEval) {
+      bkpt_pass(s, count, lam, acc);
+    } else if (compact) {
+      double* out[4] = {A.buf[0][0] + off, A.buf[0][1] + off, A.buf[0][2] + off, A.buf[0][3] + off};
+      eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + blockIdx.x, acc, lds_i);
+    } else {
+      eval_pass<SrcOrig<TIn>, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, lds_i);
+    }
+  } else {
+    const int si = src - 1, di = 1 - si;
+    SrcForm s{A.buf[si][0] + off, A.buf[si][1] + off, A.buf[si][2] + off, A.buf[si][3] + off};
+    const int64_t count = A.cnt[si][blockIdx.x];
+    if (mode != kModeEval) {
+      bkpt_pass(s, count, lam, acc);
+    } else if (compact) {
+      double* out[4] = {A.buf[di][0] + off, A.buf[di][1] + off, A.buf[di][2] + off,
+                        A.buf[di][3] + off};
+      eval_pass<SrcForm, true>(s, count, lam, lo, hi, out, A.cnt[di] + blockIdx.x, acc, lds_i);
+    } else {
+      eval_pass<SrcForm, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, lds_i);
+    }
+  }
+
+  block_reduce<NSUM, 1, 1, kBlock>(acc.s, &acc.br, &acc.bl, lds, tot);
+  if (threadIdx.x == 0) {
+    double* p = A.partials + (size_t)blockIdx.x * NPART;
+    for (int i = 0; i < NPART; ++i) p[i] = tot[i];
+  }
+  if (last_block_arrives(&st->ticket)) {
+    reduce_partials<NSUM, 1, 1, kBlock>(A.partials, gridDim.x, lds, tot);
+    if (threadIdx.x == 0) {
+      if (mode == kModeEval) update_after_eval(st, tot, A.trace);
+      else update_after_bkpt(st, tot, A.trace);
+      st->ticket = 0;
+    }
+  }
+}
+
+// eq. (CQKlambda0) with J = all indices: lam0 = (r - sum b a/d) / sum b^2/d,
+// plus the input checks.
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_lambda0_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  constexpr int V = VecWidth<TIn>::value;
+  const int64_t off = (int64_t)blockIdx.x * A.chunk;
+  const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
+  SrcOrig<TIn> src{(const TIn*)A.d + off, (const TIn*)A.a + off, (const TIn*)A.b + off,
+                   (const TIn*)A.l + off, (const TIn*)A.u + off};
+  double sums[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
+    double c[V], s[V], bl[V], bu[V];
+    src.load(i, count, c, s, bl, bu, sums[2]);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (i + k < count) {
+        sums[0] += c[k];
+        sums[1] += s[k];
+      }
+    }
+  }
+  __shared__ double lds[3 * (kBlock / kWave)];
+  __shared__ double tot[3];
+  block_reduce<3, 0, 0, kBlock>(sums, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) {
+    double* p = A.partials + (size_t)blockIdx.x * 3;
+    for (int i = 0; i < 3; ++i) p[i] = tot[i];
+  }
+  if (last_block_arrives(&st->ticket)) {
+    reduce_partials<3, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
+    if (threadIdx.x == 0) {
+      st->ticket = 0;
+      st->passes += 1;
+      if (tot[2] > 0.0) {
+        st->status = CQK_INVALID_ARG;
+      } else {
+        const double lam0 = (tot[1] > 0.0) ? (st->r - tot[0]) / tot[1] : 0.0;
+        st->lam = lam0;
+        st->lam0 = lam0;
+      }
+      trace_push(st, A.trace, 0, 0, 0, st->lam, tot[0], tot[1], A.n, 0);
+    }
+  }
+}
+
+// x_i = clamp((a_i + lam b_i)/d_i, l_i, u_i) over all n (eq. (xopt)), with
+// b^T x, sum |b x| and the free count reduced for the caller's info.
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
+  GenState* st = A.st;
+  const int status = st->status;
+  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
+  constexpr int V = VecWidth<TIn>::value;
+  const double lam = st->lam_final;
+  const int64_t off = (int64_t)blockIdx.x * A.chunk;
+  const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
+  const TIn* d = (const TIn*)A.d + off;
+  const TIn* a = (const TIn*)A.a + off;
+  const TIn* b = (const TIn*)A.b + off;
+  const TIn* l = (const TIn*)A.l + off;
+  const TIn* u = (const TIn*)A.u + off;
+  TIn* x = (TIn*)A.x + off;
+  double sums[3] = {0.0, 0.0, 0.0};
+  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
+    double vd[V], va[V], vb[V], vl[V], vu[V];
+    Vec<TIn, V>::load(d, i, count, 1.0, vd);
+    Vec<TIn, V>::load(a, i, count, 0.0, va);
+    Vec<TIn, V>::load(b, i, count, 0.0, vb);
+    Vec<TIn, V>::load(l, i, count, 0.0, vl);
+    Vec<TIn, V>::load(u, i, count, 0.0, vu);
+    TIn xo[V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const double t = fma(vb[k], lam, va[k]) / vd[k];
+      const double xv = fmin(fmax(t, vl[k]), vu[k]);
+      xo[k] = (TIn)xv;
+      const double xr = (double)xo[k];
+      if (i + k < count) {
+        sums[0] += vb[k] * xr;
+        sums[1] += fabs(vb[k] * xr);
+        sums[2] += (xr > vl[k] && xr < vu[k]) ? 1.0 : 0.0;
+      }
+    }
+    if (i + V <= count) {
+      if constexpr (V == 2) {
+        dbl2 v;
+        v.x = xo[0];
+        v.y = xo[1];
+        __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(x + i));
+      } else {
+        flt4 v;
+        v.x = xo[0];
+        v.y = xo[1];
+        v.z = xo[2];
+        v.w = xo[3];
+        __builtin_nontemporal_store(v, reinterpret_cast<flt4*>(x + i));
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k)
+        if (i + k < count) x[i + k] = xo[k];
+    }
+  }
+  __shared__ double lds[3 * (kBlock / kWave)];
+  __shared__ double tot[3];
+  block_reduce<3, 0, 0, kBlock>(sums, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) {
+    double* p = A.partials + (size_t)blockIdx.x * 3;
+    for (int i = 0; i < 3; ++i) p[i] = tot[i];
+  }
+  if (last_block_arrives(&st->ticket)) {
+    reduce_partials<3, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
+    if (threadIdx.x == 0) {
+      st->ticket = 0;
+      st->res_P = tot[0];
+      st->res_A = tot[1];
+      st->n_free = (int64_t)tot[2];
+    }
+  }
+}
+
+__global__ void gen_init_kernel(GenState* st, GenState init) { *st = init; }
+
+int choose_grid(int64_t n, int num_cus) {
+  const int64_t want = (n + 1023) / 1024;
+  const int64_t cap = (int64_t)num_cus * 8;
+  return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
+template <typename TIn>
+cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, const TIn* b,
+                       const TIn* l, const TIn* u, double r, TIn* x, const cqk_opts& o,
+                       cqk_info* info) {
+  const int G0 = choose_grid(n, ctx->num_cus);
+  int64_t chunk = (n + G0 - 1) / G0;
+  chunk = (chunk + 7) / 8 * 8;
+  const int G = (int)((n + chunk - 1) / chunk);
+  const int64_t npad = (int64_t)G * chunk;
+  const bool compaction = o.compaction != CQK_COMPACT_OFF;
+
+  // workspace: partials | counts (2 x G) | buffers (2 x 4 x npad doubles)
+  const size_t part_bytes = ((size_t)G * NPART * sizeof(double) + 255) / 256 * 256;
+  const size_t cnt_bytes = ((size_t)2 * G * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t buf_bytes = compaction ? (size_t)8 * npad * sizeof(double) : 0;
+  cqk_status stt = ensure_buffer(ctx->ws, part_bytes + cnt_bytes + buf_bytes);
+  if (stt != CQK_OK) return stt;
+  const size_t st_bytes = 1024 + sizeof(cqk_trace_rec) * kMaxTrace;
+  stt = ensure_buffer(ctx->state, st_bytes);
+  if (stt != CQK_OK) return stt;
+
+  char* ws = (char*)ctx->ws.ptr;
+  GenArgs A{};
+  A.d = d;
+  A.a = a;
+  A.b = b;
+  A.l = l;
+  A.u = u;
+  A.x = x;
+  A.n = n;
+  A.chunk = chunk;
+  A.partials = (double*)ws;
+  A.cnt[0] = (int32_t*)(ws + part_bytes);
+  A.cnt[1] = A.cnt[0] + G;
+  if (compaction) {
+    double* bb = (double*)(ws + part_bytes + cnt_bytes);
+    for (int k = 0; k < 2; ++k)
+      for (int j = 0; j < 4; ++j) A.buf[k][j] = bb + (size_t)(k * 4 + j) * npad;
+  }
+  A.st = (GenState*)ctx->state.ptr;
+  A.trace = (cqk_trace_rec*)((char*)ctx->state.ptr + 1024);
+
+  const bool is_f32 = sizeof(TIn) == 4;
+  const double eps = (is_f32 && o.accum == CQK_ACCUM_F32) ? 1.1920928955078125e-07
+                                                          : 2.220446049250313e-16;
+  GenState init{};
+  init.lam = (o.lambda0_mode == CQK_LAMBDA0_USER) ? o.lambda0_user : 0.0;
+  init.lam0 = init.lam;
+  init.lam_prev = __builtin_nan("");
+  init.lo = -__builtin_huge_val();
+  init.hi = __builtin_huge_val();
+  init.phi_lo = init.phi_hi = __builtin_nan("");
+  init.r = r;
+  init.tol = (o.tol > 0.0) ? o.tol : std::pow(eps, 0.75);
+  init.theta = (o.compact_theta > 0.0) ? o.compact_theta : 0.5;
+  init.n_src = n;
+  init.status = kRunning;
+  init.max_iter = o.max_iter;
+  init.compaction = o.compaction;
+  init.trace_cap = o.trace ? kMaxTrace : 0;
+  init.nblocks = G;
+  init.lam_final = __builtin_nan("");
+
+  hipStream_t s = ctx->stream;
+  const size_t nev = (size_t)2 * (o.max_iter * 2 + 8);
+  if (o.timing) {
+    stt = ensure_events(ctx, nev);
+    if (stt != CQK_OK) return stt;
+  }
+  hipLaunchKernelGGL(gen_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
+  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  int ev = 0;
+  auto launch = [&](auto kern) {
+    if (o.timing && ev + 2 <= (int)nev) hipEventRecord(ctx->events[ev], s);
+    hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), 0, s, A);
+    if (o.timing && ev + 2 <= (int)nev) {
+      hipEventRecord(ctx->events[ev + 1], s);
+      ev += 2;
+    }
+  };
+  if (o.lambda0_mode == CQK_LAMBDA0_FORMULA) launch(gen_lambda0_kernel<TIn>);
+
+  GenState* hs = (GenState*)ctx->host_pinned;
+  int launched = 0;
+  const int max_launch = 2 * o.max_iter + 4;
+  int batch = 8;
+  while (launched < max_launch) {
+    const int k = std::min(batch, max_launch - launched);
+    for (int i = 0; i < k; ++i) launch(gen_iter_kernel<TIn>);
+    launched += k;
+    if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+    if (hs->status != kRunning) break;
+    batch = 4;
+  }
+  const int pass_events = ev;
+  launch(gen_finalize_kernel<TIn>);
+  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
+    return CQK_DEVICE_ERROR;
+  const int ntr = std::min(hs->ntrace, kMaxTrace);
+  if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+  int ntrace = std::min(hs->ntrace, init.trace_cap);
+  ctx->last_trace.resize(ntrace);
+  ctx->last_trace_count = hs->ntrace;
+  (void)ntr;
+  if (ntrace > 0) {
+    if (hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace, sizeof(cqk_trace_rec) * ntrace,
+                         hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+  }
+  if (hs->status == kRunning) {
+    hs->status = CQK_NOT_CONVERGED;
+  }
+  if (info) {
+    info->status = hs->status;
+    info->iterations = hs->iter;
+    info->passes = hs->passes;
+    info->stop_reason = hs->stop_reason;
+    info->lambda = hs->lam_final;
+    info->lambda0 = hs->lam0;
+    info->residual = std::fabs(hs->res_P - r);
+    info->abs_bx = hs->res_A;
+    info->n_free = hs->n_free;
+    info->n_after_init = 0;
+    info->pass_bytes = 0.0;
+    info->pass_ms = 0.0;
+    info->finalize_bytes = (double)n * (6.0 * sizeof(TIn));
+    info->finalize_ms = 0.0;
+    if (o.timing) {
+      // the first hs->passes launches did work, the rest returned at once
+      const int worked = std::min(hs->passes, pass_events / 2);
+      for (int i = 0; i < worked; ++i) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]);
+        info->pass_ms += ms;
+      }
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ctx->events[pass_events], ctx->events[pass_events + 1]);
+      info->finalize_ms = ms;
+    }
+    // algorithmic bytes from the per-pass records (needs the trace)
+    for (int i = 0; i < ntrace; ++i) {
+      const cqk_trace_rec& t = ctx->last_trace[i];
+      const double per_in = (t.source == 0) ? 5.0 * sizeof(TIn) : 32.0;
+      info->pass_bytes += per_in * (double)t.n_in + 32.0 * (double)t.n_out;
+    }
+  }
+  return CQK_OK;
+}
+
+}  // namespace
+
+cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                           const double* b, const double* l, const double* u, double r,
+                           double* x, const cqk_opts& o, cqk_info* info) {
+  return run_general<double>(ctx, n, d, a, b, l, u, r, x, o, info);
+}
+
+cqk_status run_general_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                           const float* b, const float* l, const float* u, double r, float* x,
+                           const cqk_opts& o, cqk_info* info) {
+  return run_general<float>(ctx, n, d, a, b, l, u, r, x, o, info);
+}
+
+}  // namespace cqk

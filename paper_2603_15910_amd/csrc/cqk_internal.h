@@ -1,0 +1,92 @@
+// Host-side internals of libcqk: the context, device state records and the
+// kernel launchers each translation unit provides.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/cqk.h"
+
+namespace cqk {
+
+constexpr int kMaxTrace = 512;
+
+// Run state of the general (Algorithm 1) solver, one record in device memory.
+struct GenState {
+  double lam, lam_prev, lo, hi, phi_lo, phi_hi;
+  double F, AF, C0, C1, A0, A1;   // contributions of indices dropped from the pass
+  double lam_final, lam0;
+  double r, tol, theta;
+  double res_P, res_A;            // finalize: b^T x and sum |b x|
+  int64_t n_src;                  // indices in the current source
+  int64_t n_free;                 // finalize: free indices
+  int32_t status, iter, passes, mode, src, compact_next, stop_reason, max_iter;
+  int32_t compaction, trace_cap, ntrace, nblocks;
+  uint32_t ticket;
+  int32_t pad_[3];
+};
+
+// Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).
+struct SpxState {
+  double lam, lam_prev, lam0, lam_final, r, tol, theta;
+  double phi_last, slope_last, sum_abs, ymax;
+  double res_P;                   // finalize: sum x
+  int64_t n_src, n_init, n_free;
+  int32_t status, iter, passes, mode, src, compact_next, stop_reason, max_iter;
+  int32_t compaction, trace_cap, ntrace, nblocks, l1, accum_f32, inside_ball, pad0;
+  uint32_t ticket;
+  int32_t pad_[3];
+};
+
+enum RunStatus : int32_t { kRunning = -1 };
+
+enum GenMode : int32_t { kModeEval = 0, kModeBreakRight = 1, kModeBreakLeft = 2 };
+
+struct DeviceBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace cqk
+
+struct cqk_ctx {
+  int device = 0;
+  int num_cus = 256;
+  hipStream_t stream = nullptr;
+  cqk::DeviceBuf ws;          // compaction buffers, partials, per-block counts
+  cqk::DeviceBuf state;       // run-state records + trace ring
+  void* host_pinned = nullptr;  // pinned mirror of the state + trace
+  size_t host_pinned_bytes = 0;
+  std::vector<hipEvent_t> events;
+  int32_t last_trace_count = 0;
+  std::vector<cqk_trace_rec> last_trace;
+};
+
+namespace cqk {
+
+cqk_status ensure_buffer(DeviceBuf& b, size_t bytes);
+cqk_status hip_ok(hipError_t e);
+cqk_status ensure_events(cqk_ctx* ctx, size_t count);
+void fill_default_opts(cqk_opts* o);
+
+// Launchers (each returns CQK_OK or CQK_DEVICE_ERROR / CQK_NO_MEMORY).
+cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                           const double* b, const double* l, const double* u, double r,
+                           double* x, const cqk_opts& o, cqk_info* info);
+cqk_status run_general_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                           const float* b, const float* l, const float* u, double r, float* x,
+                           const cqk_opts& o, cqk_info* info);
+cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x, bool l1,
+                           const cqk_opts& o, cqk_info* info);
+cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r, double* x,
+                           bool l1, const cqk_opts& o, cqk_info* info);
+cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
+                           const double* r, double r_scalar, float* x, double* lambda_out,
+                           int32_t* nfree_out, const cqk_opts& o, cqk_info* info);
+cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const float* x, const float* g, float* grad_y,
+                                    double* grad_r, const cqk_opts& o);
+
+}  // namespace cqk

@@ -1,0 +1,69 @@
+"""Host-only checks of the C ABI: the library loads and exports every entry
+point that include/cqk.h declares; the ctypes structs have the C layout;
+host-side argument errors are reported without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2603_15910_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(cqk_[a-z0-9_]+)\s*\(", src))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.fail("libcqk.so is not built (run __graft_entry__.build())")
+    return L.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = _declared()
+    assert len(declared) >= 15
+    missing = [n for n in sorted(declared) if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(L.SIGNATURES) == declared
+
+
+def test_struct_layouts_match_header():
+    # offsets follow from the C declarations with natural alignment
+    assert C.sizeof(L.cqk_opts) == 64
+    assert L.cqk_opts.lambda0_user.offset == 8
+    assert L.cqk_opts.timing.offset == 60
+    assert C.sizeof(L.cqk_info) == 96
+    assert L.cqk_info.lambda_.offset == 16
+    assert C.sizeof(L.cqk_trace_rec) == 72
+
+
+def test_status_strings_and_defaults(lib):
+    assert lib.cqk_status_string(0) == b"CQK_OK"
+    assert lib.cqk_status_string(1) == b"CQK_INFEASIBLE"
+    assert lib.cqk_status_string(99) == b"CQK_UNKNOWN_STATUS"
+    o = L.cqk_opts()
+    lib.cqk_default_opts(C.byref(o))
+    assert o.max_iter == 100 and o.compaction == 1 and o.sync == 1
+
+
+def test_host_side_argument_errors(lib):
+    # every case is rejected before a device is touched (null context)
+    null = None
+    assert lib.cqk_solve_f64(null, 10, null, null, null, null, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_simplex_f32(null, 10, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_l1_f64(null, 10, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_simplex_batched_f32(null, 4, null, null, null, 1.0, null, null, null,
+                                               None, None) == 2
+    assert lib.cqk_create(None, None) == 2
+    assert lib.cqk_set_stream(null, null) == 2
+    assert lib.cqk_last_trace(null, None, 0, None) == 2
