@@ -160,13 +160,78 @@ __device__ __forceinline__ void reduce_partials(const double* partials, int G, d
   for (int g = threadIdx.x; g < G; g += BLOCK) {
     const double* p = partials + (size_t)g * NV;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) s[i] += __builtin_nontemporal_load(p + i);
+    for (int i = 0; i < NS; ++i) s[i] += p[i];
 #pragma unroll
-    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], __builtin_nontemporal_load(p + NS + i));
+    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], p[NS + i]);
 #pragma unroll
-    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], __builtin_nontemporal_load(p + NS + NM + i));
+    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], p[NS + NM + i]);
   }
   block_reduce<NS, NM, NX, BLOCK>(s, mn, mx, lds, out);
+}
+
+// ---------------------------------------------------------------------------
+// (key, weight) reduction: the smallest key with the summed weight of every
+// entry holding that key.  Associative and commutative, so the butterfly and
+// the ordered block/grid combination give the same bits everywhere.
+// ---------------------------------------------------------------------------
+struct KeySum {
+  double k, w;
+};
+
+__device__ __forceinline__ KeySum ks_min(KeySum a, KeySum b) {
+  if (a.k < b.k) return a;
+  if (b.k < a.k) return b;
+  return KeySum{a.k, a.w + b.w};
+}
+
+__device__ __forceinline__ KeySum wave_ks_min(KeySum v) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) {
+    KeySum t{__shfl_xor(v.k, o, kWave), __shfl_xor(v.w, o, kWave)};
+    v = ks_min(v, t);
+  }
+  return v;
+}
+
+// NK key-sum pairs per thread -> thread 0 gets the block result.
+template <int NK, int BLOCK>
+__device__ __forceinline__ void block_ks_min(const KeySum* v, double* lds, KeySum* out) {
+  constexpr int NW = BLOCK / kWave;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NK; ++i) {
+    KeySum r = wave_ks_min(v[i]);
+    if (lane == 0) {
+      lds[(2 * i) * NW + wid] = r.k;
+      lds[(2 * i + 1) * NW + wid] = r.w;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NK; ++i) {
+      KeySum acc{lds[(2 * i) * NW], lds[(2 * i + 1) * NW]};
+      for (int w = 1; w < NW; ++w) acc = ks_min(acc, KeySum{lds[(2 * i) * NW + w], lds[(2 * i + 1) * NW + w]});
+      out[i] = acc;
+    }
+  }
+  __syncthreads();
+}
+
+// Grid version over G partial records of NK pairs (k0, w0, k1, w1, ...).
+template <int NK, int BLOCK>
+__device__ __forceinline__ void reduce_partials_ks(const double* partials, int G, double* lds,
+                                                   KeySum* out) {
+  KeySum acc[NK];
+#pragma unroll
+  for (int i = 0; i < NK; ++i) acc[i] = KeySum{inf_d(), 0.0};
+  for (int g = threadIdx.x; g < G; g += BLOCK) {
+    const double* p = partials + (size_t)g * 2 * NK;
+#pragma unroll
+    for (int i = 0; i < NK; ++i) acc[i] = ks_min(acc[i], KeySum{p[2 * i], p[2 * i + 1]});
+  }
+  block_ks_min<NK, BLOCK>(acc, lds, out);
 }
 
 // ---------------------------------------------------------------------------

@@ -39,7 +39,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kUnroll = 2;
 
-// Partial record: NSUM sums, then one min (BR) and one max (BL).
+// Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
+// two (key, weight) pairs instead.
 enum {
   P_P = 0,     // sum g_i(lam)
   P_A,         // sum |g_i(lam)|
@@ -58,7 +59,7 @@ enum {
   P_BAD,       // indices failing the input checks
   NSUM
 };
-constexpr int NPART = NSUM + 2;
+constexpr int NPART = NSUM;
 
 struct GenArgs {
   const void* d;
@@ -78,14 +79,11 @@ struct GenArgs {
 
 struct Acc {
   double s[NSUM];
-  double br, bl;
 };
 
 __device__ __forceinline__ void acc_init(Acc& a) {
 #pragma unroll
   for (int i = 0; i < NSUM; ++i) a.s[i] = 0.0;
-  a.br = inf_d();
-  a.bl = -inf_d();
 }
 
 // Per-index form of the original data (eq. (xopt) times b), with the input
@@ -147,13 +145,20 @@ __device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double 
   return true;
 }
 
-// Closest breakpoints around lam (Algorithm 1, breakpoint steps).
-__device__ __forceinline__ void bkpt_index(Acc& acc, double c, double s, double bl, double bu,
+// Closest breakpoints around lam (Algorithm 1, breakpoint steps), with the
+// slope that opens there.  The candidates are chosen with the same predicate
+// the slopes use (an index below its lower bound at lam can only become free
+// as lam grows), so an index that rounding left on the wrong side of a
+// breakpoint equal to lam is still found (its key is then lam itself).
+// Indices with l = u never become free and are skipped.
+//   ks[0]: (min over candidates of max(lbar_i, lam), sum of s_i at that key)
+//   ks[1]: (min of -min(ubar_i, lam), sum of s_i)  -- the left search
+__device__ __forceinline__ void bkpt_index(KeySum* ks, double c, double s, double bl, double bu,
                                            double lam) {
-  const double lb = (bl - c) / s;
-  const double ub = (bu - c) / s;
-  if (lb > lam) acc.br = fmin(acc.br, lb);
-  if (ub < lam) acc.bl = fmax(acc.bl, ub);
+  if (!(bl < bu)) return;
+  const double f = fma(s, lam, c);
+  if (f < bl) ks[0] = ks_min(ks[0], KeySum{fmax((bl - c) / s, lam), s});
+  if (f > bu) ks[1] = ks_min(ks[1], KeySum{-fmin((bu - c) / s, lam), s});
 }
 
 // Sources: the caller's arrays or a compacted region.
@@ -238,7 +243,7 @@ __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, 
 }
 
 template <typename Src>
-__device__ void bkpt_pass(const Src& src, int64_t count, double lam, Acc& acc) {
+__device__ void bkpt_pass(const Src& src, int64_t count, double lam, KeySum* ks) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kBlock * E;
@@ -252,7 +257,7 @@ __device__ void bkpt_pass(const Src& src, int64_t count, double lam, Acc& acc) {
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
-        if (i + k < count) bkpt_index(acc, c[e], s[e], bl[e], bu[e], lam);
+        if (i + k < count) bkpt_index(ks, c[e], s[e], bl[e], bu[e], lam);
       }
     }
   }
@@ -368,23 +373,46 @@ __device__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* 
   advance(st, next);
 }
 
-__device__ void update_after_bkpt(GenState* st, const double* t, cqk_trace_rec* tr) {
+// Breakpoint step of Algorithm 1.  phi is constant between lam_k and the
+// closest breakpoint bp (no index changes on that interval), so the next
+// iterate lam_{k+1} = bp is evaluated without another pass: phi(bp) =
+// phi(lam_k) and the one-sided slope at bp is the summed s of the indices
+// whose breakpoint is bp.  The Newton step from bp follows as in Algorithm 1.
+__device__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec* tr) {
   st->passes += 1;
   const bool right = st->mode == kModeBreakRight;
-  const double bp = right ? t[NSUM] : t[NSUM + 1];
-  trace_push(st, tr, 2, 0, st->src, st->lam, bp, 0.0, (int64_t)st->n_src, 0);
+  const double bp = right ? ks[0].k : -ks[1].k;
+  const double sw = right ? ks[0].w : ks[1].w;
+  trace_push(st, tr, 2, 0, st->src, st->lam, bp, sw, (int64_t)st->n_src, 0);
   if (!(fabs(bp) < inf_d())) {
     st->status = CQK_INFEASIBLE;
     return;
   }
+  const double phi = right ? st->phi_lo : st->phi_hi;
+  const double r = st->r, tol = st->tol;
+  const double res = phi - r;
+  if (right) st->lo = bp;
+  else st->hi = bp;
   const double lo = st->lo, hi = st->hi;
-  double next = bp;
-  if (!(next > lo && next < hi)) {
-    if (fabs(lo) < inf_d() && fabs(hi) < inf_d()) {
-      next = lo - (st->phi_lo - st->r) * (hi - lo) / (st->phi_hi - st->phi_lo);
-      if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
-    }
+  trace_push(st, tr, 5, 0, st->src, bp, phi, sw, 0, 0);
+  st->iter += 1;
+  st->lam_prev = st->lam;
+  st->lam = bp;
+  if (st->iter >= st->max_iter) {
+    st->status = CQK_NOT_CONVERGED;
+    st->lam_final = bp;
+    return;
   }
+  if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, bp, 3);
+  if (!(sw > 0.0)) return;  // still flat past bp: search again from bp
+  const double step = res / sw;
+  double next = bp - step;
+  if (fabs(step) < tol) return finish(st, fmin(fmax(next, lo), hi), 2);
+  if (!(next > lo && next < hi)) {
+    next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+  }
+  if (next == bp) return finish(st, bp, 2);
   advance(st, next);
 }
 
@@ -404,12 +432,13 @@ __global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
 
   Acc acc;
   acc_init(acc);
+  KeySum ks[2] = {KeySum{inf_d(), 0.0}, KeySum{inf_d(), 0.0}};
   if (src == 0) {
     SrcOrig<TIn> s{(const TIn*)A.d + off, (const TIn*)A.a + off, (const TIn*)A.b + off,
                    (const TIn*)A.l + off, (const TIn*)A.u + off};
     const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
     if (mode != kModeEval) {
-      bkpt_pass(s, count, lam, acc);
+      bkpt_pass(s, count, lam, ks);
     } else if (compact) {
       double* out[4] = {A.buf[0][0] + off, A.buf[0][1] + off, A.buf[0][2] + off, A.buf[0][3] + off};
       eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + blockIdx.x, acc, lds_i);
@@ -421,7 +450,7 @@ __global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
     SrcForm s{A.buf[si][0] + off, A.buf[si][1] + off, A.buf[si][2] + off, A.buf[si][3] + off};
     const int64_t count = A.cnt[si][blockIdx.x];
     if (mode != kModeEval) {
-      bkpt_pass(s, count, lam, acc);
+      bkpt_pass(s, count, lam, ks);
     } else if (compact) {
       double* out[4] = {A.buf[di][0] + off, A.buf[di][1] + off, A.buf[di][2] + off,
                         A.buf[di][3] + off};
@@ -431,17 +460,35 @@ __global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
     }
   }
 
-  block_reduce<NSUM, 1, 1, kBlock>(acc.s, &acc.br, &acc.bl, lds, tot);
-  if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * NPART;
-    for (int i = 0; i < NPART; ++i) p[i] = tot[i];
-  }
-  if (last_block_arrives(&st->ticket)) {
-    reduce_partials<NSUM, 1, 1, kBlock>(A.partials, gridDim.x, lds, tot);
+  if (mode == kModeEval) {
+    block_reduce<NSUM, 0, 0, kBlock>(acc.s, nullptr, nullptr, lds, tot);
     if (threadIdx.x == 0) {
-      if (mode == kModeEval) update_after_eval(st, tot, A.trace);
-      else update_after_bkpt(st, tot, A.trace);
-      st->ticket = 0;
+      double* p = A.partials + (size_t)blockIdx.x * NPART;
+      for (int i = 0; i < NPART; ++i) p[i] = tot[i];
+    }
+    if (last_block_arrives(&st->ticket)) {
+      reduce_partials<NSUM, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
+      if (threadIdx.x == 0) {
+        update_after_eval(st, tot, A.trace);
+        st->ticket = 0;
+      }
+    }
+  } else {
+    __shared__ KeySum ktot[2];
+    block_ks_min<2, kBlock>(ks, lds, ktot);
+    if (threadIdx.x == 0) {
+      double* p = A.partials + (size_t)blockIdx.x * 4;
+      p[0] = ktot[0].k;
+      p[1] = ktot[0].w;
+      p[2] = ktot[1].k;
+      p[3] = ktot[1].w;
+    }
+    if (last_block_arrives(&st->ticket)) {
+      reduce_partials_ks<2, kBlock>(A.partials, gridDim.x, lds, ktot);
+      if (threadIdx.x == 0) {
+        update_after_bkpt(st, ktot, A.trace);
+        st->ticket = 0;
+      }
     }
   }
 }
