@@ -101,6 +101,9 @@ typedef struct cqk_info {
   double pass_ms;           /* their summed kernel time (opts.timing = 1) */
   double finalize_bytes;    /* algorithmic bytes of the x-writing pass */
   double finalize_ms;       /* its kernel time (opts.timing = 1) */
+  int64_t rows_spilled;     /* batched: long rows whose survivors of Alg. 2 did
+                               not fit the on-chip list (Newton then re-reads
+                               the row); 0 otherwise */
 } cqk_info;
 
 /* One record per kernel pass (opts.trace = 1). */

@@ -138,7 +138,7 @@ def cqk_project_simplex_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, g
 # torch-tensor helpers
 # ---------------------------------------------------------------------------
 def make_opts(lambda0=None, lambda0_user=0.0, max_iter=100, tol=0.0, compaction="auto",
-              theta=0.0, accum="default", trace=False, timing=False, simplex=False):
+              theta=0.0, accum="default", trace=False, timing=False, simplex=False, sync=True):
     o = cqk_default_opts()
     if lambda0 is None:
         lambda0 = "condat" if simplex else "zero"
@@ -149,7 +149,7 @@ def make_opts(lambda0=None, lambda0_user=0.0, max_iter=100, tol=0.0, compaction=
     o.compaction = L.COMPACTION[compaction]
     o.compact_theta = float(theta)
     o.accum = L.ACCUM[accum]
-    o.sync = 1
+    o.sync = 1 if sync else 0
     o.trace = 1 if trace else 0
     o.timing = 1 if timing else 0
     return o

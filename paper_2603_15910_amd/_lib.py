@@ -60,6 +60,7 @@ class cqk_info(C.Structure):
         ("pass_ms", C.c_double),
         ("finalize_bytes", C.c_double),
         ("finalize_ms", C.c_double),
+        ("rows_spilled", C.c_int64),
     ]
 
     def as_dict(self):

@@ -30,15 +30,19 @@ struct GenState {
 
 // Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).
 struct SpxState {
-  double lam, lam_prev, lam0, lam_final, r, tol, theta;
-  double phi_last, slope_last, sum_abs, ymax;
-  double res_P;                   // finalize: sum x
-  int64_t n_src, n_init, n_free;
-  int32_t status, iter, passes, mode, src, compact_next, stop_reason, max_iter;
-  int32_t compaction, trace_cap, ntrace, nblocks, l1, accum_f32, inside_ball, pad0;
+  double lam, lam_prev, lam0, lam_final, r, tol;
+  double lo, hi, sum_abs, vmax;
+  double res_P;                   // finalize: sum of x (l1: sum |x|)
+  double cm_prev;
+  int64_t n_src, n_init, n_free, m, chunk_src;
+  int32_t status, iter, passes, src, compact_next, stop_reason, max_iter;
+  int32_t compaction, trace_cap, ntrace, l1, fin_mode, need_safeguard, first_done;
   uint32_t ticket;
   int32_t pad_[3];
 };
+
+// How the simplex finalize writes x.
+enum FinMode : int32_t { kFinDense = 0, kFinScatter = 1, kFinCopy = 2, kFinZero = 3 };
 
 enum RunStatus : int32_t { kRunning = -1 };
 
