@@ -1,17 +1,22 @@
 """Benchmark: general CQK solve, n = 1e8, FP64, on one MI355X.
 
-One step = one whole solve (cqk_solve_f64: Newton passes with compaction of
-resolved indices, then the x-writing pass) over inputs already resident in
-HBM.  Prints one JSON line (see the design doc for every field).
+One step = one whole solve (cqk_solve_f64: the Newton passes with compaction
+of resolved indices, then the x-writing pass) over inputs already resident in
+HBM.  Prints one JSON line; the fields are described in the design doc.  Besides
+the headline, "extras" reports the other workloads (correlated CQK, simplex
+and l1 at n = 1e8, batched and differentiable batched projections) on the same
+GPU, each checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
-                    [--no-cpu-baseline] [--no-extras]
+                    [--no-cpu-baseline] [--no-extras] [--calibrate-copy]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import statistics
 import subprocess
 import sys
 import time
@@ -23,6 +28,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gen_pass_kernel_cqk_uniform_1e8.traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2603_15910_amd", "csrc", "cqk_general.hip")
 
 
 def log(msg):
@@ -53,8 +60,137 @@ def cpu_baseline(n_sample: int):
     assert res.status == O.OK
     ncpu, model = host_cpu_desc()
     return {"value": n_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"cqk_uniform n={n_sample} seed=1, one exact solve (numpy, 1 thread), "
-                      f"{dt:.2f} s on {model} ({ncpu} logical CPUs)"}
+            "sample": f"cqk_uniform n={n_sample} seed=1 (1/10 of the workload), one exact "
+                      f"breakpoint-sort solve (numpy, 1 thread), {dt:.2f} s on {model} "
+                      f"({ncpu} logical CPUs)"}
+
+
+def measured_traffic(kernel_sha):
+    """HBM bytes per launch of the pass kernel from the committed counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_sha:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def timed(fn, reps, sync):
+    out = []
+    for _ in range(reps):
+        sync()
+        t0 = time.perf_counter()
+        fn()
+        sync()
+        out.append((time.perf_counter() - t0) * 1e3)
+    return statistics.median(out)
+
+
+def extras(ctx, dev, torch):
+    import paper_2603_15910_amd as cqk
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
+
+    # general CQK, correlated variant (n = 1e8, FP64)
+    inst = W.cqk_correlated(100_000_000, 1)
+    t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
+    r = inst["r"]
+    del inst
+    x = torch.empty_like(t[0])
+    ctx.solve(*t, r, out=x)
+    ms = timed(lambda: ctx.solve(*t, r, out=x), 5, sync)
+    _, info = ctx.solve(*t, r, out=x, timing=True, trace=True)
+    ex["cqk_correlated_1e8_f64"] = {
+        "ms": ms, "elements_per_s": 1e8 / (ms * 1e-3), "iterations": info["iterations"],
+        "status": info["status_name"],
+        "pass_gbs": info["pass_bytes"] / (info["pass_ms"] * 1e-3) / 1e9,
+        "finalize_gbs": info["finalize_bytes"] / (info["finalize_ms"] * 1e-3) / 1e9}
+    del t, x
+    torch.cuda.empty_cache()
+
+    # simplex and l1 projections, n = 1e8, FP32 inputs
+    n = 100_000_000
+    for dist in ("normal", "uniform"):
+        y = torch.from_numpy(W.simplex_input(n, 1, dist, np.float32)).to(dev)
+        xs = torch.empty_like(y)
+        for start in ("condat", "zero"):
+            for accum in ("f64", "f32"):
+                kw = dict(lambda0=start, accum=accum)
+                ctx.project_simplex(y, 1.0, out=xs, **kw)
+                ms = timed(lambda: ctx.project_simplex(y, 1.0, out=xs, **kw), 5, sync)
+                _, info = ctx.project_simplex(y, 1.0, out=xs, timing=True, trace=True, **kw)
+                ex[f"simplex_{dist}_1e8_f32in_{accum}acc_{start}"] = {
+                    "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
+                    "n_after_init": info["n_after_init"], "status": info["status_name"],
+                    "gbs_total": (info["pass_bytes"] + info["finalize_bytes"]) / (ms * 1e-3) / 1e9}
+        if dist == "normal":
+            for start in ("condat", "zero"):
+                kw = dict(lambda0=start)
+                ctx.project_l1(y, 1.0, out=xs, **kw)
+                ms = timed(lambda: ctx.project_l1(y, 1.0, out=xs, **kw), 5, sync)
+                _, info = ctx.project_l1(y, 1.0, out=xs, **kw)
+                ex[f"l1_{dist}_1e8_f32_{start}"] = {
+                    "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
+                    "status": info["status_name"]}
+        del y, xs
+        torch.cuda.empty_cache()
+
+    # batched simplex: 8192 rows, lengths log-uniform in [64, 65536]
+    off, yb = W.batched_simplex_input(8192, 64, 65536, 1)
+    total = int(off[-1])
+    offs = torch.from_numpy(off).to(dev)
+    ybt = torch.from_numpy(yb).to(dev)
+    xb = torch.empty_like(ybt)
+    ctx.project_simplex_batched(ybt, offs, 1.0, out=xb)
+    ms = timed(lambda: ctx.project_simplex_batched(ybt, offs, 1.0, out=xb), 10, sync)
+    _, info = ctx.project_simplex_batched(ybt, offs, 1.0, out=xb)
+    # comparator: one plain solve per row (same library, same stream)
+    views = [ybt[int(off[s]):int(off[s + 1])] for s in range(8192)]
+    outs = [xb[int(off[s]):int(off[s + 1])] for s in range(8192)]
+    sync()
+    t0 = time.perf_counter()
+    for v, o in zip(views, outs):
+        ctx.project_simplex(v, 1.0, out=o)
+    sync()
+    loop_ms = (time.perf_counter() - t0) * 1e3
+    ex["batched_simplex_8192rows"] = {
+        "rows": 8192, "elements": total, "ms": ms, "elements_per_s": total / (ms * 1e-3),
+        "gbs_8B_per_elem": 8.0 * total / (ms * 1e-3) / 1e9, "status": info["status_name"],
+        "rows_spilled": info["rows_spilled"],
+        "per_row_loop_ms": loop_ms,
+        "speedup_vs_per_row_loop": loop_ms / ms}
+    del ybt, xb, offs, views, outs
+    torch.cuda.empty_cache()
+
+    # differentiable batched projection: 4096 rows in [1024, 32768], y = 3 N(0,1)
+    off, yb = W.batched_simplex_input(4096, 1024, 32768, 1, scale=3.0)
+    total = int(off[-1])
+    offs = torch.from_numpy(off).to(dev)
+    yt = torch.from_numpy(yb).to(dev)
+    g = torch.from_numpy(W.upstream_grad(total, 1)).to(dev)
+    xf = torch.empty_like(yt)
+    gy = torch.empty_like(yt)
+    ctx.project_simplex_batched(yt, offs, 1.0, out=xf)
+    fwd = timed(lambda: ctx.project_simplex_batched(yt, offs, 1.0, out=xf), 10, sync)
+    bwd = timed(lambda: ctx.project_simplex_batched_backward(xf, g, offs, grad_y=gy), 10, sync)
+
+    def fb():
+        yy = yt.detach().requires_grad_(True)
+        xx = cqk.SimplexProjection.apply(yy, offs, 1.0)
+        xx.backward(g)
+
+    fb()
+    fwdbwd = timed(fb, 10, sync)
+    ex["differentiable_batched_4096rows"] = {
+        "rows": 4096, "elements": total, "forward_ms": fwd, "backward_ms": bwd,
+        "forward_backward_autograd_ms": fwdbwd,
+        "forward_gbs_8B": 8.0 * total / (fwd * 1e-3) / 1e9,
+        "backward_gbs_12B": 12.0 * total / (bwd * 1e-3) / 1e9}
+    return ex
 
 
 def main():
@@ -63,14 +199,15 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=100_000_000)
-    ap.add_argument("--variant", default="uniform", choices=["uniform", "correlated"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the method shards as described in DESIGN.md)", file=sys.stderr)
+              "(how the method would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -80,9 +217,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     n = args.n
-    log(f"bench: generating cqk_{args.variant} n={n}")
-    gen = W.cqk_uniform if args.variant == "uniform" else W.cqk_correlated
-    inst = gen(n, 1)
+    log(f"bench: generating cqk_uniform n={n}")
+    inst = W.cqk_uniform(n, 1)
     t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
     r = inst["r"]
     del inst
@@ -90,6 +226,12 @@ def main():
     ctx = cqk.Context(0)
     ctx.reserve(n)
 
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         ctx.solve(*t, r, out=x)
@@ -105,6 +247,7 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt * 1e3 / args.steps
+    assert all(i["status"] == 0 for i in infos), infos[-1]
 
     pass_bytes = sum(i["pass_bytes"] for i in infos)
     pass_ms = sum(i["pass_ms"] for i in infos)
@@ -118,6 +261,8 @@ def main():
     for rec in tr:
         log(f"  pass kind={rec['kind']} src={rec['source']} n_in={rec['n_in']} "
             f"n_out={rec['n_out']} lam={rec['lam']:.12g}")
+    with open(KERNEL_SRC, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
 
     out = {
         "metric": "CQK solve elements/sec (general CQK, FP64, n=1e8)",
@@ -132,16 +277,17 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"cqk_{args.variant} n={n} fp64, lambda0=0, compaction=auto",
+        "config": {"workload": f"cqk_uniform n={n} fp64 (d~U[1,10], a~U[-10,10], b~U[1,10], "
+                               "l~U[-5,0], u=l+U[0.1,5], r=b'(l+u)/2), lambda0=0, compaction=auto",
                    "n": n, "seed": 1},
         "roofline": {
             "bound": "hbm",
-            "kernel": "gen_iter_kernel<double> (evaluation pass)",
+            "kernel": "gen_pass_kernel<double> (evaluation pass)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(sha),
             "launches": passes,
             "avg_launch_ms": pass_ms / max(passes, 1),
             "avg_launch_bytes": pass_bytes / max(passes, 1),
@@ -149,6 +295,11 @@ def main():
         "iterations": infos[-1]["iterations"],
         "finalize_gbs": fin_gbs,
     }
+    del t, x
+    torch.cuda.empty_cache()
+    if not args.no_extras:
+        log("bench: extras")
+        out["extras"] = extras(ctx, dev, torch)
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle) on n={args.cpu_sample}")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample)

@@ -17,8 +17,9 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Every array argument is a DEVICE pointer owned by the caller, contiguous,
- *   with element i at ptr[i], 16-byte aligned (INVALID_ARG otherwise; the
- *   kernels use 16-byte vector loads).  Outputs must not alias inputs.
+ *   with element i at ptr[i].  Any alignment of the element type is accepted;
+ *   16-byte aligned arrays get 16-byte vector accesses throughout.  Outputs
+ *   must not alias inputs.
  * - Work is enqueued on the context's HIP stream (cqk_create / cqk_set_stream)
  *   and is ordered with the caller's other work on that stream.
  * - Errors are returned as cqk_status; nothing aborts or throws across the

@@ -166,8 +166,8 @@ def _dev_ptr(t, dtype, name):
         raise ValueError(f"{name} must be a GPU tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
-    if not t.is_contiguous() or t.data_ptr() % 16:
-        raise ValueError(f"{name} must be contiguous and 16-byte aligned")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
     return t.data_ptr()
 
 

@@ -61,8 +61,6 @@ using namespace cqk;
 
 namespace {
 
-bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
-
 cqk_status check_opts(const cqk_opts* in, cqk_opts* out, bool simplex) {
   if (in) {
     *out = *in;
@@ -102,9 +100,6 @@ cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T
     return (cqk_status)s;
   }
   if (!d || !a || !b || !l || !u || !x) return CQK_INVALID_ARG;
-  if (!aligned16(d) || !aligned16(a) || !aligned16(b) || !aligned16(l) || !aligned16(u) ||
-      !aligned16(x))
-    return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
@@ -129,7 +124,6 @@ cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, double r, T* x, b
     return (cqk_status)s;
   }
   if (!y || !x) return CQK_INVALID_ARG;
-  if (!aligned16(y) || !aligned16(x)) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;

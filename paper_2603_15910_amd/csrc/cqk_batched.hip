@@ -205,7 +205,7 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
 #pragma unroll
     for (int q = 0; q < kK / 4; ++q) {
       const int64_t i = t0 + (int64_t)q * kBlock * 4 + (int64_t)threadIdx.x * 4;
-      if (i + 4 <= L && ((base + i) & 3) == 0) {
+      if (i + 4 <= L && aligned16(y + i)) {
         flt4 w = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(y + i));
         v[4 * q] = w.x;
         v[4 * q + 1] = w.y;
@@ -236,13 +236,13 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
     int nk = 0;
     double ks = 0.0;
     auto select = [&](double lb) {
-      const float lt = (float)fmin(lam_t, lb);
+      const double lt = fmin(lam_t, lb);
       keep = 0;
       nk = 0;
       ks = 0.0;
 #pragma unroll
       for (int e = 0; e < kK; ++e) {
-        if (((J >> e) & 1u) && (v[e] + lt > 0.f)) {
+        if (((J >> e) & 1u) && ((double)v[e] + lt > 0.0)) {
           keep |= 1u << e;
           ++nk;
           ks += (double)v[e];
@@ -293,25 +293,24 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
   double lam = lam_min;
   double prev_c = -1.0;
   for (int it = 0; it < kMaxNewton; ++it) {
-    const float lt = (float)lam;
     double cc = 0.0, ss = 0.0, ph = 0.0;
     if (!overflow) {
       for (int i = threadIdx.x; i < nsurv; i += kBlock) {
-        const float z = surv[i] + lt;
-        if (z > 0.f) {
+        const double z = (double)surv[i] + lam;
+        if (z > 0.0) {
           cc += 1.0;
           ss += (double)surv[i];
-          ph += (double)z;
+          ph += z;
         }
       }
     } else {
       for (int64_t i = threadIdx.x; i < L; i += kBlock) {
-        const float yv = y[i];
-        const float z = yv + lt;
-        if (z > 0.f) {
+        const double yv = (double)y[i];
+        const double z = yv + lam;
+        if (z > 0.0) {
           cc += 1.0;
-          ss += (double)yv;
-          ph += (double)z;
+          ss += yv;
+          ph += z;
         }
       }
     }
@@ -325,8 +324,7 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
     prev_c = tt[0];
     lam = nl;
   }
-  // x = max(0, y + lam*)
-  const float lt = (float)lam;
+  // x = max(0, y + lam*), formed in FP64 and rounded once
   double nf = 0.0;
   if (single) {
 #pragma unroll
@@ -335,11 +333,10 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
       float o[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const float z = v[4 * q + k] + lt;
-        o[k] = z > 0.f ? z : 0.f;
+        o[k] = (float)fmax((double)v[4 * q + k] + lam, 0.0);
         if (i + k < L) nf += (o[k] > 0.f) ? 1.0 : 0.0;
       }
-      if (i + 4 <= L && ((base + i) & 3) == 0) {
+      if (i + 4 <= L && aligned16(x + i)) {
         flt4 w;
         w.x = o[0];
         w.y = o[1];
@@ -354,17 +351,17 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
     }
   } else {
     for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && ((base + i0) & 3) == 0) {
+      if (i0 + 4 <= L && aligned16(y + i0) && aligned16(x + i0)) {
         flt4 w = *reinterpret_cast<const flt4*>(y + i0);
-        w.x = fmaxf(w.x + lt, 0.f);
-        w.y = fmaxf(w.y + lt, 0.f);
-        w.z = fmaxf(w.z + lt, 0.f);
-        w.w = fmaxf(w.w + lt, 0.f);
+        w.x = (float)fmax((double)w.x + lam, 0.0);
+        w.y = (float)fmax((double)w.y + lam, 0.0);
+        w.z = (float)fmax((double)w.z + lam, 0.0);
+        w.w = (float)fmax((double)w.w + lam, 0.0);
         nf += (w.x > 0.f) + (w.y > 0.f) + (w.z > 0.f) + (w.w > 0.f);
         __builtin_nontemporal_store(w, reinterpret_cast<flt4*>(x + i0));
       } else {
         for (int64_t i = i0; i < i0 + 4 && i < L; ++i) {
-          const float o = fmaxf(y[i] + lt, 0.f);
+          const float o = (float)fmax((double)y[i] + lam, 0.0);
           nf += (o > 0.f) ? 1.0 : 0.0;
           x[i] = o;
         }
@@ -432,11 +429,11 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   // refinement on the wave's own sub-problem, then Algorithm 4 on the row
   uint32_t cand = J;
   for (int it = 0; it < kRefine; ++it) {
-    const float lt = (float)fmin(lam_t, lam_b);
+    const double lt = fmin(lam_t, lam_b);
     double nk = 0.0, ks = 0.0;
 #pragma unroll
     for (int e = 0; e < kSmallPer; ++e)
-      if (((cand >> e) & 1u) && v[e] + lt > 0.f) {
+      if (((cand >> e) & 1u) && (double)v[e] + lt > 0.0) {
         nk += 1.0;
         ks += (double)v[e];
       }
@@ -451,15 +448,14 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   double lam = fmin(lam_b, wave_min(lam_t));
   double prev_c = -1.0;
   for (int it = 0; it < kMaxNewton; ++it) {
-    const float lt = (float)lam;
     double cc = 0.0, ss = 0.0, ph = 0.0;
 #pragma unroll
     for (int e = 0; e < kSmallPer; ++e) {
-      const float z = v[e] + lt;
-      if (((active >> e) & 1u) && z > 0.f) {
+      const double z = (double)v[e] + lam;
+      if (((active >> e) & 1u) && z > 0.0) {
         cc += 1.0;
         ss += (double)v[e];
-        ph += (double)z;
+        ph += z;
       }
     }
     cc = wave_sum(cc);
@@ -473,14 +469,12 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
     prev_c = cc;
     lam = nl;
   }
-  const float lt = (float)lam;
   double nf = 0.0;
 #pragma unroll
   for (int k = 0; k < kSmallPer; ++k) {
     const int64_t i = (int64_t)k * kWave + lane;
     if (i < L) {
-      const float z = v[k] + lt;
-      const float o = z > 0.f ? z : 0.f;
+      const float o = (float)fmax((double)v[k] + lam, 0.0);
       nf += (o > 0.f) ? 1.0 : 0.0;
       x[i] = o;
     }
@@ -542,7 +536,7 @@ __device__ void vjp_long_row(const BatArgs& A, int s, double* lds) {
     }
   } else {
     for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && ((base + i0) & 3) == 0) {
+      if (i0 + 4 <= L && aligned16(x + i0) && aligned16(g + i0)) {
         flt4 xv = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(x + i0));
         flt4 gv = *reinterpret_cast<const flt4*>(g + i0);
         if (xv.x > 0.f) { cnt += 1.0; sum += gv.x; }
@@ -567,7 +561,7 @@ __device__ void vjp_long_row(const BatArgs& A, int s, double* lds) {
     }
   } else {
     for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && ((base + i0) & 3) == 0) {
+      if (i0 + 4 <= L && aligned16(x + i0) && aligned16(g + i0) && aligned16(gy + i0)) {
         flt4 xv = *reinterpret_cast<const flt4*>(x + i0);
         flt4 gv = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(g + i0));
         flt4 o;

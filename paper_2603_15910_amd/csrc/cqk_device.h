@@ -49,6 +49,12 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   return v;
 }
 
+// Number of set bits of a wave mask below this lane.
+__device__ __forceinline__ int lane_prefix(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 // Inclusive prefix sum of a 32-bit count across the wave (Hillis-Steele).
 __device__ __forceinline__ int wave_incl_scan(int v) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -144,6 +150,12 @@ __device__ __forceinline__ bool last_block_arrives(uint32_t* ticket) {
   return s_last;
 }
 
+// Partial records are stored value-major: value i of block g at
+// partials[i * G + g], so the reducing block reads them coalesced.
+__device__ __forceinline__ void write_partial(double* partials, const double* v, int nv) {
+  for (int i = 0; i < nv; ++i) partials[(size_t)i * gridDim.x + blockIdx.x] = v[i];
+}
+
 // Deterministic reduction of G partial records of NV doubles (first NS are
 // sums, then NM mins, then NX maxes) by the whole block; thread 0 gets out[].
 template <int NS, int NM, int NX, int BLOCK>
@@ -158,13 +170,12 @@ __device__ __forceinline__ void reduce_partials(const double* partials, int G, d
 #pragma unroll
   for (int i = 0; i < NX; ++i) mx[i] = -inf_d();
   for (int g = threadIdx.x; g < G; g += BLOCK) {
-    const double* p = partials + (size_t)g * NV;
 #pragma unroll
-    for (int i = 0; i < NS; ++i) s[i] += p[i];
+    for (int i = 0; i < NS; ++i) s[i] += partials[(size_t)i * G + g];
 #pragma unroll
-    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], p[NS + i]);
+    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], partials[(size_t)(NS + i) * G + g]);
 #pragma unroll
-    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], p[NS + NM + i]);
+    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], partials[(size_t)(NS + NM + i) * G + g]);
   }
   block_reduce<NS, NM, NX, BLOCK>(s, mn, mx, lds, out);
 }
@@ -227,30 +238,36 @@ __device__ __forceinline__ void reduce_partials_ks(const double* partials, int G
 #pragma unroll
   for (int i = 0; i < NK; ++i) acc[i] = KeySum{inf_d(), 0.0};
   for (int g = threadIdx.x; g < G; g += BLOCK) {
-    const double* p = partials + (size_t)g * 2 * NK;
 #pragma unroll
-    for (int i = 0; i < NK; ++i) acc[i] = ks_min(acc[i], KeySum{p[2 * i], p[2 * i + 1]});
+    for (int i = 0; i < NK; ++i)
+      acc[i] = ks_min(acc[i], KeySum{partials[(size_t)(2 * i) * G + g],
+                                     partials[(size_t)(2 * i + 1) * G + g]});
   }
   block_ks_min<NK, BLOCK>(acc, lds, out);
 }
 
 // ---------------------------------------------------------------------------
-// Vector loads with a count guard (16-byte loads where the whole vector is in
-// range, element loads otherwise; out-of-range lanes get `fill`).
+// Vector loads with a count guard: one 16-byte load where the whole vector is
+// in range and its address is 16-byte aligned, element loads otherwise;
+// out-of-range lanes get `fill`.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool aligned16(const void* p) {
+  return ((uintptr_t)p & 15u) == 0;
+}
+
 template <typename T, int V>
 struct Vec;
 template <>
 struct Vec<double, 2> {
   static __device__ __forceinline__ void load(const double* p, int64_t i, int64_t n, double fill,
                                               double* o) {
-    if (i + 2 <= n) {
+    if (i + 2 <= n && aligned16(p + i)) {
       dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p + i));
       o[0] = v.x;
       o[1] = v.y;
     } else {
       o[0] = (i < n) ? p[i] : fill;
-      o[1] = fill;
+      o[1] = (i + 1 < n) ? p[i + 1] : fill;
     }
   }
 };
@@ -258,7 +275,7 @@ template <>
 struct Vec<float, 4> {
   static __device__ __forceinline__ void load(const float* p, int64_t i, int64_t n, double fill,
                                               double* o) {
-    if (i + 4 <= n) {
+    if (i + 4 <= n && aligned16(p + i)) {
       flt4 v = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(p + i));
       o[0] = v.x;
       o[1] = v.y;

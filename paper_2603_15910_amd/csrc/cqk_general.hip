@@ -37,6 +37,8 @@ namespace cqk {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRBlock = 1024;  // one-block reductions of partial records
+constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
 
 // Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
@@ -70,7 +72,8 @@ struct GenArgs {
   void* x;
   int64_t n;
   int64_t chunk;
-  double* buf[2][4];
+  double* buf[2];   // compacted sets: region r holds its four arrays at
+                    // buf[k] + (4 r + j) chunk, j = c, s, bl, bu
   int32_t* cnt[2];
   double* partials;
   GenState* st;
@@ -195,19 +198,23 @@ struct SrcForm {
   }
 };
 
+// One wave streams its own region.  Compaction writes the survivors of slot
+// e of every lane contiguously (ballot + lane prefix count), slot after slot,
+// so the layout is deterministic and needs no block-wide synchronisation.
 template <typename Src, bool COMPACT>
 __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, double hi,
-                          double* const* out, int32_t* out_cnt, Acc& acc, int* lds_i) {
+                          double* const* out, int32_t* out_cnt, Acc& acc) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
-  constexpr int64_t TILE = (int64_t)kBlock * E;
+  constexpr int64_t TILE = (int64_t)kWave * E;
+  const int lane = threadIdx.x & (kWave - 1);
   int64_t written = 0;
   for (int64_t base = 0; base < count; base += TILE) {
     double c[E], s[E], bl[E], bu[E];
     bool keep[E];
 #pragma unroll
     for (int w = 0; w < kUnroll; ++w) {
-      const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
       src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
@@ -217,26 +224,21 @@ __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, 
       }
     }
     if (COMPACT) {
-      int nk = 0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) nk += keep[e] ? 1 : 0;
-      int total;
-      const int off = block_excl_scan<kBlock>(nk, lds_i, &total);
-      int64_t pos = written + off;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
+        const uint64_t m = __ballot(keep[e]);
         if (keep[e]) {
+          const int64_t pos = written + lane_prefix(m);
           out[0][pos] = c[e];
           out[1][pos] = s[e];
           out[2][pos] = bl[e];
           out[3][pos] = bu[e];
-          ++pos;
         }
+        written += __popcll(m);
       }
-      written += total;
     }
   }
-  if (COMPACT && threadIdx.x == 0) {
+  if (COMPACT && lane == 0) {
     *out_cnt = (int32_t)written;
     acc.s[P_NOUT] += (double)written;
   }
@@ -246,12 +248,13 @@ template <typename Src>
 __device__ void bkpt_pass(const Src& src, int64_t count, double lam, KeySum* ks) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
-  constexpr int64_t TILE = (int64_t)kBlock * E;
+  constexpr int64_t TILE = (int64_t)kWave * E;
+  const int lane = threadIdx.x & (kWave - 1);
   for (int64_t base = 0; base < count; base += TILE) {
     double c[E], s[E], bl[E], bu[E];
 #pragma unroll
     for (int w = 0; w < kUnroll; ++w) {
-      const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
       double dummy = 0.0;
       src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], dummy);
 #pragma unroll
@@ -416,19 +419,23 @@ __device__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec*
   advance(st, next);
 }
 
+// One pass over the current index set.  Every block writes one partial
+// record; the scalar update runs in gen_update_kernel, so no block needs a
+// device-scope fence (the kernel boundary publishes the partials once).
 template <typename TIn>
-__global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
+__global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   GenState* st = A.st;
   if (st->status != kRunning) return;
   const int mode = st->mode;
   const int src = st->src;
   const bool compact = (mode == kModeEval) && (st->compact_next != 0);
   const double lam = st->lam, lo = st->lo, hi = st->hi;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk;
+  // each wave owns region rid of `chunk` indices
+  const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+  const int64_t off = (int64_t)rid * A.chunk;
 
   __shared__ double lds[NPART * (kBlock / kWave)];
   __shared__ double tot[NPART];
-  __shared__ int lds_i[kBlock / kWave + 1];
 
   Acc acc;
   acc_init(acc);
@@ -440,55 +447,66 @@ __global__ __launch_bounds__(kBlock) void gen_iter_kernel(GenArgs A) {
     if (mode != kModeEval) {
       bkpt_pass(s, count, lam, ks);
     } else if (compact) {
-      double* out[4] = {A.buf[0][0] + off, A.buf[0][1] + off, A.buf[0][2] + off, A.buf[0][3] + off};
-      eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + blockIdx.x, acc, lds_i);
+      double* rb = A.buf[0] + (size_t)rid * 4 * A.chunk;
+      double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
+      eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + rid, acc);
     } else {
-      eval_pass<SrcOrig<TIn>, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, lds_i);
+      eval_pass<SrcOrig<TIn>, false>(s, count, lam, lo, hi, nullptr, nullptr, acc);
     }
   } else {
     const int si = src - 1, di = 1 - si;
-    SrcForm s{A.buf[si][0] + off, A.buf[si][1] + off, A.buf[si][2] + off, A.buf[si][3] + off};
-    const int64_t count = A.cnt[si][blockIdx.x];
+    const double* sb = A.buf[si] + (size_t)rid * 4 * A.chunk;
+    SrcForm s{sb, sb + A.chunk, sb + 2 * A.chunk, sb + 3 * A.chunk};
+    const int64_t count = A.cnt[si][rid];
     if (mode != kModeEval) {
       bkpt_pass(s, count, lam, ks);
     } else if (compact) {
-      double* out[4] = {A.buf[di][0] + off, A.buf[di][1] + off, A.buf[di][2] + off,
-                        A.buf[di][3] + off};
-      eval_pass<SrcForm, true>(s, count, lam, lo, hi, out, A.cnt[di] + blockIdx.x, acc, lds_i);
+      double* rb = A.buf[di] + (size_t)rid * 4 * A.chunk;
+      double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
+      eval_pass<SrcForm, true>(s, count, lam, lo, hi, out, A.cnt[di] + rid, acc);
     } else {
-      eval_pass<SrcForm, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, lds_i);
+      eval_pass<SrcForm, false>(s, count, lam, lo, hi, nullptr, nullptr, acc);
     }
   }
 
   if (mode == kModeEval) {
     block_reduce<NSUM, 0, 0, kBlock>(acc.s, nullptr, nullptr, lds, tot);
     if (threadIdx.x == 0) {
-      double* p = A.partials + (size_t)blockIdx.x * NPART;
-      for (int i = 0; i < NPART; ++i) p[i] = tot[i];
-    }
-    if (last_block_arrives(&st->ticket)) {
-      reduce_partials<NSUM, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
-      if (threadIdx.x == 0) {
-        update_after_eval(st, tot, A.trace);
-        st->ticket = 0;
-      }
+      write_partial(A.partials, tot, NPART);
     }
   } else {
     __shared__ KeySum ktot[2];
     block_ks_min<2, kBlock>(ks, lds, ktot);
     if (threadIdx.x == 0) {
-      double* p = A.partials + (size_t)blockIdx.x * 4;
-      p[0] = ktot[0].k;
-      p[1] = ktot[0].w;
-      p[2] = ktot[1].k;
-      p[3] = ktot[1].w;
+      const double v[4] = {ktot[0].k, ktot[0].w, ktot[1].k, ktot[1].w};
+      write_partial(A.partials, v, 4);
     }
-    if (last_block_arrives(&st->ticket)) {
-      reduce_partials_ks<2, kBlock>(A.partials, gridDim.x, lds, ktot);
-      if (threadIdx.x == 0) {
-        update_after_bkpt(st, ktot, A.trace);
-        st->ticket = 0;
-      }
+  }
+}
+
+// Combines the G partial records of the pass in block order and runs the
+// scalar part of Algorithm 1 (one block).
+__global__ __launch_bounds__(kRBlock) void gen_update_kernel(GenArgs A, int G) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[NPART * (kRBlock / kWave)];
+  __shared__ double tot[NPART];
+  // the scalar update works on a register copy of the state record (one
+  // round trip to memory instead of one per field access)
+  if (st->mode == kModeEval) {
+    reduce_partials<NSUM, 0, 0, kRBlock>(A.partials, G, lds, tot);
+    if (threadIdx.x == 0) {
+      GenState s = *st;
+      update_after_eval(&s, tot, A.trace);
+      *st = s;
+    }
+  } else {
+    __shared__ KeySum ktot[2];
+    reduce_partials_ks<2, kRBlock>(A.partials, G, lds, ktot);
+    if (threadIdx.x == 0) {
+      GenState s = *st;
+      update_after_bkpt(&s, ktot, A.trace);
+      *st = s;
     }
   }
 }
@@ -500,8 +518,9 @@ __global__ __launch_bounds__(kBlock) void gen_lambda0_kernel(GenArgs A) {
   GenState* st = A.st;
   if (st->status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk;
-  const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
+  const int64_t bchunk = A.chunk * kWavesPerBlock;
+  const int64_t off = (int64_t)blockIdx.x * bchunk;
+  const int64_t count = max((int64_t)0, min(bchunk, A.n - off));
   SrcOrig<TIn> src{(const TIn*)A.d + off, (const TIn*)A.a + off, (const TIn*)A.b + off,
                    (const TIn*)A.l + off, (const TIn*)A.u + off};
   double sums[3] = {0.0, 0.0, 0.0};
@@ -520,23 +539,26 @@ __global__ __launch_bounds__(kBlock) void gen_lambda0_kernel(GenArgs A) {
   __shared__ double tot[3];
   block_reduce<3, 0, 0, kBlock>(sums, nullptr, nullptr, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * 3;
-    for (int i = 0; i < 3; ++i) p[i] = tot[i];
+    write_partial(A.partials, tot, 3);
   }
-  if (last_block_arrives(&st->ticket)) {
-    reduce_partials<3, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
-    if (threadIdx.x == 0) {
-      st->ticket = 0;
-      st->passes += 1;
-      if (tot[2] > 0.0) {
-        st->status = CQK_INVALID_ARG;
-      } else {
-        const double lam0 = (tot[1] > 0.0) ? (st->r - tot[0]) / tot[1] : 0.0;
-        st->lam = lam0;
-        st->lam0 = lam0;
-      }
-      trace_push(st, A.trace, 0, 0, 0, st->lam, tot[0], tot[1], A.n, 0);
+}
+
+__global__ __launch_bounds__(kRBlock) void gen_lambda0_update_kernel(GenArgs A, int G) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[3 * (kRBlock / kWave)];
+  __shared__ double tot[3];
+  reduce_partials<3, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x == 0) {
+    st->passes += 1;
+    if (tot[2] > 0.0) {
+      st->status = CQK_INVALID_ARG;
+    } else {
+      const double lam0 = (tot[1] > 0.0) ? (st->r - tot[0]) / tot[1] : 0.0;
+      st->lam = lam0;
+      st->lam0 = lam0;
     }
+    trace_push(st, A.trace, 0, 0, 0, st->lam, tot[0], tot[1], A.n, 0);
   }
 }
 
@@ -549,8 +571,9 @@ __global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
   if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
   constexpr int V = VecWidth<TIn>::value;
   const double lam = st->lam_final;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk;
-  const int64_t count = max((int64_t)0, min(A.chunk, A.n - off));
+  const int64_t bchunk = A.chunk * kWavesPerBlock;
+  const int64_t off = (int64_t)blockIdx.x * bchunk;
+  const int64_t count = max((int64_t)0, min(bchunk, A.n - off));
   const TIn* d = (const TIn*)A.d + off;
   const TIn* a = (const TIn*)A.a + off;
   const TIn* b = (const TIn*)A.b + off;
@@ -578,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
         sums[2] += (xr > vl[k] && xr < vu[k]) ? 1.0 : 0.0;
       }
     }
-    if (i + V <= count) {
+    if (i + V <= count && aligned16(x + i)) {
       if constexpr (V == 2) {
         dbl2 v;
         v.x = xo[0];
@@ -602,17 +625,21 @@ __global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
   __shared__ double tot[3];
   block_reduce<3, 0, 0, kBlock>(sums, nullptr, nullptr, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * 3;
-    for (int i = 0; i < 3; ++i) p[i] = tot[i];
+    write_partial(A.partials, tot, 3);
   }
-  if (last_block_arrives(&st->ticket)) {
-    reduce_partials<3, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
-    if (threadIdx.x == 0) {
-      st->ticket = 0;
-      st->res_P = tot[0];
-      st->res_A = tot[1];
-      st->n_free = (int64_t)tot[2];
-    }
+}
+
+__global__ __launch_bounds__(kRBlock) void gen_finalize_reduce_kernel(GenArgs A, int G) {
+  GenState* st = A.st;
+  const int status = st->status;
+  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
+  __shared__ double lds[3 * (kRBlock / kWave)];
+  __shared__ double tot[3];
+  reduce_partials<3, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x == 0) {
+    st->res_P = tot[0];
+    st->res_A = tot[1];
+    st->n_free = (int64_t)tot[2];
   }
 }
 
@@ -628,16 +655,19 @@ template <typename TIn>
 cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, const TIn* b,
                        const TIn* l, const TIn* u, double r, TIn* x, const cqk_opts& o,
                        cqk_info* info) {
+  // G blocks of kWavesPerBlock waves; wave region = `chunk` indices
   const int G0 = choose_grid(n, ctx->num_cus);
-  int64_t chunk = (n + G0 - 1) / G0;
+  int64_t chunk = (n + (int64_t)G0 * kWavesPerBlock - 1) / ((int64_t)G0 * kWavesPerBlock);
   chunk = (chunk + 7) / 8 * 8;
-  const int G = (int)((n + chunk - 1) / chunk);
-  const int64_t npad = (int64_t)G * chunk;
+  const int64_t bchunk = chunk * kWavesPerBlock;
+  const int G = (int)((n + bchunk - 1) / bchunk);
+  const int NR = G * kWavesPerBlock;
+  const int64_t npad = (int64_t)NR * chunk;
   const bool compaction = o.compaction != CQK_COMPACT_OFF;
 
   // workspace: partials | counts (2 x G) | buffers (2 x 4 x npad doubles)
   const size_t part_bytes = ((size_t)G * NPART * sizeof(double) + 255) / 256 * 256;
-  const size_t cnt_bytes = ((size_t)2 * G * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t cnt_bytes = ((size_t)2 * NR * sizeof(int32_t) + 255) / 256 * 256;
   const size_t buf_bytes = compaction ? (size_t)8 * npad * sizeof(double) : 0;
   cqk_status stt = ensure_buffer(ctx->ws, part_bytes + cnt_bytes + buf_bytes);
   if (stt != CQK_OK) return stt;
@@ -657,11 +687,11 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   A.chunk = chunk;
   A.partials = (double*)ws;
   A.cnt[0] = (int32_t*)(ws + part_bytes);
-  A.cnt[1] = A.cnt[0] + G;
+  A.cnt[1] = A.cnt[0] + NR;
   if (compaction) {
     double* bb = (double*)(ws + part_bytes + cnt_bytes);
-    for (int k = 0; k < 2; ++k)
-      for (int j = 0; j < 4; ++j) A.buf[k][j] = bb + (size_t)(k * 4 + j) * npad;
+    A.buf[0] = bb;
+    A.buf[1] = bb + (size_t)4 * npad;
   }
   A.st = (GenState*)ctx->state.ptr;
   A.trace = (cqk_trace_rec*)((char*)ctx->state.ptr + 1024);
@@ -696,15 +726,18 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   hipLaunchKernelGGL(gen_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   int ev = 0;
-  auto launch = [&](auto kern) {
+  // a grid pass (timed when asked) followed by its one-block reduction
+  auto launch = [&](auto kern, auto reduce) {
     if (o.timing && ev + 2 <= (int)nev) hipEventRecord(ctx->events[ev], s);
     hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), 0, s, A);
     if (o.timing && ev + 2 <= (int)nev) {
       hipEventRecord(ctx->events[ev + 1], s);
       ev += 2;
     }
+    hipLaunchKernelGGL(reduce, dim3(1), dim3(kRBlock), 0, s, A, G);
   };
-  if (o.lambda0_mode == CQK_LAMBDA0_FORMULA) launch(gen_lambda0_kernel<TIn>);
+  if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
+    launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel);
 
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
@@ -712,7 +745,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   int batch = 8;
   while (launched < max_launch) {
     const int k = std::min(batch, max_launch - launched);
-    for (int i = 0; i < k; ++i) launch(gen_iter_kernel<TIn>);
+    for (int i = 0; i < k; ++i) launch(gen_pass_kernel<TIn>, gen_update_kernel);
     launched += k;
     if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
       return CQK_DEVICE_ERROR;
@@ -721,7 +754,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     batch = 4;
   }
   const int pass_events = ev;
-  launch(gen_finalize_kernel<TIn>);
+  launch(gen_finalize_kernel<TIn>, gen_finalize_reduce_kernel);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
     return CQK_DEVICE_ERROR;

@@ -39,6 +39,8 @@ namespace cqk {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kRBlock = 1024;  // one-block reductions of partial records
+constexpr int kWaves = kBlock / kWave;
 constexpr int kCondatK = 16;  // values per thread per tile in Algorithm 2
 constexpr int kRefine = 8;    // block refinement rounds per tile
 
@@ -151,7 +153,7 @@ __device__ __forceinline__ uint32_t condat_thread(const TA* v, uint32_t active, 
 template <typename TIn>
 __device__ __forceinline__ void load_y(const TIn* y, int64_t i, int64_t n, TIn* o) {
   constexpr int V = VecWidth<TIn>::value;
-  if (i + V <= n) {
+  if (i + V <= n && aligned16(y + i)) {
     if constexpr (V == 4) {
       flt4 v = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(y + i));
       o[0] = v.x;
@@ -322,15 +324,23 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   double mx[1] = {vmax};
   block_reduce<C_NSUM, 1, 1, kBlock>(acc, mn, mx, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * C_NPART;
-    for (int i = 0; i < C_NPART; ++i) p[i] = tot[i];
+    write_partial(A.partials, tot, C_NPART);
   }
-  if (!last_block_arrives(&st->ticket)) return;
-  reduce_partials<C_NSUM, 1, 1, kBlock>(A.partials, gridDim.x, lds, tot);
+}
+
+// Merges the blocks of spx_condat_kernel (one block): lam_0 from the union of
+// the surviving sets, the smallest bound any block found, the l1 ball test,
+// and the prefix of the survivor counts for the gather.
+__global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[C_NPART * (kRBlock / kWave)];
+  __shared__ double tot[C_NPART];
+  __shared__ int lds_i[kRBlock / kWave + 1];
+  reduce_partials<C_NSUM, 1, 1, kRBlock>(A.partials, G, lds, tot);
   __shared__ int s_go;
   __shared__ int64_t s_m, s_ch;
   if (threadIdx.x == 0) {
-    st->ticket = 0;
     st->passes += 1;
     st->sum_abs = tot[C_ABS];
     st->vmax = tot[C_NSUM + 1];
@@ -349,7 +359,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       st->n_init = (int64_t)m;
       st->m = (int64_t)m;
       st->hi = lam0;
-      int64_t ch = ((int64_t)m + A.G2 - 1) / A.G2;
+      int64_t ch = ((int64_t)m + (int64_t)A.G2 * kWaves - 1) / ((int64_t)A.G2 * kWaves);
       ch = (ch + 7) / 8 * 8;
       if (ch < 8) ch = 8;
       st->chunk_src = ch;
@@ -365,18 +375,18 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   __syncthreads();
   if (!s_go) return;
   // exclusive scan of the per-block survivor counts, and the counts of the
-  // dense layout the Newton passes read (G2 regions of chunk_src)
+  // dense layout the Newton passes read (G2 x 4 wave regions of chunk_src)
   int64_t base = 0;
-  for (int g0 = 0; g0 < (int)gridDim.x; g0 += kBlock) {
+  for (int g0 = 0; g0 < G; g0 += kRBlock) {
     const int g = g0 + threadIdx.x;
-    const int cnt = (g < (int)gridDim.x) ? A.cnt[1][g] : 0;
+    const int cnt = (g < G) ? A.cnt[1][g] : 0;
     int totc;
-    const int ex = block_excl_scan<kBlock>(cnt, lds_i, &totc);
-    if (g < (int)gridDim.x) A.offs[g] = base + ex;
+    const int ex = block_excl_scan<kRBlock>(cnt, lds_i, &totc);
+    if (g < G) A.offs[g] = base + ex;
     base += totc;
   }
   const int64_t m = s_m, ch = s_ch;
-  for (int g = threadIdx.x; g < A.G2; g += kBlock) {
+  for (int g = threadIdx.x; g < A.G2 * kWaves; g += kRBlock) {
     const int64_t s0 = (int64_t)g * ch;
     A.cnt[0][g] = (int32_t)max((int64_t)0, min(ch, m - s0));
   }
@@ -432,13 +442,17 @@ __global__ __launch_bounds__(kBlock) void spx_formula_kernel(SpxArgs A) {
   __shared__ double tot[F_NSUM + 1];
   block_reduce<F_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * (F_NSUM + 1);
-    for (int i = 0; i < F_NSUM + 1; ++i) p[i] = tot[i];
+    write_partial(A.partials, tot, F_NSUM + 1);
   }
-  if (!last_block_arrives(&st->ticket)) return;
-  reduce_partials<F_NSUM, 0, 1, kBlock>(A.partials, gridDim.x, lds, tot);
+}
+
+__global__ __launch_bounds__(kRBlock) void spx_formula_update_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[(F_NSUM + 1) * (kRBlock / kWave)];
+  __shared__ double tot[F_NSUM + 1];
+  reduce_partials<F_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
   if (threadIdx.x == 0) {
-    st->ticket = 0;
     st->passes += 1;
     st->sum_abs = tot[F_ABS];
     st->vmax = tot[F_NSUM];
@@ -536,19 +550,22 @@ __device__ void spx_update(SpxState* st, const double* t, double vmax, cqk_trace
 }
 
 template <typename TIn, typename TA>
-__global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
+__global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   SpxState* st = A.st;
   if (st->status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
   constexpr int E = 2 * V;
-  constexpr int64_t TILE = (int64_t)kBlock * E;
+  constexpr int64_t TILE = (int64_t)kWave * E;
   const bool l1 = st->l1 != 0;
   const int src = st->src;
   const bool compact = st->compact_next != 0;
   const double lamd = st->lam;
   const TA lam = (TA)lamd;
-  const int64_t chunk = (src == 0) ? A.chunk0 : st->chunk_src;
-  const int64_t off = (int64_t)blockIdx.x * chunk;
+  // every wave streams its own region rid (deterministic layout, no barriers)
+  const int lane = threadIdx.x & (kWave - 1);
+  const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+  const int64_t chunk = (src == 0) ? A.chunk0 / kWaves : st->chunk_src;
+  const int64_t off = (int64_t)rid * chunk;
   int64_t count;
   const TIn* yv;
   const uint32_t* iv = nullptr;
@@ -560,7 +577,7 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
     yv = (const TIn*)A.y + off;
   } else {
     const int si = src - 1;
-    count = A.cnt[si][blockIdx.x];
+    count = A.cnt[si][rid];
     yv = (const TIn*)A.val[si] + off;
     iv = A.idx[si] + off;
   }
@@ -568,11 +585,10 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
     const int di = (src == 1) ? 1 : 0;
     ov = (TIn*)A.val[di] + off;
     oi = A.idx[di] + off;
-    ocnt = A.cnt[di] + blockIdx.x;
+    ocnt = A.cnt[di] + rid;
   }
   __shared__ double lds[(S_NSUM + 1) * (kBlock / kWave)];
   __shared__ double tot[S_NSUM + 1];
-  __shared__ int lds_i[kBlock / kWave + 1];
   TA phi = TA(0);
   double acc[S_NSUM] = {0, 0, 0, 0, 0, 0, 0};
   double vmax = -inf_d();
@@ -583,7 +599,7 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
     bool keep[E];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
-      const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
       load_y<TIn>(yv, i, count, &y[w * V]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
@@ -606,24 +622,19 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
       }
     }
     if (compact) {
-      int nk = 0;
-#pragma unroll
-      for (int e = 0; e < E; ++e) nk += keep[e] ? 1 : 0;
-      int total;
-      const int p0 = block_excl_scan<kBlock>(nk, lds_i, &total);
-      int64_t pos = written + p0;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
+        const uint64_t m = __ballot(keep[e]);
         if (keep[e]) {
+          const int64_t pos = written + lane_prefix(m);
           ov[pos] = y[e];
           oi[pos] = id[e];
-          ++pos;
         }
+        written += __popcll(m);
       }
-      written += total;
     }
   }
-  if (compact && threadIdx.x == 0) {
+  if (compact && lane == 0) {
     *ocnt = (int32_t)written;
     acc[S_NOUT] = (double)written;
   }
@@ -639,15 +650,25 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
     TA pb = phl[0];
     for (int w = 1; w < kBlock / kWave; ++w) pb += phl[w];
     tot[S_PHI] = (double)pb;
-    double* p = A.partials + (size_t)blockIdx.x * (S_NSUM + 1);
-    for (int i = 0; i < S_NSUM + 1; ++i) p[i] = tot[i];
+    write_partial(A.partials, tot, S_NSUM + 1);
   }
-  if (!last_block_arrives(&st->ticket)) return;
-  // grid level: phi summed in TA in block order, counts exactly in double
+}
+
+// One block: phi summed in TA in block order, counts exactly in double, then
+// Algorithm 4's update.
+template <typename TA>
+__global__ __launch_bounds__(kRBlock) void spx_update_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  const bool compact = st->compact_next != 0;
+  const int src = st->src;
+  __shared__ double lds[(S_NSUM + 1) * (kRBlock / kWave)];
+  __shared__ double tot[S_NSUM + 1];
+  __shared__ TA phl[kRBlock / kWave];
   TA pg = TA(0);
-  for (int g = threadIdx.x; g < (int)gridDim.x; g += kBlock)
-    pg += (TA)A.partials[(size_t)g * (S_NSUM + 1) + S_PHI];
-  reduce_partials<S_NSUM, 0, 1, kBlock>(A.partials, gridDim.x, lds, tot);
+  for (int g = threadIdx.x; g < G; g += kRBlock)
+    pg += (TA)A.partials[(size_t)S_PHI * G + g];
+  reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
   TA pw = pg;
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) pw += __shfl_xor(pw, o, kWave);
@@ -655,10 +676,11 @@ __global__ __launch_bounds__(kBlock) void spx_iter_kernel(SpxArgs A) {
   __syncthreads();
   if (threadIdx.x == 0) {
     TA pb = phl[0];
-    for (int w = 1; w < kBlock / kWave; ++w) pb += phl[w];
+    for (int w = 1; w < kRBlock / kWave; ++w) pb += phl[w];
     tot[S_PHI] = (double)pb;
-    st->ticket = 0;
-    spx_update(st, tot, tot[S_NSUM], A.trace, compact, src);
+    SpxState sc = *st;  // register copy: one round trip to memory
+    spx_update(&sc, tot, tot[S_NSUM], A.trace, compact, src);
+    *st = sc;
   }
 }
 
@@ -704,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
         }
       }
     }
-    if (i + V <= count) {
+    if (i + V <= count && aligned16(x + i)) {
       if constexpr (V == 4) {
         flt4 w;
         w.x = o[0];
@@ -728,18 +750,22 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
   __shared__ double tot[2];
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * 2;
-    p[0] = tot[0];
-    p[1] = tot[1];
+    write_partial(A.partials, tot, 2);
   }
-  if (!last_block_arrives(&st->ticket)) return;
-  reduce_partials<2, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
+}
+
+// Totals of the finalize (dense modes) or of the scatter (scatter mode).
+__global__ __launch_bounds__(kRBlock) void spx_fin_reduce_kernel(SpxArgs A, int G, int scatter) {
+  SpxState* st = A.st;
+  const int status = st->status;
+  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
+  if ((st->fin_mode == kFinScatter) != (scatter != 0)) return;
+  __shared__ double lds[2 * (kRBlock / kWave)];
+  __shared__ double tot[2];
+  reduce_partials<2, 0, 0, kRBlock>(A.partials, G, lds, tot);
   if (threadIdx.x == 0) {
-    st->ticket = 0;
-    if (mode != kFinScatter) {
-      st->res_P = tot[0];
-      st->n_free = (int64_t)tot[1];
-    }
+    st->res_P = tot[0];
+    st->n_free = (int64_t)tot[1];
   }
 }
 
@@ -754,13 +780,15 @@ __global__ __launch_bounds__(kBlock) void spx_scatter_kernel(SpxArgs A) {
   const bool l1 = st->l1 != 0;
   const TA lam = (TA)st->lam_final;
   const int si = st->src - 1;
-  const int64_t off = (int64_t)blockIdx.x * st->chunk_src;
-  const int64_t count = A.cnt[si][blockIdx.x];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+  const int64_t off = (int64_t)rid * st->chunk_src;
+  const int64_t count = A.cnt[si][rid];
   const TIn* v = (const TIn*)A.val[si] + off;
   const uint32_t* iv = A.idx[si] + off;
   TIn* x = (TIn*)A.x;
   double acc[2] = {0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < count; i += kBlock) {
+  for (int64_t i = lane; i < count; i += kWave) {
     const TA t = (TA)v[i];
     const TA z = (l1 ? absval(t) : t) + lam;
     TA xv = z > TA(0) ? z : TA(0);
@@ -774,16 +802,7 @@ __global__ __launch_bounds__(kBlock) void spx_scatter_kernel(SpxArgs A) {
   __shared__ double tot[2];
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
   if (threadIdx.x == 0) {
-    double* p = A.partials + (size_t)blockIdx.x * 2;
-    p[0] = tot[0];
-    p[1] = tot[1];
-  }
-  if (!last_block_arrives(&st->ticket)) return;
-  reduce_partials<2, 0, 0, kBlock>(A.partials, gridDim.x, lds, tot);
-  if (threadIdx.x == 0) {
-    st->ticket = 0;
-    st->res_P = tot[0];
-    st->n_free = (int64_t)tot[1];
+    write_partial(A.partials, tot, 2);
   }
 }
 
@@ -807,7 +826,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   if (n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
   const int G0i = grid0(n, ctx->num_cus);
   int64_t chunk0 = (n + G0i - 1) / G0i;
-  chunk0 = (chunk0 + 7) / 8 * 8;
+  chunk0 = (chunk0 + 31) / 32 * 32;  // wave regions of chunk0/4, multiples of 8
   const int G0 = (int)((n + chunk0 - 1) / chunk0);
   const int G2 = ctx->num_cus * 4;
   const int Gmax = std::max(G0, G2);
@@ -815,7 +834,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   const bool formula = o.lambda0_mode == CQK_LAMBDA0_FORMULA;
 
   const size_t part_bytes = ((size_t)Gmax * 8 * sizeof(double) + 255) / 256 * 256;
-  const size_t cnt_bytes = ((size_t)2 * Gmax * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t cnt_bytes = ((size_t)2 * Gmax * kWaves * sizeof(int32_t) + 255) / 256 * 256;
   const size_t offs_bytes = ((size_t)(G0 + 1) * sizeof(int64_t) + 255) / 256 * 256;
   const size_t cap = (size_t)G0 * chunk0;
   const size_t val_bytes = (cap * sizeof(TIn) + 255) / 256 * 256;
@@ -836,7 +855,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   A.chunk0 = chunk0;
   A.partials = (double*)ws;
   A.cnt[0] = (int32_t*)(ws + part_bytes);
-  A.cnt[1] = A.cnt[0] + Gmax;
+  A.cnt[1] = A.cnt[0] + Gmax * kWaves;
   A.offs = (int64_t*)(ws + part_bytes + cnt_bytes);
   if (need_bufs) {
     char* b = ws + part_bytes + cnt_bytes + offs_bytes;
@@ -861,7 +880,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   init.hi = __builtin_huge_val();
   init.cm_prev = -1.0;
   init.n_src = n;
-  init.chunk_src = chunk0;
+  init.chunk_src = chunk0 / kWaves;
   init.status = kRunning;
   init.max_iter = o.max_iter;
   init.compaction = o.compaction;
@@ -893,14 +912,20 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
       ev += 2;
     }
   };
+  // one-block reduction of the partial records of a grid of `grid` blocks
+  auto reduce = [&](auto kern, int grid) {
+    hipLaunchKernelGGL(kern, dim3(1), dim3(kRBlock), 0, s, A, grid);
+  };
   int G = G0;
   if (r != 0.0) {
     if (condat) {
       launch(spx_condat_kernel<TIn, TA>, G0);
+      reduce(spx_condat_merge_kernel, G0);
       launch(spx_gather_kernel<TIn>, G0);
       G = G2;
     } else if (formula) {
       launch(spx_formula_kernel<TIn>, G0);
+      reduce(spx_formula_update_kernel, G0);
     }
     if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
     SpxState* hs = (SpxState*)ctx->host_pinned;
@@ -909,7 +934,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     int batch = 6;
     while (launched < max_launch) {
       const int k = std::min(batch, max_launch - launched);
-      for (int i = 0; i < k; ++i) launch(spx_iter_kernel<TIn, TA>, G);
+      for (int i = 0; i < k; ++i) {
+        launch(spx_pass_kernel<TIn, TA>, G);
+        reduce(spx_update_kernel<TA>, G);
+      }
       launched += k;
       if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost, s)) != CQK_OK)
         return CQK_DEVICE_ERROR;
@@ -921,7 +949,9 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   const int work_events = ev;
   hipLaunchKernelGGL(spx_pick_fin_kernel, dim3(1), dim3(1), 0, s, A.st);
   launch(spx_finalize_kernel<TIn, TA>, G0);
+  hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0, 0);
   launch(spx_scatter_kernel<TIn, TA>, G);
+  hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G, 1);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   SpxState* hs = (SpxState*)ctx->host_pinned;
   if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost, s)) != CQK_OK)

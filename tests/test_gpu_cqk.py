@@ -193,3 +193,16 @@ def test_info_fields(ctx):
     assert info["n_free"] == int(np.sum((ref.x > inst["l"]) & (ref.x < inst["u"])))
     assert info["pass_bytes"] >= 40 * 100_000 * info["iterations"] * 0.2
     assert info["pass_ms"] > 0 and info["finalize_ms"] > 0
+
+
+@pytest.mark.parametrize("shift", [1, 3])
+def test_unaligned_views(ctx, shift):
+    inst = W.cqk_uniform(50_001, 14)
+    t = [torch.from_numpy(inst[k]).cuda()[shift:] for k in "dablu"]
+    sub = {k: inst[k][shift:] for k in "dablu"}
+    sub["r"] = float(np.dot(sub["b"], (sub["l"] + sub["u"]) / 2))
+    ref = O.solve_cqk(*[sub[k] for k in "dablu"], sub["r"])
+    xbuf = torch.empty(50_001, dtype=torch.float64, device="cuda")
+    x, info = ctx.solve(*t, sub["r"], out=xbuf[shift:], check=False)
+    assert info["status"] == 0
+    check_cqk(x.cpu().numpy(), sub, ref, 1e-10)

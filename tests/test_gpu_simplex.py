@@ -164,3 +164,20 @@ def test_other_radius(ctx):
         x, info = _run(ctx, y, r)
         assert info["status"] == 0
         check_simplex(x, y, x_ref, lam_ref, r, 1e-10)
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_unaligned_views(ctx, shift):
+    """Arrays that start at any element offset are accepted (the kernels fall
+    back to element accesses where a 16-byte access would be unaligned)."""
+    y = W.simplex_input(100_003, 12, "normal", np.float32)
+    base = torch.from_numpy(y).cuda()
+    yv = base[shift:]
+    xbuf = torch.empty(y.size, device="cuda")
+    xv = xbuf[shift:]
+    x_ref, lam_ref = _ref(y[shift:], 1.0)
+    for start in ("condat", "zero"):
+        xv.fill_(-1.0)
+        _, info = ctx.project_simplex(yv, 1.0, out=xv, lambda0=start)
+        assert info["status"] == 0
+        check_simplex(xv.cpu().numpy(), y[shift:], x_ref, lam_ref, 1.0, 1e-5)
