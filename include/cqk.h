@@ -195,6 +195,43 @@ cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
                                                     const float* g, float* grad_y,
                                                     double* grad_r, const cqk_opts* opts);
 
+/* How a batched call maps rows onto the GPU.  Rows of at most
+ * 64 * small_per values are solved by one wave each (their values stay in
+ * registers), longer rows by a workgroup of four waves.  blocks_per_cu
+ * persistent workgroups per compute unit pull rows from a device queue;
+ * short_first = 1 hands out the one-wave rows before the workgroup rows
+ * (which always go longest first). */
+typedef struct cqk_batch_schedule {
+  int32_t small_per;        /* 4 or 8 */
+  int32_t blocks_per_cu;    /* 1 .. 8 */
+  int32_t short_first;      /* 0 or 1 */
+  int32_t reserved;         /* 0 */
+} cqk_batch_schedule;
+
+/* The schedule the context uses for batched forward (backward = 0) or
+ * backward (backward = 1) calls; a new context starts with
+ * {8, 4, 0, 0}.  Set returns INVALID_ARG for a schedule outside the ranges
+ * above. */
+cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t backward, cqk_batch_schedule* out);
+cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t backward,
+                                  const cqk_batch_schedule* sched);
+
+/* Autotuner: runs cqk_project_simplex_batched_f32 on these rows under every
+ * candidate schedule (small_per in {4, 8} x blocks_per_cu in {1..4} x
+ * short_first in {0, 1}), `repeats` timed runs each after one warm-up, keeps
+ * the fastest as the context's forward schedule and returns it with its
+ * time in milliseconds (either pointer may be NULL).  x is overwritten.
+ * Synchronises the stream; not for use under graph capture. */
+cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const float* y, const double* r, double r_scalar, float* x,
+                                int32_t repeats, cqk_batch_schedule* best, double* best_ms);
+/* The same for the backward call (x: forward output, g: upstream gradient,
+ * grad_y overwritten); sets the context's backward schedule. */
+cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                         const float* x, const float* g, float* grad_y,
+                                         int32_t repeats, cqk_batch_schedule* best,
+                                         double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

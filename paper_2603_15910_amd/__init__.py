@@ -134,6 +134,32 @@ def cqk_project_simplex_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, g
                  g, grad_y, grad_r, C.byref(opts) if opts is not None else None)
 
 
+def cqk_get_batch_schedule(ctx, backward=0):
+    sc = L.cqk_batch_schedule()
+    st = _call("cqk_get_batch_schedule", C.c_void_p(ctx), int(backward), C.byref(sc))
+    return st, sc
+
+
+def cqk_set_batch_schedule(ctx, backward, sched):
+    return _call("cqk_set_batch_schedule", C.c_void_p(ctx), int(backward), C.byref(sched))
+
+
+def cqk_tune_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, repeats=3):
+    sc = L.cqk_batch_schedule()
+    ms = C.c_double(0.0)
+    st = _call("cqk_tune_batched_f32", C.c_void_p(ctx), nseg, offsets, y, r, r_scalar, x,
+               int(repeats), C.byref(sc), C.byref(ms))
+    return st, sc, ms.value
+
+
+def cqk_tune_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, repeats=3):
+    sc = L.cqk_batch_schedule()
+    ms = C.c_double(0.0)
+    st = _call("cqk_tune_batched_backward_f32", C.c_void_p(ctx), nseg, offsets, x, g, grad_y,
+               int(repeats), C.byref(sc), C.byref(ms))
+    return st, sc, ms.value
+
+
 # ---------------------------------------------------------------------------
 # torch-tensor helpers
 # ---------------------------------------------------------------------------
@@ -288,6 +314,54 @@ class Context:
         if check and st != CQK_OK:
             raise CqkError(st, "cqk_project_simplex_batched_backward_f32")
         return gy
+
+
+    def batch_schedule(self, backward=False):
+        """The context's batched schedule as a dict."""
+        st, sc = cqk_get_batch_schedule(self.handle, 1 if backward else 0)
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_get_batch_schedule")
+        return sc.as_dict()
+
+    def set_batch_schedule(self, small_per=8, blocks_per_cu=4, short_first=0, backward=False):
+        sc = L.cqk_batch_schedule(int(small_per), int(blocks_per_cu), int(short_first), 0)
+        st = cqk_set_batch_schedule(self.handle, 1 if backward else 0, sc)
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_set_batch_schedule")
+
+    def tune_batched(self, y, offsets, r=1.0, repeats=3, out=None):
+        """Times every candidate schedule on these rows and keeps the fastest
+        for later batched forward calls; returns (schedule dict, ms)."""
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        x = out if out is not None else torch.empty_like(y)
+        py = _dev_ptr(y, torch.float32, "y")
+        px = _dev_ptr(x, torch.float32, "x")
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        if torch.is_tensor(r):
+            pr, rs = _dev_ptr(r, torch.float64, "r"), 0.0
+        else:
+            pr, rs = None, float(r)
+        self._bind_stream()
+        st, sc, ms = cqk_tune_batched_f32(self.handle, nseg, po, py, pr, rs, px, repeats)
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_tune_batched_f32")
+        return sc.as_dict(), ms
+
+    def tune_batched_backward(self, x, g, offsets, repeats=3, grad_y=None):
+        """The same for the backward call; returns (schedule dict, ms)."""
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        gy = grad_y if grad_y is not None else torch.empty_like(g)
+        px = _dev_ptr(x, torch.float32, "x")
+        pg = _dev_ptr(g, torch.float32, "g")
+        pgy = _dev_ptr(gy, torch.float32, "grad_y")
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        self._bind_stream()
+        st, sc, ms = cqk_tune_batched_backward_f32(self.handle, nseg, po, px, pg, pgy, repeats)
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_tune_batched_backward_f32")
+        return sc.as_dict(), ms
 
 
 _ctx_lock = threading.Lock()

@@ -89,6 +89,18 @@ class cqk_trace_rec(C.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
+class cqk_batch_schedule(C.Structure):
+    _fields_ = [
+        ("small_per", C.c_int32),
+        ("blocks_per_cu", C.c_int32),
+        ("short_first", C.c_int32),
+        ("reserved", C.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "reserved"}
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _I32 = C.c_int32
@@ -115,6 +127,14 @@ SIGNATURES = {
         C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _P, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_backward_f32": (
         C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _OPTS]),
+    "cqk_get_batch_schedule": (C.c_int, [_P, _I32, C.POINTER(cqk_batch_schedule)]),
+    "cqk_set_batch_schedule": (C.c_int, [_P, _I32, C.POINTER(cqk_batch_schedule)]),
+    "cqk_tune_batched_f32": (
+        C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _I32, C.POINTER(cqk_batch_schedule),
+                  C.POINTER(_D)]),
+    "cqk_tune_batched_backward_f32": (
+        C.c_int, [_P, _I32, _P, _P, _P, _P, _I32, C.POINTER(cqk_batch_schedule),
+                  C.POINTER(_D)]),
 }
 
 _lib = None

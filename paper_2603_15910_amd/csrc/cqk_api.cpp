@@ -283,4 +283,38 @@ cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
   return run_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, grad_r, o);
 }
 
+cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t backward, cqk_batch_schedule* out) {
+  if (!ctx || !out || (backward != 0 && backward != 1)) return CQK_INVALID_ARG;
+  *out = backward ? ctx->sched_bwd : ctx->sched_fwd;
+  return CQK_OK;
+}
+
+cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t backward,
+                                  const cqk_batch_schedule* sched) {
+  if (!ctx || !sched || (backward != 0 && backward != 1)) return CQK_INVALID_ARG;
+  if (!valid_schedule(*sched)) return CQK_INVALID_ARG;
+  (backward ? ctx->sched_bwd : ctx->sched_fwd) = *sched;
+  return CQK_OK;
+}
+
+cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const float* y, const double* r, double r_scalar, float* x,
+                                int32_t repeats, cqk_batch_schedule* best, double* best_ms) {
+  if (!ctx || nseg <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
+  if (!offsets || !y || !x) return CQK_INVALID_ARG;
+  if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return tune_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, repeats, best, best_ms);
+}
+
+cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                         const float* x, const float* g, float* grad_y,
+                                         int32_t repeats, cqk_batch_schedule* best,
+                                         double* best_ms) {
+  if (!ctx || nseg <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
+  if (!offsets || !x || !g || !grad_y) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return tune_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, repeats, best, best_ms);
+}
+
 }  // extern "C"

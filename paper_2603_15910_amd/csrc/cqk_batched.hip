@@ -9,16 +9,25 @@
 //   dx_S/dy_S = I - 11^T/|S|,  dx_S/dr = 1/|S|,
 //   grad_y = [x > 0](g - mean_S g),  grad_r = mean_S g.
 //
-// Schedule.  Rows are classified on the device by length: long rows (more
-// than kSmallMax values) get a whole 256-thread workgroup, short rows one
-// wave each (four per workgroup).  Long rows are listed by decreasing length
-// bucket (longest first); one persistent kernel pulls work items from an
-// atomic counter until the list is exhausted.  A long row is read once from
-// HBM: each thread runs Algorithm 2 on 16 values per tile, the block refines
-// the tile's bound and appends the surviving values to an LDS list; Newton
-// runs on that list; x is then written densely (the row is re-read from
-// cache; a row of one tile keeps its values in registers).  A short row
-// stays in registers from load to store.
+// Schedule.  Rows are classified on the device by length: rows of at most
+// 64 * small_per values go to one wave each (four per workgroup), longer rows
+// get a whole workgroup.  Workgroup rows are listed by decreasing length
+// bucket; one persistent kernel pulls work items from an atomic counter
+// (wave rows first or workgroup rows first) until the list is exhausted.
+// small_per, the number of persistent workgroups per compute unit and that
+// order form the schedule, which the tuner picks by timing every candidate
+// on the caller's rows.
+//
+// A workgroup row is read once from HBM and x written once: each wave takes
+// every fourth tile of 1024 values, writes zeros to that part of x, runs
+// Algorithm 2 on 16 values per lane and keeps only the values above its
+// running bound (wave reductions only), appending them with their indices to
+// its LDS list.  After one barrier every wave combines the four lists'
+// bounds, refines the start at 12 candidate points, runs Algorithm 4 on the
+// lists (all waves get the same multiplier) and writes x for its own list's
+// entries; every other x is the zero already written.  The backward pass
+// does the same with the support: zeros first, then g - mean_S g on S.
+// A wave row keeps its values in registers from load to store.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -31,19 +40,20 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kK = 16;              // values per thread per tile (long rows)
-constexpr int kTile = kBlock * kK;  // 4096
-constexpr int kSmallPer = 8;        // values per lane (short rows)
-constexpr int kSmallMax = kWave * kSmallPer;  // 512
-constexpr int kLdsCap = 6144;       // survivor values kept in LDS per long row
-constexpr int kNB = 24;             // length buckets (bucket 0: short rows)
+constexpr int kK = 16;               // values per lane per wave tile (workgroup rows)
+constexpr int kWTile = kWave * kK;   // 1024
+constexpr int kSurvW = 1024;         // LDS list slots per wave (value + index)
+constexpr int kNB = 24;              // length buckets (bucket 0: wave rows)
 constexpr int kRefine = 8;
 constexpr int kMaxNewton = 100;
+constexpr int kCand = 12;            // start refinement candidates
 
 enum BatFlags : int32_t { kBadRadius = 1, kBadValue = 2, kInfeasible = 4 };
 
 struct BatArgs {
   int32_t nseg;
+  int32_t small_max;    // longest wave row
+  int32_t short_first;  // 1: wave rows are handed out first
   const int64_t* off;
   const float* y;
   const double* r;
@@ -54,21 +64,20 @@ struct BatArgs {
   const float* g;       // backward: upstream gradient
   float* gy;            // backward: grad_y
   double* gr;           // backward: grad_r
-  int32_t* list;        // row ids: long rows by bucket, then short rows
+  int32_t* list;        // row ids: workgroup rows by bucket, then wave rows
   int32_t* counters;    // [0,kNB) counts, [kNB,2kNB) cursors, [2kNB,3kNB) bases,
                         // 3kNB: n_long, +1: n_short, +2: n_items, +3: queue, +4: flags,
                         // +5: ticket, +6: survivors total, +7: overflow rows
-  double* partials;
 };
 
 constexpr int CTR_NLONG = 3 * kNB, CTR_NSHORT = 3 * kNB + 1, CTR_NITEMS = 3 * kNB + 2,
               CTR_QUEUE = 3 * kNB + 3, CTR_FLAGS = 3 * kNB + 4, CTR_TICKET = 3 * kNB + 5,
               CTR_SURV = 3 * kNB + 6, CTR_OVER = 3 * kNB + 7, CTR_TOTAL = 3 * kNB + 8;
 
-__device__ __forceinline__ int bucket_of(int64_t L) {
-  if (L <= kSmallMax) return 0;
-  int b = 64 - __clzll((unsigned long long)L);  // bit length, >= 10 here
-  b = b - 9;                                   // 1 .. for L > 512
+__device__ __forceinline__ int bucket_of(int64_t L, int small_max) {
+  if (L <= small_max) return 0;
+  int b = 64 - __clzll((unsigned long long)L) - 8;  // bit length - 8
+  b = b < 1 ? 1 : b;
   return b >= kNB ? kNB - 1 : b;
 }
 
@@ -80,13 +89,13 @@ __global__ __launch_bounds__(kBlock) void bat_count_kernel(BatArgs A) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s < A.nseg) {
     const int64_t L = A.off[s + 1] - A.off[s];
-    atomicAdd(&A.counters[bucket_of(L)], 1);
+    atomicAdd(&A.counters[bucket_of(L, A.small_max)], 1);
     __threadfence();
   }
   if (!last_block_arrives((uint32_t*)&A.counters[CTR_TICKET])) return;
   if (threadIdx.x == 0) {
     int base = 0;
-    for (int b = kNB - 1; b >= 1; --b) {  // long rows, longest bucket first
+    for (int b = kNB - 1; b >= 1; --b) {  // workgroup rows, longest bucket first
       A.counters[2 * kNB + b] = base;
       base += A.counters[b];
     }
@@ -103,7 +112,7 @@ __global__ __launch_bounds__(kBlock) void bat_place_kernel(BatArgs A) {
   const int s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= A.nseg) return;
   const int64_t L = A.off[s + 1] - A.off[s];
-  const int b = bucket_of(L);
+  const int b = bucket_of(L, A.small_max);
   const int pos = A.counters[2 * kNB + b] + atomicAdd(&A.counters[kNB + b], 1);
   A.list[pos] = s;
 }
@@ -112,25 +121,16 @@ __device__ __forceinline__ double row_radius(const BatArgs& A, int s) {
   return A.r ? A.r[s] : A.r_scalar;
 }
 
-// Sum of an int and two doubles over the block; every thread gets the totals.
+// Block sum of three doubles; every thread gets the totals.
 __device__ __forceinline__ void block_sum3(double a, double b, double c, double* lds, double* o) {
   __shared__ double bc[3];
   double in[3] = {a, b, c};
-  double tot[3];
-  block_reduce<3, 0, 0, kBlock>(in, nullptr, nullptr, lds, tot);
-  if (threadIdx.x == 0) {
-    bc[0] = tot[0];
-    bc[1] = tot[1];
-    bc[2] = tot[2];
-  }
-  __syncthreads();
+  block_reduce<3, 0, 0, kBlock>(in, nullptr, nullptr, lds, bc);
   o[0] = bc[0];
   o[1] = bc[1];
   o[2] = bc[2];
   __syncthreads();
 }
-
-__device__ __forceinline__ double wave_sum_d(double v) { return wave_sum(v); }
 
 // Algorithm 2 over K values (division-free comparisons, see the simplex
 // kernels): returns the J mask, its count and sum.
@@ -176,17 +176,145 @@ __device__ __forceinline__ uint32_t alg2(const float* v, uint32_t active, float 
   return J;
 }
 
+// LDS of one workgroup: the four waves' lists and their bound records.
+struct BatLds {
+  float sv[kWaves][kSurvW];
+  int32_t si[kWaves][kSurvW];
+  double ws[kWaves][8];
+  double red[3 * kWaves];
+  int item;
+};
+
+enum { W_C = 0, W_S, W_LMIN, W_VMAX, W_BAD, W_N, W_NF };
+
+// One wave's share of Algorithm 2 on a tile of kK values per lane already in
+// registers (v, active): the lanes' sets, the wave's bound refined against
+// its running survivors (run_c, run_s), the values kept.  Returns the keep
+// mask; nk/ks are the lane's kept count and sum; lam_min takes the new bound.
+__device__ __forceinline__ uint32_t wave_tile_alg2(const float* v, uint32_t active, double rd,
+                                                   double run_c, double run_s, double& lam_min,
+                                                   double& nk, double& ks) {
+  const float r = (float)rd;
+  int c = 0;
+  float S = 0.f;
+  uint32_t J;
+  if (__ballot(__popc(active) > 1) != 0) {
+    J = alg2<kK>(v, active, r, c, S);
+  } else {
+    // at most one value per lane: Algorithm 2 keeps it
+    J = active;
+    c = __popc(active);
+#pragma unroll
+    for (int e = 0; e < kK; ++e)
+      if ((active >> e) & 1u) S = v[e];
+  }
+  const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
+  // every bound below is lam_J of a non-empty J, hence >= lam* (eq. (lambdaJ))
+  const double ct = wave_sum((double)c), skt = wave_sum((double)S);
+  double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
+  if (ct > 0.0 && run_c > 0.0) lam_b = fmin(lam_b, (rd - (skt + run_s)) / (ct + run_c));
+  if (run_c > 0.0) lam_b = fmin(lam_b, (rd - run_s) / run_c);
+  uint32_t keep = 0;
+  auto select = [&](double lb) {
+    const double lt = fmin(lam_t, lb);
+    keep = 0;
+    nk = 0.0;
+    ks = 0.0;
+#pragma unroll
+    for (int e = 0; e < kK; ++e) {
+      if (((J >> e) & 1u) && ((double)v[e] + lt > 0.0)) {
+        keep |= 1u << e;
+        nk += 1.0;
+        ks += (double)v[e];
+      }
+    }
+  };
+  for (int it = 0; it < kRefine; ++it) {
+    select(lam_b);
+    const double kc = wave_sum(nk), kss = wave_sum(ks);
+    if (kc == 0.0) break;
+    double nl = (rd - kss) / kc;
+    if (run_c > 0.0) nl = fmin(nl, (rd - (kss + run_s)) / (kc + run_c));
+    if (!(nl < lam_b)) break;
+    lam_b = nl;
+  }
+  select(lam_b);
+  lam_min = fmin(lam_min, lam_b);
+  return keep;
+}
+
+// Loads four floats of a row (count-guarded, 16-byte where aligned).
+__device__ __forceinline__ void load4(const float* p, int64_t i, int64_t n, float* o) {
+  if (i + 4 <= n && aligned16(p + i)) {
+    flt4 w = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(p + i));
+    o[0] = w.x;
+    o[1] = w.y;
+    o[2] = w.z;
+    o[3] = w.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) o[k] = (i + k < n) ? p[i + k] : 0.f;
+  }
+}
+
+__device__ __forceinline__ void zero4(float* p, int64_t i, int64_t n) {
+  if (i + 4 <= n && aligned16(p + i)) {
+    flt4 z = {0.f, 0.f, 0.f, 0.f};
+    __builtin_nontemporal_store(z, reinterpret_cast<flt4*>(p + i));
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (i + k < n) p[i + k] = 0.f;
+  }
+}
+
+// Algorithm 4 from lam (>= lam*) on the four LDS lists, run by one wave:
+// lam_{k+1} = lam_J(J_k), J_k = {v + lam_k > 0}; stops as the paper's
+// Algorithm 4 (phi(lam_k) <= r for k >= 1) or when J no longer changes.
+__device__ __forceinline__ double wave_newton_lists(const BatLds& L, const int* nw, double rd,
+                                                    double lam) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double prev_c = -1.0;
+  for (int it = 0; it < kMaxNewton; ++it) {
+    double cc = 0.0, ss = 0.0, ph = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      for (int i = lane; i < nw[w]; i += kWave) {
+        const double v = (double)L.sv[w][i];
+        const double z = v + lam;
+        if (z > 0.0) {
+          cc += 1.0;
+          ss += v;
+          ph += z;
+        }
+      }
+    }
+    cc = wave_sum(cc);
+    ss = wave_sum(ss);
+    ph = wave_sum(ph);
+    if (cc == prev_c) break;
+    if (it > 0 && ph <= rd) break;
+    if (cc == 0.0) break;
+    const double nl = (rd - ss) / cc;
+    if (!(nl < lam)) break;
+    prev_c = cc;
+    lam = nl;
+  }
+  return lam;
+}
+
 // ---------------------------------------------------------------------------
-// One long row, whole workgroup.
+// One workgroup row.
 // ---------------------------------------------------------------------------
-__device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv, int* lds_i) {
+__device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
   const int64_t base = A.off[s];
-  const int64_t L = A.off[s + 1] - base;
+  const int64_t n = A.off[s + 1] - base;
   const double rd = row_radius(A, s);
   const float* y = A.y + base;
   float* x = A.x + base;
   if (!(rd >= 0.0) || !(rd < inf_d())) {
-    for (int64_t i = threadIdx.x; i < L; i += kBlock) x[i] = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) x[i] = 0.f;
     if (threadIdx.x == 0) {
       atomicOr(&A.counters[CTR_FLAGS], kBadRadius);
       if (A.lam_out) A.lam_out[s] = __builtin_nan("");
@@ -194,117 +322,102 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
     }
     return;
   }
-  const float r = (float)rd;
-  const bool single = L <= kTile;
-  double run_c = 0.0, run_s = 0.0, lam_min = inf_d(), bad = 0.0;
-  int nsurv = 0;  // block-uniform
-  bool overflow = false;
-  float v[kK];
-  for (int64_t t0 = 0; t0 < L; t0 += kTile) {
+  // wave-uniform running state: survivors kept, smallest bound found
+  double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
+  float vmx = -__builtin_huge_valf();
+  int nbad = 0;
+  int nw = 0;
+  const int64_t ntiles = (n + kWTile - 1) / kWTile;
+  for (int64_t t = wid; t < ntiles; t += kWaves) {
+    const int64_t t0 = t * kWTile;
+    float v[kK];
     uint32_t active = 0;
 #pragma unroll
     for (int q = 0; q < kK / 4; ++q) {
-      const int64_t i = t0 + (int64_t)q * kBlock * 4 + (int64_t)threadIdx.x * 4;
-      if (i + 4 <= L && aligned16(y + i)) {
-        flt4 w = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(y + i));
-        v[4 * q] = w.x;
-        v[4 * q + 1] = w.y;
-        v[4 * q + 2] = w.z;
-        v[4 * q + 3] = w.w;
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) v[4 * q + k] = (i + k < L) ? y[i + k] : 0.f;
-      }
+      const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+      load4(y, i, n, &v[4 * q]);
+      // x is zero wherever the lists below do not write it
+      zero4(x, i, n);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        if (i + k < L) {
+        if (i + k < n) {
           active |= 1u << (4 * q + k);
-          bad += (fabsf(v[4 * q + k]) < __builtin_huge_valf()) ? 0.0 : 1.0;
+          nbad += (fabsf(v[4 * q + k]) < __builtin_huge_valf()) ? 0 : 1;
+          vmx = fmaxf(vmx, v[4 * q + k]);
         }
       }
     }
-    int c;
-    float S;
-    const uint32_t J = alg2<kK>(v, active, r, c, S);
-    const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
-    double tt[3];
-    block_sum3((double)c, (double)S, 0.0, lds, tt);
-    double lam_b = (tt[0] > 0) ? (rd - tt[1]) / tt[0] : inf_d();
-    if (tt[0] > 0 && run_c > 0) lam_b = fmin(lam_b, (rd - (tt[1] + run_s)) / (tt[0] + run_c));
-    if (run_c > 0) lam_b = fmin(lam_b, (rd - run_s) / run_c);
-    uint32_t keep = 0;
-    int nk = 0;
-    double ks = 0.0;
-    auto select = [&](double lb) {
-      const double lt = fmin(lam_t, lb);
-      keep = 0;
-      nk = 0;
-      ks = 0.0;
-#pragma unroll
-      for (int e = 0; e < kK; ++e) {
-        if (((J >> e) & 1u) && ((double)v[e] + lt > 0.0)) {
-          keep |= 1u << e;
-          ++nk;
-          ks += (double)v[e];
-        }
-      }
-    };
-    for (int it = 0; it < kRefine; ++it) {
-      select(lam_b);
-      block_sum3((double)nk, ks, 0.0, lds, tt);
-      if (tt[0] == 0.0) break;
-      double nl = (rd - tt[1]) / tt[0];
-      if (run_c > 0) nl = fmin(nl, (rd - (tt[1] + run_s)) / (tt[0] + run_c));
-      if (!(nl < lam_b)) break;
-      lam_b = nl;
-    }
-    select(lam_b);
-    int total;
-    const int p0 = block_excl_scan<kBlock>(nk, lds_i, &total);
-    if (!overflow && nsurv + total <= kLdsCap) {
-      int p = nsurv + p0;
+    // values at or below the wave's best bound so far are zero at the solution
+    if (lam_min < inf_d()) {
 #pragma unroll
       for (int e = 0; e < kK; ++e)
-        if ((keep >> e) & 1u) surv[p++] = v[e];
-      nsurv += total;
-    } else {
-      overflow = true;
+        if (!((double)v[e] + lam_min > 0.0)) active &= ~(1u << e);
     }
-    block_sum3((double)nk, ks, 0.0, lds, tt);
-    run_c += tt[0];
-    run_s += tt[1];
-    lam_min = fmin(lam_min, lam_b);
-    if (run_c > 0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
+    if (__ballot(active != 0u) == 0) continue;
+    double nk, ks;
+    const uint32_t keep = wave_tile_alg2(v, active, rd, run_c, run_s, lam_min, nk, ks);
+    if (__ballot(keep != 0u) == 0) continue;
+#pragma unroll
+    for (int e = 0; e < kK; ++e) {
+      const bool kb = (keep >> e) & 1u;
+      const uint64_t m = __ballot(kb);
+      if (kb) {
+        const int pos = nw + lane_prefix(m);
+        if (pos < kSurvW) {
+          L.sv[wid][pos] = v[e];
+          L.si[wid][pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
+        }
+      }
+      nw += __popcll(m);
+    }
+    run_c += wave_sum(nk);
+    run_s += wave_sum(ks);
+    if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
   }
-  double tb[3];
-  block_sum3(bad, 0.0, 0.0, lds, tb);
-  if (tb[0] > 0.0 || L == 0 || rd == 0.0) {
-    for (int64_t i = threadIdx.x; i < L; i += kBlock) x[i] = 0.f;
+  const double wbad = wave_sum((double)nbad);
+  const double wmax = wave_max((double)vmx);
+  if (lane == 0) {
+    L.ws[wid][W_C] = run_c;
+    L.ws[wid][W_S] = run_s;
+    L.ws[wid][W_LMIN] = lam_min;
+    L.ws[wid][W_VMAX] = wmax;
+    L.ws[wid][W_BAD] = wbad;
+    L.ws[wid][W_N] = (double)nw;
+  }
+  __syncthreads();
+  // every wave combines the four records in the same order
+  double C = 0.0, S = 0.0, lmin = inf_d(), vmax = -inf_d(), bad = 0.0;
+  bool over = false;
+  int nws[kWaves];
+  int ntot = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    C += L.ws[w][W_C];
+    S += L.ws[w][W_S];
+    lmin = fmin(lmin, L.ws[w][W_LMIN]);
+    vmax = fmax(vmax, L.ws[w][W_VMAX]);
+    bad += L.ws[w][W_BAD];
+    nws[w] = (int)L.ws[w][W_N];
+    over = over || nws[w] > kSurvW;
+    ntot += nws[w];
+  }
+  if (bad > 0.0 || n == 0 || rd == 0.0) {
+    // x is already zero
     if (threadIdx.x == 0) {
-      if (tb[0] > 0.0) atomicOr(&A.counters[CTR_FLAGS], kBadValue);
-      if (L == 0 && rd > 0.0) atomicOr(&A.counters[CTR_FLAGS], kInfeasible);
-      if (A.lam_out) A.lam_out[s] = (tb[0] > 0.0 || L == 0) ? __builtin_nan("") : 0.0;
+      if (bad > 0.0) atomicOr(&A.counters[CTR_FLAGS], kBadValue);
+      if (n == 0 && rd > 0.0) atomicOr(&A.counters[CTR_FLAGS], kInfeasible);
+      if (A.lam_out) A.lam_out[s] = (bad > 0.0 || n == 0) ? __builtin_nan("") : 0.0;
       if (A.nfree_out) A.nfree_out[s] = 0;
     }
     return;
   }
-  __syncthreads();  // survivors in LDS visible to every thread
-  // Algorithm 4 from lam_0 >= lam*: lam_{k+1} = lam_J(J_k), J_k = {y + lam_k > 0}
-  double lam = lam_min;
-  double prev_c = -1.0;
-  for (int it = 0; it < kMaxNewton; ++it) {
-    double cc = 0.0, ss = 0.0, ph = 0.0;
-    if (!overflow) {
-      for (int i = threadIdx.x; i < nsurv; i += kBlock) {
-        const double z = (double)surv[i] + lam;
-        if (z > 0.0) {
-          cc += 1.0;
-          ss += (double)surv[i];
-          ph += z;
-        }
-      }
-    } else {
-      for (int64_t i = threadIdx.x; i < L; i += kBlock) {
+  const double lam0 = (C > 0.0) ? fmin((rd - S) / C, lmin) : lmin;
+  if (over) {
+    // a list overflowed: Algorithm 4 over the row itself (re-read from cache)
+    double lam = lam0, prev_c = -1.0;
+    for (int it = 0; it < kMaxNewton; ++it) {
+      double cc = 0.0, ss = 0.0, ph = 0.0;
+      for (int64_t i = threadIdx.x; i < n; i += kBlock) {
         const double yv = (double)y[i];
         const double z = yv + lam;
         if (z > 0.0) {
@@ -313,74 +426,84 @@ __device__ void solve_long_row(const BatArgs& A, int s, double* lds, float* surv
           ph += z;
         }
       }
+      double tt[3];
+      block_sum3(cc, ss, ph, L.red, tt);
+      if (tt[0] == prev_c) break;
+      if (it > 0 && tt[2] <= rd) break;
+      if (tt[0] == 0.0) break;
+      const double nl = (rd - tt[1]) / tt[0];
+      if (!(nl < lam)) break;
+      prev_c = tt[0];
+      lam = nl;
     }
-    double tt[3];
-    block_sum3(cc, ss, ph, lds, tt);
-    if (tt[0] == prev_c) break;
-    if (it > 0 && tt[2] <= rd) break;
-    if (tt[0] == 0.0) break;
-    const double nl = (rd - tt[1]) / tt[0];
-    if (!(nl < lam)) break;
-    prev_c = tt[0];
-    lam = nl;
+    double nf = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) {
+      const float o = (float)fmax((double)y[i] + lam, 0.0);
+      nf += (o > 0.f) ? 1.0 : 0.0;
+      x[i] = o;
+    }
+    double tn[3];
+    block_sum3(nf, 0.0, 0.0, L.red, tn);
+    if (threadIdx.x == 0) {
+      if (A.lam_out) A.lam_out[s] = lam;
+      if (A.nfree_out) A.nfree_out[s] = (int32_t)tn[0];
+      atomicAdd(&A.counters[CTR_SURV], ntot);
+      atomicAdd(&A.counters[CTR_OVER], 1);
+    }
+    return;
   }
-  // x = max(0, y + lam*), formed in FP64 and rounded once
-  double nf = 0.0;
-  if (single) {
+  // start refinement: Newton steps lam_J(J_j), J_j = {v + lam_j > 0}, from
+  // candidates between lam_0 and -max y; each is an upper bound of lam*
+  double lam = lam0;
+  {
+    double cc[kCand], cs[kCand], lj[kCand];
 #pragma unroll
-    for (int q = 0; q < kK / 4; ++q) {
-      const int64_t i = (int64_t)q * kBlock * 4 + (int64_t)threadIdx.x * 4;
-      float o[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        o[k] = (float)fmax((double)v[4 * q + k] + lam, 0.0);
-        if (i + k < L) nf += (o[k] > 0.f) ? 1.0 : 0.0;
-      }
-      if (i + 4 <= L && aligned16(x + i)) {
-        flt4 w;
-        w.x = o[0];
-        w.y = o[1];
-        w.z = o[2];
-        w.w = o[3];
-        __builtin_nontemporal_store(w, reinterpret_cast<flt4*>(x + i));
-      } else {
-#pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (i + k < L) x[i + k] = o[k];
-      }
+    for (int j = 0; j < kCand; ++j) {
+      lj[j] = -vmax + (lam0 + vmax) / (double)(1u << j);
+      cc[j] = 0.0;
+      cs[j] = 0.0;
     }
-  } else {
-    for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && aligned16(y + i0) && aligned16(x + i0)) {
-        flt4 w = *reinterpret_cast<const flt4*>(y + i0);
-        w.x = (float)fmax((double)w.x + lam, 0.0);
-        w.y = (float)fmax((double)w.y + lam, 0.0);
-        w.z = (float)fmax((double)w.z + lam, 0.0);
-        w.w = (float)fmax((double)w.w + lam, 0.0);
-        nf += (w.x > 0.f) + (w.y > 0.f) + (w.z > 0.f) + (w.w > 0.f);
-        __builtin_nontemporal_store(w, reinterpret_cast<flt4*>(x + i0));
-      } else {
-        for (int64_t i = i0; i < i0 + 4 && i < L; ++i) {
-          const float o = (float)fmax((double)y[i] + lam, 0.0);
-          nf += (o > 0.f) ? 1.0 : 0.0;
-          x[i] = o;
+    for (int w = 0; w < kWaves; ++w) {
+      for (int i = lane; i < nws[w]; i += kWave) {
+        const double v = (double)L.sv[w][i];
+#pragma unroll
+        for (int j = 0; j < kCand; ++j) {
+          const bool in = v + lj[j] > 0.0;
+          cc[j] += in ? 1.0 : 0.0;
+          cs[j] += in ? v : 0.0;
         }
       }
     }
+#pragma unroll
+    for (int j = 0; j < kCand; ++j) {
+      const double c = wave_sum(cc[j]), sj = wave_sum(cs[j]);
+      if (c > 0.0) lam = fmin(lam, (rd - sj) / c);
+    }
   }
-  double tn[3];
-  block_sum3(nf, 0.0, 0.0, lds, tn);
+  lam = wave_newton_lists(L, nws, rd, lam);
+  // x for this wave's list; every other x of the row is already zero
+  double nf = 0.0;
+  for (int i = lane; i < nws[wid]; i += kWave) {
+    const float o = (float)fmax((double)L.sv[wid][i] + lam, 0.0);
+    x[L.si[wid][i]] = o;
+    nf += (o > 0.f) ? 1.0 : 0.0;
+  }
+  nf = wave_sum(nf);
+  if (lane == 0) L.ws[wid][W_NF] = nf;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    double nft = 0.0;
+    for (int w = 0; w < kWaves; ++w) nft += L.ws[w][W_NF];
     if (A.lam_out) A.lam_out[s] = lam;
-    if (A.nfree_out) A.nfree_out[s] = (int32_t)tn[0];
-    atomicAdd(&A.counters[CTR_SURV], nsurv);
-    if (overflow) atomicAdd(&A.counters[CTR_OVER], 1);
+    if (A.nfree_out) A.nfree_out[s] = (int32_t)nft;
+    atomicAdd(&A.counters[CTR_SURV], ntot);
   }
 }
 
 // ---------------------------------------------------------------------------
-// One short row (L <= 512), one wave, values in registers.
+// One wave row (L <= 64 * SP), values in registers.
 // ---------------------------------------------------------------------------
+template <int SP>
 __device__ void solve_short_row(const BatArgs& A, int s) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t base = A.off[s];
@@ -388,11 +511,11 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   const double rd = row_radius(A, s);
   const float* y = A.y + base;
   float* x = A.x + base;
-  float v[kSmallPer];
+  float v[SP];
   uint32_t active = 0;
   double bad = 0.0;
 #pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
+  for (int k = 0; k < SP; ++k) {
     const int64_t i = (int64_t)k * kWave + lane;
     v[k] = (i < L) ? y[i] : 0.f;
     if (i < L) {
@@ -404,7 +527,7 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   const bool bad_r = !(rd >= 0.0) || !(rd < inf_d());
   if (bad_r || bad > 0.0 || L == 0 || rd == 0.0) {
 #pragma unroll
-    for (int k = 0; k < kSmallPer; ++k) {
+    for (int k = 0; k < SP; ++k) {
       const int64_t i = (int64_t)k * kWave + lane;
       if (i < L) x[i] = 0.f;
     }
@@ -422,18 +545,17 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   const float r = (float)rd;
   int c;
   float S;
-  const uint32_t J = alg2<kSmallPer>(v, active, r, c, S);
+  const uint32_t J = alg2<SP>(v, active, r, c, S);
   const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
   const double cw = wave_sum((double)c), sw = wave_sum((double)S);
   double lam_b = (cw > 0) ? (rd - sw) / cw : inf_d();
   // refinement on the wave's own sub-problem, then Algorithm 4 on the row
-  uint32_t cand = J;
   for (int it = 0; it < kRefine; ++it) {
     const double lt = fmin(lam_t, lam_b);
     double nk = 0.0, ks = 0.0;
 #pragma unroll
-    for (int e = 0; e < kSmallPer; ++e)
-      if (((cand >> e) & 1u) && (double)v[e] + lt > 0.0) {
+    for (int e = 0; e < SP; ++e)
+      if (((J >> e) & 1u) && (double)v[e] + lt > 0.0) {
         nk += 1.0;
         ks += (double)v[e];
       }
@@ -450,7 +572,7 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   for (int it = 0; it < kMaxNewton; ++it) {
     double cc = 0.0, ss = 0.0, ph = 0.0;
 #pragma unroll
-    for (int e = 0; e < kSmallPer; ++e) {
+    for (int e = 0; e < SP; ++e) {
       const double z = (double)v[e] + lam;
       if (((active >> e) & 1u) && z > 0.0) {
         cc += 1.0;
@@ -471,7 +593,7 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
   }
   double nf = 0.0;
 #pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
+  for (int k = 0; k < SP; ++k) {
     const int64_t i = (int64_t)k * kWave + lane;
     if (i < L) {
       const float o = (float)fmax((double)v[k] + lam, 0.0);
@@ -484,28 +606,47 @@ __device__ void solve_short_row(const BatArgs& A, int s) {
     if (A.lam_out) A.lam_out[s] = lam;
     if (A.nfree_out) A.nfree_out[s] = (int32_t)nf;
   }
-  (void)cand;
 }
 
+// Work item -> workgroup row (true) or group of four wave rows (false), and
+// its index in that class, under the schedule's order.
+__device__ __forceinline__ bool item_is_long(const BatArgs& A, int item, int nlong, int nsg,
+                                             int* idx) {
+  if (A.short_first) {
+    if (item < nsg) {
+      *idx = item;
+      return false;
+    }
+    *idx = item - nsg;
+    return true;
+  }
+  if (item < nlong) {
+    *idx = item;
+    return true;
+  }
+  *idx = item - nlong;
+  return false;
+}
+
+template <int SP>
 __global__ __launch_bounds__(kBlock) void bat_solve_kernel(BatArgs A) {
-  __shared__ double lds[3 * kWaves];
-  __shared__ float surv[kLdsCap];
-  __shared__ int lds_i[kWaves + 1];
-  __shared__ int s_item;
+  __shared__ BatLds L;
   const int nlong = A.counters[CTR_NLONG];
   const int nshort = A.counters[CTR_NSHORT];
   const int nitems = A.counters[CTR_NITEMS];
+  const int nsg = nitems - nlong;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&A.counters[CTR_QUEUE], 1);
+    if (threadIdx.x == 0) L.item = atomicAdd(&A.counters[CTR_QUEUE], 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = L.item;
     __syncthreads();
     if (item >= nitems) break;
-    if (item < nlong) {
-      solve_long_row(A, A.list[item], lds, surv, lds_i);
+    int idx;
+    if (item_is_long(A, item, nlong, nsg, &idx)) {
+      solve_long_row(A, A.list[idx], L);
     } else {
-      const int k = (item - nlong) * kWaves + (int)(threadIdx.x / kWave);
-      if (k < nshort) solve_short_row(A, A.list[nlong + k]);
+      const int k = idx * kWaves + (int)(threadIdx.x / kWave);
+      if (k < nshort) solve_short_row<SP>(A, A.list[nlong + k]);
     }
     __syncthreads();
   }
@@ -514,78 +655,90 @@ __global__ __launch_bounds__(kBlock) void bat_solve_kernel(BatArgs A) {
 // ---------------------------------------------------------------------------
 // Backward: grad_y = [x > 0](g - mean_S g), grad_r = mean_S g.
 // ---------------------------------------------------------------------------
-__device__ void vjp_long_row(const BatArgs& A, int s, double* lds) {
+__device__ void vjp_long_row(const BatArgs& A, int s, BatLds& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
   const int64_t base = A.off[s];
-  const int64_t L = A.off[s + 1] - base;
+  const int64_t n = A.off[s + 1] - base;
   const float* x = A.x + base;
   const float* g = A.g + base;
   float* gy = A.gy + base;
-  const bool single = L <= kTile;
-  float xs[kK], gs[kK];
   double cnt = 0.0, sum = 0.0;
-  if (single) {
+  int nw = 0;
+  const int64_t ntiles = (n + kWTile - 1) / kWTile;
+  for (int64_t t = wid; t < ntiles; t += kWaves) {
+    const int64_t t0 = t * kWTile;
+    float xs[kK], gs[kK];
+    uint32_t sup = 0;
 #pragma unroll
-    for (int q = 0; q < kK; ++q) {
-      const int64_t i = (int64_t)q * kBlock + threadIdx.x;
-      xs[q] = (i < L) ? x[i] : 0.f;
-      gs[q] = (i < L) ? g[i] : 0.f;
-      if (xs[q] > 0.f) {
-        cnt += 1.0;
-        sum += (double)gs[q];
+    for (int q = 0; q < kK / 4; ++q) {
+      const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+      load4(x, i, n, &xs[4 * q]);
+      load4(g, i, n, &gs[4 * q]);
+      // grad_y is zero off the support
+      zero4(gy, i, n);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = 4 * q + k;
+        if (i + k < n && xs[e] > 0.f) {
+          sup |= 1u << e;
+          cnt += 1.0;
+          sum += (double)gs[e];
+        }
       }
     }
-  } else {
-    for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && aligned16(x + i0) && aligned16(g + i0)) {
-        flt4 xv = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(x + i0));
-        flt4 gv = *reinterpret_cast<const flt4*>(g + i0);
-        if (xv.x > 0.f) { cnt += 1.0; sum += gv.x; }
-        if (xv.y > 0.f) { cnt += 1.0; sum += gv.y; }
-        if (xv.z > 0.f) { cnt += 1.0; sum += gv.z; }
-        if (xv.w > 0.f) { cnt += 1.0; sum += gv.w; }
-      } else {
-        for (int64_t i = i0; i < i0 + 4 && i < L; ++i)
-          if (x[i] > 0.f) { cnt += 1.0; sum += g[i]; }
+    if (__ballot(sup != 0u) == 0) continue;
+#pragma unroll
+    for (int e = 0; e < kK; ++e) {
+      const bool kb = (sup >> e) & 1u;
+      const uint64_t m = __ballot(kb);
+      if (kb) {
+        const int pos = nw + lane_prefix(m);
+        if (pos < kSurvW) {
+          L.sv[wid][pos] = gs[e];
+          L.si[wid][pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
+        }
       }
+      nw += __popcll(m);
     }
   }
-  double tt[3];
-  block_sum3(cnt, sum, 0.0, lds, tt);
-  const double gbar = (tt[0] > 0.0) ? tt[1] / tt[0] : 0.0;
-  const float gb = (float)gbar;
-  if (single) {
+  cnt = wave_sum(cnt);
+  sum = wave_sum(sum);
+  if (lane == 0) {
+    L.ws[wid][W_C] = cnt;
+    L.ws[wid][W_S] = sum;
+    L.ws[wid][W_N] = (double)nw;
+  }
+  __syncthreads();
+  double C = 0.0, Sg = 0.0;
+  bool over = false;
 #pragma unroll
-    for (int q = 0; q < kK; ++q) {
-      const int64_t i = (int64_t)q * kBlock + threadIdx.x;
-      if (i < L) gy[i] = (xs[q] > 0.f) ? gs[q] - gb : 0.f;
-    }
+  for (int w = 0; w < kWaves; ++w) {
+    C += L.ws[w][W_C];
+    Sg += L.ws[w][W_S];
+    over = over || L.ws[w][W_N] > (double)kSurvW;
+  }
+  const double gbar = (C > 0.0) ? Sg / C : 0.0;
+  const float gb = (float)gbar;
+  if (over) {
+    // the support did not fit the lists: a second pass over the row
+    for (int64_t i = threadIdx.x; i < n; i += kBlock)
+      if (x[i] > 0.f) gy[i] = g[i] - gb;
   } else {
-    for (int64_t i0 = (int64_t)threadIdx.x * 4; i0 < L; i0 += (int64_t)kBlock * 4) {
-      if (i0 + 4 <= L && aligned16(x + i0) && aligned16(g + i0) && aligned16(gy + i0)) {
-        flt4 xv = *reinterpret_cast<const flt4*>(x + i0);
-        flt4 gv = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(g + i0));
-        flt4 o;
-        o.x = xv.x > 0.f ? gv.x - gb : 0.f;
-        o.y = xv.y > 0.f ? gv.y - gb : 0.f;
-        o.z = xv.z > 0.f ? gv.z - gb : 0.f;
-        o.w = xv.w > 0.f ? gv.w - gb : 0.f;
-        __builtin_nontemporal_store(o, reinterpret_cast<flt4*>(gy + i0));
-      } else {
-        for (int64_t i = i0; i < i0 + 4 && i < L; ++i) gy[i] = (x[i] > 0.f) ? g[i] - gb : 0.f;
-      }
-    }
+    for (int i = lane; i < nw; i += kWave) gy[L.si[wid][i]] = L.sv[wid][i] - gb;
   }
   if (threadIdx.x == 0 && A.gr) A.gr[s] = gbar;
 }
 
+template <int SP>
 __device__ void vjp_short_row(const BatArgs& A, int s) {
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t base = A.off[s];
   const int64_t L = A.off[s + 1] - base;
-  float xs[kSmallPer], gs[kSmallPer];
+  float xs[SP], gs[SP];
   double cnt = 0.0, sum = 0.0;
 #pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
+  for (int k = 0; k < SP; ++k) {
     const int64_t i = (int64_t)k * kWave + lane;
     xs[k] = (i < L) ? A.x[base + i] : 0.f;
     gs[k] = (i < L) ? A.g[base + i] : 0.f;
@@ -599,30 +752,32 @@ __device__ void vjp_short_row(const BatArgs& A, int s) {
   const double gbar = (cnt > 0.0) ? sum / cnt : 0.0;
   const float gb = (float)gbar;
 #pragma unroll
-  for (int k = 0; k < kSmallPer; ++k) {
+  for (int k = 0; k < SP; ++k) {
     const int64_t i = (int64_t)k * kWave + lane;
     if (i < L) A.gy[base + i] = (xs[k] > 0.f) ? gs[k] - gb : 0.f;
   }
   if (lane == 0 && A.gr) A.gr[s] = gbar;
 }
 
+template <int SP>
 __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
-  __shared__ double lds[3 * kWaves];
-  __shared__ int s_item;
+  __shared__ BatLds L;
   const int nlong = A.counters[CTR_NLONG];
   const int nshort = A.counters[CTR_NSHORT];
   const int nitems = A.counters[CTR_NITEMS];
+  const int nsg = nitems - nlong;
   for (;;) {
-    if (threadIdx.x == 0) s_item = atomicAdd(&A.counters[CTR_QUEUE], 1);
+    if (threadIdx.x == 0) L.item = atomicAdd(&A.counters[CTR_QUEUE], 1);
     __syncthreads();
-    const int item = s_item;
+    const int item = L.item;
     __syncthreads();
     if (item >= nitems) break;
-    if (item < nlong) {
-      vjp_long_row(A, A.list[item], lds);
+    int idx;
+    if (item_is_long(A, item, nlong, nsg, &idx)) {
+      vjp_long_row(A, A.list[idx], L);
     } else {
-      const int k = (item - nlong) * kWaves + (int)(threadIdx.x / kWave);
-      if (k < nshort) vjp_short_row(A, A.list[nlong + k]);
+      const int k = idx * kWaves + (int)(threadIdx.x / kWave);
+      if (k < nshort) vjp_short_row<SP>(A, A.list[nlong + k]);
     }
     __syncthreads();
   }
@@ -631,7 +786,6 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
 struct BatWs {
   int32_t* list;
   int32_t* counters;
-  double* partials;
 };
 
 cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
@@ -642,13 +796,12 @@ cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
   char* p = (char*)ctx->ws.ptr;
   w->list = (int32_t*)p;
   w->counters = (int32_t*)(p + list_bytes);
-  w->partials = nullptr;
   return CQK_OK;
 }
 
-int persistent_grid(cqk_ctx* ctx, int items) {
-  const int g = ctx->num_cus * 4;
-  return std::max(1, std::min(g, items));
+int persistent_grid(cqk_ctx* ctx, const cqk_batch_schedule& sc, int nseg) {
+  const int g = ctx->num_cus * sc.blocks_per_cu;
+  return std::max(1, std::min(g, nseg));
 }
 
 void plan(cqk_ctx* ctx, const BatArgs& A) {
@@ -659,14 +812,35 @@ void plan(cqk_ctx* ctx, const BatArgs& A) {
   hipLaunchKernelGGL(bat_place_kernel, dim3(gb), dim3(kBlock), 0, s, A);
 }
 
-}  // namespace
+void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A) {
+  A->small_max = kWave * sc.small_per;
+  A->short_first = sc.short_first;
+}
 
-cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
-                           const double* r, double r_scalar, float* x, double* lambda_out,
-                           int32_t* nfree_out, const cqk_opts& o, cqk_info* info) {
-  BatWs w;
-  cqk_status st = bat_workspace(ctx, nseg, &w);
-  if (st != CQK_OK) return st;
+// Queues one forward call under schedule sc.
+void launch_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
+  apply_schedule(sc, &A);
+  plan(ctx, A);
+  const dim3 grid(persistent_grid(ctx, sc, A.nseg));
+  if (sc.small_per == 4)
+    hipLaunchKernelGGL(bat_solve_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+  else
+    hipLaunchKernelGGL(bat_solve_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+}
+
+void launch_backward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
+  apply_schedule(sc, &A);
+  plan(ctx, A);
+  const dim3 grid(persistent_grid(ctx, sc, A.nseg));
+  if (sc.small_per == 4)
+    hipLaunchKernelGGL(bat_vjp_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+  else
+    hipLaunchKernelGGL(bat_vjp_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+}
+
+BatArgs forward_args(int32_t nseg, const int64_t* offsets, const float* y, const double* r,
+                     double r_scalar, float* x, double* lambda_out, int32_t* nfree_out,
+                     const BatWs& w) {
   BatArgs A{};
   A.nseg = nseg;
   A.off = offsets;
@@ -678,15 +852,87 @@ cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, c
   A.nfree_out = nfree_out;
   A.list = w.list;
   A.counters = w.counters;
+  return A;
+}
+
+BatArgs backward_args(int32_t nseg, const int64_t* offsets, const float* x, const float* g,
+                      float* grad_y, double* grad_r, const BatWs& w) {
+  BatArgs A{};
+  A.nseg = nseg;
+  A.off = offsets;
+  A.x = const_cast<float*>(x);
+  A.g = g;
+  A.gy = grad_y;
+  A.gr = grad_r;
+  A.list = w.list;
+  A.counters = w.counters;
+  return A;
+}
+
+// The candidate schedules the tuner times.
+int candidate_schedules(cqk_batch_schedule* out, int cap) {
+  int k = 0;
+  for (int sp : {4, 8})
+    for (int bpc : {1, 2, 3, 4})
+      for (int sf : {0, 1})
+        if (k < cap) out[k++] = cqk_batch_schedule{sp, bpc, sf, 0};
+  return k;
+}
+
+// Times `launch` for each candidate (`repeats` runs each after one warm-up,
+// the fastest counts) and returns the index of the best.
+template <typename Launch>
+cqk_status tune(cqk_ctx* ctx, const cqk_batch_schedule* cand, int ncand, int repeats,
+                Launch launch, int* best, double* best_ms) {
+  cqk_status st = ensure_events(ctx, 2);
+  if (st != CQK_OK) return st;
+  hipStream_t s = ctx->stream;
+  *best = 0;
+  *best_ms = 1e300;
+  for (int c = 0; c < ncand; ++c) {
+    launch(cand[c]);
+    double t = 1e300;
+    for (int k = 0; k < repeats; ++k) {
+      hipEventRecord(ctx->events[0], s);
+      launch(cand[c]);
+      hipEventRecord(ctx->events[1], s);
+      if (hip_ok(hipEventSynchronize(ctx->events[1])) != CQK_OK) return CQK_DEVICE_ERROR;
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
+      t = std::min(t, (double)ms);
+    }
+    if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+    if (t < *best_ms) {
+      *best_ms = t;
+      *best = c;
+    }
+  }
+  return CQK_OK;
+}
+
+}  // namespace
+
+bool valid_schedule(const cqk_batch_schedule& sc) {
+  return (sc.small_per == 4 || sc.small_per == 8) && sc.blocks_per_cu >= 1 &&
+         sc.blocks_per_cu <= 8 && (sc.short_first == 0 || sc.short_first == 1);
+}
+
+cqk_batch_schedule default_schedule() { return cqk_batch_schedule{8, 4, 0, 0}; }
+
+cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
+                           const double* r, double r_scalar, float* x, double* lambda_out,
+                           int32_t* nfree_out, const cqk_opts& o, cqk_info* info) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  const BatArgs A = forward_args(nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, w);
   hipStream_t s = ctx->stream;
   if (o.timing) {
     st = ensure_events(ctx, 2);
     if (st != CQK_OK) return st;
     hipEventRecord(ctx->events[0], s);
   }
-  plan(ctx, A);
-  // items <= nseg, so a grid of min(persistent size, nseg) covers them
-  hipLaunchKernelGGL(bat_solve_kernel, dim3(persistent_grid(ctx, nseg)), dim3(kBlock), 0, s, A);
+  launch_forward(ctx, ctx->sched_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (info) std::memset(info, 0, sizeof(*info));
@@ -724,20 +970,50 @@ cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* o
   BatWs w;
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
-  BatArgs A{};
-  A.nseg = nseg;
-  A.off = offsets;
-  A.x = const_cast<float*>(x);
-  A.g = g;
-  A.gy = grad_y;
-  A.gr = grad_r;
-  A.list = w.list;
-  A.counters = w.counters;
-  hipStream_t s = ctx->stream;
-  plan(ctx, A);
-  hipLaunchKernelGGL(bat_vjp_kernel, dim3(persistent_grid(ctx, nseg)), dim3(kBlock), 0, s, A);
+  launch_backward(ctx, ctx->sched_bwd, backward_args(nseg, offsets, x, g, grad_y, grad_r, w));
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  if (o.sync && hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+  if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
+  return CQK_OK;
+}
+
+cqk_status tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
+                            const double* r, double r_scalar, float* x, int32_t repeats,
+                            cqk_batch_schedule* best, double* best_ms) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  const BatArgs A = forward_args(nseg, offsets, y, r, r_scalar, x, nullptr, nullptr, w);
+  cqk_batch_schedule cand[32];
+  const int nc = candidate_schedules(cand, 32);
+  int bi = 0;
+  double ms = 0.0;
+  st = tune(ctx, cand, nc, repeats,
+            [&](const cqk_batch_schedule& sc) { launch_forward(ctx, sc, A); }, &bi, &ms);
+  if (st != CQK_OK) return st;
+  ctx->sched_fwd = cand[bi];
+  if (best) *best = cand[bi];
+  if (best_ms) *best_ms = ms;
+  return CQK_OK;
+}
+
+cqk_status tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                     const float* x, const float* g, float* grad_y,
+                                     int32_t repeats, cqk_batch_schedule* best,
+                                     double* best_ms) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  const BatArgs A = backward_args(nseg, offsets, x, g, grad_y, nullptr, w);
+  cqk_batch_schedule cand[32];
+  const int nc = candidate_schedules(cand, 32);
+  int bi = 0;
+  double ms = 0.0;
+  st = tune(ctx, cand, nc, repeats,
+            [&](const cqk_batch_schedule& sc) { launch_backward(ctx, sc, A); }, &bi, &ms);
+  if (st != CQK_OK) return st;
+  ctx->sched_bwd = cand[bi];
+  if (best) *best = cand[bi];
+  if (best_ms) *best_ms = ms;
   return CQK_OK;
 }
 

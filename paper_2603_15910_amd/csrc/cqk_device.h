@@ -1,9 +1,10 @@
 // Device building blocks shared by the libcqk kernels (gfx950, wave64).
 //
-// Reductions are deterministic: a fixed xor butterfly inside the wave, wave
-// results combined in wave order through LDS, block partials combined in
-// block order by the last block to finish (ticket counter).  Repeated calls
-// on the same input give bit-identical results.
+// Reductions are deterministic: a fixed sequence of DPP lane moves inside the
+// wave, wave results combined in wave order through LDS, block partials
+// combined in block order by a one-block reduction kernel (or by the last
+// block to finish, where a kernel uses the ticket below).  Repeated calls on
+// the same input give bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,27 +22,79 @@ typedef int32_t int4v __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ double inf_d() { return __builtin_huge_val(); }
 
 // ---------------------------------------------------------------------------
-// Wave reductions: xor butterfly, every lane ends with the same bits.
+// Wave reductions through DPP lane moves (no LDS round trip): pairs and quads
+// (quad_perm), eight and sixteen lanes (half-row and row mirrors), then rows
+// 0+1 and 2+3 (row_bcast15) and all four rows (row_bcast31) into lane 63,
+// read back as a scalar.  Every lane gets the same bits, and the order of
+// the operations is fixed, so repeated calls agree bit for bit.  Must be
+// called with the whole wave active.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+namespace dpp {
+constexpr int kXor1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int kXor2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int kHalfMirror = 0x141;
+constexpr int kMirror = 0x140;
+constexpr int kBcast15 = 0x142;
+constexpr int kBcast31 = 0x143;
+}  // namespace dpp
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_move(float v, float identity) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, identity),
+                                         __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xF, false));
 }
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double v, double identity) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint64_t o = __builtin_bit_cast(uint64_t, identity);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)u,
+                                                            CTRL, ROW_MASK, 0xF, false);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(
+      (int)(uint32_t)(o >> 32), (int)(uint32_t)(u >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
+
+__device__ __forceinline__ float read_lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double read_lane63(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, T identity, Op op) {
+  v = op(v, dpp_move<dpp::kXor1, 0xF>(v, identity));
+  v = op(v, dpp_move<dpp::kXor2, 0xF>(v, identity));
+  v = op(v, dpp_move<dpp::kHalfMirror, 0xF>(v, identity));
+  v = op(v, dpp_move<dpp::kMirror, 0xF>(v, identity));
+  v = op(v, dpp_move<dpp::kBcast15, 0xA>(v, identity));
+  v = op(v, dpp_move<dpp::kBcast31, 0xC>(v, identity));
+  return read_lane63(v);
+}
+
+struct OpAdd {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMin {
+  __device__ __forceinline__ double operator()(double a, double b) const { return fmin(a, b); }
+};
+struct OpMax {
+  __device__ __forceinline__ double operator()(double a, double b) const { return fmax(a, b); }
+};
+
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce(v, 0.0, OpAdd{}); }
+__device__ __forceinline__ float wave_sum(float v) { return wave_reduce(v, 0.0f, OpAdd{}); }
 __device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce(v, __builtin_huge_val(), OpMin{});
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  return wave_reduce(v, -__builtin_huge_val(), OpMax{});
 }
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 #pragma unroll
@@ -68,8 +121,8 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 
 // ---------------------------------------------------------------------------
 // Block reductions of NS sums and NM mins / NX maxes held per thread.
-// `lds` needs (NS + NM + NX) * (blockDim/64) doubles.  Thread 0 receives the
-// block totals in out[] (combined in wave order).
+// `lds` needs (NS + NM + NX) * (blockDim/64) doubles; `out` is in LDS and
+// holds the block totals (combined in wave order) for every thread on return.
 // ---------------------------------------------------------------------------
 template <int NS, int NM, int NX, int BLOCK>
 __device__ __forceinline__ void block_reduce(const double* sums, const double* mins,
@@ -94,18 +147,18 @@ __device__ __forceinline__ void block_reduce(const double* sums, const double* m
     if (lane == 0) lds[(NS + NM + i) * NW + wid] = v;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  // one thread per value combines the waves, in wave order
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    double acc = lds[i * NW];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double acc = lds[i * NW];
-      for (int w = 1; w < NW; ++w) {
-        double t = lds[i * NW + w];
-        if (i < NS) acc += t;
-        else if (i < NS + NM) acc = fmin(acc, t);
-        else acc = fmax(acc, t);
-      }
-      out[i] = acc;
+    for (int w = 1; w < NW; ++w) {
+      const double t = lds[i * NW + w];
+      if (i < NS) acc += t;
+      else if (i < NS + NM) acc = fmin(acc, t);
+      else acc = fmax(acc, t);
     }
+    out[i] = acc;
   }
   __syncthreads();
 }

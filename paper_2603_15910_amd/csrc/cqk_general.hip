@@ -127,25 +127,19 @@ __device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double 
   acc.s[P_PREDHI] += res_lo_lam ? 0.0 : 1.0;
   acc.s[P_PREDLO] += res_lam_hi ? 0.0 : 1.0;
   if (!COMPACT) return true;
-  if (fix_l) {
-    acc.s[P_DF] += bl;
-    acc.s[P_DAF] += fabs(bl);
-    return false;
-  }
-  if (fix_u) {
-    acc.s[P_DF] += bu;
-    acc.s[P_DAF] += fabs(bu);
-    return false;
-  }
-  if ((fl >= bl) && (fh <= bu) && (fl >= 0.0 || fh <= 0.0)) {
-    const double sg = (fl >= 0.0) ? 1.0 : -1.0;
-    acc.s[P_DC0] += c;
-    acc.s[P_DC1] += s;
-    acc.s[P_DA0] += sg * c;
-    acc.s[P_DA1] += sg * s;
-    return false;
-  }
-  return true;
+  // fixed at a bound on the whole bracket, else free on the whole bracket
+  // with one sign; written as selects so the accumulators stay in registers
+  const double fixv = fix_l ? bl : (fix_u ? bu : 0.0);
+  acc.s[P_DF] += fixv;
+  acc.s[P_DAF] += fabs(fixv);
+  const bool freeb = !fix_l && !fix_u && (fl >= bl) && (fh <= bu) && (fl >= 0.0 || fh <= 0.0);
+  const double sg = (fl >= 0.0) ? 1.0 : -1.0;
+  const double fc = freeb ? c : 0.0, fs = freeb ? s : 0.0;
+  acc.s[P_DC0] += fc;
+  acc.s[P_DC1] += fs;
+  acc.s[P_DA0] += sg * fc;
+  acc.s[P_DA1] += sg * fs;
+  return !(fix_l || fix_u || freeb);
 }
 
 // Closest breakpoints around lam (Algorithm 1, breakpoint steps), with the
@@ -285,13 +279,13 @@ __device__ void trace_push(GenState* st, cqk_trace_rec* tr, int kind, int compac
   st->ntrace += 1;
 }
 
-__device__ void finish(GenState* st, double lamf, int reason) {
+__device__ __forceinline__ void finish(GenState* st, double lamf, int reason) {
   st->status = CQK_OK;
   st->lam_final = lamf;
   st->stop_reason = reason;
 }
 
-__device__ void advance(GenState* st, double next) {
+__device__ __forceinline__ void advance(GenState* st, double next) {
   st->lam_prev = st->lam;
   st->lam = next;
   st->mode = kModeEval;
@@ -302,7 +296,7 @@ __device__ void advance(GenState* st, double next) {
 }
 
 // The scalar part of Algorithm 1, run by one thread after an evaluation pass.
-__device__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
+__device__ __forceinline__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
   const double lam = st->lam;
   const bool compacted = st->compact_next != 0;
   const int source = st->src;
@@ -330,14 +324,11 @@ __device__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* 
   st->compact_next = 0;
   const double r = st->r, tol = st->tol;
   const double res = phi - r;
-  double lo = st->lo, hi = st->hi;
-  if (res < 0.0) {
-    lo = lam;
-    st->phi_lo = phi;
-  } else if (res > 0.0) {
-    hi = lam;
-    st->phi_hi = phi;
-  }
+  // selects rather than branches, so the state stays in registers
+  const double lo = (res < 0.0) ? lam : st->lo;
+  const double hi = (res > 0.0) ? lam : st->hi;
+  st->phi_lo = (res < 0.0) ? phi : st->phi_lo;
+  st->phi_hi = (res > 0.0) ? phi : st->phi_hi;
   st->lo = lo;
   st->hi = hi;
   const double slope = (res < 0.0) ? Qp : Qm;
@@ -381,7 +372,7 @@ __device__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* 
 // iterate lam_{k+1} = bp is evaluated without another pass: phi(bp) =
 // phi(lam_k) and the one-sided slope at bp is the summed s of the indices
 // whose breakpoint is bp.  The Newton step from bp follows as in Algorithm 1.
-__device__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec* tr) {
+__device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec* tr) {
   st->passes += 1;
   const bool right = st->mode == kModeBreakRight;
   const double bp = right ? ks[0].k : -ks[1].k;
@@ -394,9 +385,9 @@ __device__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec*
   const double phi = right ? st->phi_lo : st->phi_hi;
   const double r = st->r, tol = st->tol;
   const double res = phi - r;
-  if (right) st->lo = bp;
-  else st->hi = bp;
-  const double lo = st->lo, hi = st->hi;
+  const double lo = right ? bp : st->lo, hi = right ? st->hi : bp;
+  st->lo = lo;
+  st->hi = hi;
   trace_push(st, tr, 5, 0, st->src, bp, phi, sw, 0, 0);
   st->iter += 1;
   st->lam_prev = st->lam;

@@ -34,11 +34,12 @@ struct SpxState {
   double lo, hi, sum_abs, vmax;
   double res_P;                   // finalize: sum of x (l1: sum |x|)
   double cm_prev;
-  int64_t n_src, n_init, n_free, m, chunk_src;
+  int64_t n_src, n_init, n_free, tail_cap, chunk_src;
   int32_t status, iter, passes, src, compact_next, stop_reason, max_iter;
   int32_t compaction, trace_cap, ntrace, l1, fin_mode, need_safeguard, first_done;
-  uint32_t ticket;
-  int32_t pad_[3];
+  int32_t tail;                   // 1: the remaining iterations run in one block
+  int32_t multi;                  // 1: the next pass refines the start (candidates)
+  int32_t pad_[2];
 };
 
 // How the simplex finalize writes x.
@@ -66,6 +67,8 @@ struct cqk_ctx {
   std::vector<hipEvent_t> events;
   int32_t last_trace_count = 0;
   std::vector<cqk_trace_rec> last_trace;
+  cqk_batch_schedule sched_fwd{8, 4, 0, 0};  // batched forward / backward schedules
+  cqk_batch_schedule sched_bwd{8, 4, 0, 0};
 };
 
 namespace cqk {
@@ -92,5 +95,13 @@ cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, c
 cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                     const float* x, const float* g, float* grad_y,
                                     double* grad_r, const cqk_opts& o);
+bool valid_schedule(const cqk_batch_schedule& sc);
+cqk_status tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
+                            const double* r, double r_scalar, float* x, int32_t repeats,
+                            cqk_batch_schedule* best, double* best_ms);
+cqk_status tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                     const float* x, const float* g, float* grad_y,
+                                     int32_t repeats, cqk_batch_schedule* best,
+                                     double* best_ms);
 
 }  // namespace cqk

@@ -11,24 +11,35 @@
 // phi'_+(lam) = #{y + lam >= 0}, phi'_-(lam) = #{y + lam > 0}.
 // For the l1 ball the same runs on |y| and x gets the signs of y back.
 //
+// Layout: the grid is G0 blocks of 4 waves; wave region r owns chunk0/4
+// consecutive indices of y, and every compacted set keeps the same regions
+// (values and their indices in y, written with ballot + lane prefix counts:
+// deterministic, no block-wide synchronisation).
+//
 // Kernels:
-//   spx_condat_kernel    one read of y: every thread runs Algorithm 2 on 16
-//                        register-resident values; the block merges the
-//                        thread sets (counts and sums) into lam_J bounds and
-//                        keeps only values above every bound found; survivors
-//                        (value, index) go to the block's region.  The last
-//                        block merges all blocks: lam_0 and a prefix scan of
-//                        the survivor counts.
-//   spx_gather_kernel    packs the block regions into one dense array.
-//   spx_formula_kernel   eq. (CQKlambda0) start: lam_0 = (r - sum y)/n, plus
-//                        max y for the safeguard of Algorithm 4.
-//   spx_iter_kernel      one evaluation of phi and the counts over the
-//                        current set; drops y + lam_k <= 0 (valid because
-//                        lam_k >= lam*, Theorem 1); Algorithm 4's update in
-//                        the last block.
-//   spx_finalize_kernel  dense x = max(0, y + lam*) (or 0, or a copy of y);
-//   spx_scatter_kernel   x[idx] for the surviving indices when the rest of x
-//                        is known to be zero.
+//   spx_condat_kernel       one read of y: every thread runs Algorithm 2 on 16
+//                           register-resident values; the wave merges its
+//                           lanes' sets into lam_J bounds, refines them and
+//                           keeps only values above the smallest bound found
+//                           (wave reductions only, no barriers); values at or
+//                           below the wave's best bound skip Algorithm 2.
+//   spx_condat_merge_kernel lam_0 = the smallest bound any wave found and the
+//                           bound of the union of every surviving set.
+//   spx_pass_kernel<MULTI>  right after the start: the survivors' counts and
+//                           sums at 12 candidate points give 12 more bounds,
+//                           the smallest becomes lam_0 (spx_start_update_kernel).
+//   spx_formula_kernel      eq. (CQKlambda0) start, plus max y.
+//   spx_pass_kernel         one evaluation of phi and the counts over the
+//                           current set; drops y + lam_k <= 0 (valid because
+//                           lam_k >= lam*, Theorem 1).
+//   spx_update_kernel       Algorithm 4's update (one block).
+//   spx_tail_kernel         once the set fits in LDS: copies it there and runs
+//                           every remaining iteration inside one block.
+//   spx_finalize_kernel     dense x = max(0, y + lam*) (or 0, or a copy of y);
+//   spx_scatter_kernel      x[idx] for the surviving indices when the rest of
+//                           x is known to be zero.
+// The finalize kernels do nothing while the loop is still running, so the
+// host queues them behind every batch of iterations and waits once per batch.
 #include <algorithm>
 #include <cmath>
 
@@ -39,24 +50,26 @@ namespace cqk {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kRBlock = 1024;  // one-block reductions of partial records
+constexpr int kRBlock = 1024;  // one-block kernels (reductions, the tail loop)
 constexpr int kWaves = kBlock / kWave;
-constexpr int kCondatK = 16;  // values per thread per tile in Algorithm 2
-constexpr int kRefine = 8;    // block refinement rounds per tile
+constexpr int kCondatK = 16;   // values per lane per tile in Algorithm 2
+constexpr int kRefine = 8;     // refinement rounds per wave tile
+constexpr int kTailBytes = 128 * 1024;  // LDS copy of the set the tail loop runs on
+constexpr int kTailRegs = 4;            // region counts per thread when packing
+constexpr int kCand = 12;               // start refinement candidates
 
 struct SpxArgs {
   const void* y;
   void* x;
   int64_t n;
-  int64_t chunk0;   // region size of the original layout
-  void* val[2];     // compacted values (signed y), TIn
-  uint32_t* idx[2]; // their indices in y
-  int32_t* cnt[2];  // per-block counts of each buffer
-  int64_t* offs;    // prefix of the Algorithm 2 survivor counts
+  int64_t chunk0;    // block region of the original layout; wave region = chunk0/4
+  void* val[2];      // compacted values (signed y), TIn
+  uint32_t* idx[2];  // their indices in y
+  int32_t* cnt[2];   // per-wave-region counts of each buffer
+  uint32_t* tidx;    // indices of the set the tail loop ran on
   double* partials;
   SpxState* st;
   cqk_trace_rec* trace;
-  int G0, G2;
 };
 
 template <typename T>
@@ -64,7 +77,7 @@ __device__ __forceinline__ T absval(T v) {
   return v < T(0) ? -v : v;
 }
 
-__device__ void spx_trace(SpxState* st, cqk_trace_rec* tr, int kind, int compacted, int source,
+__device__ __forceinline__ void spx_trace(SpxState* st, cqk_trace_rec* tr, int kind, int compacted, int source,
                           double lam, double phi, double slope, int64_t nin, int64_t nout) {
   if (st->ntrace < st->trace_cap) {
     cqk_trace_rec& t = tr[st->ntrace];
@@ -83,7 +96,7 @@ __device__ void spx_trace(SpxState* st, cqk_trace_rec* tr, int kind, int compact
   st->ntrace += 1;
 }
 
-__device__ void spx_finish(SpxState* st, double lamf, int reason) {
+__device__ __forceinline__ void spx_finish(SpxState* st, double lamf, int reason) {
   st->status = CQK_OK;
   st->lam_final = lamf;
   st->stop_reason = reason;
@@ -149,7 +162,8 @@ __device__ __forceinline__ uint32_t condat_thread(const TA* v, uint32_t active, 
   return J;
 }
 
-// Loads V consecutive values of y starting at i (count-guarded).
+// Loads V consecutive values of y starting at i (count-guarded; a 16-byte
+// load where it is aligned).
 template <typename TIn>
 __device__ __forceinline__ void load_y(const TIn* y, int64_t i, int64_t n, TIn* o) {
   constexpr int V = VecWidth<TIn>::value;
@@ -171,24 +185,6 @@ __device__ __forceinline__ void load_y(const TIn* y, int64_t i, int64_t n, TIn* 
   }
 }
 
-// Block-wide sum of one int and one double (thread 0 gets both, then
-// broadcast through LDS).
-__device__ __forceinline__ void block_sum_cs(int c, double s, double* lds, int* out_c,
-                                             double* out_s) {
-  double in[2] = {(double)c, s};
-  double tot[2];
-  __shared__ double bc[2];
-  block_reduce<2, 0, 0, kBlock>(in, nullptr, nullptr, lds, tot);
-  if (threadIdx.x == 0) {
-    bc[0] = tot[0];
-    bc[1] = tot[1];
-  }
-  __syncthreads();
-  *out_c = (int)bc[0];
-  *out_s = bc[1];
-  __syncthreads();
-}
-
 // Partial record of the Algorithm 2 kernel.
 enum { C_CNT = 0, C_SUM, C_ABS, C_BAD, C_NOUT, C_NSUM };  // + min lam, max v
 constexpr int C_NPART = C_NSUM + 2;
@@ -199,25 +195,28 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   if (st->status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
   constexpr int K = kCondatK;
-  constexpr int NL = K / V;  // vector loads per thread per tile
-  constexpr int64_t TILE = (int64_t)kBlock * K;
+  constexpr int NL = K / V;  // vector loads per lane per tile
+  constexpr int64_t TILE = (int64_t)kWave * K;
   const bool l1 = st->l1 != 0;
   const TA r = (TA)st->r;
   const double rd = st->r;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk0;
-  const int64_t count = max((int64_t)0, min(A.chunk0, A.n - off));
+  const int lane = threadIdx.x & (kWave - 1);
+  const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+  const int64_t cw = A.chunk0 / kWaves;
+  const int64_t off = (int64_t)rid * cw;
+  const int64_t count = max((int64_t)0, min(cw, A.n - off));
   const TIn* y = (const TIn*)A.y + off;
   TIn* outv = (TIn*)A.val[1] + off;
   uint32_t* outi = A.idx[1] + off;
 
   __shared__ double lds[C_NPART * (kBlock / kWave)];
   __shared__ double tot[C_NPART];
-  __shared__ int lds_i[kBlock / kWave + 1];
 
-  double run_c = 0.0, run_s = 0.0;       // survivors kept so far by this block
-  double lam_min = inf_d();              // smallest valid bound seen
+  // wave-uniform: the survivors this wave kept so far, the smallest bound
+  double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
   double acc[C_NSUM] = {0, 0, 0, 0, 0};
-  double vmax = -inf_d();
+  TA vmx = -__builtin_huge_valf();
+  int nbad = 0;
   int64_t written = 0;
   for (int64_t base = 0; base < count; base += TILE) {
     TIn yv[K];
@@ -225,266 +224,125 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     uint32_t active = 0;
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
-      const int64_t i = base + (int64_t)q * kBlock * V + (int64_t)threadIdx.x * V;
+      const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
       load_y<TIn>(y, i, count, &yv[q * V]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = q * V + k;
-        const bool in = i + k < count;
         const TA t = (TA)yv[e];
         v[e] = l1 ? absval(t) : t;
-        if (in) {
+        if (i + k < count) {
           active |= 1u << e;
-          const double td = (double)yv[e];
-          acc[C_ABS] += fabs(td);
-          acc[C_BAD] += (fabs(td) < inf_d()) ? 0.0 : 1.0;
-          vmax = fmax(vmax, (double)v[e]);
+          acc[C_ABS] += fabs((double)yv[e]);
+          nbad += (absval(yv[e]) < (TIn)__builtin_huge_val()) ? 0 : 1;
+          vmx = max(vmx, v[e]);
         }
       }
     }
+    // values at or below the wave's best bound so far are zero at the
+    // solution: only the rest enters Algorithm 2, and a tile with none left
+    // costs no wave reduction
+    if (lam_min < inf_d()) {
+      const TA lb = (TA)lam_min;
+#pragma unroll
+      for (int e = 0; e < K; ++e)
+        if (!(v[e] + lb > TA(0))) active &= ~(1u << e);
+    }
+    if (__ballot(active != 0u) == 0) continue;
     int c = 0;
     TA S = TA(0);
-    const uint32_t J = condat_thread<K, TA>(v, active, r, l1, c, S);
+    uint32_t J;
+    if (__ballot(__popc(active) > 1) != 0) {
+      J = condat_thread<K, TA>(v, active, r, l1, c, S);
+    } else {
+      // at most one value per lane: Algorithm 2 keeps it (l1: if non-zero)
+      J = 0;
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
+          J = 1u << e;
+          c = 1;
+          S = v[e];
+        }
+      }
+    }
     const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
-    int ct;
-    double skt;
-    block_sum_cs(c, (double)S, lds, &ct, &skt);
     // Every lam below is lam_J of some non-empty J, hence >= lam*
-    // (Section 2.2): the union of the thread sets, its union with the
-    // block's earlier survivors, and the refinements
+    // (Section 2.2): the union of the lanes' sets, its union with the
+    // wave's earlier survivors, and the refinements
     //   lam <- lam_J'  with  J' = {j in J : y_j + lam > 0},
-    // each of which can only lower lam (it is the Newton step of Algorithm 4
-    // on the tile's own sub-problem).
-    double lam_b = (ct > 0) ? (rd - skt) / (double)ct : inf_d();
-    if (ct > 0 && run_c > 0.0) lam_b = fmin(lam_b, (rd - (skt + run_s)) / ((double)ct + run_c));
+    // each of which can only lower lam (it is Algorithm 4's step on the
+    // tile's own sub-problem).
+    const double ct = wave_sum((double)c);
+    const double skt = wave_sum((double)S);
+    double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
+    if (ct > 0.0 && run_c > 0.0) lam_b = fmin(lam_b, (rd - (skt + run_s)) / (ct + run_c));
     if (run_c > 0.0) lam_b = fmin(lam_b, (rd - run_s) / run_c);
     uint32_t keep = 0;
-    int nk = 0;
-    double ks = 0.0;
-    auto select = [&](double lam_blk) {
-      const TA lt = (TA)fmin(lam_t, lam_blk);
+    double nk = 0.0, ks = 0.0;
+    auto select = [&](double lb) {
+      const TA lt = (TA)fmin(lam_t, lb);
       keep = 0;
-      nk = 0;
+      nk = 0.0;
       ks = 0.0;
 #pragma unroll
       for (int e = 0; e < K; ++e) {
         if (((J >> e) & 1u) && (v[e] + lt > TA(0))) {
           keep |= 1u << e;
-          ++nk;
+          nk += 1.0;
           ks += (double)v[e];
         }
       }
     };
     for (int it = 0; it < kRefine; ++it) {
       select(lam_b);
-      int kc;
-      double kss;
-      block_sum_cs(nk, ks, lds, &kc, &kss);
-      if (kc == 0) break;
-      double nl = (rd - kss) / (double)kc;
-      if (run_c > 0.0) nl = fmin(nl, (rd - (kss + run_s)) / ((double)kc + run_c));
+      const double kc = wave_sum(nk), kss = wave_sum(ks);
+      if (kc == 0.0) break;
+      double nl = (rd - kss) / kc;
+      if (run_c > 0.0) nl = fmin(nl, (rd - (kss + run_s)) / (kc + run_c));
       if (!(nl < lam_b)) break;
       lam_b = nl;
     }
     select(lam_b);
-    int total;
-    const int pos0 = block_excl_scan<kBlock>(nk, lds_i, &total);
-    int64_t pos = written + pos0;
-#pragma unroll
-    for (int q = 0; q < NL; ++q) {
-      const int64_t i = base + (int64_t)q * kBlock * V + (int64_t)threadIdx.x * V;
-#pragma unroll
-      for (int k = 0; k < V; ++k) {
-        const int e = q * V + k;
-        if ((keep >> e) & 1u) {
-          outv[pos] = yv[e];
-          outi[pos] = (uint32_t)(off + i + k);
-          ++pos;
-        }
-      }
-    }
-    written += total;
-    int kc;
-    double kss;
-    block_sum_cs(nk, ks, lds, &kc, &kss);
-    run_c += (double)kc;
-    run_s += kss;
     lam_min = fmin(lam_min, lam_b);
+    if (__ballot(keep != 0u) == 0) continue;
+#pragma unroll
+    for (int e = 0; e < K; ++e) {
+      const bool kb = (keep >> e) & 1u;
+      const uint64_t m = __ballot(kb);
+      if (kb) {
+        const int64_t pos = written + lane_prefix(m);
+        const int q = e / V, k = e % V;
+        outv[pos] = yv[e];
+        outi[pos] = (uint32_t)(off + base + (int64_t)q * kWave * V + (int64_t)lane * V + k);
+      }
+      written += __popcll(m);
+    }
+    run_c += wave_sum(nk);
+    run_s += wave_sum(ks);
     if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
   }
-  if (threadIdx.x == 0) {
+  if (lane == 0) {
     acc[C_CNT] = run_c;
     acc[C_SUM] = run_s;
     acc[C_NOUT] = (double)written;
-    A.cnt[1][blockIdx.x] = (int32_t)written;
+    A.cnt[1][rid] = (int32_t)written;
   } else {
     acc[C_CNT] = acc[C_SUM] = acc[C_NOUT] = 0.0;
   }
-  double mn[1] = {lam_min};
-  double mx[1] = {vmax};
-  block_reduce<C_NSUM, 1, 1, kBlock>(acc, mn, mx, lds, tot);
-  if (threadIdx.x == 0) {
-    write_partial(A.partials, tot, C_NPART);
-  }
-}
-
-// Merges the blocks of spx_condat_kernel (one block): lam_0 from the union of
-// the surviving sets, the smallest bound any block found, the l1 ball test,
-// and the prefix of the survivor counts for the gather.
-__global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, int G) {
-  SpxState* st = A.st;
-  if (st->status != kRunning) return;
-  __shared__ double lds[C_NPART * (kRBlock / kWave)];
-  __shared__ double tot[C_NPART];
-  __shared__ int lds_i[kRBlock / kWave + 1];
-  reduce_partials<C_NSUM, 1, 1, kRBlock>(A.partials, G, lds, tot);
-  __shared__ int s_go;
-  __shared__ int64_t s_m, s_ch;
-  if (threadIdx.x == 0) {
-    st->passes += 1;
-    st->sum_abs = tot[C_ABS];
-    st->vmax = tot[C_NSUM + 1];
-    s_go = 0;
-    if (tot[C_BAD] > 0.0) {
-      st->status = CQK_INVALID_ARG;
-    } else if (st->l1 && tot[C_ABS] <= st->r) {
-      st->fin_mode = kFinCopy;
-      spx_finish(st, 0.0, 5);
-    } else {
-      const double m = tot[C_CNT];
-      double lam0 = (m > 0.0) ? (st->r - tot[C_SUM]) / m : 0.0;
-      lam0 = fmin(lam0, tot[C_NSUM]);
-      st->lam = lam0;
-      st->lam0 = lam0;
-      st->n_init = (int64_t)m;
-      st->m = (int64_t)m;
-      st->hi = lam0;
-      int64_t ch = ((int64_t)m + (int64_t)A.G2 * kWaves - 1) / ((int64_t)A.G2 * kWaves);
-      ch = (ch + 7) / 8 * 8;
-      if (ch < 8) ch = 8;
-      st->chunk_src = ch;
-      st->src = 1;
-      st->n_src = (int64_t)m;
-      st->compact_next = (st->compaction != CQK_COMPACT_OFF) ? 1 : 0;
-      s_m = (int64_t)m;
-      s_ch = ch;
-      s_go = 1;
-    }
-    spx_trace(st, A.trace, 0, 1, 0, st->lam, tot[C_SUM], tot[C_CNT], A.n, (int64_t)tot[C_NOUT]);
-  }
-  __syncthreads();
-  if (!s_go) return;
-  // exclusive scan of the per-block survivor counts, and the counts of the
-  // dense layout the Newton passes read (G2 x 4 wave regions of chunk_src)
-  int64_t base = 0;
-  for (int g0 = 0; g0 < G; g0 += kRBlock) {
-    const int g = g0 + threadIdx.x;
-    const int cnt = (g < G) ? A.cnt[1][g] : 0;
-    int totc;
-    const int ex = block_excl_scan<kRBlock>(cnt, lds_i, &totc);
-    if (g < G) A.offs[g] = base + ex;
-    base += totc;
-  }
-  const int64_t m = s_m, ch = s_ch;
-  for (int g = threadIdx.x; g < A.G2 * kWaves; g += kRBlock) {
-    const int64_t s0 = (int64_t)g * ch;
-    A.cnt[0][g] = (int32_t)max((int64_t)0, min(ch, m - s0));
-  }
-}
-
-template <typename TIn>
-__global__ __launch_bounds__(kBlock) void spx_gather_kernel(SpxArgs A) {
-  SpxState* st = A.st;
-  if (st->status != kRunning) return;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk0;
-  const int64_t cnt = A.cnt[1][blockIdx.x];
-  const int64_t dst = A.offs[blockIdx.x];
-  const TIn* sv = (const TIn*)A.val[1] + off;
-  const uint32_t* si = A.idx[1] + off;
-  TIn* dv = (TIn*)A.val[0] + dst;
-  uint32_t* di = A.idx[0] + dst;
-  for (int64_t i = threadIdx.x; i < cnt; i += kBlock) {
-    dv[i] = sv[i];
-    di[i] = si[i];
-  }
-}
-
-// eq. (CQKlambda0) with J = all indices, D = I, b = 1: lam_0 = (r - sum y)/n,
-// then lam_0 <- max(lam_0, -max y) (Algorithm 4, first line).
-enum { F_SUM = 0, F_ABS, F_BAD, F_NSUM };
-template <typename TIn>
-__global__ __launch_bounds__(kBlock) void spx_formula_kernel(SpxArgs A) {
-  SpxState* st = A.st;
-  if (st->status != kRunning) return;
-  constexpr int V = VecWidth<TIn>::value;
-  const bool l1 = st->l1 != 0;
-  const int64_t off = (int64_t)blockIdx.x * A.chunk0;
-  const int64_t count = max((int64_t)0, min(A.chunk0, A.n - off));
-  const TIn* y = (const TIn*)A.y + off;
-  double acc[F_NSUM] = {0, 0, 0};
-  double vmax = -inf_d();
-  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
-    TIn yv[V];
-    load_y<TIn>(y, i, count, yv);
-#pragma unroll
-    for (int k = 0; k < V; ++k) {
-      if (i + k < count) {
-        const double t = (double)yv[k];
-        const double v = l1 ? fabs(t) : t;
-        acc[F_SUM] += v;
-        acc[F_ABS] += fabs(t);
-        acc[F_BAD] += (fabs(t) < inf_d()) ? 0.0 : 1.0;
-        vmax = fmax(vmax, v);
-      }
-    }
-  }
-  __shared__ double lds[(F_NSUM + 1) * (kBlock / kWave)];
-  __shared__ double tot[F_NSUM + 1];
-  block_reduce<F_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
-  if (threadIdx.x == 0) {
-    write_partial(A.partials, tot, F_NSUM + 1);
-  }
-}
-
-__global__ __launch_bounds__(kRBlock) void spx_formula_update_kernel(SpxArgs A, int G) {
-  SpxState* st = A.st;
-  if (st->status != kRunning) return;
-  __shared__ double lds[(F_NSUM + 1) * (kRBlock / kWave)];
-  __shared__ double tot[F_NSUM + 1];
-  reduce_partials<F_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
-  if (threadIdx.x == 0) {
-    st->passes += 1;
-    st->sum_abs = tot[F_ABS];
-    st->vmax = tot[F_NSUM];
-    if (tot[F_BAD] > 0.0) {
-      st->status = CQK_INVALID_ARG;
-    } else if (st->l1 && tot[F_ABS] <= st->r) {
-      st->fin_mode = kFinCopy;
-      spx_finish(st, 0.0, 5);
-    } else {
-      double lam0 = (st->r - tot[F_SUM]) / (double)A.n;
-      lam0 = fmax(lam0, -tot[F_NSUM]);
-      st->lam = lam0;
-      st->lam0 = lam0;
-      st->need_safeguard = 0;
-    }
-    spx_trace(st, A.trace, 0, 0, 0, st->lam, tot[F_SUM], (double)A.n, A.n, 0);
-  }
+  acc[C_BAD] = (double)nbad;
+  const double vmax = (double)vmx;
+  block_reduce<C_NSUM, 1, 1, kBlock>(acc, &lam_min, &vmax, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, C_NPART);
 }
 
 // Partial record of an evaluation pass.
 enum { S_PHI = 0, S_CM, S_CP, S_BAD, S_NIN, S_NOUT, S_ABS, S_NSUM };  // + max v
+constexpr int kPassRec = S_NSUM + 1;  // the candidate sums of a MULTI pass follow
 
-template <typename TA>
-__device__ __forceinline__ void spx_eval(TA v, TA lam, TA& phi, double& cm, double& cp) {
-  const TA z = v + lam;
-  phi += z > TA(0) ? z : TA(0);
-  cm += z > TA(0) ? 1.0 : 0.0;
-  cp += z >= TA(0) ? 1.0 : 0.0;
-}
-
-// Algorithm 4's update, run by one thread after an evaluation pass.
-__device__ void spx_update(SpxState* st, const double* t, double vmax, cqk_trace_rec* tr,
+// Algorithm 4's update, run by one thread after an evaluation (source: 0 the
+// caller's y, 1/2 a compacted buffer, 3 the packed set of the tail loop).
+__device__ __forceinline__ void spx_update(SpxState* st, const double* t, double vmax, cqk_trace_rec* tr,
                            bool compacted, int source) {
   st->passes += 1;
   if (t[S_BAD] > 0.0) {
@@ -520,14 +378,11 @@ __device__ void spx_update(SpxState* st, const double* t, double vmax, cqk_trace
   }
   const int k = st->iter;
   st->iter += 1;
-  double slope;
-  if (k == 0 && phi < r) {
-    slope = cp;
-    st->lo = lam;
-  } else {
-    slope = cm;
-    if (phi > r) st->hi = lam;
-  }
+  // selects rather than branches, so the state stays in registers
+  const bool below = (k == 0 && phi < r);
+  const double slope = below ? cp : cm;
+  st->lo = below ? lam : st->lo;
+  st->hi = (!below && phi > r) ? lam : st->hi;
   spx_trace(st, tr, 1, compacted, source, lam, phi, slope, (int64_t)t[S_NIN],
             compacted ? (int64_t)t[S_NOUT] : 0);
   if (phi == r) return spx_finish(st, lam, 4);
@@ -543,28 +398,340 @@ __device__ void spx_update(SpxState* st, const double* t, double vmax, cqk_trace
   st->lam = next;
   // every later iterate is >= lam* (Theorem 1), so y + lam_k <= 0 fixes x at 0
   st->compact_next = (st->compaction != CQK_COMPACT_OFF) ? 1 : 0;
+  if (st->n_src <= st->tail_cap) st->tail = 1;
   if (st->iter >= st->max_iter) {
     st->status = CQK_NOT_CONVERGED;
     st->lam_final = lam;
   }
 }
 
+// Shared memory of the tail loop; a kernel that may run the loop declares one.
 template <typename TIn, typename TA>
-__global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
+struct TailLds {
+  static constexpr int CAP = kTailBytes / (int)sizeof(TIn);
+  static constexpr int RB = kRBlock * kTailRegs;
+  static constexpr int NW = kRBlock / kWave;
+  TIn tv[CAP];
+  int reg[RB + 1];
+  int off[NW + 1];
+  double lds[(S_NSUM + 1) * NW];
+  double tot[S_NSUM + 1];
+  TA phl[NW];
+  int run;
+  double lam;
+};
+
+// The remaining Newton iterations inside one block of kRBlock threads, on a
+// copy of the current set in LDS (the caller's y when it is small from the
+// start, else the compacted regions packed densely; their indices go to a
+// global list for the final scatter).  Each iteration is one sweep of LDS.
+// `sc` is thread 0's copy of the state (status running, tail set); src and
+// l1 are the block-uniform values of that state.  Thread 0 stores the state
+// back when the loop has stopped.
+template <typename TIn, typename TA>
+__device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState& sc, int src, bool l1,
+                             TailLds<TIn, TA>& L) {
+  constexpr int CAP = TailLds<TIn, TA>::CAP;
+  constexpr int RB = TailLds<TIn, TA>::RB;
+  constexpr int NW = TailLds<TIn, TA>::NW;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  int64_t total;
+  if (src == 0) {
+    total = A.n;
+    const TIn* y = (const TIn*)A.y;
+    for (int i = threadIdx.x; i < CAP && i < A.n; i += kRBlock) L.tv[i] = y[i];
+  } else {
+    // Every thread takes kTailRegs consecutive region counts, a block scan
+    // gives each region its output offset, then output position p is copied
+    // from the region a binary search over those offsets finds (eight
+    // positions per thread at a time, so their loads overlap).
+    const int si = src - 1;
+    const int64_t chunk = A.chunk0 / kWaves;
+    const TIn* sv = (const TIn*)A.val[si];
+    const uint32_t* sx = A.idx[si];
+    int64_t base = 0;
+    for (int r0 = 0; r0 < NR; r0 += RB) {
+      int c[kTailRegs];
+      int csum = 0;
+#pragma unroll
+      for (int j = 0; j < kTailRegs; ++j) {
+        const int r = r0 + threadIdx.x * kTailRegs + j;
+        c[j] = (r < NR) ? A.cnt[si][r] : 0;
+        csum += c[j];
+      }
+      int totc;
+      int ex = block_excl_scan<kRBlock>(csum, L.off, &totc);
+#pragma unroll
+      for (int j = 0; j < kTailRegs; ++j) {
+        L.reg[threadIdx.x * kTailRegs + j] = ex;
+        ex += c[j];
+      }
+      if (threadIdx.x == 0) L.reg[RB] = totc;
+      __syncthreads();
+      constexpr int U = 8;
+      for (int p0 = 0; p0 < totc; p0 += U * kRBlock) {
+        int64_t from[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int p = p0 + u * kRBlock + threadIdx.x;
+          from[u] = -1;
+          if (p < totc && base + p < CAP) {
+            int lo = 0, hi = RB;  // reg[lo] <= p < reg[hi]
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (L.reg[mid] <= p) lo = mid;
+              else hi = mid;
+            }
+            from[u] = (int64_t)(r0 + lo) * chunk + (p - L.reg[lo]);
+          }
+        }
+        TIn val[U];
+        uint32_t ix[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (from[u] >= 0) {
+            val[u] = sv[from[u]];
+            ix[u] = sx[from[u]];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (from[u] >= 0) {
+            const int p = p0 + u * kRBlock + threadIdx.x;
+            L.tv[base + p] = val[u];
+            A.tidx[base + p] = ix[u];
+          }
+        }
+      }
+      base += totc;
+      __syncthreads();
+    }
+    total = base;
+  }
+  __syncthreads();
+  if (total > CAP) {
+    // the updates only hand over sets that fit
+    if (threadIdx.x == 0) {
+      sc.status = CQK_DEVICE_ERROR;
+      *A.st = sc;
+    }
+    return;
+  }
+  const int m = (int)total;
+  if (threadIdx.x == 0) L.lam = sc.lam;
+  __syncthreads();
+  for (;;) {
+    const TA lam = (TA)L.lam;
+    TA phi = TA(0);
+    double acc[S_NSUM] = {0, 0, 0, 0, 0, 0, 0};
+    double vmax = -inf_d();
+#pragma unroll 4
+    for (int i = threadIdx.x; i < m; i += kRBlock) {
+      const TA t = (TA)L.tv[i];
+      const TA vv = l1 ? absval(t) : t;
+      const TA z = vv + lam;
+      phi += z > TA(0) ? z : TA(0);
+      acc[S_CM] += z > TA(0) ? 1.0 : 0.0;
+      acc[S_CP] += z >= TA(0) ? 1.0 : 0.0;
+      acc[S_NIN] += 1.0;
+      if (src == 0) {
+        const double td = (double)t;
+        acc[S_ABS] += fabs(td);
+        acc[S_BAD] += (fabs(td) < inf_d()) ? 0.0 : 1.0;
+        vmax = fmax(vmax, (double)vv);
+      }
+    }
+    const TA phw = wave_sum(phi);
+    if (lane == 0) L.phl[wid] = phw;
+    block_reduce<S_NSUM, 0, 1, kRBlock>(acc, nullptr, &vmax, L.lds, L.tot);
+    if (threadIdx.x == 0) {
+      TA pb = L.phl[0];
+      for (int w = 1; w < NW; ++w) pb += L.phl[w];
+      double t[S_NSUM + 1];
+      for (int i = 0; i < S_NSUM + 1; ++i) t[i] = L.tot[i];
+      t[S_PHI] = (double)pb;
+      spx_update(&sc, t, t[S_NSUM], A.trace, false, src == 0 ? 0 : 3);
+      L.run = (sc.status == kRunning) ? 1 : 0;
+      L.lam = sc.lam;
+    }
+    __syncthreads();
+    if (!L.run) break;
+  }
+  if (threadIdx.x == 0) {
+    sc.tail = 0;
+    if (src != 0) {
+      sc.src = 3;  // the packed list: the scatter reads it
+      sc.n_src = m;
+    }
+    *A.st = sc;
+  }
+}
+
+// Shared flags handed from thread 0 to the block: enter the tail loop, and
+// the state's src and l1 for it.
+struct TailGo {
+  int go, src, l1;
+};
+
+__device__ __forceinline__ void tail_flags(TailGo* f, const SpxState& s) {
+  f->go = (s.status == kRunning && s.tail) ? 1 : 0;
+  f->src = s.src;
+  f->l1 = s.l1;
+}
+
+// Entry into the tail loop when the state says so at the start of the solve
+// (a small instance whose start reads y anyway).
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kRBlock) void spx_tail_kernel(SpxArgs A, int NR) {
+  __shared__ TailLds<TIn, TA> L;
+  __shared__ TailGo f;
+  SpxState sc;
+  if (threadIdx.x == 0) {
+    sc = *A.st;
+    tail_flags(&f, sc);
+  }
+  __syncthreads();
+  if (f.go) spx_tail_run<TIn, TA>(A, NR, sc, f.src, f.l1 != 0, L);
+}
+
+// Merges the blocks of spx_condat_kernel (one block): lam_0 is the smallest
+// of the bounds the waves found and the bound of the union of every
+// surviving set (all of them >= lam*), the l1 ball test, and the survivor
+// count; a set that fits goes straight into the tail loop.
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[C_NPART * (kRBlock / kWave)];
+  __shared__ double tot[C_NPART];
+  __shared__ TailLds<TIn, TA> L;
+  __shared__ TailGo f;
+  reduce_partials<C_NSUM, 1, 1, kRBlock>(A.partials, G, lds, tot);
+  SpxState s;
+  if (threadIdx.x == 0) {
+    s = *st;
+    s.passes += 1;
+    s.sum_abs = tot[C_ABS];
+    s.vmax = tot[C_NSUM + 1];
+    if (tot[C_BAD] > 0.0) {
+      s.status = CQK_INVALID_ARG;
+    } else if (s.l1 && tot[C_ABS] <= s.r) {
+      s.fin_mode = kFinCopy;
+      spx_finish(&s, 0.0, 5);
+    } else {
+      const double m = tot[C_CNT];
+      double lam0 = (m > 0.0) ? (s.r - tot[C_SUM]) / m : 0.0;
+      lam0 = fmin(lam0, tot[C_NSUM]);
+      s.lam = lam0;
+      s.lam0 = lam0;
+      s.n_init = (int64_t)tot[C_NOUT];
+      s.hi = lam0;
+      s.src = 2;  // the survivors sit in buffer 1, same regions as y
+      s.n_src = (int64_t)tot[C_NOUT];
+      s.compact_next = (s.compaction != CQK_COMPACT_OFF) ? 1 : 0;
+      s.tail = (s.n_src <= s.tail_cap) ? 1 : 0;
+      s.multi = s.tail ? 0 : 1;
+    }
+    spx_trace(&s, A.trace, 0, 1, 0, s.lam, tot[C_SUM], tot[C_CNT], A.n, (int64_t)tot[C_NOUT]);
+    *st = s;
+    tail_flags(&f, s);
+  }
+  __syncthreads();
+  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, s, f.src, f.l1 != 0, L);
+}
+
+// eq. (CQKlambda0) with J = all indices, D = I, b = 1: lam_0 = (r - sum y)/n,
+// then lam_0 <- max(lam_0, -max y) (Algorithm 4, first line).
+enum { F_SUM = 0, F_ABS, F_BAD, F_NSUM };
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void spx_formula_kernel(SpxArgs A) {
   SpxState* st = A.st;
   if (st->status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
-  constexpr int E = 2 * V;
+  const bool l1 = st->l1 != 0;
+  const int64_t off = (int64_t)blockIdx.x * A.chunk0;
+  const int64_t count = max((int64_t)0, min(A.chunk0, A.n - off));
+  const TIn* y = (const TIn*)A.y + off;
+  double acc[F_NSUM] = {0, 0, 0};
+  double vmax = -inf_d();
+  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
+    TIn yv[V];
+    load_y<TIn>(y, i, count, yv);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (i + k < count) {
+        const double t = (double)yv[k];
+        const double v = l1 ? fabs(t) : t;
+        acc[F_SUM] += v;
+        acc[F_ABS] += fabs(t);
+        acc[F_BAD] += (fabs(t) < inf_d()) ? 0.0 : 1.0;
+        vmax = fmax(vmax, v);
+      }
+    }
+  }
+  __shared__ double lds[(F_NSUM + 1) * (kBlock / kWave)];
+  __shared__ double tot[F_NSUM + 1];
+  block_reduce<F_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, F_NSUM + 1);
+}
+
+__global__ __launch_bounds__(kRBlock) void spx_formula_update_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[(F_NSUM + 1) * (kRBlock / kWave)];
+  __shared__ double tot[F_NSUM + 1];
+  reduce_partials<F_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x != 0) return;
+  SpxState s = *st;
+  s.passes += 1;
+  s.sum_abs = tot[F_ABS];
+  s.vmax = tot[F_NSUM];
+  if (tot[F_BAD] > 0.0) {
+    s.status = CQK_INVALID_ARG;
+  } else if (s.l1 && tot[F_ABS] <= s.r) {
+    s.fin_mode = kFinCopy;
+    spx_finish(&s, 0.0, 5);
+  } else {
+    double lam0 = (s.r - tot[F_SUM]) / (double)A.n;
+    lam0 = fmax(lam0, -tot[F_NSUM]);
+    s.lam = lam0;
+    s.lam0 = lam0;
+    s.need_safeguard = 0;
+    s.first_done = 1;
+  }
+  spx_trace(&s, A.trace, 0, 0, 0, s.lam, tot[F_SUM], (double)A.n, A.n, 0);
+  *st = s;
+}
+
+// Candidate j of the start refinement: between lam_0 and -max v (a lower
+// bound of lam*), halving the distance to -max v at every step.
+__device__ __forceinline__ double cand_lambda(double lam0, double vmax, int j) {
+  return -vmax + (lam0 + vmax) / (double)(1u << j);
+}
+
+// One evaluation of phi and its one-sided slopes at lam_k over the current
+// set (counts exactly in double, phi in TA), dropping y + lam_k <= 0 when
+// compaction is on (lam_k >= lam*).  MULTI: the pass right after Algorithm 2
+// also counts and sums, for every candidate lam_j, the set
+// J_j = {v + lam_j > 0}; each lam_{J_j} = (r - S_j)/c_j is an upper bound of
+// lam* (eq. (lambdaJ)), and j = 0 gives Algorithm 4's first step.
+template <typename TIn, typename TA, bool MULTI>
+__global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
+  SpxState* st = A.st;
+  if (st->status != kRunning || st->tail || (st->multi != 0) != MULTI) return;
+  constexpr int V = VecWidth<TIn>::value;
+  constexpr int E = 4 * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
+  constexpr int NC = MULTI ? kCand : 1;
   const bool l1 = st->l1 != 0;
   const int src = st->src;
   const bool compact = st->compact_next != 0;
-  const double lamd = st->lam;
-  const TA lam = (TA)lamd;
+  const TA lam = (TA)st->lam;
   // every wave streams its own region rid (deterministic layout, no barriers)
   const int lane = threadIdx.x & (kWave - 1);
   const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
-  const int64_t chunk = (src == 0) ? A.chunk0 / kWaves : st->chunk_src;
+  const int64_t chunk = A.chunk0 / kWaves;
   const int64_t off = (int64_t)rid * chunk;
   int64_t count;
   const TIn* yv;
@@ -587,6 +754,17 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
     oi = A.idx[di] + off;
     ocnt = A.cnt[di] + rid;
   }
+  TA lj[NC];
+  double cc[NC], cs[NC];
+  if constexpr (MULTI) {
+    const double lam0 = st->lam, vmx = st->vmax;
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      lj[j] = (TA)cand_lambda(lam0, vmx, j);
+      cc[j] = 0.0;
+      cs[j] = 0.0;
+    }
+  }
   __shared__ double lds[(S_NSUM + 1) * (kBlock / kWave)];
   __shared__ double tot[S_NSUM + 1];
   TA phi = TA(0);
@@ -595,10 +773,9 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   int64_t written = 0;
   for (int64_t base = 0; base < count; base += TILE) {
     TIn y[E];
-    uint32_t id[E];
     bool keep[E];
 #pragma unroll
-    for (int w = 0; w < 2; ++w) {
+    for (int w = 0; w < E / V; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
       load_y<TIn>(yv, i, count, &y[w * V]);
 #pragma unroll
@@ -608,7 +785,10 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
         if (i + k < count) {
           const TA t = (TA)y[e];
           const TA v = l1 ? absval(t) : t;
-          spx_eval<TA>(v, lam, phi, acc[S_CM], acc[S_CP]);
+          const TA z = v + lam;
+          phi += z > TA(0) ? z : TA(0);
+          acc[S_CM] += z > TA(0) ? 1.0 : 0.0;
+          acc[S_CP] += z >= TA(0) ? 1.0 : 0.0;
           acc[S_NIN] += 1.0;
           if (src == 0) {
             const double td = (double)y[e];
@@ -616,8 +796,15 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
             acc[S_BAD] += (fabs(td) < inf_d()) ? 0.0 : 1.0;
             vmax = fmax(vmax, (double)v);
           }
-          keep[e] = compact && (v + lam > TA(0));
-          if (compact) id[e] = (src == 0) ? (uint32_t)(off + i + k) : iv[i + k];
+          if constexpr (MULTI) {
+#pragma unroll
+            for (int j = 0; j < NC; ++j) {
+              const bool in = v + lj[j] > TA(0);
+              cc[j] += in ? 1.0 : 0.0;
+              cs[j] += in ? (double)v : 0.0;
+            }
+          }
+          keep[e] = compact && (z > TA(0));
         }
       }
     }
@@ -627,8 +814,9 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
         const uint64_t m = __ballot(keep[e]);
         if (keep[e]) {
           const int64_t pos = written + lane_prefix(m);
+          const int64_t i = base + (int64_t)(e / V) * kWave * V + (int64_t)lane * V + (e % V);
           ov[pos] = y[e];
-          oi[pos] = id[e];
+          oi[pos] = (src == 0) ? (uint32_t)(off + i) : iv[i];
         }
         written += __popcll(m);
       }
@@ -639,11 +827,9 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
     acc[S_NOUT] = (double)written;
   }
   // phi: reduced in the working precision TA (wave, then waves in order)
-  TA phw = phi;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) phw += __shfl_xor(phw, o, kWave);
+  const TA phw = wave_sum(phi);
   __shared__ TA phl[kBlock / kWave];
-  if ((threadIdx.x & (kWave - 1)) == 0) phl[threadIdx.x / kWave] = phw;
+  if (lane == 0) phl[threadIdx.x / kWave] = phw;
   acc[S_PHI] = 0.0;
   block_reduce<S_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
   if (threadIdx.x == 0) {
@@ -652,47 +838,121 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
     tot[S_PHI] = (double)pb;
     write_partial(A.partials, tot, S_NSUM + 1);
   }
+  if constexpr (MULTI) {
+    __shared__ double lds2[2 * NC * (kBlock / kWave)];
+    __shared__ double tot2[2 * NC];
+    double both[2 * NC];
+#pragma unroll
+    for (int j = 0; j < NC; ++j) {
+      both[j] = cc[j];
+      both[NC + j] = cs[j];
+    }
+    block_reduce<2 * NC, 0, 0, kBlock>(both, nullptr, nullptr, lds2, tot2);
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < 2 * NC; ++i)
+        A.partials[(size_t)(kPassRec + i) * gridDim.x + blockIdx.x] = tot2[i];
+    }
+  }
 }
 
 // One block: phi summed in TA in block order, counts exactly in double, then
-// Algorithm 4's update.
-template <typename TA>
+// Algorithm 4's update; a set that now fits goes on into the tail loop.
+template <typename TIn, typename TA>
 __global__ __launch_bounds__(kRBlock) void spx_update_kernel(SpxArgs A, int G) {
   SpxState* st = A.st;
-  if (st->status != kRunning) return;
+  if (st->status != kRunning || st->tail || st->multi) return;
   const bool compact = st->compact_next != 0;
   const int src = st->src;
   __shared__ double lds[(S_NSUM + 1) * (kRBlock / kWave)];
   __shared__ double tot[S_NSUM + 1];
   __shared__ TA phl[kRBlock / kWave];
+  __shared__ TailLds<TIn, TA> L;
+  __shared__ TailGo f;
   TA pg = TA(0);
-  for (int g = threadIdx.x; g < G; g += kRBlock)
-    pg += (TA)A.partials[(size_t)S_PHI * G + g];
+  for (int g = threadIdx.x; g < G; g += kRBlock) pg += (TA)A.partials[(size_t)S_PHI * G + g];
   reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
-  TA pw = pg;
-#pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) pw += __shfl_xor(pw, o, kWave);
+  const TA pw = wave_sum(pg);
   if ((threadIdx.x & (kWave - 1)) == 0) phl[threadIdx.x / kWave] = pw;
   __syncthreads();
+  SpxState sc;
   if (threadIdx.x == 0) {
     TA pb = phl[0];
     for (int w = 1; w < kRBlock / kWave; ++w) pb += phl[w];
     tot[S_PHI] = (double)pb;
-    SpxState sc = *st;  // register copy: one round trip to memory
+    sc = *st;  // register copy: one round trip to memory
     spx_update(&sc, tot, tot[S_NSUM], A.trace, compact, src);
     *st = sc;
+    tail_flags(&f, sc);
   }
+  __syncthreads();
+  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, sc, f.src, f.l1 != 0, L);
+}
+
+// Closes the start after the MULTI pass: keeps that pass's compaction (done
+// at lam_0 >= lam*) and moves lam_0 down to the smallest candidate bound; a
+// set that now fits goes on into the tail loop.
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kRBlock) void spx_start_update_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (st->status != kRunning || st->tail || !st->multi) return;
+  __shared__ double lds[2 * kCand * (kRBlock / kWave)];
+  __shared__ double tot[S_NSUM + 1];
+  __shared__ double tc[2 * kCand];
+  __shared__ TailLds<TIn, TA> L;
+  __shared__ TailGo f;
+  reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
+  reduce_partials<2 * kCand, 0, 0, kRBlock>(A.partials + (size_t)kPassRec * G, G, lds, tc);
+  SpxState s;
+  if (threadIdx.x == 0) {
+    s = *st;
+    s.passes += 1;
+    s.multi = 0;
+    const int src0 = s.src;
+    const bool compacted = s.compact_next != 0;
+    if (compacted) {
+      s.src = (src0 == 1) ? 2 : 1;
+      s.n_src = (int64_t)tot[S_NOUT];
+    }
+    double best = s.lam;
+    for (int j = 0; j < kCand; ++j) {
+      if (tc[j] > 0.0) best = fmin(best, (s.r - tc[kCand + j]) / tc[j]);
+    }
+    spx_trace(&s, A.trace, 0, compacted ? 1 : 0, src0, best, tot[S_PHI], tot[S_CM],
+              (int64_t)tot[S_NIN], compacted ? (int64_t)tot[S_NOUT] : 0);
+    s.lam = best;
+    s.lam0 = best;
+    s.hi = best;
+    if (s.n_src <= s.tail_cap) s.tail = 1;
+    *st = s;
+    tail_flags(&f, s);
+  }
+  __syncthreads();
+  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, s, f.src, f.l1 != 0, L);
+}
+
+// How x is written once the Newton loop has stopped: the zero fill + scatter
+// form whenever the final set is a compacted one (every index left out of it
+// is fixed at zero), the dense map otherwise.
+__device__ __forceinline__ int spx_fin_mode(const SpxState* st) {
+  const int mode = st->fin_mode;
+  return (mode == kFinDense && st->src != 0) ? (int)kFinScatter : mode;
+}
+
+__device__ __forceinline__ bool spx_done(const SpxState* st) {
+  return st->status == CQK_OK || st->status == CQK_NOT_CONVERGED;
 }
 
 // Dense finalize over all n: x = max(0, y + lam) (l1: with the signs of y),
 // or zeros (the scatter kernel then writes the survivors), or a copy of y.
+// For FP32 data with FP64 accumulation y + lam is formed in FP64 and x is
+// rounded once.  Does nothing while the solve is still running.
 template <typename TIn, typename TA>
 __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
   SpxState* st = A.st;
-  const int status = st->status;
-  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
+  if (!spx_done(st)) return;
   constexpr int V = VecWidth<TIn>::value;
-  const int mode = st->fin_mode;
+  const int mode = spx_fin_mode(st);
   const bool l1 = st->l1 != 0;
   const TA lam = (TA)st->lam_final;
   const int64_t off = (int64_t)blockIdx.x * A.chunk0;
@@ -714,8 +974,8 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
           o[k] = yv[k];
         } else {
           const TA t = (TA)yv[k];
-          const TA v = l1 ? absval(t) : t;
-          const TA z = v + lam;
+          const TA vv = l1 ? absval(t) : t;
+          const TA z = vv + lam;
           TA xv = z > TA(0) ? z : TA(0);
           if (l1 && t < TA(0)) xv = -xv;
           o[k] = (TIn)xv;
@@ -746,27 +1006,11 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
         if (i + k < count) x[i + k] = o[k];
     }
   }
+  if (mode == kFinScatter) return;  // the scatter kernel writes the totals
   __shared__ double lds[2 * (kBlock / kWave)];
   __shared__ double tot[2];
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
-  if (threadIdx.x == 0) {
-    write_partial(A.partials, tot, 2);
-  }
-}
-
-// Totals of the finalize (dense modes) or of the scatter (scatter mode).
-__global__ __launch_bounds__(kRBlock) void spx_fin_reduce_kernel(SpxArgs A, int G, int scatter) {
-  SpxState* st = A.st;
-  const int status = st->status;
-  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
-  if ((st->fin_mode == kFinScatter) != (scatter != 0)) return;
-  __shared__ double lds[2 * (kRBlock / kWave)];
-  __shared__ double tot[2];
-  reduce_partials<2, 0, 0, kRBlock>(A.partials, G, lds, tot);
-  if (threadIdx.x == 0) {
-    st->res_P = tot[0];
-    st->n_free = (int64_t)tot[1];
-  }
+  if (threadIdx.x == 0) write_partial(A.partials, tot, 2);
 }
 
 // x[idx] = max(0, v + lam) for the indices that survived every compaction;
@@ -774,43 +1018,58 @@ __global__ __launch_bounds__(kRBlock) void spx_fin_reduce_kernel(SpxArgs A, int 
 template <typename TIn, typename TA>
 __global__ __launch_bounds__(kBlock) void spx_scatter_kernel(SpxArgs A) {
   SpxState* st = A.st;
-  const int status = st->status;
-  if (status != CQK_OK && status != CQK_NOT_CONVERGED) return;
-  if (st->fin_mode != kFinScatter) return;
+  if (!spx_done(st) || spx_fin_mode(st) != kFinScatter) return;
   const bool l1 = st->l1 != 0;
   const TA lam = (TA)st->lam_final;
-  const int si = st->src - 1;
+  const int src = st->src;
   const int lane = threadIdx.x & (kWave - 1);
-  const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
-  const int64_t off = (int64_t)rid * st->chunk_src;
-  const int64_t count = A.cnt[si][rid];
-  const TIn* v = (const TIn*)A.val[si] + off;
-  const uint32_t* iv = A.idx[si] + off;
   TIn* x = (TIn*)A.x;
   double acc[2] = {0.0, 0.0};
-  for (int64_t i = lane; i < count; i += kWave) {
-    const TA t = (TA)v[i];
+  auto put = [&](TIn yv, uint32_t ix) {
+    const TA t = (TA)yv;
     const TA z = (l1 ? absval(t) : t) + lam;
     TA xv = z > TA(0) ? z : TA(0);
     if (l1 && t < TA(0)) xv = -xv;
     const TIn xo = (TIn)xv;
-    x[iv[i]] = xo;
+    x[ix] = xo;
     acc[0] += fabs((double)xo);
     acc[1] += (xo != TIn(0)) ? 1.0 : 0.0;
+  };
+  if (src == 3) {
+    // the tail loop's list: indices only, the values come from y
+    const TIn* y = (const TIn*)A.y;
+    const int64_t m = st->n_src;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+         i += (int64_t)gridDim.x * kBlock) {
+      const uint32_t ix = A.tidx[i];
+      put(y[ix], ix);
+    }
+  } else {
+    const int si = src - 1;
+    const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+    const int64_t off = (int64_t)rid * (A.chunk0 / kWaves);
+    const int64_t count = A.cnt[si][rid];
+    const TIn* v = (const TIn*)A.val[si] + off;
+    const uint32_t* iv = A.idx[si] + off;
+    for (int64_t i = lane; i < count; i += kWave) put(v[i], iv[i]);
   }
   __shared__ double lds[2 * (kBlock / kWave)];
   __shared__ double tot[2];
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
-  if (threadIdx.x == 0) {
-    write_partial(A.partials, tot, 2);
-  }
+  if (threadIdx.x == 0) write_partial(A.partials, tot, 2);
 }
 
-// Marks the finalize mode once the Newton loop has stopped: the zero-fill +
-// scatter form whenever the final set is a compacted one (every index left
-// out of it is fixed at zero), the dense map otherwise.
-__global__ void spx_pick_fin_kernel(SpxState* st) {
-  if (st->fin_mode == kFinDense && st->src != 0) st->fin_mode = kFinScatter;
+// Totals of the finalize (dense modes) or of the scatter (scatter mode).
+__global__ __launch_bounds__(kRBlock) void spx_fin_reduce_kernel(SpxArgs A, int G) {
+  SpxState* st = A.st;
+  if (!spx_done(st)) return;
+  __shared__ double lds[2 * (kRBlock / kWave)];
+  __shared__ double tot[2];
+  reduce_partials<2, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x == 0) {
+    st->res_P = tot[0];
+    st->n_free = (int64_t)tot[1];
+  }
 }
 
 __global__ void spx_init_kernel(SpxState* st, SpxState init) { *st = init; }
@@ -824,23 +1083,24 @@ template <typename TIn, typename TA>
 cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, bool l1,
                        const cqk_opts& o, cqk_info* info) {
   if (n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
+  constexpr int64_t CAP = kTailBytes / (int64_t)sizeof(TIn);
   const int G0i = grid0(n, ctx->num_cus);
   int64_t chunk0 = (n + G0i - 1) / G0i;
   chunk0 = (chunk0 + 31) / 32 * 32;  // wave regions of chunk0/4, multiples of 8
   const int G0 = (int)((n + chunk0 - 1) / chunk0);
-  const int G2 = ctx->num_cus * 4;
-  const int Gmax = std::max(G0, G2);
+  const int NR = G0 * kWaves;
   const bool condat = o.lambda0_mode == CQK_LAMBDA0_CONDAT;
   const bool formula = o.lambda0_mode == CQK_LAMBDA0_FORMULA;
 
-  const size_t part_bytes = ((size_t)Gmax * 8 * sizeof(double) + 255) / 256 * 256;
-  const size_t cnt_bytes = ((size_t)2 * Gmax * kWaves * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t offs_bytes = ((size_t)(G0 + 1) * sizeof(int64_t) + 255) / 256 * 256;
+  const size_t part_bytes =
+      ((size_t)G0 * (kPassRec + 2 * kCand) * sizeof(double) + 255) / 256 * 256;
+  const size_t cnt_bytes = ((size_t)2 * NR * sizeof(int32_t) + 255) / 256 * 256;
   const size_t cap = (size_t)G0 * chunk0;
   const size_t val_bytes = (cap * sizeof(TIn) + 255) / 256 * 256;
   const size_t idx_bytes = (cap * sizeof(uint32_t) + 255) / 256 * 256;
+  const size_t ti_bytes = ((size_t)std::min<int64_t>(n, CAP) * sizeof(uint32_t) + 255) / 256 * 256;
   const bool need_bufs = (o.compaction != CQK_COMPACT_OFF) || condat;
-  const size_t total = part_bytes + cnt_bytes + offs_bytes +
+  const size_t total = part_bytes + cnt_bytes + ti_bytes +
                        (need_bufs ? 2 * (val_bytes + idx_bytes) : 0);
   cqk_status stt = ensure_buffer(ctx->ws, total);
   if (stt != CQK_OK) return stt;
@@ -855,10 +1115,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   A.chunk0 = chunk0;
   A.partials = (double*)ws;
   A.cnt[0] = (int32_t*)(ws + part_bytes);
-  A.cnt[1] = A.cnt[0] + Gmax * kWaves;
-  A.offs = (int64_t*)(ws + part_bytes + cnt_bytes);
+  A.cnt[1] = A.cnt[0] + NR;
+  A.tidx = (uint32_t*)(ws + part_bytes + cnt_bytes);
   if (need_bufs) {
-    char* b = ws + part_bytes + cnt_bytes + offs_bytes;
+    char* b = ws + part_bytes + cnt_bytes + ti_bytes;
     A.val[0] = b;
     A.idx[0] = (uint32_t*)(b + val_bytes);
     A.val[1] = b + val_bytes + idx_bytes;
@@ -866,8 +1126,6 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   }
   A.st = (SpxState*)ctx->state.ptr;
   A.trace = (cqk_trace_rec*)((char*)ctx->state.ptr + 1024);
-  A.G0 = G0;
-  A.G2 = G2;
 
   const double eps = sizeof(TA) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   SpxState init{};
@@ -888,6 +1146,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   init.l1 = l1 ? 1 : 0;
   init.fin_mode = kFinDense;
   init.need_safeguard = (!condat && !formula) ? 1 : 0;
+  // the tail loop takes sets of at most CAP values (its LDS copy); a small
+  // instance whose start reads y anyway goes there at once
+  init.tail_cap = CAP;
+  init.tail = (!condat && n <= CAP) ? 1 : 0;
   if (r == 0.0) {
     init.status = CQK_OK;
     init.fin_mode = kFinZero;
@@ -896,13 +1158,15 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   }
 
   hipStream_t s = ctx->stream;
-  const size_t nev = (size_t)2 * (o.max_iter + 16);
+  // events 0..3: the finalize and scatter of the last finalize chain;
+  // then one pair per grid pass
+  const size_t nev = (size_t)4 + 2 * (o.max_iter + 8);
   if (o.timing) {
     stt = ensure_events(ctx, nev);
     if (stt != CQK_OK) return stt;
   }
   hipLaunchKernelGGL(spx_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
-  int ev = 0;
+  int ev = 4;
   auto launch = [&](auto kern, int grid) {
     const bool rec = o.timing && ev + 2 <= (int)nev;
     if (rec) hipEventRecord(ctx->events[ev], s);
@@ -916,47 +1180,63 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   auto reduce = [&](auto kern, int grid) {
     hipLaunchKernelGGL(kern, dim3(1), dim3(kRBlock), 0, s, A, grid);
   };
-  int G = G0;
-  if (r != 0.0) {
+  auto tail = [&]() {
+    hipLaunchKernelGGL((spx_tail_kernel<TIn, TA>), dim3(1), dim3(kRBlock), 0, s, A, NR);
+  };
+  // Writes x once the state says the loop has stopped; a no-op before that,
+  // so it can follow every batch and the host waits once per batch.
+  auto fin_chain = [&]() {
+    if (o.timing) hipEventRecord(ctx->events[0], s);
+    hipLaunchKernelGGL((spx_finalize_kernel<TIn, TA>), dim3(G0), dim3(kBlock), 0, s, A);
+    if (o.timing) hipEventRecord(ctx->events[1], s);
+    if (o.timing) hipEventRecord(ctx->events[2], s);
+    hipLaunchKernelGGL((spx_scatter_kernel<TIn, TA>), dim3(G0), dim3(kBlock), 0, s, A);
+    if (o.timing) hipEventRecord(ctx->events[3], s);
+    hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
+  };
+  SpxState* hs = (SpxState*)ctx->host_pinned;
+  auto wait_state = [&]() -> cqk_status {
+    if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+    if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost, s)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    return hip_ok(hipStreamSynchronize(s));
+  };
+  if (r == 0.0) {
+    fin_chain();
+    if (wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
+  } else {
     if (condat) {
       launch(spx_condat_kernel<TIn, TA>, G0);
-      reduce(spx_condat_merge_kernel, G0);
-      launch(spx_gather_kernel<TIn>, G0);
-      G = G2;
+      reduce(spx_condat_merge_kernel<TIn, TA>, G0);
     } else if (formula) {
       launch(spx_formula_kernel<TIn>, G0);
       reduce(spx_formula_update_kernel, G0);
     }
-    if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-    SpxState* hs = (SpxState*)ctx->host_pinned;
+    // a small instance whose start reads y anyway runs in one block at once
+    if (init.tail) tail();
+    if (condat) {
+      launch(spx_pass_kernel<TIn, TA, true>, G0);
+      reduce(spx_start_update_kernel<TIn, TA>, G0);
+    }
     int launched = 0;
     const int max_launch = o.max_iter + 2;
-    int batch = 6;
-    while (launched < max_launch) {
+    // after the refined start of Algorithm 2 one more pass usually leaves a
+    // set small enough for the tail loop (entered by the update kernels)
+    int batch = condat ? 1 : 2;
+    for (;;) {
       const int k = std::min(batch, max_launch - launched);
       for (int i = 0; i < k; ++i) {
-        launch(spx_pass_kernel<TIn, TA>, G);
-        reduce(spx_update_kernel<TA>, G);
+        launch(spx_pass_kernel<TIn, TA, false>, G0);
+        reduce(spx_update_kernel<TIn, TA>, G0);
       }
       launched += k;
-      if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost, s)) != CQK_OK)
-        return CQK_DEVICE_ERROR;
-      if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
-      if (hs->status != kRunning) break;
+      fin_chain();
+      if (wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
+      if (hs->status != kRunning || launched >= max_launch) break;
       batch = 4;
     }
   }
-  const int work_events = ev;
-  hipLaunchKernelGGL(spx_pick_fin_kernel, dim3(1), dim3(1), 0, s, A.st);
-  launch(spx_finalize_kernel<TIn, TA>, G0);
-  hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0, 0);
-  launch(spx_scatter_kernel<TIn, TA>, G);
-  hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G, 1);
-  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  SpxState* hs = (SpxState*)ctx->host_pinned;
-  if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost, s)) != CQK_OK)
-    return CQK_DEVICE_ERROR;
-  if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+  const int pass_events = ev;
   const int ntrace = std::min(hs->ntrace, init.trace_cap);
   ctx->last_trace.resize(ntrace);
   if (ntrace > 0 && hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace,
@@ -979,8 +1259,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     info->pass_bytes = 0.0;
     info->pass_ms = 0.0;
     info->finalize_ms = 0.0;
-    const bool scatter = hs->fin_mode == kFinScatter;
-    info->finalize_bytes = (double)n * sizeof(TIn) * ((scatter || hs->fin_mode == kFinZero) ? 1.0 : 2.0);
+    info->rows_spilled = 0;
+    const bool scatter = hs->fin_mode == kFinDense && hs->src != 0;
+    info->finalize_bytes =
+        (double)n * sizeof(TIn) * ((scatter || hs->fin_mode == kFinZero) ? 1.0 : 2.0);
     for (int i = 0; i < ntrace; ++i) {
       const cqk_trace_rec& t = ctx->last_trace[i];
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
@@ -988,16 +1270,16 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
     }
     if (o.timing) {
-      const int worked = std::min(hs->passes + (condat ? 1 : 0), work_events / 2);
-      for (int i = 0; i < worked; ++i) {
+      // every grid pass launched (those after the loop stopped return at
+      // once); the tail loop runs in one block between them and is not here
+      for (int i = 4; i + 1 < pass_events; i += 2) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]);
+        hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
         info->pass_ms += ms;
       }
       for (int j = 0; j < 2; ++j) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->events[work_events + 2 * j],
-                            ctx->events[work_events + 2 * j + 1]);
+        hipEventElapsedTime(&ms, ctx->events[2 * j], ctx->events[2 * j + 1]);
         info->finalize_ms += ms;
       }
     }

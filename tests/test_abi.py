@@ -45,6 +45,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(L.cqk_info) == 104
     assert L.cqk_info.lambda_.offset == 16
     assert C.sizeof(L.cqk_trace_rec) == 72
+    assert C.sizeof(L.cqk_batch_schedule) == 16
 
 
 def test_status_strings_and_defaults(lib):
@@ -67,3 +68,9 @@ def test_host_side_argument_errors(lib):
     assert lib.cqk_create(None, None) == 2
     assert lib.cqk_set_stream(null, null) == 2
     assert lib.cqk_last_trace(null, None, 0, None) == 2
+    sc = L.cqk_batch_schedule(8, 4, 0, 0)
+    assert lib.cqk_get_batch_schedule(null, 0, C.byref(sc)) == 2
+    assert lib.cqk_set_batch_schedule(null, 0, C.byref(sc)) == 2
+    assert lib.cqk_tune_batched_f32(null, 4, null, null, null, 1.0, null, 3, None, None) == 2
+    assert lib.cqk_tune_batched_backward_f32(null, 4, null, null, null, null, 3, None,
+                                             None) == 2

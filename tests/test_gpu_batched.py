@@ -209,3 +209,61 @@ def test_graph_capture_replays(ctx):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(x, eager)
+
+
+SCHEDULES = [(sp, bpc, sf) for sp in (4, 8) for bpc in (1, 2, 3, 4) for sf in (0, 1)]
+
+
+@pytest.mark.parametrize("sp,bpc,sf", SCHEDULES)
+def test_every_schedule_matches_oracle(ctx, sp, bpc, sf):
+    """Each schedule the tuner may pick gives oracle-matching rows, forward
+    and backward, including lengths at the wave/workgroup boundary."""
+    lens = [1, 63, 64, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025, 4097, 20000, 65536, 3]
+    rng = np.random.default_rng(sp * 100 + bpc * 10 + sf)
+    lens += list(rng.integers(1, 3000, 40))
+    off = np.zeros(len(lens) + 1, dtype=np.int64)
+    off[1:] = np.cumsum(lens)
+    y = (3.0 * W.simplex_input(int(off[-1]), 21, "normal", np.float32)).astype(np.float32)
+    ctx.set_batch_schedule(sp, bpc, sf)
+    ctx.set_batch_schedule(sp, bpc, sf, backward=True)
+    try:
+        x, lam, nf, info = _run(ctx, off, y)
+        assert info["status"] == 0, info
+        _rows_check(x, y, off, 1.0, lam, nf)
+        g = W.upstream_grad(y.size, 21)
+        _grad_check(ctx, off, y, g, x)
+    finally:
+        ctx.set_batch_schedule(8, 4, 0)
+        ctx.set_batch_schedule(8, 4, 0, backward=True)
+
+
+def test_schedule_argument_errors(ctx):
+    import paper_2603_15910_amd as cqk
+    for bad in ((5, 4, 0), (8, 0, 0), (8, 9, 0), (8, 4, 2)):
+        with pytest.raises(cqk.CqkError):
+            ctx.set_batch_schedule(*bad)
+    assert ctx.batch_schedule() == {"small_per": 8, "blocks_per_cu": 4, "short_first": 0}
+
+
+def test_tuner_keeps_the_fastest_schedule(ctx):
+    off, y = W.batched_simplex_input(1024, 64, 65536, 7)
+    offs = torch.from_numpy(off).cuda()
+    yt = torch.from_numpy(y).cuda()
+    try:
+        sched, ms = ctx.tune_batched(yt, offs, 1.0, repeats=2)
+        assert ms > 0
+        assert (sched["small_per"], sched["blocks_per_cu"], sched["short_first"]) in \
+            [tuple(s) for s in SCHEDULES]
+        assert ctx.batch_schedule() == sched
+        x, lam, nf, info = _run(ctx, off, y)
+        assert info["status"] == 0
+        _rows_check(x, y, off, 1.0, lam, nf)
+        g = W.upstream_grad(y.size, 7)
+        xt = torch.from_numpy(x).cuda()
+        gt = torch.from_numpy(g).cuda()
+        bsched, bms = ctx.tune_batched_backward(xt, gt, offs, repeats=2)
+        assert bms > 0 and ctx.batch_schedule(backward=True) == bsched
+        _grad_check(ctx, off, y, g, x)
+    finally:
+        ctx.set_batch_schedule(8, 4, 0)
+        ctx.set_batch_schedule(8, 4, 0, backward=True)

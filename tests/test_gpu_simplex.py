@@ -129,7 +129,9 @@ def test_condat_start_invariants(ctx, dist):
     assert info["status"] == 0
     assert info["lambda0"] >= lam_ref - 1e-12
     assert info["n_after_init"] >= int(np.sum(x_ref > 0))
-    assert info["n_after_init"] < y.size // 20
+    # every wave region keeps at least its own sub-problem's support, about
+    # sqrt(2 * region) values for uniform data: a few percent at this size
+    assert info["n_after_init"] < y.size // 10
 
 
 @pytest.mark.parametrize("start", ["zero", "formula", "condat"])
