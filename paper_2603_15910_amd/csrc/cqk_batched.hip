@@ -243,28 +243,42 @@ __device__ __forceinline__ uint32_t wave_tile_alg2(const float* v, uint32_t acti
   return keep;
 }
 
-// Loads four floats of a row (count-guarded, 16-byte where aligned).
-__device__ __forceinline__ void load4(const float* p, int64_t i, int64_t n, float* o) {
-  if (i + 4 <= n && aligned16(p + i)) {
-    flt4 w = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(p + i));
-    o[0] = w.x;
-    o[1] = w.y;
-    o[2] = w.z;
-    o[3] = w.w;
+// One wave tile of a row: kK values per lane, four 16-byte vectors at
+// t0 + q*256 + lane*4 (q < 4); when the tile is in range every load is
+// issued before the first use.  Rows start at any element, so the vectors
+// are only element-aligned.
+__device__ __forceinline__ void load_wtile(const float* p, int64_t t0, int lane, int64_t n,
+                                           float* o) {
+  if (t0 + kWTile <= n) {
+    flt4u r[kK / 4];
+#pragma unroll
+    for (int q = 0; q < kK / 4; ++q) r[q] = ld16(p + t0 + q * kWave * 4 + lane * 4);
+#pragma unroll
+    for (int q = 0; q < kK / 4; ++q)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[4 * q + k] = r[q][k];
   } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) o[k] = (i + k < n) ? p[i + k] : 0.f;
+    for (int q = 0; q < kK / 4; ++q) {
+      const int64_t i = t0 + q * kWave * 4 + lane * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) o[4 * q + k] = (i + k < n) ? p[i + k] : 0.f;
+    }
   }
 }
 
-__device__ __forceinline__ void zero4(float* p, int64_t i, int64_t n) {
-  if (i + 4 <= n && aligned16(p + i)) {
-    flt4 z = {0.f, 0.f, 0.f, 0.f};
-    __builtin_nontemporal_store(z, reinterpret_cast<flt4*>(p + i));
-  } else {
+__device__ __forceinline__ void zero_wtile(float* p, int64_t t0, int lane, int64_t n) {
+  const flt4u z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (i + k < n) p[i + k] = 0.f;
+  for (int q = 0; q < kK / 4; ++q) {
+    const int64_t i = t0 + q * kWave * 4 + lane * 4;
+    if (i + 4 <= n) {
+      st16(p + i, z);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (i + k < n) p[i + k] = 0.f;
+    }
   }
 }
 
@@ -332,12 +346,12 @@ __device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
     const int64_t t0 = t * kWTile;
     float v[kK];
     uint32_t active = 0;
+    load_wtile(y, t0, lane, n, v);
+    // x is zero wherever the lists below do not write it
+    zero_wtile(x, t0, lane, n);
 #pragma unroll
     for (int q = 0; q < kK / 4; ++q) {
       const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
-      load4(y, i, n, &v[4 * q]);
-      // x is zero wherever the lists below do not write it
-      zero4(x, i, n);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         if (i + k < n) {
@@ -670,13 +684,13 @@ __device__ void vjp_long_row(const BatArgs& A, int s, BatLds& L) {
     const int64_t t0 = t * kWTile;
     float xs[kK], gs[kK];
     uint32_t sup = 0;
+    load_wtile(x, t0, lane, n, xs);
+    load_wtile(g, t0, lane, n, gs);
+    // grad_y is zero off the support
+    zero_wtile(gy, t0, lane, n);
 #pragma unroll
     for (int q = 0; q < kK / 4; ++q) {
       const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
-      load4(x, i, n, &xs[4 * q]);
-      load4(g, i, n, &gs[4 * q]);
-      // grad_y is zero off the support
-      zero4(gy, i, n);
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int e = 4 * q + k;

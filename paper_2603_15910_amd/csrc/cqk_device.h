@@ -16,6 +16,11 @@ constexpr int kWave = 64;
 
 typedef double dbl2 __attribute__((ext_vector_type(2)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+// 16-byte vectors at element alignment: global_load/store_dwordx4 needs only
+// dword alignment, so rows and views that start anywhere still move 16 bytes
+// per lane per access.
+typedef double dbl2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float flt4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef float flt2 __attribute__((ext_vector_type(2)));
 typedef int32_t int4v __attribute__((ext_vector_type(4)));
 
@@ -301,11 +306,31 @@ __device__ __forceinline__ void reduce_partials_ks(const double* partials, int G
 
 // ---------------------------------------------------------------------------
 // Vector loads with a count guard: one 16-byte load where the whole vector is
-// in range and its address is 16-byte aligned, element loads otherwise;
-// out-of-range lanes get `fill`.
+// in range, element loads otherwise; out-of-range lanes get `fill`.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool aligned16(const void* p) {
   return ((uintptr_t)p & 15u) == 0;
+}
+
+// Unguarded 16-byte load / store at element alignment; the caller has
+// checked the range.
+template <typename T>
+struct Raw16;
+template <>
+struct Raw16<double> {
+  typedef dbl2u type;
+};
+template <>
+struct Raw16<float> {
+  typedef flt4u type;
+};
+template <typename T>
+__device__ __forceinline__ typename Raw16<T>::type ld16(const T* p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const typename Raw16<T>::type*>(p));
+}
+template <typename T>
+__device__ __forceinline__ void st16(T* p, typename Raw16<T>::type v) {
+  __builtin_nontemporal_store(v, reinterpret_cast<typename Raw16<T>::type*>(p));
 }
 
 template <typename T, int V>
@@ -314,8 +339,8 @@ template <>
 struct Vec<double, 2> {
   static __device__ __forceinline__ void load(const double* p, int64_t i, int64_t n, double fill,
                                               double* o) {
-    if (i + 2 <= n && aligned16(p + i)) {
-      dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(p + i));
+    if (i + 2 <= n) {
+      dbl2u v = ld16(p + i);
       o[0] = v.x;
       o[1] = v.y;
     } else {
@@ -328,8 +353,8 @@ template <>
 struct Vec<float, 4> {
   static __device__ __forceinline__ void load(const float* p, int64_t i, int64_t n, double fill,
                                               double* o) {
-    if (i + 4 <= n && aligned16(p + i)) {
-      flt4 v = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(p + i));
+    if (i + 4 <= n) {
+      flt4u v = ld16(p + i);
       o[0] = v.x;
       o[1] = v.y;
       o[2] = v.z;

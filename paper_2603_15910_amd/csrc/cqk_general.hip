@@ -178,6 +178,32 @@ struct SrcOrig {
       if (i + k < n) bad += tb;
     }
   }
+  // U full vectors per lane, every load issued before the first use
+  template <int U>
+  __device__ __forceinline__ void load_fast(int64_t base, int lane, double* c, double* s,
+                                            double* bl, double* bu, double& bad) const {
+    typename Raw16<TIn>::type rd[U], ra[U], rb[U], rl[U], ru[U];
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+      rd[w] = ld16(d + i);
+      ra[w] = ld16(a + i);
+      rb[w] = ld16(b + i);
+      rl[w] = ld16(l + i);
+      ru[w] = ld16(u + i);
+    }
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = w * V + k;
+        double tb = 0.0;
+        to_form((double)rd[w][k], (double)ra[w][k], (double)rb[w][k], (double)rl[w][k],
+                (double)ru[w][k], c[e], s[e], bl[e], bu[e], tb);
+        bad += tb;
+      }
+    }
+  }
 };
 
 struct SrcForm {
@@ -189,6 +215,29 @@ struct SrcForm {
     Vec<double, 2>::load(s, i, n, 1.0, os);
     Vec<double, 2>::load(bl, i, n, 0.0, obl);
     Vec<double, 2>::load(bu, i, n, 0.0, obu);
+  }
+  template <int U>
+  __device__ __forceinline__ void load_fast(int64_t base, int lane, double* oc, double* os,
+                                            double* obl, double* obu, double&) const {
+    dbl2u rc[U], rs[U], rl[U], ru[U];
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+      rc[w] = ld16(c + i);
+      rs[w] = ld16(s + i);
+      rl[w] = ld16(bl + i);
+      ru[w] = ld16(bu + i);
+    }
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        oc[w * V + k] = rc[w][k];
+        os[w * V + k] = rs[w][k];
+        obl[w * V + k] = rl[w][k];
+        obu[w * V + k] = ru[w][k];
+      }
+    }
   }
 };
 
@@ -206,10 +255,18 @@ __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, 
   for (int64_t base = 0; base < count; base += TILE) {
     double c[E], s[E], bl[E], bu[E];
     bool keep[E];
+    if (base + TILE <= count) {
+      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
+    } else {
+#pragma unroll
+      for (int w = 0; w < kUnroll; ++w) {
+        const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+        src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
+      }
+    }
 #pragma unroll
     for (int w = 0; w < kUnroll; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
-      src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
@@ -246,11 +303,19 @@ __device__ void bkpt_pass(const Src& src, int64_t count, double lam, KeySum* ks)
   const int lane = threadIdx.x & (kWave - 1);
   for (int64_t base = 0; base < count; base += TILE) {
     double c[E], s[E], bl[E], bu[E];
+    double dummy = 0.0;
+    if (base + TILE <= count) {
+      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, dummy);
+    } else {
+#pragma unroll
+      for (int w = 0; w < kUnroll; ++w) {
+        const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+        src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], dummy);
+      }
+    }
 #pragma unroll
     for (int w = 0; w < kUnroll; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
-      double dummy = 0.0;
-      src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], dummy);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
@@ -572,14 +637,9 @@ __global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
   const TIn* u = (const TIn*)A.u + off;
   TIn* x = (TIn*)A.x + off;
   double sums[3] = {0.0, 0.0, 0.0};
-  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
-    double vd[V], va[V], vb[V], vl[V], vu[V];
-    Vec<TIn, V>::load(d, i, count, 1.0, vd);
-    Vec<TIn, V>::load(a, i, count, 0.0, va);
-    Vec<TIn, V>::load(b, i, count, 0.0, vb);
-    Vec<TIn, V>::load(l, i, count, 0.0, vl);
-    Vec<TIn, V>::load(u, i, count, 0.0, vu);
-    TIn xo[V];
+  // x_i from the loaded values; the residual sums use x as stored
+  auto map = [&](const double* vd, const double* va, const double* vb, const double* vl,
+                 const double* vu, int64_t i, TIn* xo) {
 #pragma unroll
     for (int k = 0; k < V; ++k) {
       const double t = fma(vb[k], lam, va[k]) / vd[k];
@@ -592,24 +652,56 @@ __global__ __launch_bounds__(kBlock) void gen_finalize_kernel(GenArgs A) {
         sums[2] += (xr > vl[k] && xr < vu[k]) ? 1.0 : 0.0;
       }
     }
-    if (i + V <= count && aligned16(x + i)) {
-      if constexpr (V == 2) {
-        dbl2 v;
-        v.x = xo[0];
-        v.y = xo[1];
-        __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(x + i));
-      } else {
-        flt4 v;
-        v.x = xo[0];
-        v.y = xo[1];
-        v.z = xo[2];
-        v.w = xo[3];
-        __builtin_nontemporal_store(v, reinterpret_cast<flt4*>(x + i));
+  };
+  constexpr int U = 2;
+  constexpr int64_t TILE = (int64_t)kBlock * V * U;
+  for (int64_t base = 0; base < count; base += TILE) {
+    if (base + TILE <= count) {
+      // full tile: every load issued before the first use
+      typename Raw16<TIn>::type rd[U], ra[U], rb[U], rl[U], ru[U];
+#pragma unroll
+      for (int w = 0; w < U; ++w) {
+        const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+        rd[w] = ld16(d + i);
+        ra[w] = ld16(a + i);
+        rb[w] = ld16(b + i);
+        rl[w] = ld16(l + i);
+        ru[w] = ld16(u + i);
+      }
+#pragma unroll
+      for (int w = 0; w < U; ++w) {
+        const int64_t i = base + (int64_t)w * kBlock * V + (int64_t)threadIdx.x * V;
+        double vd[V], va[V], vb[V], vl[V], vu[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+          vd[k] = rd[w][k];
+          va[k] = ra[w][k];
+          vb[k] = rb[w][k];
+          vl[k] = rl[w][k];
+          vu[k] = ru[w][k];
+        }
+        TIn xo[V];
+        map(vd, va, vb, vl, vu, i, xo);
+        typename Raw16<TIn>::type o;
+#pragma unroll
+        for (int k = 0; k < V; ++k) o[k] = xo[k];
+        st16(x + i, o);
       }
     } else {
+      for (int64_t i = base + (int64_t)threadIdx.x * V; i < min(count, base + TILE);
+           i += (int64_t)kBlock * V) {
+        double vd[V], va[V], vb[V], vl[V], vu[V];
+        Vec<TIn, V>::load(d, i, count, 1.0, vd);
+        Vec<TIn, V>::load(a, i, count, 0.0, va);
+        Vec<TIn, V>::load(b, i, count, 0.0, vb);
+        Vec<TIn, V>::load(l, i, count, 0.0, vl);
+        Vec<TIn, V>::load(u, i, count, 0.0, vu);
+        TIn xo[V];
+        map(vd, va, vb, vl, vu, i, xo);
 #pragma unroll
-      for (int k = 0; k < V; ++k)
-        if (i + k < count) x[i + k] = xo[k];
+        for (int k = 0; k < V; ++k)
+          if (i + k < count) x[i + k] = xo[k];
+      }
     }
   }
   __shared__ double lds[3 * (kBlock / kWave)];

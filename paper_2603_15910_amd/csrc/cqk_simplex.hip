@@ -162,27 +162,54 @@ __device__ __forceinline__ uint32_t condat_thread(const TA* v, uint32_t active, 
   return J;
 }
 
-// Loads V consecutive values of y starting at i (count-guarded; a 16-byte
-// load where it is aligned).
+// Loads V consecutive values of y starting at i (count-guarded; one 16-byte
+// load when the vector is in range).
 template <typename TIn>
 __device__ __forceinline__ void load_y(const TIn* y, int64_t i, int64_t n, TIn* o) {
   constexpr int V = VecWidth<TIn>::value;
-  if (i + V <= n && aligned16(y + i)) {
-    if constexpr (V == 4) {
-      flt4 v = __builtin_nontemporal_load(reinterpret_cast<const flt4*>(y + i));
-      o[0] = v.x;
-      o[1] = v.y;
-      o[2] = v.z;
-      o[3] = v.w;
-    } else {
-      dbl2 v = __builtin_nontemporal_load(reinterpret_cast<const dbl2*>(y + i));
-      o[0] = v.x;
-      o[1] = v.y;
-    }
+  if (i + V <= n) {
+    const typename Raw16<TIn>::type v = ld16(y + i);
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[k] = v[k];
   } else {
 #pragma unroll
     for (int k = 0; k < V; ++k) o[k] = (i + k < n) ? y[i + k] : TIn(0);
   }
+}
+
+// NL vectors per lane at base + q*64*V + lane*V, q < NL; when the whole tile
+// is in range every load is issued before the first use.
+template <typename TIn, int NL>
+__device__ __forceinline__ void load_tile(const TIn* y, int64_t base, int lane, int64_t n,
+                                          TIn* o) {
+  constexpr int V = VecWidth<TIn>::value;
+  if (base + (int64_t)NL * kWave * V <= n) {
+    typename Raw16<TIn>::type r[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) r[q] = ld16(y + base + (int64_t)q * kWave * V + lane * V);
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+#pragma unroll
+      for (int k = 0; k < V; ++k) o[q * V + k] = r[q][k];
+  } else {
+#pragma unroll
+    for (int q = 0; q < NL; ++q)
+      load_y<TIn>(y, base + (int64_t)q * kWave * V + lane * V, n, &o[q * V]);
+  }
+}
+
+// The largest T not above x (so that v > result never drops a v > x).
+template <typename T>
+__device__ __forceinline__ T round_down_to(double x);
+template <>
+__device__ __forceinline__ float round_down_to<float>(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -__builtin_huge_valf());
+  return f;
+}
+template <>
+__device__ __forceinline__ double round_down_to<double>(double x) {
+  return x;
 }
 
 // Partial record of the Algorithm 2 kernel.
@@ -215,40 +242,56 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   // wave-uniform: the survivors this wave kept so far, the smallest bound
   double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
   double acc[C_NSUM] = {0, 0, 0, 0, 0};
-  TA vmx = -__builtin_huge_valf();
-  int nbad = 0;
+  double abs_sum = 0.0;            // sum |y| (l1 only)
+  TIn vmx = -(TIn)__builtin_huge_val();
+  TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
   for (int64_t base = 0; base < count; base += TILE) {
+    const bool full = base + TILE <= count;
     TIn yv[K];
-    TA v[K];
+    TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
+    load_tile<TIn, NL>(y, base, lane, count, yv);
+    TIn tmax = -(TIn)__builtin_huge_val();
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = q * V + k;
+        const bool in = full || (i + k < count);
+        av[e] = l1 ? absval(yv[e]) : yv[e];
+        badacc += in ? yv[e] * TIn(0) : TIn(0);
+        if (l1) abs_sum += in ? (double)av[e] : 0.0;
+        tmax = max(tmax, in ? av[e] : -(TIn)__builtin_huge_val());
+      }
+    }
+    vmx = max(vmx, tmax);
+    // The first bound: J = {the tile's largest value} gives lam_J = r - max
+    // (Algorithm 2's own first set, with the best single element).
+    if (lam_min == inf_d()) {
+      const double m = wave_max((double)tmax);
+      if (m > -inf_d()) lam_min = rd - m;
+    }
+    // Values at or below -lam_min (any lam_J >= lam*, eq. (lambdaJ)) are zero
+    // at the solution: only the rest enters Algorithm 2.  The threshold is
+    // rounded down into TIn, so the comparison never drops a value it must
+    // keep.
+    const TIn thr = round_down_to<TIn>(-lam_min);
     uint32_t active = 0;
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
-      load_y<TIn>(y, i, count, &yv[q * V]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = q * V + k;
-        const TA t = (TA)yv[e];
-        v[e] = l1 ? absval(t) : t;
-        if (i + k < count) {
-          active |= 1u << e;
-          acc[C_ABS] += fabs((double)yv[e]);
-          nbad += (absval(yv[e]) < (TIn)__builtin_huge_val()) ? 0 : 1;
-          vmx = max(vmx, v[e]);
-        }
+        const bool in = full || (i + k < count);
+        active |= (in && av[e] > thr) ? (1u << e) : 0u;
       }
     }
-    // values at or below the wave's best bound so far are zero at the
-    // solution: only the rest enters Algorithm 2, and a tile with none left
-    // costs no wave reduction
-    if (lam_min < inf_d()) {
-      const TA lb = (TA)lam_min;
-#pragma unroll
-      for (int e = 0; e < K; ++e)
-        if (!(v[e] + lb > TA(0))) active &= ~(1u << e);
-    }
     if (__ballot(active != 0u) == 0) continue;
+    TA v[K];
+#pragma unroll
+    for (int e = 0; e < K; ++e) v[e] = (TA)av[e];
     int c = 0;
     TA S = TA(0);
     uint32_t J;
@@ -278,6 +321,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
     if (ct > 0.0 && run_c > 0.0) lam_b = fmin(lam_b, (rd - (skt + run_s)) / (ct + run_c));
     if (run_c > 0.0) lam_b = fmin(lam_b, (rd - run_s) / run_c);
+    lam_b = fmin(lam_b, lam_min);
     uint32_t keep = 0;
     double nk = 0.0, ks = 0.0;
     auto select = [&](double lb) {
@@ -330,7 +374,8 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   } else {
     acc[C_CNT] = acc[C_SUM] = acc[C_NOUT] = 0.0;
   }
-  acc[C_BAD] = (double)nbad;
+  acc[C_BAD] = (badacc == TIn(0)) ? 0.0 : 1.0;
+  acc[C_ABS] = abs_sum;
   const double vmax = (double)vmx;
   block_reduce<C_NSUM, 1, 1, kBlock>(acc, &lam_min, &vmax, lds, tot);
   if (threadIdx.x == 0) write_partial(A.partials, tot, C_NPART);
@@ -769,32 +814,36 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   __shared__ double tot[S_NSUM + 1];
   TA phi = TA(0);
   double acc[S_NSUM] = {0, 0, 0, 0, 0, 0, 0};
-  double vmax = -inf_d();
+  // per-lane counts in integers; |y| sums only where the l1 test needs them
+  int cm = 0, cp = 0, nin = 0;
+  double abs_sum = 0.0;
+  TIn vmx = -(TIn)__builtin_huge_val();
+  TIn badacc = TIn(0);
   int64_t written = 0;
   for (int64_t base = 0; base < count; base += TILE) {
+    const bool full = base + TILE <= count;
     TIn y[E];
     bool keep[E];
+    load_tile<TIn, E / V>(yv, base, lane, count, y);
 #pragma unroll
     for (int w = 0; w < E / V; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
-      load_y<TIn>(yv, i, count, &y[w * V]);
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
         keep[e] = false;
-        if (i + k < count) {
-          const TA t = (TA)y[e];
-          const TA v = l1 ? absval(t) : t;
+        if (full || i + k < count) {
+          const TIn a = l1 ? absval(y[e]) : y[e];
+          const TA v = (TA)a;
           const TA z = v + lam;
           phi += z > TA(0) ? z : TA(0);
-          acc[S_CM] += z > TA(0) ? 1.0 : 0.0;
-          acc[S_CP] += z >= TA(0) ? 1.0 : 0.0;
-          acc[S_NIN] += 1.0;
+          cm += z > TA(0) ? 1 : 0;
+          cp += z >= TA(0) ? 1 : 0;
+          nin += 1;
           if (src == 0) {
-            const double td = (double)y[e];
-            acc[S_ABS] += fabs(td);
-            acc[S_BAD] += (fabs(td) < inf_d()) ? 0.0 : 1.0;
-            vmax = fmax(vmax, (double)v);
+            badacc += y[e] * TIn(0);
+            vmx = max(vmx, a);
+            if (l1) abs_sum += (double)a;
           }
           if constexpr (MULTI) {
 #pragma unroll
@@ -826,6 +875,12 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
     *ocnt = (int32_t)written;
     acc[S_NOUT] = (double)written;
   }
+  acc[S_CM] = (double)cm;
+  acc[S_CP] = (double)cp;
+  acc[S_NIN] = (double)nin;
+  acc[S_ABS] = abs_sum;
+  acc[S_BAD] = (badacc == TIn(0)) ? 0.0 : 1.0;
+  const double vmax = (double)vmx;
   // phi: reduced in the working precision TA (wave, then waves in order)
   const TA phw = wave_sum(phi);
   __shared__ TA phl[kBlock / kWave];
@@ -960,50 +1015,62 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
   const TIn* y = (const TIn*)A.y + off;
   TIn* x = (TIn*)A.x + off;
   double acc[2] = {0.0, 0.0};
-  for (int64_t i = (int64_t)threadIdx.x * V; i < count; i += (int64_t)kBlock * V) {
-    TIn o[V];
-    if (mode == kFinScatter || mode == kFinZero) {
+  constexpr int U = 4;
+  constexpr int64_t TILE = (int64_t)kBlock * V * U;
+  const bool zero = (mode == kFinScatter || mode == kFinZero);
+  for (int64_t base = 0; base < count; base += TILE) {
+    const bool full = base + TILE <= count;
+    TIn yv[U * V];
+    if (!zero) {
+      if (full) {
+        typename Raw16<TIn>::type r[U];
 #pragma unroll
-      for (int k = 0; k < V; ++k) o[k] = TIn(0);
-    } else {
-      TIn yv[V];
-      load_y<TIn>(y, i, count, yv);
+        for (int u = 0; u < U; ++u)
+          r[u] = ld16(y + base + (int64_t)u * kBlock * V + (int64_t)threadIdx.x * V);
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int k = 0; k < V; ++k) yv[u * V + k] = r[u][k];
+      } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          load_y<TIn>(y, base + (int64_t)u * kBlock * V + (int64_t)threadIdx.x * V, count,
+                      &yv[u * V]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + (int64_t)u * kBlock * V + (int64_t)threadIdx.x * V;
+      TIn o[V];
 #pragma unroll
       for (int k = 0; k < V; ++k) {
-        if (mode == kFinCopy) {
-          o[k] = yv[k];
+        if (zero) {
+          o[k] = TIn(0);
+        } else if (mode == kFinCopy) {
+          o[k] = yv[u * V + k];
         } else {
-          const TA t = (TA)yv[k];
+          const TA t = (TA)yv[u * V + k];
           const TA vv = l1 ? absval(t) : t;
           const TA z = vv + lam;
           TA xv = z > TA(0) ? z : TA(0);
           if (l1 && t < TA(0)) xv = -xv;
           o[k] = (TIn)xv;
         }
-        if (i + k < count) {
+        if (!zero && i + k < count) {
           acc[0] += fabs((double)o[k]);
           acc[1] += (o[k] != TIn(0)) ? 1.0 : 0.0;
         }
       }
-    }
-    if (i + V <= count && aligned16(x + i)) {
-      if constexpr (V == 4) {
-        flt4 w;
-        w.x = o[0];
-        w.y = o[1];
-        w.z = o[2];
-        w.w = o[3];
-        __builtin_nontemporal_store(w, reinterpret_cast<flt4*>(x + i));
-      } else {
-        dbl2 w;
-        w.x = o[0];
-        w.y = o[1];
-        __builtin_nontemporal_store(w, reinterpret_cast<dbl2*>(x + i));
-      }
-    } else {
+      if (i + V <= count) {
+        typename Raw16<TIn>::type w;
 #pragma unroll
-      for (int k = 0; k < V; ++k)
-        if (i + k < count) x[i + k] = o[k];
+        for (int k = 0; k < V; ++k) w[k] = o[k];
+        st16(x + i, w);
+      } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k)
+          if (i + k < count) x[i + k] = o[k];
+      }
     }
   }
   if (mode == kFinScatter) return;  // the scatter kernel writes the totals
