@@ -89,13 +89,57 @@ def timed(fn, reps, sync):
     return statistics.median(out)
 
 
-def extras(ctx, dev, torch):
+def graph_replay_ms(torch, fn, reps):
+    """Captures fn (queue-only, no host sync) in a graph and times replays
+    with events on the replay stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        graph.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+EXTRA_SECTIONS = ("correlated", "simplex", "batched", "differentiable")
+
+
+def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
     import paper_2603_15910_amd as cqk
     from paper_2603_15910_amd import workloads as W
     sync = torch.cuda.synchronize
     ex = {}
+    default_sched = ctx.batch_schedule()
 
     # general CQK, correlated variant (n = 1e8, FP64)
+    if "correlated" in sections:
+        ex.update(extra_correlated(ctx, dev, torch))
+    if "simplex" in sections:
+        ex.update(extra_simplex(ctx, dev, torch))
+    if "batched" in sections:
+        ex.update(extra_batched(ctx, dev, torch, row_loop))
+    if "differentiable" in sections:
+        ex.update(extra_differentiable(ctx, dev, torch))
+    ctx.set_batch_schedule(**default_sched)
+    ctx.set_batch_schedule(**default_sched, backward=True)
+    return ex
+
+
+def extra_correlated(ctx, dev, torch):
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
     inst = W.cqk_correlated(100_000_000, 1)
     t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
     r = inst["r"]
@@ -111,7 +155,13 @@ def extras(ctx, dev, torch):
         "finalize_gbs": info["finalize_bytes"] / (info["finalize_ms"] * 1e-3) / 1e9}
     del t, x
     torch.cuda.empty_cache()
+    return ex
 
+
+def extra_simplex(ctx, dev, torch):
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
     # simplex and l1 projections, n = 1e8, FP32 inputs
     n = 100_000_000
     for dist in ("normal", "uniform"):
@@ -138,34 +188,59 @@ def extras(ctx, dev, torch):
                     "status": info["status_name"]}
         del y, xs
         torch.cuda.empty_cache()
+    return ex
 
+
+def extra_batched(ctx, dev, torch, row_loop=True):
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
     # batched simplex: 8192 rows, lengths log-uniform in [64, 65536]
     off, yb = W.batched_simplex_input(8192, 64, 65536, 1)
     total = int(off[-1])
     offs = torch.from_numpy(off).to(dev)
     ybt = torch.from_numpy(yb).to(dev)
     xb = torch.empty_like(ybt)
+    default_sched = ctx.batch_schedule()
     ctx.project_simplex_batched(ybt, offs, 1.0, out=xb)
+    ms_default = timed(lambda: ctx.project_simplex_batched(ybt, offs, 1.0, out=xb), 10, sync)
+    sched, tune_ms = ctx.tune_batched(ybt, offs, 1.0, repeats=3, out=xb)
     ms = timed(lambda: ctx.project_simplex_batched(ybt, offs, 1.0, out=xb), 10, sync)
     _, info = ctx.project_simplex_batched(ybt, offs, 1.0, out=xb)
+    graph_ms = graph_replay_ms(torch, lambda: ctx.project_simplex_batched(
+        ybt, offs, 1.0, out=xb, sync=False), 20)
     # comparator: one plain solve per row (same library, same stream)
-    views = [ybt[int(off[s]):int(off[s + 1])] for s in range(8192)]
-    outs = [xb[int(off[s]):int(off[s + 1])] for s in range(8192)]
-    sync()
-    t0 = time.perf_counter()
-    for v, o in zip(views, outs):
-        ctx.project_simplex(v, 1.0, out=o)
-    sync()
-    loop_ms = (time.perf_counter() - t0) * 1e3
+    loop_ms = None
+    if row_loop:
+        views = [ybt[int(off[s]):int(off[s + 1])] for s in range(8192)]
+        outs = [xb[int(off[s]):int(off[s + 1])] for s in range(8192)]
+        sync()
+        t0 = time.perf_counter()
+        for v, o in zip(views, outs):
+            ctx.project_simplex(v, 1.0, out=o)
+        sync()
+        loop_ms = (time.perf_counter() - t0) * 1e3
+        del views, outs
     ex["batched_simplex_8192rows"] = {
         "rows": 8192, "elements": total, "ms": ms, "elements_per_s": total / (ms * 1e-3),
         "gbs_8B_per_elem": 8.0 * total / (ms * 1e-3) / 1e9, "status": info["status_name"],
+        "graph_replay_ms": graph_ms,
+        "graph_gbs_8B_per_elem": 8.0 * total / (graph_ms * 1e-3) / 1e9,
+        "schedule": sched, "tuned_kernel_ms": tune_ms,
+        "default_schedule": default_sched, "default_schedule_ms": ms_default,
         "rows_spilled": info["rows_spilled"],
         "per_row_loop_ms": loop_ms,
-        "speedup_vs_per_row_loop": loop_ms / ms}
-    del ybt, xb, offs, views, outs
+        "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}
+    del ybt, xb, offs
     torch.cuda.empty_cache()
+    return ex
 
+
+def extra_differentiable(ctx, dev, torch):
+    import paper_2603_15910_amd as cqk
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
     # differentiable batched projection: 4096 rows in [1024, 32768], y = 3 N(0,1)
     off, yb = W.batched_simplex_input(4096, 1024, 32768, 1, scale=3.0)
     total = int(off[-1])
@@ -175,6 +250,9 @@ def extras(ctx, dev, torch):
     xf = torch.empty_like(yt)
     gy = torch.empty_like(yt)
     ctx.project_simplex_batched(yt, offs, 1.0, out=xf)
+    fsched, _ = ctx.tune_batched(yt, offs, 1.0, repeats=3, out=xf)
+    ctx.project_simplex_batched(yt, offs, 1.0, out=xf)
+    bsched, _ = ctx.tune_batched_backward(xf, g, offs, repeats=3, grad_y=gy)
     fwd = timed(lambda: ctx.project_simplex_batched(yt, offs, 1.0, out=xf), 10, sync)
     bwd = timed(lambda: ctx.project_simplex_batched_backward(xf, g, offs, grad_y=gy), 10, sync)
 
@@ -189,7 +267,8 @@ def extras(ctx, dev, torch):
         "rows": 4096, "elements": total, "forward_ms": fwd, "backward_ms": bwd,
         "forward_backward_autograd_ms": fwdbwd,
         "forward_gbs_8B": 8.0 * total / (fwd * 1e-3) / 1e9,
-        "backward_gbs_12B": 12.0 * total / (bwd * 1e-3) / 1e9}
+        "backward_gbs_12B": 12.0 * total / (bwd * 1e-3) / 1e9,
+        "forward_schedule": fsched, "backward_schedule": bsched}
     return ex
 
 
@@ -204,6 +283,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device copy (reference for HBM counters)")
+    ap.add_argument("--only", choices=EXTRA_SECTIONS, default=None,
+                    help="run one extra workload alone (for profiling) and print its record")
+    ap.add_argument("--no-row-loop", action="store_true",
+                    help="skip the per-row loop comparator of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -216,6 +299,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.only:
+        ctx = cqk.Context(0)
+        ex = extras(ctx, dev, torch, sections=(args.only,), row_loop=not args.no_row_loop)
+        print(json.dumps({"only": args.only, "extras": ex}))
+        return
     n = args.n
     log(f"bench: generating cqk_uniform n={n}")
     inst = W.cqk_uniform(n, 1)
@@ -251,7 +339,8 @@ def main():
 
     pass_bytes = sum(i["pass_bytes"] for i in infos)
     pass_ms = sum(i["pass_ms"] for i in infos)
-    passes = sum(i["passes"] for i in infos)
+    # every launch of the pass kernel, as a kernel trace counts them
+    passes = sum(i["pass_launches"] for i in infos)
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9 if pass_ms > 0 else 0.0
     fin_gbs = (sum(i["finalize_bytes"] for i in infos) /
                (sum(i["finalize_ms"] for i in infos) * 1e-3) / 1e9)

@@ -105,6 +105,9 @@ typedef struct cqk_info {
   int64_t rows_spilled;     /* batched: long rows whose survivors of Alg. 2 did
                                not fit the on-chip list (Newton then re-reads
                                the row); 0 otherwise */
+  int64_t pass_launches;    /* grid passes queued (pass_ms covers all of them;
+                               those queued after the loop stopped return at
+                               once and move no bytes) */
 } cqk_info;
 
 /* One record per kernel pass (opts.trace = 1). */

@@ -61,6 +61,7 @@ class cqk_info(C.Structure):
         ("finalize_bytes", C.c_double),
         ("finalize_ms", C.c_double),
         ("rows_spilled", C.c_int64),
+        ("pass_launches", C.c_int64),
     ]
 
     def as_dict(self):

@@ -35,7 +35,10 @@ cqk_status ensure_buffer(DeviceBuf& b, size_t bytes) {
 cqk_status ensure_events(cqk_ctx* ctx, size_t count) {
   while (ctx->events.size() < count) {
     hipEvent_t e;
-    if (hipEventCreate(&e) != hipSuccess) return CQK_DEVICE_ERROR;
+    // timing only (read after the stream is synchronised): no system-scope
+    // fence, which would write back the L2 caches between the kernels timed
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+      return CQK_DEVICE_ERROR;
     ctx->events.push_back(e);
   }
   return CQK_OK;

@@ -29,6 +29,7 @@
 // the bracket, plus the free-side analogue.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "cqk_device.h"
 #include "cqk_internal.h"
@@ -801,14 +802,15 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.lam_final = __builtin_nan("");
 
   hipStream_t s = ctx->stream;
-  const size_t nev = (size_t)2 * (o.max_iter * 2 + 8);
+  // events 0, 1: the finalize of the last batch; then one pair per grid pass
+  const size_t nev = (size_t)2 + 2 * (o.max_iter * 2 + 8);
   if (o.timing) {
     stt = ensure_events(ctx, nev);
     if (stt != CQK_OK) return stt;
   }
   hipLaunchKernelGGL(gen_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  int ev = 0;
+  int ev = 2;
   // a grid pass (timed when asked) followed by its one-block reduction
   auto launch = [&](auto kern, auto reduce) {
     if (o.timing && ev + 2 <= (int)nev) hipEventRecord(ctx->events[ev], s);
@@ -819,17 +821,28 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     }
     hipLaunchKernelGGL(reduce, dim3(1), dim3(kRBlock), 0, s, A, G);
   };
+  // The primal recovery does nothing while the loop still runs, so it is
+  // queued behind every batch and the host waits once per batch.
+  auto finalize = [&]() {
+    if (o.timing) hipEventRecord(ctx->events[0], s);
+    hipLaunchKernelGGL(gen_finalize_kernel<TIn>, dim3(G), dim3(kBlock), 0, s, A);
+    if (o.timing) hipEventRecord(ctx->events[1], s);
+    hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G);
+  };
   if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
     launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel);
 
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;
-  int batch = 8;
+  // Algorithm 1 typically stops after five to seven evaluations here
+  int batch = 6;
   while (launched < max_launch) {
     const int k = std::min(batch, max_launch - launched);
     for (int i = 0; i < k; ++i) launch(gen_pass_kernel<TIn>, gen_update_kernel);
     launched += k;
+    finalize();
+    if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
     if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
       return CQK_DEVICE_ERROR;
     if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
@@ -837,16 +850,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     batch = 4;
   }
   const int pass_events = ev;
-  launch(gen_finalize_kernel<TIn>, gen_finalize_reduce_kernel);
-  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
-    return CQK_DEVICE_ERROR;
-  const int ntr = std::min(hs->ntrace, kMaxTrace);
-  if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
   int ntrace = std::min(hs->ntrace, init.trace_cap);
   ctx->last_trace.resize(ntrace);
   ctx->last_trace_count = hs->ntrace;
-  (void)ntr;
   if (ntrace > 0) {
     if (hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace, sizeof(cqk_trace_rec) * ntrace,
                          hipMemcpyDeviceToHost)) != CQK_OK)
@@ -856,6 +862,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     hs->status = CQK_NOT_CONVERGED;
   }
   if (info) {
+    std::memset(info, 0, sizeof(*info));
     info->status = hs->status;
     info->iterations = hs->iter;
     info->passes = hs->passes;
@@ -870,16 +877,16 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     info->pass_ms = 0.0;
     info->finalize_bytes = (double)n * (6.0 * sizeof(TIn));
     info->finalize_ms = 0.0;
+    info->pass_launches = (pass_events - 2) / 2;
     if (o.timing) {
-      // the first hs->passes launches did work, the rest returned at once
-      const int worked = std::min(hs->passes, pass_events / 2);
-      for (int i = 0; i < worked; ++i) {
+      // every grid pass queued; those after the loop stopped returned at once
+      for (int i = 2; i + 1 < pass_events; i += 2) {
         float ms = 0.f;
-        hipEventElapsedTime(&ms, ctx->events[2 * i], ctx->events[2 * i + 1]);
+        hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
         info->pass_ms += ms;
       }
       float ms = 0.f;
-      hipEventElapsedTime(&ms, ctx->events[pass_events], ctx->events[pass_events + 1]);
+      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
       info->finalize_ms = ms;
     }
     // algorithmic bytes from the per-pass records (needs the trace)

@@ -42,6 +42,7 @@
 // host queues them behind every batch of iterations and waits once per batch.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "cqk_device.h"
 #include "cqk_internal.h"
@@ -53,7 +54,8 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block kernels (reductions, the tail loop)
 constexpr int kWaves = kBlock / kWave;
 constexpr int kCondatK = 16;   // values per lane per tile in Algorithm 2
-constexpr int kRefine = 8;     // refinement rounds per wave tile
+constexpr int kRefine = 8;     // refinement rounds on a wave's first tile
+constexpr int kRefineLater = 3;  // and on its later (already filtered) tiles
 constexpr int kTailBytes = 128 * 1024;  // LDS copy of the set the tail loop runs on
 constexpr int kTailRegs = 4;            // region counts per thread when packing
 constexpr int kCand = 12;               // start refinement candidates
@@ -295,17 +297,19 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     int c = 0;
     TA S = TA(0);
     uint32_t J;
-    if (__ballot(__popc(active) > 1) != 0) {
+    const bool first = run_c == 0.0;
+    if (first && __ballot(__popc(active) > 1) != 0) {
       J = condat_thread<K, TA>(v, active, r, l1, c, S);
     } else {
-      // at most one value per lane: Algorithm 2 keeps it (l1: if non-zero)
+      // at most one value per lane, or a tile the wave's running bound has
+      // already filtered: every remaining value joins J (l1: if non-zero)
       J = 0;
 #pragma unroll
       for (int e = 0; e < K; ++e) {
         if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
-          J = 1u << e;
-          c = 1;
-          S = v[e];
+          J |= 1u << e;
+          c += 1;
+          S += v[e];
         }
       }
     }
@@ -338,7 +342,8 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         }
       }
     };
-    for (int it = 0; it < kRefine; ++it) {
+    const int rounds = first ? kRefine : kRefineLater;
+    for (int it = 0; it < rounds; ++it) {
       select(lam_b);
       const double kc = wave_sum(nk), kss = wave_sum(ks);
       if (kc == 0.0) break;
@@ -1312,6 +1317,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     return CQK_DEVICE_ERROR;
   if (hs->status == kRunning) hs->status = CQK_NOT_CONVERGED;
   if (info) {
+    std::memset(info, 0, sizeof(*info));
     info->status = hs->status;
     info->iterations = hs->iter;
     info->passes = hs->passes;
@@ -1325,6 +1331,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     info->n_after_init = hs->n_init;
     info->pass_bytes = 0.0;
     info->pass_ms = 0.0;
+    info->pass_launches = (pass_events - 4) / 2;
     info->finalize_ms = 0.0;
     info->rows_spilled = 0;
     const bool scatter = hs->fin_mode == kFinDense && hs->src != 0;

@@ -42,7 +42,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(L.cqk_opts) == 64
     assert L.cqk_opts.lambda0_user.offset == 8
     assert L.cqk_opts.timing.offset == 60
-    assert C.sizeof(L.cqk_info) == 104
+    assert C.sizeof(L.cqk_info) == 112
     assert L.cqk_info.lambda_.offset == 16
     assert C.sizeof(L.cqk_trace_rec) == 72
     assert C.sizeof(L.cqk_batch_schedule) == 16

@@ -183,3 +183,16 @@ def test_unaligned_views(ctx, shift):
         _, info = ctx.project_simplex(yv, 1.0, out=xv, lambda0=start)
         assert info["status"] == 0
         check_simplex(xv.cpu().numpy(), y[shift:], x_ref, lam_ref, 1.0, 1e-5)
+
+
+@pytest.mark.parametrize("dtype,n", [(np.float32, 32768), (np.float32, 32769),
+                                     (np.float64, 16384), (np.float64, 16385)])
+@pytest.mark.parametrize("start", ["condat", "zero"])
+def test_tail_loop_capacity_boundary(ctx, dtype, n, start):
+    """Sets of exactly the one-block loop's LDS capacity and one more."""
+    for dist in ("uniform", "normal_small"):
+        y = W.simplex_input(n, 31, dist, dtype)
+        x_ref, lam_ref = _ref(y, 1.0)
+        x, info = _run(ctx, y, 1.0, lambda0=start)
+        assert info["status"] == 0, info
+        check_simplex(x, y, x_ref, lam_ref, 1.0, TOL[dtype])
