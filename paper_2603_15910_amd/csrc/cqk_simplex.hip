@@ -54,8 +54,7 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block kernels (reductions, the tail loop)
 constexpr int kWaves = kBlock / kWave;
 constexpr int kCondatK = 16;   // values per lane per tile in Algorithm 2
-constexpr int kRefine = 8;     // refinement rounds on a wave's first tile
-constexpr int kRefineLater = 3;  // and on its later (already filtered) tiles
+constexpr int kRefine = 8;     // refinement rounds on a wave's first kept tile
 constexpr int kTailBytes = 128 * 1024;  // LDS copy of the set the tail loop runs on
 constexpr int kTailRegs = 4;            // region counts per thread when packing
 constexpr int kCand = 12;               // start refinement candidates
@@ -291,69 +290,77 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       }
     }
     if (__ballot(active != 0u) == 0) continue;
-    TA v[K];
-#pragma unroll
-    for (int e = 0; e < K; ++e) v[e] = (TA)av[e];
-    int c = 0;
-    TA S = TA(0);
-    uint32_t J;
-    const bool first = run_c == 0.0;
-    if (first && __ballot(__popc(active) > 1) != 0) {
-      J = condat_thread<K, TA>(v, active, r, l1, c, S);
-    } else {
-      // at most one value per lane, or a tile the wave's running bound has
-      // already filtered: every remaining value joins J (l1: if non-zero)
-      J = 0;
-#pragma unroll
-      for (int e = 0; e < K; ++e) {
-        if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
-          J |= 1u << e;
-          c += 1;
-          S += v[e];
-        }
-      }
-    }
-    const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
-    // Every lam below is lam_J of some non-empty J, hence >= lam*
-    // (Section 2.2): the union of the lanes' sets, its union with the
-    // wave's earlier survivors, and the refinements
-    //   lam <- lam_J'  with  J' = {j in J : y_j + lam > 0},
-    // each of which can only lower lam (it is Algorithm 4's step on the
-    // tile's own sub-problem).
-    const double ct = wave_sum((double)c);
-    const double skt = wave_sum((double)S);
-    double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
-    if (ct > 0.0 && run_c > 0.0) lam_b = fmin(lam_b, (rd - (skt + run_s)) / (ct + run_c));
-    if (run_c > 0.0) lam_b = fmin(lam_b, (rd - run_s) / run_c);
-    lam_b = fmin(lam_b, lam_min);
     uint32_t keep = 0;
     double nk = 0.0, ks = 0.0;
-    auto select = [&](double lb) {
-      const TA lt = (TA)fmin(lam_t, lb);
-      keep = 0;
-      nk = 0.0;
-      ks = 0.0;
+    if (run_c > 0.0) {
+      // A later tile: the wave's running bound has already filtered it and
+      // every value left is kept (l1: if non-zero); the bound becomes lam_J
+      // of everything kept so far (below), again >= lam*.
 #pragma unroll
       for (int e = 0; e < K; ++e) {
-        if (((J >> e) & 1u) && (v[e] + lt > TA(0))) {
+        if (((active >> e) & 1u) && (!l1 || av[e] > TIn(0))) {
           keep |= 1u << e;
           nk += 1.0;
-          ks += (double)v[e];
+          ks += (double)av[e];
         }
       }
-    };
-    const int rounds = first ? kRefine : kRefineLater;
-    for (int it = 0; it < rounds; ++it) {
+    } else {
+      TA v[K];
+#pragma unroll
+      for (int e = 0; e < K; ++e) v[e] = (TA)av[e];
+      int c = 0;
+      TA S = TA(0);
+      uint32_t J;
+      if (__ballot(__popc(active) > 1) != 0) {
+        J = condat_thread<K, TA>(v, active, r, l1, c, S);
+      } else {
+        // at most one value per lane: it joins J (l1: if non-zero)
+        J = 0;
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+          if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
+            J |= 1u << e;
+            c += 1;
+            S += v[e];
+          }
+        }
+      }
+      const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
+      // The wave's first kept tile.  Every lam below is lam_J of some
+      // non-empty J, hence >= lam* (Section 2.2): the union of the lanes'
+      // sets and the refinements
+      //   lam <- lam_J'  with  J' = {j in J : y_j + lam > 0},
+      // each of which can only lower lam (it is Algorithm 4's step on the
+      // tile's own sub-problem).
+      const double ct = wave_sum((double)c);
+      const double skt = wave_sum((double)S);
+      double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
+      lam_b = fmin(lam_b, lam_min);
+      auto select = [&](double lb) {
+        const TA lt = (TA)fmin(lam_t, lb);
+        keep = 0;
+        nk = 0.0;
+        ks = 0.0;
+#pragma unroll
+        for (int e = 0; e < K; ++e) {
+          if (((J >> e) & 1u) && (v[e] + lt > TA(0))) {
+            keep |= 1u << e;
+            nk += 1.0;
+            ks += (double)v[e];
+          }
+        }
+      };
+      for (int it = 0; it < kRefine; ++it) {
+        select(lam_b);
+        const double kc = wave_sum(nk), kss = wave_sum(ks);
+        if (kc == 0.0) break;
+        const double nl = (rd - kss) / kc;
+        if (!(nl < lam_b)) break;
+        lam_b = nl;
+      }
       select(lam_b);
-      const double kc = wave_sum(nk), kss = wave_sum(ks);
-      if (kc == 0.0) break;
-      double nl = (rd - kss) / kc;
-      if (run_c > 0.0) nl = fmin(nl, (rd - (kss + run_s)) / (kc + run_c));
-      if (!(nl < lam_b)) break;
-      lam_b = nl;
+      lam_min = fmin(lam_min, lam_b);
     }
-    select(lam_b);
-    lam_min = fmin(lam_min, lam_b);
     if (__ballot(keep != 0u) == 0) continue;
 #pragma unroll
     for (int e = 0; e < K; ++e) {
