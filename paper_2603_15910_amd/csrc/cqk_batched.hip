@@ -468,31 +468,23 @@ __device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
   }
   // start refinement: Newton steps lam_J(J_j), J_j = {v + lam_j > 0}, from
   // candidates between lam_0 and -max y; each is an upper bound of lam*
+  // (one candidate at a time: the lists are short and in LDS, and this keeps
+  // the register count low enough for more workgroups per compute unit)
   double lam = lam0;
-  {
-    double cc[kCand], cs[kCand], lj[kCand];
-#pragma unroll
-    for (int j = 0; j < kCand; ++j) {
-      lj[j] = -vmax + (lam0 + vmax) / (double)(1u << j);
-      cc[j] = 0.0;
-      cs[j] = 0.0;
-    }
+  for (int j = 0; j < kCand; ++j) {
+    const double lj = -vmax + (lam0 + vmax) / (double)(1u << j);
+    double cc = 0.0, cs = 0.0;
     for (int w = 0; w < kWaves; ++w) {
       for (int i = lane; i < nws[w]; i += kWave) {
         const double v = (double)L.sv[w][i];
-#pragma unroll
-        for (int j = 0; j < kCand; ++j) {
-          const bool in = v + lj[j] > 0.0;
-          cc[j] += in ? 1.0 : 0.0;
-          cs[j] += in ? v : 0.0;
-        }
+        const bool in = v + lj > 0.0;
+        cc += in ? 1.0 : 0.0;
+        cs += in ? v : 0.0;
       }
     }
-#pragma unroll
-    for (int j = 0; j < kCand; ++j) {
-      const double c = wave_sum(cc[j]), sj = wave_sum(cs[j]);
-      if (c > 0.0) lam = fmin(lam, (rd - sj) / c);
-    }
+    cc = wave_sum(cc);
+    cs = wave_sum(cs);
+    if (cc > 0.0) lam = fmin(lam, (rd - cs) / cc);
   }
   lam = wave_newton_lists(L, nws, rd, lam);
   // x for this wave's list; every other x of the row is already zero
@@ -643,7 +635,7 @@ __device__ __forceinline__ bool item_is_long(const BatArgs& A, int item, int nlo
 }
 
 template <int SP>
-__global__ __launch_bounds__(kBlock) void bat_solve_kernel(BatArgs A) {
+__global__ __launch_bounds__(kBlock, 3) void bat_solve_kernel(BatArgs A) {
   __shared__ BatLds L;
   const int nlong = A.counters[CTR_NLONG];
   const int nshort = A.counters[CTR_NSHORT];

@@ -56,8 +56,15 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kCondatK = 16;   // values per lane per tile in Algorithm 2
 constexpr int kRefine = 8;     // refinement rounds on a wave's first kept tile
 constexpr int kTailBytes = 128 * 1024;  // LDS copy of the set the tail loop runs on
-constexpr int kTailRegs = 4;            // region counts per thread when packing
 constexpr int kCand = 12;               // start refinement candidates
+
+// Tail states (SpxState::tail): the set of the next evaluation fits the
+// one-block loop.
+//   kTailPack: it sits in compacted regions; the next grid pass copies them
+//              densely to tval/tidx (at offsets this block writes to toff),
+//              and the update kernel after it runs the loop on that copy;
+//   kTailY:    the caller's y itself is that small (run from y at once).
+enum : int32_t { kTailNone = 0, kTailPack = 1, kTailY = 2 };
 
 struct SpxArgs {
   const void* y;
@@ -67,7 +74,9 @@ struct SpxArgs {
   void* val[2];      // compacted values (signed y), TIn
   uint32_t* idx[2];  // their indices in y
   int32_t* cnt[2];   // per-wave-region counts of each buffer
-  uint32_t* tidx;    // indices of the set the tail loop ran on
+  void* tval;        // dense copy of the set the tail loop runs on (TIn)
+  uint32_t* tidx;    // its indices in y
+  int32_t* toff;     // per wave region: offset of its survivors in that copy
   double* partials;
   SpxState* st;
   cqk_trace_rec* trace;
@@ -455,7 +464,7 @@ __device__ __forceinline__ void spx_update(SpxState* st, const double* t, double
   st->lam = next;
   // every later iterate is >= lam* (Theorem 1), so y + lam_k <= 0 fixes x at 0
   st->compact_next = (st->compaction != CQK_COMPACT_OFF) ? 1 : 0;
-  if (st->n_src <= st->tail_cap) st->tail = 1;
+  if (st->n_src <= st->tail_cap && st->src != 0) st->tail = kTailPack;
   if (st->iter >= st->max_iter) {
     st->status = CQK_NOT_CONVERGED;
     st->lam_final = lam;
@@ -466,10 +475,8 @@ __device__ __forceinline__ void spx_update(SpxState* st, const double* t, double
 template <typename TIn, typename TA>
 struct TailLds {
   static constexpr int CAP = kTailBytes / (int)sizeof(TIn);
-  static constexpr int RB = kRBlock * kTailRegs;
   static constexpr int NW = kRBlock / kWave;
   TIn tv[CAP];
-  int reg[RB + 1];
   int off[NW + 1];
   double lds[(S_NSUM + 1) * NW];
   double tot[S_NSUM + 1];
@@ -478,95 +485,56 @@ struct TailLds {
   double lam;
 };
 
+// Exclusive prefix of the region counts of buffer si (one block of kRBlock
+// threads): toff[r] = sum of counts of regions < r.
+__device__ __forceinline__ void spx_tail_offsets(const SpxArgs& A, int NR, int si, int* lds_i) {
+  constexpr int P = 8;  // regions per thread per round
+  int base = 0;
+  for (int r0 = 0; r0 < NR; r0 += kRBlock * P) {
+    int c[P];
+    int csum = 0;
+    const int rb = r0 + threadIdx.x * P;
+    if (rb + P <= NR) {
+      // two 16-byte loads (the count arrays are 256-byte aligned, rb % 8 == 0)
+      const int4v* cp = reinterpret_cast<const int4v*>(A.cnt[si] + rb);
+      const int4v c0 = cp[0], c1 = cp[1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        c[j] = c0[j];
+        c[4 + j] = c1[j];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) c[j] = (rb + j < NR) ? A.cnt[si][rb + j] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < P; ++j) csum += c[j];
+    int totc;
+    int ex = base + block_excl_scan<kRBlock>(csum, lds_i, &totc);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int r = r0 + threadIdx.x * P + j;
+      if (r < NR) A.toff[r] = ex;
+      ex += c[j];
+    }
+    base += totc;
+  }
+}
+
 // The remaining Newton iterations inside one block of kRBlock threads, on a
 // copy of the current set in LDS (the caller's y when it is small from the
-// start, else the compacted regions packed densely; their indices go to a
-// global list for the final scatter).  Each iteration is one sweep of LDS.
+// start, else the dense copy the last grid pass made, whose indices stay in
+// tidx for the final scatter).  Each iteration is one sweep of LDS.
 // `sc` is thread 0's copy of the state (status running, tail set); src and
 // l1 are the block-uniform values of that state.  Thread 0 stores the state
 // back when the loop has stopped.
 template <typename TIn, typename TA>
-__device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState& sc, int src, bool l1,
-                             TailLds<TIn, TA>& L) {
+__device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int64_t total, SpxState& sc,
+                                             int src, bool l1, TailLds<TIn, TA>& L) {
   constexpr int CAP = TailLds<TIn, TA>::CAP;
-  constexpr int RB = TailLds<TIn, TA>::RB;
   constexpr int NW = TailLds<TIn, TA>::NW;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  int64_t total;
-  if (src == 0) {
-    total = A.n;
-    const TIn* y = (const TIn*)A.y;
-    for (int i = threadIdx.x; i < CAP && i < A.n; i += kRBlock) L.tv[i] = y[i];
-  } else {
-    // Every thread takes kTailRegs consecutive region counts, a block scan
-    // gives each region its output offset, then output position p is copied
-    // from the region a binary search over those offsets finds (eight
-    // positions per thread at a time, so their loads overlap).
-    const int si = src - 1;
-    const int64_t chunk = A.chunk0 / kWaves;
-    const TIn* sv = (const TIn*)A.val[si];
-    const uint32_t* sx = A.idx[si];
-    int64_t base = 0;
-    for (int r0 = 0; r0 < NR; r0 += RB) {
-      int c[kTailRegs];
-      int csum = 0;
-#pragma unroll
-      for (int j = 0; j < kTailRegs; ++j) {
-        const int r = r0 + threadIdx.x * kTailRegs + j;
-        c[j] = (r < NR) ? A.cnt[si][r] : 0;
-        csum += c[j];
-      }
-      int totc;
-      int ex = block_excl_scan<kRBlock>(csum, L.off, &totc);
-#pragma unroll
-      for (int j = 0; j < kTailRegs; ++j) {
-        L.reg[threadIdx.x * kTailRegs + j] = ex;
-        ex += c[j];
-      }
-      if (threadIdx.x == 0) L.reg[RB] = totc;
-      __syncthreads();
-      constexpr int U = 8;
-      for (int p0 = 0; p0 < totc; p0 += U * kRBlock) {
-        int64_t from[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int p = p0 + u * kRBlock + threadIdx.x;
-          from[u] = -1;
-          if (p < totc && base + p < CAP) {
-            int lo = 0, hi = RB;  // reg[lo] <= p < reg[hi]
-            while (hi - lo > 1) {
-              const int mid = (lo + hi) >> 1;
-              if (L.reg[mid] <= p) lo = mid;
-              else hi = mid;
-            }
-            from[u] = (int64_t)(r0 + lo) * chunk + (p - L.reg[lo]);
-          }
-        }
-        TIn val[U];
-        uint32_t ix[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (from[u] >= 0) {
-            val[u] = sv[from[u]];
-            ix[u] = sx[from[u]];
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (from[u] >= 0) {
-            const int p = p0 + u * kRBlock + threadIdx.x;
-            L.tv[base + p] = val[u];
-            A.tidx[base + p] = ix[u];
-          }
-        }
-      }
-      base += totc;
-      __syncthreads();
-    }
-    total = base;
-  }
-  __syncthreads();
   if (total > CAP) {
     // the updates only hand over sets that fit
     if (threadIdx.x == 0) {
@@ -576,6 +544,9 @@ __device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState&
     return;
   }
   const int m = (int)total;
+  const TIn* from = (src == 0) ? (const TIn*)A.y : (const TIn*)A.tval;
+#pragma unroll 4
+  for (int i = threadIdx.x; i < m; i += kRBlock) L.tv[i] = from[i];
   if (threadIdx.x == 0) L.lam = sc.lam;
   __syncthreads();
   for (;;) {
@@ -583,15 +554,15 @@ __device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState&
     TA phi = TA(0);
     double acc[S_NSUM] = {0, 0, 0, 0, 0, 0, 0};
     double vmax = -inf_d();
+    int cm = 0, cp = 0;
 #pragma unroll 4
     for (int i = threadIdx.x; i < m; i += kRBlock) {
       const TA t = (TA)L.tv[i];
       const TA vv = l1 ? absval(t) : t;
       const TA z = vv + lam;
       phi += z > TA(0) ? z : TA(0);
-      acc[S_CM] += z > TA(0) ? 1.0 : 0.0;
-      acc[S_CP] += z >= TA(0) ? 1.0 : 0.0;
-      acc[S_NIN] += 1.0;
+      cm += z > TA(0) ? 1 : 0;
+      cp += z >= TA(0) ? 1 : 0;
       if (src == 0) {
         const double td = (double)t;
         acc[S_ABS] += fabs(td);
@@ -599,6 +570,9 @@ __device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState&
         vmax = fmax(vmax, (double)vv);
       }
     }
+    acc[S_CM] = (double)cm;
+    acc[S_CP] = (double)cp;
+    acc[S_NIN] = (threadIdx.x == 0) ? (double)m : 0.0;
     const TA phw = wave_sum(phi);
     if (lane == 0) L.phl[wid] = phw;
     block_reduce<S_NSUM, 0, 1, kRBlock>(acc, nullptr, &vmax, L.lds, L.tot);
@@ -616,40 +590,43 @@ __device__ __forceinline__ void spx_tail_run(const SpxArgs& A, int NR, SpxState&
     if (!L.run) break;
   }
   if (threadIdx.x == 0) {
-    sc.tail = 0;
+    sc.tail = kTailNone;
     if (src != 0) {
-      sc.src = 3;  // the packed list: the scatter reads it
+      sc.src = 3;  // the dense list: the scatter reads it
       sc.n_src = m;
     }
     *A.st = sc;
   }
 }
 
-// Shared flags handed from thread 0 to the block: enter the tail loop, and
-// the state's src and l1 for it.
+// Shared flags handed from thread 0 to the block: enter the tail loop (or
+// write the region offsets for the pack), and the state's src and l1.
 struct TailGo {
-  int go, src, l1;
+  int go, offsets, src, l1;
+  int64_t n;
 };
 
-__device__ __forceinline__ void tail_flags(TailGo* f, const SpxState& s) {
-  f->go = (s.status == kRunning && s.tail) ? 1 : 0;
+__device__ __forceinline__ void tail_flags(TailGo* f, const SpxState& s, bool run_now) {
+  const bool running = s.status == kRunning;
+  f->go = (running && run_now) ? 1 : 0;
+  f->offsets = (running && !run_now && s.tail == kTailPack) ? 1 : 0;
   f->src = s.src;
   f->l1 = s.l1;
+  f->n = s.n_src;
 }
 
-// Entry into the tail loop when the state says so at the start of the solve
-// (a small instance whose start reads y anyway).
+// The loop over y itself when the instance is that small from the start.
 template <typename TIn, typename TA>
-__global__ __launch_bounds__(kRBlock) void spx_tail_kernel(SpxArgs A, int NR) {
+__global__ __launch_bounds__(kRBlock) void spx_tail_kernel(SpxArgs A) {
   __shared__ TailLds<TIn, TA> L;
   __shared__ TailGo f;
   SpxState sc;
   if (threadIdx.x == 0) {
     sc = *A.st;
-    tail_flags(&f, sc);
+    tail_flags(&f, sc, sc.tail == kTailY);
   }
   __syncthreads();
-  if (f.go) spx_tail_run<TIn, TA>(A, NR, sc, f.src, f.l1 != 0, L);
+  if (f.go) spx_tail_run<TIn, TA>(A, A.n, sc, 0, f.l1 != 0, L);
 }
 
 // Merges the blocks of spx_condat_kernel (one block): lam_0 is the smallest
@@ -662,7 +639,7 @@ __global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, in
   if (st->status != kRunning) return;
   __shared__ double lds[C_NPART * (kRBlock / kWave)];
   __shared__ double tot[C_NPART];
-  __shared__ TailLds<TIn, TA> L;
+  __shared__ int offl[kRBlock / kWave + 1];
   __shared__ TailGo f;
   reduce_partials<C_NSUM, 1, 1, kRBlock>(A.partials, G, lds, tot);
   SpxState s;
@@ -687,15 +664,15 @@ __global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, in
       s.src = 2;  // the survivors sit in buffer 1, same regions as y
       s.n_src = (int64_t)tot[C_NOUT];
       s.compact_next = (s.compaction != CQK_COMPACT_OFF) ? 1 : 0;
-      s.tail = (s.n_src <= s.tail_cap) ? 1 : 0;
+      s.tail = (s.n_src <= s.tail_cap) ? kTailPack : kTailNone;
       s.multi = s.tail ? 0 : 1;
     }
     spx_trace(&s, A.trace, 0, 1, 0, s.lam, tot[C_SUM], tot[C_CNT], A.n, (int64_t)tot[C_NOUT]);
     *st = s;
-    tail_flags(&f, s);
+    tail_flags(&f, s, false);
   }
   __syncthreads();
-  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, s, f.src, f.l1 != 0, L);
+  if (f.offsets) spx_tail_offsets(A, G * kWaves, f.src - 1, offl);
 }
 
 // eq. (CQKlambda0) with J = all indices, D = I, b = 1: lam_0 = (r - sum y)/n,
@@ -776,7 +753,28 @@ __device__ __forceinline__ double cand_lambda(double lam0, double vmax, int j) {
 template <typename TIn, typename TA, bool MULTI>
 __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   SpxState* st = A.st;
-  if (st->status != kRunning || st->tail || (st->multi != 0) != MULTI) return;
+  if (st->status != kRunning || (st->multi != 0) != MULTI) return;
+  if (st->tail != kTailNone) {
+    // the set fits the one-block loop: copy each wave region of it to its
+    // place in the dense list (offsets from the update kernel)
+    if (!MULTI && st->tail == kTailPack) {
+      const int si = st->src - 1;
+      const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+      const int64_t off = (int64_t)rid * (A.chunk0 / kWaves);
+      const int c = A.cnt[si][rid];
+      const int64_t o = A.toff[rid];
+      const int64_t cap = st->tail_cap;
+      const TIn* sv = (const TIn*)A.val[si] + off;
+      const uint32_t* sx = A.idx[si] + off;
+      for (int i = (int)(threadIdx.x & (kWave - 1)); i < c; i += kWave) {
+        if (o + i < cap) {
+          ((TIn*)A.tval)[o + i] = sv[i];
+          A.tidx[o + i] = sx[i];
+        }
+      }
+    }
+    return;
+  }
   constexpr int V = VecWidth<TIn>::value;
   constexpr int E = 4 * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
@@ -924,25 +922,37 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
 }
 
 // One block: phi summed in TA in block order, counts exactly in double, then
-// Algorithm 4's update; a set that now fits goes on into the tail loop.
+// Algorithm 4's update.  When the update finds that the next set fits the
+// one-block loop it writes the region offsets for the pack; the update
+// after that pack runs the loop.
 template <typename TIn, typename TA>
 __global__ __launch_bounds__(kRBlock) void spx_update_kernel(SpxArgs A, int G) {
   SpxState* st = A.st;
-  if (st->status != kRunning || st->tail || st->multi) return;
+  if (st->status != kRunning || st->multi || st->tail == kTailY) return;
+  __shared__ TailLds<TIn, TA> L;
+  __shared__ TailGo f;
+  SpxState sc;
+  if (st->tail == kTailPack) {
+    // the grid pass just before this one copied the set to tval
+    if (threadIdx.x == 0) {
+      sc = *st;
+      tail_flags(&f, sc, true);
+    }
+    __syncthreads();
+    if (f.go) spx_tail_run<TIn, TA>(A, f.n, sc, f.src, f.l1 != 0, L);
+    return;
+  }
   const bool compact = st->compact_next != 0;
   const int src = st->src;
   __shared__ double lds[(S_NSUM + 1) * (kRBlock / kWave)];
   __shared__ double tot[S_NSUM + 1];
   __shared__ TA phl[kRBlock / kWave];
-  __shared__ TailLds<TIn, TA> L;
-  __shared__ TailGo f;
   TA pg = TA(0);
   for (int g = threadIdx.x; g < G; g += kRBlock) pg += (TA)A.partials[(size_t)S_PHI * G + g];
   reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
   const TA pw = wave_sum(pg);
   if ((threadIdx.x & (kWave - 1)) == 0) phl[threadIdx.x / kWave] = pw;
   __syncthreads();
-  SpxState sc;
   if (threadIdx.x == 0) {
     TA pb = phl[0];
     for (int w = 1; w < kRBlock / kWave; ++w) pb += phl[w];
@@ -950,10 +960,10 @@ __global__ __launch_bounds__(kRBlock) void spx_update_kernel(SpxArgs A, int G) {
     sc = *st;  // register copy: one round trip to memory
     spx_update(&sc, tot, tot[S_NSUM], A.trace, compact, src);
     *st = sc;
-    tail_flags(&f, sc);
+    tail_flags(&f, sc, false);
   }
   __syncthreads();
-  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, sc, f.src, f.l1 != 0, L);
+  if (f.offsets) spx_tail_offsets(A, G * kWaves, f.src - 1, L.off);
 }
 
 // Closes the start after the MULTI pass: keeps that pass's compaction (done
@@ -966,7 +976,7 @@ __global__ __launch_bounds__(kRBlock) void spx_start_update_kernel(SpxArgs A, in
   __shared__ double lds[2 * kCand * (kRBlock / kWave)];
   __shared__ double tot[S_NSUM + 1];
   __shared__ double tc[2 * kCand];
-  __shared__ TailLds<TIn, TA> L;
+  __shared__ int offl[kRBlock / kWave + 1];
   __shared__ TailGo f;
   reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
   reduce_partials<2 * kCand, 0, 0, kRBlock>(A.partials + (size_t)kPassRec * G, G, lds, tc);
@@ -990,12 +1000,12 @@ __global__ __launch_bounds__(kRBlock) void spx_start_update_kernel(SpxArgs A, in
     s.lam = best;
     s.lam0 = best;
     s.hi = best;
-    if (s.n_src <= s.tail_cap) s.tail = 1;
+    if (s.n_src <= s.tail_cap && s.src != 0) s.tail = kTailPack;
     *st = s;
-    tail_flags(&f, s);
+    tail_flags(&f, s, false);
   }
   __syncthreads();
-  if (f.go) spx_tail_run<TIn, TA>(A, G * kWaves, s, f.src, f.l1 != 0, L);
+  if (f.offsets) spx_tail_offsets(A, G * kWaves, f.src - 1, offl);
 }
 
 // How x is written once the Newton loop has stopped: the zero fill + scatter
@@ -1177,9 +1187,12 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   const size_t cap = (size_t)G0 * chunk0;
   const size_t val_bytes = (cap * sizeof(TIn) + 255) / 256 * 256;
   const size_t idx_bytes = (cap * sizeof(uint32_t) + 255) / 256 * 256;
-  const size_t ti_bytes = ((size_t)std::min<int64_t>(n, CAP) * sizeof(uint32_t) + 255) / 256 * 256;
+  const size_t tcap = (size_t)std::min<int64_t>(n, CAP);
+  const size_t ti_bytes = (tcap * sizeof(uint32_t) + 255) / 256 * 256;
+  const size_t tv_bytes = (tcap * sizeof(TIn) + 255) / 256 * 256;
+  const size_t to_bytes = ((size_t)NR * sizeof(int32_t) + 255) / 256 * 256;
   const bool need_bufs = (o.compaction != CQK_COMPACT_OFF) || condat;
-  const size_t total = part_bytes + cnt_bytes + ti_bytes +
+  const size_t total = part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes +
                        (need_bufs ? 2 * (val_bytes + idx_bytes) : 0);
   cqk_status stt = ensure_buffer(ctx->ws, total);
   if (stt != CQK_OK) return stt;
@@ -1196,8 +1209,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   A.cnt[0] = (int32_t*)(ws + part_bytes);
   A.cnt[1] = A.cnt[0] + NR;
   A.tidx = (uint32_t*)(ws + part_bytes + cnt_bytes);
+  A.tval = ws + part_bytes + cnt_bytes + ti_bytes;
+  A.toff = (int32_t*)(ws + part_bytes + cnt_bytes + ti_bytes + tv_bytes);
   if (need_bufs) {
-    char* b = ws + part_bytes + cnt_bytes + ti_bytes;
+    char* b = ws + part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes;
     A.val[0] = b;
     A.idx[0] = (uint32_t*)(b + val_bytes);
     A.val[1] = b + val_bytes + idx_bytes;
@@ -1228,7 +1243,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   // the tail loop takes sets of at most CAP values (its LDS copy); a small
   // instance whose start reads y anyway goes there at once
   init.tail_cap = CAP;
-  init.tail = (!condat && n <= CAP) ? 1 : 0;
+  init.tail = (!condat && n <= CAP) ? kTailY : kTailNone;
   if (r == 0.0) {
     init.status = CQK_OK;
     init.fin_mode = kFinZero;
@@ -1260,7 +1275,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     hipLaunchKernelGGL(kern, dim3(1), dim3(kRBlock), 0, s, A, grid);
   };
   auto tail = [&]() {
-    hipLaunchKernelGGL((spx_tail_kernel<TIn, TA>), dim3(1), dim3(kRBlock), 0, s, A, NR);
+    hipLaunchKernelGGL((spx_tail_kernel<TIn, TA>), dim3(1), dim3(kRBlock), 0, s, A);
   };
   // Writes x once the state says the loop has stopped; a no-op before that,
   // so it can follow every batch and the host waits once per batch.
@@ -1299,9 +1314,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     }
     int launched = 0;
     const int max_launch = o.max_iter + 2;
-    // after the refined start of Algorithm 2 one more pass usually leaves a
-    // set small enough for the tail loop (entered by the update kernels)
-    int batch = condat ? 1 : 2;
+    // after the refined start of Algorithm 2 at most one more pass usually
+    // leaves a set small enough for the one-block loop, which then takes a
+    // pass (the pack) and an update (the loop)
+    int batch = 2;
     for (;;) {
       const int k = std::min(batch, max_launch - launched);
       for (int i = 0; i < k; ++i) {
