@@ -17,9 +17,10 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * - Every array argument is a DEVICE pointer owned by the caller, contiguous,
- *   with element i at ptr[i].  Any alignment of the element type is accepted;
- *   16-byte aligned arrays get 16-byte vector accesses throughout.  Outputs
- *   must not alias inputs.
+ *   with element i at ptr[i].  Any alignment of the element type is accepted
+ *   (the kernels move 16 bytes per lane per access either way).  Outputs must
+ *   not alias inputs: some calls write parts of x before they have finished
+ *   reading y.
  * - Work is enqueued on the context's HIP stream (cqk_create / cqk_set_stream)
  *   and is ordered with the caller's other work on that stream.
  * - Errors are returned as cqk_status; nothing aborts or throws across the

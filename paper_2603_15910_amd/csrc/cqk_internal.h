@@ -39,7 +39,8 @@ struct SpxState {
   int32_t compaction, trace_cap, ntrace, l1, fin_mode, need_safeguard, first_done;
   int32_t tail;                   // 1: the remaining iterations run in one block
   int32_t multi;                  // 1: the next pass refines the start (candidates)
-  int32_t pad_[2];
+  int32_t x_zeroed;               // 1: the start already wrote x = 0 everywhere
+  int32_t pad_[1];
 };
 
 // How the simplex finalize writes x.

@@ -222,6 +222,26 @@ __device__ __forceinline__ double round_down_to<double>(double x) {
   return x;
 }
 
+// Zeros at the NL vectors per lane load_tile reads.
+template <typename TIn, int NL>
+__device__ __forceinline__ void zero_tile(TIn* x, int64_t base, int lane, int64_t n) {
+  constexpr int V = VecWidth<TIn>::value;
+  typename Raw16<TIn>::type z;
+#pragma unroll
+  for (int k = 0; k < V; ++k) z[k] = TIn(0);
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int64_t i = base + (int64_t)q * kWave * V + lane * V;
+    if (i + V <= n) {
+      st16(x + i, z);
+    } else {
+#pragma unroll
+      for (int k = 0; k < V; ++k)
+        if (i + k < n) x[i + k] = TIn(0);
+    }
+  }
+}
+
 // Partial record of the Algorithm 2 kernel.
 enum { C_CNT = 0, C_SUM, C_ABS, C_BAD, C_NOUT, C_NSUM };  // + min lam, max v
 constexpr int C_NPART = C_NSUM + 2;
@@ -243,6 +263,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   const int64_t off = (int64_t)rid * cw;
   const int64_t count = max((int64_t)0, min(cw, A.n - off));
   const TIn* y = (const TIn*)A.y + off;
+  TIn* x = (TIn*)A.x + off;
   TIn* outv = (TIn*)A.val[1] + off;
   uint32_t* outi = A.idx[1] + off;
 
@@ -261,6 +282,9 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     TIn yv[K];
     TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
     load_tile<TIn, NL>(y, base, lane, count, yv);
+    // x_i = 0 for every index (survivors get their value from the scatter at
+    // the end), written while this kernel is busy with Algorithm 2 anyway
+    zero_tile<TIn, NL>(x, base, lane, count);
     TIn tmax = -(TIn)__builtin_huge_val();
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -648,6 +672,7 @@ __global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, in
     s.passes += 1;
     s.sum_abs = tot[C_ABS];
     s.vmax = tot[C_NSUM + 1];
+    s.x_zeroed = 1;
     if (tot[C_BAD] > 0.0) {
       s.status = CQK_INVALID_ARG;
     } else if (s.l1 && tot[C_ABS] <= s.r) {
@@ -1040,6 +1065,7 @@ __global__ __launch_bounds__(kBlock) void spx_finalize_kernel(SpxArgs A) {
   constexpr int U = 4;
   constexpr int64_t TILE = (int64_t)kBlock * V * U;
   const bool zero = (mode == kFinScatter || mode == kFinZero);
+  if (mode == kFinScatter && st->x_zeroed) return;  // zeros already in place
   for (int64_t base = 0; base < count; base += TILE) {
     const bool full = base + TILE <= count;
     TIn yv[U * V];
@@ -1358,13 +1384,20 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     info->finalize_ms = 0.0;
     info->rows_spilled = 0;
     const bool scatter = hs->fin_mode == kFinDense && hs->src != 0;
-    info->finalize_bytes =
-        (double)n * sizeof(TIn) * ((scatter || hs->fin_mode == kFinZero) ? 1.0 : 2.0);
+    // dense map: read y, write x; zero fill: write x (nothing when the
+    // Algorithm 2 kernel already wrote the zeros); scatter: per survivor
+    // read value and index, write x
+    double fin = (double)n * sizeof(TIn) * ((scatter || hs->fin_mode == kFinZero) ? 1.0 : 2.0);
+    if (scatter && hs->x_zeroed) fin = 0.0;
+    if (scatter) fin += (2.0 * sizeof(TIn) + 4.0) * (double)hs->n_src;
+    info->finalize_bytes = fin;
     for (int i = 0; i < ntrace; ++i) {
       const cqk_trace_rec& t = ctx->last_trace[i];
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
       const double per_out = (double)sizeof(TIn) + 4.0;
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
+      // the Algorithm 2 kernel also writes x = 0 everywhere
+      if (t.kind == 0 && t.source == 0 && t.compacted) info->pass_bytes += sizeof(TIn) * (double)t.n_in;
     }
     if (o.timing) {
       // every grid pass launched (those after the loop stopped return at
