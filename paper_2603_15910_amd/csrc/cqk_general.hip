@@ -28,6 +28,7 @@
 // its slopes are unchanged; this is the fixing of Section 2.2 applied through
 // the bracket, plus the free-side analogue.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 
@@ -41,6 +42,7 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
+constexpr int kStage = 128;  // LDS ring per wave and array for compaction
 
 // Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
 // two (key, weight) pairs instead.
@@ -242,21 +244,42 @@ struct SrcForm {
   }
 };
 
-// One wave streams its own region.  Compaction writes the survivors of slot
-// e of every lane contiguously (ballot + lane prefix count), slot after slot,
-// so the layout is deterministic and needs no block-wide synchronisation.
+// One wave streams its own region.  Compaction stages the survivors of slot
+// e of every lane in the wave's slice of LDS (ballot + lane prefix count,
+// slot after slot, so the layout is deterministic and needs no block-wide
+// synchronisation) and writes them out 64 at a time: one store per array
+// then fills 512 contiguous bytes, instead of one partial store per slot.
+// The LDS operations of one wave complete in issue order, so a lane reads
+// what another lane staged without a wait; the wave-scope fences only keep
+// the compiler from reordering those accesses.
 template <typename Src, bool COMPACT>
 __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, double hi,
-                          double* const* out, int32_t* out_cnt, Acc& acc) {
+                          double* const* out, int32_t* out_cnt, Acc& acc, double* stg) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
   int64_t written = 0;
-  for (int64_t base = 0; base < count; base += TILE) {
+  int head = 0, pend = 0;  // staged survivors occupy ring slots head .. head + pend - 1
+  auto flush = [&](int m) {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane < m) {
+      const int q = (head + lane) & (kStage - 1);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[j][written + lane] = stg[j * kStage + q];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    head = (head + m) & (kStage - 1);
+    written += m;
+    pend -= m;
+  };
+  // full tiles take the unguarded path; only the last tile of a region checks
+  // its range
+  auto tile = [&](int64_t base, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
     double c[E], s[E], bl[E], bu[E];
     bool keep[E];
-    if (base + TILE <= count) {
+    if (FULL) {
       src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
     } else {
 #pragma unroll
@@ -272,7 +295,8 @@ __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, 
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
         keep[e] = false;
-        if (i + k < count) keep[e] = eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi);
+        if (FULL || i + k < count)
+          keep[e] = eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi);
       }
     }
     if (COMPACT) {
@@ -280,19 +304,27 @@ __device__ void eval_pass(const Src& src, int64_t count, double lam, double lo, 
       for (int e = 0; e < E; ++e) {
         const uint64_t m = __ballot(keep[e]);
         if (keep[e]) {
-          const int64_t pos = written + lane_prefix(m);
-          out[0][pos] = c[e];
-          out[1][pos] = s[e];
-          out[2][pos] = bl[e];
-          out[3][pos] = bu[e];
+          const int q = (head + pend + lane_prefix(m)) & (kStage - 1);
+          stg[q] = c[e];
+          stg[kStage + q] = s[e];
+          stg[2 * kStage + q] = bl[e];
+          stg[3 * kStage + q] = bu[e];
         }
-        written += __popcll(m);
+        pend += __popcll(m);
+        // pend < 64 before this slot, so the ring never holds more than 127
+        if (pend >= kWave) flush(kWave);
       }
     }
-  }
-  if (COMPACT && lane == 0) {
-    *out_cnt = (int32_t)written;
-    acc.s[P_NOUT] += (double)written;
+  };
+  int64_t base = 0;
+  for (; base + TILE <= count; base += TILE) tile(base, std::true_type{});
+  if (base < count) tile(base, std::false_type{});
+  if (COMPACT) {
+    if (pend > 0) flush(pend);
+    if (lane == 0) {
+      *out_cnt = (int32_t)written;
+      acc.s[P_NOUT] += (double)written;
+    }
   }
 }
 
@@ -493,6 +525,8 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
 
   __shared__ double lds[NPART * (kBlock / kWave)];
   __shared__ double tot[NPART];
+  __shared__ double stage[kWavesPerBlock * 4 * kStage];
+  double* stg = stage + (threadIdx.x / kWave) * 4 * kStage;
 
   Acc acc;
   acc_init(acc);
@@ -506,9 +540,9 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     } else if (compact) {
       double* rb = A.buf[0] + (size_t)rid * 4 * A.chunk;
       double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
-      eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + rid, acc);
+      eval_pass<SrcOrig<TIn>, true>(s, count, lam, lo, hi, out, A.cnt[0] + rid, acc, stg);
     } else {
-      eval_pass<SrcOrig<TIn>, false>(s, count, lam, lo, hi, nullptr, nullptr, acc);
+      eval_pass<SrcOrig<TIn>, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, stg);
     }
   } else {
     const int si = src - 1, di = 1 - si;
@@ -520,9 +554,9 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     } else if (compact) {
       double* rb = A.buf[di] + (size_t)rid * 4 * A.chunk;
       double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
-      eval_pass<SrcForm, true>(s, count, lam, lo, hi, out, A.cnt[di] + rid, acc);
+      eval_pass<SrcForm, true>(s, count, lam, lo, hi, out, A.cnt[di] + rid, acc, stg);
     } else {
-      eval_pass<SrcForm, false>(s, count, lam, lo, hi, nullptr, nullptr, acc);
+      eval_pass<SrcForm, false>(s, count, lam, lo, hi, nullptr, nullptr, acc, stg);
     }
   }
 
@@ -742,7 +776,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // G blocks of kWavesPerBlock waves; wave region = `chunk` indices
   const int G0 = choose_grid(n, ctx->num_cus);
   int64_t chunk = (n + (int64_t)G0 * kWavesPerBlock - 1) / ((int64_t)G0 * kWavesPerBlock);
-  chunk = (chunk + 7) / 8 * 8;
+  chunk = (chunk + 15) / 16 * 16;  // every array of a region starts a 128-byte line
   const int64_t bchunk = chunk * kWavesPerBlock;
   const int G = (int)((n + bchunk - 1) / bchunk);
   const int NR = G * kWavesPerBlock;
@@ -813,20 +847,17 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   int ev = 2;
   // a grid pass (timed when asked) followed by its one-block reduction
   auto launch = [&](auto kern, auto reduce) {
-    if (o.timing && ev + 2 <= (int)nev) hipEventRecord(ctx->events[ev], s);
-    hipLaunchKernelGGL(kern, dim3(G), dim3(kBlock), 0, s, A);
-    if (o.timing && ev + 2 <= (int)nev) {
-      hipEventRecord(ctx->events[ev + 1], s);
-      ev += 2;
-    }
+    const bool rec = o.timing && ev + 2 <= (int)nev;
+    launch_timed(kern, dim3(G), dim3(kBlock), s, rec ? ctx->events[ev] : nullptr,
+                 rec ? ctx->events[ev + 1] : nullptr, A);
+    if (rec) ev += 2;
     hipLaunchKernelGGL(reduce, dim3(1), dim3(kRBlock), 0, s, A, G);
   };
   // The primal recovery does nothing while the loop still runs, so it is
   // queued behind every batch and the host waits once per batch.
   auto finalize = [&]() {
-    if (o.timing) hipEventRecord(ctx->events[0], s);
-    hipLaunchKernelGGL(gen_finalize_kernel<TIn>, dim3(G), dim3(kBlock), 0, s, A);
-    if (o.timing) hipEventRecord(ctx->events[1], s);
+    launch_timed(gen_finalize_kernel<TIn>, dim3(G), dim3(kBlock), s,
+                 o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G);
   };
   if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)

@@ -2,6 +2,7 @@
 // kernel launchers each translation unit provides.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,6 +13,20 @@
 namespace cqk {
 
 constexpr int kMaxTrace = 512;
+
+// Launches a kernel on stream s.  With a pair of events the dispatch itself
+// stamps its start and end into them, so no marker packet sits between two
+// kernels (an event recorded on the stream would add a few microseconds of
+// idle time around every timed kernel).
+template <typename F, typename... Args>
+inline void launch_timed(F kern, dim3 grid, dim3 block, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, Args... args) {
+  if (e0 != nullptr) {
+    hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, args...);
+  } else {
+    hipLaunchKernelGGL(kern, grid, block, 0, s, args...);
+  }
+}
 
 // Run state of the general (Algorithm 1) solver, one record in device memory.
 struct GenState {

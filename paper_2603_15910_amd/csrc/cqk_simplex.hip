@@ -1289,12 +1289,9 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   int ev = 4;
   auto launch = [&](auto kern, int grid) {
     const bool rec = o.timing && ev + 2 <= (int)nev;
-    if (rec) hipEventRecord(ctx->events[ev], s);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, A);
-    if (rec) {
-      hipEventRecord(ctx->events[ev + 1], s);
-      ev += 2;
-    }
+    launch_timed(kern, dim3(grid), dim3(kBlock), s, rec ? ctx->events[ev] : nullptr,
+                 rec ? ctx->events[ev + 1] : nullptr, A);
+    if (rec) ev += 2;
   };
   // one-block reduction of the partial records of a grid of `grid` blocks
   auto reduce = [&](auto kern, int grid) {
@@ -1306,12 +1303,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   // Writes x once the state says the loop has stopped; a no-op before that,
   // so it can follow every batch and the host waits once per batch.
   auto fin_chain = [&]() {
-    if (o.timing) hipEventRecord(ctx->events[0], s);
-    hipLaunchKernelGGL((spx_finalize_kernel<TIn, TA>), dim3(G0), dim3(kBlock), 0, s, A);
-    if (o.timing) hipEventRecord(ctx->events[1], s);
-    if (o.timing) hipEventRecord(ctx->events[2], s);
-    hipLaunchKernelGGL((spx_scatter_kernel<TIn, TA>), dim3(G0), dim3(kBlock), 0, s, A);
-    if (o.timing) hipEventRecord(ctx->events[3], s);
+    launch_timed(spx_finalize_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
+                 o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
+    launch_timed(spx_scatter_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
+                 o.timing ? ctx->events[2] : nullptr, o.timing ? ctx->events[3] : nullptr, A);
     hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
   };
   SpxState* hs = (SpxState*)ctx->host_pinned;
