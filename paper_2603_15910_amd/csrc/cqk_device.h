@@ -227,13 +227,19 @@ __device__ __forceinline__ void reduce_partials(const double* partials, int G, d
   for (int i = 0; i < NM; ++i) mn[i] = inf_d();
 #pragma unroll
   for (int i = 0; i < NX; ++i) mx[i] = -inf_d();
+  // Each record's loads are all issued before its first add (the scheduling
+  // barrier): left to itself the compiler waited for every load in turn.
   for (int g = threadIdx.x; g < G; g += BLOCK) {
+    double v[NV];
 #pragma unroll
-    for (int i = 0; i < NS; ++i) s[i] += partials[(size_t)i * G + g];
+    for (int i = 0; i < NV; ++i) v[i] = partials[(size_t)i * G + g];
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], partials[(size_t)(NS + i) * G + g]);
+    for (int i = 0; i < NS; ++i) s[i] += v[i];
 #pragma unroll
-    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], partials[(size_t)(NS + NM + i) * G + g]);
+    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], v[NS + i]);
+#pragma unroll
+    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], v[NS + NM + i]);
   }
   block_reduce<NS, NM, NX, BLOCK>(s, mn, mx, lds, out);
 }

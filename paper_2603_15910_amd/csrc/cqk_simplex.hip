@@ -428,7 +428,8 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
 
 // Partial record of an evaluation pass.
 enum { S_PHI = 0, S_CM, S_CP, S_BAD, S_NIN, S_NOUT, S_ABS, S_NSUM };  // + max v
-constexpr int kPassRec = S_NSUM + 1;  // the candidate sums of a MULTI pass follow
+constexpr int kPassRec = S_NSUM + 1;
+// a MULTI pass's record: the S_NSUM sums, then 2 * kCand candidate sums
 
 // Algorithm 4's update, run by one thread after an evaluation (source: 0 the
 // caller's y, 1/2 a compacted buffer, 3 the packed set of the tail loop).
@@ -769,6 +770,15 @@ __device__ __forceinline__ double cand_lambda(double lam0, double vmax, int j) {
   return -vmax + (lam0 + vmax) / (double)(1u << j);
 }
 
+// A value every lane of the wave holds, moved to scalar registers.
+__device__ __forceinline__ double wave_uniform(double v) {
+  return __hiloint2double(__builtin_amdgcn_readfirstlane(__double2hiint(v)),
+                          __builtin_amdgcn_readfirstlane(__double2loint(v)));
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // One evaluation of phi and its one-sided slopes at lam_k over the current
 // set (counts exactly in double, phi in TA), dropping y + lam_k <= 0 when
 // compaction is on (lam_k >= lam*).  MULTI: the pass right after Algorithm 2
@@ -834,14 +844,18 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
     oi = A.idx[di] + off;
     ocnt = A.cnt[di] + rid;
   }
+  // candidate multipliers in scalar registers, counts in integers: the
+  // MULTI pass then needs few enough vector registers to keep all of its
+  // short waves resident at once
   TA lj[NC];
-  double cc[NC], cs[NC];
+  int cc[NC];
+  double cs[NC];
   if constexpr (MULTI) {
     const double lam0 = st->lam, vmx = st->vmax;
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      lj[j] = (TA)cand_lambda(lam0, vmx, j);
-      cc[j] = 0.0;
+      lj[j] = wave_uniform((TA)cand_lambda(lam0, vmx, j));
+      cc[j] = 0;
       cs[j] = 0.0;
     }
   }
@@ -884,7 +898,7 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
 #pragma unroll
             for (int j = 0; j < NC; ++j) {
               const bool in = v + lj[j] > TA(0);
-              cc[j] += in ? 1.0 : 0.0;
+              cc[j] += in ? 1 : 0;
               cs[j] += in ? (double)v : 0.0;
             }
           }
@@ -921,27 +935,34 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   __shared__ TA phl[kBlock / kWave];
   if (lane == 0) phl[threadIdx.x / kWave] = phw;
   acc[S_PHI] = 0.0;
-  block_reduce<S_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
-  if (threadIdx.x == 0) {
-    TA pb = phl[0];
-    for (int w = 1; w < kBlock / kWave; ++w) pb += phl[w];
-    tot[S_PHI] = (double)pb;
-    write_partial(A.partials, tot, S_NSUM + 1);
-  }
   if constexpr (MULTI) {
-    __shared__ double lds2[2 * NC * (kBlock / kWave)];
-    __shared__ double tot2[2 * NC];
-    double both[2 * NC];
+    // one record: the pass sums, then the candidate counts and sums (the
+    // set is compacted, so there is no max to carry)
+    constexpr int NV = S_NSUM + 2 * NC;
+    __shared__ double lds2[NV * (kBlock / kWave)];
+    __shared__ double tot2[NV];
+    double all[NV];
+#pragma unroll
+    for (int i = 0; i < S_NSUM; ++i) all[i] = acc[i];
 #pragma unroll
     for (int j = 0; j < NC; ++j) {
-      both[j] = cc[j];
-      both[NC + j] = cs[j];
+      all[S_NSUM + j] = (double)cc[j];
+      all[S_NSUM + NC + j] = cs[j];
     }
-    block_reduce<2 * NC, 0, 0, kBlock>(both, nullptr, nullptr, lds2, tot2);
+    block_reduce<NV, 0, 0, kBlock>(all, nullptr, nullptr, lds2, tot2);
     if (threadIdx.x == 0) {
-#pragma unroll
-      for (int i = 0; i < 2 * NC; ++i)
-        A.partials[(size_t)(kPassRec + i) * gridDim.x + blockIdx.x] = tot2[i];
+      TA pb = phl[0];
+      for (int w = 1; w < kBlock / kWave; ++w) pb += phl[w];
+      tot2[S_PHI] = (double)pb;
+      write_partial(A.partials, tot2, NV);
+    }
+  } else {
+    block_reduce<S_NSUM, 0, 1, kBlock>(acc, nullptr, &vmax, lds, tot);
+    if (threadIdx.x == 0) {
+      TA pb = phl[0];
+      for (int w = 1; w < kBlock / kWave; ++w) pb += phl[w];
+      tot[S_PHI] = (double)pb;
+      write_partial(A.partials, tot, S_NSUM + 1);
     }
   }
 }
@@ -998,13 +1019,13 @@ template <typename TIn, typename TA>
 __global__ __launch_bounds__(kRBlock) void spx_start_update_kernel(SpxArgs A, int G) {
   SpxState* st = A.st;
   if (st->status != kRunning || st->tail || !st->multi) return;
-  __shared__ double lds[2 * kCand * (kRBlock / kWave)];
-  __shared__ double tot[S_NSUM + 1];
-  __shared__ double tc[2 * kCand];
+  constexpr int NV = S_NSUM + 2 * kCand;  // the MULTI pass's record
+  __shared__ double lds[NV * (kRBlock / kWave)];
+  __shared__ double tot[NV];
   __shared__ int offl[kRBlock / kWave + 1];
   __shared__ TailGo f;
-  reduce_partials<S_NSUM, 0, 1, kRBlock>(A.partials, G, lds, tot);
-  reduce_partials<2 * kCand, 0, 0, kRBlock>(A.partials + (size_t)kPassRec * G, G, lds, tc);
+  reduce_partials<NV, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  const double* tc = tot + S_NSUM;
   SpxState s;
   if (threadIdx.x == 0) {
     s = *st;
