@@ -95,6 +95,15 @@ cqk_status ensure_events(cqk_ctx* ctx, size_t count);
 void fill_default_opts(cqk_opts* o);
 
 // Launchers (each returns CQK_OK or CQK_DEVICE_ERROR / CQK_NO_MEMORY).
+// Grid and workspace of the general solver for n indices of `vec` values per
+// 16-byte vector (2: FP64 inputs, 4: FP32 inputs).
+struct GenLayout {
+  int G, NR, GF;
+  int64_t chunk;
+  size_t part_bytes, cnt_bytes, bytes;
+};
+GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction);
+
 cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
                            const double* b, const double* l, const double* u, double r,
                            double* x, const cqk_opts& o, cqk_info* info);
