@@ -259,13 +259,15 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   const double rd = st->r;
   const int lane = threadIdx.x & (kWave - 1);
   const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+  // tiles go to waves grid-stride (tile t to wave t mod NR); wave rid keeps
+  // its survivors in region rid, which holds every value the wave reads
+  const int64_t nr = (int64_t)gridDim.x * kWaves;
   const int64_t cw = A.chunk0 / kWaves;
-  const int64_t off = (int64_t)rid * cw;
-  const int64_t count = max((int64_t)0, min(cw, A.n - off));
-  const TIn* y = (const TIn*)A.y + off;
-  TIn* x = (TIn*)A.x + off;
-  TIn* outv = (TIn*)A.val[1] + off;
-  uint32_t* outi = A.idx[1] + off;
+  const int64_t count = A.n;
+  const TIn* y = (const TIn*)A.y;
+  TIn* x = (TIn*)A.x;
+  TIn* outv = (TIn*)A.val[1] + (int64_t)rid * cw;
+  uint32_t* outi = A.idx[1] + (int64_t)rid * cw;
 
   __shared__ double lds[C_NPART * (kBlock / kWave)];
   __shared__ double tot[C_NPART];
@@ -277,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   TIn vmx = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
-  for (int64_t base = 0; base < count; base += TILE) {
+  for (int64_t base = (int64_t)rid * TILE; base < count; base += nr * TILE) {
     const bool full = base + TILE <= count;
     TIn yv[K];
     TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         const int64_t pos = written + lane_prefix(m);
         const int q = e / V, k = e % V;
         outv[pos] = yv[e];
-        outi[pos] = (uint32_t)(off + base + (int64_t)q * kWave * V + (int64_t)lane * V + k);
+        outi[pos] = (uint32_t)(base + (int64_t)q * kWave * V + (int64_t)lane * V + k);
       }
       written += __popcll(m);
     }
@@ -829,9 +831,14 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   TIn* ov = nullptr;
   uint32_t* oi = nullptr;
   int32_t* ocnt = nullptr;
+  // the caller's y: tiles grid-stride over all waves (as in the Algorithm 2
+  // kernel); a compacted set: the wave's own region
+  int64_t base0 = 0, step = TILE;
   if (src == 0) {
-    count = max((int64_t)0, min(chunk, A.n - off));
-    yv = (const TIn*)A.y + off;
+    count = A.n;
+    yv = (const TIn*)A.y;
+    base0 = (int64_t)rid * TILE;
+    step = (int64_t)gridDim.x * kWaves * TILE;
   } else {
     const int si = src - 1;
     count = A.cnt[si][rid];
@@ -869,7 +876,7 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
   TIn vmx = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);
   int64_t written = 0;
-  for (int64_t base = 0; base < count; base += TILE) {
+  for (int64_t base = base0; base < count; base += step) {
     const bool full = base + TILE <= count;
     TIn y[E];
     bool keep[E];
@@ -914,7 +921,7 @@ __global__ __launch_bounds__(kBlock) void spx_pass_kernel(SpxArgs A) {
           const int64_t pos = written + lane_prefix(m);
           const int64_t i = base + (int64_t)(e / V) * kWave * V + (int64_t)lane * V + (e % V);
           ov[pos] = y[e];
-          oi[pos] = (src == 0) ? (uint32_t)(off + i) : iv[i];
+          oi[pos] = (src == 0) ? (uint32_t)i : iv[i];
         }
         written += __popcll(m);
       }
@@ -1220,10 +1227,17 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
                        const cqk_opts& o, cqk_info* info) {
   if (n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
   constexpr int64_t CAP = kTailBytes / (int64_t)sizeof(TIn);
+  // G0 blocks of kWaves waves.  Passes over y hand out tiles of at most
+  // kWave * kCondatK values grid-stride, at most tpw each per wave, so a wave
+  // region of chunk0/kWaves = tpw tiles holds every survivor a wave keeps
+  // (the pass kernel's FP64 tiles are half as long, hence at most 2 tpw).
   const int G0i = grid0(n, ctx->num_cus);
-  int64_t chunk0 = (n + G0i - 1) / G0i;
-  chunk0 = (chunk0 + 31) / 32 * 32;  // wave regions of chunk0/4, multiples of 8
-  const int G0 = (int)((n + chunk0 - 1) / chunk0);
+  constexpr int64_t kT = (int64_t)kWave * kCondatK;
+  const int64_t ntiles = (n + kT - 1) / kT;
+  const int64_t tpw =
+      std::max<int64_t>(1, (ntiles + (int64_t)G0i * kWaves - 1) / ((int64_t)G0i * kWaves));
+  const int64_t chunk0 = tpw * kT * kWaves;
+  const int G0 = (int)std::max<int64_t>(1, (n + chunk0 - 1) / chunk0);
   const int NR = G0 * kWaves;
   const bool condat = o.lambda0_mode == CQK_LAMBDA0_CONDAT;
   const bool formula = o.lambda0_mode == CQK_LAMBDA0_FORMULA;
