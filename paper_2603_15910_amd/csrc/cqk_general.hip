@@ -43,6 +43,9 @@ constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
 constexpr int kStage = 128;  // LDS ring per wave and array for compaction
+constexpr int kPieceLog = 6;
+constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
+static_assert(kPiece == kWave, "a flush writes one piece");
 
 // Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
 // two (key, weight) pairs instead.
@@ -75,8 +78,9 @@ struct GenArgs {
   void* x;
   int64_t n;
   int64_t chunk;
-  double* buf[2];   // compacted sets: region r holds its four arrays at
-                    // buf[k] + (4 r + j) chunk, j = c, s, bl, bu
+  double* buf[2];   // compacted sets: array j (c, s, bl, bu) of set k is the
+                    // plane buf[k] + j NR chunk, in pieces of kPiece values
+                    // (see piece_pos)
   int32_t* cnt[2];
   double* partials;
   GenState* st;
@@ -209,27 +213,46 @@ struct SrcOrig {
   }
 };
 
+// A compacted set is stored in pieces of kPiece values: value j of wave rid
+// lives at piece_pos(j) of each plane, so piece k of every wave sits next to
+// piece k of the others.  Waves write and read their k-th pieces at about the
+// same time, so the compacted stream moves through neighbouring addresses
+// like the grid-stride passes over the caller's arrays.
+struct Pieces {
+  int64_t rid, nr;
+  __device__ __forceinline__ int64_t pos(int64_t j) const {
+    return ((j >> kPieceLog) * nr + rid) * kPiece + (j & (kPiece - 1));
+  }
+};
+
 struct SrcForm {
   static constexpr int V = 2;
-  const double *c, *s, *bl, *bu;
+  const double *c, *s, *bl, *bu;  // planes
+  Pieces P;
   __device__ __forceinline__ void load(int64_t i, int64_t n, double* oc, double* os, double* obl,
                                        double* obu, double&) const {
-    Vec<double, 2>::load(c, i, n, 0.0, oc);
-    Vec<double, 2>::load(s, i, n, 1.0, os);
-    Vec<double, 2>::load(bl, i, n, 0.0, obl);
-    Vec<double, 2>::load(bu, i, n, 0.0, obu);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      const bool in = i + k < n;
+      const int64_t q = in ? P.pos(i + k) : 0;
+      oc[k] = in ? c[q] : 0.0;
+      os[k] = in ? s[q] : 1.0;
+      obl[k] = in ? bl[q] : 0.0;
+      obu[k] = in ? bu[q] : 0.0;
+    }
   }
+  // a lane's two values never straddle a piece (i is even, kPiece too)
   template <int U>
   __device__ __forceinline__ void load_fast(int64_t base, int lane, double* oc, double* os,
                                             double* obl, double* obu, double&) const {
     dbl2u rc[U], rs[U], rl[U], ru[U];
 #pragma unroll
     for (int w = 0; w < U; ++w) {
-      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
-      rc[w] = ld16(c + i);
-      rs[w] = ld16(s + i);
-      rl[w] = ld16(bl + i);
-      ru[w] = ld16(bu + i);
+      const int64_t q = P.pos(base + (int64_t)w * kWave * V + (int64_t)lane * V);
+      rc[w] = ld16(c + q);
+      rs[w] = ld16(s + q);
+      rl[w] = ld16(bl + q);
+      ru[w] = ld16(bu + q);
     }
 #pragma unroll
     for (int w = 0; w < U; ++w) {
@@ -244,7 +267,7 @@ struct SrcForm {
   }
 };
 
-// One wave streams its own region.  Compaction stages the survivors of slot
+// One wave streams its tiles.  Compaction stages the survivors of slot
 // e of every lane in the wave's slice of LDS (ballot + lane prefix count,
 // slot after slot, so the layout is deterministic and needs no block-wide
 // synchronisation) and writes them out 64 at a time: one store per array
@@ -254,20 +277,23 @@ struct SrcForm {
 // the compiler from reordering those accesses.
 template <typename Src, bool COMPACT>
 __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t stride, double lam,
-                          double lo, double hi, double* const* out, int32_t* out_cnt, Acc& acc,
-                          double* stg) {
+                          double lo, double hi, double* const* out, Pieces op, int32_t* out_cnt,
+                          Acc& acc, double* stg) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
   int64_t written = 0;
   int head = 0, pend = 0;  // staged survivors occupy ring slots head .. head + pend - 1
+  // `written` is a multiple of kPiece = kWave at every flush, so a flush
+  // fills (the start of) one piece; non-temporal, like the other streams
   auto flush = [&](int m) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     if (lane < m) {
       const int q = (head + lane) & (kStage - 1);
+      const int64_t p = op.pos(written) + lane;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) out[j][written + lane] = stg[j * kStage + q];
+      for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(stg[j * kStage + q], &out[j][p]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     head = (head + m) & (kStage - 1);
@@ -523,10 +549,12 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   const double lam = st->lam, lo = st->lo, hi = st->hi;
   // Passes over the caller's arrays hand tiles to waves grid-stride (tile t
   // to wave t mod NR), so all waves stream through neighbouring addresses;
-  // wave rid keeps its survivors in region rid of a buffer (at most `chunk`
-  // of them) and later passes stream that region.
+  // wave rid keeps its survivors (at most `chunk`) in its pieces of a
+  // compacted set, and later passes stream those pieces.
   const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
   const int64_t nr = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t plane = nr * A.chunk;  // one array of a compacted set
+  const Pieces pc{rid, nr};
 
   __shared__ double lds[NPART * (kBlock / kWave)];
   __shared__ double tot[NPART];
@@ -544,28 +572,28 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     if (mode != kModeEval) {
       bkpt_pass(s, A.n, first, stride, lam, ks);
     } else if (compact) {
-      double* rb = A.buf[0] + (size_t)rid * 4 * A.chunk;
-      double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
-      eval_pass<SrcOrig<TIn>, true>(s, A.n, first, stride, lam, lo, hi, out, A.cnt[0] + rid, acc,
-                                    stg);
+      double* rb = A.buf[0];
+      double* out[4] = {rb, rb + plane, rb + 2 * plane, rb + 3 * plane};
+      eval_pass<SrcOrig<TIn>, true>(s, A.n, first, stride, lam, lo, hi, out, pc, A.cnt[0] + rid,
+                                    acc, stg);
     } else {
-      eval_pass<SrcOrig<TIn>, false>(s, A.n, first, stride, lam, lo, hi, nullptr, nullptr, acc,
-                                     stg);
+      eval_pass<SrcOrig<TIn>, false>(s, A.n, first, stride, lam, lo, hi, nullptr, pc, nullptr,
+                                     acc, stg);
     }
   } else {
     const int si = src - 1, di = 1 - si;
-    const double* sb = A.buf[si] + (size_t)rid * 4 * A.chunk;
-    SrcForm s{sb, sb + A.chunk, sb + 2 * A.chunk, sb + 3 * A.chunk};
+    const double* sb = A.buf[si];
+    SrcForm s{sb, sb + plane, sb + 2 * plane, sb + 3 * plane, pc};
     constexpr int64_t T = (int64_t)kWave * kUnroll * SrcForm::V;
     const int64_t count = A.cnt[si][rid];
     if (mode != kModeEval) {
       bkpt_pass(s, count, 0, T, lam, ks);
     } else if (compact) {
-      double* rb = A.buf[di] + (size_t)rid * 4 * A.chunk;
-      double* out[4] = {rb, rb + A.chunk, rb + 2 * A.chunk, rb + 3 * A.chunk};
-      eval_pass<SrcForm, true>(s, count, 0, T, lam, lo, hi, out, A.cnt[di] + rid, acc, stg);
+      double* rb = A.buf[di];
+      double* out[4] = {rb, rb + plane, rb + 2 * plane, rb + 3 * plane};
+      eval_pass<SrcForm, true>(s, count, 0, T, lam, lo, hi, out, pc, A.cnt[di] + rid, acc, stg);
     } else {
-      eval_pass<SrcForm, false>(s, count, 0, T, lam, lo, hi, nullptr, nullptr, acc, stg);
+      eval_pass<SrcForm, false>(s, count, 0, T, lam, lo, hi, nullptr, pc, nullptr, acc, stg);
     }
   }
 
