@@ -215,33 +215,57 @@ __device__ __forceinline__ void write_partial(double* partials, const double* v,
 }
 
 // Deterministic reduction of G partial records of NV doubles (first NS are
-// sums, then NM mins, then NX maxes) by the whole block; thread 0 gets out[].
+// sums, then NM mins, then NX maxes) by the whole block; out[] (shared) holds
+// the results for every thread on return.  Records are value-major, so value
+// i of all G records is one contiguous row.  Each row is cut into S segments
+// (S = NW / NV when there are fewer rows than waves), and wave w takes the
+// (row, segment) items w, w + NW, ...: each lane combines its strided share
+// of the segment with all of a round's loads in flight, one butterfly
+// combines the lanes, and the segments of a row are combined in order at the
+// end.  lds must hold NV * (BLOCK / kWave) doubles.
 template <int NS, int NM, int NX, int BLOCK>
 __device__ __forceinline__ void reduce_partials(const double* partials, int G, double* lds,
                                                 double* out) {
   constexpr int NV = NS + NM + NX;
-  double s[NS > 0 ? NS : 1], mn[NM > 0 ? NM : 1], mx[NX > 0 ? NX : 1];
+  constexpr int NW = BLOCK / kWave;
+  constexpr int S = (NV < NW) ? NW / NV : 1;
+  constexpr int R = 32;  // loads per lane and round
+  const int lane = threadIdx.x & (kWave - 1);
+  const int seg = ((G + S - 1) / S + kWave - 1) / kWave * kWave;
+  for (int j = (int)(threadIdx.x / kWave); j < NV * S; j += NW) {
+    const int i = j / S;
+    const int kind = (i < NS) ? 0 : ((i < NS + NM) ? 1 : 2);  // wave-uniform
+    const double idv = (kind == 0) ? 0.0 : ((kind == 1) ? inf_d() : -inf_d());
+    const double* row = partials + (size_t)i * G;
+    const int g_end = min(G, (j % S + 1) * seg);
+    double a = idv;
+    for (int g0 = (j % S) * seg; g0 < g_end; g0 += kWave * R) {
+      double v[R];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) s[i] = 0.0;
+      for (int k = 0; k < R; ++k) {
+        const int g = g0 + k * kWave + lane;
+        v[k] = (g < g_end) ? row[g] : idv;
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-  for (int i = 0; i < NM; ++i) mn[i] = inf_d();
-#pragma unroll
-  for (int i = 0; i < NX; ++i) mx[i] = -inf_d();
-  // Each record's loads are all issued before its first add (the scheduling
-  // barrier): left to itself the compiler waited for every load in turn.
-  for (int g = threadIdx.x; g < G; g += BLOCK) {
-    double v[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = partials[(size_t)i * G + g];
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int i = 0; i < NS; ++i) s[i] += v[i];
-#pragma unroll
-    for (int i = 0; i < NM; ++i) mn[i] = fmin(mn[i], v[NS + i]);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) mx[i] = fmax(mx[i], v[NS + NM + i]);
+      for (int k = 0; k < R; ++k)
+        a = (kind == 0) ? a + v[k] : ((kind == 1) ? fmin(a, v[k]) : fmax(a, v[k]));
+    }
+    a = (kind == 0) ? wave_sum(a) : ((kind == 1) ? wave_min(a) : wave_max(a));
+    if (lane == 0) lds[j] = a;
   }
-  block_reduce<NS, NM, NX, BLOCK>(s, mn, mx, lds, out);
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    const int i = threadIdx.x;
+    const int kind = (i < NS) ? 0 : ((i < NS + NM) ? 1 : 2);
+    double a = lds[i * S];
+    for (int q = 1; q < S; ++q) {
+      const double v = lds[i * S + q];
+      a = (kind == 0) ? a + v : ((kind == 1) ? fmin(a, v) : fmax(a, v));
+    }
+    out[i] = a;
+  }
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
