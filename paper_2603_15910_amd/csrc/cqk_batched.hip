@@ -65,13 +65,13 @@ struct BatArgs {
   float* gy;            // backward: grad_y
   double* gr;           // backward: grad_r
   int32_t* list;        // row ids: workgroup rows by bucket, then wave rows
-  int32_t* counters;    // [0,kNB) counts, [kNB,2kNB) cursors, [2kNB,3kNB) bases,
-                        // 3kNB: n_long, +1: n_short, +2: n_items, +3: queue, +4: flags,
-                        // +5: ticket, +6: survivors total, +7: overflow rows
+  int32_t* counters;    // 3kNB: n_long, +1: n_short, +2: n_items, +3: queue, +4: flags,
+                        // +6: survivors total, +7: overflow rows
+  int32_t* bhist;       // planning: rows per length bucket of each block of kPBlock rows
 };
 
 constexpr int CTR_NLONG = 3 * kNB, CTR_NSHORT = 3 * kNB + 1, CTR_NITEMS = 3 * kNB + 2,
-              CTR_QUEUE = 3 * kNB + 3, CTR_FLAGS = 3 * kNB + 4, CTR_TICKET = 3 * kNB + 5,
+              CTR_QUEUE = 3 * kNB + 3, CTR_FLAGS = 3 * kNB + 4,
               CTR_SURV = 3 * kNB + 6, CTR_OVER = 3 * kNB + 7, CTR_TOTAL = 3 * kNB + 8;
 
 __device__ __forceinline__ int bucket_of(int64_t L, int small_max) {
@@ -81,40 +81,105 @@ __device__ __forceinline__ int bucket_of(int64_t L, int small_max) {
   return b >= kNB ? kNB - 1 : b;
 }
 
-__global__ void bat_zero_kernel(int32_t* counters) {
-  for (int i = threadIdx.x; i < CTR_TOTAL; i += blockDim.x) counters[i] = 0;
+// Planning: the rows are listed by length bucket (workgroup rows longest
+// bucket first, then the wave rows), in row order inside a bucket, without
+// atomics: each block of kPBlock rows counts its buckets with ballots, then
+// each block places its rows after the rows of its bucket in earlier blocks.
+constexpr int kPBlock = 1024;
+constexpr int kPW = kPBlock / kWave;
+
+// length bucket of row s, -1 past the last row
+__device__ __forceinline__ int plan_bucket(const BatArgs& A, int s) {
+  return (s < A.nseg) ? bucket_of(A.off[s + 1] - A.off[s], A.small_max) : -1;
 }
 
-__global__ __launch_bounds__(kBlock) void bat_count_kernel(BatArgs A) {
-  const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s < A.nseg) {
-    const int64_t L = A.off[s + 1] - A.off[s];
-    atomicAdd(&A.counters[bucket_of(L, A.small_max)], 1);
-    __threadfence();
+__global__ __launch_bounds__(kPBlock) void bat_count_kernel(BatArgs A) {
+  __shared__ int wh[kPW][kNB];
+  const int s = blockIdx.x * kPBlock + (int)threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int b = plan_bucket(A, s);
+  for (int k = 0; k < kNB; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (lane == 0) wh[w][k] = __popcll(m);
   }
-  if (!last_block_arrives((uint32_t*)&A.counters[CTR_TICKET])) return;
-  if (threadIdx.x == 0) {
-    int base = 0;
-    for (int b = kNB - 1; b >= 1; --b) {  // workgroup rows, longest bucket first
-      A.counters[2 * kNB + b] = base;
-      base += A.counters[b];
+  __syncthreads();
+  if (threadIdx.x < kNB) {
+    int c = 0;
+    for (int q = 0; q < kPW; ++q) c += wh[q][threadIdx.x];
+    A.bhist[(size_t)blockIdx.x * kNB + threadIdx.x] = c;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    A.counters[CTR_QUEUE] = 0;
+    A.counters[CTR_FLAGS] = 0;
+    A.counters[CTR_SURV] = 0;
+    A.counters[CTR_OVER] = 0;
+  }
+}
+
+__global__ __launch_bounds__(kPBlock) void bat_place_kernel(BatArgs A) {
+  __shared__ int part[2][kNB][32];
+  __shared__ int base[kNB], pre[kNB];
+  __shared__ int wh[kPW][kNB];
+  const int nblk = gridDim.x;
+  // bucket totals over all blocks and over the blocks before this one,
+  // 32 threads per bucket
+  if (threadIdx.x < kNB * 32) {
+    const int k = threadIdx.x / 32, sub = threadIdx.x % 32;
+    int t = 0, p = 0;
+    for (int q = sub; q < nblk; q += 32) {
+      const int v = A.bhist[(size_t)q * kNB + k];
+      t += v;
+      p += (q < (int)blockIdx.x) ? v : 0;
     }
-    A.counters[CTR_NLONG] = base;
-    A.counters[2 * kNB + 0] = base;
-    const int nshort = A.counters[0];
-    A.counters[CTR_NSHORT] = nshort;
-    A.counters[CTR_NITEMS] = base + (nshort + kWaves - 1) / kWaves;
-    A.counters[CTR_TICKET] = 0;
+    part[0][k][sub] = t;
+    part[1][k][sub] = p;
   }
-}
-
-__global__ __launch_bounds__(kBlock) void bat_place_kernel(BatArgs A) {
-  const int s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= A.nseg) return;
-  const int64_t L = A.off[s + 1] - A.off[s];
-  const int b = bucket_of(L, A.small_max);
-  const int pos = A.counters[2 * kNB + b] + atomicAdd(&A.counters[kNB + b], 1);
-  A.list[pos] = s;
+  const int s = blockIdx.x * kPBlock + (int)threadIdx.x;
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  const int b = plan_bucket(A, s);
+  int rank = 0;
+  for (int k = 0; k < kNB; ++k) {
+    const uint64_t m = __ballot(b == k);
+    if (b == k) rank = lane_prefix(m);
+    if (lane == 0) wh[w][k] = __popcll(m);
+  }
+  __syncthreads();
+  if (threadIdx.x < kNB) {
+    const int k = threadIdx.x;
+    int t = 0, p = 0;
+    for (int q = 0; q < 32; ++q) {
+      t += part[0][k][q];
+      p += part[1][k][q];
+    }
+    base[k] = t;  // totals for now
+    pre[k] = p;
+    // exclusive scan of the per-wave counts of this block
+    int c = 0;
+    for (int q = 0; q < kPW; ++q) {
+      const int v = wh[q][k];
+      wh[q][k] = c;
+      c += v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // workgroup rows, longest bucket first, then the wave rows
+    int acc = 0;
+    for (int k = kNB - 1; k >= 1; --k) {
+      const int t = base[k];
+      base[k] = acc;
+      acc += t;
+    }
+    const int nshort = base[0];
+    base[0] = acc;
+    if (blockIdx.x == 0) {
+      A.counters[CTR_NLONG] = acc;
+      A.counters[CTR_NSHORT] = nshort;
+      A.counters[CTR_NITEMS] = acc + (nshort + kWaves - 1) / kWaves;
+    }
+  }
+  __syncthreads();
+  if (b >= 0) A.list[base[b] + pre[b] + wh[w][b] + rank] = s;
 }
 
 __device__ __forceinline__ double row_radius(const BatArgs& A, int s) {
@@ -792,16 +857,20 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
 struct BatWs {
   int32_t* list;
   int32_t* counters;
+  int32_t* bhist;
 };
 
 cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
   const size_t list_bytes = ((size_t)nseg * sizeof(int32_t) + 255) / 256 * 256;
   const size_t ctr_bytes = 256 * sizeof(int32_t);
-  cqk_status st = ensure_buffer(ctx->ws, list_bytes + ctr_bytes);
+  const size_t nblk = std::max<size_t>(1, ((size_t)nseg + kPBlock - 1) / kPBlock);
+  const size_t hist_bytes = (nblk * kNB * sizeof(int32_t) + 255) / 256 * 256;
+  cqk_status st = ensure_buffer(ctx->ws, list_bytes + ctr_bytes + hist_bytes);
   if (st != CQK_OK) return st;
   char* p = (char*)ctx->ws.ptr;
   w->list = (int32_t*)p;
   w->counters = (int32_t*)(p + list_bytes);
+  w->bhist = (int32_t*)(p + list_bytes + ctr_bytes);
   return CQK_OK;
 }
 
@@ -812,10 +881,9 @@ int persistent_grid(cqk_ctx* ctx, const cqk_batch_schedule& sc, int nseg) {
 
 void plan(cqk_ctx* ctx, const BatArgs& A) {
   hipStream_t s = ctx->stream;
-  hipLaunchKernelGGL(bat_zero_kernel, dim3(1), dim3(256), 0, s, A.counters);
-  const int gb = (A.nseg + kBlock - 1) / kBlock;
-  hipLaunchKernelGGL(bat_count_kernel, dim3(gb), dim3(kBlock), 0, s, A);
-  hipLaunchKernelGGL(bat_place_kernel, dim3(gb), dim3(kBlock), 0, s, A);
+  const int gb = std::max(1, (A.nseg + kPBlock - 1) / kPBlock);
+  hipLaunchKernelGGL(bat_count_kernel, dim3(gb), dim3(kPBlock), 0, s, A);
+  hipLaunchKernelGGL(bat_place_kernel, dim3(gb), dim3(kPBlock), 0, s, A);
 }
 
 void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A) {
@@ -858,6 +926,7 @@ BatArgs forward_args(int32_t nseg, const int64_t* offsets, const float* y, const
   A.nfree_out = nfree_out;
   A.list = w.list;
   A.counters = w.counters;
+  A.bhist = w.bhist;
   return A;
 }
 
@@ -872,6 +941,7 @@ BatArgs backward_args(int32_t nseg, const int64_t* offsets, const float* x, cons
   A.gr = grad_r;
   A.list = w.list;
   A.counters = w.counters;
+  A.bhist = w.bhist;
   return A;
 }
 

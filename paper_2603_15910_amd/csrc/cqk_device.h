@@ -191,23 +191,6 @@ __device__ __forceinline__ int block_excl_scan(int v, int* lds_i, int* total) {
   return base + incl - v;
 }
 
-// ---------------------------------------------------------------------------
-// Grid completion ticket: returns true in exactly one block, the last one to
-// arrive, after every other block's partial is visible to it.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ bool last_block_arrives(uint32_t* ticket) {
-  __shared__ bool s_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    uint32_t t = atomicAdd(ticket, 1u);
-    s_last = (t == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) __threadfence();
-  return s_last;
-}
-
 // Partial records are stored value-major: value i of block g at
 // partials[i * G + g], so the reducing block reads them coalesced.
 __device__ __forceinline__ void write_partial(double* partials, const double* v, int nv) {
