@@ -1,10 +1,9 @@
 // Device building blocks shared by the libcqk kernels (gfx950, wave64).
 //
-// Reductions are deterministic: a fixed sequence of DPP lane moves inside the
+// Reductions are deterministic: a fixed sequence of lane exchanges inside the
 // wave, wave results combined in wave order through LDS, block partials
-// combined in block order by a one-block reduction kernel (or by the last
-// block to finish, where a kernel uses the ticket below).  Repeated calls on
-// the same input give bit-identical results.
+// combined in a fixed order by a one-block reduction kernel.  Repeated calls
+// on the same input give bit-identical results.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -129,6 +128,59 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 // `lds` needs (NS + NM + NX) * (blockDim/64) doubles; `out` is in LDS and
 // holds the block totals (combined in wave order) for every thread on return.
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Many sums over a wave by halving exchanges: at each of the six lane bits
+// (5, 4 through cross-row swizzles; 3, 2, 1, 0 through DPP mirrors and quad
+// permutes, each pairing lanes with opposite bit) a lane keeps half of the
+// values it still holds, adds its partner's copy of that half, and hands the
+// other half to the partner; once one value is left the remaining steps add
+// the partner's value.  N sums then cost about N exchanges instead of the 6N
+// of one butterfly per value.  Afterwards lane l holds in v[0] the total of
+// value (l >> (6 - log2 N)) & (N - 1); lanes that share it hold the same
+// bits.  Whole wave active.
+// ---------------------------------------------------------------------------
+namespace detail {
+template <int BIT>
+__device__ __forceinline__ double lane_swap(double v) {
+  if constexpr (BIT == 5) return __shfl_xor(v, 32, kWave);
+  else if constexpr (BIT == 4) return __shfl_xor(v, 16, kWave);
+  else if constexpr (BIT == 3) return dpp_move<dpp::kMirror, 0xF>(v, 0.0);
+  else if constexpr (BIT == 2) return dpp_move<dpp::kHalfMirror, 0xF>(v, 0.0);
+  else if constexpr (BIT == 1) return dpp_move<dpp::kXor2, 0xF>(v, 0.0);
+  else return dpp_move<dpp::kXor1, 0xF>(v, 0.0);
+}
+
+template <int BIT, int M>
+__device__ __forceinline__ void halve(double* v, int lane) {
+  if constexpr (M > 1) {
+    const bool low = ((lane >> BIT) & 1) == 0;
+#pragma unroll
+    for (int k = 0; k < M / 2; ++k) {
+      const double send = low ? v[M / 2 + k] : v[k];
+      const double keep = low ? v[k] : v[M / 2 + k];
+      v[k] = keep + lane_swap<BIT>(send);
+    }
+  } else {
+    v[0] = v[0] + lane_swap<BIT>(v[0]);
+  }
+}
+
+constexpr int ilog2(int n) { return n <= 1 ? 0 : 1 + ilog2(n / 2); }
+constexpr int at_least_one(int n) { return n < 1 ? 1 : n; }
+}  // namespace detail
+
+template <int N>
+__device__ __forceinline__ void wave_sum_many(double* v) {
+  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "N: a power of two up to 64");
+  const int lane = threadIdx.x & (kWave - 1);
+  detail::halve<5, N>(v, lane);
+  detail::halve<4, detail::at_least_one(N / 2)>(v, lane);
+  detail::halve<3, detail::at_least_one(N / 4)>(v, lane);
+  detail::halve<2, detail::at_least_one(N / 8)>(v, lane);
+  detail::halve<1, detail::at_least_one(N / 16)>(v, lane);
+  detail::halve<0, detail::at_least_one(N / 32)>(v, lane);
+}
+
 template <int NS, int NM, int NX, int BLOCK>
 __device__ __forceinline__ void block_reduce(const double* sums, const double* mins,
                                              const double* maxs, double* lds, double* out) {
@@ -136,10 +188,22 @@ __device__ __forceinline__ void block_reduce(const double* sums, const double* m
   constexpr int NV = NS + NM + NX;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
+  if constexpr (NS >= 4) {
+    static_assert(NS <= 32, "at most 32 sums");
+    constexpr int N = (NS <= 4) ? 4 : (NS <= 8) ? 8 : (NS <= 16) ? 16 : 32;
+    constexpr int SH = 6 - detail::ilog2(N);
+    double v[N];
 #pragma unroll
-  for (int i = 0; i < NS; ++i) {
-    double v = wave_sum(sums[i]);
-    if (lane == 0) lds[i * NW + wid] = v;
+    for (int i = 0; i < N; ++i) v[i] = (i < NS) ? sums[i] : 0.0;
+    wave_sum_many<N>(v);
+    const int idx = (lane >> SH) & (N - 1);
+    if ((lane & ((1 << SH) - 1)) == 0 && idx < NS) lds[idx * NW + wid] = v[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      double v = wave_sum(sums[i]);
+      if (lane == 0) lds[i * NW + wid] = v;
+    }
   }
 #pragma unroll
   for (int i = 0; i < NM; ++i) {
