@@ -433,8 +433,21 @@ __device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
         if (!((double)v[e] + lam_min > 0.0)) active &= ~(1u << e);
     }
     if (__ballot(active != 0u) == 0) continue;
-    double nk, ks;
-    const uint32_t keep = wave_tile_alg2(v, active, rd, run_c, run_s, lam_min, nk, ks);
+    double nk = 0.0, ks = 0.0;
+    uint32_t keep = 0;
+    if (run_c > 0.0) {
+      // a later tile: the running bound has already filtered it and every
+      // value left is kept; lam_J of everything kept so far becomes the
+      // bound below (again >= lam*)
+      keep = active;
+#pragma unroll
+      for (int e = 0; e < kK; ++e) {
+        nk += ((active >> e) & 1u) ? 1.0 : 0.0;
+        ks += ((active >> e) & 1u) ? (double)v[e] : 0.0;
+      }
+    } else {
+      keep = wave_tile_alg2(v, active, rd, run_c, run_s, lam_min, nk, ks);
+    }
     if (__ballot(keep != 0u) == 0) continue;
 #pragma unroll
     for (int e = 0; e < kK; ++e) {
