@@ -20,12 +20,12 @@
 //
 // A workgroup row is read once from HBM and x written once: each wave takes
 // every fourth tile of 1024 values, writes zeros to that part of x, runs
-// Algorithm 2 on 16 values per lane and keeps only the values above its
-// running bound (wave reductions only), appending them with their indices to
-// its LDS list.  After one barrier every wave combines the four lists'
-// bounds, refines the start at 12 candidate points, runs Algorithm 4 on the
-// lists (all waves get the same multiplier) and writes x for its own list's
-// entries; every other x is the zero already written.  The backward pass
+// Algorithm 2 on 16 values per lane on its first tile with values above its
+// running bound and keeps every such value of later tiles (wave reductions
+// only), appending them with their indices to its LDS list.  After one barrier every wave combines the four lists'
+// bounds, runs Algorithm 4 on the lists from the combined bound (all waves
+// get the same multiplier) and writes x for its own list's entries; every
+// other x is the zero already written.  The backward pass
 // does the same with the support: zeros first, then g - mean_S g on S.
 // A wave row keeps its values in registers from load to store.
 #include <algorithm>
@@ -46,7 +46,6 @@ constexpr int kSurvW = 1024;         // LDS list slots per wave (value + index)
 constexpr int kNB = 24;              // length buckets (bucket 0: wave rows)
 constexpr int kRefine = 8;
 constexpr int kMaxNewton = 100;
-constexpr int kCand = 12;            // start refinement candidates
 
 enum BatFlags : int32_t { kBadRadius = 1, kBadValue = 2, kInfeasible = 4 };
 
@@ -65,6 +64,7 @@ struct BatArgs {
   float* gy;            // backward: grad_y
   double* gr;           // backward: grad_r
   int32_t* list;        // row ids: workgroup rows by bucket, then wave rows
+  int64_t* lrow;        // per list entry: the row's first element and its length
   int32_t* counters;    // 3kNB: n_long, +1: n_short, +2: n_items, +3: queue, +4: flags,
                         // +6: survivors total, +7: overflow rows
   int32_t* bhist;       // planning: rows per length bucket of each block of kPBlock rows
@@ -179,7 +179,13 @@ __global__ __launch_bounds__(kPBlock) void bat_place_kernel(BatArgs A) {
     }
   }
   __syncthreads();
-  if (b >= 0) A.list[base[b] + pre[b] + wh[w][b] + rank] = s;
+  if (b >= 0) {
+    const int pos = base[b] + pre[b] + wh[w][b] + rank;
+    A.list[pos] = s;
+    // the solve kernels read the row's extent with its id, in one round trip
+    A.lrow[2 * (size_t)pos] = A.off[s];
+    A.lrow[2 * (size_t)pos + 1] = A.off[s + 1] - A.off[s];
+  }
 }
 
 __device__ __forceinline__ double row_radius(const BatArgs& A, int s) {
@@ -384,11 +390,9 @@ __device__ __forceinline__ double wave_newton_lists(const BatLds& L, const int* 
 // ---------------------------------------------------------------------------
 // One workgroup row.
 // ---------------------------------------------------------------------------
-__device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
+__device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n, BatLds& L) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const int64_t base = A.off[s];
-  const int64_t n = A.off[s + 1] - base;
   const double rd = row_radius(A, s);
   const float* y = A.y + base;
   float* x = A.x + base;
@@ -544,26 +548,10 @@ __device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
     }
     return;
   }
-  // start refinement: Newton steps lam_J(J_j), J_j = {v + lam_j > 0}, from
-  // candidates between lam_0 and -max y; each is an upper bound of lam*
-  // (one candidate at a time: the lists are short and in LDS, and this keeps
-  // the register count low enough for more workgroups per compute unit)
+  // Algorithm 4 from lam_0 (>= lam*) on the lists.  (The start refinement of
+  // the single-instance path, 12 candidate sets, is left out here: on lists
+  // in LDS it cost more than the Newton steps it saves.)
   double lam = lam0;
-  for (int j = 0; j < kCand; ++j) {
-    const double lj = -vmax + (lam0 + vmax) / (double)(1u << j);
-    double cc = 0.0, cs = 0.0;
-    for (int w = 0; w < kWaves; ++w) {
-      for (int i = lane; i < nws[w]; i += kWave) {
-        const double v = (double)L.sv[w][i];
-        const bool in = v + lj > 0.0;
-        cc += in ? 1.0 : 0.0;
-        cs += in ? v : 0.0;
-      }
-    }
-    cc = wave_sum(cc);
-    cs = wave_sum(cs);
-    if (cc > 0.0) lam = fmin(lam, (rd - cs) / cc);
-  }
   lam = wave_newton_lists(L, nws, rd, lam);
   // x for this wave's list; every other x of the row is already zero
   double nf = 0.0;
@@ -588,10 +576,8 @@ __device__ void solve_long_row(const BatArgs& A, int s, BatLds& L) {
 // One wave row (L <= 64 * SP), values in registers.
 // ---------------------------------------------------------------------------
 template <int SP>
-__device__ void solve_short_row(const BatArgs& A, int s) {
+__device__ void solve_short_row(const BatArgs& A, int s, int64_t base, int64_t L) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t base = A.off[s];
-  const int64_t L = A.off[s + 1] - base;
   const double rd = row_radius(A, s);
   const float* y = A.y + base;
   float* x = A.x + base;
@@ -727,10 +713,13 @@ __global__ __launch_bounds__(kBlock, 3) void bat_solve_kernel(BatArgs A) {
     if (item >= nitems) break;
     int idx;
     if (item_is_long(A, item, nlong, nsg, &idx)) {
-      solve_long_row(A, A.list[idx], L);
+      solve_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], L);
     } else {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
-      if (k < nshort) solve_short_row<SP>(A, A.list[nlong + k]);
+      if (k < nshort) {
+        const size_t e = (size_t)nlong + k;
+        solve_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+      }
     }
     __syncthreads();
   }
@@ -739,11 +728,9 @@ __global__ __launch_bounds__(kBlock, 3) void bat_solve_kernel(BatArgs A) {
 // ---------------------------------------------------------------------------
 // Backward: grad_y = [x > 0](g - mean_S g), grad_r = mean_S g.
 // ---------------------------------------------------------------------------
-__device__ void vjp_long_row(const BatArgs& A, int s, BatLds& L) {
+__device__ void vjp_long_row(const BatArgs& A, int s, int64_t base, int64_t n, BatLds& L) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  const int64_t base = A.off[s];
-  const int64_t n = A.off[s + 1] - base;
   const float* x = A.x + base;
   const float* g = A.g + base;
   float* gy = A.gy + base;
@@ -815,10 +802,8 @@ __device__ void vjp_long_row(const BatArgs& A, int s, BatLds& L) {
 }
 
 template <int SP>
-__device__ void vjp_short_row(const BatArgs& A, int s) {
+__device__ void vjp_short_row(const BatArgs& A, int s, int64_t base, int64_t L) {
   const int lane = threadIdx.x & (kWave - 1);
-  const int64_t base = A.off[s];
-  const int64_t L = A.off[s + 1] - base;
   float xs[SP], gs[SP];
   double cnt = 0.0, sum = 0.0;
 #pragma unroll
@@ -858,10 +843,13 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
     if (item >= nitems) break;
     int idx;
     if (item_is_long(A, item, nlong, nsg, &idx)) {
-      vjp_long_row(A, A.list[idx], L);
+      vjp_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], L);
     } else {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
-      if (k < nshort) vjp_short_row<SP>(A, A.list[nlong + k]);
+      if (k < nshort) {
+        const size_t e = (size_t)nlong + k;
+        vjp_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+      }
     }
     __syncthreads();
   }
@@ -871,6 +859,7 @@ struct BatWs {
   int32_t* list;
   int32_t* counters;
   int32_t* bhist;
+  int64_t* lrow;
 };
 
 cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
@@ -878,12 +867,14 @@ cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
   const size_t ctr_bytes = 256 * sizeof(int32_t);
   const size_t nblk = std::max<size_t>(1, ((size_t)nseg + kPBlock - 1) / kPBlock);
   const size_t hist_bytes = (nblk * kNB * sizeof(int32_t) + 255) / 256 * 256;
-  cqk_status st = ensure_buffer(ctx->ws, list_bytes + ctr_bytes + hist_bytes);
+  const size_t lrow_bytes = ((size_t)nseg * 2 * sizeof(int64_t) + 255) / 256 * 256;
+  cqk_status st = ensure_buffer(ctx->ws, list_bytes + ctr_bytes + hist_bytes + lrow_bytes);
   if (st != CQK_OK) return st;
   char* p = (char*)ctx->ws.ptr;
   w->list = (int32_t*)p;
   w->counters = (int32_t*)(p + list_bytes);
   w->bhist = (int32_t*)(p + list_bytes + ctr_bytes);
+  w->lrow = (int64_t*)(p + list_bytes + ctr_bytes + hist_bytes);
   return CQK_OK;
 }
 
@@ -940,6 +931,7 @@ BatArgs forward_args(int32_t nseg, const int64_t* offsets, const float* y, const
   A.list = w.list;
   A.counters = w.counters;
   A.bhist = w.bhist;
+  A.lrow = w.lrow;
   return A;
 }
 
@@ -955,6 +947,7 @@ BatArgs backward_args(int32_t nseg, const int64_t* offsets, const float* x, cons
   A.list = w.list;
   A.counters = w.counters;
   A.bhist = w.bhist;
+  A.lrow = w.lrow;
   return A;
 }
 
