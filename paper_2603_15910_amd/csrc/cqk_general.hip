@@ -42,10 +42,10 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
-constexpr int kStage = 128;  // LDS ring per wave and array for compaction
-constexpr int kPieceLog = 6;
+constexpr int kStage = 256;  // LDS ring per wave and array for compaction
+constexpr int kPieceLog = 7;
 constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
-static_assert(kPiece == kWave, "a flush writes one piece");
+static_assert(kPiece == 2 * kWave, "a full flush writes one piece, two values per lane");
 
 // Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
 // two (key, weight) pairs instead.
@@ -270,8 +270,8 @@ struct SrcForm {
 // One wave streams its tiles.  Compaction stages the survivors of slot
 // e of every lane in the wave's slice of LDS (ballot + lane prefix count,
 // slot after slot, so the layout is deterministic and needs no block-wide
-// synchronisation) and writes them out 64 at a time: one store per array
-// then fills 512 contiguous bytes, instead of one partial store per slot.
+// synchronisation) and writes them out kPiece = 128 at a time: one store per
+// array then fills 1 KB, instead of one partial store per slot.
 // The LDS operations of one wave complete in issue order, so a lane reads
 // what another lane staged without a wait; the wave-scope fences only keep
 // the compiler from reordering those accesses.
@@ -285,15 +285,27 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
   const int lane = threadIdx.x & (kWave - 1);
   int64_t written = 0;
   int head = 0, pend = 0;  // staged survivors occupy ring slots head .. head + pend - 1
-  // `written` is a multiple of kPiece = kWave at every flush, so a flush
-  // fills (the start of) one piece; non-temporal, like the other streams
+  // `written` and `head` are multiples of kPiece at every flush, so a flush
+  // fills (the start of) one piece: a full one with 16 bytes per lane and
+  // array (1 KB per store), the last one value by value; non-temporal, like
+  // the other streams
   auto flush = [&](int m) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    if (lane < m) {
-      const int q = (head + lane) & (kStage - 1);
-      const int64_t p = op.pos(written) + lane;
+    const int64_t p0 = op.pos(written);
+    if (m == kPiece) {
+      const int q = (head + 2 * lane) & (kStage - 1);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(stg[j * kStage + q], &out[j][p]);
+      for (int j = 0; j < 4; ++j) {
+        const dbl2 v = *reinterpret_cast<const dbl2*>(&stg[j * kStage + q]);
+        __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(&out[j][p0 + 2 * lane]));
+      }
+    } else {
+      for (int i = lane; i < m; i += kWave) {
+        const int q = (head + i) & (kStage - 1);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          __builtin_nontemporal_store(stg[j * kStage + q], &out[j][p0 + i]);
+      }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     head = (head + m) & (kStage - 1);
@@ -338,8 +350,9 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
           stg[3 * kStage + q] = bu[e];
         }
         pend += __popcll(m);
-        // pend < 64 before this slot, so the ring never holds more than 127
-        if (pend >= kWave) flush(kWave);
+        // pend < kPiece before this slot, so the ring never holds more than
+        // kPiece + 63 < kStage values
+        if (pend >= kPiece) flush(kPiece);
       }
     }
   };
