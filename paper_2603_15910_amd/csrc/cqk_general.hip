@@ -444,6 +444,9 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     st->status = CQK_INVALID_ARG;
     return;
   }
+  // algorithmic bytes: the set read (caller's arrays or the 32-byte form) and
+  // the survivors written
+  st->bytes += ((source == 0) ? st->in_bytes : 32.0) * t[P_NIN] + (compacted ? 32.0 * t[P_NOUT] : 0.0);
   const double phi = (st->F + st->C0) + (lam * st->C1 + t[P_P]);
   const double A = (st->AF + st->A0) + (lam * st->A1 + t[P_A]);
   const double Qp = st->C1 + t[P_QP];
@@ -513,6 +516,7 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
 // whose breakpoint is bp.  The Newton step from bp follows as in Algorithm 1.
 __device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec* tr) {
   st->passes += 1;
+  st->bytes += ((st->src == 0) ? st->in_bytes : 32.0) * (double)st->n_src;
   const bool right = st->mode == kModeBreakRight;
   const double bp = right ? ks[0].k : -ks[1].k;
   const double sw = right ? ks[0].w : ks[1].w;
@@ -692,6 +696,7 @@ __global__ __launch_bounds__(kRBlock) void gen_lambda0_update_kernel(GenArgs A, 
   reduce_partials<3, 0, 0, kRBlock>(A.partials, G, lds, tot);
   if (threadIdx.x == 0) {
     st->passes += 1;
+    st->bytes += st->in_bytes * (double)A.n;
     if (tot[2] > 0.0) {
       st->status = CQK_INVALID_ARG;
     } else {
@@ -902,6 +907,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.tol = (o.tol > 0.0) ? o.tol : std::pow(eps, 0.75);
   init.theta = (o.compact_theta > 0.0) ? o.compact_theta : 0.5;
   init.n_src = n;
+  init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
   init.max_iter = o.max_iter;
   init.compaction = o.compaction;
@@ -994,12 +1000,8 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
       hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
       info->finalize_ms = ms;
     }
-    // algorithmic bytes from the per-pass records (needs the trace)
-    for (int i = 0; i < ntrace; ++i) {
-      const cqk_trace_rec& t = ctx->last_trace[i];
-      const double per_in = (t.source == 0) ? 5.0 * sizeof(TIn) : 32.0;
-      info->pass_bytes += per_in * (double)t.n_in + 32.0 * (double)t.n_out;
-    }
+    // algorithmic bytes of the grid passes, summed on the device
+    info->pass_bytes = hs->bytes;
   }
   return CQK_OK;
 }

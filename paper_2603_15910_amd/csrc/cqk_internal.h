@@ -35,6 +35,8 @@ struct GenState {
   double lam_final, lam0;
   double r, tol, theta;
   double res_P, res_A;            // finalize: b^T x and sum |b x|
+  double bytes;                   // algorithmic bytes of the grid passes so far
+  double in_bytes;                // bytes per index of the caller's arrays
   int64_t n_src;                  // indices in the current source
   int64_t n_free;                 // finalize: free indices
   int32_t status, iter, passes, mode, src, compact_next, stop_reason, max_iter;
