@@ -12,10 +12,15 @@
 // b l < c + lam s <= b u.
 //
 // Kernels:
-//   gen_iter_kernel     one pass over the current index set + the scalar
-//                       Algorithm 1 update in the last block to finish;
+//   gen_pass_kernel     one pass over the current index set (evaluation at
+//                       lam, or the closest-breakpoint search), each block
+//                       writing one partial record;
+//   gen_update_kernel   one block: reduces the records and runs the scalar
+//                       Algorithm 1 update on the device-resident state;
 //   gen_lambda0_kernel  eq. (CQKlambda0) over all indices, with input checks;
 //   gen_finalize_kernel x(lam*) over all n indices (eq. (xopt)), b^T x.
+// The host queues passes in batches and reads the state once per batch;
+// a pass queued after the loop has stopped returns at once.
 //
 // Compaction.  Once the Newton bracket [lo, hi] is known, an index whose
 // bound is active on the whole bracket (c + hi s <= b l, or c + lo s >= b u)
@@ -23,14 +28,14 @@
 // the whole bracket, whose contribution is the line c + lam s.  Such indices
 // are dropped from the pass (their contributions kept as a few scalars) and
 // the survivors are written, in the per-index form above, to a ping-pong
-// buffer: block b always owns the same region, so no grid-wide scan is needed
-// and the layout is deterministic.  In exact arithmetic the values of phi and
-// its slopes are unchanged; this is the fixing of Section 2.2 applied through
-// the bracket, plus the free-side analogue.
+// set: wave w always owns the same pieces of it, so no grid-wide scan is
+// needed and the layout is deterministic.  In exact arithmetic the values of
+// phi and its slopes are unchanged; this is the fixing of Section 2.2 applied
+// through the bracket, plus the free-side analogue.
 #include <algorithm>
-#include <type_traits>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "cqk_device.h"
 #include "cqk_internal.h"

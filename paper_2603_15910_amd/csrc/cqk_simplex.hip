@@ -11,18 +11,20 @@
 // phi'_+(lam) = #{y + lam >= 0}, phi'_-(lam) = #{y + lam > 0}.
 // For the l1 ball the same runs on |y| and x gets the signs of y back.
 //
-// Layout: the grid is G0 blocks of 4 waves; wave region r owns chunk0/4
-// consecutive indices of y, and every compacted set keeps the same regions
-// (values and their indices in y, written with ballot + lane prefix counts:
-// deterministic, no block-wide synchronisation).
+// Layout: the grid is G0 blocks of 4 waves.  Passes over y hand its tiles to
+// the waves grid-stride (tile t to wave t mod NR); wave w writes the values
+// it keeps, with their indices in y, to region w of a compacted set (ballot
+// + lane prefix counts: deterministic, no block-wide synchronisation), and
+// later passes stream those regions.
 //
 // Kernels:
-//   spx_condat_kernel       one read of y: every thread runs Algorithm 2 on 16
-//                           register-resident values; the wave merges its
-//                           lanes' sets into lam_J bounds, refines them and
-//                           keeps only values above the smallest bound found
-//                           (wave reductions only, no barriers); values at or
-//                           below the wave's best bound skip Algorithm 2.
+//   spx_condat_kernel       one read of y (and x = 0 written over it): on a
+//                           wave's first tile with values above its bound
+//                           every thread runs Algorithm 2 on 16
+//                           register-resident values and the wave merges the
+//                           lanes' sets into lam_J bounds and refines them;
+//                           later tiles keep every value above the running
+//                           bound (wave reductions only, no barriers).
 //   spx_condat_merge_kernel lam_0 = the smallest bound any wave found and the
 //                           bound of the union of every surviving set.
 //   spx_pass_kernel<MULTI>  right after the start: the survivors' counts and
@@ -32,9 +34,12 @@
 //   spx_pass_kernel         one evaluation of phi and the counts over the
 //                           current set; drops y + lam_k <= 0 (valid because
 //                           lam_k >= lam*, Theorem 1).
-//   spx_update_kernel       Algorithm 4's update (one block).
-//   spx_tail_kernel         once the set fits in LDS: copies it there and runs
-//                           every remaining iteration inside one block.
+//   spx_update_kernel       Algorithm 4's update (one block); once the next set
+//                           fits in LDS the grid pass before it packs the set
+//                           densely and this kernel runs every remaining
+//                           iteration inside its block.
+//   spx_tail_kernel         the same loop for an input that fits from the
+//                           start (read from y).
 //   spx_finalize_kernel     dense x = max(0, y + lam*) (or 0, or a copy of y);
 //   spx_scatter_kernel      x[idx] for the surviving indices when the rest of
 //                           x is known to be zero.
