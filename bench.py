@@ -2,10 +2,14 @@
 
 One step = one whole solve (cqk_solve_f64: the Newton passes with compaction
 of resolved indices, then the x-writing pass) over inputs already resident in
-HBM.  Prints one JSON line; the fields are described in the design doc.  Besides
-the headline, "extras" reports the other workloads (correlated CQK, simplex
-and l1 at n = 1e8, batched and differentiable batched projections) on the same
-GPU, each checked for its status.
+HBM.  Prints one JSON line: the metric (elements/s = n / ms per solve), the
+roofline of the pass kernel (algorithmic bytes per launch over its average
+launch time from HIP events stamped by its dispatches in the timed region,
+against 8 TB/s, and the measured HBM traffic per launch when the committed
+counter summary matches the kernel source), the oracle's CPU rate on a 1e7
+sample, and "extras": the other workloads (correlated CQK, simplex and l1 at
+n = 1e8, batched and differentiable batched projections) on the same GPU,
+each checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
                     [--no-cpu-baseline] [--no-extras] [--calibrate-copy]
@@ -136,6 +140,25 @@ def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
     return ex
 
 
+def copy_ceiling(torch):
+    """Read + write GB/s of a 1 GiB device-to-device copy, best of 5."""
+    src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2.0 * (1 << 30) / (best * 1e-3) / 1e9
+
+
 def extra_correlated(ctx, dev, torch):
     from paper_2603_15910_amd import workloads as W
     sync = torch.cuda.synchronize
@@ -153,6 +176,14 @@ def extra_correlated(ctx, dev, torch):
         "status": info["status_name"],
         "pass_gbs": info["pass_bytes"] / (info["pass_ms"] * 1e-3) / 1e9,
         "finalize_gbs": info["finalize_bytes"] / (info["finalize_ms"] * 1e-3) / 1e9}
+    # the eq. (CQKlambda0) start instead of lambda_0 = 0
+    ctx.solve(*t, r, out=x, lambda0="formula")
+    ms = timed(lambda: ctx.solve(*t, r, out=x, lambda0="formula"), 5, sync)
+    _, info = ctx.solve(*t, r, out=x, lambda0="formula", timing=True)
+    ex["cqk_correlated_1e8_f64_formula_start"] = {
+        "ms": ms, "elements_per_s": 1e8 / (ms * 1e-3), "iterations": info["iterations"],
+        "status": info["status_name"],
+        "pass_gbs": info["pass_bytes"] / (info["pass_ms"] * 1e-3) / 1e9}
     del t, x
     torch.cuda.empty_cache()
     return ex
@@ -177,13 +208,14 @@ def extra_simplex(ctx, dev, torch):
                     "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
                     "n_after_init": info["n_after_init"], "status": info["status_name"],
                     "gbs_total": (info["pass_bytes"] + info["finalize_bytes"]) / (ms * 1e-3) / 1e9}
-        if dist == "normal":
-            for start in ("condat", "zero"):
-                kw = dict(lambda0=start)
+        # l1 ball of radius 1 (on U[0,1] input this is the simplex problem)
+        for start in ("condat", "zero"):
+            for accum in ("f64", "f32"):
+                kw = dict(lambda0=start, accum=accum)
                 ctx.project_l1(y, 1.0, out=xs, **kw)
                 ms = timed(lambda: ctx.project_l1(y, 1.0, out=xs, **kw), 5, sync)
                 _, info = ctx.project_l1(y, 1.0, out=xs, **kw)
-                ex[f"l1_{dist}_1e8_f32_{start}"] = {
+                ex[f"l1_{dist}_1e8_f32in_{accum}acc_{start}"] = {
                     "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
                     "status": info["status_name"]}
         del y, xs
@@ -289,8 +321,8 @@ def main():
                     help="skip the per-row loop comparator of the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(how the method would shard is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -348,6 +380,13 @@ def main():
                (sum(i["finalize_ms"] for i in infos) * 1e-3) / 1e9)
     ctx.solve(*t, r, out=x, trace=True)  # after the timed region: the per-pass log
     tr = ctx.trace()
+    # context beside the headline (not the metric): the eq. (CQKlambda0) start
+    # on the same instance, and the device-copy ceiling of this part
+    ctx.solve(*t, r, out=x, lambda0="formula")
+    ms_formula = timed(lambda: ctx.solve(*t, r, out=x, lambda0="formula"), 5,
+                       torch.cuda.synchronize)
+    _, info_formula = ctx.solve(*t, r, out=x, lambda0="formula")
+    copy_gbs = copy_ceiling(torch)
     log(f"bench: {ms:.3f} ms/solve, iterations={infos[-1]['iterations']}, "
         f"pass GB/s={achieved:.0f}, finalize GB/s={fin_gbs:.0f}")
     for rec in tr:
@@ -386,7 +425,10 @@ def main():
         },
         "iterations": infos[-1]["iterations"],
         "finalize_gbs": fin_gbs,
+        "formula_start": {"ms": ms_formula, "iterations": info_formula["iterations"],
+                          "elements_per_s": n / (ms_formula * 1e-3)},
     }
+    out["roofline"]["copy_ceiling_gbs"] = copy_gbs
     del t, x
     torch.cuda.empty_cache()
     if not args.no_extras:
