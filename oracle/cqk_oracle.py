@@ -33,6 +33,14 @@ Functions and the passage each follows:
 * ``condat_lambda0``    -- Algorithm 2 (Condat-style initial multiplier),
                            with the l1 test of Section 3.2.
 * ``lambda_J``          -- eq. (lambdaJ).
+* ``cqk_lambda0``       -- eq. (CQKlambda0), J = all indices.
+* ``cqk_lambda0_warm``  -- the warm start of Section 2.1 from a primal
+                           estimate: eq. (CQKlambda0) over the estimate's
+                           free set, its bound-fixed indices on the right-hand
+                           side.
+* ``simplex_lambda0_warm`` -- the warm start of Section 3.1: Algorithm 2 over
+                           the estimate's support, with the fallback given
+                           there when no support index is used.
 * ``newton_simplex``    -- Algorithm 4 (trace for invariant tests).
 * ``newton_cqk``        -- Algorithm 1 with the stopping criteria of
                            Section 5 (trace for invariant tests).
@@ -467,6 +475,62 @@ def condat_lambda0(y, r, I=None, l1=False):
             lam = (r - S - vj) / (len(J) + 1)
             J.append(j)
             S += vj
+    return lam, J
+
+
+def cqk_lambda0(d, a, b, l, u, r) -> float:
+    """eq. (CQKlambda0) with J = all indices: the multiplier of the problem
+    without bounds, (r - sum b a/d) / sum b^2/d."""
+    d, a, b = _as64(d, a, b)
+    return (float(r) - _lsum(b * a / d)) / _lsum(b * b / d)
+
+
+def cqk_lambda0_warm(d, a, b, l, u, r, xbar) -> float:
+    """Warm start of Section 2.1 from a primal estimate xbar.
+
+    The indices strictly inside their bounds in xbar, J = {l < xbar < u}, are
+    taken as free; an index at or beyond a bound in xbar is taken as fixed at
+    that bound.  lam0 is then the multiplier of that guess:
+
+        lam0 = (r - sum_{xbar <= l} b l - sum_{xbar >= u} b u - sum_J b a/d)
+               / sum_J b^2/d.
+
+    Reading: the paper applies eq. (CQKlambda0) with this J and calls the
+    other indices "expected to have active bounds"; the printed formula has
+    no term for them, and the reading here moves their b x (at the bound they
+    reach) to the right-hand side, so that the estimate x* itself returns
+    lam*.  With J empty xbar is discarded and J = all indices (plain
+    eq. (CQKlambda0))."""
+    d, a, b, l, u, xb = _as64(d, a, b, l, u, xbar)
+    free = (xb > l) & (xb < u)
+    if not free.any():
+        return cqk_lambda0(d, a, b, l, u, r)
+    at_l = (~free) & (xb <= l)
+    at_u = (~free) & (xb >= u)
+    fixed = _lsum(np.concatenate([b[at_l] * l[at_l], b[at_u] * u[at_u]]))
+    s = _lsum(b[free] * a[free] / d[free])
+    q = _lsum(b[free] * b[free] / d[free])
+    return (float(r) - fixed - s) / q
+
+
+def simplex_lambda0_warm(y, r, xbar, l1=False):
+    """Warm start of Section 3.1: Algorithm 2 over I = {xbar > 0} (the
+    support of the estimate; l1: {xbar != 0}), in index order.  When no
+    index of I is used (I empty), lam0 = max{r/n, -max y}.
+
+    Reading: the fallback is printed as max{r/n, -y_1}; -y_1 is read as
+    -max_i y_i (l1: -max |y_i|), the lower bound of lam* that the section
+    names, so lam0 >= that bound as stated there.
+
+    Returns (lam0, J): J the indices Algorithm 2 used (empty on the
+    fallback)."""
+    y = np.asarray(y, dtype=np.float64)
+    xb = np.asarray(xbar, dtype=np.float64)
+    I = np.flatnonzero(xb != 0.0) if l1 else np.flatnonzero(xb > 0.0)
+    lam, J = condat_lambda0(y, r, I=I, l1=l1) if I.size else (math.nan, [])
+    if not J:
+        v = np.abs(y) if l1 else y
+        return max(float(r) / y.size, -float(np.max(v))), []
     return lam, J
 
 

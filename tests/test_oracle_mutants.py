@@ -201,8 +201,35 @@ def pin_vjp_fd(M):
     return True
 
 
+def pin_warm(M):
+    # warm starts from the exact solutions return lam*; the hand instance;
+    # the fallbacks
+    inst = W.cqk_uniform(400, 9)
+    d, a, b, l, u, r = (inst[k] for k in ("d", "a", "b", "l", "u", "r"))
+    res = M.solve_cqk(d, a, b, l, u, r)
+    if abs(M.cqk_lambda0_warm(d, a, b, l, u, r, res.x) - res.lam) > 1e-11 * max(1, abs(res.lam)):
+        return False
+    dd = np.array([1.0, 2.0, 1.0]); aa = np.array([4.0, 2.0, -1.0]); bb = np.array([1.0, 1.0, 2.0])
+    if M.cqk_lambda0_warm(dd, aa, bb, np.zeros(3), np.ones(3), 2.5, np.array([1.5, 0.5, -1.0])) != 1.0:
+        return False
+    if M.cqk_lambda0_warm(dd, aa, bb, np.zeros(3), np.ones(3), 2.5, np.array([1.0, 0.0, 1.0])) \
+            != (2.5 - 3.0) / 5.5:
+        return False
+    y = W.simplex_input(1000, 9, "normal", np.float64)
+    x, lam = M.project_simplex(y, 1.0)
+    lam0, J = M.simplex_lambda0_warm(y, 1.0, x)
+    if abs(lam0 - lam) > 1e-11 * max(1, abs(lam)) or sorted(J) != list(np.flatnonzero(x > 0)):
+        return False
+    yy = np.array([0.3, -0.2, 0.9, 0.1])
+    lam0, J = M.simplex_lambda0_warm(yy, 1.0, np.array([0.0, -1.0, 0.0, 0.0]))
+    if J or lam0 != 0.25:
+        return False
+    lam0, J = M.simplex_lambda0_warm(yy, 5.0, np.zeros(4))
+    return lam0 == 1.25
+
+
 PINS = [pin_golden, pin_bruteforce, pin_kkt, pin_simplex_special_case, pin_condat,
-        pin_newton_cqk, pin_vjp_fd, pin_slopes]
+        pin_newton_cqk, pin_vjp_fd, pin_slopes, pin_warm]
 
 
 def _survives(M):
@@ -249,6 +276,14 @@ MUTANTS = [
     ("vjp mean", "gbar = _lsum(g[S]) / k", "gbar = _lsum(g[S]) / x.size"),
     ("cqk vjp drops d", "return np.where(F, (g - b * mu) / d, 0.0), mu", "return np.where(F, (g - b * mu), 0.0), mu"),
     ("kkt sign", "g = d * x - a - lam * b", "g = d * x - a + lam * b"),
+    ("warm drops fixed term", "return (float(r) - fixed - s) / q", "return (float(r) - s) / q"),
+    ("warm fixed at wrong bound", "fixed = _lsum(np.concatenate([b[at_l] * l[at_l], b[at_u] * u[at_u]]))",
+     "fixed = _lsum(np.concatenate([b[at_l] * u[at_l], b[at_u] * l[at_u]]))"),
+    ("warm free set closed", "free = (xb > l) & (xb < u)", "free = (xb >= l) & (xb <= u)"),
+    ("warm support test", "I = np.flatnonzero(xb != 0.0) if l1 else np.flatnonzero(xb > 0.0)",
+     "I = np.flatnonzero(xb != 0.0) if l1 else np.flatnonzero(xb >= 0.0)"),
+    ("warm fallback", "return max(float(r) / y.size, -float(np.max(v))), []",
+     "return max(float(r), -float(np.max(v))), []"),
 ]
 
 

@@ -463,3 +463,81 @@ def test_batched_rowwise():
         xs, ls = O.project_simplex(y[off[s]:off[s + 1]], 1.0)
         np.testing.assert_array_equal(x[off[s]:off[s + 1]], xs)
         assert lam[s] == ls
+
+
+# ---------------------------------------------------------------------------
+# Warm starts from a primal estimate (Section 2.1 end, Section 3.1)
+# ---------------------------------------------------------------------------
+def test_cqk_lambda0_is_unbounded_solution():
+    # eq. (CQKlambda0) with J = all indices is the multiplier of the problem
+    # without bounds: the sort solver on the same data with infinite bounds
+    inst = W.cqk_uniform(300, 4)
+    d, a, b = inst["d"], inst["a"], inst["b"]
+    l = np.full(300, -np.inf)
+    u = np.full(300, np.inf)
+    res = O.solve_cqk(d, a, b, l, u, 3.0)
+    assert abs(O.cqk_lambda0(d, a, b, l, u, 3.0) - res.lam) <= 1e-13 * abs(res.lam)
+
+
+@pytest.mark.parametrize("gen", ["uniform", "correlated", "paper_unc", "paper_cor"])
+def test_cqk_warm_from_the_solution_is_lambda_star(gen):
+    # the estimate's free set and bound set are the solution's: the linear
+    # equation of that guess is the one the sort solver solves on its piece
+    gens = {"uniform": lambda: W.cqk_uniform(2000, 5),
+            "correlated": lambda: W.cqk_correlated(2000, 5),
+            "paper_unc": lambda: W.cqk_paper(2000, 5, "uncorrelated"),
+            "paper_cor": lambda: W.cqk_paper(2000, 5, "correlated")}
+    inst = gens[gen]()
+    d, a, b, l, u, r = (inst[k] for k in ("d", "a", "b", "l", "u", "r"))
+    res = O.solve_cqk(d, a, b, l, u, r)
+    lam0 = O.cqk_lambda0_warm(d, a, b, l, u, r, res.x)
+    assert abs(lam0 - res.lam) <= 1e-12 * max(1.0, abs(res.lam))
+
+
+def test_cqk_warm_hand_instance():
+    # n = 3, d = (1, 2, 1), a = (4, 2, -1), b = (1, 1, 2), l = 0, u = 1, r = 2.5,
+    # xbar = (1.5, 0.5, -1): index 0 at u, index 1 free, index 2 at l.
+    # lam0 = (2.5 - b0*u0 - b2*l2 - b1*a1/d1) / (b1^2/d1) = (2.5 - 1 - 0 - 1)/0.5 = 1
+    d = np.array([1.0, 2.0, 1.0]); a = np.array([4.0, 2.0, -1.0]); b = np.array([1.0, 1.0, 2.0])
+    l = np.zeros(3); u = np.ones(3)
+    lam0 = O.cqk_lambda0_warm(d, a, b, l, u, 2.5, np.array([1.5, 0.5, -1.0]))
+    assert lam0 == 1.0
+    # with no index strictly inside its bounds the estimate is discarded
+    lam_all = O.cqk_lambda0_warm(d, a, b, l, u, 2.5, np.array([1.0, 0.0, 1.0]))
+    assert lam_all == O.cqk_lambda0(d, a, b, l, u, 2.5)
+    assert lam_all == (2.5 - (4.0 + 1.0 - 2.0)) / (1.0 + 0.5 + 4.0)
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform", "normal_small"])
+def test_simplex_warm_from_the_solution_is_lambda_star(dist):
+    y = W.simplex_input(5000, 6, dist, np.float64)
+    x, lam = O.project_simplex(y, 1.0)
+    lam0, J = O.simplex_lambda0_warm(y, 1.0, x)
+    assert sorted(J) == list(np.flatnonzero(x > 0))
+    assert abs(lam0 - lam) <= 1e-12 * max(1.0, abs(lam))
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform"])
+def test_simplex_warm_bounds_and_fixing(dist):
+    # Algorithm 2 over any support gives lam0 >= lam* (eq. (lambdaJ)), and
+    # y + lam0 <= 0 fixes x* at zero; also for an l1 estimate with signs
+    y = W.simplex_input(3000, 7, dist, np.float64)
+    x, lam = O.project_simplex(y, 1.0)
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        xbar = x + rng.normal(0.0, 0.01, x.size) * (rng.random(x.size) < 0.5)
+        lam0, J = O.simplex_lambda0_warm(y, 1.0, xbar)
+        assert J and lam0 >= lam - 1e-12
+        assert np.all(x[y + lam0 <= 0] == 0.0)
+        assert set(J) <= set(np.flatnonzero(xbar > 0))
+    xl, laml = O.project_l1(-y, 1.0)
+    lam0, J = O.simplex_lambda0_warm(-y, 1.0, xl, l1=True)
+    assert abs(lam0 - laml) <= 1e-12 * max(1.0, abs(laml))
+
+
+def test_simplex_warm_fallback():
+    y = np.array([0.3, -0.2, 0.9, 0.1])
+    lam0, J = O.simplex_lambda0_warm(y, 1.0, np.array([0.0, -1.0, 0.0, 0.0]))
+    assert J == [] and lam0 == max(1.0 / 4, -0.9)
+    lam0, J = O.simplex_lambda0_warm(y, 5.0, np.zeros(4))
+    assert lam0 == 5.0 / 4
