@@ -8,7 +8,8 @@ launch time from HIP events stamped by its dispatches in the timed region,
 against 8 TB/s, and the measured HBM traffic per launch when the committed
 counter summary matches the kernel source), the oracle's CPU rate on a 1e7
 sample, and "extras": the other workloads (correlated CQK, simplex and l1 at
-n = 1e8, batched and differentiable batched projections) on the same GPU,
+n = 1e8, warm starts from a previous solution, batched and differentiable
+batched projections) on the same GPU,
 each checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
@@ -116,7 +117,7 @@ def graph_replay_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-EXTRA_SECTIONS = ("correlated", "simplex", "batched", "differentiable")
+EXTRA_SECTIONS = ("correlated", "simplex", "warm", "batched", "differentiable")
 
 
 def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
@@ -131,6 +132,8 @@ def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
         ex.update(extra_correlated(ctx, dev, torch))
     if "simplex" in sections:
         ex.update(extra_simplex(ctx, dev, torch))
+    if "warm" in sections:
+        ex.update(extra_warm(ctx, dev, torch))
     if "batched" in sections:
         ex.update(extra_batched(ctx, dev, torch, row_loop))
     if "differentiable" in sections:
@@ -220,6 +223,57 @@ def extra_simplex(ctx, dev, torch):
                     "status": info["status_name"]}
         del y, xs
         torch.cuda.empty_cache()
+    return ex
+
+
+def extra_warm(ctx, dev, torch):
+    """Warm starts as an outer loop uses them: the problem moves a little
+    (a, or y, perturbed by 1e-3 of its deviation) and the previous solution
+    is the estimate; cold solves of the same problem beside them."""
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    ex = {}
+    n = 100_000_000
+
+    def entry(ms, info):
+        return {"ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
+                "lambda0": info["lambda0"], "lambda": info["lambda"],
+                "status": info["status_name"]}
+
+    inst = W.cqk_uniform(n, 1)
+    t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
+    r = inst["r"]
+    xprev = torch.empty_like(t[0])
+    ctx.solve(*t, r, out=xprev)
+    t[1] = torch.from_numpy(W.perturbed(inst["a"], 2, 1e-3)).to(dev)
+    del inst
+    x = torch.empty_like(xprev)
+    for name, kw in (("warm", dict(xbar=xprev)), ("cold", {})):
+        ctx.solve(*t, r, out=x, **kw)
+        ms = timed(lambda: ctx.solve(*t, r, out=x, **kw), 5, sync)
+        _, info = ctx.solve(*t, r, out=x, **kw)
+        ex[f"cqk_uniform_1e8_f64_perturbed_{name}"] = entry(ms, info)
+    del t, x, xprev
+    torch.cuda.empty_cache()
+
+    y0 = W.simplex_input(n, 1, "normal", np.float32)
+    y = torch.from_numpy(y0).to(dev)
+    y1 = torch.from_numpy(W.perturbed(y0, 2, 1e-3)).to(dev)
+    del y0
+    for kind, fn, rad in (("simplex", ctx.project_simplex, 1.0), ("l1", ctx.project_l1, 1.0)):
+        xprev = torch.empty_like(y)
+        fn(y, rad, out=xprev)
+        x = torch.empty_like(y)
+        for name, kw in (("warm", dict(xbar=xprev)), ("cold", {})):
+            fn(y1, rad, out=x, **kw)
+            ms = timed(lambda: fn(y1, rad, out=x, **kw), 5, sync)
+            _, info = fn(y1, rad, out=x, **kw)
+            e = entry(ms, info)
+            e["n_after_init"] = info["n_after_init"]
+            ex[f"{kind}_normal_1e8_f32in_perturbed_{name}"] = e
+        del xprev, x
+    del y, y1
+    torch.cuda.empty_cache()
     return ex
 
 

@@ -174,6 +174,49 @@ cqk_status cqk_project_l1_f32(cqk_ctx* ctx, int64_t n, const float* y, double ra
 cqk_status cqk_project_l1_f64(cqk_ctx* ctx, int64_t n, const double* y, double radius,
                               double* x, const cqk_opts* opts, cqk_info* info);
 
+/* Warm starts from a primal estimate xbar (n DEVICE values, same type as x,
+ * read only; it must not overlap x).  They return what the calls above
+ * return; only lambda_0 (info->lambda0) and the indices dropped before the
+ * first Newton pass change.  opts->lambda0_mode is ignored.
+ *
+ * General CQK (Section 2.1, the estimate's variant of eq. (CQKlambda0)):
+ * J = {l_i < xbar_i < u_i} is taken as free and every other index as fixed
+ * at the bound xbar reaches (xbar_i <= l_i: l_i, xbar_i >= u_i: u_i):
+ *   lambda_0 = (r - sum_{xbar<=l} b l - sum_{xbar>=u} b u - sum_J b a/d)
+ *              / sum_J b^2/d,
+ * plain eq. (CQKlambda0) over all indices when J is empty.  One extra read
+ * of d, a, b, l, u, xbar.  A NaN in xbar counts as fixed at neither bound
+ * and outside J.
+ *
+ * Simplex / l1 (Section 3.1): I = {xbar_i > 0} (l1: {xbar_i != 0}).  The
+ * start pass runs Algorithm 2 as the cold call does (its bounds fix values
+ * at zero whatever set they come from) and reads xbar beside y: the
+ * estimate's bound is lam_J over the kept values of I (every value of I that
+ * is free at the solution is kept), or r - max_I v when none is kept
+ * (v = y, l1: |y|).  lambda_0 is the smallest of it and the cold bounds, all
+ * upper bounds of lam*.  If I is empty, lambda_0 = max{r/n, -max_i v_i} and
+ * Newton's first step may come from below.
+ * INVALID_ARG: as the cold calls, plus xbar null or overlapping x. */
+cqk_status cqk_solve_warm_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                              const double* b, const double* l, const double* u,
+                              const double* xbar, double r, double* x, const cqk_opts* opts,
+                              cqk_info* info);
+cqk_status cqk_solve_warm_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                              const float* b, const float* l, const float* u, const float* xbar,
+                              double r, float* x, const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_simplex_warm_f32(cqk_ctx* ctx, int64_t n, const float* y,
+                                        const float* xbar, double r, float* x,
+                                        const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_simplex_warm_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                        const double* xbar, double r, double* x,
+                                        const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_l1_warm_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
+                                   double radius, float* x, const cqk_opts* opts,
+                                   cqk_info* info);
+cqk_status cqk_project_l1_warm_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xbar,
+                                   double radius, double* x, const cqk_opts* opts,
+                                   cqk_info* info);
+
 /* Many simplex projections in one launch: row s is y[offsets[s] ..
  * offsets[s+1]) (Section 3 Algorithms 2 and 4 applied per row).
  * offsets: int64[nseg+1] DEVICE array, non-decreasing, offsets[0] = 0.

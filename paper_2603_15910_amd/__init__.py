@@ -120,6 +120,40 @@ def cqk_project_l1_f64(ctx, n, y, radius, x, opts=None, info=None):
     return _proj("cqk_project_l1_f64", ctx, n, y, radius, x, opts, info)
 
 
+def _ref(o):
+    return C.byref(o) if o is not None else None
+
+
+def cqk_solve_warm_f64(ctx, n, d, a, b, l, u, xbar, r, x, opts=None, info=None):
+    return _call("cqk_solve_warm_f64", C.c_void_p(ctx), n, d, a, b, l, u, xbar, r, x,
+                 _ref(opts), _ref(info))
+
+
+def cqk_solve_warm_f32(ctx, n, d, a, b, l, u, xbar, r, x, opts=None, info=None):
+    return _call("cqk_solve_warm_f32", C.c_void_p(ctx), n, d, a, b, l, u, xbar, r, x,
+                 _ref(opts), _ref(info))
+
+
+def cqk_project_simplex_warm_f32(ctx, n, y, xbar, r, x, opts=None, info=None):
+    return _call("cqk_project_simplex_warm_f32", C.c_void_p(ctx), n, y, xbar, r, x,
+                 _ref(opts), _ref(info))
+
+
+def cqk_project_simplex_warm_f64(ctx, n, y, xbar, r, x, opts=None, info=None):
+    return _call("cqk_project_simplex_warm_f64", C.c_void_p(ctx), n, y, xbar, r, x,
+                 _ref(opts), _ref(info))
+
+
+def cqk_project_l1_warm_f32(ctx, n, y, xbar, radius, x, opts=None, info=None):
+    return _call("cqk_project_l1_warm_f32", C.c_void_p(ctx), n, y, xbar, radius, x,
+                 _ref(opts), _ref(info))
+
+
+def cqk_project_l1_warm_f64(ctx, n, y, xbar, radius, x, opts=None, info=None):
+    return _call("cqk_project_l1_warm_f64", C.c_void_p(ctx), n, y, xbar, radius, x,
+                 _ref(opts), _ref(info))
+
+
 def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out=None,
                                     nfree_out=None, opts=None, info=None):
     return _call("cqk_project_simplex_batched_f32", C.c_void_p(ctx), nseg, offsets, y, r,
@@ -231,7 +265,9 @@ class Context:
     def trace(self):
         return cqk_last_trace(self.handle)
 
-    def solve(self, d, a, b, l, u, r, out=None, check=True, **kw):
+    def solve(self, d, a, b, l, u, r, out=None, check=True, xbar=None, **kw):
+        """General CQK.  xbar: a primal estimate (same dtype and size) for
+        the warm start; lambda0 options are then ignored."""
         torch = _torch()
         dt = d.dtype
         if dt not in (torch.float64, torch.float32):
@@ -242,14 +278,21 @@ class Context:
         opts = make_opts(**kw)
         info = cqk_info()
         self._bind_stream()
-        fn = cqk_solve_f64 if dt == torch.float64 else cqk_solve_f32
-        st = fn(self.handle, n, *ptrs[:5], float(r), ptrs[5], opts, info)
+        if xbar is None:
+            fn = cqk_solve_f64 if dt == torch.float64 else cqk_solve_f32
+            st = fn(self.handle, n, *ptrs[:5], float(r), ptrs[5], opts, info)
+        else:
+            pw = _dev_ptr(xbar, dt, "xbar")
+            if xbar.numel() != n:
+                raise ValueError("xbar must have as many elements as d")
+            fn = cqk_solve_warm_f64 if dt == torch.float64 else cqk_solve_warm_f32
+            st = fn(self.handle, n, *ptrs[:5], pw, float(r), ptrs[5], opts, info)
         self.last_info = info.as_dict()
         if check and st not in (CQK_OK,):
             raise CqkError(st, "cqk_solve")
         return x, self.last_info
 
-    def _project(self, name64, name32, y, r, out, check, kw):
+    def _project(self, name64, name32, y, r, out, check, kw, xbar=None, warm=None):
         torch = _torch()
         x = out if out is not None else torch.empty_like(y)
         dt = y.dtype
@@ -260,18 +303,31 @@ class Context:
         opts = make_opts(simplex=True, **kw)
         info = cqk_info()
         self._bind_stream()
-        fn = name64 if dt == torch.float64 else name32
-        st = fn(self.handle, y.numel(), py, float(r), px, opts, info)
+        if xbar is None:
+            fn = name64 if dt == torch.float64 else name32
+            st = fn(self.handle, y.numel(), py, float(r), px, opts, info)
+        else:
+            pw = _dev_ptr(xbar, dt, "xbar")
+            if xbar.numel() != y.numel():
+                raise ValueError("xbar must have as many elements as y")
+            fn = warm[0] if dt == torch.float64 else warm[1]
+            st = fn(self.handle, y.numel(), py, pw, float(r), px, opts, info)
         self.last_info = info.as_dict()
         if check and st != CQK_OK:
             raise CqkError(st, fn.__name__)
         return x, self.last_info
 
-    def project_simplex(self, y, r=1.0, out=None, check=True, **kw):
-        return self._project(cqk_project_simplex_f64, cqk_project_simplex_f32, y, r, out, check, kw)
+    def project_simplex(self, y, r=1.0, out=None, check=True, xbar=None, **kw):
+        """Projection onto the r-simplex.  xbar: a primal estimate for the
+        warm start (Algorithm 2 over its support)."""
+        return self._project(cqk_project_simplex_f64, cqk_project_simplex_f32, y, r, out, check,
+                             kw, xbar, (cqk_project_simplex_warm_f64, cqk_project_simplex_warm_f32))
 
-    def project_l1(self, y, radius=1.0, out=None, check=True, **kw):
-        return self._project(cqk_project_l1_f64, cqk_project_l1_f32, y, radius, out, check, kw)
+    def project_l1(self, y, radius=1.0, out=None, check=True, xbar=None, **kw):
+        """Projection onto the l1 ball.  xbar: a primal estimate for the warm
+        start (Algorithm 2 over {xbar != 0})."""
+        return self._project(cqk_project_l1_f64, cqk_project_l1_f32, y, radius, out, check, kw,
+                             xbar, (cqk_project_l1_warm_f64, cqk_project_l1_warm_f32))
 
     def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
                                 nfree_out=None, check=True, **kw):

@@ -124,6 +124,12 @@ SIGNATURES = {
     "cqk_project_simplex_f64": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_l1_f32": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_l1_f64": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_solve_warm_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_solve_warm_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_project_simplex_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_project_simplex_warm_f64": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_project_l1_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_project_l1_warm_f64": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_f32": (
         C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _P, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_backward_f32": (

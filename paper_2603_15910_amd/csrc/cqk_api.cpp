@@ -83,6 +83,13 @@ cqk_status check_opts(const cqk_opts* in, cqk_opts* out, bool simplex) {
   return CQK_OK;
 }
 
+// true if the n-element arrays at p and q share any byte
+template <typename T>
+bool overlaps(const T* p, const T* q, int64_t n) {
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q, len = (uintptr_t)n * sizeof(T);
+  return a < b + len && b < a + len;
+}
+
 void info_trivial(cqk_info* info, int status, double lam) {
   if (!info) return;
   std::memset(info, 0, sizeof(*info));
@@ -93,7 +100,8 @@ void info_trivial(cqk_info* info, int status, double lam) {
 
 template <typename T>
 cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T* b, const T* l,
-                        const T* u, double r, T* x, const cqk_opts* opts, cqk_info* info) {
+                        const T* u, const T* xw, bool warm, double r, T* x, const cqk_opts* opts,
+                        cqk_info* info) {
   if (!ctx || n < 0 || !std::isfinite(r)) return CQK_INVALID_ARG;
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, false);
@@ -104,20 +112,21 @@ cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T
     return (cqk_status)s;
   }
   if (!d || !a || !b || !l || !u || !x) return CQK_INVALID_ARG;
+  if (warm && (!xw || overlaps(xw, (const T*)x, n))) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
-    st = run_general_f64(ctx, n, d, a, b, l, u, r, x, o, inf);
+    st = run_general_f64(ctx, n, d, a, b, l, u, xw, r, x, o, inf);
   else
-    st = run_general_f32(ctx, n, d, a, b, l, u, r, x, o, inf);
+    st = run_general_f32(ctx, n, d, a, b, l, u, xw, r, x, o, inf);
   if (st != CQK_OK) return st;
   return (cqk_status)inf->status;
 }
 
 template <typename T>
-cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, double r, T* x, bool l1,
-                          const cqk_opts* opts, cqk_info* info) {
+cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xw, bool warm, double r,
+                          T* x, bool l1, const cqk_opts* opts, cqk_info* info) {
   if (!ctx || n < 0 || !std::isfinite(r) || r < 0.0) return CQK_INVALID_ARG;
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, true);
@@ -128,13 +137,14 @@ cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, double r, T* x, b
     return (cqk_status)s;
   }
   if (!y || !x) return CQK_INVALID_ARG;
+  if (warm && (!xw || overlaps(xw, (const T*)x, n))) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
-    st = run_simplex_f64(ctx, n, y, r, x, l1, o, inf);
+    st = run_simplex_f64(ctx, n, y, xw, r, x, l1, o, inf);
   else
-    st = run_simplex_f32(ctx, n, y, r, x, l1, o, inf);
+    st = run_simplex_f32(ctx, n, y, xw, r, x, l1, o, inf);
   if (st != CQK_OK) return st;
   return (cqk_status)inf->status;
 }
@@ -225,33 +235,70 @@ cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t
 cqk_status cqk_solve_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
                          const double* b, const double* l, const double* u, double r, double* x,
                          const cqk_opts* opts, cqk_info* info) {
-  return solve_common<double>(ctx, n, d, a, b, l, u, r, x, opts, info);
+  return solve_common<double>(ctx, n, d, a, b, l, u, nullptr, false, r, x, opts, info);
 }
 
 cqk_status cqk_solve_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
                          const float* b, const float* l, const float* u, double r, float* x,
                          const cqk_opts* opts, cqk_info* info) {
-  return solve_common<float>(ctx, n, d, a, b, l, u, r, x, opts, info);
+  return solve_common<float>(ctx, n, d, a, b, l, u, nullptr, false, r, x, opts, info);
 }
 
 cqk_status cqk_project_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x,
                                    const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, r, x, false, opts, info);
+  return simplex_common<float>(ctx, n, y, nullptr, false, r, x, false, opts, info);
 }
 
 cqk_status cqk_project_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r,
                                    double* x, const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, r, x, false, opts, info);
+  return simplex_common<double>(ctx, n, y, nullptr, false, r, x, false, opts, info);
 }
 
 cqk_status cqk_project_l1_f32(cqk_ctx* ctx, int64_t n, const float* y, double radius, float* x,
                               const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, radius, x, true, opts, info);
+  return simplex_common<float>(ctx, n, y, nullptr, false, radius, x, true, opts, info);
 }
 
 cqk_status cqk_project_l1_f64(cqk_ctx* ctx, int64_t n, const double* y, double radius,
                               double* x, const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, radius, x, true, opts, info);
+  return simplex_common<double>(ctx, n, y, nullptr, false, radius, x, true, opts, info);
+}
+
+cqk_status cqk_solve_warm_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                              const double* b, const double* l, const double* u,
+                              const double* xbar, double r, double* x, const cqk_opts* opts,
+                              cqk_info* info) {
+  return solve_common<double>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info);
+}
+
+cqk_status cqk_solve_warm_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                              const float* b, const float* l, const float* u, const float* xbar,
+                              double r, float* x, const cqk_opts* opts, cqk_info* info) {
+  return solve_common<float>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info);
+}
+
+cqk_status cqk_project_simplex_warm_f32(cqk_ctx* ctx, int64_t n, const float* y,
+                                        const float* xbar, double r, float* x,
+                                        const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<float>(ctx, n, y, xbar, true, r, x, false, opts, info);
+}
+
+cqk_status cqk_project_simplex_warm_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                        const double* xbar, double r, double* x,
+                                        const cqk_opts* opts, cqk_info* info) {
+  return simplex_common<double>(ctx, n, y, xbar, true, r, x, false, opts, info);
+}
+
+cqk_status cqk_project_l1_warm_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
+                                   double radius, float* x, const cqk_opts* opts,
+                                   cqk_info* info) {
+  return simplex_common<float>(ctx, n, y, xbar, true, radius, x, true, opts, info);
+}
+
+cqk_status cqk_project_l1_warm_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xbar,
+                                   double radius, double* x, const cqk_opts* opts,
+                                   cqk_info* info) {
+  return simplex_common<double>(ctx, n, y, xbar, true, radius, x, true, opts, info);
 }
 
 cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,

@@ -80,6 +80,7 @@ struct GenArgs {
   const void* b;
   const void* l;
   const void* u;
+  const void* xw;   // primal estimate for the warm start (or null)
   void* x;
   int64_t n;
   int64_t chunk;
@@ -713,6 +714,85 @@ __global__ __launch_bounds__(kRBlock) void gen_lambda0_update_kernel(GenArgs A, 
   }
 }
 
+// Warm start from a primal estimate xbar (end of Section 2.1): the indices
+// strictly inside their bounds in xbar are taken as free, an index at or
+// beyond a bound as fixed at that bound, and lam_0 is the multiplier of that
+// guess, eq. (CQKlambda0) over the free set J with the fixed indices' b x on
+// the right-hand side:
+//   lam_0 = (r - sum_{xbar <= l} b l - sum_{xbar >= u} b u - sum_J b a/d)
+//           / sum_J b^2/d.
+// With J empty the estimate is discarded: eq. (CQKlambda0) over all indices.
+// Also the input checks.  (An entry of xbar that is NaN counts nowhere.)
+enum { WM_SJ = 0, WM_QJ, WM_FIX, WM_NJ, WM_SALL, WM_QALL, WM_BAD, WM_NSUM };
+
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_warm_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  constexpr int V = VecWidth<TIn>::value;
+  const int64_t n = A.n;
+  const TIn* d = (const TIn*)A.d;
+  const TIn* a = (const TIn*)A.a;
+  const TIn* b = (const TIn*)A.b;
+  const TIn* l = (const TIn*)A.l;
+  const TIn* u = (const TIn*)A.u;
+  const TIn* xw = (const TIn*)A.xw;
+  double acc[WM_NSUM] = {0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * V; i < n;
+       i += (int64_t)gridDim.x * kBlock * V) {
+    double vd[V], va[V], vb[V], vl[V], vu[V], vx[V];
+    Vec<TIn, V>::load(d, i, n, 1.0, vd);
+    Vec<TIn, V>::load(a, i, n, 0.0, va);
+    Vec<TIn, V>::load(b, i, n, 1.0, vb);
+    Vec<TIn, V>::load(l, i, n, 0.0, vl);
+    Vec<TIn, V>::load(u, i, n, 0.0, vu);
+    Vec<TIn, V>::load(xw, i, n, 0.0, vx);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (i + k < n) {
+        double c, s, bl, bu, bad = 0.0;
+        to_form(vd[k], va[k], vb[k], vl[k], vu[k], c, s, bl, bu, bad);
+        const bool fr = (vx[k] > vl[k]) && (vx[k] < vu[k]);
+        const bool at_l = !fr && (vx[k] <= vl[k]);
+        const bool at_u = !fr && (vx[k] >= vu[k]);
+        acc[WM_SJ] += fr ? c : 0.0;
+        acc[WM_QJ] += fr ? s : 0.0;
+        acc[WM_NJ] += fr ? 1.0 : 0.0;
+        acc[WM_FIX] += at_l ? bl : (at_u ? bu : 0.0);
+        acc[WM_SALL] += c;
+        acc[WM_QALL] += s;
+        acc[WM_BAD] += bad;
+      }
+    }
+  }
+  __shared__ double lds[WM_NSUM * (kBlock / kWave)];
+  __shared__ double tot[WM_NSUM];
+  block_reduce<WM_NSUM, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, WM_NSUM);
+}
+
+__global__ __launch_bounds__(kRBlock) void gen_warm_update_kernel(GenArgs A, int G) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[WM_NSUM * (kRBlock / kWave)];
+  __shared__ double tot[WM_NSUM];
+  reduce_partials<WM_NSUM, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x == 0) {
+    st->passes += 1;
+    st->bytes += (st->in_bytes * 6.0 / 5.0) * (double)A.n;  // the five arrays and xbar
+    if (tot[WM_BAD] > 0.0) {
+      st->status = CQK_INVALID_ARG;
+    } else {
+      const double lam0 = (tot[WM_NJ] > 0.0)
+                              ? (st->r - tot[WM_FIX] - tot[WM_SJ]) / tot[WM_QJ]
+                              : (st->r - tot[WM_SALL]) / tot[WM_QALL];
+      st->lam = lam0;
+      st->lam0 = lam0;
+    }
+    trace_push(st, A.trace, 0, 0, 0, st->lam, tot[WM_SJ], tot[WM_QJ], A.n, (int64_t)tot[WM_NJ]);
+  }
+}
+
 // x_i = clamp((a_i + lam b_i)/d_i, l_i, u_i) over all n (eq. (xopt)), with
 // b^T x, sum |b x| and the free count reduced for the caller's info.
 template <typename TIn>
@@ -864,8 +944,8 @@ namespace {
 
 template <typename TIn>
 cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, const TIn* b,
-                       const TIn* l, const TIn* u, double r, TIn* x, const cqk_opts& o,
-                       cqk_info* info) {
+                       const TIn* l, const TIn* u, const TIn* xw, double r, TIn* x,
+                       const cqk_opts& o, cqk_info* info) {
   const GenLayout Lg = gen_layout(n, ctx->num_cus, VecWidth<TIn>::value, o.compaction != CQK_COMPACT_OFF);
   const int G = Lg.G, NR = Lg.NR, GF = Lg.GF;
   const int64_t chunk = Lg.chunk;
@@ -884,6 +964,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   A.b = b;
   A.l = l;
   A.u = u;
+  A.xw = xw;
   A.x = x;
   A.n = n;
   A.chunk = chunk;
@@ -902,7 +983,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   const double eps = (is_f32 && o.accum == CQK_ACCUM_F32) ? 1.1920928955078125e-07
                                                           : 2.220446049250313e-16;
   GenState init{};
-  init.lam = (o.lambda0_mode == CQK_LAMBDA0_USER) ? o.lambda0_user : 0.0;
+  init.lam = (o.lambda0_mode == CQK_LAMBDA0_USER && xw == nullptr) ? o.lambda0_user : 0.0;
   init.lam0 = init.lam;
   init.lam_prev = __builtin_nan("");
   init.lo = -__builtin_huge_val();
@@ -945,7 +1026,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
                  o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, GF);
   };
-  if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
+  if (xw != nullptr)
+    launch(gen_warm_kernel<TIn>, gen_warm_update_kernel);
+  else if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
     launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel);
 
   GenState* hs = (GenState*)ctx->host_pinned;
@@ -1014,15 +1097,15 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
 }  // namespace
 
 cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
-                           const double* b, const double* l, const double* u, double r,
-                           double* x, const cqk_opts& o, cqk_info* info) {
-  return run_general<double>(ctx, n, d, a, b, l, u, r, x, o, info);
+                           const double* b, const double* l, const double* u, const double* xw,
+                           double r, double* x, const cqk_opts& o, cqk_info* info) {
+  return run_general<double>(ctx, n, d, a, b, l, u, xw, r, x, o, info);
 }
 
 cqk_status run_general_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
-                           const float* b, const float* l, const float* u, double r, float* x,
-                           const cqk_opts& o, cqk_info* info) {
-  return run_general<float>(ctx, n, d, a, b, l, u, r, x, o, info);
+                           const float* b, const float* l, const float* u, const float* xw,
+                           double r, float* x, const cqk_opts& o, cqk_info* info) {
+  return run_general<float>(ctx, n, d, a, b, l, u, xw, r, x, o, info);
 }
 
 }  // namespace cqk

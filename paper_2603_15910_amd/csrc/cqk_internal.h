@@ -57,7 +57,7 @@ struct SpxState {
   int32_t tail;                   // 1: the remaining iterations run in one block
   int32_t multi;                  // 1: the next pass refines the start (candidates)
   int32_t x_zeroed;               // 1: the start already wrote x = 0 everywhere
-  int32_t pad_[1];
+  int32_t warm;                   // 1: Algorithm 2 ran over the estimate's support
 };
 
 // How the simplex finalize writes x.
@@ -106,16 +106,18 @@ struct GenLayout {
 };
 GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction);
 
+// xw: the primal estimate of a warm start, or null (opts.lambda0_mode then
+// chooses the start)
 cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
-                           const double* b, const double* l, const double* u, double r,
-                           double* x, const cqk_opts& o, cqk_info* info);
+                           const double* b, const double* l, const double* u, const double* xw,
+                           double r, double* x, const cqk_opts& o, cqk_info* info);
 cqk_status run_general_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
-                           const float* b, const float* l, const float* u, double r, float* x,
-                           const cqk_opts& o, cqk_info* info);
-cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x, bool l1,
-                           const cqk_opts& o, cqk_info* info);
-cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r, double* x,
-                           bool l1, const cqk_opts& o, cqk_info* info);
+                           const float* b, const float* l, const float* u, const float* xw,
+                           double r, float* x, const cqk_opts& o, cqk_info* info);
+cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, double r,
+                           float* x, bool l1, const cqk_opts& o, cqk_info* info);
+cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw, double r,
+                           double* x, bool l1, const cqk_opts& o, cqk_info* info);
 cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                            const double* r, double r_scalar, float* x, double* lambda_out,
                            int32_t* nfree_out, const cqk_opts& o, cqk_info* info);

@@ -73,6 +73,7 @@ enum : int32_t { kTailNone = 0, kTailPack = 1, kTailY = 2 };
 
 struct SpxArgs {
   const void* y;
+  const void* xw;    // primal estimate of a warm start (or null), TIn
   void* x;
   int64_t n;
   int64_t chunk0;    // block region of the original layout; wave region = chunk0/4
@@ -248,10 +249,16 @@ __device__ __forceinline__ void zero_tile(TIn* x, int64_t base, int lane, int64_
 }
 
 // Partial record of the Algorithm 2 kernel.
-enum { C_CNT = 0, C_SUM, C_ABS, C_BAD, C_NOUT, C_NSUM };  // + min lam, max v
-constexpr int C_NPART = C_NSUM + 2;
+// C_CNTI, C_SUMI: the kept values of a warm start's support I.
+enum { C_CNT = 0, C_SUM, C_ABS, C_BAD, C_NOUT, C_CNTI, C_SUMI, C_NSUM };
+constexpr int C_NPART = C_NSUM + 3;  // + min lam, max v, max v over I
 
-template <typename TIn, typename TA>
+// WARM: also the warm start of Section 3.1 from a primal estimate xbar, with
+// I = {xbar > 0} (l1: xbar != 0).  The kernel runs as without it: every bound
+// it finds is lam_J of some non-empty J, so it fixes values at zero whatever
+// J is.  It also sums the kept values of I and takes the largest value of I,
+// from which the merge forms the estimate's lam_J.
+template <typename TIn, typename TA, bool WARM>
 __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   SpxState* st = A.st;
   if (st->status != kRunning) return;
@@ -279,9 +286,11 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
 
   // wave-uniform: the survivors this wave kept so far, the smallest bound
   double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
-  double acc[C_NSUM] = {0, 0, 0, 0, 0};
+  double acc[C_NSUM] = {0, 0, 0, 0, 0, 0, 0};
   double abs_sum = 0.0;            // sum |y| (l1 only)
+  double run_ci = 0.0, run_si = 0.0;  // kept values of I (WARM)
   TIn vmx = -(TIn)__builtin_huge_val();
+  TIn vmxI = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
   for (int64_t base = (int64_t)rid * TILE; base < count; base += nr * TILE) {
@@ -289,10 +298,19 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     TIn yv[K];
     TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
     load_tile<TIn, NL>(y, base, lane, count, yv);
+    uint32_t inI = 0xFFFFFFFFu;  // the values Algorithm 2 may use
+    if constexpr (WARM) {
+      TIn xv[K];
+      load_tile<TIn, NL>((const TIn*)A.xw, base, lane, count, xv);
+      inI = 0;
+#pragma unroll
+      for (int e = 0; e < K; ++e) inI |= (l1 ? (xv[e] != TIn(0)) : (xv[e] > TIn(0))) ? (1u << e) : 0u;
+    }
     // x_i = 0 for every index (survivors get their value from the scatter at
     // the end), written while this kernel is busy with Algorithm 2 anyway
     zero_tile<TIn, NL>(x, base, lane, count);
     TIn tmax = -(TIn)__builtin_huge_val();
+    TIn tmaxI = -(TIn)__builtin_huge_val();
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
@@ -304,9 +322,11 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         badacc += in ? yv[e] * TIn(0) : TIn(0);
         if (l1) abs_sum += in ? (double)av[e] : 0.0;
         tmax = max(tmax, in ? av[e] : -(TIn)__builtin_huge_val());
+        tmaxI = max(tmaxI, (in && ((inI >> e) & 1u)) ? av[e] : -(TIn)__builtin_huge_val());
       }
     }
     vmx = max(vmx, tmax);
+    vmxI = max(vmxI, tmaxI);
     // The first bound: J = {the tile's largest value} gives lam_J = r - max
     // (Algorithm 2's own first set, with the best single element).
     if (lam_min == inf_d()) {
@@ -402,6 +422,17 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       lam_min = fmin(lam_min, lam_b);
     }
     if (__ballot(keep != 0u) == 0) continue;
+    if constexpr (WARM) {
+      double ci = 0.0, si = 0.0;
+#pragma unroll
+      for (int e = 0; e < K; ++e) {
+        const bool kI = ((keep & inI) >> e) & 1u;
+        ci += kI ? 1.0 : 0.0;
+        si += kI ? (double)av[e] : 0.0;
+      }
+      run_ci += wave_sum(ci);
+      run_si += wave_sum(si);
+    }
 #pragma unroll
     for (int e = 0; e < K; ++e) {
       const bool kb = (keep >> e) & 1u;
@@ -422,14 +453,16 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     acc[C_CNT] = run_c;
     acc[C_SUM] = run_s;
     acc[C_NOUT] = (double)written;
+    acc[C_CNTI] = run_ci;
+    acc[C_SUMI] = run_si;
     A.cnt[1][rid] = (int32_t)written;
   } else {
-    acc[C_CNT] = acc[C_SUM] = acc[C_NOUT] = 0.0;
+    acc[C_CNT] = acc[C_SUM] = acc[C_NOUT] = acc[C_CNTI] = acc[C_SUMI] = 0.0;
   }
   acc[C_BAD] = (badacc == TIn(0)) ? 0.0 : 1.0;
   acc[C_ABS] = abs_sum;
-  const double vmax = (double)vmx;
-  block_reduce<C_NSUM, 1, 1, kBlock>(acc, &lam_min, &vmax, lds, tot);
+  const double vmax[2] = {(double)vmx, (double)vmxI};
+  block_reduce<C_NSUM, 1, 2, kBlock>(acc, &lam_min, vmax, lds, tot);
   if (threadIdx.x == 0) write_partial(A.partials, tot, C_NPART);
 }
 
@@ -673,9 +706,10 @@ __global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, in
   __shared__ double tot[C_NPART];
   __shared__ int offl[kRBlock / kWave + 1];
   __shared__ TailGo f;
-  reduce_partials<C_NSUM, 1, 1, kRBlock>(A.partials, G, lds, tot);
+  reduce_partials<C_NSUM, 1, 2, kRBlock>(A.partials, G, lds, tot);
   SpxState s;
   if (threadIdx.x == 0) {
+    double lam_w = __builtin_nan("");
     s = *st;
     s.passes += 1;
     s.sum_abs = tot[C_ABS];
@@ -688,19 +722,50 @@ __global__ __launch_bounds__(kRBlock) void spx_condat_merge_kernel(SpxArgs A, in
       spx_finish(&s, 0.0, 5);
     } else {
       const double m = tot[C_CNT];
-      double lam0 = (m > 0.0) ? (s.r - tot[C_SUM]) / m : 0.0;
-      lam0 = fmin(lam0, tot[C_NSUM]);
-      s.lam = lam0;
-      s.lam0 = lam0;
+      const double wb = tot[C_NSUM];  // the smallest bound a wave found
+      const double vmaxI = tot[C_NSUM + 2];
       s.n_init = (int64_t)tot[C_NOUT];
-      s.hi = lam0;
-      s.src = 2;  // the survivors sit in buffer 1, same regions as y
+      s.src = 2;  // the survivors sit in buffer 1, one region per wave
       s.n_src = (int64_t)tot[C_NOUT];
-      s.compact_next = (s.compaction != CQK_COMPACT_OFF) ? 1 : 0;
-      s.tail = (s.n_src <= s.tail_cap) ? kTailPack : kTailNone;
-      s.multi = s.tail ? 0 : 1;
+      // lam_J of the union of the kept sets, and the smallest wave bound
+      double lam0 = fmin((m > 0.0) ? (s.r - tot[C_SUM]) / m : wb, wb);
+      if (s.warm && !(vmaxI > -inf_d())) {
+        // warm start with an empty support: the fallback of Section 3.1,
+        // lam_0 = max{r/n, -max v}.  It is not known to be >= lam*, so
+        // Algorithm 4 starts from it as from the formula start (its first
+        // step decides the side, compaction follows).  The buffer lost only
+        // values below a lam_J, zero at the solution: the reduced problem
+        // has the same multiplier.
+        lam_w = fmax(s.r / (double)A.n, -s.vmax);
+        s.lam = lam_w;
+        s.lam0 = lam_w;
+        s.first_done = 1;
+        s.need_safeguard = 0;
+        s.compact_next = 0;
+        s.multi = 0;
+        s.tail = kTailNone;
+      } else {
+        if (s.warm) {
+          // the estimate's lam_J: over the kept values of I (every value of
+          // I above lam* is kept), or, if none was kept, over I's largest
+          // value alone (Algorithm 2's first set).  Every candidate is an
+          // upper bound of lam*; the smallest one starts Algorithm 4.
+          lam_w = s.r - vmaxI;
+          if (tot[C_CNTI] > 0.0) lam_w = fmin(lam_w, (s.r - tot[C_SUMI]) / tot[C_CNTI]);
+          lam0 = fmin(lam0, lam_w);
+        }
+        s.lam = lam0;
+        s.lam0 = lam0;
+        s.hi = lam0;
+        s.compact_next = (s.compaction != CQK_COMPACT_OFF) ? 1 : 0;
+        s.tail = (s.n_src <= s.tail_cap) ? kTailPack : kTailNone;
+        s.multi = s.tail ? 0 : 1;
+      }
     }
-    spx_trace(&s, A.trace, 0, 1, 0, s.lam, tot[C_SUM], tot[C_CNT], A.n, (int64_t)tot[C_NOUT]);
+    // a warm start records the estimate's own lam_J (NaN without one) and
+    // the count of I's kept values in place of the union's sum and count
+    spx_trace(&s, A.trace, 0, 1, 0, s.lam, s.warm ? lam_w : tot[C_SUM],
+              s.warm ? tot[C_CNTI] : tot[C_CNT], A.n, (int64_t)tot[C_NOUT]);
     *st = s;
     tail_flags(&f, s, false);
   }
@@ -1228,8 +1293,8 @@ int grid0(int64_t n, int num_cus) {
 }
 
 template <typename TIn, typename TA>
-cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, bool l1,
-                       const cqk_opts& o, cqk_info* info) {
+cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, double r, TIn* x,
+                       bool l1, const cqk_opts& o, cqk_info* info) {
   if (n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
   constexpr int64_t CAP = kTailBytes / (int64_t)sizeof(TIn);
   // G0 blocks of kWaves waves.  Passes over y hand out tiles of at most
@@ -1244,8 +1309,11 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   const int64_t chunk0 = tpw * kT * kWaves;
   const int G0 = (int)std::max<int64_t>(1, (n + chunk0 - 1) / chunk0);
   const int NR = G0 * kWaves;
-  const bool condat = o.lambda0_mode == CQK_LAMBDA0_CONDAT;
-  const bool formula = o.lambda0_mode == CQK_LAMBDA0_FORMULA;
+  // a warm start runs Algorithm 2 over the estimate's support, whatever the
+  // start option says
+  const bool warm = xw != nullptr;
+  const bool condat = warm || o.lambda0_mode == CQK_LAMBDA0_CONDAT;
+  const bool formula = !warm && o.lambda0_mode == CQK_LAMBDA0_FORMULA;
 
   const size_t part_bytes =
       ((size_t)G0 * (kPassRec + 2 * kCand) * sizeof(double) + 255) / 256 * 256;
@@ -1268,6 +1336,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
   char* ws = (char*)ctx->ws.ptr;
   SpxArgs A{};
   A.y = y;
+  A.xw = xw;
   A.x = x;
   A.n = n;
   A.chunk0 = chunk0;
@@ -1289,7 +1358,8 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
 
   const double eps = sizeof(TA) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   SpxState init{};
-  init.lam = (o.lambda0_mode == CQK_LAMBDA0_USER) ? o.lambda0_user : 0.0;
+  init.lam = (!warm && o.lambda0_mode == CQK_LAMBDA0_USER) ? o.lambda0_user : 0.0;
+  init.warm = warm ? 1 : 0;
   init.lam0 = init.lam;
   init.lam_prev = init.lam_final = __builtin_nan("");
   init.r = r;
@@ -1361,7 +1431,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
     if (wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
   } else {
     if (condat) {
-      launch(spx_condat_kernel<TIn, TA>, G0);
+      if (warm)
+        launch(spx_condat_kernel<TIn, TA, true>, G0);
+      else
+        launch(spx_condat_kernel<TIn, TA, false>, G0);
       reduce(spx_condat_merge_kernel<TIn, TA>, G0);
     } else if (formula) {
       launch(spx_formula_kernel<TIn>, G0);
@@ -1431,8 +1504,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
       const double per_out = (double)sizeof(TIn) + 4.0;
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
-      // the Algorithm 2 kernel also writes x = 0 everywhere
-      if (t.kind == 0 && t.source == 0 && t.compacted) info->pass_bytes += sizeof(TIn) * (double)t.n_in;
+      // the Algorithm 2 kernel also writes x = 0 everywhere (and reads the
+      // estimate of a warm start)
+      if (t.kind == 0 && t.source == 0 && t.compacted)
+        info->pass_bytes += sizeof(TIn) * (double)t.n_in * (warm ? 2.0 : 1.0);
     }
     if (o.timing) {
       // every grid pass launched (those after the loop stopped return at
@@ -1454,15 +1529,15 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, double r, TIn* x, 
 
 }  // namespace
 
-cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x, bool l1,
-                           const cqk_opts& o, cqk_info* info) {
-  if (o.accum == CQK_ACCUM_F32) return run_simplex<float, float>(ctx, n, y, r, x, l1, o, info);
-  return run_simplex<float, double>(ctx, n, y, r, x, l1, o, info);
+cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, double r,
+                           float* x, bool l1, const cqk_opts& o, cqk_info* info) {
+  if (o.accum == CQK_ACCUM_F32) return run_simplex<float, float>(ctx, n, y, xw, r, x, l1, o, info);
+  return run_simplex<float, double>(ctx, n, y, xw, r, x, l1, o, info);
 }
 
-cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r, double* x,
-                           bool l1, const cqk_opts& o, cqk_info* info) {
-  return run_simplex<double, double>(ctx, n, y, r, x, l1, o, info);
+cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw, double r,
+                           double* x, bool l1, const cqk_opts& o, cqk_info* info) {
+  return run_simplex<double, double>(ctx, n, y, xw, r, x, l1, o, info);
 }
 
 }  // namespace cqk

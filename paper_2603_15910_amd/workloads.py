@@ -19,6 +19,10 @@ Section 5.2.1 for the simplex):
                       not say whether 1e-3 is a variance or a deviation; it is
                       used as the deviation here); redrawn if any y_i == 0.
 * ``segment_offsets`` row lengths round(exp(U[ln lo, ln hi])) (log-uniform).
+* ``perturbed``       v + eps * std(v) * N(0,1), the next point of an outer
+                      loop whose previous projection serves as a warm start
+                      (Section 3.1): for CQK only a is perturbed,
+                      so r stays feasible.
 """
 from __future__ import annotations
 
@@ -113,3 +117,18 @@ def batched_simplex_input(nseg: int, lo: int, hi: int, seed: int, scale: float =
 
 def upstream_grad(n: int, seed: int, dtype=np.float32):
     return _rng(seed + 104729).standard_normal(n).astype(dtype)
+
+
+def perturbed(v, seed: int, eps: float = 1e-3):
+    """v + eps * std(v) * N(0,1), in v's dtype."""
+    v = np.asarray(v)
+    g = _rng(seed + 15485863)
+    sd = float(np.std(v.astype(np.float64))) if v.size else 0.0
+    return (v.astype(np.float64) + eps * sd * g.standard_normal(v.size)).astype(v.dtype)
+
+
+def cqk_perturbed(inst: dict, seed: int, eps: float = 1e-3) -> dict:
+    """The instance with a replaced by perturbed(a, seed, eps)."""
+    out = dict(inst)
+    out["a"] = perturbed(inst["a"], seed, eps)
+    return out

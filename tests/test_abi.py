@@ -63,6 +63,14 @@ def test_host_side_argument_errors(lib):
     assert lib.cqk_solve_f64(null, 10, null, null, null, null, null, 1.0, null, None, None) == 2
     assert lib.cqk_project_simplex_f32(null, 10, null, 1.0, null, None, None) == 2
     assert lib.cqk_project_l1_f64(null, 10, null, 1.0, null, None, None) == 2
+    assert lib.cqk_solve_warm_f64(null, 10, null, null, null, null, null, null, 1.0, null, None,
+                                  None) == 2
+    assert lib.cqk_solve_warm_f32(null, 10, null, null, null, null, null, null, 1.0, null, None,
+                                  None) == 2
+    assert lib.cqk_project_simplex_warm_f32(null, 10, null, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_simplex_warm_f64(null, 10, null, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_l1_warm_f32(null, 10, null, null, 1.0, null, None, None) == 2
+    assert lib.cqk_project_l1_warm_f64(null, 10, null, null, 1.0, null, None, None) == 2
     assert lib.cqk_project_simplex_batched_f32(null, 4, null, null, null, 1.0, null, null, null,
                                                None, None) == 2
     assert lib.cqk_create(None, None) == 2
