@@ -8,9 +8,9 @@ launch time from HIP events stamped by its dispatches in the timed region,
 against 8 TB/s, and the measured HBM traffic per launch when the committed
 counter summary matches the kernel source), the oracle's CPU rate on a 1e7
 sample, and "extras": the other workloads (correlated CQK, simplex and l1 at
-n = 1e8, warm starts from a previous solution, batched and differentiable
-batched projections) on the same GPU,
-each checked for its status.
+n = 1e8 with dense and sparse output, warm starts from a previous solution,
+batched and differentiable batched projections) on the same GPU, each
+checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
                     [--no-cpu-baseline] [--no-extras] [--calibrate-copy]
@@ -211,6 +211,18 @@ def extra_simplex(ctx, dev, torch):
                     "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
                     "n_after_init": info["n_after_init"], "status": info["status_name"],
                     "gbs_total": (info["pass_bytes"] + info["finalize_bytes"]) / (ms * 1e-3) / 1e9}
+        # the same projection returned as its support (no dense x written)
+        out = (torch.empty(1 << 20, dtype=torch.int64, device=dev),
+               torch.empty(1 << 20, dtype=torch.float32, device=dev))
+        for kind, fn in (("simplex", ctx.project_simplex_sparse), ("l1", ctx.project_l1_sparse)):
+            fn(y, 1.0, out=out)
+            ms = timed(lambda: fn(y, 1.0, out=out), 5, sync)
+            _, _, info = fn(y, 1.0, out=out, timing=True)
+            ex[f"{kind}_{dist}_1e8_f32in_f64acc_condat_sparse"] = {
+                "ms": ms, "elements_per_s": n / (ms * 1e-3), "iterations": info["iterations"],
+                "nnz": info["nnz"], "status": info["status_name"],
+                "output_ms": info["finalize_ms"]}
+        del out
         # l1 ball of radius 1 (on U[0,1] input this is the simplex problem)
         for start in ("condat", "zero"):
             for accum in ("f64", "f32"):

@@ -48,7 +48,9 @@ typedef enum cqk_status {
   CQK_INVALID_ARG = 2,    /* bad argument or input data (see each call) */
   CQK_NOT_CONVERGED = 3,  /* max_iter reached; x = x(lam_last) written */
   CQK_DEVICE_ERROR = 4,   /* a HIP runtime call failed */
-  CQK_NO_MEMORY = 5       /* workspace allocation failed */
+  CQK_NO_MEMORY = 5,      /* workspace allocation failed */
+  CQK_BUFFER_TOO_SMALL = 6  /* sparse output: the support exceeds the
+                               capacity; nothing written, count returned */
 } cqk_status;
 
 /* Initial multiplier (Section 2.1 eq. (CQKlambda0); Section 3.1 Alg. 2). */
@@ -216,6 +218,36 @@ cqk_status cqk_project_l1_warm_f32(cqk_ctx* ctx, int64_t n, const float* y, cons
 cqk_status cqk_project_l1_warm_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xbar,
                                    double radius, double* x, const cqk_opts* opts,
                                    cqk_info* info);
+
+/* Sparse output of the simplex / l1 projections (Sec. 5.2: the support of x
+ * returned as (index, value) pairs instead of a dense x, so no n-sized
+ * write).  The support S = {i : x_i != 0} is written in ascending index
+ * order: idx[k] (DEVICE int64) and val[k] (DEVICE, the type of y) for
+ * k < |S|; *nnz (HOST, may be NULL) receives |S|.  No dense x is written at
+ * any point (the start pass's zero fill is skipped).
+ * xbar: NULL for the cold start opts->lambda0_mode chooses, else a warm-start
+ * estimate as in the _warm calls.
+ * cap: entries idx and val hold.  BUFFER_TOO_SMALL: |S| > cap; nothing is
+ * written to idx / val and *nnz holds |S| (cap = 0 with NULL idx / val only
+ * counts).  INVALID_ARG: the cold calls' cases, cap < 0, idx or val NULL
+ * with cap > 0, or idx, val and y overlapping.  y inside the l1 ball gives
+ * S = {y_i != 0} and val = y there; r = 0 gives S empty.
+ * The context keeps a bitmap of n bits (n/8 bytes) for these calls. */
+cqk_status cqk_project_simplex_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y,
+                                          const float* xbar, double r, int64_t cap,
+                                          int64_t* idx, float* val, int64_t* nnz,
+                                          const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_simplex_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                          const double* xbar, double r, int64_t cap,
+                                          int64_t* idx, double* val, int64_t* nnz,
+                                          const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_l1_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
+                                     double radius, int64_t cap, int64_t* idx, float* val,
+                                     int64_t* nnz, const cqk_opts* opts, cqk_info* info);
+cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                     const double* xbar, double radius, int64_t cap,
+                                     int64_t* idx, double* val, int64_t* nnz,
+                                     const cqk_opts* opts, cqk_info* info);
 
 /* Many simplex projections in one launch: row s is y[offsets[s] ..
  * offsets[s+1]) (Section 3 Algorithms 2 and 4 applied per row).

@@ -20,15 +20,15 @@ import ctypes as C
 import threading
 
 from . import _lib as L
-from ._lib import (CQK_DEVICE_ERROR, CQK_INFEASIBLE, CQK_INVALID_ARG, CQK_NO_MEMORY,
-                   CQK_NOT_CONVERGED, CQK_OK, STATUS_NAMES, CqkLibraryMissing, cqk_info,
-                   cqk_opts, cqk_trace_rec)
+from ._lib import (CQK_BUFFER_TOO_SMALL, CQK_DEVICE_ERROR, CQK_INFEASIBLE, CQK_INVALID_ARG,
+                   CQK_NO_MEMORY, CQK_NOT_CONVERGED, CQK_OK, STATUS_NAMES, CqkLibraryMissing,
+                   cqk_info, cqk_opts, cqk_trace_rec)
 
 __all__ = [
     "CQK_OK", "CQK_INFEASIBLE", "CQK_INVALID_ARG", "CQK_NOT_CONVERGED", "CQK_DEVICE_ERROR",
-    "CQK_NO_MEMORY", "CqkError", "CqkLibraryMissing", "Context", "solve", "project_simplex",
-    "project_l1", "project_simplex_batched", "project_simplex_batched_backward",
-    "SimplexProjection", "lib",
+    "CQK_NO_MEMORY", "CQK_BUFFER_TOO_SMALL", "CqkError", "CqkLibraryMissing", "Context", "solve",
+    "project_simplex", "project_l1", "project_simplex_sparse", "project_l1_sparse",
+    "project_simplex_batched", "project_simplex_batched_backward", "SimplexProjection", "lib",
 ]
 
 
@@ -152,6 +152,35 @@ def cqk_project_l1_warm_f32(ctx, n, y, xbar, radius, x, opts=None, info=None):
 def cqk_project_l1_warm_f64(ctx, n, y, xbar, radius, x, opts=None, info=None):
     return _call("cqk_project_l1_warm_f64", C.c_void_p(ctx), n, y, xbar, radius, x,
                  _ref(opts), _ref(info))
+
+
+def _sparse(name, ctx, n, y, xbar, r, cap, idx, val, opts, info):
+    nnz = C.c_int64(0)
+    st = _call(name, C.c_void_p(ctx), n, y, xbar, r, cap, idx, val, C.byref(nnz), _ref(opts),
+               _ref(info))
+    return st, nnz.value
+
+
+def cqk_project_simplex_sparse_f32(ctx, n, y, xbar, r, cap, idx, val, opts=None, info=None):
+    """Returns (status, nnz)."""
+    return _sparse("cqk_project_simplex_sparse_f32", ctx, n, y, xbar, r, cap, idx, val, opts, info)
+
+
+def cqk_project_simplex_sparse_f64(ctx, n, y, xbar, r, cap, idx, val, opts=None, info=None):
+    """Returns (status, nnz)."""
+    return _sparse("cqk_project_simplex_sparse_f64", ctx, n, y, xbar, r, cap, idx, val, opts, info)
+
+
+def cqk_project_l1_sparse_f32(ctx, n, y, xbar, radius, cap, idx, val, opts=None, info=None):
+    """Returns (status, nnz)."""
+    return _sparse("cqk_project_l1_sparse_f32", ctx, n, y, xbar, radius, cap, idx, val, opts,
+                   info)
+
+
+def cqk_project_l1_sparse_f64(ctx, n, y, xbar, radius, cap, idx, val, opts=None, info=None):
+    """Returns (status, nnz)."""
+    return _sparse("cqk_project_l1_sparse_f64", ctx, n, y, xbar, radius, cap, idx, val, opts,
+                   info)
 
 
 def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out=None,
@@ -329,6 +358,60 @@ class Context:
         return self._project(cqk_project_l1_f64, cqk_project_l1_f32, y, radius, out, check, kw,
                              xbar, (cqk_project_l1_warm_f64, cqk_project_l1_warm_f32))
 
+    def _project_sparse(self, names, y, r, cap, xbar, check, kw, out=None):
+        torch = _torch()
+        dt = y.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("projection takes float64 or float32 tensors")
+        n = y.numel()
+        py = _dev_ptr(y, dt, "y")
+        pw = None
+        if xbar is not None:
+            pw = _dev_ptr(xbar, dt, "xbar")
+            if xbar.numel() != n:
+                raise ValueError("xbar must have as many elements as y")
+        fn = names[0] if dt == torch.float64 else names[1]
+        opts = make_opts(simplex=True, **kw)
+        info = cqk_info()
+        self._bind_stream()
+        if out is not None:
+            idx, val = out
+            _dev_ptr(idx, torch.int64, "out[0]")
+            _dev_ptr(val, dt, "out[1]")
+            cap = min(idx.numel(), val.numel())
+        else:
+            cap = min(n, 1 << 16) if cap is None else int(cap)
+        for attempt in range(2):
+            if out is None or attempt == 1:
+                idx = torch.empty(max(cap, 1), dtype=torch.int64, device=y.device)
+                val = torch.empty(max(cap, 1), dtype=dt, device=y.device)
+            st, nnz = fn(self.handle, n, py, pw, float(r), cap, idx.data_ptr(), val.data_ptr(),
+                         opts, info)
+            if st != CQK_BUFFER_TOO_SMALL or attempt == 1:
+                break
+            cap = nnz   # the support is known now: solve once more into room for it
+        self.last_info = info.as_dict()
+        self.last_info["nnz"] = nnz
+        if check and st != CQK_OK:
+            raise CqkError(st, fn.__name__)
+        return idx[:nnz], val[:nnz], self.last_info
+
+    def project_simplex_sparse(self, y, r=1.0, cap=None, xbar=None, check=True, out=None, **kw):
+        """Projection onto the r-simplex returned as its support: (indices
+        ascending, int64; values; info).  cap: room for the support (default
+        min(n, 65536); a larger support is solved once more with room for
+        it).  out: (int64 tensor, value tensor) to write into instead, the
+        room being their size.  xbar: a warm-start estimate."""
+        return self._project_sparse((cqk_project_simplex_sparse_f64,
+                                     cqk_project_simplex_sparse_f32), y, r, cap, xbar, check, kw,
+                                    out)
+
+    def project_l1_sparse(self, y, radius=1.0, cap=None, xbar=None, check=True, out=None, **kw):
+        """Projection onto the l1 ball returned as its support (see
+        project_simplex_sparse)."""
+        return self._project_sparse((cqk_project_l1_sparse_f64, cqk_project_l1_sparse_f32), y,
+                                    radius, cap, xbar, check, kw, out)
+
     def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
                                 nfree_out=None, check=True, **kw):
         torch = _torch()
@@ -444,6 +527,14 @@ def project_simplex(y, r=1.0, **kw):
 
 def project_l1(y, radius=1.0, **kw):
     return default_context(y.device).project_l1(y, radius, **kw)
+
+
+def project_simplex_sparse(y, r=1.0, **kw):
+    return default_context(y.device).project_simplex_sparse(y, r, **kw)
+
+
+def project_l1_sparse(y, radius=1.0, **kw):
+    return default_context(y.device).project_l1_sparse(y, radius, **kw)
 
 
 def project_simplex_batched(y, offsets, r=1.0, **kw):

@@ -17,8 +17,9 @@ CQK_INVALID_ARG = 2
 CQK_NOT_CONVERGED = 3
 CQK_DEVICE_ERROR = 4
 CQK_NO_MEMORY = 5
+CQK_BUFFER_TOO_SMALL = 6
 STATUS_NAMES = {0: "OK", 1: "INFEASIBLE", 2: "INVALID_ARG", 3: "NOT_CONVERGED",
-                4: "DEVICE_ERROR", 5: "NO_MEMORY"}
+                4: "DEVICE_ERROR", 5: "NO_MEMORY", 6: "BUFFER_TOO_SMALL"}
 
 LAMBDA0 = {"zero": 0, "formula": 1, "condat": 2, "user": 3}
 COMPACTION = {"off": 0, "auto": 1, "always": 2}
@@ -124,6 +125,12 @@ SIGNATURES = {
     "cqk_project_simplex_f64": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_l1_f32": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_l1_f64": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),
+    "cqk_project_simplex_sparse_f32": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS,
+                                                 _INFO]),
+    "cqk_project_simplex_sparse_f64": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS,
+                                                 _INFO]),
+    "cqk_project_l1_sparse_f32": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS, _INFO]),
+    "cqk_project_l1_sparse_f64": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS, _INFO]),
     "cqk_solve_warm_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_warm_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),

@@ -90,6 +90,12 @@ bool overlaps(const T* p, const T* q, int64_t n) {
   return a < b + len && b < a + len;
 }
 
+// true if [p, p + pb) and [q, q + qb) share any byte
+bool overlaps_bytes(const void* p, size_t pb, const void* q, size_t qb) {
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+  return pb > 0 && qb > 0 && a < b + qb && b < a + pb;
+}
+
 void info_trivial(cqk_info* info, int status, double lam) {
   if (!info) return;
   std::memset(info, 0, sizeof(*info));
@@ -126,7 +132,8 @@ cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T
 
 template <typename T>
 cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xw, bool warm, double r,
-                          T* x, bool l1, const cqk_opts* opts, cqk_info* info) {
+                          T* x, bool l1, const cqk_opts* opts, cqk_info* info,
+                          SparseOut* sp = nullptr) {
   if (!ctx || n < 0 || !std::isfinite(r) || r < 0.0) return CQK_INVALID_ARG;
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, true);
@@ -134,19 +141,38 @@ cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xw, bool
   if (n == 0) {
     const int s = (r == 0.0 || l1) ? CQK_OK : CQK_INFEASIBLE;
     info_trivial(info, s, 0.0);
+    if (sp) sp->nnz = 0;
     return (cqk_status)s;
   }
-  if (!y || !x) return CQK_INVALID_ARG;
-  if (warm && (!xw || overlaps(xw, (const T*)x, n))) return CQK_INVALID_ARG;
+  if (!y || (!x && !sp)) return CQK_INVALID_ARG;
+  if (warm && (!xw || (x && overlaps(xw, (const T*)x, n)))) return CQK_INVALID_ARG;
+  if (sp) {
+    if (sp->cap < 0 || (sp->cap > 0 && (!sp->idx || !sp->val))) return CQK_INVALID_ARG;
+    const size_t yb = (size_t)n * sizeof(T), ib = (size_t)sp->cap * 8, vb = (size_t)sp->cap * sizeof(T);
+    if (overlaps_bytes(sp->idx, ib, y, yb) || overlaps_bytes(sp->val, vb, y, yb) ||
+        overlaps_bytes(sp->idx, ib, sp->val, vb))
+      return CQK_INVALID_ARG;
+  }
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
-    st = run_simplex_f64(ctx, n, y, xw, r, x, l1, o, inf);
+    st = run_simplex_f64(ctx, n, y, xw, sp, r, x, l1, o, inf);
   else
-    st = run_simplex_f32(ctx, n, y, xw, r, x, l1, o, inf);
+    st = run_simplex_f32(ctx, n, y, xw, sp, r, x, l1, o, inf);
   if (st != CQK_OK) return st;
   return (cqk_status)inf->status;
+}
+
+template <typename T>
+cqk_status sparse_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xbar, double r,
+                         int64_t cap, int64_t* idx, T* val, int64_t* nnz, bool l1,
+                         const cqk_opts* opts, cqk_info* info) {
+  SparseOut sp{idx, val, cap, 0};
+  const cqk_status st =
+      simplex_common<T>(ctx, n, y, xbar, xbar != nullptr, r, nullptr, l1, opts, info, &sp);
+  if (nnz) *nnz = sp.nnz;
+  return st;
 }
 
 }  // namespace
@@ -182,6 +208,7 @@ void cqk_destroy(cqk_ctx* ctx) {
   else hipDeviceSynchronize();
   if (ctx->ws.ptr) hipFree(ctx->ws.ptr);
   if (ctx->state.ptr) hipFree(ctx->state.ptr);
+  if (ctx->bitmap.ptr) hipFree(ctx->bitmap.ptr);
   if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->events) hipEventDestroy(e);
   delete ctx;
@@ -215,6 +242,7 @@ const char* cqk_status_string(int32_t s) {
     case CQK_NOT_CONVERGED: return "CQK_NOT_CONVERGED";
     case CQK_DEVICE_ERROR: return "CQK_DEVICE_ERROR";
     case CQK_NO_MEMORY: return "CQK_NO_MEMORY";
+    case CQK_BUFFER_TOO_SMALL: return "CQK_BUFFER_TOO_SMALL";
     default: return "CQK_UNKNOWN_STATUS";
   }
 }
@@ -299,6 +327,33 @@ cqk_status cqk_project_l1_warm_f64(cqk_ctx* ctx, int64_t n, const double* y, con
                                    double radius, double* x, const cqk_opts* opts,
                                    cqk_info* info) {
   return simplex_common<double>(ctx, n, y, xbar, true, radius, x, true, opts, info);
+}
+
+cqk_status cqk_project_simplex_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y,
+                                          const float* xbar, double r, int64_t cap,
+                                          int64_t* idx, float* val, int64_t* nnz,
+                                          const cqk_opts* opts, cqk_info* info) {
+  return sparse_common<float>(ctx, n, y, xbar, r, cap, idx, val, nnz, false, opts, info);
+}
+
+cqk_status cqk_project_simplex_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                          const double* xbar, double r, int64_t cap,
+                                          int64_t* idx, double* val, int64_t* nnz,
+                                          const cqk_opts* opts, cqk_info* info) {
+  return sparse_common<double>(ctx, n, y, xbar, r, cap, idx, val, nnz, false, opts, info);
+}
+
+cqk_status cqk_project_l1_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
+                                     double radius, int64_t cap, int64_t* idx, float* val,
+                                     int64_t* nnz, const cqk_opts* opts, cqk_info* info) {
+  return sparse_common<float>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
+}
+
+cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
+                                     const double* xbar, double radius, int64_t cap,
+                                     int64_t* idx, double* val, int64_t* nnz,
+                                     const cqk_opts* opts, cqk_info* info) {
+  return sparse_common<double>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
 }
 
 cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,

@@ -52,12 +52,24 @@ struct SpxState {
   double res_P;                   // finalize: sum of x (l1: sum |x|)
   double cm_prev;
   int64_t n_src, n_init, n_free, tail_cap, chunk_src;
+  int64_t nnz;                    // sparse output: entries of the support
   int32_t status, iter, passes, src, compact_next, stop_reason, max_iter;
   int32_t compaction, trace_cap, ntrace, l1, fin_mode, need_safeguard, first_done;
   int32_t tail;                   // 1: the remaining iterations run in one block
   int32_t multi;                  // 1: the next pass refines the start (candidates)
   int32_t x_zeroed;               // 1: the start already wrote x = 0 everywhere
-  int32_t warm;                   // 1: Algorithm 2 ran over the estimate's support
+  int32_t warm;                   // 1: a warm start (the start pass also reads xbar)
+  int32_t sp_over;                // sparse output: the support exceeded the capacity
+  int32_t pad_[1];
+};
+
+// Sparse output of a simplex / l1 projection: the support in ascending index
+// order, as (index, value) pairs in caller memory of `cap` entries.
+struct SparseOut {
+  int64_t* idx;
+  void* val;
+  int64_t cap;
+  int64_t nnz;   // set on return
 };
 
 // How the simplex finalize writes x.
@@ -80,6 +92,8 @@ struct cqk_ctx {
   hipStream_t stream = nullptr;
   cqk::DeviceBuf ws;          // compaction buffers, partials, per-block counts
   cqk::DeviceBuf state;       // run-state records + trace ring
+  cqk::DeviceBuf bitmap;      // sparse output: one bit per index, zero between calls
+  bool bitmap_clean = false;  // the bitmap is known to be all zero
   void* host_pinned = nullptr;  // pinned mirror of the state + trace
   size_t host_pinned_bytes = 0;
   std::vector<hipEvent_t> events;
@@ -114,10 +128,13 @@ cqk_status run_general_f64(cqk_ctx* ctx, int64_t n, const double* d, const doubl
 cqk_status run_general_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
                            const float* b, const float* l, const float* u, const float* xw,
                            double r, float* x, const cqk_opts& o, cqk_info* info);
-cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, double r,
-                           float* x, bool l1, const cqk_opts& o, cqk_info* info);
-cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw, double r,
-                           double* x, bool l1, const cqk_opts& o, cqk_info* info);
+// xw: warm-start estimate or null; sp: sparse output (x is then unused) or
+// null
+cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, SparseOut* sp,
+                           double r, float* x, bool l1, const cqk_opts& o, cqk_info* info);
+cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw,
+                           SparseOut* sp, double r, double* x, bool l1, const cqk_opts& o,
+                           cqk_info* info);
 cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                            const double* r, double r_scalar, float* x, double* lambda_out,
                            int32_t* nfree_out, const cqk_opts& o, cqk_info* info);

@@ -86,6 +86,14 @@ struct SpxArgs {
   double* partials;
   SpxState* st;
   cqk_trace_rec* trace;
+  // sparse output (x is null then)
+  uint32_t* bm;      // one bit per index, ceil(n/32) words
+  int64_t nwords;
+  int64_t sp_wpb;    // bitmap words per block of the count and write kernels
+  int32_t* sp_cnt;   // per block: set bits in its words
+  int64_t* sp_idx;   // caller's output: indices, values
+  void* sp_val;
+  int64_t sp_cap;
 };
 
 template <typename T>
@@ -307,8 +315,9 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       for (int e = 0; e < K; ++e) inI |= (l1 ? (xv[e] != TIn(0)) : (xv[e] > TIn(0))) ? (1u << e) : 0u;
     }
     // x_i = 0 for every index (survivors get their value from the scatter at
-    // the end), written while this kernel is busy with Algorithm 2 anyway
-    zero_tile<TIn, NL>(x, base, lane, count);
+    // the end), written while this kernel is busy with Algorithm 2 anyway;
+    // a sparse output has no x
+    if (x != nullptr) zero_tile<TIn, NL>(x, base, lane, count);
     TIn tmax = -(TIn)__builtin_huge_val();
     TIn tmaxI = -(TIn)__builtin_huge_val();
 #pragma unroll
@@ -1285,6 +1294,215 @@ __global__ __launch_bounds__(kRBlock) void spx_fin_reduce_kernel(SpxArgs A, int 
   }
 }
 
+// x_i from y_i and lam* (Sec. 1 (proj_Delta); l1: Lemma 1), or y_i itself when
+// y is inside the l1 ball.  FP32 data with FP64 accumulation forms y + lam in
+// FP64 and rounds once, as the dense finalize does.
+template <typename TIn, typename TA>
+__device__ __forceinline__ TIn spx_x_of(TIn yv, TA lam, bool l1, bool copy) {
+  if (copy) return yv;
+  const TA t = (TA)yv;
+  const TA z = (l1 ? absval(t) : t) + lam;
+  TA xv = z > TA(0) ? z : TA(0);
+  if (l1 && t < TA(0)) xv = -xv;
+  return (TIn)xv;
+}
+
+// Sparse output, first kernel: sets one bit per index whose x is non-zero in
+// a bitmap that is all zero on entry (the write kernel clears what it read).
+// The final set is read as the scatter reads it; its indices of one 32-bit
+// word may sit in the regions of different waves, hence an atomic OR.  When
+// x is a dense map of y (nothing was compacted, or y is inside the l1 ball)
+// y is read in wave tiles and each word is assembled from ballots and stored
+// whole.  Also the partial record of sum |x| and the count.
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kBlock) void spx_sp_mark_kernel(SpxArgs A) {
+  SpxState* st = A.st;
+  if (!spx_done(st)) return;
+  const int mode = spx_fin_mode(st);
+  const bool l1 = st->l1 != 0;
+  const TA lam = (TA)st->lam_final;
+  const int lane = threadIdx.x & (kWave - 1);
+  double acc[2] = {0.0, 0.0};
+  if (mode == kFinScatter) {
+    auto mark = [&](TIn yv, uint32_t ix) {
+      const TIn xo = spx_x_of<TIn, TA>(yv, lam, l1, false);
+      if (xo != TIn(0)) atomicOr(A.bm + (ix >> 5), 1u << (ix & 31u));
+      acc[0] += fabs((double)xo);
+      acc[1] += (xo != TIn(0)) ? 1.0 : 0.0;
+    };
+    if (st->src == 3) {
+      const TIn* y = (const TIn*)A.y;
+      const int64_t m = st->n_src;
+      for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m;
+           i += (int64_t)gridDim.x * kBlock) {
+        const uint32_t ix = A.tidx[i];
+        mark(y[ix], ix);
+      }
+    } else {
+      const int si = st->src - 1;
+      const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
+      const int64_t off = (int64_t)rid * (A.chunk0 / kWaves);
+      const int64_t count = A.cnt[si][rid];
+      const TIn* v = (const TIn*)A.val[si] + off;
+      const uint32_t* iv = A.idx[si] + off;
+      for (int64_t i = lane; i < count; i += kWave) mark(v[i], iv[i]);
+    }
+  } else if (mode != kFinZero) {
+    constexpr int V = VecWidth<TIn>::value;
+    constexpr int64_t T = (int64_t)kWave * V;  // values per wave tile
+    constexpr int LW = 32 / V;                 // lanes per bitmap word
+    constexpr int WPT = kWave / LW;            // words per wave tile
+    const bool copy = mode == kFinCopy;
+    const TIn* y = (const TIn*)A.y;
+    const int64_t n = A.n;
+    const int64_t ntiles = (n + T - 1) / T;
+    const int64_t nw = (int64_t)gridDim.x * kWaves;
+    for (int64_t t = (int64_t)blockIdx.x * kWaves + threadIdx.x / kWave; t < ntiles; t += nw) {
+      const int64_t i = t * T + (int64_t)lane * V;
+      TIn yv[V];
+      load_y<TIn>(y, i, n, yv);
+      uint64_t m[V];
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const TIn xo = spx_x_of<TIn, TA>(yv[k], lam, l1, copy);
+        const bool nz = (i + k < n) && xo != TIn(0);
+        acc[0] += nz ? fabs((double)xo) : 0.0;
+        acc[1] += nz ? 1.0 : 0.0;
+        m[k] = __ballot(nz);
+      }
+      // word j of the tile: lanes j*LW .. j*LW+LW-1, value k of lane
+      // j*LW + q at bit q*V + k
+      if (lane < WPT) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int q = 0; q < LW; ++q)
+#pragma unroll
+          for (int k = 0; k < V; ++k)
+            w |= (uint32_t)((m[k] >> (lane * LW + q)) & 1u) << (q * V + k);
+        const int64_t wi = t * WPT + lane;
+        if (wi < A.nwords) A.bm[wi] = w;
+      }
+    }
+  }
+  __shared__ double lds[2 * (kBlock / kWave)];
+  __shared__ double tot[2];
+  block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, 2);
+}
+
+// The count and write kernels give each thread kSpWords consecutive bitmap
+// words per step (four 16-byte loads); a block covers sp_wpb words, a
+// multiple of kSpStep.
+constexpr int kSpWords = 16;
+constexpr int64_t kSpStep = (int64_t)kBlock * kSpWords;
+
+// The thread's kSpWords words at w (zero beyond w1); w is a multiple of 16
+// and the bitmap 256-byte aligned.
+__device__ __forceinline__ void sp_load_words(const uint32_t* bm, int64_t w, int64_t w1,
+                                              uint32_t* o) {
+  if (w + kSpWords <= w1) {
+#pragma unroll
+    for (int q = 0; q < kSpWords / 4; ++q) {
+      const int4v v = *reinterpret_cast<const int4v*>(bm + w + 4 * q);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) o[4 * q + j] = (uint32_t)v[j];
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kSpWords; ++j) o[j] = (w + j < w1) ? bm[w + j] : 0u;
+  }
+}
+
+// Sparse output, second kernel: set bits per block of sp_wpb bitmap words.
+__global__ __launch_bounds__(kBlock) void spx_sp_count_kernel(SpxArgs A) {
+  SpxState* st = A.st;
+  if (!spx_done(st) || spx_fin_mode(st) == kFinZero) return;
+  const int64_t w0 = (int64_t)blockIdx.x * A.sp_wpb;
+  const int64_t w1 = min(w0 + A.sp_wpb, A.nwords);
+  int c = 0;
+  for (int64_t w = w0 + (int64_t)threadIdx.x * kSpWords; w < w1; w += kSpStep) {
+    uint32_t b[kSpWords];
+    sp_load_words(A.bm, w, w1, b);
+#pragma unroll
+    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j]);
+  }
+  __shared__ int lds_i[kBlock / kWave + 1];
+  int total = 0;
+  block_excl_scan<kBlock>(c, lds_i, &total);
+  if (threadIdx.x == 0) A.sp_cnt[blockIdx.x] = total;
+}
+
+// Sparse output, last kernel: each block places the set bits of its words at
+// its offset (the counts of the blocks before it) in ascending index order,
+// with x_i recomputed from y_i, and clears the words it read.  If the support
+// exceeds the caller's capacity nothing is written (the count is still
+// returned).
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kBlock) void spx_sp_write_kernel(SpxArgs A, int GS) {
+  SpxState* st = A.st;
+  if (!spx_done(st)) return;
+  const int mode = spx_fin_mode(st);
+  if (mode == kFinZero) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->nnz = 0;
+    return;
+  }
+  double acc[2] = {0.0, 0.0};  // entries before this block, all entries
+  for (int b = threadIdx.x; b < GS; b += kBlock) {
+    const double c = (double)A.sp_cnt[b];
+    acc[0] += (b < (int)blockIdx.x) ? c : 0.0;
+    acc[1] += c;
+  }
+  __shared__ double lds[2 * (kBlock / kWave)];
+  __shared__ double tot[2];
+  __shared__ int lds_i[kBlock / kWave + 1];
+  block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, lds, tot);
+  const int64_t before = (int64_t)tot[0];
+  const int64_t total = (int64_t)tot[1];
+  const bool over = total > A.sp_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st->nnz = total;
+    st->sp_over = over ? 1 : 0;
+  }
+  const bool l1 = st->l1 != 0;
+  const bool copy = mode == kFinCopy;
+  const TA lam = (TA)st->lam_final;
+  const TIn* y = (const TIn*)A.y;
+  TIn* ov = (TIn*)A.sp_val;
+  const int64_t w0 = (int64_t)blockIdx.x * A.sp_wpb;
+  const int64_t w1 = min(w0 + A.sp_wpb, A.nwords);
+  int64_t pos = before;
+  for (int64_t ws = w0; ws < w1; ws += kSpStep) {
+    const int64_t w = ws + (int64_t)threadIdx.x * kSpWords;
+    uint32_t b[kSpWords];
+    sp_load_words(A.bm, w, w1, b);
+    int c = 0;
+#pragma unroll
+    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j]);
+    int step = 0;
+    const int ex = block_excl_scan<kBlock>(c, lds_i, &step);
+    if (c != 0) {
+      int64_t p = pos + ex;
+#pragma unroll
+      for (int j = 0; j < kSpWords; ++j) {
+        uint32_t rest = b[j];
+        if (rest == 0u) continue;
+        if (!over) {
+          while (rest != 0u) {
+            const int k = __builtin_ctz(rest);
+            rest &= rest - 1u;
+            const int64_t ix = (w + j) * 32 + k;
+            A.sp_idx[p] = ix;
+            ov[p] = spx_x_of<TIn, TA>(y[ix], lam, l1, copy);
+            ++p;
+          }
+        }
+        A.bm[w + j] = 0u;  // leave the bitmap clear for the next call
+      }
+    }
+    pos += step;
+  }
+}
+
 __global__ void spx_init_kernel(SpxState* st, SpxState init) { *st = init; }
 
 int grid0(int64_t n, int num_cus) {
@@ -1293,8 +1511,8 @@ int grid0(int64_t n, int num_cus) {
 }
 
 template <typename TIn, typename TA>
-cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, double r, TIn* x,
-                       bool l1, const cqk_opts& o, cqk_info* info) {
+cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, SparseOut* sp,
+                       double r, TIn* x, bool l1, const cqk_opts& o, cqk_info* info) {
   if (n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
   constexpr int64_t CAP = kTailBytes / (int64_t)sizeof(TIn);
   // G0 blocks of kWaves waves.  Passes over y hand out tiles of at most
@@ -1326,10 +1544,28 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
   const size_t tv_bytes = (tcap * sizeof(TIn) + 255) / 256 * 256;
   const size_t to_bytes = ((size_t)NR * sizeof(int32_t) + 255) / 256 * 256;
   const bool need_bufs = (o.compaction != CQK_COMPACT_OFF) || condat;
-  const size_t total = part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes +
+  // sparse output: GS blocks of sp_wpb bitmap words (a multiple of kSpStep) each
+  const bool sparse = sp != nullptr;
+  const int64_t nwords = (n + 31) / 32;
+  const int GS =
+      (int)std::min<int64_t>(1024, std::max<int64_t>(1, (nwords + kSpStep - 1) / kSpStep));
+  const int64_t wpb = ((nwords + GS - 1) / GS + kSpStep - 1) / kSpStep * kSpStep;
+  const size_t sc_bytes = sparse ? ((size_t)GS * sizeof(int32_t) + 255) / 256 * 256 : 0;
+  const size_t total = part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes + sc_bytes +
                        (need_bufs ? 2 * (val_bytes + idx_bytes) : 0);
   cqk_status stt = ensure_buffer(ctx->ws, total);
   if (stt != CQK_OK) return stt;
+  if (sparse) {
+    const size_t bm_bytes = ((size_t)nwords * sizeof(uint32_t) + 255) / 256 * 256;
+    if (ctx->bitmap.bytes < bm_bytes) ctx->bitmap_clean = false;
+    stt = ensure_buffer(ctx->bitmap, bm_bytes);
+    if (stt != CQK_OK) return stt;
+    // all zero from here (the write kernel clears what it reads)
+    if (!ctx->bitmap_clean &&
+        hip_ok(hipMemsetAsync(ctx->bitmap.ptr, 0, bm_bytes, ctx->stream)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    ctx->bitmap_clean = false;  // until this call has run to its end
+  }
   stt = ensure_buffer(ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
   if (stt != CQK_OK) return stt;
 
@@ -1337,7 +1573,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
   SpxArgs A{};
   A.y = y;
   A.xw = xw;
-  A.x = x;
+  A.x = sparse ? nullptr : x;
   A.n = n;
   A.chunk0 = chunk0;
   A.partials = (double*)ws;
@@ -1355,6 +1591,16 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
   }
   A.st = (SpxState*)ctx->state.ptr;
   A.trace = (cqk_trace_rec*)((char*)ctx->state.ptr + 1024);
+  if (sparse) {
+    A.bm = (uint32_t*)ctx->bitmap.ptr;
+    A.nwords = nwords;
+    A.sp_wpb = wpb;
+    A.sp_cnt = (int32_t*)(ws + part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes +
+                          (need_bufs ? 2 * (val_bytes + idx_bytes) : 0));
+    A.sp_idx = sp->idx;
+    A.sp_val = sp->val;
+    A.sp_cap = sp->cap;
+  }
 
   const double eps = sizeof(TA) == 4 ? 1.1920928955078125e-07 : 2.220446049250313e-16;
   SpxState init{};
@@ -1413,6 +1659,16 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
   // Writes x once the state says the loop has stopped; a no-op before that,
   // so it can follow every batch and the host waits once per batch.
   auto fin_chain = [&]() {
+    if (sparse) {
+      launch_timed(spx_sp_mark_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
+                   o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
+      hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
+      hipLaunchKernelGGL(spx_sp_count_kernel, dim3(GS), dim3(kBlock), 0, s, A);
+      launch_timed(spx_sp_write_kernel<TIn, TA>, dim3(GS), dim3(kBlock), s,
+                   o.timing ? ctx->events[2] : nullptr, o.timing ? ctx->events[3] : nullptr, A,
+                   GS);
+      return;
+    }
     launch_timed(spx_finalize_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
                  o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
     launch_timed(spx_scatter_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
@@ -1498,16 +1754,27 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
     double fin = (double)n * sizeof(TIn) * ((scatter || hs->fin_mode == kFinZero) ? 1.0 : 2.0);
     if (scatter && hs->x_zeroed) fin = 0.0;
     if (scatter) fin += (2.0 * sizeof(TIn) + 4.0) * (double)hs->n_src;
+    if (sparse) {
+      // mark: the final set (scatter form) or y and the bitmap (dense
+      // form); count and write: the bitmap twice; per entry an index and a
+      // value written and y read again
+      const double bm = 4.0 * (double)nwords;
+      fin = 0.0;
+      if (hs->fin_mode != kFinZero) {
+        fin = scatter ? (sizeof(TIn) + 4.0) * (double)hs->n_src : (double)n * sizeof(TIn) + bm;
+        fin += 2.0 * bm + (8.0 + 2.0 * sizeof(TIn)) * (double)hs->nnz;
+      }
+    }
     info->finalize_bytes = fin;
     for (int i = 0; i < ntrace; ++i) {
       const cqk_trace_rec& t = ctx->last_trace[i];
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
       const double per_out = (double)sizeof(TIn) + 4.0;
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
-      // the Algorithm 2 kernel also writes x = 0 everywhere (and reads the
-      // estimate of a warm start)
+      // the Algorithm 2 kernel also writes x = 0 everywhere (not for a
+      // sparse output) and reads the estimate of a warm start
       if (t.kind == 0 && t.source == 0 && t.compacted)
-        info->pass_bytes += sizeof(TIn) * (double)t.n_in * (warm ? 2.0 : 1.0);
+        info->pass_bytes += sizeof(TIn) * (double)t.n_in * ((sparse ? 0.0 : 1.0) + (warm ? 1.0 : 0.0));
     }
     if (o.timing) {
       // every grid pass launched (those after the loop stopped return at
@@ -1524,20 +1791,28 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, dou
       }
     }
   }
+  if (sparse) {
+    ctx->bitmap_clean = true;  // cleared by the write kernel, or never set
+    sp->nnz = hs->nnz;
+    if (hs->sp_over && info && (info->status == CQK_OK || info->status == CQK_NOT_CONVERGED))
+      info->status = CQK_BUFFER_TOO_SMALL;
+  }
   return CQK_OK;
 }
 
 }  // namespace
 
-cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, double r,
-                           float* x, bool l1, const cqk_opts& o, cqk_info* info) {
-  if (o.accum == CQK_ACCUM_F32) return run_simplex<float, float>(ctx, n, y, xw, r, x, l1, o, info);
-  return run_simplex<float, double>(ctx, n, y, xw, r, x, l1, o, info);
+cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xw, SparseOut* sp,
+                           double r, float* x, bool l1, const cqk_opts& o, cqk_info* info) {
+  if (o.accum == CQK_ACCUM_F32)
+    return run_simplex<float, float>(ctx, n, y, xw, sp, r, x, l1, o, info);
+  return run_simplex<float, double>(ctx, n, y, xw, sp, r, x, l1, o, info);
 }
 
-cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw, double r,
-                           double* x, bool l1, const cqk_opts& o, cqk_info* info) {
-  return run_simplex<double, double>(ctx, n, y, xw, r, x, l1, o, info);
+cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw,
+                           SparseOut* sp, double r, double* x, bool l1, const cqk_opts& o,
+                           cqk_info* info) {
+  return run_simplex<double, double>(ctx, n, y, xw, sp, r, x, l1, o, info);
 }
 
 }  // namespace cqk

@@ -71,6 +71,13 @@ def test_host_side_argument_errors(lib):
     assert lib.cqk_project_simplex_warm_f64(null, 10, null, null, 1.0, null, None, None) == 2
     assert lib.cqk_project_l1_warm_f32(null, 10, null, null, 1.0, null, None, None) == 2
     assert lib.cqk_project_l1_warm_f64(null, 10, null, null, 1.0, null, None, None) == 2
+    for name in ("cqk_project_simplex_sparse_f32", "cqk_project_simplex_sparse_f64",
+                 "cqk_project_l1_sparse_f32", "cqk_project_l1_sparse_f64"):
+        nnz = C.c_int64(-1)
+        assert getattr(lib, name)(null, 10, null, null, 1.0, 4, null, null, C.byref(nnz), None,
+                                  None) == 2
+        assert nnz.value == 0
+    assert lib.cqk_status_string(6) == b"CQK_BUFFER_TOO_SMALL"
     assert lib.cqk_project_simplex_batched_f32(null, 4, null, null, null, 1.0, null, null, null,
                                                None, None) == 2
     assert lib.cqk_create(None, None) == 2

@@ -1,0 +1,248 @@
+"""GPU parity of the sparse-output simplex and l1 projections (the support of
+x as ascending (index, value) pairs, Sec. 5.2) against the CPU oracle,
+through the C ABI (cqk_project_simplex_sparse_*, cqk_project_l1_sparse_*).
+
+For every case the pairs are scattered into a dense vector on the host and
+held to the parity bar of the dense calls (tests/parity.py); the indices must
+be strictly ascending and every value non-zero, and the count equals the
+number of pairs.  Every way the final set can be held when x is formed is
+covered: a compacted set (Algorithm 2 start), the one-block tail list (zero
+start on small inputs), the whole of y (compaction off, and y inside the l1
+ball), and r = 0."""
+import numpy as np
+import pytest
+
+from oracle import cqk_oracle as O
+from paper_2603_15910_amd import workloads as W
+from tests.parity import check_simplex
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL = {np.float32: 1e-5, np.float64: 1e-10}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_15910_amd as cqk
+    c = cqk.Context(0)
+    yield c
+    c.close()
+
+
+def _dt(y):
+    return torch.float64 if y.dtype == np.float64 else torch.float32
+
+
+def _sparse(ctx, y, r, l1=False, **kw):
+    yt = torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    fn = ctx.project_l1_sparse if l1 else ctx.project_simplex_sparse
+    idx, val, info = fn(yt, r, check=False, **kw)
+    return idx.cpu().numpy(), val.cpu().numpy(), info
+
+
+def _dense_of(idx, val, n, dtype):
+    x = np.zeros(n, dtype=dtype)
+    x[idx] = val
+    return x
+
+
+def _ref(y, r, l1=False):
+    y64 = y.astype(np.float64)
+    return O.project_l1(y64, r) if l1 else O.project_simplex(y64, r)
+
+
+def _check(ctx, y, r, l1=False, **kw):
+    x_ref, lam_ref = _ref(y, r, l1)
+    idx, val, info = _sparse(ctx, y, r, l1, **kw)
+    assert info["status"] == 0, info
+    assert info["nnz"] == idx.size == val.size
+    assert np.all(np.diff(idx) > 0)
+    assert np.all(val != 0)
+    assert idx.size == 0 or (idx[0] >= 0 and idx[-1] < y.size)
+    x = _dense_of(idx, val, y.size, y.dtype)
+    check_simplex(x, y, x_ref, lam_ref, r, TOL[y.dtype.type], l1=l1)
+    return idx, val, info
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("dist", ["normal", "uniform", "normal_small"])
+@pytest.mark.parametrize("start", ["condat", "zero", "formula"])
+@pytest.mark.parametrize("n", [1, 2, 17, 4099, 65537, 1_000_003])
+def test_sparse_simplex_parity(ctx, dtype, dist, start, n):
+    y = W.simplex_input(n, 101 + n % 11, dist, dtype)
+    idx, val, info = _check(ctx, y, 1.0, lambda0=start)
+    # the dense call of the same solve gives the same entries
+    xd, _ = ctx.project_simplex(torch.from_numpy(y).cuda(), 1.0, lambda0=start)
+    xd = xd.cpu().numpy()
+    assert np.array_equal(np.flatnonzero(xd), idx)
+    assert np.array_equal(xd[idx], val)
+
+
+@pytest.mark.parametrize("compaction", ["off", "always"])
+@pytest.mark.parametrize("start", ["condat", "zero"])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sparse_compaction_modes(ctx, compaction, start, dtype):
+    # compaction off with the zero start: x is a dense map of y when formed
+    y = W.simplex_input(300_007, 111, "uniform", dtype)
+    _check(ctx, y, 1.0, lambda0=start, compaction=compaction)
+
+
+@pytest.mark.parametrize("accum", ["f32", "f64"])
+def test_sparse_fp32_accumulation(ctx, accum):
+    y = W.simplex_input(2_000_003, 121, "uniform", np.float32)
+    _check(ctx, y, 1.0, accum=accum)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n", [17, 4099, 1_000_003])
+@pytest.mark.parametrize("start", ["condat", "zero"])
+def test_sparse_l1_parity(ctx, dtype, n, start):
+    y = W.simplex_input(n, 131, "normal", dtype)
+    radius = 0.05 * float(np.sum(np.abs(y.astype(np.float64))))
+    idx, val, _ = _check(ctx, y, radius, l1=True, lambda0=start)
+    assert np.all(np.sign(val) == np.sign(y[idx]))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_sparse_l1_inside_ball(ctx, dtype):
+    """y inside the ball: x = y, the support is {y != 0} (zeros planted)."""
+    n = 100_003
+    y = W.simplex_input(n, 141, "normal", dtype)
+    y[::7] = 0
+    radius = 2.0 * float(np.sum(np.abs(y.astype(np.float64))))
+    idx, val, info = _sparse(ctx, y, radius, l1=True)
+    assert info["status"] == 0
+    assert np.array_equal(idx, np.flatnonzero(y))
+    assert np.array_equal(val, y[idx])
+
+
+def test_sparse_large_support(ctx):
+    """r large against U[0,1]: most of the indices are in the support."""
+    n = 1_000_003
+    y = W.simplex_input(n, 151, "uniform", np.float32)
+    idx, _, info = _check(ctx, y, 0.4 * n, cap=n)
+    assert idx.size > n // 2
+
+
+def test_sparse_r_zero_and_empty(ctx):
+    y = W.simplex_input(1000, 161, "normal", np.float64)
+    idx, val, info = _sparse(ctx, y, 0.0)
+    assert info["status"] == 0 and idx.size == 0 and val.size == 0
+    idx, val, info = _sparse(ctx, y, 0.0, l1=True)
+    assert info["status"] == 0 and idx.size == 0
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    i, v, info = ctx.project_l1_sparse(e, 1.0)
+    assert info["status"] == 0 and i.numel() == 0
+
+
+def test_sparse_capacity(ctx):
+    import paper_2603_15910_amd as cqk
+    n = 200_003
+    y = W.simplex_input(n, 171, "uniform", np.float64)
+    x_ref, _ = _ref(y, 1.0)
+    k = int(np.count_nonzero(x_ref))
+    assert k > 2
+    yt = torch.from_numpy(y).cuda()
+    idx = torch.full((k,), -7, dtype=torch.int64, device="cuda")
+    val = torch.full((k,), -7.0, dtype=torch.float64, device="cuda")
+    info = cqk.cqk_info()
+    # one entry short: nothing written, the count returned
+    st, nnz = cqk.cqk_project_simplex_sparse_f64(ctx.handle, n, yt.data_ptr(), None, 1.0, k - 1,
+                                                 idx.data_ptr(), val.data_ptr(), None, info)
+    assert st == cqk.CQK_BUFFER_TOO_SMALL and nnz == k
+    assert torch.all(idx == -7) and torch.all(val == -7.0)
+    # count only
+    st, nnz = cqk.cqk_project_simplex_sparse_f64(ctx.handle, n, yt.data_ptr(), None, 1.0, 0,
+                                                 None, None, None, info)
+    assert st == cqk.CQK_BUFFER_TOO_SMALL and nnz == k
+    # exactly enough
+    st, nnz = cqk.cqk_project_simplex_sparse_f64(ctx.handle, n, yt.data_ptr(), None, 1.0, k,
+                                                 idx.data_ptr(), val.data_ptr(), None, info)
+    assert st == cqk.CQK_OK and nnz == k
+    assert np.array_equal(idx.cpu().numpy(), np.flatnonzero(x_ref))
+    # the binding solves once more with room for the support
+    i2, v2, inf2 = ctx.project_simplex_sparse(yt, 1.0, cap=1)
+    assert inf2["status"] == 0 and torch.equal(i2, idx) and torch.equal(v2, val)
+
+
+def test_sparse_argument_errors(ctx):
+    import paper_2603_15910_amd as cqk
+    n = 1000
+    y = torch.from_numpy(W.simplex_input(n, 181, "normal", np.float32)).cuda()
+    val = torch.empty(n, dtype=torch.float32, device="cuda")
+    idx = torch.empty(n, dtype=torch.int64, device="cuda")
+    info = cqk.cqk_info()
+    f = cqk.cqk_project_simplex_sparse_f32
+    assert f(ctx.handle, n, y.data_ptr(), None, 1.0, -1, idx.data_ptr(), val.data_ptr(), None,
+             info)[0] == cqk.CQK_INVALID_ARG
+    assert f(ctx.handle, n, y.data_ptr(), None, 1.0, 5, None, val.data_ptr(), None,
+             info)[0] == cqk.CQK_INVALID_ARG
+    # values written over y
+    assert f(ctx.handle, n, y.data_ptr(), None, 1.0, n, idx.data_ptr(), y.data_ptr(), None,
+             info)[0] == cqk.CQK_INVALID_ARG
+    # indices over values
+    assert f(ctx.handle, n, y.data_ptr(), None, 1.0, n, val.data_ptr(), val.data_ptr(), None,
+             info)[0] == cqk.CQK_INVALID_ARG
+    bad = y.clone()
+    bad[3] = float("nan")
+    assert f(ctx.handle, n, bad.data_ptr(), None, 1.0, n, idx.data_ptr(), val.data_ptr(), None,
+             info)[0] == cqk.CQK_INVALID_ARG
+
+
+def test_sparse_calls_in_a_row(ctx):
+    """The bitmap is clean after every call: a sequence of calls of other
+    sizes and kinds, a capacity miss and a failed call between them."""
+    import paper_2603_15910_amd as cqk
+    seq = [(W.simplex_input(50_000, 191, "uniform", np.float64), 1.0, False),
+           (W.simplex_input(3_000_017, 192, "uniform", np.float32), 2.0, False),
+           (W.simplex_input(777, 193, "normal", np.float32), 0.5, True),
+           (W.simplex_input(1_000_003, 194, "uniform", np.float32), 1.0, False)]
+    for k, (y, r, l1) in enumerate(seq):
+        if k == 2:
+            yt = torch.from_numpy(seq[1][0]).cuda()
+            i, v, info = ctx.project_simplex_sparse(yt, 1e6, cap=1, check=False)
+            nan = torch.full((10,), float("nan"), device="cuda")
+            with pytest.raises(cqk.CqkError):
+                ctx.project_simplex_sparse(nan, 1.0)
+            # a general solve in between uses the shared workspace
+            inst = W.cqk_uniform(100_000, 195)
+            t = [torch.from_numpy(inst[c]).cuda() for c in "dablu"]
+            ctx.solve(*t, inst["r"])
+        _check(ctx, y, r, l1=l1)
+
+
+@pytest.mark.parametrize("l1", [False, True])
+def test_sparse_with_warm_start(ctx, l1):
+    n = 1_000_003
+    y0 = W.simplex_input(n, 201, "normal", np.float64)
+    r = 0.05 * float(np.sum(np.abs(y0))) if l1 else 1.0
+    xbar, _ = _ref(y0, r, l1)
+    y = W.perturbed(y0, 202, 1e-3)
+    _, _, info = _check(ctx, y, r, l1=l1, xbar=torch.from_numpy(xbar).cuda())
+    _, lam_ref = _ref(y, r, l1)
+    assert info["lambda0"] >= lam_ref - 1e-12 * max(1.0, abs(lam_ref))
+
+
+@pytest.mark.parametrize("dist", ["normal", "uniform"])
+def test_sparse_simplex_1e8_fp32(ctx, dist):
+    """The benchmark size: against the oracle's exact sort solution."""
+    n = 100_000_000
+    y = W.simplex_input(n, 1, dist, np.float32)
+    yt = torch.from_numpy(y).cuda()
+    i, v, info = ctx.project_simplex_sparse(yt, 1.0, check=False)
+    assert info["status"] == 0, info
+    idx, val = i.cpu().numpy(), v.cpu().numpy()
+    del yt, i, v
+    torch.cuda.empty_cache()
+    x_ref, lam_ref = O.project_simplex(y.astype(np.float64), 1.0)
+    assert np.all(np.diff(idx) > 0)
+    x = np.zeros(n, dtype=np.float64)
+    x[idx] = val
+    S = max(float(np.max(np.abs(x_ref))), float(np.max(np.abs(y))), abs(lam_ref))
+    assert abs(info["lambda"] - lam_ref) <= 1e-5 * S
+    assert float(np.max(np.abs(x - x_ref))) <= 1e-5 * S
+    assert abs(float(np.sum(val, dtype=np.float64)) - 1.0) <= 1e-5
