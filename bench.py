@@ -331,7 +331,56 @@ def extra_batched(ctx, dev, torch, row_loop=True):
         "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}
     del ybt, xb, offs
     torch.cuda.empty_cache()
+    ex.update(extra_batched_cqk(ctx, dev, torch, row_loop))
     return ex
+
+
+def extra_batched_cqk(ctx, dev, torch, row_loop=True):
+    """Batched general CQK, FP64: 8192 rows of log-uniform length in
+    [64, 65536], forward and the VJP w.r.t. a and r."""
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    off, inst = W.cqk_batched(8192, 64, 65536, 1)
+    total = int(off[-1])
+    offs = torch.from_numpy(off).to(dev)
+    t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
+    r = torch.from_numpy(inst["r"]).to(dev)
+    del inst
+    x = torch.empty_like(t[0])
+    ctx.solve_batched(*t, offs, r, out=x)
+    ms = timed(lambda: ctx.solve_batched(*t, offs, r, out=x), 5, sync)
+    _, info = ctx.solve_batched(*t, offs, r, out=x)
+    g = torch.randn(total, dtype=torch.float64, device=dev,
+                    generator=torch.Generator(device=dev).manual_seed(5))
+    ga = torch.empty_like(g)
+    gr = torch.empty(8192, dtype=torch.float64, device=dev)
+    bwd = lambda: ctx.solve_batched_backward(x, g, t[0], t[2], t[3], t[4], offs, grad_a=ga,
+                                             grad_r=gr)
+    bwd()
+    ms_b = timed(bwd, 5, sync)
+    # comparator: one plain solve per row over the first 512 rows, scaled
+    loop_ms = None
+    if row_loop:
+        rr = r.cpu().numpy()
+        k = 512
+        sync()
+        t0 = time.perf_counter()
+        for s in range(k):
+            lo, hi = int(off[s]), int(off[s + 1])
+            ctx.solve(*[v[lo:hi] for v in t], float(rr[s]), out=x[lo:hi])
+        sync()
+        loop_ms = (time.perf_counter() - t0) * 1e3 * (8192 / k)
+    out = {"batched_cqk_8192rows_f64": {
+        "rows": 8192, "elements": total, "ms": ms, "elements_per_s": total / (ms * 1e-3),
+        "mean_iterations": info["passes"] / 8192, "max_iterations": info["iterations"],
+        "gbs_40B_per_elem_per_iteration": 40.0 * total * info["passes"] / 8192 / (ms * 1e-3) / 1e9,
+        "status": info["status_name"], "backward_ms": ms_b,
+        "backward_gbs_48B_per_elem": 48.0 * total / (ms_b * 1e-3) / 1e9,
+        "per_row_loop_ms_scaled_from_512_rows": loop_ms,
+        "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}}
+    del t, x, g, ga, gr, offs, r
+    torch.cuda.empty_cache()
+    return out
 
 
 def extra_differentiable(ctx, dev, torch):

@@ -264,6 +264,39 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
                                            float* x, double* lambda_out, int32_t* nfree_out,
                                            const cqk_opts* opts, cqk_info* info);
 
+/* Many general CQK instances in one launch (Section 2.1, Algorithm 1 per
+ * row, each row with its own bracket, breakpoint and secant state): row s
+ * is (d, a, b, l, u)[offsets[s] .. offsets[s+1]) with right-hand side r[s].
+ * offsets: int64[nseg+1] DEVICE array, non-decreasing, offsets[0] = 0.
+ * d, a, b, l, u, x: DEVICE float64 arrays of offsets[nseg] values.
+ * r: DEVICE float64[nseg] (required).
+ * lambda_out: optional DEVICE float64[nseg], the row multipliers (NaN for a
+ * row without one).  status_out: optional DEVICE int32[nseg], each row's
+ * cqk_status.
+ * opts: lambda0_mode ZERO, FORMULA (eq. (CQKlambda0) per row) or USER (the
+ * same lambda0_user for every row); compaction is not used.
+ * Returns the worst row status: INVALID_ARG (a row failing the input checks
+ * of cqk_solve_f64, or a non-finite r[s]), else INFEASIBLE, else
+ * NOT_CONVERGED, else OK; x of a row without a multiplier is NaN.
+ * An empty row is OK iff r[s] = 0.  info->iterations: the largest row
+ * iteration count; info->passes: the iterations summed over rows. */
+cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                 const double* d, const double* a, const double* b,
+                                 const double* l, const double* u, const double* r, double* x,
+                                 double* lambda_out, int32_t* status_out, const cqk_opts* opts,
+                                 cqk_info* info);
+
+/* Vector-Jacobian product of the batched CQK solution w.r.t. a and r on each
+ * row's free set F = {l_i < x_i < u_i} (eq. (xopt) on F, eq. (opt)
+ * differentiated):  q = sum_F b^2/d,  mu = (sum_F g b/d)/q,
+ *   grad_a_i = [i in F](g_i - b_i mu)/d_i,   grad_r[s] = mu   (0 if F empty).
+ * x: forward output, g: upstream gradient, grad_a: output, all DEVICE
+ * float64 in the forward layout; grad_r: optional DEVICE float64[nseg]. */
+cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                          const double* x, const double* g, const double* d,
+                                          const double* b, const double* l, const double* u,
+                                          double* grad_a, double* grad_r, const cqk_opts* opts);
+
 /* Vector-Jacobian product of the batched simplex projection w.r.t. y and r
  * on each row's support S = {x_i > 0} (derived from eq. (lambdaJ)):
  *   grad_y_i = [i in S] (g_i - mean_S g),   grad_r[s] = mean_S g.

@@ -712,6 +712,34 @@ def project_simplex_batched(values, offsets, r):
     return x, lam
 
 
+def solve_cqk_batched(d, a, b, l, u, offsets, r):
+    """Row-by-row solve_cqk; r has one value per row.  Returns the list of
+    per-row CQKResult."""
+    d, a, b, l, u = _as64(d, a, b, l, u)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    r = np.asarray(r, dtype=np.float64)
+    out = []
+    for s in range(offsets.size - 1):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        out.append(solve_cqk(d[lo:hi], a[lo:hi], b[lo:hi], l[lo:hi], u[lo:hi], float(r[s])))
+    return out
+
+
+def cqk_vjp_batched(x, g, d, b, l, u, offsets):
+    """Row-by-row cqk_vjp: (grad_a, grad_r per row)."""
+    x, g, d, b, l, u = _as64(x, g, d, b, l, u)
+    offsets = np.asarray(offsets, dtype=np.int64)
+    nseg = offsets.size - 1
+    ga = np.zeros_like(g)
+    gr = np.zeros(nseg)
+    for s in range(nseg):
+        lo, hi = int(offsets[s]), int(offsets[s + 1])
+        if hi > lo:
+            ga[lo:hi], gr[s] = cqk_vjp(x[lo:hi], g[lo:hi], d[lo:hi], b[lo:hi], l[lo:hi],
+                                       u[lo:hi])
+    return ga, gr
+
+
 def simplex_vjp_batched(x, g, offsets):
     x = np.asarray(x, dtype=np.float64)
     g = np.asarray(g, dtype=np.float64)

@@ -28,6 +28,7 @@ __all__ = [
     "CQK_OK", "CQK_INFEASIBLE", "CQK_INVALID_ARG", "CQK_NOT_CONVERGED", "CQK_DEVICE_ERROR",
     "CQK_NO_MEMORY", "CQK_BUFFER_TOO_SMALL", "CqkError", "CqkLibraryMissing", "Context", "solve",
     "project_simplex", "project_l1", "project_simplex_sparse", "project_l1_sparse",
+    "solve_batched", "solve_batched_backward", "CqkBatchedSolve",
     "project_simplex_batched", "project_simplex_batched_backward", "SimplexProjection", "lib",
 ]
 
@@ -181,6 +182,18 @@ def cqk_project_l1_sparse_f64(ctx, n, y, xbar, radius, cap, idx, val, opts=None,
     """Returns (status, nnz)."""
     return _sparse("cqk_project_l1_sparse_f64", ctx, n, y, xbar, radius, cap, idx, val, opts,
                    info)
+
+
+def cqk_solve_batched_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out=None,
+                          status_out=None, opts=None, info=None):
+    return _call("cqk_solve_batched_f64", C.c_void_p(ctx), nseg, offsets, d, a, b, l, u, r, x,
+                 lambda_out, status_out, _ref(opts), _ref(info))
+
+
+def cqk_solve_batched_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r=None,
+                                   opts=None):
+    return _call("cqk_solve_batched_backward_f64", C.c_void_p(ctx), nseg, offsets, x, g, d, b,
+                 l, u, grad_a, grad_r, _ref(opts))
 
 
 def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out=None,
@@ -412,6 +425,48 @@ class Context:
         return self._project_sparse((cqk_project_l1_sparse_f64, cqk_project_l1_sparse_f32), y,
                                     radius, cap, xbar, check, kw, out)
 
+    def solve_batched(self, d, a, b, l, u, offsets, r, out=None, lambda_out=None,
+                      status_out=None, check=True, **kw):
+        """Many general CQK rows in one launch: row s is [offsets[s],
+        offsets[s+1]) of the float64 arrays d, a, b, l, u; r a float64 GPU
+        tensor [nseg].  Returns (x, info)."""
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        x = out if out is not None else torch.empty_like(d)
+        ptrs = [_dev_ptr(t, torch.float64, nm) for t, nm in zip((d, a, b, l, u, x), "dablux")]
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        pr = _dev_ptr(r, torch.float64, "r")
+        if r.numel() != nseg:
+            raise ValueError("r needs one value per row")
+        pl = _dev_ptr(lambda_out, torch.float64, "lambda_out") if lambda_out is not None else None
+        ps = _dev_ptr(status_out, torch.int32, "status_out") if status_out is not None else None
+        opts = make_opts(**kw)
+        info = cqk_info()
+        self._bind_stream()
+        st = cqk_solve_batched_f64(self.handle, nseg, po, *ptrs[:5], pr, ptrs[5], pl, ps, opts,
+                                   info)
+        self.last_info = info.as_dict()
+        if check and st != CQK_OK:
+            raise CqkError(st, "cqk_solve_batched_f64")
+        return x, self.last_info
+
+    def solve_batched_backward(self, x, g, d, b, l, u, offsets, grad_a=None, grad_r=None,
+                               check=True, **kw):
+        """VJP of solve_batched w.r.t. a (returned) and r (into grad_r)."""
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        ga = grad_a if grad_a is not None else torch.empty_like(g)
+        ptrs = [_dev_ptr(t, torch.float64, nm)
+                for t, nm in zip((x, g, d, b, l, u, ga), ("x", "g", "d", "b", "l", "u", "grad_a"))]
+        po = _dev_ptr(offsets, torch.int64, "offsets")
+        pgr = _dev_ptr(grad_r, torch.float64, "grad_r") if grad_r is not None else None
+        opts = make_opts(**kw)
+        self._bind_stream()
+        st = cqk_solve_batched_backward_f64(self.handle, nseg, po, *ptrs, pgr, opts)
+        if check and st != CQK_OK:
+            raise CqkError(st, "cqk_solve_batched_backward_f64")
+        return ga
+
     def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
                                 nfree_out=None, check=True, **kw):
         torch = _torch()
@@ -545,6 +600,14 @@ def project_simplex_batched_backward(x, g, offsets, **kw):
     return default_context(x.device).project_simplex_batched_backward(x, g, offsets, **kw)
 
 
+def solve_batched(d, a, b, l, u, offsets, r, **kw):
+    return default_context(d.device).solve_batched(d, a, b, l, u, offsets, r, **kw)
+
+
+def solve_batched_backward(x, g, d, b, l, u, offsets, **kw):
+    return default_context(x.device).solve_batched_backward(x, g, d, b, l, u, offsets, **kw)
+
+
 def _autograd_cls():
     torch = _torch()
 
@@ -573,16 +636,42 @@ def _autograd_cls():
             gr = grad_r if ctx.r_is_tensor else None
             return gy, None, gr
 
-    return _SimplexProjection
+    class _CqkBatchedSolve(torch.autograd.Function):
+        """Batched general CQK with a hand-written HIP backward.
+
+        forward(d, a, b, l, u, offsets, r): float64 GPU tensors, offsets
+        int64 [nseg+1], r float64 [nseg].  Differentiable in a and r;
+        backward returns (None, grad_a, None, None, None, None, grad_r)."""
+
+        @staticmethod
+        def forward(ctx, d, a, b, l, u, offsets, r):
+            x, _ = solve_batched(d, a.contiguous(), b, l, u, offsets, r)
+            ctx.save_for_backward(x, d, b, l, u, offsets)
+            return x
+
+        @staticmethod
+        def backward(ctx, g):
+            x, d, b, l, u, offsets = ctx.saved_tensors
+            nseg = offsets.numel() - 1
+            grad_r = torch.empty(nseg, dtype=torch.float64, device=x.device)
+            ga = solve_batched_backward(x, g.contiguous().double(), d, b, l, u, offsets,
+                                        grad_r=grad_r)
+            return None, ga, None, None, None, None, grad_r
+
+    return _SimplexProjection, _CqkBatchedSolve
 
 
 class _Lazy:
     _cls = None
 
+    def __init__(self, which):
+        self._which = which
+
     def __getattr__(self, item):
         if _Lazy._cls is None:
             _Lazy._cls = _autograd_cls()
-        return getattr(_Lazy._cls, item)
+        return getattr(_Lazy._cls[self._which], item)
 
 
-SimplexProjection = _Lazy()
+SimplexProjection = _Lazy(0)
+CqkBatchedSolve = _Lazy(1)

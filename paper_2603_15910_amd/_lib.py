@@ -131,6 +131,10 @@ SIGNATURES = {
                                                  _INFO]),
     "cqk_project_l1_sparse_f32": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS, _INFO]),
     "cqk_project_l1_sparse_f64": (C.c_int, [_P, _I64, _P, _P, _D, _I64, _P, _P, _P, _OPTS, _INFO]),
+    "cqk_solve_batched_f64": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        _OPTS, _INFO]),
+    "cqk_solve_batched_backward_f64": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                 _P, _OPTS]),
     "cqk_solve_warm_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_warm_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),

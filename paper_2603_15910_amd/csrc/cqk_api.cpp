@@ -356,6 +356,43 @@ cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
   return sparse_common<double>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
 }
 
+cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                 const double* d, const double* a, const double* b,
+                                 const double* l, const double* u, const double* r, double* x,
+                                 double* lambda_out, int32_t* status_out, const cqk_opts* opts,
+                                 cqk_info* info) {
+  if (!ctx || nseg < 0) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, false);
+  if (st != CQK_OK) return st;
+  if (nseg == 0) {
+    info_trivial(info, CQK_OK, 0.0);
+    return CQK_OK;
+  }
+  if (!offsets || !d || !a || !b || !l || !u || !r || !x) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_info tmp;
+  cqk_info* inf = info ? info : &tmp;
+  st = run_batched_cqk_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out, status_out, o,
+                           inf);
+  if (st != CQK_OK) return st;
+  return (cqk_status)inf->status;
+}
+
+cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                          const double* x, const double* g, const double* d,
+                                          const double* b, const double* l, const double* u,
+                                          double* grad_a, double* grad_r, const cqk_opts* opts) {
+  if (!ctx || nseg < 0) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, false);
+  if (st != CQK_OK) return st;
+  if (nseg == 0) return CQK_OK;
+  if (!offsets || !x || !g || !d || !b || !l || !u || !grad_a) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return run_batched_cqk_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
+}
+
 cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                            const float* y, const double* r, double r_scalar,
                                            float* x, double* lambda_out, int32_t* nfree_out,

@@ -32,6 +32,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "cqk_alg1.h"
 #include "cqk_device.h"
 #include "cqk_internal.h"
 
@@ -47,7 +48,7 @@ constexpr int kNB = 24;              // length buckets (bucket 0: wave rows)
 constexpr int kRefine = 8;
 constexpr int kMaxNewton = 100;
 
-enum BatFlags : int32_t { kBadRadius = 1, kBadValue = 2, kInfeasible = 4 };
+enum BatFlags : int32_t { kBadRadius = 1, kBadValue = 2, kInfeasible = 4, kNotConverged = 8 };
 
 struct BatArgs {
   int32_t nseg;
@@ -88,12 +89,16 @@ __device__ __forceinline__ int bucket_of(int64_t L, int small_max) {
 constexpr int kPBlock = 1024;
 constexpr int kPW = kPBlock / kWave;
 
-// length bucket of row s, -1 past the last row
-__device__ __forceinline__ int plan_bucket(const BatArgs& A, int s) {
+// length bucket of row s, -1 past the last row.  Args: the simplex or the
+// general form's argument record (both carry nseg, small_max, off and the
+// planning buffers).
+template <typename Args>
+__device__ __forceinline__ int plan_bucket(const Args& A, int s) {
   return (s < A.nseg) ? bucket_of(A.off[s + 1] - A.off[s], A.small_max) : -1;
 }
 
-__global__ __launch_bounds__(kPBlock) void bat_count_kernel(BatArgs A) {
+template <typename Args>
+__global__ __launch_bounds__(kPBlock) void bat_count_kernel(Args A) {
   __shared__ int wh[kPW][kNB];
   const int s = blockIdx.x * kPBlock + (int)threadIdx.x;
   const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
@@ -116,7 +121,8 @@ __global__ __launch_bounds__(kPBlock) void bat_count_kernel(BatArgs A) {
   }
 }
 
-__global__ __launch_bounds__(kPBlock) void bat_place_kernel(BatArgs A) {
+template <typename Args>
+__global__ __launch_bounds__(kPBlock) void bat_place_kernel(Args A) {
   __shared__ int part[2][kNB][32];
   __shared__ int base[kNB], pre[kNB];
   __shared__ int wh[kPW][kNB];
@@ -855,6 +861,393 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
   }
 }
 
+
+// ===========================================================================
+// Batched general CQK (Section 2.1, Algorithm 1 per row) and its VJP.
+//
+// Row s is (d, a, b, l, u)[off[s] .. off[s+1]) with its own r[s].  Every row
+// runs Algorithm 1 from lam = 0 (or eq. (CQKlambda0) over the row) with its
+// own bracket, breakpoint and secant state: the scalar update of the
+// single-instance solver on a state record each wave or workgroup keeps in
+// registers, every lane updating its own copy from the same reduced sums (so
+// all copies stay identical and the control flow uniform).  A row of at most
+// 64 * kCqkSP values is one wave's, its per-index form (c, s, bl, bu) held in
+// registers from load to store; a longer row is a workgroup's, which re-reads
+// the row from memory at every evaluation.  x = clamp((a + lam b)/d, l, u)
+// (eq. (xopt)) is written once.
+//
+// Backward, on a locally constant free set F = {l < x < u} (eq. (xopt) on F
+// and eq. (opt) differentiated): with q = sum_F b^2/d and
+// mu = (sum_F g b/d)/q,
+//   grad_a = [F](g - b mu)/d,   grad_r = mu   (both 0 when F is empty).
+// ===========================================================================
+constexpr int kCqkSP = 4;   // values per lane of a wave row
+constexpr int kCqkU = 4;    // values per thread in flight in a workgroup pass
+constexpr int CTR_ITSUM = CTR_SURV, CTR_ITMAX = CTR_OVER;
+
+struct BatCqkArgs {
+  int32_t nseg;
+  int32_t small_max;    // longest wave row
+  int32_t short_first;  // 1: wave rows are handed out first
+  int32_t lambda0_mode; // CQK_LAMBDA0_ZERO, _FORMULA or _USER
+  int32_t max_iter;
+  double tol;
+  double lam0_user;     // the start of every row with CQK_LAMBDA0_USER
+  const int64_t* off;
+  const double *d, *a, *b, *l, *u;
+  const double* r;
+  double* x;            // forward output; backward input
+  double* lam_out;
+  int32_t* status_out;
+  const double* g;      // backward: upstream gradient
+  double* ga;           // backward: grad_a
+  double* gr;           // backward: grad_r
+  int32_t* list;
+  int64_t* lrow;
+  int32_t* counters;
+  int32_t* bhist;
+};
+
+__device__ __forceinline__ GenState cqk_row_state(const BatCqkArgs& A, double r) {
+  GenState st{};
+  st.lam = (A.lambda0_mode == CQK_LAMBDA0_USER) ? A.lam0_user : 0.0;
+  st.lam0 = st.lam;
+  st.lam_prev = __builtin_nan("");
+  st.lam_final = __builtin_nan("");
+  st.lo = -inf_d();
+  st.hi = inf_d();
+  st.phi_lo = st.phi_hi = __builtin_nan("");
+  st.r = r;
+  st.tol = A.tol;
+  st.status = kRunning;
+  st.max_iter = A.max_iter;
+  st.compaction = CQK_COMPACT_OFF;
+  st.mode = kModeEval;
+  return st;
+}
+
+// Per-row outputs and the call's flags, by one thread of the row's owner.
+__device__ __forceinline__ void cqk_row_report(const BatCqkArgs& A, int s, const GenState& st,
+                                               double lam) {
+  if (A.lam_out) A.lam_out[s] = lam;
+  if (A.status_out) A.status_out[s] = st.status;
+  int f = 0;
+  if (st.status == CQK_INVALID_ARG) f = kBadValue;
+  else if (st.status == CQK_INFEASIBLE) f = kInfeasible;
+  else if (st.status == CQK_NOT_CONVERGED) f = kNotConverged;
+  if (f) atomicOr(&A.counters[CTR_FLAGS], f);
+  atomicAdd(&A.counters[CTR_ITSUM], st.iter);
+  atomicMax(&A.counters[CTR_ITMAX], st.iter);
+}
+
+// x_i of eq. (xopt) at the row's multiplier (NaN for a row without one).
+__device__ __forceinline__ double cqk_x_at(const BatCqkArgs& A, int64_t i, double lam) {
+  const double t = fma(A.b[i], lam, A.a[i]) / A.d[i];
+  return fmin(fmax(t, A.l[i]), A.u[i]);
+}
+
+__device__ __forceinline__ bool cqk_has_lambda(const GenState& st) {
+  return st.status == CQK_OK || st.status == CQK_NOT_CONVERGED;
+}
+
+// ---------------------------------------------------------------------------
+// One wave row (L <= 64 * SP), per-index form in registers.
+// ---------------------------------------------------------------------------
+template <int SP>
+__device__ void cqk_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double c[SP], sv[SP], bl[SP], bu[SP];
+  double bad = 0.0, sc = 0.0, ss = 0.0;
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int64_t i = lane + (int64_t)k * kWave;
+    c[k] = sv[k] = bl[k] = bu[k] = 0.0;
+    if (i < L) {
+      const int64_t e = base + i;
+      to_form(A.d[e], A.a[e], A.b[e], A.l[e], A.u[e], c[k], sv[k], bl[k], bu[k], bad);
+      sc += c[k];
+      ss += sv[k];
+    }
+  }
+  const double r = A.r[s];
+  GenState st = cqk_row_state(A, r);
+  if (wave_sum(bad) > 0.0 || !(fabs(r) < inf_d())) {
+    st.status = CQK_INVALID_ARG;
+  } else if (L == 0) {
+    st.status = (r == 0.0) ? CQK_OK : CQK_INFEASIBLE;
+    st.lam_final = 0.0;
+  } else if (A.lambda0_mode == CQK_LAMBDA0_FORMULA) {
+    const double tc = wave_sum(sc), ts = wave_sum(ss);
+    st.lam = st.lam0 = (ts > 0.0) ? (r - tc) / ts : 0.0;
+  }
+  while (st.status == kRunning) {
+    if (st.mode == kModeEval) {
+      Acc acc;
+      acc_init(acc);
+#pragma unroll
+      for (int k = 0; k < SP; ++k)
+        if (lane + (int64_t)k * kWave < L) eval_index<false>(acc, c[k], sv[k], bl[k], bu[k], st.lam, st.lo, st.hi);
+      double t[NSUM];
+#pragma unroll
+      for (int i = 0; i < NSUM; ++i) t[i] = 0.0;
+      t[P_P] = wave_sum(acc.s[P_P]);
+      t[P_A] = wave_sum(acc.s[P_A]);
+      t[P_QP] = wave_sum(acc.s[P_QP]);
+      t[P_QM] = wave_sum(acc.s[P_QM]);
+      t[P_NIN] = (double)L;
+      update_after_eval(&st, t, nullptr);
+    } else {
+      KeySum ks[2] = {KeySum{inf_d(), 0.0}, KeySum{inf_d(), 0.0}};
+#pragma unroll
+      for (int k = 0; k < SP; ++k)
+        if (lane + (int64_t)k * kWave < L) bkpt_index(ks, c[k], sv[k], bl[k], bu[k], st.lam);
+      ks[0] = wave_ks_min(ks[0]);
+      ks[1] = wave_ks_min(ks[1]);
+      update_after_bkpt(&st, ks, nullptr);
+    }
+  }
+  const bool ok = cqk_has_lambda(st);
+  const double lam = ok ? st.lam_final : __builtin_nan("");
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int64_t i = lane + (int64_t)k * kWave;
+    if (i < L) A.x[base + i] = ok ? cqk_x_at(A, base + i, lam) : __builtin_nan("");
+  }
+  if (lane == 0) cqk_row_report(A, s, st, lam);
+}
+
+// ---------------------------------------------------------------------------
+// One workgroup row: every evaluation streams the row.
+// ---------------------------------------------------------------------------
+struct CqkLds {
+  double red[8 * kWaves];
+  double tot[8];
+  KeySum ks[2];
+  int item;
+};
+
+__device__ void cqk_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L, CqkLds& S) {
+  const double r = A.r[s];
+  GenState st = cqk_row_state(A, r);
+  const double* d = A.d + base;
+  const double* a = A.a + base;
+  const double* b = A.b + base;
+  const double* l = A.l + base;
+  const double* u = A.u + base;
+  constexpr int64_t STEP = (int64_t)kBlock * kCqkU;
+  // kCqkU values per thread with every load issued before the first use
+  auto stream = [&](auto&& fn) {
+    for (int64_t i0 = threadIdx.x; i0 < L; i0 += STEP) {
+      double vd[kCqkU], va[kCqkU], vb[kCqkU], vl[kCqkU], vu[kCqkU];
+#pragma unroll
+      for (int k = 0; k < kCqkU; ++k) {
+        const int64_t i = i0 + (int64_t)k * kBlock;
+        const bool in = i < L;
+        vd[k] = in ? d[i] : 1.0;
+        va[k] = in ? a[i] : 0.0;
+        vb[k] = in ? b[i] : 1.0;
+        vl[k] = in ? l[i] : 0.0;
+        vu[k] = in ? u[i] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kCqkU; ++k)
+        if (i0 + (int64_t)k * kBlock < L) fn(i0 + (int64_t)k * kBlock, vd[k], va[k], vb[k], vl[k], vu[k]);
+    }
+  };
+  if (!(fabs(r) < inf_d())) {
+    st.status = CQK_INVALID_ARG;
+  } else if (A.lambda0_mode == CQK_LAMBDA0_FORMULA) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    stream([&](int64_t, double vd, double va, double vb, double vl, double vu) {
+      double c, sv, bl, bu;
+      to_form(vd, va, vb, vl, vu, c, sv, bl, bu, acc[2]);
+      acc[0] += c;
+      acc[1] += sv;
+    });
+    block_reduce<3, 0, 0, kBlock>(acc, nullptr, nullptr, S.red, S.tot);
+    if (S.tot[2] > 0.0) st.status = CQK_INVALID_ARG;
+    else st.lam = st.lam0 = (S.tot[1] > 0.0) ? (r - S.tot[0]) / S.tot[1] : 0.0;
+  }
+  while (st.status == kRunning) {
+    if (st.mode == kModeEval) {
+      Acc acc;
+      acc_init(acc);
+      double bad = 0.0;
+      const double lam = st.lam, lo = st.lo, hi = st.hi;
+      stream([&](int64_t, double vd, double va, double vb, double vl, double vu) {
+        double c, sv, bl, bu;
+        to_form(vd, va, vb, vl, vu, c, sv, bl, bu, bad);
+        eval_index<false>(acc, c, sv, bl, bu, lam, lo, hi);
+      });
+      double v[5] = {acc.s[P_P], acc.s[P_A], acc.s[P_QP], acc.s[P_QM], bad};
+      block_reduce<5, 0, 0, kBlock>(v, nullptr, nullptr, S.red, S.tot);
+      double t[NSUM];
+#pragma unroll
+      for (int i = 0; i < NSUM; ++i) t[i] = 0.0;
+      t[P_P] = S.tot[0];
+      t[P_A] = S.tot[1];
+      t[P_QP] = S.tot[2];
+      t[P_QM] = S.tot[3];
+      t[P_BAD] = S.tot[4];
+      t[P_NIN] = (double)L;
+      update_after_eval(&st, t, nullptr);
+    } else {
+      KeySum ks[2] = {KeySum{inf_d(), 0.0}, KeySum{inf_d(), 0.0}};
+      const double lam = st.lam;
+      double bad = 0.0;
+      stream([&](int64_t, double vd, double va, double vb, double vl, double vu) {
+        double c, sv, bl, bu;
+        to_form(vd, va, vb, vl, vu, c, sv, bl, bu, bad);
+        bkpt_index(ks, c, sv, bl, bu, lam);
+      });
+      block_ks_min<2, kBlock>(ks, S.red, S.ks);
+      const KeySum kt[2] = {S.ks[0], S.ks[1]};
+      __syncthreads();
+      update_after_bkpt(&st, kt, nullptr);
+    }
+  }
+  const bool ok = cqk_has_lambda(st);
+  const double lam = ok ? st.lam_final : __builtin_nan("");
+  double* x = A.x + base;
+  stream([&](int64_t i, double vd, double va, double vb, double vl, double vu) {
+    const double t = fma(vb, lam, va) / vd;
+    x[i] = ok ? fmin(fmax(t, vl), vu) : __builtin_nan("");
+  });
+  if (threadIdx.x == 0) cqk_row_report(A, s, st, lam);
+}
+
+template <int SP>
+__global__ __launch_bounds__(kBlock) void bat_cqk_solve_kernel(BatCqkArgs A) {
+  __shared__ CqkLds S;
+  const int nlong = A.counters[CTR_NLONG];
+  const int nshort = A.counters[CTR_NSHORT];
+  const int nitems = A.counters[CTR_NITEMS];
+  const int nsg = nitems - nlong;
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(&A.counters[CTR_QUEUE], 1);
+    __syncthreads();
+    const int item = S.item;
+    __syncthreads();
+    if (item >= nitems) break;
+    int idx;
+    bool is_long;
+    if (A.short_first) {
+      is_long = item >= nsg;
+      idx = is_long ? item - nsg : item;
+    } else {
+      is_long = item < nlong;
+      idx = is_long ? item : item - nlong;
+    }
+    if (is_long) {
+      cqk_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], S);
+    } else {
+      const int k = idx * kWaves + (int)(threadIdx.x / kWave);
+      if (k < nshort) {
+        const size_t e = (size_t)nlong + k;
+        cqk_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Backward of one wave row.
+template <int SP>
+__device__ void cqk_vjp_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double q = 0.0, m = 0.0;
+  double gv[SP], bd[SP], dv[SP];
+  bool fr[SP];
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int64_t i = lane + (int64_t)k * kWave;
+    fr[k] = false;
+    gv[k] = bd[k] = 0.0;
+    dv[k] = 1.0;
+    if (i < L) {
+      const int64_t e = base + i;
+      const double xv = A.x[e];
+      fr[k] = (xv > A.l[e]) && (xv < A.u[e]);
+      gv[k] = A.g[e];
+      dv[k] = A.d[e];
+      bd[k] = A.b[e];
+      if (fr[k]) {
+        q += bd[k] * bd[k] / dv[k];
+        m += gv[k] * bd[k] / dv[k];
+      }
+    }
+  }
+  q = wave_sum(q);
+  m = wave_sum(m);
+  const double mu = (q > 0.0) ? m / q : 0.0;
+#pragma unroll
+  for (int k = 0; k < SP; ++k) {
+    const int64_t i = lane + (int64_t)k * kWave;
+    if (i < L) A.ga[base + i] = fr[k] ? (gv[k] - bd[k] * mu) / dv[k] : 0.0;
+  }
+  if (lane == 0 && A.gr) A.gr[s] = mu;
+}
+
+// Backward of one workgroup row: the two sums, then the map.
+__device__ void cqk_vjp_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L,
+                                 CqkLds& S) {
+  double acc[2] = {0.0, 0.0};
+  for (int64_t i = threadIdx.x; i < L; i += kBlock) {
+    const int64_t e = base + i;
+    const double xv = A.x[e];
+    if ((xv > A.l[e]) && (xv < A.u[e])) {
+      const double bv = A.b[e], dv = A.d[e];
+      acc[0] += bv * bv / dv;
+      acc[1] += A.g[e] * bv / dv;
+    }
+  }
+  block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, S.red, S.tot);
+  const double q = S.tot[0];
+  const double mu = (q > 0.0) ? S.tot[1] / q : 0.0;
+  for (int64_t i = threadIdx.x; i < L; i += kBlock) {
+    const int64_t e = base + i;
+    const double xv = A.x[e];
+    const bool f = (xv > A.l[e]) && (xv < A.u[e]);
+    A.ga[e] = f ? (A.g[e] - A.b[e] * mu) / A.d[e] : 0.0;
+  }
+  if (threadIdx.x == 0 && A.gr) A.gr[s] = mu;
+}
+
+template <int SP>
+__global__ __launch_bounds__(kBlock) void bat_cqk_vjp_kernel(BatCqkArgs A) {
+  __shared__ CqkLds S;
+  const int nlong = A.counters[CTR_NLONG];
+  const int nshort = A.counters[CTR_NSHORT];
+  const int nitems = A.counters[CTR_NITEMS];
+  const int nsg = nitems - nlong;
+  for (;;) {
+    if (threadIdx.x == 0) S.item = atomicAdd(&A.counters[CTR_QUEUE], 1);
+    __syncthreads();
+    const int item = S.item;
+    __syncthreads();
+    if (item >= nitems) break;
+    int idx;
+    bool is_long;
+    if (A.short_first) {
+      is_long = item >= nsg;
+      idx = is_long ? item - nsg : item;
+    } else {
+      is_long = item < nlong;
+      idx = is_long ? item : item - nlong;
+    }
+    if (is_long) {
+      cqk_vjp_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], S);
+    } else {
+      const int k = idx * kWaves + (int)(threadIdx.x / kWave);
+      if (k < nshort) {
+        const size_t e = (size_t)nlong + k;
+        cqk_vjp_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 struct BatWs {
   int32_t* list;
   int32_t* counters;
@@ -883,11 +1276,12 @@ int persistent_grid(cqk_ctx* ctx, const cqk_batch_schedule& sc, int nseg) {
   return std::max(1, std::min(g, nseg));
 }
 
-void plan(cqk_ctx* ctx, const BatArgs& A) {
+template <typename Args>
+void plan(cqk_ctx* ctx, const Args& A) {
   hipStream_t s = ctx->stream;
   const int gb = std::max(1, (A.nseg + kPBlock - 1) / kPBlock);
-  hipLaunchKernelGGL(bat_count_kernel, dim3(gb), dim3(kPBlock), 0, s, A);
-  hipLaunchKernelGGL(bat_place_kernel, dim3(gb), dim3(kPBlock), 0, s, A);
+  hipLaunchKernelGGL(bat_count_kernel<Args>, dim3(gb), dim3(kPBlock), 0, s, A);
+  hipLaunchKernelGGL(bat_place_kernel<Args>, dim3(gb), dim3(kPBlock), 0, s, A);
 }
 
 void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A) {
@@ -992,6 +1386,107 @@ cqk_status tune(cqk_ctx* ctx, const cqk_batch_schedule* cand, int ncand, int rep
   return CQK_OK;
 }
 
+
+// Batched general CQK: the plan, then one persistent launch.
+BatCqkArgs cqk_args(int32_t nseg, const int64_t* offsets, const double* d, const double* a,
+                    const double* b, const double* l, const double* u, const BatWs& w) {
+  BatCqkArgs A{};
+  A.nseg = nseg;
+  A.small_max = kWave * kCqkSP;
+  A.short_first = 0;
+  A.off = offsets;
+  A.d = d;
+  A.a = a;
+  A.b = b;
+  A.l = l;
+  A.u = u;
+  A.list = w.list;
+  A.counters = w.counters;
+  A.bhist = w.bhist;
+  A.lrow = w.lrow;
+  return A;
+}
+
+int cqk_grid(cqk_ctx* ctx, int nseg) { return std::max(1, std::min(ctx->num_cus * 4, nseg)); }
+
+}  // namespace
+
+cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                               const double* d, const double* a, const double* b,
+                               const double* l, const double* u, const double* r, double* x,
+                               double* lambda_out, int32_t* status_out, const cqk_opts& o,
+                               cqk_info* info) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  BatCqkArgs A = cqk_args(nseg, offsets, d, a, b, l, u, w);
+  A.r = r;
+  A.x = x;
+  A.lam_out = lambda_out;
+  A.status_out = status_out;
+  A.lambda0_mode = o.lambda0_mode;
+  A.lam0_user = o.lambda0_user;
+  A.max_iter = o.max_iter;
+  A.tol = (o.tol > 0.0) ? o.tol : std::pow(2.220446049250313e-16, 0.75);
+  hipStream_t s = ctx->stream;
+  if (o.timing) {
+    st = ensure_events(ctx, 2);
+    if (st != CQK_OK) return st;
+    hipEventRecord(ctx->events[0], s);
+  }
+  plan(ctx, A);
+  hipLaunchKernelGGL(bat_cqk_solve_kernel<kCqkSP>, dim3(cqk_grid(ctx, nseg)), dim3(kBlock), 0, s, A);
+  if (o.timing) hipEventRecord(ctx->events[1], s);
+  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!o.sync) {
+    if (info) info->status = CQK_OK;
+    return CQK_OK;
+  }
+  int32_t* hc = (int32_t*)ctx->host_pinned;
+  if (hip_ok(hipMemcpyAsync(hc, A.counters, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            s)) != CQK_OK)
+    return CQK_DEVICE_ERROR;
+  if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+  const int flags = hc[CTR_FLAGS];
+  int status = CQK_OK;
+  if (flags & kBadValue) status = CQK_INVALID_ARG;
+  else if (flags & kInfeasible) status = CQK_INFEASIBLE;
+  else if (flags & kNotConverged) status = CQK_NOT_CONVERGED;
+  if (info) {
+    info->status = status;
+    info->iterations = hc[CTR_ITMAX];
+    info->passes = hc[CTR_ITSUM];
+    if (o.timing) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
+      info->pass_ms = ms;
+    }
+  }
+  return CQK_OK;
+}
+
+cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                        const double* x, const double* g, const double* d,
+                                        const double* b, const double* l, const double* u,
+                                        double* grad_a, double* grad_r, const cqk_opts& o) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  BatCqkArgs A = cqk_args(nseg, offsets, d, nullptr, b, l, u, w);
+  A.x = const_cast<double*>(x);
+  A.g = g;
+  A.ga = grad_a;
+  A.gr = grad_r;
+  plan(ctx, A);
+  hipLaunchKernelGGL(bat_cqk_vjp_kernel<kCqkSP>, dim3(cqk_grid(ctx, nseg)), dim3(kBlock), 0,
+                     ctx->stream, A);
+  if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
+  return CQK_OK;
+}
+
+namespace {
 }  // namespace
 
 bool valid_schedule(const cqk_batch_schedule& sc) {

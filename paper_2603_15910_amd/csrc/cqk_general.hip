@@ -37,6 +37,7 @@
 #include <cstring>
 #include <type_traits>
 
+#include "cqk_alg1.h"
 #include "cqk_device.h"
 #include "cqk_internal.h"
 
@@ -51,28 +52,6 @@ constexpr int kStage = 256;  // LDS ring per wave and array for compaction
 constexpr int kPieceLog = 7;
 constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
 static_assert(kPiece == 2 * kWave, "a full flush writes one piece, two values per lane");
-
-// Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
-// two (key, weight) pairs instead.
-enum {
-  P_P = 0,     // sum g_i(lam)
-  P_A,         // sum |g_i(lam)|
-  P_QP,        // phi'_+ part
-  P_QM,        // phi'_- part
-  P_DF,        // bounds of indices fixed in this pass
-  P_DAF,       // |bounds| of indices fixed in this pass
-  P_DC0,       // c of indices found free on the bracket
-  P_DC1,       // s of those
-  P_DA0,       // sgn * c of those
-  P_DA1,       // sgn * s of those
-  P_NIN,       // indices read
-  P_NOUT,      // indices written
-  P_PREDLO,    // survivors if lo moves to lam
-  P_PREDHI,    // survivors if hi moves to lam
-  P_BAD,       // indices failing the input checks
-  NSUM
-};
-constexpr int NPART = NSUM;
 
 struct GenArgs {
   const void* d;
@@ -92,84 +71,6 @@ struct GenArgs {
   GenState* st;
   cqk_trace_rec* trace;
 };
-
-struct Acc {
-  double s[NSUM];
-};
-
-__device__ __forceinline__ void acc_init(Acc& a) {
-#pragma unroll
-  for (int i = 0; i < NSUM; ++i) a.s[i] = 0.0;
-}
-
-// Per-index form of the original data (eq. (xopt) times b), with the input
-// checks of Section 5.
-__device__ __forceinline__ void to_form(double d, double a, double b, double l, double u,
-                                        double& c, double& s, double& bl, double& bu,
-                                        double& bad) {
-  const double inv = 1.0 / d;
-  c = (b * a) * inv;
-  s = (b * b) * inv;
-  bl = b * l;
-  bu = b * u;
-  const bool ok = (d > 0.0) && (d < inf_d()) && (b > 0.0) && (b < inf_d()) &&
-                  (fabs(a) < inf_d()) && (l <= u) && (l < inf_d()) && (u > -inf_d());
-  bad += ok ? 0.0 : 1.0;
-}
-
-// One index of an evaluation pass.  Returns true if the index survives
-// compaction (always true when not compacting).
-template <bool COMPACT>
-__device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double bl, double bu,
-                                           double lam, double lo, double hi) {
-  const double f = fma(s, lam, c);
-  const double g = fmin(fmax(f, bl), bu);
-  acc.s[P_P] += g;
-  acc.s[P_A] += fabs(g);
-  const bool ge_l = f >= bl, gt_l = f > bl, lt_u = f < bu, le_u = f <= bu;
-  acc.s[P_QP] += (ge_l && lt_u) ? s : 0.0;
-  acc.s[P_QM] += (gt_l && le_u) ? s : 0.0;
-  acc.s[P_NIN] += 1.0;
-  const double fl = fma(s, lo, c);
-  const double fh = fma(s, hi, c);
-  const bool fix_l = fh <= bl;
-  const bool fix_u = fl >= bu;
-  // resolved under the two brackets the update can produce
-  const bool res_lo_lam = (f <= bl) || fix_u || ((fl >= bl) && le_u && (fl >= 0.0 || f <= 0.0));
-  const bool res_lam_hi = fix_l || (f >= bu) || (ge_l && (fh <= bu) && (f >= 0.0 || fh <= 0.0));
-  acc.s[P_PREDHI] += res_lo_lam ? 0.0 : 1.0;
-  acc.s[P_PREDLO] += res_lam_hi ? 0.0 : 1.0;
-  if (!COMPACT) return true;
-  // fixed at a bound on the whole bracket, else free on the whole bracket
-  // with one sign; written as selects so the accumulators stay in registers
-  const double fixv = fix_l ? bl : (fix_u ? bu : 0.0);
-  acc.s[P_DF] += fixv;
-  acc.s[P_DAF] += fabs(fixv);
-  const bool freeb = !fix_l && !fix_u && (fl >= bl) && (fh <= bu) && (fl >= 0.0 || fh <= 0.0);
-  const double sg = (fl >= 0.0) ? 1.0 : -1.0;
-  const double fc = freeb ? c : 0.0, fs = freeb ? s : 0.0;
-  acc.s[P_DC0] += fc;
-  acc.s[P_DC1] += fs;
-  acc.s[P_DA0] += sg * fc;
-  acc.s[P_DA1] += sg * fs;
-  return !(fix_l || fix_u || freeb);
-}
-
-// Closest breakpoints around lam (Algorithm 1, breakpoint steps), with the
-// slope that opens there.  The candidates are chosen with the same predicate
-// the slopes use (an index below its lower bound at lam can only become free
-// as lam grows), so an index that rounding left on the wrong side of a
-// breakpoint equal to lam is still found (its key is then lam itself).
-// Indices with l = u never become free and are skipped.
-//   ks[0]: (min over candidates of max(lbar_i, lam), sum of s_i at that key)
-//   ks[1]: (min of -min(ubar_i, lam), sum of s_i)  -- the left search
-__device__ __forceinline__ void bkpt_index(KeySum* ks, double c, double s, double bl, double bu,
-                                           double lam) {
-  if (!(bl < bu)) return;
-  const double f = fma(s, lam, c);
-  if (f < bl) ks[0] = ks_min(ks[0], KeySum{fmax((bl - c) / s, lam), s});
-  if (f > bu) ks[1] = ks_min(ks[1], KeySum{-fmin((bu - c) / s, lam), s});
-}
 
 // Sources: the caller's arrays or a compacted region.
 template <typename TIn>
@@ -405,159 +306,6 @@ __device__ void bkpt_pass(const Src& src, int64_t count, int64_t first, int64_t 
   }
 }
 
-__device__ void trace_push(GenState* st, cqk_trace_rec* tr, int kind, int compacted, int source,
-                           double lam, double phi, double slope, int64_t nin, int64_t nout) {
-  if (st->ntrace < st->trace_cap) {
-    cqk_trace_rec& t = tr[st->ntrace];
-    t.iter = st->iter;
-    t.kind = kind;
-    t.compacted = compacted;
-    t.source = source;
-    t.lam = lam;
-    t.phi = phi;
-    t.slope = slope;
-    t.lo = st->lo;
-    t.hi = st->hi;
-    t.n_in = nin;
-    t.n_out = nout;
-  }
-  st->ntrace += 1;
-}
-
-__device__ __forceinline__ void finish(GenState* st, double lamf, int reason) {
-  st->status = CQK_OK;
-  st->lam_final = lamf;
-  st->stop_reason = reason;
-}
-
-__device__ __forceinline__ void advance(GenState* st, double next) {
-  st->lam_prev = st->lam;
-  st->lam = next;
-  st->mode = kModeEval;
-  if (st->iter >= st->max_iter) {
-    st->status = CQK_NOT_CONVERGED;
-    st->lam_final = st->lam_prev;
-  }
-}
-
-// The scalar part of Algorithm 1, run by one thread after an evaluation pass.
-__device__ __forceinline__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
-  const double lam = st->lam;
-  const bool compacted = st->compact_next != 0;
-  const int source = st->src;
-  st->passes += 1;
-  if (t[P_BAD] > 0.0) {
-    st->status = CQK_INVALID_ARG;
-    return;
-  }
-  // algorithmic bytes: the set read (caller's arrays or the 32-byte form) and
-  // the survivors written
-  st->bytes += ((source == 0) ? st->in_bytes : 32.0) * t[P_NIN] + (compacted ? 32.0 * t[P_NOUT] : 0.0);
-  const double phi = (st->F + st->C0) + (lam * st->C1 + t[P_P]);
-  const double A = (st->AF + st->A0) + (lam * st->A1 + t[P_A]);
-  const double Qp = st->C1 + t[P_QP];
-  const double Qm = st->C1 + t[P_QM];
-  if (compacted) {
-    st->F += t[P_DF];
-    st->AF += t[P_DAF];
-    st->C0 += t[P_DC0];
-    st->C1 += t[P_DC1];
-    st->A0 += t[P_DA0];
-    st->A1 += t[P_DA1];
-    st->src = (source == 1) ? 2 : 1;
-    st->n_src = (int64_t)t[P_NOUT];
-  } else {
-    st->n_src = (int64_t)t[P_NIN];
-  }
-  st->compact_next = 0;
-  const double r = st->r, tol = st->tol;
-  const double res = phi - r;
-  // selects rather than branches, so the state stays in registers
-  const double lo = (res < 0.0) ? lam : st->lo;
-  const double hi = (res > 0.0) ? lam : st->hi;
-  st->phi_lo = (res < 0.0) ? phi : st->phi_lo;
-  st->phi_hi = (res > 0.0) ? phi : st->phi_hi;
-  st->lo = lo;
-  st->hi = hi;
-  const double slope = (res < 0.0) ? Qp : Qm;
-  trace_push(st, tr, 1, compacted ? 1 : 0, source, lam, phi, slope, (int64_t)t[P_NIN],
-             compacted ? (int64_t)t[P_NOUT] : 0);
-  st->iter += 1;
-  // Section 5 criterion 1 (and the exact stop of Algorithm 1)
-  if (res == 0.0) return finish(st, lam, 4);
-  if (fabs(res) < tol * (A + fabs(r))) return finish(st, lam, 1);
-  // compaction decision for the next evaluation pass
-  if (st->compaction != CQK_COMPACT_OFF) {
-    const double pred = (res < 0.0) ? t[P_PREDLO] : t[P_PREDHI];
-    const double ncur = (double)st->n_src;
-    st->compact_next = (st->compaction == CQK_COMPACT_ALWAYS) ? (pred < ncur)
-                                                              : (pred <= st->theta * ncur);
-  }
-  // criterion 3
-  if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, lam, 3);
-  double next;
-  bool secant = false;
-  if (slope > 0.0) {
-    const double step = res / slope;
-    if (fabs(step) < tol) return finish(st, fmin(fmax(lam - step, lo), hi), 2);  // criterion 2
-    next = lam - step;
-    secant = (res < 0.0) ? !(next < hi) : !(next > lo);
-  } else {
-    // slope zero: the closest breakpoint in the needed direction
-    st->mode = (res < 0.0) ? kModeBreakRight : kModeBreakLeft;
-    return;
-  }
-  if (secant) {
-    next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
-    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
-  }
-  if (next == lam) return finish(st, lam, 2);  // criterion 2, lam_{k-1} = lam_k
-  advance(st, next);
-}
-
-// Breakpoint step of Algorithm 1.  phi is constant between lam_k and the
-// closest breakpoint bp (no index changes on that interval), so the next
-// iterate lam_{k+1} = bp is evaluated without another pass: phi(bp) =
-// phi(lam_k) and the one-sided slope at bp is the summed s of the indices
-// whose breakpoint is bp.  The Newton step from bp follows as in Algorithm 1.
-__device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks, cqk_trace_rec* tr) {
-  st->passes += 1;
-  st->bytes += ((st->src == 0) ? st->in_bytes : 32.0) * (double)st->n_src;
-  const bool right = st->mode == kModeBreakRight;
-  const double bp = right ? ks[0].k : -ks[1].k;
-  const double sw = right ? ks[0].w : ks[1].w;
-  trace_push(st, tr, 2, 0, st->src, st->lam, bp, sw, (int64_t)st->n_src, 0);
-  if (!(fabs(bp) < inf_d())) {
-    st->status = CQK_INFEASIBLE;
-    return;
-  }
-  const double phi = right ? st->phi_lo : st->phi_hi;
-  const double r = st->r, tol = st->tol;
-  const double res = phi - r;
-  const double lo = right ? bp : st->lo, hi = right ? st->hi : bp;
-  st->lo = lo;
-  st->hi = hi;
-  trace_push(st, tr, 5, 0, st->src, bp, phi, sw, 0, 0);
-  st->iter += 1;
-  st->lam_prev = st->lam;
-  st->lam = bp;
-  if (st->iter >= st->max_iter) {
-    st->status = CQK_NOT_CONVERGED;
-    st->lam_final = bp;
-    return;
-  }
-  if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, bp, 3);
-  if (!(sw > 0.0)) return;  // still flat past bp: search again from bp
-  const double step = res / sw;
-  double next = bp - step;
-  if (fabs(step) < tol) return finish(st, fmin(fmax(next, lo), hi), 2);
-  if (!(next > lo && next < hi)) {
-    next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
-    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
-  }
-  if (next == bp) return finish(st, bp, 2);
-  advance(st, next);
-}
 
 // One pass over the current index set.  Every block writes one partial
 // record; the scalar update runs in gen_update_kernel, so no block needs a

@@ -135,6 +135,16 @@ cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float*
 cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw,
                            SparseOut* sp, double r, double* x, bool l1, const cqk_opts& o,
                            cqk_info* info);
+// Batched general CQK (FP64 rows) and its VJP w.r.t. a and r.
+cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                               const double* d, const double* a, const double* b,
+                               const double* l, const double* u, const double* r, double* x,
+                               double* lambda_out, int32_t* status_out, const cqk_opts& o,
+                               cqk_info* info);
+cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                        const double* x, const double* g, const double* d,
+                                        const double* b, const double* l, const double* u,
+                                        double* grad_a, double* grad_r, const cqk_opts& o);
 cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                            const double* r, double r_scalar, float* x, double* lambda_out,
                            int32_t* nfree_out, const cqk_opts& o, cqk_info* info);

@@ -19,6 +19,9 @@ Section 5.2.1 for the simplex):
                       not say whether 1e-3 is a variance or a deviation; it is
                       used as the deviation here); redrawn if any y_i == 0.
 * ``segment_offsets`` row lengths round(exp(U[ln lo, ln hi])) (log-uniform).
+* ``cqk_batched``     rows of log-uniform length (``segment_offsets``), the
+                      values drawn as in ``cqk_uniform`` over all rows, and
+                      r per row = b^T(l+u)/2 over the row (feasible).
 * ``perturbed``       v + eps * std(v) * N(0,1), the next point of an outer
                       loop whose previous projection serves as a warm start
                       (Section 3.1): for CQK only a is perturbed,
@@ -117,6 +120,18 @@ def batched_simplex_input(nseg: int, lo: int, hi: int, seed: int, scale: float =
 
 def upstream_grad(n: int, seed: int, dtype=np.float32):
     return _rng(seed + 104729).standard_normal(n).astype(dtype)
+
+
+def cqk_batched(nseg: int, lo: int, hi: int, seed: int):
+    """Returns (offsets, instance dict with r a float64 array per row)."""
+    off = segment_offsets(nseg, lo, hi, seed)
+    inst = cqk_uniform(int(off[-1]), seed + 31337)
+    mid = inst["b"] * (inst["l"] + inst["u"]) * 0.5
+    r = np.zeros(nseg)
+    for s in range(nseg):
+        r[s] = float(np.sum(mid[off[s]:off[s + 1]]))
+    inst["r"] = r
+    return off, inst
 
 
 def perturbed(v, seed: int, eps: float = 1e-3):

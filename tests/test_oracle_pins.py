@@ -465,6 +465,60 @@ def test_batched_rowwise():
         assert lam[s] == ls
 
 
+def test_cqk_batched_rows_are_independent():
+    """Each row is solved on its own slice: reversing the row order reverses
+    the results, an empty row is OK exactly when its r is 0, and a row's
+    solution satisfies eq. (opt) with its own r."""
+    off, inst = W.cqk_batched(9, 1, 60, 21)
+    d, a, b, l, u, r = (inst[k] for k in "dablur")
+    lens = np.diff(off)
+    res = O.solve_cqk_batched(d, a, b, l, u, off, r)
+    # reversed rows
+    order = np.arange(9)[::-1]
+    pieces = [np.arange(off[s], off[s + 1]) for s in order]
+    perm = np.concatenate(pieces)
+    off_r = np.concatenate([[0], np.cumsum(lens[order])])
+    res_r = O.solve_cqk_batched(d[perm], a[perm], b[perm], l[perm], u[perm], off_r, r[order])
+    for k, s in enumerate(order):
+        assert res_r[k].status == res[s].status == O.OK
+        np.testing.assert_array_equal(res_r[k].x, res[s].x)
+        lo, hi = off[s], off[s + 1]
+        assert abs(float(np.dot(b[lo:hi], res[s].x)) - r[s]) <= 1e-11 * max(1.0, abs(r[s]))
+    # an empty row between two rows
+    off_e = np.array([0, 3, 3, 6])
+    z = np.ones(6)
+    e = O.solve_cqk_batched(z, z, z, 0 * z, 2 * z, off_e, np.array([3.0, 0.0, 3.0]))
+    assert [x.status for x in e] == [O.OK, O.OK, O.OK]
+    e = O.solve_cqk_batched(z, z, z, 0 * z, 2 * z, off_e, np.array([3.0, 1.0, 3.0]))
+    assert e[1].status == O.INFEASIBLE
+
+
+def test_cqk_vjp_batched_finite_differences():
+    """The batched VJP against FP64 central differences of the batched solve
+    w.r.t. every a_i and every row's r."""
+    off, inst = W.cqk_batched(4, 2, 12, 22)
+    d, a, b, l, u, r = (inst[k] for k in "dablur")
+    n = d.size
+    rng = np.random.default_rng(23)
+    g = rng.standard_normal(n)
+
+    def f(aa, rr):
+        xs = [res.x for res in O.solve_cqk_batched(d, aa, b, l, u, off, rr)]
+        return float(np.dot(g, np.concatenate(xs)))
+
+    x = np.concatenate([res.x for res in O.solve_cqk_batched(d, a, b, l, u, off, r)])
+    ga, gr = O.cqk_vjp_batched(x, g, d, b, l, u, off)
+    h = 1e-6
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        assert abs(ga[i] - (f(a + e, r) - f(a - e, r)) / (2 * h)) < 1e-7
+    for s in range(4):
+        e = np.zeros(4)
+        e[s] = h
+        assert abs(gr[s] - (f(a, r + e) - f(a, r - e)) / (2 * h)) < 1e-7
+
+
 # ---------------------------------------------------------------------------
 # Warm starts from a primal estimate (Section 2.1 end, Section 3.1)
 # ---------------------------------------------------------------------------
