@@ -47,6 +47,15 @@ Functions and the passage each follows:
 * ``simplex_vjp``       -- vector-Jacobian product of the simplex projection
                            on its (fixed) support, from eq. (lambdaJ).
 * ``cqk_vjp``           -- the same for general CQK, from eq. (xopt)/(opt).
+* ``solve_cqk_batched``, ``cqk_vjp_batched`` -- plain loops over rows.
+* ``spg_l1_lasso``      -- the l1-constrained least-squares problem of
+                           Section 5.2 (basis pursuit) solved by the spectral
+                           projected gradient method the paper uses there
+                           (Birgin, Martinez and Raydan's SPG2: spectral step,
+                           non-monotone line search), each projection by
+                           ``project_l1``, started at the origin, stopped when
+                           the infinity norm of the projected gradient falls
+                           below the tolerance.
 
 Readings of passages the paper leaves open are listed next to the code that
 takes them.  Parity pins for every function live in ``tests/test_oracle_*``.
@@ -752,3 +761,82 @@ def simplex_vjp_batched(x, g, offsets):
         if hi > lo:
             ga[lo:hi], gr[s] = simplex_vjp(x[lo:hi], g[lo:hi])
     return ga, gr
+
+
+# ---------------------------------------------------------------------------
+# SPG for the l1-constrained least-squares problem (Section 5.2, basis
+# pursuit): min 1/2 ||A x - b||^2  s.t.  ||x||_1 <= radius
+# ---------------------------------------------------------------------------
+SPG_GAMMA = 1e-4     # sufficient decrease
+SPG_SIGMA1 = 0.1     # safeguards of the quadratic interpolation
+SPG_SIGMA2 = 0.9
+SPG_LMIN = 1e-30     # spectral step bounds
+SPG_LMAX = 1e30
+
+
+def spg_l1_lasso(A, b, radius, tol=1e-4, max_iter=10000, memory=10):
+    """The spectral projected gradient method (SPG2 of Birgin, Martinez and
+    Raydan) on f(x) = 1/2 ||Ax - b||^2 over the l1 ball, as Section 5.2
+    applies it: x_0 = 0; the step length of iteration k is the spectral
+    (Barzilai-Borwein) quotient s's/s'y of the previous step, clipped to
+    [1e-30, 1e30] (1e30 when s'y <= 0), the first one 1/||P(x_0 - g_0) -
+    x_0||_inf; the direction d = P(x - lam g) - x; the non-monotone line
+    search accepts t when f(x + t d) <= max of the last `memory` values of f
+    + 1e-4 t g'd, else t becomes the minimiser of the quadratic through
+    f(x), g'd and f(x + t d) if that lies in [0.1, 0.9 t], else t/2.  Stops
+    when ||P(x - g) - x||_inf <= tol.
+
+    f and g are formed from their definitions at every point (A x - b, then
+    A^T of it).  Returns (x, info) with info: iterations, f, pg,
+    projections, status ("OK" or "NOT_CONVERGED")."""
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = A.shape[1]
+
+    def f_of(x):
+        res = A @ x - b
+        return 0.5 * float(res @ res)
+
+    def grad(x):
+        return A.T @ (A @ x - b)
+
+    def proj(v):
+        return project_l1(v, radius)[0]
+
+    x = proj(np.zeros(n))
+    g = grad(x)
+    fx = f_of(x)
+    hist = [fx]
+    pg = float(np.max(np.abs(proj(x - g) - x))) if n else 0.0
+    lam = min(SPG_LMAX, max(SPG_LMIN, 1.0 / pg)) if pg > 0 else 1.0
+    nproj = 2
+    it = 0
+    status = OK
+    while pg > tol:
+        if it >= max_iter:
+            status = NOT_CONVERGED
+            break
+        d = proj(x - lam * g) - x
+        nproj += 1
+        gtd = float(g @ d)
+        fmax = max(hist[-memory:])
+        t = 1.0
+        while True:
+            fn = f_of(x + t * d)
+            if fn <= fmax + SPG_GAMMA * t * gtd:
+                break
+            tq = -0.5 * t * t * gtd / (fn - fx - t * gtd)
+            t = tq if (SPG_SIGMA1 <= tq <= SPG_SIGMA2 * t) else 0.5 * t
+        s_ = t * d
+        x = x + s_
+        gn = grad(x)
+        y_ = gn - g
+        g = gn
+        fx = fn
+        hist.append(fx)
+        sty = float(s_ @ y_)
+        lam = SPG_LMAX if sty <= 0 else min(SPG_LMAX, max(SPG_LMIN, float(s_ @ s_) / sty))
+        it += 1
+        pg = float(np.max(np.abs(proj(x - g) - x)))
+        nproj += 1
+    return x, {"iterations": it, "f": fx, "pg": pg, "projections": nproj, "status": status}

@@ -595,3 +595,57 @@ def test_simplex_warm_fallback():
     assert J == [] and lam0 == max(1.0 / 4, -0.9)
     lam0, J = O.simplex_lambda0_warm(y, 5.0, np.zeros(4))
     assert lam0 == 5.0 / 4
+
+
+# ---------------------------------------------------------------------------
+# SPG on the l1-constrained least-squares problem (Section 5.2)
+# ---------------------------------------------------------------------------
+def test_spg_identity_matrix_is_one_projection():
+    """A = I: the minimiser of 1/2||x - b||^2 on the ball is P(b)."""
+    rng = np.random.default_rng(61)
+    b = rng.standard_normal(50)
+    for radius in (0.5, 3.0, 1e3):
+        x, info = O.spg_l1_lasso(np.eye(50), b, radius, tol=1e-12)
+        assert info["status"] == O.OK
+        np.testing.assert_allclose(x, O.project_l1(b, radius)[0], atol=1e-12)
+
+
+def test_spg_inactive_ball_is_least_squares():
+    rng = np.random.default_rng(62)
+    A = rng.standard_normal((80, 30))
+    b = rng.standard_normal(80)
+    x, info = O.spg_l1_lasso(A, b, 1e3, tol=1e-11)
+    assert info["status"] == O.OK
+    np.testing.assert_allclose(x, np.linalg.lstsq(A, b, rcond=None)[0], atol=1e-9)
+
+
+def test_spg_active_ball_matches_a_qp_solver():
+    """x = p - q with p, q >= 0 and sum(p + q) <= radius turns the problem
+    into a smooth QP; scipy's SLSQP on it gives the same optimal value."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(63)
+    A = rng.standard_normal((12, 6))
+    b = rng.standard_normal(12)
+    radius = 0.7
+    x, info = O.spg_l1_lasso(A, b, radius, tol=1e-12)
+    assert info["status"] == O.OK
+    assert abs(np.sum(np.abs(x)) - radius) < 1e-10   # the ball is active here
+
+    def obj(z):
+        r = A @ (z[:6] - z[6:]) - b
+        return 0.5 * r @ r
+
+    cons = [{"type": "ineq", "fun": lambda z: radius - np.sum(z)}]
+    sol = minimize(obj, np.full(12, 0.01), method="SLSQP", bounds=[(0, None)] * 12,
+                   constraints=cons, options={"ftol": 1e-15, "maxiter": 1000})
+    assert abs(info["f"] - sol.fun) <= 1e-8 * max(1.0, sol.fun)
+    assert info["f"] <= sol.fun + 1e-12
+
+
+def test_spg_iteration_limit():
+    rng = np.random.default_rng(64)
+    A = rng.standard_normal((40, 100))
+    b = rng.standard_normal(40)
+    x, info = O.spg_l1_lasso(A, b, 2.0, tol=1e-14, max_iter=3)
+    assert info["status"] == O.NOT_CONVERGED and info["iterations"] == 3
+    assert np.sum(np.abs(x)) <= 2.0 + 1e-12
