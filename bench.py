@@ -117,7 +117,7 @@ def graph_replay_ms(torch, fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-EXTRA_SECTIONS = ("correlated", "simplex", "warm", "batched", "differentiable")
+EXTRA_SECTIONS = ("correlated", "simplex", "warm", "batched", "differentiable", "spg")
 
 
 def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
@@ -138,6 +138,8 @@ def extras(ctx, dev, torch, sections=EXTRA_SECTIONS, row_loop=True):
         ex.update(extra_batched(ctx, dev, torch, row_loop))
     if "differentiable" in sections:
         ex.update(extra_differentiable(ctx, dev, torch))
+    if "spg" in sections:
+        ex.update(extra_spg(ctx, dev, torch))
     ctx.set_batch_schedule(**default_sched)
     ctx.set_batch_schedule(**default_sched, backward=True)
     return ex
@@ -379,6 +381,35 @@ def extra_batched_cqk(ctx, dev, torch, row_loop=True):
         "per_row_loop_ms_scaled_from_512_rows": loop_ms,
         "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}}
     del t, x, g, ga, gr, offs, r
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_spg(ctx, dev, torch):
+    """SPG on the l1-constrained least-squares problem of Section 5.2 with a
+    random 2048 x 65536 FP64 matrix (1 GiB), a 200-sparse x_true and the
+    radius ||x_true||_1; projections warm-started from the iterate, and
+    cold, to the paper's tolerance 1e-4."""
+    from paper_2603_15910_amd import workloads as W
+    A, b, x_true = W.lasso_instance(2048, 65536, 200, 1)
+    radius = float(np.sum(np.abs(x_true)))
+    At = torch.from_numpy(A).to(dev)
+    bt = torch.from_numpy(b).to(dev)
+    del A
+    x = torch.empty(65536, dtype=torch.float64, device=dev)
+    out = {}
+    for name, warm in (("warm", True), ("cold", False)):
+        ctx.spg_l1_lasso(At, bt, radius, out=x, warm=warm, max_iter=5, check=False)
+        _, info = ctx.spg_l1_lasso(At, bt, radius, out=x, warm=warm)
+        it = max(1, info["iterations"])
+        out[f"spg_l1_lasso_2048x65536_f64_{name}"] = {
+            "ms": info["total_ms"], "iterations": info["iterations"],
+            "ms_per_iteration": info["total_ms"] / it,
+            "projection_ms": info["proj_ms"], "projections": info["projections"],
+            "newton_iterations_per_projection": info["newton_iterations"] / max(1, info["projections"]),
+            "objective": info["objective"], "pg": info["pg"], "status": info["status_name"],
+            "matrix_gbs": 2 * 2048 * 65536 * 8 * it / ((info["total_ms"] - info["proj_ms"]) * 1e-3) / 1e9}
+    del At, bt, x
     torch.cuda.empty_cache()
     return out
 

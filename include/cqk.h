@@ -249,6 +249,44 @@ cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
                                      int64_t* idx, double* val, int64_t* nnz,
                                      const cqk_opts* opts, cqk_info* info);
 
+/* Spectral projected gradient on the l1-constrained least-squares problem
+ * of Section 5.2 (basis pursuit):
+ *     min 1/2 ||A x - b||^2   s.t.  ||x||_1 <= radius,
+ * every projection by the l1 projection above, warm-started from the
+ * current iterate (Section 3.1) unless opts->warm = 0.  Steps of SPG2
+ * (Birgin, Martinez, Raydan): x_0 = 0, spectral step clipped to
+ * [1e-30, 1e30], non-monotone line search over the last `memory` values
+ * with sufficient-decrease constant 1e-4 and safeguarded quadratic
+ * interpolation in [0.1, 0.9] t; stops when ||P(x - g) - x||_inf <= tol.
+ * A: DEVICE float64 m x n row-major; b: DEVICE float64[m]; x: DEVICE
+ * float64[n] output (must not overlap A or b).  Two products with A and
+ * two projections per iteration; the host reads a few scalars per step.
+ * NOT_CONVERGED: max_iter reached (x is the last iterate).  A projection's
+ * failure status is returned as is. */
+typedef struct cqk_spg_opts {
+  double tol;               /* projected-gradient tolerance; default 1e-4 */
+  int32_t max_iter;         /* default 10000 */
+  int32_t memory;           /* non-monotone line search memory; default 10 */
+  int32_t warm;             /* 1 (default): warm-started projections */
+  int32_t pad_;
+} cqk_spg_opts;
+
+typedef struct cqk_spg_info {
+  int32_t status;
+  int32_t iterations;       /* SPG iterations */
+  int64_t projections;      /* l1 projections made */
+  int64_t newton_iterations;/* Newton iterations summed over the projections */
+  double objective;         /* 1/2 ||A x - b||^2 at the returned x */
+  double pg;                /* ||P(x - g) - x||_inf there */
+  double total_ms;          /* host wall time of the call */
+  double proj_ms;           /* of which in the projections */
+} cqk_spg_info;
+
+void cqk_spg_default_opts(cqk_spg_opts* opts);
+cqk_status cqk_spg_l1_lasso_f64(cqk_ctx* ctx, int64_t m, int64_t n, const double* A,
+                                const double* b, double radius, double* x,
+                                const cqk_spg_opts* opts, cqk_spg_info* info);
+
 /* Many simplex projections in one launch: row s is y[offsets[s] ..
  * offsets[s+1]) (Section 3 Algorithms 2 and 4 applied per row).
  * offsets: int64[nseg+1] DEVICE array, non-decreasing, offsets[0] = 0.

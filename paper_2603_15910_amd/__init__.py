@@ -28,7 +28,7 @@ __all__ = [
     "CQK_OK", "CQK_INFEASIBLE", "CQK_INVALID_ARG", "CQK_NOT_CONVERGED", "CQK_DEVICE_ERROR",
     "CQK_NO_MEMORY", "CQK_BUFFER_TOO_SMALL", "CqkError", "CqkLibraryMissing", "Context", "solve",
     "project_simplex", "project_l1", "project_simplex_sparse", "project_l1_sparse",
-    "solve_batched", "solve_batched_backward", "CqkBatchedSolve",
+    "solve_batched", "solve_batched_backward", "CqkBatchedSolve", "spg_l1_lasso",
     "project_simplex_batched", "project_simplex_batched_backward", "SimplexProjection", "lib",
 ]
 
@@ -182,6 +182,21 @@ def cqk_project_l1_sparse_f64(ctx, n, y, xbar, radius, cap, idx, val, opts=None,
     """Returns (status, nnz)."""
     return _sparse("cqk_project_l1_sparse_f64", ctx, n, y, xbar, radius, cap, idx, val, opts,
                    info)
+
+
+def cqk_spg_l1_lasso_f64(ctx, m, n, A, b, radius, x, opts=None, info=None):
+    return _call("cqk_spg_l1_lasso_f64", C.c_void_p(ctx), m, n, A, b, radius, x, _ref(opts),
+                 _ref(info))
+
+
+def spg_opts(tol=1e-4, max_iter=10000, memory=10, warm=True):
+    o = L.cqk_spg_opts()
+    lib().cqk_spg_default_opts(C.byref(o))
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.memory = int(memory)
+    o.warm = 1 if warm else 0
+    return o
 
 
 def cqk_solve_batched_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out=None,
@@ -467,6 +482,29 @@ class Context:
             raise CqkError(st, "cqk_solve_batched_backward_f64")
         return ga
 
+    def spg_l1_lasso(self, A, b, radius, out=None, check=True, **kw):
+        """min 1/2||A x - b||^2 s.t. ||x||_1 <= radius by SPG with warm-started
+        l1 projections.  A: float64 GPU tensor [m, n] (row-major), b [m].
+        kw: tol, max_iter, memory, warm.  Returns (x, info)."""
+        torch = _torch()
+        if A.dim() != 2:
+            raise ValueError("A must be a matrix")
+        m, n = A.shape
+        if b.numel() != m:
+            raise ValueError("b needs one value per row of A")
+        x = out if out is not None else torch.empty(n, dtype=torch.float64, device=A.device)
+        pa = _dev_ptr(A, torch.float64, "A")
+        pb = _dev_ptr(b, torch.float64, "b")
+        px = _dev_ptr(x, torch.float64, "x")
+        info = L.cqk_spg_info()
+        self._bind_stream()
+        st = cqk_spg_l1_lasso_f64(self.handle, m, n, pa, pb, float(radius), px, spg_opts(**kw),
+                                  info)
+        self.last_info = info.as_dict()
+        if check and st != CQK_OK:
+            raise CqkError(st, "cqk_spg_l1_lasso_f64")
+        return x, self.last_info
+
     def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
                                 nfree_out=None, check=True, **kw):
         torch = _torch()
@@ -598,6 +636,10 @@ def project_simplex_batched(y, offsets, r=1.0, **kw):
 
 def project_simplex_batched_backward(x, g, offsets, **kw):
     return default_context(x.device).project_simplex_batched_backward(x, g, offsets, **kw)
+
+
+def spg_l1_lasso(A, b, radius, **kw):
+    return default_context(A.device).spg_l1_lasso(A, b, radius, **kw)
 
 
 def solve_batched(d, a, b, l, u, offsets, r, **kw):

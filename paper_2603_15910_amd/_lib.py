@@ -103,6 +103,34 @@ class cqk_batch_schedule(C.Structure):
         return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "reserved"}
 
 
+class cqk_spg_opts(C.Structure):
+    _fields_ = [
+        ("tol", C.c_double),
+        ("max_iter", C.c_int32),
+        ("memory", C.c_int32),
+        ("warm", C.c_int32),
+        ("pad_", C.c_int32),
+    ]
+
+
+class cqk_spg_info(C.Structure):
+    _fields_ = [
+        ("status", C.c_int32),
+        ("iterations", C.c_int32),
+        ("projections", C.c_int64),
+        ("newton_iterations", C.c_int64),
+        ("objective", C.c_double),
+        ("pg", C.c_double),
+        ("total_ms", C.c_double),
+        ("proj_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        d = {f[0]: getattr(self, f[0]) for f in self._fields_}
+        d["status_name"] = STATUS_NAMES.get(d["status"], str(d["status"]))
+        return d
+
+
 _P = C.c_void_p
 _I64 = C.c_int64
 _I32 = C.c_int32
@@ -135,6 +163,9 @@ SIGNATURES = {
                                         _OPTS, _INFO]),
     "cqk_solve_batched_backward_f64": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
                                                  _P, _OPTS]),
+    "cqk_spg_default_opts": (None, [C.POINTER(cqk_spg_opts)]),
+    "cqk_spg_l1_lasso_f64": (C.c_int, [_P, _I64, _I64, _P, _P, _D, _P, C.POINTER(cqk_spg_opts),
+                                       C.POINTER(cqk_spg_info)]),
     "cqk_solve_warm_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_warm_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),

@@ -209,6 +209,7 @@ void cqk_destroy(cqk_ctx* ctx) {
   if (ctx->ws.ptr) hipFree(ctx->ws.ptr);
   if (ctx->state.ptr) hipFree(ctx->state.ptr);
   if (ctx->bitmap.ptr) hipFree(ctx->bitmap.ptr);
+  if (ctx->spg.ptr) hipFree(ctx->spg.ptr);
   if (ctx->host_pinned) hipHostFree(ctx->host_pinned);
   for (hipEvent_t e : ctx->events) hipEventDestroy(e);
   delete ctx;
@@ -391,6 +392,32 @@ cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int6
   if (!offsets || !x || !g || !d || !b || !l || !u || !grad_a) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   return run_batched_cqk_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
+}
+
+void cqk_spg_default_opts(cqk_spg_opts* opts) {
+  if (opts) fill_default_spg_opts(opts);
+}
+
+cqk_status cqk_spg_l1_lasso_f64(cqk_ctx* ctx, int64_t m, int64_t n, const double* A,
+                                const double* b, double radius, double* x,
+                                const cqk_spg_opts* opts, cqk_spg_info* info) {
+  if (!ctx || m <= 0 || n <= 0 || !A || !b || !x) return CQK_INVALID_ARG;
+  if (!std::isfinite(radius) || radius < 0.0 || n > (int64_t)UINT32_MAX) return CQK_INVALID_ARG;
+  cqk_spg_opts o;
+  if (opts) o = *opts;
+  else fill_default_spg_opts(&o);
+  if (!(o.tol >= 0.0) || o.max_iter < 0 || o.memory < 1 || (o.warm != 0 && o.warm != 1))
+    return CQK_INVALID_ARG;
+  // x is written while A, b are read: no overlap
+  if (overlaps_bytes(x, (size_t)n * 8, A, (size_t)m * n * 8) ||
+      overlaps_bytes(x, (size_t)n * 8, b, (size_t)m * 8))
+    return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  cqk_spg_info tmp;
+  cqk_spg_info* inf = info ? info : &tmp;
+  const cqk_status st = run_spg_l1_lasso_f64(ctx, m, n, A, b, radius, x, o, inf);
+  if (st != CQK_OK) return st;
+  return (cqk_status)inf->status;
 }
 
 cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,

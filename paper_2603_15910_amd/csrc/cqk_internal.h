@@ -93,6 +93,7 @@ struct cqk_ctx {
   cqk::DeviceBuf ws;          // compaction buffers, partials, per-block counts
   cqk::DeviceBuf state;       // run-state records + trace ring
   cqk::DeviceBuf bitmap;      // sparse output: one bit per index, zero between calls
+  cqk::DeviceBuf spg;         // the SPG driver's vectors
   bool bitmap_clean = false;  // the bitmap is known to be all zero
   void* host_pinned = nullptr;  // pinned mirror of the state + trace
   size_t host_pinned_bytes = 0;
@@ -135,6 +136,11 @@ cqk_status run_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, const float*
 cqk_status run_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xw,
                            SparseOut* sp, double r, double* x, bool l1, const cqk_opts& o,
                            cqk_info* info);
+// SPG on the l1-constrained least-squares problem (dense row-major A).
+void fill_default_spg_opts(cqk_spg_opts* o);
+cqk_status run_spg_l1_lasso_f64(cqk_ctx* ctx, int64_t m, int64_t n, const double* A,
+                                const double* b, double radius, double* x,
+                                const cqk_spg_opts& so, cqk_spg_info* info);
 // Batched general CQK (FP64 rows) and its VJP w.r.t. a and r.
 cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                const double* d, const double* a, const double* b,

@@ -22,6 +22,10 @@ Section 5.2.1 for the simplex):
 * ``cqk_batched``     rows of log-uniform length (``segment_offsets``), the
                       values drawn as in ``cqk_uniform`` over all rows, and
                       r per row = b^T(l+u)/2 over the row (feasible).
+* ``lasso_instance``  the l1-constrained least-squares problem of Section 5.2
+                      with a random matrix in place of its test matrices:
+                      A ~ N(0, 1/m) (m x n, row-major), a k-sparse x_true
+                      with N(0,1) entries, b = A x_true + 0.01 N(0,1).
 * ``perturbed``       v + eps * std(v) * N(0,1), the next point of an outer
                       loop whose previous projection serves as a warm start
                       (Section 3.1): for CQK only a is perturbed,
@@ -147,3 +151,14 @@ def cqk_perturbed(inst: dict, seed: int, eps: float = 1e-3) -> dict:
     out = dict(inst)
     out["a"] = perturbed(inst["a"], seed, eps)
     return out
+
+
+def lasso_instance(m: int, n: int, k: int, seed: int):
+    """Returns (A, b, x_true); A float64 [m, n] row-major."""
+    g = _rng(seed)
+    A = g.standard_normal((m, n)) / np.sqrt(m)
+    x_true = np.zeros(n)
+    idx = g.choice(n, size=min(k, n), replace=False)
+    x_true[idx] = g.standard_normal(idx.size)
+    b = A @ x_true + 0.01 * g.standard_normal(m)
+    return A, b, x_true

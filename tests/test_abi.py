@@ -78,6 +78,14 @@ def test_host_side_argument_errors(lib):
                                   None) == 2
         assert nnz.value == 0
     assert lib.cqk_status_string(6) == b"CQK_BUFFER_TOO_SMALL"
+    assert lib.cqk_spg_l1_lasso_f64(null, 4, 4, null, null, 1.0, null, None, None) == 2
+    assert lib.cqk_solve_batched_f64(null, 2, null, null, null, null, null, null, null, null,
+                                     null, null, None, None) == 2
+    assert lib.cqk_solve_batched_backward_f64(null, 2, null, null, null, null, null, null, null,
+                                              null, null, None) == 2
+    so = L.cqk_spg_opts()
+    lib.cqk_spg_default_opts(C.byref(so))
+    assert so.tol == 1e-4 and so.max_iter == 10000 and so.memory == 10 and so.warm == 1
     assert lib.cqk_project_simplex_batched_f32(null, 4, null, null, null, 1.0, null, null, null,
                                                None, None) == 2
     assert lib.cqk_create(None, None) == 2
