@@ -1413,6 +1413,13 @@ __device__ __forceinline__ void sp_load_words(const uint32_t* bm, int64_t w, int
   }
 }
 
+// Bits of word w that name indices below n (all of them except in the last
+// word): the count and the write ignore anything beyond n.
+__device__ __forceinline__ uint32_t sp_word_mask(int64_t w, int64_t n) {
+  const int64_t rest = n - w * 32;
+  return (rest >= 32) ? 0xFFFFFFFFu : ((rest <= 0) ? 0u : ((1u << rest) - 1u));
+}
+
 // Sparse output, second kernel: set bits per block of sp_wpb bitmap words.
 __global__ __launch_bounds__(kBlock) void spx_sp_count_kernel(SpxArgs A) {
   SpxState* st = A.st;
@@ -1424,7 +1431,7 @@ __global__ __launch_bounds__(kBlock) void spx_sp_count_kernel(SpxArgs A) {
     uint32_t b[kSpWords];
     sp_load_words(A.bm, w, w1, b);
 #pragma unroll
-    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j]);
+    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j] & sp_word_mask(w + j, A.n));
   }
   __shared__ int lds_i[kBlock / kWave + 1];
   int total = 0;
@@ -1477,15 +1484,15 @@ __global__ __launch_bounds__(kBlock) void spx_sp_write_kernel(SpxArgs A, int GS)
     sp_load_words(A.bm, w, w1, b);
     int c = 0;
 #pragma unroll
-    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j]);
+    for (int j = 0; j < kSpWords; ++j) c += __popc(b[j] & sp_word_mask(w + j, A.n));
     int step = 0;
     const int ex = block_excl_scan<kBlock>(c, lds_i, &step);
     if (c != 0) {
       int64_t p = pos + ex;
 #pragma unroll
       for (int j = 0; j < kSpWords; ++j) {
-        uint32_t rest = b[j];
-        if (rest == 0u) continue;
+        if (b[j] == 0u) continue;
+        uint32_t rest = b[j] & sp_word_mask(w + j, A.n);
         if (!over) {
           while (rest != 0u) {
             const int k = __builtin_ctz(rest);
@@ -1557,12 +1564,14 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   if (stt != CQK_OK) return stt;
   if (sparse) {
     const size_t bm_bytes = ((size_t)nwords * sizeof(uint32_t) + 255) / 256 * 256;
-    if (ctx->bitmap.bytes < bm_bytes) ctx->bitmap_clean = false;
+    const bool grows = ctx->bitmap.bytes < bm_bytes;
     stt = ensure_buffer(ctx->bitmap, bm_bytes);
     if (stt != CQK_OK) return stt;
-    // all zero from here (the write kernel clears what it reads)
+    if (grows) ctx->bitmap_clean = false;
+    // all zero from here, the whole allocation (a later, longer call reads
+    // more of it); the write kernel clears what it reads
     if (!ctx->bitmap_clean &&
-        hip_ok(hipMemsetAsync(ctx->bitmap.ptr, 0, bm_bytes, ctx->stream)) != CQK_OK)
+        hip_ok(hipMemsetAsync(ctx->bitmap.ptr, 0, ctx->bitmap.bytes, ctx->stream)) != CQK_OK)
       return CQK_DEVICE_ERROR;
     ctx->bitmap_clean = false;  // until this call has run to its end
   }

@@ -246,3 +246,19 @@ def test_sparse_simplex_1e8_fp32(ctx, dist):
     assert abs(info["lambda"] - lam_ref) <= 1e-5 * S
     assert float(np.max(np.abs(x - x_ref))) <= 1e-5 * S
     assert abs(float(np.sum(val, dtype=np.float64)) - 1.0) <= 1e-5
+
+
+def test_sparse_growing_sizes_in_one_context():
+    """A short call, then longer ones that fit the same bitmap allocation and
+    then outgrow it: every call sees only its own support."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_15910_amd as cqk
+    c = cqk.Context(0)
+    try:
+        for n, dist in ((1, "normal"), (33, "uniform"), (4099, "normal"), (32_768, "uniform"),
+                        (40_000, "normal"), (300_001, "uniform")):
+            y = W.simplex_input(n, 211 + n % 17, dist, np.float32)
+            _check(c, y, 1.0)
+    finally:
+        c.close()
