@@ -83,3 +83,58 @@ def test_simplex_1e8_fp32_against_sort(ctx, dist):
     assert abs(info["lambda"] - lam_ref) <= 1e-5 * S
     assert float(np.max(np.abs(x.astype(np.float64) - x_ref))) <= 1e-5 * S
     assert abs(float(np.sum(x, dtype=np.float64)) - 1.0) <= 1e-5
+
+
+def test_cqk_1e8_warm_from_previous_solution(ctx):
+    """The warm start at the benchmark size: the previous point's solution
+    (oracle x(lam) at the previous problem's multiplier, from eq. (xopt))
+    starts a solve of the problem with a perturbed; the result is held to the
+    same properties as the cold solve, and lambda_0 to the oracle's warm
+    formula over all n."""
+    prev = W.cqk_uniform(N, 1)
+    d, b, l, u = (prev[k] for k in "dblu")
+    r = prev["r"]
+    t = {k: torch.from_numpy(prev[k]).cuda() for k in "dablu"}
+    _, info0 = ctx.solve(*[t[k] for k in "dablu"], r, check=False)
+    assert info0["status"] == 0
+    xbar = O.x_of_lambda(info0["lambda"], d, prev["a"], b, l, u)
+    a = W.perturbed(prev["a"], 2, 1e-3)
+    del prev
+    t["a"] = torch.from_numpy(a).cuda()
+    x_dev, info = ctx.solve(*[t[k] for k in "dablu"], r, xbar=torch.from_numpy(xbar).cuda(),
+                            check=False)
+    del t
+    assert info["status"] == 0, info
+    lam0_ref = O.cqk_lambda0_warm(d, a, b, l, u, r, xbar)
+    assert abs(info["lambda0"] - lam0_ref) <= 1e-9 * max(1.0, abs(lam0_ref))
+    lam = info["lambda"]
+    x = x_dev.cpu().numpy()
+    del x_dev
+    torch.cuda.empty_cache()
+    rng = np.random.default_rng(8)
+    idx = rng.choice(N, 200_000, replace=False)
+    xo = O.x_of_lambda(lam, d[idx], a[idx], b[idx], l[idx], u[idx])
+    S = max(np.max(np.abs(xo)), np.max(np.abs(a[idx] / d[idx])), abs(lam) * np.max(b[idx] / d[idx]))
+    assert np.max(np.abs(x[idx] - xo)) <= 1e-10 * S
+    b1 = float(np.sum(np.abs(b)))
+    xinf = float(np.max(np.abs(x)))
+    assert abs(O.phi(lam, d, a, b, l, u) - r) <= 1e-10 * b1 * xinf
+
+
+def test_simplex_1e8_fp32_warm_against_sort(ctx):
+    y0 = W.simplex_input(N, 1, "normal", np.float32)
+    x0, _ = O.project_simplex(y0.astype(np.float64), 1.0)
+    y = W.perturbed(y0, 2, 1e-3)
+    del y0
+    yt = torch.from_numpy(y).cuda()
+    x_dev, info = ctx.project_simplex(yt, 1.0, xbar=torch.from_numpy(x0.astype(np.float32)).cuda(),
+                                      check=False)
+    assert info["status"] == 0, info
+    x = x_dev.cpu().numpy()
+    del x_dev, yt
+    torch.cuda.empty_cache()
+    x_ref, lam_ref = O.project_simplex(y.astype(np.float64), 1.0)
+    S = max(float(np.max(np.abs(x_ref))), float(np.max(np.abs(y))), abs(lam_ref))
+    assert info["lambda0"] >= lam_ref - 1e-12 * S
+    assert abs(info["lambda"] - lam_ref) <= 1e-5 * S
+    assert float(np.max(np.abs(x.astype(np.float64) - x_ref))) <= 1e-5 * S

@@ -228,8 +228,34 @@ def pin_warm(M):
     return lam0 == 1.25
 
 
+def pin_spg(M):
+    # A = I: the solution is the projection of b; an inactive ball: least
+    # squares; the batched loops row by row
+    rng = np.random.default_rng(65)
+    bvec = rng.standard_normal(30)
+    x, info = M.spg_l1_lasso(np.eye(30), bvec, 2.0, tol=1e-12)
+    if np.max(np.abs(x - M.project_l1(bvec, 2.0)[0])) > 1e-10:
+        return False
+    A = rng.standard_normal((50, 12))
+    bb = rng.standard_normal(50)
+    x, info = M.spg_l1_lasso(A, bb, 1e3, tol=1e-11)
+    if np.max(np.abs(x - np.linalg.lstsq(A, bb, rcond=None)[0])) > 1e-8:
+        return False
+    x, info = M.spg_l1_lasso(A, bb, 0.3, tol=1e-11)
+    g = A.T @ (A @ x - bb)
+    if np.max(np.abs(M.project_l1(x - g, 0.3)[0] - x)) > 1e-9 or np.sum(np.abs(x)) > 0.3 + 1e-12:
+        return False
+    off, inst = W.cqk_batched(5, 1, 40, 66)
+    res = M.solve_cqk_batched(*[inst[k] for k in "dablu"], off, inst["r"])
+    for s in range(5):
+        lo, hi = off[s], off[s + 1]
+        if abs(float(np.dot(inst["b"][lo:hi], res[s].x)) - inst["r"][s]) > 1e-10 * max(1, abs(inst["r"][s])):
+            return False
+    return True
+
+
 PINS = [pin_golden, pin_bruteforce, pin_kkt, pin_simplex_special_case, pin_condat,
-        pin_newton_cqk, pin_vjp_fd, pin_slopes, pin_warm]
+        pin_newton_cqk, pin_vjp_fd, pin_slopes, pin_warm, pin_spg]
 
 
 def _survives(M):
@@ -284,6 +310,12 @@ MUTANTS = [
      "I = np.flatnonzero(xb != 0.0) if l1 else np.flatnonzero(xb >= 0.0)"),
     ("warm fallback", "return max(float(r) / y.size, -float(np.max(v))), []",
      "return max(float(r), -float(np.max(v))), []"),
+    ("spg gradient sign", "return A.T @ (A @ x - b)", "return A.T @ (b - A @ x)"),
+    ("spg direction", "d = proj(x - lam * g) - x", "d = proj(x + lam * g) - x"),
+    ("spg stop test", "pg = float(np.max(np.abs(proj(x - g) - x)))\n        nproj",
+     "pg = float(np.max(np.abs(proj(x) - x)))\n        nproj"),
+    ("batched row slice", "out.append(solve_cqk(d[lo:hi], a[lo:hi], b[lo:hi], l[lo:hi], u[lo:hi], float(r[s])))",
+     "out.append(solve_cqk(d[lo:hi], a[lo:hi], b[lo:hi], l[lo:hi], u[lo:hi], float(r[0])))"),
 ]
 
 
