@@ -881,7 +881,7 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
 // mu = (sum_F g b/d)/q,
 //   grad_a = [F](g - b mu)/d,   grad_r = mu   (both 0 when F is empty).
 // ===========================================================================
-constexpr int kCqkSP = 4;   // values per lane of a wave row
+constexpr int kCqkSP = 8;   // values per lane of a wave row
 constexpr int kCqkU = 4;    // values per thread in flight in a workgroup pass
 constexpr int CTR_ITSUM = CTR_SURV, CTR_ITMAX = CTR_OVER;
 

@@ -2,7 +2,7 @@
 Section 2.1) and of its VJP w.r.t. a and r against the CPU oracle, through
 the C ABI (cqk_solve_batched_f64, cqk_solve_batched_backward_f64).
 
-Rows of at most 256 values are solved by one wave, longer rows by a
+Rows of at most 512 values are solved by one wave, longer rows by a
 workgroup; the sizes below mix both, with ragged lengths and empty rows.
 Every row is held to the single-instance FP64 bar (tests/parity.py), its
 multiplier to the oracle's where the oracle calls it unique, and bad rows
@@ -84,8 +84,9 @@ def test_batched_cqk_user_start(ctx):
 
 
 def test_batched_cqk_every_length_near_the_wave_limit(ctx):
-    """Lengths 250..262 straddle the wave-row limit (256)."""
-    lens = np.arange(250, 263)
+    """Lengths around 256 and 506..518 straddle the wave-row limit (512) and
+    the register tiers below it."""
+    lens = np.concatenate([np.arange(250, 263), np.arange(506, 519)])
     off = np.concatenate([[0], np.cumsum(lens)])
     inst = W.cqk_uniform(int(off[-1]), 7)
     mid = inst["b"] * (inst["l"] + inst["u"]) * 0.5
