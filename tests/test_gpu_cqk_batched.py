@@ -248,3 +248,47 @@ def test_batched_cqk_argument_errors(ctx):
     st = cqk.cqk_solve_batched_f64(ctx.handle, 4, _dev(off, torch.int64).data_ptr(),
                                    *[v.data_ptr() for v in t], None, t[0].data_ptr())
     assert st == cqk.CQK_INVALID_ARG
+
+
+def test_batched_cqk_degenerate_rows(ctx):
+    """Rows the single-instance edge cases cover, side by side in one call:
+    unbounded, every index with l = u, a single index, mixed infinite bounds,
+    and a long unbounded row (workgroup path)."""
+    rng = np.random.default_rng(61)
+    rows = []
+
+    def row(n, lo_kind, hi_kind):
+        d = rng.uniform(1, 10, n)
+        a = rng.uniform(-10, 10, n)
+        b = rng.uniform(1, 10, n)
+        l = {"inf": np.full(n, -np.inf), "fin": rng.uniform(-5, 0, n)}[lo_kind]
+        u = {"inf": np.full(n, np.inf), "fin": (np.where(np.isfinite(l), l, -1.0)
+                                               + rng.uniform(0.1, 5, n))}[hi_kind]
+        return d, a, b, l, u
+
+    # unbounded rows, short and long
+    for n in (40, 3000):
+        d, a, b, l, u = row(n, "inf", "inf")
+        rows.append((d, a, b, l, u, 3.0))
+    # l = u everywhere: the only feasible r is b'l
+    d, a, b, l, u = row(50, "fin", "fin")
+    u = l.copy()
+    rows.append((d, a, b, l, u, float(np.dot(b, l))))
+    # a single index, r inside its range
+    d, a, b, l, u = row(1, "fin", "fin")
+    rows.append((d, a, b, l, u, float(b[0] * (0.3 * l[0] + 0.7 * u[0]))))
+    # lower bounds only, upper bounds only
+    d, a, b, l, u = row(700, "fin", "inf")
+    rows.append((d, a, b, l, u, float(np.dot(b, l)) + 50.0))
+    d, a, b, l, u = row(90, "inf", "fin")
+    rows.append((d, a, b, l, u, float(np.dot(b, u)) - 20.0))
+    off = np.concatenate([[0], np.cumsum([r[0].size for r in rows])])
+    inst = {k: np.concatenate([r[i] for r in rows]) for i, k in enumerate("dablu")}
+    inst["r"] = np.array([r[5] for r in rows])
+    x, lam, sts, info = _run(ctx, off, inst)
+    assert info["status"] == 0, (info, sts)
+    for s in range(len(rows)):
+        row_ = _row(inst, off, s)
+        ref = O.solve_cqk(*[row_[c] for c in "dablu"], row_["r"])
+        assert ref.status == O.OK
+        check_cqk(x[off[s]:off[s + 1]], row_, ref, 1e-10)
