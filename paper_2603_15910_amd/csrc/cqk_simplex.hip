@@ -48,6 +48,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "cqk_device.h"
 #include "cqk_internal.h"
@@ -222,6 +223,37 @@ __device__ __forceinline__ void load_tile(const TIn* y, int64_t base, int lane, 
   }
 }
 
+// load_tile and zero_tile for a tile known to be in range: no checks.
+template <typename TIn, int NL>
+__device__ __forceinline__ void load_tile_full(const TIn* y, int64_t base, int lane, TIn* o) {
+  constexpr int V = VecWidth<TIn>::value;
+  typename Raw16<TIn>::type r[NL];
+#pragma unroll
+  for (int q = 0; q < NL; ++q) r[q] = ld16(y + base + (int64_t)q * kWave * V + lane * V);
+#pragma unroll
+  for (int q = 0; q < NL; ++q)
+#pragma unroll
+    for (int k = 0; k < V; ++k) o[q * V + k] = r[q][k];
+}
+
+template <typename TIn, int NL>
+__device__ __forceinline__ void zero_tile_full(TIn* x, int64_t base, int lane) {
+  constexpr int V = VecWidth<TIn>::value;
+  typename Raw16<TIn>::type z;
+#pragma unroll
+  for (int k = 0; k < V; ++k) z[k] = TIn(0);
+#pragma unroll
+  for (int q = 0; q < NL; ++q) st16(x + base + (int64_t)q * kWave * V + lane * V, z);
+}
+
+// |v| when mask clears the sign bit (l1), v when it is all ones.
+__device__ __forceinline__ float abs_if(float v, uint32_t mask) {
+  return __int_as_float((int)((uint32_t)__float_as_int(v) & mask));
+}
+__device__ __forceinline__ double abs_if(double v, uint32_t mask) {
+  return __hiloint2double((int)((uint32_t)__double2hiint(v) & mask), __double2loint(v));
+}
+
 // The largest T not above x (so that v > result never drops a v > x).
 template <typename T>
 __device__ __forceinline__ T round_down_to(double x);
@@ -301,11 +333,17 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   TIn vmxI = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
-  for (int64_t base = (int64_t)rid * TILE; base < count; base += nr * TILE) {
-    const bool full = base + TILE <= count;
+  const uint32_t amask = l1 ? 0x7FFFFFFFu : 0xFFFFFFFFu;
+  // One tile; `full` (a tile wholly in range) is known at compile time, so
+  // the in-range tests of the other tiles cost nothing here.
+  auto tile = [&](const int64_t base, auto full_tag) {
+    constexpr bool full = decltype(full_tag)::value;
     TIn yv[K];
     TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
-    load_tile<TIn, NL>(y, base, lane, count, yv);
+    if constexpr (full)
+      load_tile_full<TIn, NL>(y, base, lane, yv);
+    else
+      load_tile<TIn, NL>(y, base, lane, count, yv);
     uint32_t inI = 0xFFFFFFFFu;  // the values Algorithm 2 may use
     if constexpr (WARM) {
       TIn xv[K];
@@ -317,7 +355,12 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     // x_i = 0 for every index (survivors get their value from the scatter at
     // the end), written while this kernel is busy with Algorithm 2 anyway;
     // a sparse output has no x
-    if (x != nullptr) zero_tile<TIn, NL>(x, base, lane, count);
+    if (x != nullptr) {
+      if constexpr (full)
+        zero_tile_full<TIn, NL>(x, base, lane);
+      else
+        zero_tile<TIn, NL>(x, base, lane, count);
+    }
     TIn tmax = -(TIn)__builtin_huge_val();
     TIn tmaxI = -(TIn)__builtin_huge_val();
 #pragma unroll
@@ -327,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       for (int k = 0; k < V; ++k) {
         const int e = q * V + k;
         const bool in = full || (i + k < count);
-        av[e] = l1 ? absval(yv[e]) : yv[e];
+        av[e] = abs_if(yv[e], amask);
         badacc += in ? yv[e] * TIn(0) : TIn(0);
         if (l1) abs_sum += in ? (double)av[e] : 0.0;
         tmax = max(tmax, in ? av[e] : -(TIn)__builtin_huge_val());
@@ -358,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         active |= (in && av[e] > thr) ? (1u << e) : 0u;
       }
     }
-    if (__ballot(active != 0u) == 0) continue;
+    if (__ballot(active != 0u) == 0) return;
     uint32_t keep = 0;
     double nk = 0.0, ks = 0.0;
     if (run_c > 0.0) {
@@ -430,7 +473,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       select(lam_b);
       lam_min = fmin(lam_min, lam_b);
     }
-    if (__ballot(keep != 0u) == 0) continue;
+    if (__ballot(keep != 0u) == 0) return;
     if constexpr (WARM) {
       double ci = 0.0, si = 0.0;
 #pragma unroll
@@ -457,6 +500,12 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     run_c += wave_sum(nk);
     run_s += wave_sum(ks);
     if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
+  };
+  for (int64_t base = (int64_t)rid * TILE; base < count; base += nr * TILE) {
+    if (base + TILE <= count)
+      tile(base, std::true_type{});
+    else
+      tile(base, std::false_type{});
   }
   if (lane == 0) {
     acc[C_CNT] = run_c;
