@@ -359,6 +359,14 @@ __device__ __forceinline__ void zero_wtile(float* p, int64_t t0, int lane, int64
   }
 }
 
+// The largest float not above x: v > result exactly when v + x' > 0 for
+// x' = -x, so a bound filters FP32 values with one FP32 compare.
+__device__ __forceinline__ float float_at_or_below(double x) {
+  float f = (float)x;
+  if ((double)f > x) f = nextafterf(f, -__builtin_huge_valf());
+  return f;
+}
+
 // Algorithm 4 from lam (>= lam*) on the four LDS lists, run by one wave:
 // lam_{k+1} = lam_J(J_k), J_k = {v + lam_k > 0}; stops as the paper's
 // Algorithm 4 (phi(lam_k) <= r for k >= 1) or when J no longer changes.
@@ -414,7 +422,7 @@ __device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n,
   // wave-uniform running state: survivors kept, smallest bound found
   double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
   float vmx = -__builtin_huge_valf();
-  int nbad = 0;
+  float badf = 0.f;  // NaN once a value is NaN or infinite
   int nw = 0;
   const int64_t ntiles = (n + kWTile - 1) / kWTile;
   for (int64_t t = wid; t < ntiles; t += kWaves) {
@@ -422,25 +430,40 @@ __device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n,
     float v[kK];
     uint32_t active = 0;
     load_wtile(y, t0, lane, n, v);
-    // x is zero wherever the lists below do not write it
-    zero_wtile(x, t0, lane, n);
+    if (t0 + kWTile <= n) {
+      // a tile wholly in the row: no per-value range tests
+      const flt4u z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < kK / 4; ++q) {
-      const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+      for (int q = 0; q < kK / 4; ++q) st16(x + t0 + q * kWave * 4 + lane * 4, z);
+      active = (1u << kK) - 1u;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (i + k < n) {
-          active |= 1u << (4 * q + k);
-          nbad += (fabsf(v[4 * q + k]) < __builtin_huge_valf()) ? 0 : 1;
-          vmx = fmaxf(vmx, v[4 * q + k]);
+      for (int e = 0; e < kK; ++e) {
+        badf += v[e] * 0.f;
+        vmx = fmaxf(vmx, v[e]);
+      }
+    } else {
+      // x is zero wherever the lists below do not write it
+      zero_wtile(x, t0, lane, n);
+#pragma unroll
+      for (int q = 0; q < kK / 4; ++q) {
+        const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          if (i + k < n) {
+            active |= 1u << (4 * q + k);
+            badf += v[4 * q + k] * 0.f;
+            vmx = fmaxf(vmx, v[4 * q + k]);
+          }
         }
       }
     }
-    // values at or below the wave's best bound so far are zero at the solution
+    // values at or below the wave's best bound so far are zero at the
+    // solution (v <= thr exactly when v + lam_min <= 0)
     if (lam_min < inf_d()) {
+      const float thr = float_at_or_below(-lam_min);
 #pragma unroll
       for (int e = 0; e < kK; ++e)
-        if (!((double)v[e] + lam_min > 0.0)) active &= ~(1u << e);
+        if (!(v[e] > thr)) active &= ~(1u << e);
     }
     if (__ballot(active != 0u) == 0) continue;
     double nk = 0.0, ks = 0.0;
@@ -476,7 +499,7 @@ __device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n,
     run_s += wave_sum(ks);
     if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
   }
-  const double wbad = wave_sum((double)nbad);
+  const double wbad = wave_sum((badf == 0.f) ? 0.0 : 1.0);
   const double wmax = wave_max((double)vmx);
   if (lane == 0) {
     L.ws[wid][W_C] = run_c;
