@@ -292,3 +292,38 @@ def test_batched_cqk_degenerate_rows(ctx):
         ref = O.solve_cqk(*[row_[c] for c in "dablu"], row_["r"])
         assert ref.status == O.OK
         check_cqk(x[off[s]:off[s + 1]], row_, ref, 1e-10)
+
+
+def test_batched_cqk_graph_capture_replays(ctx):
+    """Forward and backward captured in one HIP graph (no allocation, no host
+    sync inside); every replay matches the eager results."""
+    off, inst = W.cqk_batched(300, 10, 6000, 71)
+    t = [_dev(inst[k]) for k in "dablu"]
+    offs = _dev(off, torch.int64)
+    r = _dev(inst["r"])
+    x = torch.empty_like(t[0])
+    lam = torch.empty(300, dtype=torch.float64, device="cuda")
+    g = torch.from_numpy(np.random.default_rng(72).standard_normal(x.numel())).cuda()
+    ga = torch.empty_like(x)
+    gr = torch.empty(300, dtype=torch.float64, device="cuda")
+    # eager pass (sizes the workspace)
+    ctx.solve_batched(*t, offs, r, out=x, lambda_out=lam)
+    ctx.solve_batched_backward(x, g, t[0], t[2], t[3], t[4], offs, grad_a=ga, grad_r=gr)
+    ex, el, ega, egr = x.clone(), lam.clone(), ga.clone(), gr.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            ctx.solve_batched(*t, offs, r, out=x, lambda_out=lam, sync=False, check=False)
+            ctx.solve_batched_backward(x, g, t[0], t[2], t[3], t[4], offs, grad_a=ga,
+                                       grad_r=gr, sync=False)
+    torch.cuda.current_stream().wait_stream(s)
+    for _ in range(4):
+        for v in (x, lam, ga, gr):
+            v.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(x, ex) and torch.equal(lam, el)
+        assert torch.equal(ga, ega) and torch.equal(gr, egr)
