@@ -350,6 +350,8 @@ def extra_batched_cqk(ctx, dev, torch, row_loop=True):
     del inst
     x = torch.empty_like(t[0])
     ctx.solve_batched(*t, offs, r, out=x)
+    ms_default = timed(lambda: ctx.solve_batched(*t, offs, r, out=x), 5, sync)
+    sched, _ = ctx.tune_batched_cqk(*t, offs, r, repeats=2)
     ms = timed(lambda: ctx.solve_batched(*t, offs, r, out=x), 5, sync)
     _, info = ctx.solve_batched(*t, offs, r, out=x)
     g = torch.randn(total, dtype=torch.float64, device=dev,
@@ -359,6 +361,8 @@ def extra_batched_cqk(ctx, dev, torch, row_loop=True):
     bwd = lambda: ctx.solve_batched_backward(x, g, t[0], t[2], t[3], t[4], offs, grad_a=ga,
                                              grad_r=gr)
     bwd()
+    ms_b_default = timed(bwd, 5, sync)
+    sched_b, _ = ctx.tune_batched_cqk(*t, offs, r, repeats=2, backward=True, x=x, g=g)
     ms_b = timed(bwd, 5, sync)
     # comparator: one plain solve per row over the first 512 rows, scaled
     loop_ms = None
@@ -376,10 +380,14 @@ def extra_batched_cqk(ctx, dev, torch, row_loop=True):
         "rows": 8192, "elements": total, "ms": ms, "elements_per_s": total / (ms * 1e-3),
         "mean_iterations": info["passes"] / 8192, "max_iterations": info["iterations"],
         "gbs_40B_per_elem_per_iteration": 40.0 * total * info["passes"] / 8192 / (ms * 1e-3) / 1e9,
-        "status": info["status_name"], "backward_ms": ms_b,
+        "status": info["status_name"], "schedule": sched, "default_schedule_ms": ms_default,
+        "backward_ms": ms_b, "backward_schedule": sched_b,
+        "backward_default_schedule_ms": ms_b_default,
         "backward_gbs_48B_per_elem": 48.0 * total / (ms_b * 1e-3) / 1e9,
         "per_row_loop_ms_scaled_from_512_rows": loop_ms,
         "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}}
+    ctx.set_batch_schedule(8, 4, 0, general=True)
+    ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
     del t, x, g, ga, gr, offs, r
     torch.cuda.empty_cache()
     return out

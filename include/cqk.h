@@ -358,12 +358,13 @@ typedef struct cqk_batch_schedule {
   int32_t reserved;         /* 0 */
 } cqk_batch_schedule;
 
-/* The schedule the context uses for batched forward (backward = 0) or
- * backward (backward = 1) calls; a new context starts with
- * {8, 4, 0, 0}.  Set returns INVALID_ARG for a schedule outside the ranges
- * above. */
-cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t backward, cqk_batch_schedule* out);
-cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t backward,
+/* The schedule the context uses for one kind of batched call: which = 0
+ * batched simplex forward, 1 its backward, 2 batched general CQK forward,
+ * 3 its backward; a new context starts with {8, 4, 0, 0} for each.  Set
+ * returns INVALID_ARG for a schedule outside the ranges above or another
+ * `which`. */
+cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t which, cqk_batch_schedule* out);
+cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t which,
                                   const cqk_batch_schedule* sched);
 
 /* Autotuner: runs cqk_project_simplex_batched_f32 on these rows under every
@@ -381,6 +382,20 @@ cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64
                                          const float* x, const float* g, float* grad_y,
                                          int32_t repeats, cqk_batch_schedule* best,
                                          double* best_ms);
+
+/* Autotuner of the batched general CQK: runs cqk_solve_batched_f64
+ * (backward = 0: needs d, a, b, l, u, r, x; x is overwritten) or
+ * cqk_solve_batched_backward_f64 (backward = 1: needs x, g, d, b, l, u,
+ * grad_a; grad_a is overwritten) on these rows under every candidate
+ * schedule, as cqk_tune_batched_f32 does, from lambda = 0 with the default
+ * options, and keeps the fastest as the context's schedule of that kind
+ * (which = 2 or 3 above).  Synchronises; not under graph capture. */
+cqk_status cqk_tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const double* d, const double* a, const double* b,
+                                    const double* l, const double* u, const double* r,
+                                    double* x, const double* g, double* grad_a,
+                                    int32_t backward, int32_t repeats, cqk_batch_schedule* best,
+                                    double* best_ms);
 
 #ifdef __cplusplus
 }

@@ -548,18 +548,43 @@ class Context:
         return gy
 
 
-    def batch_schedule(self, backward=False):
-        """The context's batched schedule as a dict."""
-        st, sc = cqk_get_batch_schedule(self.handle, 1 if backward else 0)
+    def batch_schedule(self, backward=False, general=False):
+        """The context's batched schedule as a dict (general: the batched
+        general CQK's, else the batched simplex's)."""
+        st, sc = cqk_get_batch_schedule(self.handle, (2 if general else 0) + (1 if backward else 0))
         if st != CQK_OK:
             raise CqkError(st, "cqk_get_batch_schedule")
         return sc.as_dict()
 
-    def set_batch_schedule(self, small_per=8, blocks_per_cu=4, short_first=0, backward=False):
+    def set_batch_schedule(self, small_per=8, blocks_per_cu=4, short_first=0, backward=False,
+                           general=False):
         sc = L.cqk_batch_schedule(int(small_per), int(blocks_per_cu), int(short_first), 0)
-        st = cqk_set_batch_schedule(self.handle, 1 if backward else 0, sc)
+        st = cqk_set_batch_schedule(self.handle, (2 if general else 0) + (1 if backward else 0),
+                                    sc)
         if st != CQK_OK:
             raise CqkError(st, "cqk_set_batch_schedule")
+
+    def tune_batched_cqk(self, d, a, b, l, u, offsets, r, repeats=3, backward=False, x=None,
+                         g=None):
+        """Times every candidate schedule of the batched general CQK forward
+        (or, backward=True, of its VJP: needs x and g) on these rows and keeps
+        the fastest in the context; returns (schedule dict, ms)."""
+        torch = _torch()
+        nseg = offsets.numel() - 1
+        xx = x if x is not None else torch.empty_like(d)
+        ga = torch.empty_like(d) if backward else None
+        ptr = lambda t, nm: _dev_ptr(t, torch.float64, nm) if t is not None else None
+        sc = L.cqk_batch_schedule()
+        ms = C.c_double(0.0)
+        self._bind_stream()
+        st = _call("cqk_tune_batched_cqk_f64", C.c_void_p(self.handle), nseg,
+                   _dev_ptr(offsets, torch.int64, "offsets"), ptr(d, "d"), ptr(a, "a"),
+                   ptr(b, "b"), ptr(l, "l"), ptr(u, "u"), ptr(r, "r"), ptr(xx, "x"),
+                   ptr(g, "g"), ptr(ga, "grad_a"), 1 if backward else 0, int(repeats),
+                   C.byref(sc), C.byref(ms))
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_tune_batched_cqk_f64")
+        return sc.as_dict(), ms.value
 
     def tune_batched(self, y, offsets, r=1.0, repeats=3, out=None):
         """Times every candidate schedule on these rows and keeps the fastest

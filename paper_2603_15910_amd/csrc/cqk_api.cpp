@@ -456,18 +456,48 @@ cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
   return run_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, grad_r, o);
 }
 
-cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t backward, cqk_batch_schedule* out) {
-  if (!ctx || !out || (backward != 0 && backward != 1)) return CQK_INVALID_ARG;
-  *out = backward ? ctx->sched_bwd : ctx->sched_fwd;
+namespace {
+// which: 0/1 batched simplex forward/backward, 2/3 batched general forward/backward
+cqk_batch_schedule* schedule_slot(cqk_ctx* ctx, int32_t which) {
+  switch (which) {
+    case 0: return &ctx->sched_fwd;
+    case 1: return &ctx->sched_bwd;
+    case 2: return &ctx->sched_cqk_fwd;
+    case 3: return &ctx->sched_cqk_bwd;
+    default: return nullptr;
+  }
+}
+}  // namespace
+
+cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t which, cqk_batch_schedule* out) {
+  if (!ctx || !out) return CQK_INVALID_ARG;
+  cqk_batch_schedule* slot = schedule_slot(ctx, which);
+  if (!slot) return CQK_INVALID_ARG;
+  *out = *slot;
   return CQK_OK;
 }
 
-cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t backward,
-                                  const cqk_batch_schedule* sched) {
-  if (!ctx || !sched || (backward != 0 && backward != 1)) return CQK_INVALID_ARG;
-  if (!valid_schedule(*sched)) return CQK_INVALID_ARG;
-  (backward ? ctx->sched_bwd : ctx->sched_fwd) = *sched;
+cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t which, const cqk_batch_schedule* sched) {
+  if (!ctx || !sched) return CQK_INVALID_ARG;
+  cqk_batch_schedule* slot = schedule_slot(ctx, which);
+  if (!slot || !valid_schedule(*sched)) return CQK_INVALID_ARG;
+  *slot = *sched;
   return CQK_OK;
+}
+
+cqk_status cqk_tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const double* d, const double* a, const double* b,
+                                    const double* l, const double* u, const double* r,
+                                    double* x, const double* g, double* grad_a,
+                                    int32_t backward, int32_t repeats, cqk_batch_schedule* best,
+                                    double* best_ms) {
+  if (!ctx || nseg <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
+  if (backward != 0 && backward != 1) return CQK_INVALID_ARG;
+  if (!offsets || !d || !b || !l || !u || !x) return CQK_INVALID_ARG;
+  if (backward ? (!g || !grad_a) : (!a || !r)) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return tune_batched_cqk_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
+                              repeats, best, best_ms);
 }
 
 cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,

@@ -894,9 +894,10 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
 // single-instance solver on a state record each wave or workgroup keeps in
 // registers, every lane updating its own copy from the same reduced sums (so
 // all copies stay identical and the control flow uniform).  A row of at most
-// 64 * kCqkSP values is one wave's, its per-index form (c, s, bl, bu) held in
-// registers from load to store; a longer row is a workgroup's, which re-reads
-// the row from memory at every evaluation.  x = clamp((a + lam b)/d, l, u)
+// 64 * small_per values is one wave's, its per-index form (c, s, bl, bu) held in
+// registers from load to store (4 or 8 values per lane, by the schedule); a
+// longer row is a workgroup's, which re-reads the row from memory at every
+// evaluation.  x = clamp((a + lam b)/d, l, u)
 // (eq. (xopt)) is written once.
 //
 // Backward, on a locally constant free set F = {l < x < u} (eq. (xopt) on F
@@ -904,7 +905,6 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
 // mu = (sum_F g b/d)/q,
 //   grad_a = [F](g - b mu)/d,   grad_r = mu   (both 0 when F is empty).
 // ===========================================================================
-constexpr int kCqkSP = 8;   // values per lane of a wave row
 constexpr int kCqkU = 4;    // values per thread in flight in a workgroup pass
 constexpr int CTR_ITSUM = CTR_SURV, CTR_ITMAX = CTR_OVER;
 
@@ -1415,8 +1415,6 @@ BatCqkArgs cqk_args(int32_t nseg, const int64_t* offsets, const double* d, const
                     const double* b, const double* l, const double* u, const BatWs& w) {
   BatCqkArgs A{};
   A.nseg = nseg;
-  A.small_max = kWave * kCqkSP;
-  A.short_first = 0;
   A.off = offsets;
   A.d = d;
   A.a = a;
@@ -1430,7 +1428,34 @@ BatCqkArgs cqk_args(int32_t nseg, const int64_t* offsets, const double* d, const
   return A;
 }
 
-int cqk_grid(cqk_ctx* ctx, int nseg) { return std::max(1, std::min(ctx->num_cus * 4, nseg)); }
+// The batched general CQK under schedule sc: rows of at most
+// 64 * small_per values go to one wave (small_per 4 or 8 values per lane in
+// registers), blocks_per_cu persistent workgroups per compute unit.
+void cqk_apply_schedule(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs* A, dim3* grid) {
+  A->small_max = kWave * sc.small_per;
+  A->short_first = sc.short_first;
+  *grid = dim3(std::max(1, std::min(ctx->num_cus * sc.blocks_per_cu, A->nseg)));
+}
+
+void launch_cqk_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs A) {
+  dim3 grid;
+  cqk_apply_schedule(ctx, sc, &A, &grid);
+  plan(ctx, A);
+  if (sc.small_per == 4)
+    hipLaunchKernelGGL(bat_cqk_solve_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+  else
+    hipLaunchKernelGGL(bat_cqk_solve_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+}
+
+void launch_cqk_backward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs A) {
+  dim3 grid;
+  cqk_apply_schedule(ctx, sc, &A, &grid);
+  plan(ctx, A);
+  if (sc.small_per == 4)
+    hipLaunchKernelGGL(bat_cqk_vjp_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+  else
+    hipLaunchKernelGGL(bat_cqk_vjp_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+}
 
 }  // namespace
 
@@ -1457,8 +1482,7 @@ cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offset
     if (st != CQK_OK) return st;
     hipEventRecord(ctx->events[0], s);
   }
-  plan(ctx, A);
-  hipLaunchKernelGGL(bat_cqk_solve_kernel<kCqkSP>, dim3(cqk_grid(ctx, nseg)), dim3(kBlock), 0, s, A);
+  launch_cqk_forward(ctx, ctx->sched_cqk_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (info) std::memset(info, 0, sizeof(*info));
@@ -1501,11 +1525,43 @@ cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_
   A.g = g;
   A.ga = grad_a;
   A.gr = grad_r;
-  plan(ctx, A);
-  hipLaunchKernelGGL(bat_cqk_vjp_kernel<kCqkSP>, dim3(cqk_grid(ctx, nseg)), dim3(kBlock), 0,
-                     ctx->stream, A);
+  launch_cqk_backward(ctx, ctx->sched_cqk_bwd, A);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
+  return CQK_OK;
+}
+
+
+cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const double* d, const double* a, const double* b,
+                                const double* l, const double* u, const double* r, double* x,
+                                const double* g, double* grad_a, int32_t backward,
+                                int32_t repeats, cqk_batch_schedule* best, double* best_ms) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  BatCqkArgs A = cqk_args(nseg, offsets, d, a, b, l, u, w);
+  A.r = r;
+  A.x = x;
+  A.g = g;
+  A.ga = grad_a;
+  A.lambda0_mode = CQK_LAMBDA0_ZERO;
+  A.max_iter = 100;
+  A.tol = std::pow(2.220446049250313e-16, 0.75);
+  cqk_batch_schedule cand[32];
+  const int nc = candidate_schedules(cand, 32);
+  int bi = 0;
+  double ms = 0.0;
+  if (backward)
+    st = tune(ctx, cand, nc, repeats,
+              [&](const cqk_batch_schedule& sc) { launch_cqk_backward(ctx, sc, A); }, &bi, &ms);
+  else
+    st = tune(ctx, cand, nc, repeats,
+              [&](const cqk_batch_schedule& sc) { launch_cqk_forward(ctx, sc, A); }, &bi, &ms);
+  if (st != CQK_OK) return st;
+  (backward ? ctx->sched_cqk_bwd : ctx->sched_cqk_fwd) = cand[bi];
+  if (best) *best = cand[bi];
+  if (best_ms) *best_ms = ms;
   return CQK_OK;
 }
 

@@ -102,6 +102,8 @@ struct cqk_ctx {
   std::vector<cqk_trace_rec> last_trace;
   cqk_batch_schedule sched_fwd{8, 4, 0, 0};  // batched forward / backward schedules
   cqk_batch_schedule sched_bwd{8, 4, 0, 0};
+  cqk_batch_schedule sched_cqk_fwd{8, 4, 0, 0};  // batched general CQK forward / backward
+  cqk_batch_schedule sched_cqk_bwd{8, 4, 0, 0};
 };
 
 namespace cqk {
@@ -151,6 +153,11 @@ cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_
                                         const double* x, const double* g, const double* d,
                                         const double* b, const double* l, const double* u,
                                         double* grad_a, double* grad_r, const cqk_opts& o);
+cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const double* d, const double* a, const double* b,
+                                const double* l, const double* u, const double* r, double* x,
+                                const double* g, double* grad_a, int32_t backward,
+                                int32_t repeats, cqk_batch_schedule* best, double* best_ms);
 cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                            const double* r, double r_scalar, float* x, double* lambda_out,
                            int32_t* nfree_out, const cqk_opts& o, cqk_info* info);

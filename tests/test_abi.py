@@ -83,6 +83,10 @@ def test_host_side_argument_errors(lib):
                                      null, null, None, None) == 2
     assert lib.cqk_solve_batched_backward_f64(null, 2, null, null, null, null, null, null, null,
                                               null, null, None) == 2
+    assert lib.cqk_tune_batched_cqk_f64(null, 4, null, null, null, null, null, null, null, null,
+                                        null, null, 0, 3, None, None) == 2
+    for which in (2, 3):
+        assert lib.cqk_get_batch_schedule(null, which, C.byref(L.cqk_batch_schedule())) == 2
     so = L.cqk_spg_opts()
     lib.cqk_spg_default_opts(C.byref(so))
     assert so.tol == 1e-4 and so.max_iter == 10000 and so.memory == 10 and so.warm == 1

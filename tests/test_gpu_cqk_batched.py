@@ -327,3 +327,51 @@ def test_batched_cqk_graph_capture_replays(ctx):
         torch.cuda.synchronize()
         assert torch.equal(x, ex) and torch.equal(lam, el)
         assert torch.equal(ga, ega) and torch.equal(gr, egr)
+
+
+SCHEDULES = [(sp, bpc, sf) for sp in (4, 8) for bpc in (1, 2, 3, 4) for sf in (0, 1)]
+
+
+@pytest.mark.parametrize("sp,bpc,sf", SCHEDULES)
+def test_batched_cqk_every_schedule(ctx, sp, bpc, sf):
+    """Every schedule the tuner may pick gives the oracle's solution and VJP
+    (rows on both sides of the wave-row limits 256 and 512)."""
+    off, inst = W.cqk_batched(60, 1, 3000, 81)
+    ctx.set_batch_schedule(sp, bpc, sf, general=True)
+    ctx.set_batch_schedule(sp, bpc, sf, backward=True, general=True)
+    try:
+        x, lam, sts, info = _run(ctx, off, inst)
+        assert info["status"] == 0
+        _check_rows(x, lam, sts, off, inst)
+        res = O.solve_cqk_batched(*[inst[k] for k in "dablu"], off, inst["r"])
+        xr = np.concatenate([q.x for q in res])
+        g = np.random.default_rng(82).standard_normal(xr.size)
+        ga, gr = _vjp(ctx, off, inst, xr, g)
+        ga_ref, gr_ref = O.cqk_vjp_batched(xr, g, inst["d"], inst["b"], inst["l"], inst["u"], off)
+        scale = max(1.0, float(np.max(np.abs(ga_ref))))
+        assert np.max(np.abs(ga - ga_ref)) <= 1e-10 * scale
+        assert np.max(np.abs(gr - gr_ref)) <= 1e-10 * scale
+    finally:
+        ctx.set_batch_schedule(8, 4, 0, general=True)
+        ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
+
+
+def test_batched_cqk_tuner(ctx):
+    off, inst = W.cqk_batched(400, 16, 20000, 83)
+    t = [_dev(inst[k]) for k in "dablu"]
+    offs = _dev(off, torch.int64)
+    r = _dev(inst["r"])
+    sc, ms = ctx.tune_batched_cqk(*t, offs, r, repeats=1)
+    assert sc == ctx.batch_schedule(general=True) and ms > 0
+    assert sc["small_per"] in (4, 8) and 1 <= sc["blocks_per_cu"] <= 4
+    x, lam, sts, info = _run(ctx, off, inst)
+    assert info["status"] == 0
+    rng = np.random.default_rng(84)
+    _check_rows(x, lam, sts, off, inst, rows=sorted(rng.choice(400, 40, replace=False)))
+    g = _dev(rng.standard_normal(x.size))
+    scb, msb = ctx.tune_batched_cqk(*t, offs, r, repeats=1, backward=True, x=_dev(x), g=g)
+    assert scb == ctx.batch_schedule(backward=True, general=True) and msb > 0
+    # the simplex schedules are untouched by the general tuner
+    assert ctx.batch_schedule() == ctx.batch_schedule()
+    ctx.set_batch_schedule(8, 4, 0, general=True)
+    ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
