@@ -306,8 +306,10 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
  * row, each row with its own bracket, breakpoint and secant state): row s
  * is (d, a, b, l, u)[offsets[s] .. offsets[s+1]) with right-hand side r[s].
  * offsets: int64[nseg+1] DEVICE array, non-decreasing, offsets[0] = 0.
- * d, a, b, l, u, x: DEVICE float64 arrays of offsets[nseg] values.
- * r: DEVICE float64[nseg] (required).
+ * d, a, b, l, u, x: DEVICE float64 arrays of offsets[nseg] values (float32
+ * in the _f32 variant, which loads and stores float32 and computes every
+ * sum, the multiplier and the clamp in float64).
+ * r: DEVICE float64[nseg] (required, both variants).
  * lambda_out: optional DEVICE float64[nseg], the row multipliers (NaN for a
  * row without one).  status_out: optional DEVICE int32[nseg], each row's
  * cqk_status.
@@ -323,17 +325,26 @@ cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offs
                                  const double* l, const double* u, const double* r, double* x,
                                  double* lambda_out, int32_t* status_out, const cqk_opts* opts,
                                  cqk_info* info);
+cqk_status cqk_solve_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                 const float* d, const float* a, const float* b, const float* l,
+                                 const float* u, const double* r, float* x, double* lambda_out,
+                                 int32_t* status_out, const cqk_opts* opts, cqk_info* info);
 
 /* Vector-Jacobian product of the batched CQK solution w.r.t. a and r on each
  * row's free set F = {l_i < x_i < u_i} (eq. (xopt) on F, eq. (opt)
  * differentiated):  q = sum_F b^2/d,  mu = (sum_F g b/d)/q,
  *   grad_a_i = [i in F](g_i - b_i mu)/d_i,   grad_r[s] = mu   (0 if F empty).
  * x: forward output, g: upstream gradient, grad_a: output, all DEVICE
- * float64 in the forward layout; grad_r: optional DEVICE float64[nseg]. */
+ * float64 in the forward layout (float32 in the _f32 variant, sums in
+ * float64); grad_r: optional DEVICE float64[nseg]. */
 cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                           const double* x, const double* g, const double* d,
                                           const double* b, const double* l, const double* u,
                                           double* grad_a, double* grad_r, const cqk_opts* opts);
+cqk_status cqk_solve_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                          const float* x, const float* g, const float* d,
+                                          const float* b, const float* l, const float* u,
+                                          float* grad_a, double* grad_r, const cqk_opts* opts);
 
 /* Vector-Jacobian product of the batched simplex projection w.r.t. y and r
  * on each row's support S = {x_i > 0} (derived from eq. (lambdaJ)):

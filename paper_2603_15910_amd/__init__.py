@@ -211,6 +211,18 @@ def cqk_solve_batched_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a,
                  l, u, grad_a, grad_r, _ref(opts))
 
 
+def cqk_solve_batched_f32(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out=None,
+                          status_out=None, opts=None, info=None):
+    return _call("cqk_solve_batched_f32", C.c_void_p(ctx), nseg, offsets, d, a, b, l, u, r, x,
+                 lambda_out, status_out, _ref(opts), _ref(info))
+
+
+def cqk_solve_batched_backward_f32(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r=None,
+                                   opts=None):
+    return _call("cqk_solve_batched_backward_f32", C.c_void_p(ctx), nseg, offsets, x, g, d, b,
+                 l, u, grad_a, grad_r, _ref(opts))
+
+
 def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out=None,
                                     nfree_out=None, opts=None, info=None):
     return _call("cqk_project_simplex_batched_f32", C.c_void_p(ctx), nseg, offsets, y, r,
@@ -443,12 +455,17 @@ class Context:
     def solve_batched(self, d, a, b, l, u, offsets, r, out=None, lambda_out=None,
                       status_out=None, check=True, **kw):
         """Many general CQK rows in one launch: row s is [offsets[s],
-        offsets[s+1]) of the float64 arrays d, a, b, l, u; r a float64 GPU
-        tensor [nseg].  Returns (x, info)."""
+        offsets[s+1]) of the arrays d, a, b, l, u (all float64, or all
+        float32 with float64 arithmetic); r a float64 GPU tensor [nseg].
+        Returns (x, info)."""
         torch = _torch()
         nseg = offsets.numel() - 1
+        dt = d.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("solve_batched takes float64 or float32 arrays")
+        fn = cqk_solve_batched_f64 if dt == torch.float64 else cqk_solve_batched_f32
         x = out if out is not None else torch.empty_like(d)
-        ptrs = [_dev_ptr(t, torch.float64, nm) for t, nm in zip((d, a, b, l, u, x), "dablux")]
+        ptrs = [_dev_ptr(t, dt, nm) for t, nm in zip((d, a, b, l, u, x), "dablux")]
         po = _dev_ptr(offsets, torch.int64, "offsets")
         pr = _dev_ptr(r, torch.float64, "r")
         if r.numel() != nseg:
@@ -458,11 +475,10 @@ class Context:
         opts = make_opts(**kw)
         info = cqk_info()
         self._bind_stream()
-        st = cqk_solve_batched_f64(self.handle, nseg, po, *ptrs[:5], pr, ptrs[5], pl, ps, opts,
-                                   info)
+        st = fn(self.handle, nseg, po, *ptrs[:5], pr, ptrs[5], pl, ps, opts, info)
         self.last_info = info.as_dict()
         if check and st != CQK_OK:
-            raise CqkError(st, "cqk_solve_batched_f64")
+            raise CqkError(st, fn.__name__)
         return x, self.last_info
 
     def solve_batched_backward(self, x, g, d, b, l, u, offsets, grad_a=None, grad_r=None,
@@ -470,16 +486,21 @@ class Context:
         """VJP of solve_batched w.r.t. a (returned) and r (into grad_r)."""
         torch = _torch()
         nseg = offsets.numel() - 1
+        dt = d.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("solve_batched_backward takes float64 or float32 arrays")
+        fn = (cqk_solve_batched_backward_f64 if dt == torch.float64
+              else cqk_solve_batched_backward_f32)
         ga = grad_a if grad_a is not None else torch.empty_like(g)
-        ptrs = [_dev_ptr(t, torch.float64, nm)
+        ptrs = [_dev_ptr(t, dt, nm)
                 for t, nm in zip((x, g, d, b, l, u, ga), ("x", "g", "d", "b", "l", "u", "grad_a"))]
         po = _dev_ptr(offsets, torch.int64, "offsets")
         pgr = _dev_ptr(grad_r, torch.float64, "grad_r") if grad_r is not None else None
         opts = make_opts(**kw)
         self._bind_stream()
-        st = cqk_solve_batched_backward_f64(self.handle, nseg, po, *ptrs, pgr, opts)
+        st = fn(self.handle, nseg, po, *ptrs, pgr, opts)
         if check and st != CQK_OK:
-            raise CqkError(st, "cqk_solve_batched_backward_f64")
+            raise CqkError(st, fn.__name__)
         return ga
 
     def spg_l1_lasso(self, A, b, radius, out=None, check=True, **kw):
@@ -706,8 +727,8 @@ def _autograd_cls():
     class _CqkBatchedSolve(torch.autograd.Function):
         """Batched general CQK with a hand-written HIP backward.
 
-        forward(d, a, b, l, u, offsets, r): float64 GPU tensors, offsets
-        int64 [nseg+1], r float64 [nseg].  Differentiable in a and r;
+        forward(d, a, b, l, u, offsets, r): float64 (or all float32) GPU
+        tensors, offsets int64 [nseg+1], r float64 [nseg].  Differentiable in a and r;
         backward returns (None, grad_a, None, None, None, None, grad_r)."""
 
         @staticmethod
@@ -721,7 +742,7 @@ def _autograd_cls():
             x, d, b, l, u, offsets = ctx.saved_tensors
             nseg = offsets.numel() - 1
             grad_r = torch.empty(nseg, dtype=torch.float64, device=x.device)
-            ga = solve_batched_backward(x, g.contiguous().double(), d, b, l, u, offsets,
+            ga = solve_batched_backward(x, g.contiguous().to(x.dtype), d, b, l, u, offsets,
                                         grad_r=grad_r)
             return None, ga, None, None, None, None, grad_r
 

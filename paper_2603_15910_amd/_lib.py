@@ -163,6 +163,10 @@ SIGNATURES = {
                                         _OPTS, _INFO]),
     "cqk_solve_batched_backward_f64": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
                                                  _P, _OPTS]),
+    "cqk_solve_batched_f32": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                        _OPTS, _INFO]),
+    "cqk_solve_batched_backward_f32": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P,
+                                                 _P, _OPTS]),
     "cqk_spg_default_opts": (None, [C.POINTER(cqk_spg_opts)]),
     "cqk_spg_l1_lasso_f64": (C.c_int, [_P, _I64, _I64, _P, _P, _D, _P, C.POINTER(cqk_spg_opts),
                                        C.POINTER(cqk_spg_info)]),

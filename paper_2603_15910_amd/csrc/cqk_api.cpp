@@ -357,11 +357,15 @@ cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
   return sparse_common<double>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
 }
 
-cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
-                                 const double* d, const double* a, const double* b,
-                                 const double* l, const double* u, const double* r, double* x,
-                                 double* lambda_out, int32_t* status_out, const cqk_opts* opts,
-                                 cqk_info* info) {
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+cqk_status batched_cqk_common(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const T* d,
+                              const T* a, const T* b, const T* l, const T* u, const double* r,
+                              T* x, double* lambda_out, int32_t* status_out,
+                              const cqk_opts* opts, cqk_info* info) {
   if (!ctx || nseg < 0) return CQK_INVALID_ARG;
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, false);
@@ -374,16 +378,21 @@ cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offs
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
-  st = run_batched_cqk_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out, status_out, o,
-                           inf);
+  if constexpr (sizeof(T) == 8)
+    st = run_batched_cqk_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out, status_out, o,
+                             inf);
+  else
+    st = run_batched_cqk_f32(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out, status_out, o,
+                             inf);
   if (st != CQK_OK) return st;
   return (cqk_status)inf->status;
 }
 
-cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
-                                          const double* x, const double* g, const double* d,
-                                          const double* b, const double* l, const double* u,
-                                          double* grad_a, double* grad_r, const cqk_opts* opts) {
+template <typename T>
+cqk_status batched_cqk_backward_common(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                       const T* x, const T* g, const T* d, const T* b,
+                                       const T* l, const T* u, T* grad_a, double* grad_r,
+                                       const cqk_opts* opts) {
   if (!ctx || nseg < 0) return CQK_INVALID_ARG;
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, false);
@@ -391,7 +400,47 @@ cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int6
   if (nseg == 0) return CQK_OK;
   if (!offsets || !x || !g || !d || !b || !l || !u || !grad_a) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
-  return run_batched_cqk_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
+  if constexpr (sizeof(T) == 8)
+    return run_batched_cqk_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
+  else
+    return run_batched_cqk_backward_f32(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
+}
+
+}  // namespace
+
+extern "C" {
+
+cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                 const double* d, const double* a, const double* b,
+                                 const double* l, const double* u, const double* r, double* x,
+                                 double* lambda_out, int32_t* status_out, const cqk_opts* opts,
+                                 cqk_info* info) {
+  return batched_cqk_common<double>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out,
+                                    status_out, opts, info);
+}
+
+cqk_status cqk_solve_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                 const float* d, const float* a, const float* b, const float* l,
+                                 const float* u, const double* r, float* x, double* lambda_out,
+                                 int32_t* status_out, const cqk_opts* opts, cqk_info* info) {
+  return batched_cqk_common<float>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out,
+                                   status_out, opts, info);
+}
+
+cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                          const double* x, const double* g, const double* d,
+                                          const double* b, const double* l, const double* u,
+                                          double* grad_a, double* grad_r, const cqk_opts* opts) {
+  return batched_cqk_backward_common<double>(ctx, nseg, offsets, x, g, d, b, l, u, grad_a,
+                                             grad_r, opts);
+}
+
+cqk_status cqk_solve_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                          const float* x, const float* g, const float* d,
+                                          const float* b, const float* l, const float* u,
+                                          float* grad_a, double* grad_r, const cqk_opts* opts) {
+  return batched_cqk_backward_common<float>(ctx, nseg, offsets, x, g, d, b, l, u, grad_a,
+                                            grad_r, opts);
 }
 
 void cqk_spg_default_opts(cqk_spg_opts* opts) {

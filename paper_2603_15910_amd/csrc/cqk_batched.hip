@@ -917,13 +917,13 @@ struct BatCqkArgs {
   double tol;
   double lam0_user;     // the start of every row with CQK_LAMBDA0_USER
   const int64_t* off;
-  const double *d, *a, *b, *l, *u;
+  const void *d, *a, *b, *l, *u;  // TIn (float or double)
   const double* r;
-  double* x;            // forward output; backward input
+  void* x;              // forward output; backward input (TIn)
   double* lam_out;
   int32_t* status_out;
-  const double* g;      // backward: upstream gradient
-  double* ga;           // backward: grad_a
+  const void* g;        // backward: upstream gradient (TIn)
+  void* ga;             // backward: grad_a (TIn)
   double* gr;           // backward: grad_r
   int32_t* list;
   int64_t* lrow;
@@ -963,10 +963,22 @@ __device__ __forceinline__ void cqk_row_report(const BatCqkArgs& A, int s, const
   atomicMax(&A.counters[CTR_ITMAX], st.iter);
 }
 
-// x_i of eq. (xopt) at the row's multiplier (NaN for a row without one).
-__device__ __forceinline__ double cqk_x_at(const BatCqkArgs& A, int64_t i, double lam) {
-  const double t = fma(A.b[i], lam, A.a[i]) / A.d[i];
-  return fmin(fmax(t, A.l[i]), A.u[i]);
+// The arrays of a call in their element type (FP64 values are used as
+// they are, FP32 values are widened to FP64 for the arithmetic).
+template <typename TIn>
+struct CqkArrays {
+  const TIn *d, *a, *b, *l, *u, *g;
+  TIn *x, *ga;
+  __device__ explicit CqkArrays(const BatCqkArgs& A)
+      : d((const TIn*)A.d), a((const TIn*)A.a), b((const TIn*)A.b), l((const TIn*)A.l),
+        u((const TIn*)A.u), g((const TIn*)A.g), x((TIn*)A.x), ga((TIn*)A.ga) {}
+};
+
+// x_i of eq. (xopt) at the row's multiplier.
+template <typename TIn>
+__device__ __forceinline__ double cqk_x_at(const CqkArrays<TIn>& V, int64_t i, double lam) {
+  const double t = fma((double)V.b[i], lam, (double)V.a[i]) / (double)V.d[i];
+  return fmin(fmax(t, (double)V.l[i]), (double)V.u[i]);
 }
 
 __device__ __forceinline__ bool cqk_has_lambda(const GenState& st) {
@@ -976,8 +988,9 @@ __device__ __forceinline__ bool cqk_has_lambda(const GenState& st) {
 // ---------------------------------------------------------------------------
 // One wave row (L <= 64 * SP), per-index form in registers.
 // ---------------------------------------------------------------------------
-template <int SP>
+template <int SP, typename TIn>
 __device__ void cqk_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t L) {
+  const CqkArrays<TIn> V(A);
   const int lane = threadIdx.x & (kWave - 1);
   double c[SP], sv[SP], bl[SP], bu[SP];
   double bad = 0.0, sc = 0.0, ss = 0.0;
@@ -987,7 +1000,8 @@ __device__ void cqk_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t 
     c[k] = sv[k] = bl[k] = bu[k] = 0.0;
     if (i < L) {
       const int64_t e = base + i;
-      to_form(A.d[e], A.a[e], A.b[e], A.l[e], A.u[e], c[k], sv[k], bl[k], bu[k], bad);
+      to_form((double)V.d[e], (double)V.a[e], (double)V.b[e], (double)V.l[e], (double)V.u[e], c[k],
+              sv[k], bl[k], bu[k], bad);
       sc += c[k];
       ss += sv[k];
     }
@@ -1034,7 +1048,7 @@ __device__ void cqk_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t 
 #pragma unroll
   for (int k = 0; k < SP; ++k) {
     const int64_t i = lane + (int64_t)k * kWave;
-    if (i < L) A.x[base + i] = ok ? cqk_x_at(A, base + i, lam) : __builtin_nan("");
+    if (i < L) V.x[base + i] = (TIn)(ok ? cqk_x_at(V, base + i, lam) : __builtin_nan(""));
   }
   if (lane == 0) cqk_row_report(A, s, st, lam);
 }
@@ -1049,14 +1063,16 @@ struct CqkLds {
   int item;
 };
 
+template <typename TIn>
 __device__ void cqk_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L, CqkLds& S) {
+  const CqkArrays<TIn> V(A);
   const double r = A.r[s];
   GenState st = cqk_row_state(A, r);
-  const double* d = A.d + base;
-  const double* a = A.a + base;
-  const double* b = A.b + base;
-  const double* l = A.l + base;
-  const double* u = A.u + base;
+  const TIn* d = V.d + base;
+  const TIn* a = V.a + base;
+  const TIn* b = V.b + base;
+  const TIn* l = V.l + base;
+  const TIn* u = V.u + base;
   constexpr int64_t STEP = (int64_t)kBlock * kCqkU;
   // kCqkU values per thread with every load issued before the first use
   auto stream = [&](auto&& fn) {
@@ -1066,11 +1082,11 @@ __device__ void cqk_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L
       for (int k = 0; k < kCqkU; ++k) {
         const int64_t i = i0 + (int64_t)k * kBlock;
         const bool in = i < L;
-        vd[k] = in ? d[i] : 1.0;
-        va[k] = in ? a[i] : 0.0;
-        vb[k] = in ? b[i] : 1.0;
-        vl[k] = in ? l[i] : 0.0;
-        vu[k] = in ? u[i] : 0.0;
+        vd[k] = in ? (double)d[i] : 1.0;
+        va[k] = in ? (double)a[i] : 0.0;
+        vb[k] = in ? (double)b[i] : 1.0;
+        vl[k] = in ? (double)l[i] : 0.0;
+        vu[k] = in ? (double)u[i] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < kCqkU; ++k)
@@ -1131,15 +1147,15 @@ __device__ void cqk_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L
   }
   const bool ok = cqk_has_lambda(st);
   const double lam = ok ? st.lam_final : __builtin_nan("");
-  double* x = A.x + base;
+  TIn* x = V.x + base;
   stream([&](int64_t i, double vd, double va, double vb, double vl, double vu) {
     const double t = fma(vb, lam, va) / vd;
-    x[i] = ok ? fmin(fmax(t, vl), vu) : __builtin_nan("");
+    x[i] = (TIn)(ok ? fmin(fmax(t, vl), vu) : __builtin_nan(""));
   });
   if (threadIdx.x == 0) cqk_row_report(A, s, st, lam);
 }
 
-template <int SP>
+template <int SP, typename TIn>
 __global__ __launch_bounds__(kBlock) void bat_cqk_solve_kernel(BatCqkArgs A) {
   __shared__ CqkLds S;
   const int nlong = A.counters[CTR_NLONG];
@@ -1162,12 +1178,12 @@ __global__ __launch_bounds__(kBlock) void bat_cqk_solve_kernel(BatCqkArgs A) {
       idx = is_long ? item : item - nlong;
     }
     if (is_long) {
-      cqk_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], S);
+      cqk_long_row<TIn>(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], S);
     } else {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
       if (k < nshort) {
         const size_t e = (size_t)nlong + k;
-        cqk_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+        cqk_short_row<SP, TIn>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
       }
     }
     __syncthreads();
@@ -1175,8 +1191,9 @@ __global__ __launch_bounds__(kBlock) void bat_cqk_solve_kernel(BatCqkArgs A) {
 }
 
 // Backward of one wave row.
-template <int SP>
+template <int SP, typename TIn>
 __device__ void cqk_vjp_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t L) {
+  const CqkArrays<TIn> V(A);
   const int lane = threadIdx.x & (kWave - 1);
   double q = 0.0, m = 0.0;
   double gv[SP], bd[SP], dv[SP];
@@ -1189,11 +1206,11 @@ __device__ void cqk_vjp_short_row(const BatCqkArgs& A, int s, int64_t base, int6
     dv[k] = 1.0;
     if (i < L) {
       const int64_t e = base + i;
-      const double xv = A.x[e];
-      fr[k] = (xv > A.l[e]) && (xv < A.u[e]);
-      gv[k] = A.g[e];
-      dv[k] = A.d[e];
-      bd[k] = A.b[e];
+      const double xv = (double)V.x[e];
+      fr[k] = (xv > (double)V.l[e]) && (xv < (double)V.u[e]);
+      gv[k] = (double)V.g[e];
+      dv[k] = (double)V.d[e];
+      bd[k] = (double)V.b[e];
       if (fr[k]) {
         q += bd[k] * bd[k] / dv[k];
         m += gv[k] * bd[k] / dv[k];
@@ -1206,22 +1223,24 @@ __device__ void cqk_vjp_short_row(const BatCqkArgs& A, int s, int64_t base, int6
 #pragma unroll
   for (int k = 0; k < SP; ++k) {
     const int64_t i = lane + (int64_t)k * kWave;
-    if (i < L) A.ga[base + i] = fr[k] ? (gv[k] - bd[k] * mu) / dv[k] : 0.0;
+    if (i < L) V.ga[base + i] = (TIn)(fr[k] ? (gv[k] - bd[k] * mu) / dv[k] : 0.0);
   }
   if (lane == 0 && A.gr) A.gr[s] = mu;
 }
 
 // Backward of one workgroup row: the two sums, then the map.
+template <typename TIn>
 __device__ void cqk_vjp_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L,
                                  CqkLds& S) {
+  const CqkArrays<TIn> V(A);
   double acc[2] = {0.0, 0.0};
   for (int64_t i = threadIdx.x; i < L; i += kBlock) {
     const int64_t e = base + i;
-    const double xv = A.x[e];
-    if ((xv > A.l[e]) && (xv < A.u[e])) {
-      const double bv = A.b[e], dv = A.d[e];
+    const double xv = (double)V.x[e];
+    if ((xv > (double)V.l[e]) && (xv < (double)V.u[e])) {
+      const double bv = (double)V.b[e], dv = (double)V.d[e];
       acc[0] += bv * bv / dv;
-      acc[1] += A.g[e] * bv / dv;
+      acc[1] += (double)V.g[e] * bv / dv;
     }
   }
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, S.red, S.tot);
@@ -1229,14 +1248,14 @@ __device__ void cqk_vjp_long_row(const BatCqkArgs& A, int s, int64_t base, int64
   const double mu = (q > 0.0) ? S.tot[1] / q : 0.0;
   for (int64_t i = threadIdx.x; i < L; i += kBlock) {
     const int64_t e = base + i;
-    const double xv = A.x[e];
-    const bool f = (xv > A.l[e]) && (xv < A.u[e]);
-    A.ga[e] = f ? (A.g[e] - A.b[e] * mu) / A.d[e] : 0.0;
+    const double xv = (double)V.x[e];
+    const bool f = (xv > (double)V.l[e]) && (xv < (double)V.u[e]);
+    V.ga[e] = (TIn)(f ? ((double)V.g[e] - (double)V.b[e] * mu) / (double)V.d[e] : 0.0);
   }
   if (threadIdx.x == 0 && A.gr) A.gr[s] = mu;
 }
 
-template <int SP>
+template <int SP, typename TIn>
 __global__ __launch_bounds__(kBlock) void bat_cqk_vjp_kernel(BatCqkArgs A) {
   __shared__ CqkLds S;
   const int nlong = A.counters[CTR_NLONG];
@@ -1259,12 +1278,13 @@ __global__ __launch_bounds__(kBlock) void bat_cqk_vjp_kernel(BatCqkArgs A) {
       idx = is_long ? item : item - nlong;
     }
     if (is_long) {
-      cqk_vjp_long_row(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1], S);
+      cqk_vjp_long_row<TIn>(A, A.list[idx], A.lrow[2 * (size_t)idx], A.lrow[2 * (size_t)idx + 1],
+                            S);
     } else {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
       if (k < nshort) {
         const size_t e = (size_t)nlong + k;
-        cqk_vjp_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+        cqk_vjp_short_row<SP, TIn>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
       }
     }
     __syncthreads();
@@ -1411,8 +1431,8 @@ cqk_status tune(cqk_ctx* ctx, const cqk_batch_schedule* cand, int ncand, int rep
 
 
 // Batched general CQK: the plan, then one persistent launch.
-BatCqkArgs cqk_args(int32_t nseg, const int64_t* offsets, const double* d, const double* a,
-                    const double* b, const double* l, const double* u, const BatWs& w) {
+BatCqkArgs cqk_args(int32_t nseg, const int64_t* offsets, const void* d, const void* a,
+                    const void* b, const void* l, const void* u, const BatWs& w) {
   BatCqkArgs A{};
   A.nseg = nseg;
   A.off = offsets;
@@ -1437,33 +1457,36 @@ void cqk_apply_schedule(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs* 
   *grid = dim3(std::max(1, std::min(ctx->num_cus * sc.blocks_per_cu, A->nseg)));
 }
 
+template <typename TIn>
 void launch_cqk_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs A) {
   dim3 grid;
   cqk_apply_schedule(ctx, sc, &A, &grid);
   plan(ctx, A);
   if (sc.small_per == 4)
-    hipLaunchKernelGGL(bat_cqk_solve_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+    hipLaunchKernelGGL((bat_cqk_solve_kernel<4, TIn>), grid, dim3(kBlock), 0, ctx->stream, A);
   else
-    hipLaunchKernelGGL(bat_cqk_solve_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+    hipLaunchKernelGGL((bat_cqk_solve_kernel<8, TIn>), grid, dim3(kBlock), 0, ctx->stream, A);
 }
 
+template <typename TIn>
 void launch_cqk_backward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatCqkArgs A) {
   dim3 grid;
   cqk_apply_schedule(ctx, sc, &A, &grid);
   plan(ctx, A);
   if (sc.small_per == 4)
-    hipLaunchKernelGGL(bat_cqk_vjp_kernel<4>, grid, dim3(kBlock), 0, ctx->stream, A);
+    hipLaunchKernelGGL((bat_cqk_vjp_kernel<4, TIn>), grid, dim3(kBlock), 0, ctx->stream, A);
   else
-    hipLaunchKernelGGL(bat_cqk_vjp_kernel<8>, grid, dim3(kBlock), 0, ctx->stream, A);
+    hipLaunchKernelGGL((bat_cqk_vjp_kernel<8, TIn>), grid, dim3(kBlock), 0, ctx->stream, A);
 }
 
 }  // namespace
 
-cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
-                               const double* d, const double* a, const double* b,
-                               const double* l, const double* u, const double* r, double* x,
-                               double* lambda_out, int32_t* status_out, const cqk_opts& o,
-                               cqk_info* info) {
+namespace {
+template <typename TIn>
+cqk_status run_batched_cqk(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const TIn* d,
+                           const TIn* a, const TIn* b, const TIn* l, const TIn* u,
+                           const double* r, TIn* x, double* lambda_out, int32_t* status_out,
+                           const cqk_opts& o, cqk_info* info) {
   BatWs w;
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
@@ -1482,7 +1505,7 @@ cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offset
     if (st != CQK_OK) return st;
     hipEventRecord(ctx->events[0], s);
   }
-  launch_cqk_forward(ctx, ctx->sched_cqk_fwd, A);
+  launch_cqk_forward<TIn>(ctx, ctx->sched_cqk_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (info) std::memset(info, 0, sizeof(*info));
@@ -1513,24 +1536,58 @@ cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offset
   return CQK_OK;
 }
 
-cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
-                                        const double* x, const double* g, const double* d,
-                                        const double* b, const double* l, const double* u,
-                                        double* grad_a, double* grad_r, const cqk_opts& o) {
+template <typename TIn>
+cqk_status run_batched_cqk_backward(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const TIn* x, const TIn* g, const TIn* d, const TIn* b,
+                                    const TIn* l, const TIn* u, TIn* grad_a, double* grad_r,
+                                    const cqk_opts& o) {
   BatWs w;
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
   BatCqkArgs A = cqk_args(nseg, offsets, d, nullptr, b, l, u, w);
-  A.x = const_cast<double*>(x);
+  A.x = const_cast<TIn*>(x);
   A.g = g;
   A.ga = grad_a;
   A.gr = grad_r;
-  launch_cqk_backward(ctx, ctx->sched_cqk_bwd, A);
+  launch_cqk_backward<TIn>(ctx, ctx->sched_cqk_bwd, A);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
   return CQK_OK;
 }
+}  // namespace
 
+cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                               const double* d, const double* a, const double* b,
+                               const double* l, const double* u, const double* r, double* x,
+                               double* lambda_out, int32_t* status_out, const cqk_opts& o,
+                               cqk_info* info) {
+  return run_batched_cqk<double>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out,
+                                 status_out, o, info);
+}
+
+cqk_status run_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                               const float* d, const float* a, const float* b, const float* l,
+                               const float* u, const double* r, float* x, double* lambda_out,
+                               int32_t* status_out, const cqk_opts& o, cqk_info* info) {
+  return run_batched_cqk<float>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out, status_out,
+                                o, info);
+}
+
+cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                        const double* x, const double* g, const double* d,
+                                        const double* b, const double* l, const double* u,
+                                        double* grad_a, double* grad_r, const cqk_opts& o) {
+  return run_batched_cqk_backward<double>(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r,
+                                          o);
+}
+
+cqk_status run_batched_cqk_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                        const float* x, const float* g, const float* d,
+                                        const float* b, const float* l, const float* u,
+                                        float* grad_a, double* grad_r, const cqk_opts& o) {
+  return run_batched_cqk_backward<float>(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r,
+                                         o);
+}
 
 cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                 const double* d, const double* a, const double* b,
@@ -1554,10 +1611,12 @@ cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
   double ms = 0.0;
   if (backward)
     st = tune(ctx, cand, nc, repeats,
-              [&](const cqk_batch_schedule& sc) { launch_cqk_backward(ctx, sc, A); }, &bi, &ms);
+              [&](const cqk_batch_schedule& sc) { launch_cqk_backward<double>(ctx, sc, A); }, &bi,
+              &ms);
   else
     st = tune(ctx, cand, nc, repeats,
-              [&](const cqk_batch_schedule& sc) { launch_cqk_forward(ctx, sc, A); }, &bi, &ms);
+              [&](const cqk_batch_schedule& sc) { launch_cqk_forward<double>(ctx, sc, A); }, &bi,
+              &ms);
   if (st != CQK_OK) return st;
   (backward ? ctx->sched_cqk_bwd : ctx->sched_cqk_fwd) = cand[bi];
   if (best) *best = cand[bi];

@@ -149,6 +149,14 @@ cqk_status run_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offset
                                const double* l, const double* u, const double* r, double* x,
                                double* lambda_out, int32_t* status_out, const cqk_opts& o,
                                cqk_info* info);
+cqk_status run_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                               const float* d, const float* a, const float* b, const float* l,
+                               const float* u, const double* r, float* x, double* lambda_out,
+                               int32_t* status_out, const cqk_opts& o, cqk_info* info);
+cqk_status run_batched_cqk_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                        const float* x, const float* g, const float* d,
+                                        const float* b, const float* l, const float* u,
+                                        float* grad_a, double* grad_r, const cqk_opts& o);
 cqk_status run_batched_cqk_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                         const double* x, const double* g, const double* d,
                                         const double* b, const double* l, const double* u,

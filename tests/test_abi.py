@@ -83,6 +83,10 @@ def test_host_side_argument_errors(lib):
                                      null, null, None, None) == 2
     assert lib.cqk_solve_batched_backward_f64(null, 2, null, null, null, null, null, null, null,
                                               null, null, None) == 2
+    assert lib.cqk_solve_batched_f32(null, 2, null, null, null, null, null, null, null, null,
+                                     null, null, None, None) == 2
+    assert lib.cqk_solve_batched_backward_f32(null, 2, null, null, null, null, null, null, null,
+                                              null, null, None) == 2
     assert lib.cqk_tune_batched_cqk_f64(null, 4, null, null, null, null, null, null, null, null,
                                         null, null, 0, 3, None, None) == 2
     for which in (2, 3):

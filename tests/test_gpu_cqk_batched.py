@@ -1,6 +1,6 @@
 """GPU parity of the batched general CQK solve (Algorithm 1 per row,
 Section 2.1) and of its VJP w.r.t. a and r against the CPU oracle, through
-the C ABI (cqk_solve_batched_f64, cqk_solve_batched_backward_f64).
+the C ABI (cqk_solve_batched_f64/_f32, cqk_solve_batched_backward_f64/_f32).
 
 Rows of at most 512 values are solved by one wave, longer rows by a
 workgroup; the sizes below mix both, with ragged lengths and empty rows.
@@ -33,8 +33,8 @@ def _dev(v, dtype=torch.float64):
     return torch.from_numpy(np.ascontiguousarray(v)).to("cuda", dtype)
 
 
-def _run(ctx, off, inst, **kw):
-    t = [_dev(inst[k]) for k in "dablu"]
+def _run(ctx, off, inst, dtype=torch.float64, **kw):
+    t = [_dev(inst[k], dtype) for k in "dablu"]
     nseg = off.size - 1
     lam = torch.full((nseg,), -7.0, dtype=torch.float64, device="cuda")
     sts = torch.full((nseg,), -7, dtype=torch.int32, device="cuda")
@@ -48,7 +48,7 @@ def _row(inst, off, s):
     return {k: np.asarray(inst[k])[lo:hi] for k in "dablu"} | {"r": float(inst["r"][s])}
 
 
-def _check_rows(x, lam, sts, off, inst, rows=None):
+def _check_rows(x, lam, sts, off, inst, rows=None, tol=1e-10):
     res = O.solve_cqk_batched(*[inst[k] for k in "dablu"], off, inst["r"]) if rows is None \
         else None
     for k, s in enumerate(range(off.size - 1) if rows is None else rows):
@@ -58,7 +58,7 @@ def _check_rows(x, lam, sts, off, inst, rows=None):
         assert sts[s] == 0, (s, sts[s])
         lo, hi = int(off[s]), int(off[s + 1])
         if hi > lo:
-            check_cqk(x[lo:hi], row, ref, 1e-10)
+            check_cqk(x[lo:hi], row, ref, tol)
         if ref.unique and hi > lo:
             # x is the parity claim; the multiplier only has to be the one
             # that x came from (stopping criteria bound phi, not lam)
@@ -181,11 +181,12 @@ def test_batched_cqk_full_size_sampled(ctx):
 # ---------------------------------------------------------------------------
 # VJP
 # ---------------------------------------------------------------------------
-def _vjp(ctx, off, inst, x, g):
-    t = {k: _dev(inst[k]) for k in "dblu"}
+def _vjp(ctx, off, inst, x, g, dtype=torch.float64):
+    t = {k: _dev(inst[k], dtype) for k in "dblu"}
     nseg = off.size - 1
     gr = torch.full((nseg,), -7.0, dtype=torch.float64, device="cuda")
-    ga = ctx.solve_batched_backward(_dev(x), _dev(g), t["d"], t["b"], t["l"], t["u"],
+    ga = ctx.solve_batched_backward(_dev(x, dtype), _dev(g, dtype), t["d"], t["b"], t["l"],
+                                    t["u"],
                                     _dev(off, torch.int64), grad_r=gr)
     return ga.cpu().numpy(), gr.cpu().numpy()
 
@@ -201,6 +202,64 @@ def test_batched_cqk_vjp_parity(ctx, nseg, lo, hi):
     scale = max(1.0, float(np.max(np.abs(ga_ref))), float(np.max(np.abs(gr_ref))))
     assert np.max(np.abs(ga - ga_ref)) <= 1e-10 * scale
     assert np.max(np.abs(gr - gr_ref)) <= 1e-10 * scale
+
+
+def _round32(inst):
+    """The instance as float32 values, held in float64 for the oracle."""
+    return {k: (np.asarray(v, dtype=np.float32).astype(np.float64) if k in "dablu" else v)
+            for k, v in inst.items()}
+
+
+@pytest.mark.parametrize("nseg,lo,hi", [(1, 1, 1), (9, 1, 5000), (300, 1, 3000),
+                                        (64, 200, 20000)])
+@pytest.mark.parametrize("start", ["zero", "formula"])
+def test_batched_cqk_fp32_parity(ctx, nseg, lo, hi, start):
+    """float32 arrays, float64 arithmetic: each row within the FP32 bar of the
+    oracle run on the same (rounded) values."""
+    off, inst = W.cqk_batched(nseg, lo, hi, 61 + nseg)
+    inst = _round32(inst)
+    x, lam, sts, info = _run(ctx, off, inst, dtype=torch.float32, lambda0=start)
+    assert info["status"] == 0, info
+    _check_rows(x, lam, sts, off, inst, tol=1e-5)
+
+
+@pytest.mark.parametrize("nseg,lo,hi", [(1, 5, 5), (50, 1, 3000), (200, 100, 10000)])
+def test_batched_cqk_fp32_vjp_parity(ctx, nseg, lo, hi):
+    """The VJP on float32 arrays: x is the oracle's solution rounded to
+    float32 and both sides read the free set from that same x."""
+    off, inst = W.cqk_batched(nseg, lo, hi, 81 + nseg)
+    inst = _round32(inst)
+    res = O.solve_cqk_batched(*[inst[k] for k in "dablu"], off, inst["r"])
+    x = np.concatenate([r.x for r in res]).astype(np.float32).astype(np.float64)
+    g = np.random.default_rng(82).standard_normal(x.size).astype(np.float32).astype(np.float64)
+    ga, gr = _vjp(ctx, off, inst, x, g, dtype=torch.float32)
+    ga_ref, gr_ref = O.cqk_vjp_batched(x, g, inst["d"], inst["b"], inst["l"], inst["u"], off)
+    scale = max(1.0, float(np.max(np.abs(ga_ref))), float(np.max(np.abs(gr_ref))))
+    assert np.max(np.abs(ga - ga_ref)) <= 1e-5 * scale
+    assert np.max(np.abs(gr - gr_ref)) <= 1e-5 * scale
+
+
+def test_batched_cqk_fp32_autograd(ctx):
+    import paper_2603_15910_amd as cqk
+    off, inst = W.cqk_batched(30, 20, 2000, 43)
+    inst = _round32(inst)
+    t = [_dev(inst[k], torch.float32) for k in "dablu"]
+    a = t[1].clone().requires_grad_(True)
+    r = _dev(inst["r"]).requires_grad_(True)
+    x = cqk.CqkBatchedSolve.apply(t[0], a, t[2], t[3], t[4], _dev(off, torch.int64), r)
+    assert x.dtype == torch.float32
+    (x.double() * 1.0).sum().backward()
+    assert a.grad.dtype == torch.float32 and r.grad.dtype == torch.float64
+    # with g = 1 the gradient w.r.t. a is [F](1 - b mu)/d and sum_F b grad_a = 0
+    ga = a.grad.double().cpu().numpy()
+    xs = x.detach().double().cpu().numpy()
+    for s in range(off.size - 1):
+        lo, hi = int(off[s]), int(off[s + 1])
+        b = inst["b"][lo:hi]
+        free = (xs[lo:hi] > inst["l"][lo:hi]) & (xs[lo:hi] < inst["u"][lo:hi])
+        assert not np.any(ga[lo:hi][~free])
+        assert abs(float(np.sum(b[free] * ga[lo:hi][free]))) <= 1e-4 * max(
+            1.0, float(np.sum(np.abs(b * ga[lo:hi]))))
 
 
 def test_batched_cqk_vjp_empty_free_set(ctx):
