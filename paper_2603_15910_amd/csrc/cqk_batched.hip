@@ -1074,19 +1074,32 @@ __device__ void cqk_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L
   const TIn* l = V.l + base;
   const TIn* u = V.u + base;
   constexpr int64_t STEP = (int64_t)kBlock * kCqkU;
-  // kCqkU values per thread with every load issued before the first use
+  // kCqkU values per thread with every load issued before the first use:
+  // the loads are unconditional (a lane past the end re-reads the last value,
+  // L > i0 >= 0 inside the loop) and the neutral values are selected after,
+  // so no load sits behind a branch and its own wait
   auto stream = [&](auto&& fn) {
     for (int64_t i0 = threadIdx.x; i0 < L; i0 += STEP) {
-      double vd[kCqkU], va[kCqkU], vb[kCqkU], vl[kCqkU], vu[kCqkU];
+      TIn rd[kCqkU], ra[kCqkU], rb[kCqkU], rl[kCqkU], ru[kCqkU];
 #pragma unroll
       for (int k = 0; k < kCqkU; ++k) {
         const int64_t i = i0 + (int64_t)k * kBlock;
-        const bool in = i < L;
-        vd[k] = in ? (double)d[i] : 1.0;
-        va[k] = in ? (double)a[i] : 0.0;
-        vb[k] = in ? (double)b[i] : 1.0;
-        vl[k] = in ? (double)l[i] : 0.0;
-        vu[k] = in ? (double)u[i] : 0.0;
+        const int64_t ic = i < L ? i : L - 1;
+        rd[k] = d[ic];
+        ra[k] = a[ic];
+        rb[k] = b[ic];
+        rl[k] = l[ic];
+        ru[k] = u[ic];
+      }
+      double vd[kCqkU], va[kCqkU], vb[kCqkU], vl[kCqkU], vu[kCqkU];
+#pragma unroll
+      for (int k = 0; k < kCqkU; ++k) {
+        const bool in = i0 + (int64_t)k * kBlock < L;
+        vd[k] = in ? (double)rd[k] : 1.0;
+        va[k] = in ? (double)ra[k] : 0.0;
+        vb[k] = in ? (double)rb[k] : 1.0;
+        vl[k] = in ? (double)rl[k] : 0.0;
+        vu[k] = in ? (double)ru[k] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < kCqkU; ++k)
