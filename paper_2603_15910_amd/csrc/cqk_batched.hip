@@ -1246,24 +1246,58 @@ template <typename TIn>
 __device__ void cqk_vjp_long_row(const BatCqkArgs& A, int s, int64_t base, int64_t L,
                                  CqkLds& S) {
   const CqkArrays<TIn> V(A);
+  constexpr int64_t STEP = (int64_t)kBlock * kCqkU;
+  // kCqkU values per thread, all six loads of each issued before the first
+  // use (index clamped to the row, L > i0 >= 0 inside the loop); lanes past
+  // the end count as not free
+  auto stream = [&](int64_t i0, bool (&fr)[kCqkU], double (&xg)[kCqkU], double (&xb)[kCqkU],
+                    double (&xd)[kCqkU]) {
+    TIn rx[kCqkU], rl[kCqkU], ru[kCqkU], rb[kCqkU], rd[kCqkU], rg[kCqkU];
+#pragma unroll
+    for (int k = 0; k < kCqkU; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      const int64_t e = base + (i < L ? i : L - 1);
+      rx[k] = V.x[e];
+      rl[k] = V.l[e];
+      ru[k] = V.u[e];
+      rb[k] = V.b[e];
+      rd[k] = V.d[e];
+      rg[k] = V.g[e];
+    }
+#pragma unroll
+    for (int k = 0; k < kCqkU; ++k) {
+      const double xv = (double)rx[k];
+      fr[k] = (i0 + (int64_t)k * kBlock < L) && (xv > (double)rl[k]) && (xv < (double)ru[k]);
+      xg[k] = (double)rg[k];
+      xb[k] = (double)rb[k];
+      xd[k] = (double)rd[k];
+    }
+  };
   double acc[2] = {0.0, 0.0};
-  for (int64_t i = threadIdx.x; i < L; i += kBlock) {
-    const int64_t e = base + i;
-    const double xv = (double)V.x[e];
-    if ((xv > (double)V.l[e]) && (xv < (double)V.u[e])) {
-      const double bv = (double)V.b[e], dv = (double)V.d[e];
-      acc[0] += bv * bv / dv;
-      acc[1] += (double)V.g[e] * bv / dv;
+  for (int64_t i0 = threadIdx.x; i0 < L; i0 += STEP) {
+    bool fr[kCqkU];
+    double xg[kCqkU], xb[kCqkU], xd[kCqkU];
+    stream(i0, fr, xg, xb, xd);
+#pragma unroll
+    for (int k = 0; k < kCqkU; ++k) {
+      if (fr[k]) {
+        acc[0] += xb[k] * xb[k] / xd[k];
+        acc[1] += xg[k] * xb[k] / xd[k];
+      }
     }
   }
   block_reduce<2, 0, 0, kBlock>(acc, nullptr, nullptr, S.red, S.tot);
   const double q = S.tot[0];
   const double mu = (q > 0.0) ? S.tot[1] / q : 0.0;
-  for (int64_t i = threadIdx.x; i < L; i += kBlock) {
-    const int64_t e = base + i;
-    const double xv = (double)V.x[e];
-    const bool f = (xv > (double)V.l[e]) && (xv < (double)V.u[e]);
-    V.ga[e] = (TIn)(f ? ((double)V.g[e] - (double)V.b[e] * mu) / (double)V.d[e] : 0.0);
+  for (int64_t i0 = threadIdx.x; i0 < L; i0 += STEP) {
+    bool fr[kCqkU];
+    double xg[kCqkU], xb[kCqkU], xd[kCqkU];
+    stream(i0, fr, xg, xb, xd);
+#pragma unroll
+    for (int k = 0; k < kCqkU; ++k) {
+      const int64_t i = i0 + (int64_t)k * kBlock;
+      if (i < L) V.ga[base + i] = (TIn)(fr[k] ? (xg[k] - xb[k] * mu) / xd[k] : 0.0);
+    }
   }
   if (threadIdx.x == 0 && A.gr) A.gr[s] = mu;
 }
