@@ -614,12 +614,23 @@ __device__ void solve_short_row(const BatArgs& A, int s, int64_t base, int64_t L
   uint32_t active = 0;
   double bad = 0.0;
 #pragma unroll
-  for (int k = 0; k < SP; ++k) {
-    const int64_t i = (int64_t)k * kWave + lane;
-    v[k] = (i < L) ? y[i] : 0.f;
-    if (i < L) {
-      active |= 1u << k;
-      bad += (fabsf(v[k]) < __builtin_huge_valf()) ? 0.0 : 1.0;
+  for (int k = 0; k < SP; ++k) v[k] = 0.f;
+  if (L > 0) {
+    // every load issued before the first use (index clamped to the row)
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t i = (int64_t)k * kWave + lane;
+      v[k] = y[i < L ? i : L - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t i = (int64_t)k * kWave + lane;
+      if (i < L) {
+        active |= 1u << k;
+        bad += (fabsf(v[k]) < __builtin_huge_valf()) ? 0.0 : 1.0;
+      } else {
+        v[k] = 0.f;
+      }
     }
   }
   bad = wave_sum(bad);
@@ -836,10 +847,22 @@ __device__ void vjp_short_row(const BatArgs& A, int s, int64_t base, int64_t L) 
   float xs[SP], gs[SP];
   double cnt = 0.0, sum = 0.0;
 #pragma unroll
+  for (int k = 0; k < SP; ++k) xs[k] = gs[k] = 0.f;
+  if (L > 0) {
+    // every load issued before the first use (index clamped to the row)
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t i = (int64_t)k * kWave + lane;
+      const int64_t e = base + (i < L ? i : L - 1);
+      xs[k] = A.x[e];
+      gs[k] = A.g[e];
+    }
+#pragma unroll
+    for (int k = 0; k < SP; ++k)
+      if ((int64_t)k * kWave + lane >= L) xs[k] = gs[k] = 0.f;
+  }
+#pragma unroll
   for (int k = 0; k < SP; ++k) {
-    const int64_t i = (int64_t)k * kWave + lane;
-    xs[k] = (i < L) ? A.x[base + i] : 0.f;
-    gs[k] = (i < L) ? A.g[base + i] : 0.f;
     if (xs[k] > 0.f) {
       cnt += 1.0;
       sum += (double)gs[k];
@@ -995,15 +1018,29 @@ __device__ void cqk_short_row(const BatCqkArgs& A, int s, int64_t base, int64_t 
   double c[SP], sv[SP], bl[SP], bu[SP];
   double bad = 0.0, sc = 0.0, ss = 0.0;
 #pragma unroll
-  for (int k = 0; k < SP; ++k) {
-    const int64_t i = lane + (int64_t)k * kWave;
-    c[k] = sv[k] = bl[k] = bu[k] = 0.0;
-    if (i < L) {
-      const int64_t e = base + i;
-      to_form((double)V.d[e], (double)V.a[e], (double)V.b[e], (double)V.l[e], (double)V.u[e], c[k],
-              sv[k], bl[k], bu[k], bad);
-      sc += c[k];
-      ss += sv[k];
+  for (int k = 0; k < SP; ++k) c[k] = sv[k] = bl[k] = bu[k] = 0.0;
+  if (L > 0) {
+    // every load issued before the first use (index clamped to the row), so
+    // the row costs one memory round trip, not one per value of a lane
+    TIn rd[SP], ra[SP], rb[SP], rl[SP], ru[SP];
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t i = lane + (int64_t)k * kWave;
+      const int64_t e = base + (i < L ? i : L - 1);
+      rd[k] = V.d[e];
+      ra[k] = V.a[e];
+      rb[k] = V.b[e];
+      rl[k] = V.l[e];
+      ru[k] = V.u[e];
+    }
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      if (lane + (int64_t)k * kWave < L) {
+        to_form((double)rd[k], (double)ra[k], (double)rb[k], (double)rl[k], (double)ru[k], c[k],
+                sv[k], bl[k], bu[k], bad);
+        sc += c[k];
+        ss += sv[k];
+      }
     }
   }
   const double r = A.r[s];
@@ -1213,20 +1250,36 @@ __device__ void cqk_vjp_short_row(const BatCqkArgs& A, int s, int64_t base, int6
   bool fr[SP];
 #pragma unroll
   for (int k = 0; k < SP; ++k) {
-    const int64_t i = lane + (int64_t)k * kWave;
     fr[k] = false;
     gv[k] = bd[k] = 0.0;
     dv[k] = 1.0;
-    if (i < L) {
-      const int64_t e = base + i;
-      const double xv = (double)V.x[e];
-      fr[k] = (xv > (double)V.l[e]) && (xv < (double)V.u[e]);
-      gv[k] = (double)V.g[e];
-      dv[k] = (double)V.d[e];
-      bd[k] = (double)V.b[e];
-      if (fr[k]) {
-        q += bd[k] * bd[k] / dv[k];
-        m += gv[k] * bd[k] / dv[k];
+  }
+  if (L > 0) {
+    // every load issued before the first use (index clamped to the row)
+    TIn rx[SP], rl[SP], ru[SP], rg[SP], rd[SP], rb[SP];
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      const int64_t i = lane + (int64_t)k * kWave;
+      const int64_t e = base + (i < L ? i : L - 1);
+      rx[k] = V.x[e];
+      rl[k] = V.l[e];
+      ru[k] = V.u[e];
+      rg[k] = V.g[e];
+      rd[k] = V.d[e];
+      rb[k] = V.b[e];
+    }
+#pragma unroll
+    for (int k = 0; k < SP; ++k) {
+      if (lane + (int64_t)k * kWave < L) {
+        const double xv = (double)rx[k];
+        fr[k] = (xv > (double)rl[k]) && (xv < (double)ru[k]);
+        gv[k] = (double)rg[k];
+        dv[k] = (double)rd[k];
+        bd[k] = (double)rb[k];
+        if (fr[k]) {
+          q += bd[k] * bd[k] / dv[k];
+          m += gv[k] * bd[k] / dv[k];
+        }
       }
     }
   }
