@@ -386,24 +386,27 @@ def extra_batched_cqk(ctx, dev, torch, row_loop=True):
         "backward_gbs_48B_per_elem": 48.0 * total / (ms_b * 1e-3) / 1e9,
         "per_row_loop_ms_scaled_from_512_rows": loop_ms,
         "speedup_vs_per_row_loop": (loop_ms / ms) if loop_ms else None}}
-    # the same rows as float32 arrays (float64 arithmetic), same schedules
+    # the same rows as float32 arrays (float64 arithmetic), schedules tuned on them
     t32 = [v.float() for v in t]
     x32 = torch.empty_like(t32[0])
     g32 = g.float()
     ga32 = torch.empty_like(g32)
+    sched32, _ = ctx.tune_batched_cqk(*t32, offs, r, repeats=2)
     ctx.solve_batched(*t32, offs, r, out=x32)
     ms32 = timed(lambda: ctx.solve_batched(*t32, offs, r, out=x32), 5, sync)
     _, info32 = ctx.solve_batched(*t32, offs, r, out=x32)
     bwd32 = lambda: ctx.solve_batched_backward(x32, g32, t32[0], t32[2], t32[3], t32[4], offs,
                                                grad_a=ga32, grad_r=gr)
     bwd32()
+    sched32_b, _ = ctx.tune_batched_cqk(*t32, offs, r, repeats=2, backward=True, x=x32, g=g32)
     ms32_b = timed(bwd32, 5, sync)
     out["batched_cqk_8192rows_f32"] = {
         "rows": 8192, "elements": total, "ms": ms32, "elements_per_s": total / (ms32 * 1e-3),
         "mean_iterations": info32["passes"] / 8192, "max_iterations": info32["iterations"],
         "gbs_20B_per_elem_per_iteration":
             20.0 * total * info32["passes"] / 8192 / (ms32 * 1e-3) / 1e9,
-        "status": info32["status_name"], "backward_ms": ms32_b,
+        "status": info32["status_name"], "schedule": sched32, "backward_ms": ms32_b,
+        "backward_schedule": sched32_b,
         "backward_gbs_24B_per_elem": 24.0 * total / (ms32_b * 1e-3) / 1e9}
     del t32, x32, g32, ga32
     ctx.set_batch_schedule(8, 4, 0, general=True)

@@ -400,12 +400,20 @@ cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64
  * grad_a; grad_a is overwritten) on these rows under every candidate
  * schedule, as cqk_tune_batched_f32 does, from lambda = 0 with the default
  * options, and keeps the fastest as the context's schedule of that kind
- * (which = 2 or 3 above).  Synchronises; not under graph capture. */
+ * (which = 2 or 3 above; one schedule of each kind serves both element
+ * types).  The _f32 variant times the float32 calls.  Synchronises; not under
+ * graph capture. */
 cqk_status cqk_tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                     const double* d, const double* a, const double* b,
                                     const double* l, const double* u, const double* r,
                                     double* x, const double* g, double* grad_a,
                                     int32_t backward, int32_t repeats, cqk_batch_schedule* best,
+                                    double* best_ms);
+cqk_status cqk_tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const float* d, const float* a, const float* b,
+                                    const float* l, const float* u, const double* r, float* x,
+                                    const float* g, float* grad_a, int32_t backward,
+                                    int32_t repeats, cqk_batch_schedule* best,
                                     double* best_ms);
 
 #ifdef __cplusplus

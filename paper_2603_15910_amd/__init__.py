@@ -589,22 +589,28 @@ class Context:
                          g=None):
         """Times every candidate schedule of the batched general CQK forward
         (or, backward=True, of its VJP: needs x and g) on these rows and keeps
-        the fastest in the context; returns (schedule dict, ms)."""
+        the fastest in the context; returns (schedule dict, ms).  The arrays
+        are all float64 or all float32 (r float64), as for solve_batched."""
         torch = _torch()
         nseg = offsets.numel() - 1
+        dt = d.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("tune_batched_cqk takes float64 or float32 arrays")
+        name = "cqk_tune_batched_cqk_f64" if dt == torch.float64 else "cqk_tune_batched_cqk_f32"
         xx = x if x is not None else torch.empty_like(d)
         ga = torch.empty_like(d) if backward else None
-        ptr = lambda t, nm: _dev_ptr(t, torch.float64, nm) if t is not None else None
+        ptr = lambda t, nm: _dev_ptr(t, dt, nm) if t is not None else None
         sc = L.cqk_batch_schedule()
         ms = C.c_double(0.0)
         self._bind_stream()
-        st = _call("cqk_tune_batched_cqk_f64", C.c_void_p(self.handle), nseg,
+        st = _call(name, C.c_void_p(self.handle), nseg,
                    _dev_ptr(offsets, torch.int64, "offsets"), ptr(d, "d"), ptr(a, "a"),
-                   ptr(b, "b"), ptr(l, "l"), ptr(u, "u"), ptr(r, "r"), ptr(xx, "x"),
+                   ptr(b, "b"), ptr(l, "l"), ptr(u, "u"),
+                   _dev_ptr(r, torch.float64, "r") if r is not None else None, ptr(xx, "x"),
                    ptr(g, "g"), ptr(ga, "grad_a"), 1 if backward else 0, int(repeats),
                    C.byref(sc), C.byref(ms))
         if st != CQK_OK:
-            raise CqkError(st, "cqk_tune_batched_cqk_f64")
+            raise CqkError(st, name)
         return sc.as_dict(), ms.value
 
     def tune_batched(self, y, offsets, r=1.0, repeats=3, out=None):

@@ -174,6 +174,10 @@ SIGNATURES = {
                                            _P, C.c_int32, C.c_int32,
                                            C.POINTER(cqk_batch_schedule),
                                            C.POINTER(C.c_double)]),
+    "cqk_tune_batched_cqk_f32": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P,
+                                           _P, C.c_int32, C.c_int32,
+                                           C.POINTER(cqk_batch_schedule),
+                                           C.POINTER(C.c_double)]),
     "cqk_solve_warm_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_warm_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),

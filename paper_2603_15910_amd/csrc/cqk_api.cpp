@@ -549,6 +549,21 @@ cqk_status cqk_tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* o
                               repeats, best, best_ms);
 }
 
+cqk_status cqk_tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                    const float* d, const float* a, const float* b,
+                                    const float* l, const float* u, const double* r, float* x,
+                                    const float* g, float* grad_a, int32_t backward,
+                                    int32_t repeats, cqk_batch_schedule* best,
+                                    double* best_ms) {
+  if (!ctx || nseg <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
+  if (backward != 0 && backward != 1) return CQK_INVALID_ARG;
+  if (!offsets || !d || !b || !l || !u || !x) return CQK_INVALID_ARG;
+  if (backward ? (!g || !grad_a) : (!a || !r)) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  return tune_batched_cqk_f32(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
+                              repeats, best, best_ms);
+}
+
 cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                 const float* y, const double* r, double r_scalar, float* x,
                                 int32_t repeats, cqk_batch_schedule* best, double* best_ms) {

@@ -1689,11 +1689,13 @@ cqk_status run_batched_cqk_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_
                                          o);
 }
 
-cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
-                                const double* d, const double* a, const double* b,
-                                const double* l, const double* u, const double* r, double* x,
-                                const double* g, double* grad_a, int32_t backward,
-                                int32_t repeats, cqk_batch_schedule* best, double* best_ms) {
+namespace {
+template <typename TIn>
+cqk_status tune_batched_cqk(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const TIn* d,
+                            const TIn* a, const TIn* b, const TIn* l, const TIn* u,
+                            const double* r, TIn* x, const TIn* g, TIn* grad_a,
+                            int32_t backward, int32_t repeats, cqk_batch_schedule* best,
+                            double* best_ms) {
   BatWs w;
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
@@ -1711,11 +1713,11 @@ cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
   double ms = 0.0;
   if (backward)
     st = tune(ctx, cand, nc, repeats,
-              [&](const cqk_batch_schedule& sc) { launch_cqk_backward<double>(ctx, sc, A); }, &bi,
+              [&](const cqk_batch_schedule& sc) { launch_cqk_backward<TIn>(ctx, sc, A); }, &bi,
               &ms);
   else
     st = tune(ctx, cand, nc, repeats,
-              [&](const cqk_batch_schedule& sc) { launch_cqk_forward<double>(ctx, sc, A); }, &bi,
+              [&](const cqk_batch_schedule& sc) { launch_cqk_forward<TIn>(ctx, sc, A); }, &bi,
               &ms);
   if (st != CQK_OK) return st;
   (backward ? ctx->sched_cqk_bwd : ctx->sched_cqk_fwd) = cand[bi];
@@ -1723,9 +1725,25 @@ cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
   if (best_ms) *best_ms = ms;
   return CQK_OK;
 }
-
-namespace {
 }  // namespace
+
+cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const double* d, const double* a, const double* b,
+                                const double* l, const double* u, const double* r, double* x,
+                                const double* g, double* grad_a, int32_t backward,
+                                int32_t repeats, cqk_batch_schedule* best, double* best_ms) {
+  return tune_batched_cqk<double>(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
+                                  repeats, best, best_ms);
+}
+
+cqk_status tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const float* d, const float* a, const float* b, const float* l,
+                                const float* u, const double* r, float* x, const float* g,
+                                float* grad_a, int32_t backward, int32_t repeats,
+                                cqk_batch_schedule* best, double* best_ms) {
+  return tune_batched_cqk<float>(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
+                                 repeats, best, best_ms);
+}
 
 bool valid_schedule(const cqk_batch_schedule& sc) {
   return (sc.small_per == 4 || sc.small_per == 8) && sc.blocks_per_cu >= 1 &&

@@ -166,6 +166,11 @@ cqk_status tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
                                 const double* l, const double* u, const double* r, double* x,
                                 const double* g, double* grad_a, int32_t backward,
                                 int32_t repeats, cqk_batch_schedule* best, double* best_ms);
+cqk_status tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                const float* d, const float* a, const float* b, const float* l,
+                                const float* u, const double* r, float* x, const float* g,
+                                float* grad_a, int32_t backward, int32_t repeats,
+                                cqk_batch_schedule* best, double* best_ms);
 cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                            const double* r, double r_scalar, float* x, double* lambda_out,
                            int32_t* nfree_out, const cqk_opts& o, cqk_info* info);

@@ -89,6 +89,8 @@ def test_host_side_argument_errors(lib):
                                               null, null, None) == 2
     assert lib.cqk_tune_batched_cqk_f64(null, 4, null, null, null, null, null, null, null, null,
                                         null, null, 0, 3, None, None) == 2
+    assert lib.cqk_tune_batched_cqk_f32(null, 4, null, null, null, null, null, null, null, null,
+                                        null, null, 0, 3, None, None) == 2
     for which in (2, 3):
         assert lib.cqk_get_batch_schedule(null, which, C.byref(L.cqk_batch_schedule())) == 2
     so = L.cqk_spg_opts()

@@ -415,6 +415,31 @@ def test_batched_cqk_every_schedule(ctx, sp, bpc, sf):
         ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
 
 
+def test_batched_cqk_fp32_tuner(ctx):
+    """The tuner on float32 arrays times the float32 kernels and sets the
+    schedules the float32 calls then use."""
+    off, inst = W.cqk_batched(300, 16, 20000, 87)
+    inst = _round32(inst)
+    t = [_dev(inst[k], torch.float32) for k in "dablu"]
+    offs = _dev(off, torch.int64)
+    r = _dev(inst["r"])
+    try:
+        sc, ms = ctx.tune_batched_cqk(*t, offs, r, repeats=1)
+        assert sc == ctx.batch_schedule(general=True) and ms > 0
+        x, lam, sts, info = _run(ctx, off, inst, dtype=torch.float32)
+        assert info["status"] == 0
+        rng = np.random.default_rng(88)
+        _check_rows(x, lam, sts, off, inst, rows=sorted(rng.choice(300, 30, replace=False)),
+                    tol=1e-5)
+        g = _dev(rng.standard_normal(x.size), torch.float32)
+        scb, msb = ctx.tune_batched_cqk(*t, offs, r, repeats=1, backward=True,
+                                        x=_dev(x, torch.float32), g=g)
+        assert scb == ctx.batch_schedule(backward=True, general=True) and msb > 0
+    finally:
+        ctx.set_batch_schedule(8, 4, 0, general=True)
+        ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
+
+
 def test_batched_cqk_tuner(ctx):
     off, inst = W.cqk_batched(400, 16, 20000, 83)
     t = [_dev(inst[k]) for k in "dablu"]
