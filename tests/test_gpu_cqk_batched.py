@@ -353,16 +353,17 @@ def test_batched_cqk_degenerate_rows(ctx):
         check_cqk(x[off[s]:off[s + 1]], row_, ref, 1e-10)
 
 
-def test_batched_cqk_graph_capture_replays(ctx):
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_batched_cqk_graph_capture_replays(ctx, dtype):
     """Forward and backward captured in one HIP graph (no allocation, no host
     sync inside); every replay matches the eager results."""
     off, inst = W.cqk_batched(300, 10, 6000, 71)
-    t = [_dev(inst[k]) for k in "dablu"]
+    t = [_dev(inst[k], dtype) for k in "dablu"]
     offs = _dev(off, torch.int64)
     r = _dev(inst["r"])
     x = torch.empty_like(t[0])
     lam = torch.empty(300, dtype=torch.float64, device="cuda")
-    g = torch.from_numpy(np.random.default_rng(72).standard_normal(x.numel())).cuda()
+    g = torch.from_numpy(np.random.default_rng(72).standard_normal(x.numel())).to("cuda", dtype)
     ga = torch.empty_like(x)
     gr = torch.empty(300, dtype=torch.float64, device="cuda")
     # eager pass (sizes the workspace)
