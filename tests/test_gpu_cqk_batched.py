@@ -416,6 +416,32 @@ def test_batched_cqk_every_schedule(ctx, sp, bpc, sf):
         ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
 
 
+@pytest.mark.parametrize("sp,bpc,sf", SCHEDULES)
+def test_batched_cqk_every_schedule_fp32(ctx, sp, bpc, sf):
+    """The same on float32 arrays, to the FP32 bar; the VJP reads x rounded
+    to float32 on both sides."""
+    off, inst = W.cqk_batched(60, 1, 3000, 91)
+    inst = _round32(inst)
+    ctx.set_batch_schedule(sp, bpc, sf, general=True)
+    ctx.set_batch_schedule(sp, bpc, sf, backward=True, general=True)
+    try:
+        x, lam, sts, info = _run(ctx, off, inst, dtype=torch.float32)
+        assert info["status"] == 0
+        _check_rows(x, lam, sts, off, inst, tol=1e-5)
+        res = O.solve_cqk_batched(*[inst[k] for k in "dablu"], off, inst["r"])
+        xr = np.concatenate([q.x for q in res]).astype(np.float32).astype(np.float64)
+        g = np.random.default_rng(92).standard_normal(xr.size).astype(np.float32)
+        g = g.astype(np.float64)
+        ga, gr = _vjp(ctx, off, inst, xr, g, dtype=torch.float32)
+        ga_ref, gr_ref = O.cqk_vjp_batched(xr, g, inst["d"], inst["b"], inst["l"], inst["u"], off)
+        scale = max(1.0, float(np.max(np.abs(ga_ref))), float(np.max(np.abs(gr_ref))))
+        assert np.max(np.abs(ga - ga_ref)) <= 1e-5 * scale
+        assert np.max(np.abs(gr - gr_ref)) <= 1e-5 * scale
+    finally:
+        ctx.set_batch_schedule(8, 4, 0, general=True)
+        ctx.set_batch_schedule(8, 4, 0, backward=True, general=True)
+
+
 def test_batched_cqk_fp32_tuner(ctx):
     """The tuner on float32 arrays times the float32 kernels and sets the
     schedules the float32 calls then use."""
