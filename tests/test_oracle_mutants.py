@@ -70,6 +70,16 @@ def pin_golden(M):
         gy, gr = M.simplex_vjp(ex["x"], ex["g"])
         if np.max(np.abs(gy - _f(ex["grad_y"]))) > 1e-12 or abs(gr - ex["grad_r"]) > 1e-12:
             return False
+    for ex in g["alg1_traces"]:
+        st, lam, tr = M.newton_cqk(*[_f(ex[k]) for k in "dablu"], ex["r"], lam0=0.0)
+        if st != "OK" or [t["lam"] for t in tr] != ex["lams"] or lam != ex["lam"]:
+            return False
+        if [t.get("kind") for t in tr] != ex["kinds"]:
+            return False
+    for ex in g["alg4_traces"]:
+        lam, tr = M.newton_simplex(_f(ex["y"]), ex["r"], ex["lam0"])
+        if [t["lam"] for t in tr] != ex["lams"] or lam != ex["lam"]:
+            return False
     return True
 
 
@@ -297,6 +307,13 @@ MUTANTS = [
     ("lambdaJ sign", "return float((np.longdouble(r) - np.sum(y[J]",
      "return float((np.longdouble(r) + np.sum(y[J]"),
     ("alg4 slope", "step = (ph - r) / cm\n", "step = (ph - r) / (cm + 1)\n"),
+    ("alg1 farthest right breakpoint", "nxt = float(np.min(right))", "nxt = float(np.max(right))"),
+    ("alg1 farthest left breakpoint", "nxt = float(np.max(left))", "nxt = float(np.min(left))"),
+    ("alg1 right search over ubar", "right = lbar[lbar > lam]", "right = ubar[ubar > lam]"),
+    ("alg1 left search over lbar", "left = ubar[ubar < lam]", "left = lbar[lbar < lam]"),
+    ("alg1 secant through hi only", "nxt = lo - (phlo - r) * (hi - lo) / (phhi - phlo)",
+     "nxt = hi - (phhi - r) * (hi - lo) / (phhi - phlo) * 0.5"),
+    ("alg4 no safeguard", "lam = max(float(lam0), ylow)", "lam = float(lam0)"),
     ("alg1 newton sign", "cand = lam - step\n                nxt = cand if cand < hi", "cand = lam + step\n                nxt = cand if cand < hi"),
     ("vjp sign", "return np.where(S, g - gbar, 0.0), gbar", "return np.where(S, g + gbar, 0.0), gbar"),
     ("vjp mean", "gbar = _lsum(g[S]) / k", "gbar = _lsum(g[S]) / x.size"),

@@ -65,6 +65,29 @@ def test_golden_alg2_traces(golden):
         assert sorted(J) == ex["J"], ex["name"]
 
 
+def test_golden_alg1_iterates(golden):
+    """Algorithm 1's iterates on hand-traced instances: the breakpoint step
+    in both directions (closest lbar to the right, closest ubar to the left)
+    and the secant step.  The final x is the same for several wrong
+    breakpoint choices, so the iterates themselves are compared."""
+    for ex in golden["alg1_traces"]:
+        args = [_arr(ex[k]) for k in "dablu"]
+        st, lam, tr = O.newton_cqk(*args, ex["r"], lam0=0.0)
+        assert st == O.OK, ex["name"]
+        assert [t["lam"] for t in tr] == ex["lams"], ex["name"]
+        assert [t.get("kind") for t in tr] == ex["kinds"], ex["name"]
+        assert lam == ex["lam"], ex["name"]
+        np.testing.assert_array_equal(O.x_of_lambda(lam, *args), _arr(ex["x"]))
+
+
+def test_golden_alg4_safeguard(golden):
+    """Algorithm 4's first step raises a start below -max y to -max y."""
+    for ex in golden["alg4_traces"]:
+        lam, tr = O.newton_simplex(_arr(ex["y"]), ex["r"], ex["lam0"])
+        assert [t["lam"] for t in tr] == ex["lams"], ex["name"]
+        assert lam == ex["lam"], ex["name"]
+
+
 def test_golden_bruteforce_agrees(golden):
     for ex in golden["cqk"]:
         if ex.get("status"):
