@@ -27,10 +27,27 @@
  *   ABI.  Host-side argument errors return before anything is enqueued.
  * - With opts->sync != 0 (the default) the call waits for the result and
  *   fills *info.  Outputs are then final.
+ * - With opts->sync = 0, or while the context's stream is capturing a HIP
+ *   graph, a dense-output call only enqueues its work and returns CQK_OK
+ *   (info->status = CQK_OK, nothing else filled); its outcome stays in device
+ *   memory and cqk_ctx_last_info() waits for the stream and reads it.  The
+ *   single-instance calls (cqk_solve_*, cqk_project_*) then queue every pass
+ *   their iteration cap allows (2 max_iter + 4 general, max_iter + 2
+ *   simplex / l1; each returns at once after the loop has stopped, a few
+ *   microseconds), so keep opts->max_iter near what the problem needs.
+ *   Per-pass timing (opts->timing) is skipped then.  The sparse-output calls,
+ *   the SPG driver and the tuners always wait: under capture they return
+ *   CQK_INVALID_ARG without enqueuing anything, and the sparse calls also with
+ *   sync = 0.
+ * - No call allocates device memory while its stream is capturing: if the
+ *   workspace reserved before the capture (cqk_reserve) is too small, the call
+ *   returns CQK_NO_MEMORY without enqueuing anything.
  * - On any status other than CQK_OK and CQK_NOT_CONVERGED the contents of the
  *   output array are unspecified.  CQK_NOT_CONVERGED writes x(lam_last).
  * - The context owns a device workspace that grows on demand (hipMalloc) and
- *   is reused between calls; cqk_reserve() grows it ahead of time.
+ *   is reused between calls; cqk_reserve() grows it ahead of time (before a
+ *   graph capture: cqk_reserve(ctx, n, 0) for a single call of n indices,
+ *   cqk_reserve(ctx, 0, nseg) for a batched call of nseg rows).
  * - A context is not thread safe; use one context per host thread.
  */
 #ifndef CQK_H
@@ -117,7 +134,12 @@ typedef struct cqk_info {
 typedef struct cqk_trace_rec {
   int32_t iter;             /* Newton iteration the pass belongs to */
   int32_t kind;             /* 0 init, 1 evaluate phi, 2 breakpoint search,
-                               3 Newton step taken, 4 secant, 5 breakpoint step */
+                               3 Newton step taken, 4 secant step taken,
+                               5 breakpoint step, 6 bisection (the secant
+                               point rounded onto a bracket end), 7 one
+                               thread's Algorithm 2 (simplex / l1 start, see
+                               below).  For kinds 3, 4 and 6, lam is the next
+                               iterate, phi and slope those it was taken from. */
   int32_t compacted;        /* 1 if this pass wrote a compacted set */
   int32_t source;           /* 0 original arrays, 1/2 compacted buffers */
   double lam;               /* multiplier evaluated by the pass */
@@ -141,8 +163,31 @@ cqk_status cqk_set_stream(cqk_ctx* ctx, void* hip_stream);
 cqk_status cqk_reserve(cqk_ctx* ctx, int64_t max_n, int32_t max_seg);
 const char* cqk_status_string(int32_t status);
 void cqk_default_opts(cqk_opts* opts);
+/* Outcome of the last call on this context (Section 1: the problem's status,
+ * the infeasible exits of Algorithm 1): waits for the context's stream, then
+ * reads the device-side status words and fills *info as a call with
+ * opts->sync = 1 would have (batched calls: the worst row status, as their
+ * return value; the per-row flags are in the caller's status_out /
+ * lambda_out arrays).  After a replay of a captured graph it reports that
+ * replay, provided no other call ran on the context since the capture.
+ * Returns info->status, or CQK_INVALID_ARG when no call has run yet (or the
+ * last one failed its host-side checks, or was the SPG driver), or while the
+ * stream is capturing. */
+cqk_status cqk_ctx_last_info(cqk_ctx* ctx, cqk_info* info);
+
 /* Copy up to `cap` trace records of the last call into host memory `out`;
- * *count receives the number recorded. */
+ * *count receives the number recorded.
+ * A simplex / l1 call with the CONDAT start and opts->trace = 1 writes one
+ * kind-7 record first: lane 0 of the first wave ran Algorithm 2 (Section
+ * 2.2, the per-chunk form of Section 4) on the values of the tile at index 0
+ * it holds, value e (e = 0..15, ascending in y) being y[(e / V) * 64 * V +
+ * e % V] with V = 16 / sizeof(element).  Fields: n_in = mask of the values
+ * above the wave's filter (those Algorithm 2 scanned, in order of e), n_out =
+ * mask of its final set J, compacted = |J|, phi = sum of J (of |y| for l1),
+ * lam = (r - phi) / |J| (Algorithm 2's bound), slope = the filter threshold,
+ * lo = the wave's bound after merging and refining, source = mask of the
+ * values of J kept as survivors (v + min(lam, lo) > 0; every other value of
+ * the tile is fixed at zero), hi = 0 (the tile's index). */
 cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count);
 
 /* General CQK (Section 1 eq. (CQK), Algorithm 1).

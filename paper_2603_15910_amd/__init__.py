@@ -83,6 +83,14 @@ def cqk_last_trace(ctx: int, cap: int = 512):
     return [buf[i].as_dict() for i in range(min(cap, cnt.value))]
 
 
+def cqk_ctx_last_info(ctx: int):
+    """(status, info dict) of the last call on the context, read from the
+    device after waiting for its stream."""
+    info = cqk_info()
+    st = lib().cqk_ctx_last_info(C.c_void_p(ctx), C.byref(info))
+    return st, info.as_dict()
+
+
 def _call(name, *args):
     return getattr(lib(), name)(*args)
 
@@ -333,6 +341,13 @@ class Context:
 
     def trace(self):
         return cqk_last_trace(self.handle)
+
+    def ctx_last_info(self):
+        """(status, info) of the last call, read from the device: the outcome
+        of a call made with sync=False or replayed from a captured graph.
+        Waits for torch's current stream (where a replay was launched)."""
+        self._bind_stream()
+        return cqk_ctx_last_info(self.handle)
 
     def solve(self, d, a, b, l, u, r, out=None, check=True, xbar=None, **kw):
         """General CQK.  xbar: a primal estimate (same dtype and size) for
@@ -710,8 +725,9 @@ def _autograd_cls():
 
         forward(y, offsets, r): y float32 [N], offsets int64 [nseg+1] (GPU),
         r a float or a float64 GPU tensor [nseg].  backward returns
-        (grad_y, None, grad_r) with grad_r per row, summed when r was a
-        Python number."""
+        (grad_y, None, grad_r): grad_r per row when r is a tensor, None when
+        r is a Python number (not a graph input, so autograd takes no
+        gradient for it)."""
 
         @staticmethod
         def forward(ctx, y, offsets, r):

@@ -147,6 +147,7 @@ SIGNATURES = {
     "cqk_status_string": (C.c_char_p, [_I32]),
     "cqk_default_opts": (None, [_OPTS]),
     "cqk_last_trace": (C.c_int, [_P, C.POINTER(cqk_trace_rec), _I32, C.POINTER(_I32)]),
+    "cqk_ctx_last_info": (C.c_int, [_P, _INFO]),
     "cqk_solve_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_f32": (C.c_int, [_P, _I64, _P, _D, _P, _OPTS, _INFO]),

@@ -217,11 +217,19 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     st->mode = (res < 0.0) ? kModeBreakRight : kModeBreakLeft;
     return;
   }
+  int kind = 3;  // the Newton step
   if (secant) {
     next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
-    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    kind = 4;
+    // rounding can put the secant point on an end of a bracket a few ulps
+    // wide: bisect then
+    if (!(next > lo && next < hi)) {
+      next = 0.5 * (lo + hi);
+      kind = 6;
+    }
   }
   if (next == lam) return finish(st, lam, 2);  // criterion 2, lam_{k-1} = lam_k
+  trace_push(st, tr, kind, 0, source, next, phi, slope, 0, 0);
   advance(st, next);
 }
 
@@ -261,11 +269,17 @@ __device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks
   const double step = res / sw;
   double next = bp - step;
   if (fabs(step) < tol) return finish(st, fmin(fmax(next, lo), hi), 2);
+  int kind = 3;
   if (!(next > lo && next < hi)) {
     next = lo - (st->phi_lo - r) * (hi - lo) / (st->phi_hi - st->phi_lo);
-    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    kind = 4;
+    if (!(next > lo && next < hi)) {
+      next = 0.5 * (lo + hi);
+      kind = 6;
+    }
   }
   if (next == bp) return finish(st, bp, 2);
+  trace_push(st, tr, kind, 0, st->src, next, phi, sw, 0, 0);
   advance(st, next);
 }
 

@@ -15,8 +15,25 @@ namespace cqk {
 
 cqk_status hip_ok(hipError_t e) { return e == hipSuccess ? CQK_OK : CQK_DEVICE_ERROR; }
 
-cqk_status ensure_buffer(DeviceBuf& b, size_t bytes) {
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipError_t e = hipStreamIsCapturing(s, &cs);
+  if (e == hipErrorStreamCaptureImplicit) {
+    // the legacy null stream while another stream captures
+    (void)hipGetLastError();
+    return true;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return cs != hipStreamCaptureStatusNone;
+}
+
+cqk_status ensure_buffer(cqk_ctx* ctx, DeviceBuf& b, size_t bytes) {
   if (bytes <= b.bytes && b.ptr) return CQK_OK;
+  // no allocation (or free) while a graph is being captured
+  if (stream_capturing(ctx->stream)) return CQK_NO_MEMORY;
   if (b.ptr) {
     if (hipFree(b.ptr) != hipSuccess) return CQK_DEVICE_ERROR;
     b.ptr = nullptr;
@@ -104,6 +121,18 @@ void info_trivial(cqk_info* info, int status, double lam) {
   info->stop_reason = 5;
 }
 
+// A call answered on the host (empty input): its info is also what
+// cqk_ctx_last_info reports for it.
+void last_trivial(cqk_ctx* ctx, cqk_info* info, int status, double lam) {
+  cqk_info t;
+  info_trivial(&t, status, lam);
+  if (info) *info = t;
+  ctx->last = [t](cqk_info* out) {
+    *out = t;
+    return CQK_OK;
+  };
+}
+
 template <typename T>
 cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T* b, const T* l,
                         const T* u, const T* xw, bool warm, double r, T* x, const cqk_opts* opts,
@@ -114,12 +143,13 @@ cqk_status solve_common(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T
   if (st != CQK_OK) return st;
   if (n == 0) {
     const int s = (r == 0.0) ? CQK_OK : CQK_INFEASIBLE;
-    info_trivial(info, s, 0.0);
+    last_trivial(ctx, info, s, 0.0);
     return (cqk_status)s;
   }
   if (!d || !a || !b || !l || !u || !x) return CQK_INVALID_ARG;
   if (warm && (!xw || overlaps(xw, (const T*)x, n))) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
@@ -140,13 +170,15 @@ cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xw, bool
   if (st != CQK_OK) return st;
   if (n == 0) {
     const int s = (r == 0.0 || l1) ? CQK_OK : CQK_INFEASIBLE;
-    info_trivial(info, s, 0.0);
+    last_trivial(ctx, info, s, 0.0);
     if (sp) sp->nnz = 0;
     return (cqk_status)s;
   }
   if (!y || (!x && !sp)) return CQK_INVALID_ARG;
   if (warm && (!xw || (x && overlaps(xw, (const T*)x, n)))) return CQK_INVALID_ARG;
   if (sp) {
+    // the support's size is decided on the host: sparse calls always wait
+    if (!o.sync || stream_capturing(ctx->stream)) return CQK_INVALID_ARG;
     if (sp->cap < 0 || (sp->cap > 0 && (!sp->idx || !sp->val))) return CQK_INVALID_ARG;
     const size_t yb = (size_t)n * sizeof(T), ib = (size_t)sp->cap * 8, vb = (size_t)sp->cap * sizeof(T);
     if (overlaps_bytes(sp->idx, ib, y, yb) || overlaps_bytes(sp->val, vb, y, yb) ||
@@ -154,6 +186,7 @@ cqk_status simplex_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xw, bool
       return CQK_INVALID_ARG;
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
@@ -230,9 +263,9 @@ cqk_status cqk_reserve(cqk_ctx* ctx, int64_t max_n, int32_t max_seg) {
   const size_t gen = std::max(gen_layout(max_n, ctx->num_cus, 2, true).bytes,
                               gen_layout(max_n, ctx->num_cus, 4, true).bytes);
   const size_t want = std::max(gen, (size_t)max_n * 64) + (size_t)max_seg * 64 + (4u << 20);
-  cqk_status st = ensure_buffer(ctx->ws, want);
+  cqk_status st = ensure_buffer(ctx, ctx->ws, want);
   if (st != CQK_OK) return st;
-  return ensure_buffer(ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
+  return ensure_buffer(ctx, ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
 }
 
 const char* cqk_status_string(int32_t s) {
@@ -250,6 +283,18 @@ const char* cqk_status_string(int32_t s) {
 
 void cqk_default_opts(cqk_opts* opts) {
   if (opts) fill_default_opts(opts);
+}
+
+cqk_status cqk_ctx_last_info(cqk_ctx* ctx, cqk_info* info) {
+  if (!ctx || !info) return CQK_INVALID_ARG;
+  if (!ctx->last) return CQK_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  // waiting is not possible while the stream captures a graph
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;
+  if (hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
+  const cqk_status st = ctx->last(info);
+  if (st != CQK_OK) return st;
+  return (cqk_status)info->status;
 }
 
 cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count) {
@@ -371,11 +416,12 @@ cqk_status batched_cqk_common(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets
   cqk_status st = check_opts(opts, &o, false);
   if (st != CQK_OK) return st;
   if (nseg == 0) {
-    info_trivial(info, CQK_OK, 0.0);
+    last_trivial(ctx, info, CQK_OK, 0.0);
     return CQK_OK;
   }
   if (!offsets || !d || !a || !b || !l || !u || !r || !x) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   if constexpr (sizeof(T) == 8)
@@ -397,9 +443,13 @@ cqk_status batched_cqk_backward_common(cqk_ctx* ctx, int32_t nseg, const int64_t
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, false);
   if (st != CQK_OK) return st;
-  if (nseg == 0) return CQK_OK;
+  if (nseg == 0) {
+    ctx->last = ok_info;
+    return CQK_OK;
+  }
   if (!offsets || !x || !g || !d || !b || !l || !u || !grad_a) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   if constexpr (sizeof(T) == 8)
     return run_batched_cqk_backward_f64(ctx, nseg, offsets, x, g, d, b, l, u, grad_a, grad_r, o);
   else
@@ -462,9 +512,12 @@ cqk_status cqk_spg_l1_lasso_f64(cqk_ctx* ctx, int64_t m, int64_t n, const double
       overlaps_bytes(x, (size_t)n * 8, b, (size_t)m * 8))
     return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // SPG is driven by the host
   cqk_spg_info tmp;
   cqk_spg_info* inf = info ? info : &tmp;
   const cqk_status st = run_spg_l1_lasso_f64(ctx, m, n, A, b, radius, x, o, inf);
+  ctx->last = nullptr;  // the SPG result is in *info only
   if (st != CQK_OK) return st;
   return (cqk_status)inf->status;
 }
@@ -479,11 +532,12 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
   cqk_status st = check_opts(opts, &o, true);
   if (st != CQK_OK) return st;
   if (nseg == 0) {
-    info_trivial(info, CQK_OK, 0.0);
+    last_trivial(ctx, info, CQK_OK, 0.0);
     return CQK_OK;
   }
   if (!offsets || !y || !x) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   st = run_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, o, inf);
@@ -499,9 +553,13 @@ cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, true);
   if (st != CQK_OK) return st;
-  if (nseg == 0) return CQK_OK;
+  if (nseg == 0) {
+    ctx->last = ok_info;
+    return CQK_OK;
+  }
   if (!offsets || !x || !g || !grad_y) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
   return run_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, grad_r, o);
 }
 
@@ -545,6 +603,8 @@ cqk_status cqk_tune_batched_cqk_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* o
   if (!offsets || !d || !b || !l || !u || !x) return CQK_INVALID_ARG;
   if (backward ? (!g || !grad_a) : (!a || !r)) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
   return tune_batched_cqk_f64(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
                               repeats, best, best_ms);
 }
@@ -560,6 +620,8 @@ cqk_status cqk_tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* o
   if (!offsets || !d || !b || !l || !u || !x) return CQK_INVALID_ARG;
   if (backward ? (!g || !grad_a) : (!a || !r)) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
   return tune_batched_cqk_f32(ctx, nseg, offsets, d, a, b, l, u, r, x, g, grad_a, backward,
                               repeats, best, best_ms);
 }
@@ -571,6 +633,8 @@ cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
   if (!offsets || !y || !x) return CQK_INVALID_ARG;
   if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
   return tune_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, repeats, best, best_ms);
 }
 
@@ -581,6 +645,8 @@ cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64
   if (!ctx || nseg <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
   if (!offsets || !x || !g || !grad_y) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  ctx->last = nullptr;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
   return tune_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, repeats, best, best_ms);
 }
 

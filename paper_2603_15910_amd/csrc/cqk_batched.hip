@@ -1404,7 +1404,7 @@ cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
   const size_t nblk = std::max<size_t>(1, ((size_t)nseg + kPBlock - 1) / kPBlock);
   const size_t hist_bytes = (nblk * kNB * sizeof(int32_t) + 255) / 256 * 256;
   const size_t lrow_bytes = ((size_t)nseg * 2 * sizeof(int64_t) + 255) / 256 * 256;
-  cqk_status st = ensure_buffer(ctx->ws, list_bytes + ctr_bytes + hist_bytes + lrow_bytes);
+  cqk_status st = ensure_buffer(ctx, ctx->ws, list_bytes + ctr_bytes + hist_bytes + lrow_bytes);
   if (st != CQK_OK) return st;
   char* p = (char*)ctx->ws.ptr;
   w->list = (int32_t*)p;
@@ -1608,31 +1608,39 @@ cqk_status run_batched_cqk(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, c
   launch_cqk_forward<TIn>(ctx, ctx->sched_cqk_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  if (info) std::memset(info, 0, sizeof(*info));
-  if (!o.sync) {
-    if (info) info->status = CQK_OK;
-    return CQK_OK;
-  }
+  // the call's result from the device counters (host copy in hc)
   int32_t* hc = (int32_t*)ctx->host_pinned;
+  const bool timing = o.timing != 0;
+  auto fill = [ctx, hc, timing](cqk_info* inf) {
+    const int flags = hc[CTR_FLAGS];
+    int status = CQK_OK;
+    if (flags & kBadValue) status = CQK_INVALID_ARG;
+    else if (flags & kInfeasible) status = CQK_INFEASIBLE;
+    else if (flags & kNotConverged) status = CQK_NOT_CONVERGED;
+    std::memset(inf, 0, sizeof(*inf));
+    inf->status = status;
+    inf->iterations = hc[CTR_ITMAX];
+    inf->passes = hc[CTR_ITSUM];
+    if (timing) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
+      inf->pass_ms = ms;
+    }
+  };
+  int32_t* dc = A.counters;
+  ctx->last = [hc, dc, fill](cqk_info* inf) -> cqk_status {
+    if (hip_ok(hipMemcpy(hc, dc, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    fill(inf);
+    return CQK_OK;
+  };
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!o.sync) return CQK_OK;
   if (hip_ok(hipMemcpyAsync(hc, A.counters, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost,
                             s)) != CQK_OK)
     return CQK_DEVICE_ERROR;
   if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
-  const int flags = hc[CTR_FLAGS];
-  int status = CQK_OK;
-  if (flags & kBadValue) status = CQK_INVALID_ARG;
-  else if (flags & kInfeasible) status = CQK_INFEASIBLE;
-  else if (flags & kNotConverged) status = CQK_NOT_CONVERGED;
-  if (info) {
-    info->status = status;
-    info->iterations = hc[CTR_ITMAX];
-    info->passes = hc[CTR_ITSUM];
-    if (o.timing) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
-      info->pass_ms = ms;
-    }
-  }
+  if (info) fill(info);
   return CQK_OK;
 }
 
@@ -1651,6 +1659,7 @@ cqk_status run_batched_cqk_backward(cqk_ctx* ctx, int32_t nseg, const int64_t* o
   A.gr = grad_r;
   launch_cqk_backward<TIn>(ctx, ctx->sched_cqk_bwd, A);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  ctx->last = ok_info;
   if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
   return CQK_OK;
 }
@@ -1768,32 +1777,40 @@ cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, c
   launch_forward(ctx, ctx->sched_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  if (info) std::memset(info, 0, sizeof(*info));
-  if (!o.sync) {
-    if (info) info->status = CQK_OK;
-    return CQK_OK;
-  }
+  // the call's result from the device counters (host copy in hc)
   int32_t* hc = (int32_t*)ctx->host_pinned;
+  const bool timing = o.timing != 0;
+  auto fill = [ctx, hc, timing](cqk_info* inf) {
+    const int flags = hc[CTR_FLAGS];
+    int status = CQK_OK;
+    if (flags & (kBadRadius | kBadValue)) status = CQK_INVALID_ARG;
+    else if (flags & kInfeasible) status = CQK_INFEASIBLE;
+    std::memset(inf, 0, sizeof(*inf));
+    inf->status = status;
+    inf->n_after_init = hc[CTR_SURV];
+    inf->iterations = 0;
+    inf->passes = 1;
+    inf->rows_spilled = hc[CTR_OVER];
+    if (timing) {
+      float ms = 0.f;
+      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
+      inf->pass_ms = ms;
+    }
+  };
+  int32_t* dc = A.counters;
+  ctx->last = [hc, dc, fill](cqk_info* inf) -> cqk_status {
+    if (hip_ok(hipMemcpy(hc, dc, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    fill(inf);
+    return CQK_OK;
+  };
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (!o.sync) return CQK_OK;
   if (hip_ok(hipMemcpyAsync(hc, A.counters, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost,
                             s)) != CQK_OK)
     return CQK_DEVICE_ERROR;
   if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
-  const int flags = hc[CTR_FLAGS];
-  int status = CQK_OK;
-  if (flags & (kBadRadius | kBadValue)) status = CQK_INVALID_ARG;
-  else if (flags & kInfeasible) status = CQK_INFEASIBLE;
-  if (info) {
-    info->status = status;
-    info->n_after_init = hc[CTR_SURV];
-    info->iterations = 0;
-    info->passes = 1;
-    info->rows_spilled = hc[CTR_OVER];
-    if (o.timing) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
-      info->pass_ms = ms;
-    }
-  }
+  if (info) fill(info);
   return CQK_OK;
 }
 
@@ -1805,6 +1822,7 @@ cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* o
   if (st != CQK_OK) return st;
   launch_backward(ctx, ctx->sched_bwd, backward_args(nseg, offsets, x, g, grad_y, grad_r, w));
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+  ctx->last = ok_info;
   if (o.sync && hip_ok(hipStreamSynchronize(ctx->stream)) != CQK_OK) return CQK_DEVICE_ERROR;
   return CQK_OK;
 }

@@ -699,10 +699,10 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   const int64_t chunk = Lg.chunk;
   const bool compaction = o.compaction != CQK_COMPACT_OFF;
   const size_t part_bytes = Lg.part_bytes, cnt_bytes = Lg.cnt_bytes;
-  cqk_status stt = ensure_buffer(ctx->ws, Lg.bytes);
+  cqk_status stt = ensure_buffer(ctx, ctx->ws, Lg.bytes);
   if (stt != CQK_OK) return stt;
   const size_t st_bytes = 1024 + sizeof(cqk_trace_rec) * kMaxTrace;
-  stt = ensure_buffer(ctx->state, st_bytes);
+  stt = ensure_buffer(ctx, ctx->state, st_bytes);
   if (stt != CQK_OK) return stt;
 
   char* ws = (char*)ctx->ws.ptr;
@@ -750,28 +750,35 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.lam_final = __builtin_nan("");
 
   hipStream_t s = ctx->stream;
+  // sync = 0 or graph capture: every pass the iteration cap allows is queued
+  // at once (those after the loop stops return at once) and nothing is read
+  // back; cqk_ctx_last_info reads the result later.  No per-pass timing then.
+  const bool deferred = !o.sync || stream_capturing(s);
+  const bool timing = o.timing && !deferred;
   // events 0, 1: the finalize of the last batch; then one pair per grid pass
   const size_t nev = (size_t)2 + 2 * (o.max_iter * 2 + 8);
-  if (o.timing) {
+  if (timing) {
     stt = ensure_events(ctx, nev);
     if (stt != CQK_OK) return stt;
   }
   hipLaunchKernelGGL(gen_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   int ev = 2;
+  int npass = 0;  // grid passes queued
   // a grid pass (timed when asked) followed by its one-block reduction
   auto launch = [&](auto kern, auto reduce) {
-    const bool rec = o.timing && ev + 2 <= (int)nev;
+    const bool rec = timing && ev + 2 <= (int)nev;
     launch_timed(kern, dim3(G), dim3(kBlock), s, rec ? ctx->events[ev] : nullptr,
                  rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
+    ++npass;
     hipLaunchKernelGGL(reduce, dim3(1), dim3(kRBlock), 0, s, A, G);
   };
   // The primal recovery does nothing while the loop still runs, so it is
   // queued behind every batch and the host waits once per batch.
   auto finalize = [&]() {
     launch_timed(gen_finalize_kernel<TIn>, dim3(GF), dim3(kBlock), s,
-                 o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
+                 timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, GF);
   };
   if (xw != nullptr)
@@ -782,64 +789,82 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;
-  // Algorithm 1 typically stops after five to seven evaluations here
-  int batch = 6;
-  while (launched < max_launch) {
-    const int k = std::min(batch, max_launch - launched);
-    for (int i = 0; i < k; ++i) launch(gen_pass_kernel<TIn>, gen_update_kernel);
-    launched += k;
+  if (deferred) {
+    for (; launched < max_launch; ++launched) launch(gen_pass_kernel<TIn>, gen_update_kernel);
     finalize();
     if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-    if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
-      return CQK_DEVICE_ERROR;
-    if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
-    if (hs->status != kRunning) break;
-    batch = 4;
+  } else {
+    // Algorithm 1 typically stops after five to seven evaluations here
+    int batch = 6;
+    while (launched < max_launch) {
+      const int k = std::min(batch, max_launch - launched);
+      for (int i = 0; i < k; ++i) launch(gen_pass_kernel<TIn>, gen_update_kernel);
+      launched += k;
+      finalize();
+      if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+      if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)
+        return CQK_DEVICE_ERROR;
+      if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
+      if (hs->status != kRunning) break;
+      batch = 4;
+    }
   }
   const int pass_events = ev;
-  int ntrace = std::min(hs->ntrace, init.trace_cap);
-  ctx->last_trace.resize(ntrace);
-  ctx->last_trace_count = hs->ntrace;
-  if (ntrace > 0) {
-    if (hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace, sizeof(cqk_trace_rec) * ntrace,
-                         hipMemcpyDeviceToHost)) != CQK_OK)
-      return CQK_DEVICE_ERROR;
-  }
-  if (hs->status == kRunning) {
-    hs->status = CQK_NOT_CONVERGED;
-  }
-  if (info) {
-    std::memset(info, 0, sizeof(*info));
-    info->status = hs->status;
-    info->iterations = hs->iter;
-    info->passes = hs->passes;
-    info->stop_reason = hs->stop_reason;
-    info->lambda = hs->lam_final;
-    info->lambda0 = hs->lam0;
-    info->residual = std::fabs(hs->res_P - r);
-    info->abs_bx = hs->res_A;
-    info->n_free = hs->n_free;
-    info->n_after_init = 0;
-    info->pass_bytes = 0.0;
-    info->pass_ms = 0.0;
-    info->finalize_bytes = (double)n * (6.0 * sizeof(TIn));
-    info->finalize_ms = 0.0;
-    info->pass_launches = (pass_events - 2) / 2;
-    if (o.timing) {
+  const int trace_cap = init.trace_cap;
+  // Fills an info record from the state copy in hs (the stream synchronised),
+  // reading the trace ring too.
+  auto report = [ctx, hs, A, trace_cap, n, r, timing, pass_events, npass](cqk_info* inf) -> cqk_status {
+    const int ntrace = std::min(hs->ntrace, trace_cap);
+    ctx->last_trace.resize(ntrace);
+    ctx->last_trace_count = hs->ntrace;
+    if (ntrace > 0) {
+      if (hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace, sizeof(cqk_trace_rec) * ntrace,
+                           hipMemcpyDeviceToHost)) != CQK_OK)
+        return CQK_DEVICE_ERROR;
+    }
+    std::memset(inf, 0, sizeof(*inf));
+    inf->status = (hs->status == kRunning) ? CQK_NOT_CONVERGED : hs->status;
+    inf->iterations = hs->iter;
+    inf->passes = hs->passes;
+    inf->stop_reason = hs->stop_reason;
+    inf->lambda = hs->lam_final;
+    inf->lambda0 = hs->lam0;
+    inf->residual = std::fabs(hs->res_P - r);
+    inf->abs_bx = hs->res_A;
+    inf->n_free = hs->n_free;
+    inf->n_after_init = 0;
+    inf->finalize_bytes = (double)n * (6.0 * sizeof(TIn));
+    inf->pass_launches = npass;
+    if (timing) {
       // every grid pass queued; those after the loop stopped returned at once
       for (int i = 2; i + 1 < pass_events; i += 2) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
-        info->pass_ms += ms;
+        inf->pass_ms += ms;
       }
       float ms = 0.f;
       hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
-      info->finalize_ms = ms;
+      inf->finalize_ms = ms;
     }
     // algorithmic bytes of the grid passes, summed on the device
-    info->pass_bytes = hs->bytes;
+    inf->pass_bytes = hs->bytes;
+    return CQK_OK;
+  };
+  ctx->last = [hs, A, report](cqk_info* inf) -> cqk_status {
+    if (hip_ok(hipMemcpy(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    return report(inf);
+  };
+  if (deferred) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = CQK_OK;
+      info->pass_launches = npass;
+    }
+    return CQK_OK;
   }
-  return CQK_OK;
+  cqk_info tmp;
+  return report(info ? info : &tmp);
 }
 
 }  // namespace

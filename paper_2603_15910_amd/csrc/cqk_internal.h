@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 #include "../../include/cqk.h"
@@ -104,12 +105,27 @@ struct cqk_ctx {
   cqk_batch_schedule sched_bwd{8, 4, 0, 0};
   cqk_batch_schedule sched_cqk_fwd{8, 4, 0, 0};  // batched general CQK forward / backward
   cqk_batch_schedule sched_cqk_bwd{8, 4, 0, 0};
+  // Reads the device-side result of the last call into an info record (the
+  // stream already synchronised); set by every call that got past its host
+  // checks, so cqk_ctx_last_info can report a call queued with sync = 0 or
+  // replayed from a captured graph.
+  std::function<cqk_status(cqk_info*)> last;
 };
 
 namespace cqk {
 
-cqk_status ensure_buffer(DeviceBuf& b, size_t bytes);
+// Grows b to at least `bytes`.  While ctx's stream is capturing a graph it
+// allocates nothing: a buffer too small then gives CQK_NO_MEMORY.
+cqk_status ensure_buffer(cqk_ctx* ctx, DeviceBuf& b, size_t bytes);
+// true while stream s is capturing a graph
+bool stream_capturing(hipStream_t s);
 cqk_status hip_ok(hipError_t e);
+// the device-side result of a call that always ends OK (the backward calls)
+inline cqk_status ok_info(cqk_info* inf) {
+  *inf = cqk_info{};
+  inf->status = CQK_OK;
+  return CQK_OK;
+}
 cqk_status ensure_events(cqk_ctx* ctx, size_t count);
 void fill_default_opts(cqk_opts* o);
 

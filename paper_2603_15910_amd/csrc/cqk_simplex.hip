@@ -333,6 +333,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   TIn vmxI = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
+  bool traced = false;  // this wave has run Algorithm 2 on a tile
   const uint32_t amask = l1 ? 0x7FFFFFFFu : 0xFFFFFFFFu;
   // One tile; `full` (a tile wholly in range) is known at compile time, so
   // the in-range tests of the other tiles cost nothing here.
@@ -471,6 +472,25 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         lam_b = nl;
       }
       select(lam_b);
+      // with tracing on, lane 0 of wave 0 records its own Algorithm 2 on the
+      // wave's first tile (the tile at index 0): the values it saw, J, the
+      // thread's bound and the values the wave's refined bound kept
+      if (rid == 0 && lane == 0 && !traced && st->trace_cap > 0) {
+        cqk_trace_rec& t = A.trace[0];
+        t.iter = 0;
+        t.kind = 7;
+        t.compacted = c;
+        t.source = (int32_t)keep;
+        t.lam = lam_t;
+        t.phi = (double)S;
+        t.slope = (double)thr;
+        t.lo = lam_b;
+        t.hi = (double)base;
+        t.n_in = (int64_t)active;
+        t.n_out = (int64_t)J;
+        st->ntrace = 1;
+      }
+      traced = true;
       lam_min = fmin(lam_min, lam_b);
     }
     if (__ballot(keep != 0u) == 0) return;
@@ -1609,12 +1629,12 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   const size_t sc_bytes = sparse ? ((size_t)GS * sizeof(int32_t) + 255) / 256 * 256 : 0;
   const size_t total = part_bytes + cnt_bytes + ti_bytes + tv_bytes + to_bytes + sc_bytes +
                        (need_bufs ? 2 * (val_bytes + idx_bytes) : 0);
-  cqk_status stt = ensure_buffer(ctx->ws, total);
+  cqk_status stt = ensure_buffer(ctx, ctx->ws, total);
   if (stt != CQK_OK) return stt;
   if (sparse) {
     const size_t bm_bytes = ((size_t)nwords * sizeof(uint32_t) + 255) / 256 * 256;
     const bool grows = ctx->bitmap.bytes < bm_bytes;
-    stt = ensure_buffer(ctx->bitmap, bm_bytes);
+    stt = ensure_buffer(ctx, ctx->bitmap, bm_bytes);
     if (stt != CQK_OK) return stt;
     if (grows) ctx->bitmap_clean = false;
     // all zero from here, the whole allocation (a later, longer call reads
@@ -1624,7 +1644,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
       return CQK_DEVICE_ERROR;
     ctx->bitmap_clean = false;  // until this call has run to its end
   }
-  stt = ensure_buffer(ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
+  stt = ensure_buffer(ctx, ctx->state, 1024 + sizeof(cqk_trace_rec) * kMaxTrace);
   if (stt != CQK_OK) return stt;
 
   char* ws = (char*)ctx->ws.ptr;
@@ -1692,20 +1712,27 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   }
 
   hipStream_t s = ctx->stream;
+  // sync = 0 or graph capture (dense output only): every pass the iteration
+  // cap allows is queued at once, nothing is read back; cqk_ctx_last_info
+  // reads the result later.  No per-pass timing then.
+  const bool deferred = !sparse && (!o.sync || stream_capturing(s));
+  const bool timing = o.timing && !deferred;
   // events 0..3: the finalize and scatter of the last finalize chain;
   // then one pair per grid pass
   const size_t nev = (size_t)4 + 2 * (o.max_iter + 8);
-  if (o.timing) {
+  if (timing) {
     stt = ensure_events(ctx, nev);
     if (stt != CQK_OK) return stt;
   }
   hipLaunchKernelGGL(spx_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
   int ev = 4;
+  int npass = 0;  // grid passes queued
   auto launch = [&](auto kern, int grid) {
-    const bool rec = o.timing && ev + 2 <= (int)nev;
+    const bool rec = timing && ev + 2 <= (int)nev;
     launch_timed(kern, dim3(grid), dim3(kBlock), s, rec ? ctx->events[ev] : nullptr,
                  rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
+    ++npass;
   };
   // one-block reduction of the partial records of a grid of `grid` blocks
   auto reduce = [&](auto kern, int grid) {
@@ -1719,18 +1746,18 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   auto fin_chain = [&]() {
     if (sparse) {
       launch_timed(spx_sp_mark_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
-                   o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
+                   timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
       hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
       hipLaunchKernelGGL(spx_sp_count_kernel, dim3(GS), dim3(kBlock), 0, s, A);
       launch_timed(spx_sp_write_kernel<TIn, TA>, dim3(GS), dim3(kBlock), s,
-                   o.timing ? ctx->events[2] : nullptr, o.timing ? ctx->events[3] : nullptr, A,
+                   timing ? ctx->events[2] : nullptr, timing ? ctx->events[3] : nullptr, A,
                    GS);
       return;
     }
     launch_timed(spx_finalize_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
-                 o.timing ? ctx->events[0] : nullptr, o.timing ? ctx->events[1] : nullptr, A);
+                 timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
     launch_timed(spx_scatter_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
-                 o.timing ? ctx->events[2] : nullptr, o.timing ? ctx->events[3] : nullptr, A);
+                 timing ? ctx->events[2] : nullptr, timing ? ctx->events[3] : nullptr, A);
     hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
   };
   SpxState* hs = (SpxState*)ctx->host_pinned;
@@ -1742,7 +1769,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   };
   if (r == 0.0) {
     fin_chain();
-    if (wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
+    if (!deferred && wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
   } else {
     if (condat) {
       if (warm)
@@ -1765,7 +1792,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     // after the refined start of Algorithm 2 at most one more pass usually
     // leaves a set small enough for the one-block loop, which then takes a
     // pass (the pack) and an update (the loop)
-    int batch = 2;
+    int batch = deferred ? max_launch : 2;
     for (;;) {
       const int k = std::min(batch, max_launch - launched);
       for (int i = 0; i < k; ++i) {
@@ -1774,22 +1801,29 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
       }
       launched += k;
       fin_chain();
+      if (deferred) {
+        if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
+        break;
+      }
       if (wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
       if (hs->status != kRunning || launched >= max_launch) break;
       batch = 4;
     }
   }
   const int pass_events = ev;
-  const int ntrace = std::min(hs->ntrace, init.trace_cap);
-  ctx->last_trace.resize(ntrace);
-  if (ntrace > 0 && hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace,
-                                     sizeof(cqk_trace_rec) * ntrace,
-                                     hipMemcpyDeviceToHost)) != CQK_OK)
-    return CQK_DEVICE_ERROR;
-  if (hs->status == kRunning) hs->status = CQK_NOT_CONVERGED;
-  if (info) {
+  const int trace_cap = init.trace_cap;
+  // Fills an info record from the state copy in hs (the stream synchronised),
+  // reading the trace ring too.
+  auto report = [ctx, hs, A, trace_cap, n, r, l1, sparse, warm, timing, pass_events, nwords,
+                 npass](cqk_info* info) -> cqk_status {
+    const int ntrace = std::min(hs->ntrace, trace_cap);
+    ctx->last_trace.resize(ntrace);
+    if (ntrace > 0 && hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace,
+                                       sizeof(cqk_trace_rec) * ntrace,
+                                       hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
     std::memset(info, 0, sizeof(*info));
-    info->status = hs->status;
+    info->status = (hs->status == kRunning) ? CQK_NOT_CONVERGED : hs->status;
     info->iterations = hs->iter;
     info->passes = hs->passes;
     info->stop_reason = hs->stop_reason;
@@ -1802,7 +1836,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     info->n_after_init = hs->n_init;
     info->pass_bytes = 0.0;
     info->pass_ms = 0.0;
-    info->pass_launches = (pass_events - 4) / 2;
+    info->pass_launches = npass;
     info->finalize_ms = 0.0;
     info->rows_spilled = 0;
     const bool scatter = hs->fin_mode == kFinDense && hs->src != 0;
@@ -1826,6 +1860,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     info->finalize_bytes = fin;
     for (int i = 0; i < ntrace; ++i) {
       const cqk_trace_rec& t = ctx->last_trace[i];
+      if (t.kind == 7) continue;  // one thread's Algorithm 2, not a pass
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
       const double per_out = (double)sizeof(TIn) + 4.0;
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
@@ -1834,7 +1869,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
       if (t.kind == 0 && t.source == 0 && t.compacted)
         info->pass_bytes += sizeof(TIn) * (double)t.n_in * ((sparse ? 0.0 : 1.0) + (warm ? 1.0 : 0.0));
     }
-    if (o.timing) {
+    if (timing) {
       // every grid pass launched (those after the loop stopped return at
       // once); the tail loop runs in one block between them and is not here
       for (int i = 4; i + 1 < pass_events; i += 2) {
@@ -1848,14 +1883,30 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
         info->finalize_ms += ms;
       }
     }
+    if (sparse && hs->sp_over && (info->status == CQK_OK || info->status == CQK_NOT_CONVERGED))
+      info->status = CQK_BUFFER_TOO_SMALL;
+    return CQK_OK;
+  };
+  ctx->last = [hs, A, report](cqk_info* inf) -> cqk_status {
+    if (hip_ok(hipMemcpy(hs, A.st, sizeof(SpxState), hipMemcpyDeviceToHost)) != CQK_OK)
+      return CQK_DEVICE_ERROR;
+    return report(inf);
+  };
+  if (deferred) {
+    if (info) {
+      std::memset(info, 0, sizeof(*info));
+      info->status = CQK_OK;
+      info->pass_launches = npass;
+    }
+    return CQK_OK;
   }
+  cqk_info tmp;
+  const cqk_status rs = report(info ? info : &tmp);
   if (sparse) {
     ctx->bitmap_clean = true;  // cleared by the write kernel, or never set
     sp->nnz = hs->nnz;
-    if (hs->sp_over && info && (info->status == CQK_OK || info->status == CQK_NOT_CONVERGED))
-      info->status = CQK_BUFFER_TOO_SMALL;
   }
-  return CQK_OK;
+  return rs;
 }
 
 }  // namespace

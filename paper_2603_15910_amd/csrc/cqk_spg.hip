@@ -201,7 +201,7 @@ cqk_status run_spg_l1_lasso_f64(cqk_ctx* ctx, int64_t m, int64_t n, const double
   const size_t bpart = al((size_t)W.nchunk * n * 8);
   const size_t bpar = al((size_t)(kVS + 1) * W.gvec * 8);
   const size_t total = 2 * bm + 4 * bn + bpart + bpar + 256;
-  cqk_status st = ensure_buffer(ctx->spg, total);
+  cqk_status st = ensure_buffer(ctx, ctx->spg, total);
   if (st != CQK_OK) return st;
   char* w = (char*)ctx->spg.ptr;
   W.r = (double*)w;

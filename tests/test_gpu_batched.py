@@ -173,6 +173,47 @@ def test_backward_against_fp64_finite_differences(ctx):
     assert checked >= 16
 
 
+def test_c5_rows_against_fp64_finite_differences(ctx):
+    """FD check on 32 rows sampled from the C5 workload itself (4096 rows of
+    1024-32768 values, y = 3 N(0,1), g ~ N(0,1)): on each row a subset of
+    coordinates (support and non-support) is perturbed by +-1e-6 in FP64
+    through the oracle's projection, and the central difference of g.x is
+    compared with the GPU gradient.  Rows whose support has a margin below
+    1e-4 are skipped (the VJP is a one-sided derivative there)."""
+    off, y = W.batched_simplex_input(4096, 1024, 32768, 1, scale=3.0)
+    g = W.upstream_grad(y.size, 1)
+    x, _, _, info = _run(ctx, off, y)
+    assert info["status"] == 0
+    gy, gr = _grad_check(ctx, off, y, g, x)
+    rng = np.random.default_rng(5)
+    h = 1e-6
+    checked = skipped = 0
+    for s in rng.permutation(4096):
+        if checked == 32:
+            break
+        a, b = int(off[s]), int(off[s + 1])
+        ys = y[a:b].astype(np.float64)
+        gs = g[a:b].astype(np.float64)
+        xs, lam = O.project_simplex(ys, 1.0)
+        if np.min(np.abs(ys + lam)) < 1e-4:
+            skipped += 1
+            continue
+        supp = np.flatnonzero(xs > 0)
+        rest = np.flatnonzero(xs == 0)
+        coords = np.concatenate([rng.choice(supp, min(8, supp.size), replace=False),
+                                 rng.choice(rest, min(8, rest.size), replace=False)])
+        for i in coords:
+            yp = ys.copy(); yp[i] += h
+            ym = ys.copy(); ym[i] -= h
+            fd = (gs @ O.project_simplex(yp, 1.0)[0] - gs @ O.project_simplex(ym, 1.0)[0]) / (2 * h)
+            assert abs(gy[a + i] - fd) <= 1e-5 * max(1, np.abs(gs).max()), (s, i)
+        # d(g.x)/dr by the same central difference
+        fdr = (gs @ O.project_simplex(ys, 1.0 + h)[0] - gs @ O.project_simplex(ys, 1.0 - h)[0]) / (2 * h)
+        assert abs(gr[s] - fdr) <= 1e-5 * max(1, np.abs(gs).max()), s
+        checked += 1
+    assert checked == 32, (checked, skipped)
+
+
 def test_autograd_function(ctx):
     import paper_2603_15910_amd as cqk
     off, y = W.batched_simplex_input(50, 32, 3000, 4, scale=3.0)

@@ -206,3 +206,26 @@ def test_unaligned_views(ctx, shift):
     x, info = ctx.solve(*t, sub["r"], out=xbuf[shift:], check=False)
     assert info["status"] == 0
     check_cqk(x.cpu().numpy(), sub, ref, 1e-10)
+
+
+@pytest.mark.parametrize("gen", ["uniform", "correlated"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_several_tiles_per_wave(ctx, gen, dtype):
+    """n = 8e6 + 5: every wave of the pass kernel streams four tiles (a
+    ragged last one), so its compaction ring wraps and flushes across tiles
+    as at the benchmark size; all three compaction modes against the exact
+    solution."""
+    n = 8_000_005
+    inst = W.cqk_uniform(n, 21) if gen == "uniform" else W.cqk_correlated(n, 21)
+    if dtype == torch.float32:
+        inst = {k: (v.astype(np.float32).astype(np.float64) if k in "dablu" else v)
+                for k, v in inst.items()}
+        inst["r"] = float(np.dot(inst["b"], (inst["l"] + inst["u"]) / 2))
+    ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+    tol = 1e-10 if dtype == torch.float64 else 1e-5
+    for compaction in ("auto", "always", "off"):
+        x, info = _solve(ctx, inst, dtype, compaction=compaction, trace=True)
+        assert info["status"] == 0, (compaction, info)
+        check_cqk(x, inst, ref, tol)
+        if compaction != "off":
+            assert any(t["compacted"] for t in ctx.trace())

@@ -289,7 +289,7 @@ def test_l1_warm_support_of_zero_values(ctx):
     # the estimate's bound (first trace record); lambda_0 is at most that,
     # and at least lam*
     _, info = _proj(ctx, y, xbar, radius, l1=True, trace=True)
-    tr = ctx.trace()
+    tr = [t for t in ctx.trace() if t["kind"] != 7]   # 7: one thread's Algorithm 2
     assert tr[0]["kind"] == 0 and tr[0]["phi"] == lam0   # the estimate's own bound
     assert lam_ref - 1e-12 * radius <= info["lambda0"] <= lam0
 
