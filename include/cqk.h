@@ -25,6 +25,9 @@
  *   and is ordered with the caller's other work on that stream.
  * - Errors are returned as cqk_status; nothing aborts or throws across the
  *   ABI.  Host-side argument errors return before anything is enqueued.
+ *   A call given a cqk_info also stores a non-OK return value in
+ *   info->status, whatever step it stopped at (its other fields are then
+ *   filled only if the call reached the solver).
  * - With opts->sync != 0 (the default) the call waits for the result and
  *   fills *info.  Outputs are then final.
  * - With opts->sync = 0, or while the context's stream is capturing a HIP

@@ -15,6 +15,13 @@ namespace cqk {
 
 cqk_status hip_ok(hipError_t e) { return e == hipSuccess ? CQK_OK : CQK_DEVICE_ERROR; }
 
+// Every entry point that takes a cqk_info reports its return value in
+// info->status too, also when it returns before reaching the solver.
+cqk_status stamped(cqk_info* info, cqk_status st) {
+  if (info && st != CQK_OK) info->status = st;
+  return st;
+}
+
 bool stream_capturing(hipStream_t s) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   const hipError_t e = hipStreamIsCapturing(s, &cs);
@@ -309,97 +316,105 @@ cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t
 cqk_status cqk_solve_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
                          const double* b, const double* l, const double* u, double r, double* x,
                          const cqk_opts* opts, cqk_info* info) {
-  return solve_common<double>(ctx, n, d, a, b, l, u, nullptr, false, r, x, opts, info);
+  return stamped(info, solve_common<double>(ctx,
+                         n, d, a, b, l, u, nullptr, false, r, x, opts, info));
 }
 
 cqk_status cqk_solve_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
                          const float* b, const float* l, const float* u, double r, float* x,
                          const cqk_opts* opts, cqk_info* info) {
-  return solve_common<float>(ctx, n, d, a, b, l, u, nullptr, false, r, x, opts, info);
+  return stamped(info, solve_common<float>(ctx,
+                         n, d, a, b, l, u, nullptr, false, r, x, opts, info));
 }
 
 cqk_status cqk_project_simplex_f32(cqk_ctx* ctx, int64_t n, const float* y, double r, float* x,
                                    const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, nullptr, false, r, x, false, opts, info);
+  return stamped(info, simplex_common<float>(ctx, n, y, nullptr, false, r, x, false, opts, info));
 }
 
 cqk_status cqk_project_simplex_f64(cqk_ctx* ctx, int64_t n, const double* y, double r,
                                    double* x, const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, nullptr, false, r, x, false, opts, info);
+  return stamped(info, simplex_common<double>(ctx, n, y, nullptr, false, r, x, false, opts, info));
 }
 
 cqk_status cqk_project_l1_f32(cqk_ctx* ctx, int64_t n, const float* y, double radius, float* x,
                               const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, nullptr, false, radius, x, true, opts, info);
+  return stamped(info, simplex_common<float>(ctx,
+                         n, y, nullptr, false, radius, x, true, opts, info));
 }
 
 cqk_status cqk_project_l1_f64(cqk_ctx* ctx, int64_t n, const double* y, double radius,
                               double* x, const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, nullptr, false, radius, x, true, opts, info);
+  return stamped(info, simplex_common<double>(ctx,
+                         n, y, nullptr, false, radius, x, true, opts, info));
 }
 
 cqk_status cqk_solve_warm_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
                               const double* b, const double* l, const double* u,
                               const double* xbar, double r, double* x, const cqk_opts* opts,
                               cqk_info* info) {
-  return solve_common<double>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info);
+  return stamped(info, solve_common<double>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info));
 }
 
 cqk_status cqk_solve_warm_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
                               const float* b, const float* l, const float* u, const float* xbar,
                               double r, float* x, const cqk_opts* opts, cqk_info* info) {
-  return solve_common<float>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info);
+  return stamped(info, solve_common<float>(ctx, n, d, a, b, l, u, xbar, true, r, x, opts, info));
 }
 
 cqk_status cqk_project_simplex_warm_f32(cqk_ctx* ctx, int64_t n, const float* y,
                                         const float* xbar, double r, float* x,
                                         const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, xbar, true, r, x, false, opts, info);
+  return stamped(info, simplex_common<float>(ctx, n, y, xbar, true, r, x, false, opts, info));
 }
 
 cqk_status cqk_project_simplex_warm_f64(cqk_ctx* ctx, int64_t n, const double* y,
                                         const double* xbar, double r, double* x,
                                         const cqk_opts* opts, cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, xbar, true, r, x, false, opts, info);
+  return stamped(info, simplex_common<double>(ctx, n, y, xbar, true, r, x, false, opts, info));
 }
 
 cqk_status cqk_project_l1_warm_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
                                    double radius, float* x, const cqk_opts* opts,
                                    cqk_info* info) {
-  return simplex_common<float>(ctx, n, y, xbar, true, radius, x, true, opts, info);
+  return stamped(info, simplex_common<float>(ctx, n, y, xbar, true, radius, x, true, opts, info));
 }
 
 cqk_status cqk_project_l1_warm_f64(cqk_ctx* ctx, int64_t n, const double* y, const double* xbar,
                                    double radius, double* x, const cqk_opts* opts,
                                    cqk_info* info) {
-  return simplex_common<double>(ctx, n, y, xbar, true, radius, x, true, opts, info);
+  return stamped(info, simplex_common<double>(ctx, n, y, xbar, true, radius, x, true, opts, info));
 }
 
 cqk_status cqk_project_simplex_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y,
                                           const float* xbar, double r, int64_t cap,
                                           int64_t* idx, float* val, int64_t* nnz,
                                           const cqk_opts* opts, cqk_info* info) {
-  return sparse_common<float>(ctx, n, y, xbar, r, cap, idx, val, nnz, false, opts, info);
+  return stamped(info, sparse_common<float>(ctx,
+                         n, y, xbar, r, cap, idx, val, nnz, false, opts, info));
 }
 
 cqk_status cqk_project_simplex_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
                                           const double* xbar, double r, int64_t cap,
                                           int64_t* idx, double* val, int64_t* nnz,
                                           const cqk_opts* opts, cqk_info* info) {
-  return sparse_common<double>(ctx, n, y, xbar, r, cap, idx, val, nnz, false, opts, info);
+  return stamped(info, sparse_common<double>(ctx,
+                         n, y, xbar, r, cap, idx, val, nnz, false, opts, info));
 }
 
 cqk_status cqk_project_l1_sparse_f32(cqk_ctx* ctx, int64_t n, const float* y, const float* xbar,
                                      double radius, int64_t cap, int64_t* idx, float* val,
                                      int64_t* nnz, const cqk_opts* opts, cqk_info* info) {
-  return sparse_common<float>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
+  return stamped(info, sparse_common<float>(ctx,
+                         n, y, xbar, radius, cap, idx, val, nnz, true, opts, info));
 }
 
 cqk_status cqk_project_l1_sparse_f64(cqk_ctx* ctx, int64_t n, const double* y,
                                      const double* xbar, double radius, int64_t cap,
                                      int64_t* idx, double* val, int64_t* nnz,
                                      const cqk_opts* opts, cqk_info* info) {
-  return sparse_common<double>(ctx, n, y, xbar, radius, cap, idx, val, nnz, true, opts, info);
+  return stamped(info, sparse_common<double>(ctx,
+                         n, y, xbar, radius, cap, idx, val, nnz, true, opts, info));
 }
 
 }  // extern "C"
@@ -465,16 +480,16 @@ cqk_status cqk_solve_batched_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offs
                                  const double* l, const double* u, const double* r, double* x,
                                  double* lambda_out, int32_t* status_out, const cqk_opts* opts,
                                  cqk_info* info) {
-  return batched_cqk_common<double>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out,
-                                    status_out, opts, info);
+  return stamped(info, batched_cqk_common<double>(ctx, nseg, offsets, d, a, b, l, u, r, x,
+                                               lambda_out, status_out, opts, info));
 }
 
 cqk_status cqk_solve_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                  const float* d, const float* a, const float* b, const float* l,
                                  const float* u, const double* r, float* x, double* lambda_out,
                                  int32_t* status_out, const cqk_opts* opts, cqk_info* info) {
-  return batched_cqk_common<float>(ctx, nseg, offsets, d, a, b, l, u, r, x, lambda_out,
-                                   status_out, opts, info);
+  return stamped(info, batched_cqk_common<float>(ctx, nseg, offsets, d, a, b, l, u, r, x,
+                                               lambda_out, status_out, opts, info));
 }
 
 cqk_status cqk_solve_batched_backward_f64(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
@@ -526,23 +541,23 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
                                            const float* y, const double* r, double r_scalar,
                                            float* x, double* lambda_out, int32_t* nfree_out,
                                            const cqk_opts* opts, cqk_info* info) {
-  if (!ctx || nseg < 0) return CQK_INVALID_ARG;
-  if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return CQK_INVALID_ARG;
+  if (!ctx || nseg < 0) return stamped(info, CQK_INVALID_ARG);
+  if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return stamped(info, CQK_INVALID_ARG);
   cqk_opts o;
   cqk_status st = check_opts(opts, &o, true);
-  if (st != CQK_OK) return st;
+  if (st != CQK_OK) return stamped(info, st);
   if (nseg == 0) {
     last_trivial(ctx, info, CQK_OK, 0.0);
     return CQK_OK;
   }
-  if (!offsets || !y || !x) return CQK_INVALID_ARG;
-  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  if (!offsets || !y || !x) return stamped(info, CQK_INVALID_ARG);
+  if (hipSetDevice(ctx->device) != hipSuccess) return stamped(info, CQK_DEVICE_ERROR);
   ctx->last = nullptr;
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   st = run_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, o, inf);
-  if (st != CQK_OK) return st;
-  return (cqk_status)inf->status;
+  if (st != CQK_OK) return stamped(info, st);
+  return stamped(info, (cqk_status)inf->status);
 }
 
 cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
