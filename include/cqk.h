@@ -70,7 +70,9 @@ typedef enum cqk_status {
   CQK_DEVICE_ERROR = 4,   /* a HIP runtime call failed */
   CQK_NO_MEMORY = 5,      /* workspace allocation failed */
   CQK_BUFFER_TOO_SMALL = 6  /* sparse output: the support exceeds the
-                               capacity; nothing written, count returned */
+                               capacity; nothing written, count returned.
+                               No-allocation call: more rows than its fixed
+                               buffers hold; nothing enqueued */
 } cqk_status;
 
 /* Initial multiplier (Section 2.1 eq. (CQKlambda0); Section 3.1 Alg. 2). */
@@ -349,6 +351,28 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
                                            const float* y, const double* r, double r_scalar,
                                            float* x, double* lambda_out, int32_t* nfree_out,
                                            const cqk_opts* opts, cqk_info* info);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture without a prior cqk_reserve, serving loops and harnesses that
+ * forbid hipMalloc): cqk_project_simplex_batched_f32 with the same arguments,
+ * kernels, results and statuses, whose planning buffers (row list, row
+ * extents, length histogram, counters) live in a fixed device array of the
+ * library instead of the context's workspace.  That array holds the buffers
+ * for CQK_NOALLOC_MAX_SEG rows (about 1.3 MB); each GPU the library runs on
+ * keeps its own copy until the process ends.  The call allocates nothing:
+ * nseg > CQK_NOALLOC_MAX_SEG returns CQK_BUFFER_TOO_SMALL before anything is
+ * enqueued, and opts->timing is ignored.  Every call on one GPU, from any
+ * context, shares that GPU's array (the kernels clear their counters
+ * themselves): calls that overlap in time on one GPU (different streams or
+ * host threads) race and give undefined results.  cqk_ctx_last_info reads the
+ * last such call on the context as long as no later call on the GPU has
+ * reused the array. */
+#define CQK_NOALLOC_MAX_SEG 65536
+cqk_status cqk_project_simplex_batched_noalloc_f32(cqk_ctx* ctx, int32_t nseg,
+                                                   const int64_t* offsets, const float* y,
+                                                   const double* r, double r_scalar, float* x,
+                                                   double* lambda_out, int32_t* nfree_out,
+                                                   const cqk_opts* opts, cqk_info* info);
 
 /* Many general CQK instances in one launch (Section 2.1, Algorithm 1 per
  * row, each row with its own bracket, breakpoint and secant state): row s

@@ -21,8 +21,8 @@ import threading
 
 from . import _lib as L
 from ._lib import (CQK_BUFFER_TOO_SMALL, CQK_DEVICE_ERROR, CQK_INFEASIBLE, CQK_INVALID_ARG,
-                   CQK_NO_MEMORY, CQK_NOT_CONVERGED, CQK_OK, STATUS_NAMES, CqkLibraryMissing,
-                   cqk_info, cqk_opts, cqk_trace_rec)
+                   CQK_NO_MEMORY, CQK_NOALLOC_MAX_SEG, CQK_NOT_CONVERGED, CQK_OK, STATUS_NAMES,
+                   CqkLibraryMissing, cqk_info, cqk_opts, cqk_trace_rec)
 
 __all__ = [
     "CQK_OK", "CQK_INFEASIBLE", "CQK_INVALID_ARG", "CQK_NOT_CONVERGED", "CQK_DEVICE_ERROR",
@@ -235,6 +235,15 @@ def cqk_project_simplex_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambd
                                     nfree_out=None, opts=None, info=None):
     return _call("cqk_project_simplex_batched_f32", C.c_void_p(ctx), nseg, offsets, y, r,
                  r_scalar, x, lambda_out, nfree_out,
+                 C.byref(opts) if opts is not None else None,
+                 C.byref(info) if info is not None else None)
+
+
+def cqk_project_simplex_batched_noalloc_f32(ctx, nseg, offsets, y, r, r_scalar, x,
+                                            lambda_out=None, nfree_out=None, opts=None,
+                                            info=None):
+    return _call("cqk_project_simplex_batched_noalloc_f32", C.c_void_p(ctx), nseg, offsets, y,
+                 r, r_scalar, x, lambda_out, nfree_out,
                  C.byref(opts) if opts is not None else None,
                  C.byref(info) if info is not None else None)
 
@@ -542,7 +551,11 @@ class Context:
         return x, self.last_info
 
     def project_simplex_batched(self, y, offsets, r=1.0, out=None, lambda_out=None,
-                                nfree_out=None, check=True, **kw):
+                                nfree_out=None, check=True, noalloc=False, **kw):
+        """Batched simplex projection of the rows y[offsets[s]:offsets[s+1]].
+        noalloc=True calls cqk_project_simplex_batched_noalloc_f32 (fixed
+        planning buffers, no device allocation, at most CQK_NOALLOC_MAX_SEG
+        rows)."""
         torch = _torch()
         nseg = offsets.numel() - 1
         x = out if out is not None else torch.empty_like(y)
@@ -558,11 +571,12 @@ class Context:
         opts = make_opts(simplex=True, **kw)
         info = cqk_info()
         self._bind_stream()
-        st = cqk_project_simplex_batched_f32(self.handle, nseg, po, py, pr, rs, px, pl, pn,
-                                             opts, info)
+        fn = (cqk_project_simplex_batched_noalloc_f32 if noalloc
+              else cqk_project_simplex_batched_f32)
+        st = fn(self.handle, nseg, po, py, pr, rs, px, pl, pn, opts, info)
         self.last_info = info.as_dict()
         if check and st != CQK_OK:
-            raise CqkError(st, "cqk_project_simplex_batched_f32")
+            raise CqkError(st, fn.__name__)
         return x, self.last_info
 
     def project_simplex_batched_backward(self, x, g, offsets, grad_y=None, grad_r=None,

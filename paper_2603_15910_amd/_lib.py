@@ -18,6 +18,7 @@ CQK_NOT_CONVERGED = 3
 CQK_DEVICE_ERROR = 4
 CQK_NO_MEMORY = 5
 CQK_BUFFER_TOO_SMALL = 6
+CQK_NOALLOC_MAX_SEG = 65536   # rows the no-allocation batched call holds
 STATUS_NAMES = {0: "OK", 1: "INFEASIBLE", 2: "INVALID_ARG", 3: "NOT_CONVERGED",
                 4: "DEVICE_ERROR", 5: "NO_MEMORY", 6: "BUFFER_TOO_SMALL"}
 
@@ -186,6 +187,8 @@ SIGNATURES = {
     "cqk_project_l1_warm_f32": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_l1_warm_f64": (C.c_int, [_P, _I64, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_f32": (
+        C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _P, _P, _OPTS, _INFO]),
+    "cqk_project_simplex_batched_noalloc_f32": (
         C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _P, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_backward_f32": (
         C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _OPTS]),

@@ -131,11 +131,11 @@ void info_trivial(cqk_info* info, int status, double lam) {
 // A call answered on the host (empty input): its info is also what
 // cqk_ctx_last_info reports for it.
 void last_trivial(cqk_ctx* ctx, cqk_info* info, int status, double lam) {
-  cqk_info t;
-  info_trivial(&t, status, lam);
-  if (info) *info = t;
-  ctx->last = [t](cqk_info* out) {
-    *out = t;
+  info_trivial(&ctx->trivial, status, lam);
+  if (info) *info = ctx->trivial;
+  // one captured pointer: std::function keeps it without a heap allocation
+  ctx->last = [ctx](cqk_info* out) {
+    *out = ctx->trivial;
     return CQK_OK;
   };
 }
@@ -231,6 +231,9 @@ cqk_status cqk_create(cqk_ctx** out, void* hip_stream) {
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     ctx->num_cus = prop.multiProcessorCount;
+  // the no-allocation batched call's buffers on this device (looked up now,
+  // while dev is current); a failed lookup only disables that call
+  if (noalloc_scratch(dev, &ctx->scratch) != CQK_OK) ctx->scratch = nullptr;
   ctx->host_pinned_bytes = 64 * 1024;
   if (hipHostMalloc(&ctx->host_pinned, ctx->host_pinned_bytes, hipHostMallocDefault) !=
       hipSuccess) {
@@ -556,6 +559,32 @@ cqk_status cqk_project_simplex_batched_f32(cqk_ctx* ctx, int32_t nseg, const int
   cqk_info tmp;
   cqk_info* inf = info ? info : &tmp;
   st = run_batched_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, o, inf);
+  if (st != CQK_OK) return stamped(info, st);
+  return stamped(info, (cqk_status)inf->status);
+}
+
+cqk_status cqk_project_simplex_batched_noalloc_f32(cqk_ctx* ctx, int32_t nseg,
+                                                   const int64_t* offsets, const float* y,
+                                                   const double* r, double r_scalar, float* x,
+                                                   double* lambda_out, int32_t* nfree_out,
+                                                   const cqk_opts* opts, cqk_info* info) {
+  if (!ctx || nseg < 0) return stamped(info, CQK_INVALID_ARG);
+  if (!r && (!std::isfinite(r_scalar) || r_scalar < 0.0)) return stamped(info, CQK_INVALID_ARG);
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, true);
+  if (st != CQK_OK) return stamped(info, st);
+  if (nseg > CQK_NOALLOC_MAX_SEG) return stamped(info, CQK_BUFFER_TOO_SMALL);
+  if (nseg == 0) {
+    last_trivial(ctx, info, CQK_OK, 0.0);
+    return CQK_OK;
+  }
+  if (!offsets || !y || !x) return stamped(info, CQK_INVALID_ARG);
+  if (hipSetDevice(ctx->device) != hipSuccess) return stamped(info, CQK_DEVICE_ERROR);
+  ctx->last = nullptr;
+  cqk_info tmp;
+  cqk_info* inf = info ? info : &tmp;
+  st = run_batched_noalloc_f32(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, o,
+                               inf);
   if (st != CQK_OK) return stamped(info, st);
   return stamped(info, (cqk_status)inf->status);
 }

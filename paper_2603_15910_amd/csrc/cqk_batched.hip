@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "cqk_alg1.h"
 #include "cqk_device.h"
@@ -1398,21 +1399,44 @@ struct BatWs {
   int64_t* lrow;
 };
 
-cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
-  const size_t list_bytes = ((size_t)nseg * sizeof(int32_t) + 255) / 256 * 256;
+constexpr size_t round256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Bytes of the planning buffers of a batched call on nseg rows: the row list,
+// the counters, the bucket histogram of each planning block and the row
+// extents, each on a 256-byte boundary.
+constexpr size_t bat_ws_bytes(size_t nseg) {
+  return round256(nseg * sizeof(int32_t)) + 256 * sizeof(int32_t) +
+         round256((nseg > kPBlock ? (nseg + kPBlock - 1) / kPBlock : 1) * kNB * sizeof(int32_t)) +
+         round256(nseg * 2 * sizeof(int64_t));
+}
+
+// Carves the planning buffers out of base (bat_ws_bytes(nseg) bytes).
+void bat_layout(void* base, int32_t nseg, BatWs* w) {
+  const size_t list_bytes = round256((size_t)nseg * sizeof(int32_t));
   const size_t ctr_bytes = 256 * sizeof(int32_t);
   const size_t nblk = std::max<size_t>(1, ((size_t)nseg + kPBlock - 1) / kPBlock);
-  const size_t hist_bytes = (nblk * kNB * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t lrow_bytes = ((size_t)nseg * 2 * sizeof(int64_t) + 255) / 256 * 256;
-  cqk_status st = ensure_buffer(ctx, ctx->ws, list_bytes + ctr_bytes + hist_bytes + lrow_bytes);
-  if (st != CQK_OK) return st;
-  char* p = (char*)ctx->ws.ptr;
+  const size_t hist_bytes = round256(nblk * kNB * sizeof(int32_t));
+  char* p = (char*)base;
   w->list = (int32_t*)p;
   w->counters = (int32_t*)(p + list_bytes);
   w->bhist = (int32_t*)(p + list_bytes + ctr_bytes);
   w->lrow = (int64_t*)(p + list_bytes + ctr_bytes + hist_bytes);
+}
+
+cqk_status bat_workspace(cqk_ctx* ctx, int32_t nseg, BatWs* w) {
+  cqk_status st = ensure_buffer(ctx, ctx->ws, bat_ws_bytes((size_t)nseg));
+  if (st != CQK_OK) return st;
+  bat_layout(ctx->ws.ptr, nseg, w);
   return CQK_OK;
 }
+
+// The planning buffers of cqk_project_simplex_batched_noalloc_f32: a fixed
+// device array (one copy per GPU, alive until the process ends) for up to
+// CQK_NOALLOC_MAX_SEG rows.  Host code never names it in a launch or a copy:
+// its address on a device comes from hipGetSymbolAddress (noalloc_scratch).
+static_assert(CQK_NOALLOC_MAX_SEG > 0, "row limit of the no-allocation call");
+constexpr size_t kScratchBytes = bat_ws_bytes(CQK_NOALLOC_MAX_SEG);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 int persistent_grid(cqk_ctx* ctx, const cqk_batch_schedule& sc, int nseg) {
   const int g = ctx->num_cus * sc.blocks_per_cu;
@@ -1761,57 +1785,109 @@ bool valid_schedule(const cqk_batch_schedule& sc) {
 
 cqk_batch_schedule default_schedule() { return cqk_batch_schedule{8, 4, 0, 0}; }
 
-cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
-                           const double* r, double r_scalar, float* x, double* lambda_out,
-                           int32_t* nfree_out, const cqk_opts& o, cqk_info* info) {
-  BatWs w;
-  cqk_status st = bat_workspace(ctx, nseg, &w);
-  if (st != CQK_OK) return st;
+// The info record of the last batched forward call from the host copy of its
+// counters.
+void bat_fill_info(cqk_ctx* ctx, cqk_info* inf) {
+  const int32_t* hc = (const int32_t*)ctx->host_pinned;
+  const int flags = hc[CTR_FLAGS];
+  int status = CQK_OK;
+  if (flags & (kBadRadius | kBadValue)) status = CQK_INVALID_ARG;
+  else if (flags & kInfeasible) status = CQK_INFEASIBLE;
+  std::memset(inf, 0, sizeof(*inf));
+  inf->status = status;
+  inf->n_after_init = hc[CTR_SURV];
+  inf->iterations = 0;
+  inf->passes = 1;
+  inf->rows_spilled = hc[CTR_OVER];
+  if (ctx->bat_timing) {
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
+    inf->pass_ms = ms;
+  }
+}
+
+// Reads the outcome of the last batched forward call from its device
+// counters (ctx->bat_counters) once the stream has finished it.
+cqk_status bat_read_last(cqk_ctx* ctx, cqk_info* inf) {
+  int32_t* hc = (int32_t*)ctx->host_pinned;
+  if (hip_ok(hipMemcpy(hc, ctx->bat_counters, CTR_TOTAL * sizeof(int32_t),
+                       hipMemcpyDeviceToHost)) != CQK_OK)
+    return CQK_DEVICE_ERROR;
+  bat_fill_info(ctx, inf);
+  return CQK_OK;
+}
+
+// One batched forward call with its planning buffers in w.  Allocates
+// nothing unless o.timing asks for events the context does not have yet.
+cqk_status run_batched_f32_on(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                              const float* y, const double* r, double r_scalar, float* x,
+                              double* lambda_out, int32_t* nfree_out, const BatWs& w,
+                              const cqk_opts& o, cqk_info* info) {
   const BatArgs A = forward_args(nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, w);
   hipStream_t s = ctx->stream;
   if (o.timing) {
-    st = ensure_events(ctx, 2);
+    cqk_status st = ensure_events(ctx, 2);
     if (st != CQK_OK) return st;
     hipEventRecord(ctx->events[0], s);
   }
   launch_forward(ctx, ctx->sched_fwd, A);
   if (o.timing) hipEventRecord(ctx->events[1], s);
   if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
-  // the call's result from the device counters (host copy in hc)
-  int32_t* hc = (int32_t*)ctx->host_pinned;
-  const bool timing = o.timing != 0;
-  auto fill = [ctx, hc, timing](cqk_info* inf) {
-    const int flags = hc[CTR_FLAGS];
-    int status = CQK_OK;
-    if (flags & (kBadRadius | kBadValue)) status = CQK_INVALID_ARG;
-    else if (flags & kInfeasible) status = CQK_INFEASIBLE;
-    std::memset(inf, 0, sizeof(*inf));
-    inf->status = status;
-    inf->n_after_init = hc[CTR_SURV];
-    inf->iterations = 0;
-    inf->passes = 1;
-    inf->rows_spilled = hc[CTR_OVER];
-    if (timing) {
-      float ms = 0.f;
-      hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);
-      inf->pass_ms = ms;
-    }
-  };
-  int32_t* dc = A.counters;
-  ctx->last = [hc, dc, fill](cqk_info* inf) -> cqk_status {
-    if (hip_ok(hipMemcpy(hc, dc, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost)) != CQK_OK)
-      return CQK_DEVICE_ERROR;
-    fill(inf);
-    return CQK_OK;
-  };
+  ctx->bat_counters = A.counters;
+  ctx->bat_timing = o.timing != 0;
+  // one captured pointer: std::function keeps it without a heap allocation
+  ctx->last = [ctx](cqk_info* inf) -> cqk_status { return bat_read_last(ctx, inf); };
   if (info) std::memset(info, 0, sizeof(*info));
   if (!o.sync) return CQK_OK;
-  if (hip_ok(hipMemcpyAsync(hc, A.counters, CTR_TOTAL * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            s)) != CQK_OK)
+  if (hip_ok(hipMemcpyAsync(ctx->host_pinned, A.counters, CTR_TOTAL * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s)) != CQK_OK)
     return CQK_DEVICE_ERROR;
   if (hip_ok(hipStreamSynchronize(s)) != CQK_OK) return CQK_DEVICE_ERROR;
-  if (info) fill(info);
+  if (info) bat_fill_info(ctx, info);
   return CQK_OK;
+}
+
+cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
+                           const double* r, double r_scalar, float* x, double* lambda_out,
+                           int32_t* nfree_out, const cqk_opts& o, cqk_info* info) {
+  BatWs w;
+  cqk_status st = bat_workspace(ctx, nseg, &w);
+  if (st != CQK_OK) return st;
+  return run_batched_f32_on(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, w, o,
+                            info);
+}
+
+cqk_status noalloc_scratch(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return CQK_DEVICE_ERROR;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    // the caller made `device` current
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return CQK_DEVICE_ERROR;
+    }
+    addr[device] = p;
+  }
+  *out = addr[device];
+  return CQK_OK;
+}
+
+cqk_status run_batched_noalloc_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                   const float* y, const double* r, double r_scalar, float* x,
+                                   double* lambda_out, int32_t* nfree_out, const cqk_opts& o,
+                                   cqk_info* info) {
+  if (nseg > CQK_NOALLOC_MAX_SEG) return CQK_BUFFER_TOO_SMALL;
+  if (!ctx->scratch) return CQK_DEVICE_ERROR;
+  BatWs w;
+  bat_layout(ctx->scratch, nseg, &w);
+  cqk_opts o2 = o;
+  o2.timing = 0;  // events would be created on first use
+  return run_batched_f32_on(ctx, nseg, offsets, y, r, r_scalar, x, lambda_out, nfree_out, w, o2,
+                            info);
 }
 
 cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,

@@ -14,6 +14,7 @@
 namespace cqk {
 
 constexpr int kMaxTrace = 512;
+constexpr int kMaxDevices = 64;
 
 // Launches a kernel on stream s.  With a pair of events the dispatch itself
 // stamps its start and end into them, so no marker packet sits between two
@@ -110,6 +111,10 @@ struct cqk_ctx {
   // checks, so cqk_ctx_last_info can report a call queued with sync = 0 or
   // replayed from a captured graph.
   std::function<cqk_status(cqk_info*)> last;
+  cqk_info trivial{};               // the last call answered on the host
+  int32_t* bat_counters = nullptr;  // device counters of the last batched forward call
+  bool bat_timing = false;          // that call recorded events[0..1]
+  void* scratch = nullptr;  // this device's no-allocation planning buffers (noalloc_scratch)
 };
 
 namespace cqk {
@@ -193,6 +198,15 @@ cqk_status run_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, c
 cqk_status run_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                     const float* x, const float* g, float* grad_y,
                                     double* grad_r, const cqk_opts& o);
+// The batched simplex projection on the fixed per-GPU planning buffers
+// (no allocation): CQK_BUFFER_TOO_SMALL beyond CQK_NOALLOC_MAX_SEG rows.
+cqk_status run_batched_noalloc_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
+                                   const float* y, const double* r, double r_scalar, float* x,
+                                   double* lambda_out, int32_t* nfree_out, const cqk_opts& o,
+                                   cqk_info* info);
+// Device address of those buffers on `device` (which must be current),
+// looked up once per device.
+cqk_status noalloc_scratch(int device, void** out);
 bool valid_schedule(const cqk_batch_schedule& sc);
 cqk_status tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, const float* y,
                             const double* r, double r_scalar, float* x, int32_t repeats,
