@@ -6,14 +6,18 @@ HBM.  Prints one JSON line: the metric (elements/s = n / ms per solve), the
 roofline of the pass kernel (algorithmic bytes per launch over its average
 launch time from HIP events stamped by its dispatches in the timed region,
 against 8 TB/s, and the measured HBM traffic per launch when the committed
-counter summary matches the kernel source), the oracle's CPU rate on a 1e7
-sample, and "extras": the other workloads (correlated CQK, simplex and l1 at
+counter summary matches the kernel source), each pass of one solve (indices
+read, bytes, µs, GB/s), the same solve on seeds 1-3 of both n = 1e8
+generators, the n = 1e5 latency case (seeds 1-20, median over seeds of the
+best run), the oracle's CPU rate (best of 3 on a 1e7 sample, best of 10 at
+1e5), and "extras": the other workloads (correlated CQK, simplex and l1 at
 n = 1e8 with dense and sparse output, warm starts from a previous solution,
 batched and differentiable batched projections) on the same GPU, each
 checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
                     [--no-cpu-baseline] [--no-extras] [--calibrate-copy]
+                    [--oracle-full]
 """
 from __future__ import annotations
 
@@ -53,21 +57,39 @@ def host_cpu_desc():
     return os.cpu_count(), model
 
 
-def cpu_baseline(n_sample: int):
-    """The oracle (exact breakpoint-sort solver), single-threaded, on a
-    bounded sample of the same workload."""
+def _oracle_best(n, seed, reps):
+    """Best of reps single-threaded oracle solves (exact breakpoint sort)."""
     from oracle import cqk_oracle as O
     from paper_2603_15910_amd import workloads as W
-    inst = W.cqk_uniform(n_sample, 1)
-    t0 = time.perf_counter()
-    res = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
-    dt = time.perf_counter() - t0
-    assert res.status == O.OK
+    inst = W.cqk_uniform(n, seed)
+    best = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+        dt = time.perf_counter() - t0
+        assert res.status == O.OK
+        best = dt if best is None else min(best, dt)
+    return best
+
+
+def cpu_baseline(n_sample: int, reps: int = 3, full: bool = False):
+    """The oracle (exact breakpoint-sort solver, numpy, one thread) on a
+    bounded sample of the same workload, best of reps; also the C1 size
+    (n = 1e5, best of 10) and, with full, the whole workload (n = 1e8, best
+    of 3)."""
     ncpu, model = host_cpu_desc()
-    return {"value": n_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
-            "sample": f"cqk_uniform n={n_sample} seed=1 (1/10 of the workload), one exact "
-                      f"breakpoint-sort solve (numpy, 1 thread), {dt:.2f} s on {model} "
-                      f"({ncpu} logical CPUs)"}
+    dt = _oracle_best(n_sample, 1, reps)
+    out = {"value": n_sample / dt, "unit": "elements/s", "cores": 1, "kind": "oracle",
+           "sample": f"cqk_uniform n={n_sample} seed=1 ({n_sample / 1e8:g} of the workload), "
+                     f"exact breakpoint-sort solve (numpy, 1 thread), best of {reps}: "
+                     f"{dt:.2f} s on {model} ({ncpu} logical CPUs)"}
+    dt5 = _oracle_best(100_000, 1, 10)
+    out["c1_n1e5_best_of_10_s"] = dt5
+    if full:
+        dt8 = _oracle_best(100_000_000, 1, 3)
+        out["n1e8_best_of_3_s"] = dt8
+        out["n1e8_elements_per_s"] = 1e8 / dt8
+    return out
 
 
 def measured_traffic(kernel_sha):
@@ -115,6 +137,87 @@ def graph_replay_ms(torch, fn, reps):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+def pass_table(ctx, in_bytes=40.0):
+    """Per grid pass of the last timed, traced general solve: indices read
+    (n_k), survivors written, algorithmic bytes, kernel µs and GB/s."""
+    ms = ctx.pass_ms()
+    recs = [t for t in ctx.trace() if t["kind"] in (0, 1, 2)]
+    rows = []
+    for k, t in enumerate(recs):
+        per_in = in_bytes if t["source"] == 0 else 32.0
+        nbytes = per_in * t["n_in"] + (32.0 * t["n_out"] if t["compacted"] else 0.0)
+        us = ms[k] * 1e3 if k < len(ms) else None
+        rows.append({"kind": {0: "lambda0", 1: "evaluate", 2: "breakpoint"}[t["kind"]],
+                     "source": "original" if t["source"] == 0 else "compacted",
+                     "n_in": t["n_in"], "n_out": t["n_out"] if t["compacted"] else 0,
+                     "bytes": nbytes, "us": us,
+                     "gbs": nbytes / (us * 1e-6) / 1e9 if us else None,
+                     "frac_of_peak": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if us else None})
+    # passes queued after the loop stopped: no trace record, no bytes
+    tail = [m * 1e3 for m in ms[len(recs):]]
+    return rows, tail
+
+
+def c1_latency(ctx, dev, torch, seeds=range(1, 21), runs=20):
+    """C1: general CQK, n = 1e5, FP64, lambda_0 = 0, no compaction, seeds
+    1-20.  Per seed the minimum over runs, then the median over seeds, of the
+    whole call (wall clock, one host wait) and of its kernels alone (events).
+    The 4 MB working set is cache-resident: a latency figure, not an HBM one."""
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    wall, kern, iters, per_it = [], [], [], []
+    for seed in seeds:
+        inst = W.cqk_uniform(100_000, seed)
+        t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
+        x = torch.empty_like(t[0])
+        r = inst["r"]
+        best_w = best_k = None
+        info = None
+        for _ in range(runs):
+            sync()
+            t0 = time.perf_counter()
+            _, info = ctx.solve(*t, r, out=x, compaction="off")
+            w = (time.perf_counter() - t0) * 1e3
+            best_w = w if best_w is None else min(best_w, w)
+        for _ in range(runs):
+            _, inf = ctx.solve(*t, r, out=x, compaction="off", timing=True)
+            k = inf["pass_ms"] + inf["finalize_ms"]
+            best_k = k if best_k is None else min(best_k, k)
+        assert info["status"] == 0, info
+        wall.append(best_w)
+        kern.append(best_k)
+        iters.append(info["iterations"])
+        per_it.append(best_w / max(1, info["iterations"]))
+    return {"workload": "cqk_uniform n=100000 fp64, lambda0=0, compaction=off, seeds 1-20",
+            "ms_median_of_min": statistics.median(wall),
+            "kernel_ms_median_of_min": statistics.median(kern),
+            "iterations_median": statistics.median(iters),
+            "ms_per_iteration_median": statistics.median(per_it),
+            "elements_per_s": 1e5 / (statistics.median(wall) * 1e-3),
+            "runs_per_seed": runs}
+
+
+def c2_seeds(ctx, dev, torch, gen, seeds=(1, 2, 3), reps=5):
+    """C2 on seeds 1-3: ms per solve (median of reps), iterations."""
+    from paper_2603_15910_amd import workloads as W
+    sync = torch.cuda.synchronize
+    out = []
+    for seed in seeds:
+        inst = getattr(W, gen)(100_000_000, seed)
+        t = [torch.from_numpy(inst[k]).to(dev) for k in "dablu"]
+        r = inst["r"]
+        del inst
+        x = torch.empty_like(t[0])
+        ctx.solve(*t, r, out=x)
+        ms = timed(lambda: ctx.solve(*t, r, out=x), reps, sync)
+        _, info = ctx.solve(*t, r, out=x)
+        assert info["status"] == 0, info
+        out.append({"seed": seed, "ms": ms, "elements_per_s": 1e8 / (ms * 1e-3),
+                    "iterations": info["iterations"]})
+        del t, x
+        torch.cuda.empty_cache()
+    return out
 
 
 EXTRA_SECTIONS = ("correlated", "simplex", "warm", "batched", "differentiable", "spg")
@@ -496,6 +599,8 @@ def main():
                     help="run one extra workload alone (for profiling) and print its record")
     ap.add_argument("--no-row-loop", action="store_true",
                     help="skip the per-row loop comparator of the batched workload")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="also time the oracle on the whole n = 1e8 workload (best of 3, minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path",
@@ -555,8 +660,10 @@ def main():
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9 if pass_ms > 0 else 0.0
     fin_gbs = (sum(i["finalize_bytes"] for i in infos) /
                (sum(i["finalize_ms"] for i in infos) * 1e-3) / 1e9)
-    ctx.solve(*t, r, out=x, trace=True)  # after the timed region: the per-pass log
+    # after the timed region: the per-pass log with each pass's kernel time
+    ctx.solve(*t, r, out=x, trace=True, timing=True)
     tr = ctx.trace()
+    passes_tab, tail_us = pass_table(ctx)
     # context beside the headline (not the metric): the eq. (CQKlambda0) start
     # on the same instance, and the device-copy ceiling of this part
     ctx.solve(*t, r, out=x, lambda0="formula")
@@ -601,6 +708,8 @@ def main():
             "avg_launch_bytes": pass_bytes / max(passes, 1),
         },
         "iterations": infos[-1]["iterations"],
+        "passes": passes_tab,
+        "passes_after_stop_us": tail_us,
         "finalize_gbs": fin_gbs,
         "formula_start": {"ms": ms_formula, "iterations": info_formula["iterations"],
                           "elements_per_s": n / (ms_formula * 1e-3)},
@@ -609,11 +718,17 @@ def main():
     del t, x
     torch.cuda.empty_cache()
     if not args.no_extras:
+        log("bench: C2 seeds 1-3 (uniform, correlated)")
+        out["c2_seeds"] = {"cqk_uniform": c2_seeds(ctx, dev, torch, "cqk_uniform"),
+                           "cqk_correlated": c2_seeds(ctx, dev, torch, "cqk_correlated")}
+        log("bench: C1 (n = 1e5, seeds 1-20)")
+        out["c1"] = c1_latency(ctx, dev, torch)
+    if not args.no_extras:
         log("bench: extras")
         out["extras"] = extras(ctx, dev, torch)
     if not args.no_cpu_baseline:
         log(f"bench: cpu baseline (oracle) on n={args.cpu_sample}")
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample, full=args.oracle_full)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -194,6 +194,17 @@ cqk_status cqk_ctx_last_info(cqk_ctx* ctx, cqk_info* info);
  * values of J kept as survivors (v + min(lam, lo) > 0; every other value of
  * the tile is fixed at zero), hi = 0 (the tile's index). */
 cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count);
+/* Kernel time in milliseconds of each grid pass of the last single-instance
+ * call made with opts->timing = 1 and sync = 1 (cqk_solve_*,
+ * cqk_project_*), in the order the passes were queued: the lambda_0 or
+ * Algorithm 2 pass if any, then the Newton passes, including those queued
+ * after the loop had stopped, which return at once.  The x-writing pass is
+ * not included (info->finalize_ms).  Copies min(cap, count) values; *count
+ * receives the number of passes.  The list is refilled whenever a
+ * single-instance call's info is filled (sync = 1, or cqk_ctx_last_info) and
+ * is empty unless that call had opts->timing = 1 and sync = 1; batched calls
+ * and the SPG driver leave it as it was. */
+cqk_status cqk_last_pass_ms(cqk_ctx* ctx, float* ms, int32_t cap, int32_t* count);
 
 /* General CQK (Section 1 eq. (CQK), Algorithm 1).
  * d, a, b, l, u: n inputs each; x: n outputs.  r: right-hand side.

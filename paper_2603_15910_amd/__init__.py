@@ -83,6 +83,13 @@ def cqk_last_trace(ctx: int, cap: int = 512):
     return [buf[i].as_dict() for i in range(min(cap, cnt.value))]
 
 
+def cqk_last_pass_ms(ctx: int, cap: int = 1024):
+    buf = (C.c_float * cap)()
+    cnt = C.c_int32(0)
+    lib().cqk_last_pass_ms(C.c_void_p(ctx), buf, cap, C.byref(cnt))
+    return [float(buf[i]) for i in range(min(cap, cnt.value))]
+
+
 def cqk_ctx_last_info(ctx: int):
     """(status, info dict) of the last call on the context, read from the
     device after waiting for its stream."""
@@ -350,6 +357,10 @@ class Context:
 
     def trace(self):
         return cqk_last_trace(self.handle)
+
+    def pass_ms(self):
+        """Kernel ms of each grid pass of the last timed single-instance call."""
+        return cqk_last_pass_ms(self.handle)
 
     def ctx_last_info(self):
         """(status, info) of the last call, read from the device: the outcome

@@ -148,6 +148,7 @@ SIGNATURES = {
     "cqk_status_string": (C.c_char_p, [_I32]),
     "cqk_default_opts": (None, [_OPTS]),
     "cqk_last_trace": (C.c_int, [_P, C.POINTER(cqk_trace_rec), _I32, C.POINTER(_I32)]),
+    "cqk_last_pass_ms": (C.c_int, [_P, C.POINTER(C.c_float), _I32, C.POINTER(_I32)]),
     "cqk_ctx_last_info": (C.c_int, [_P, _INFO]),
     "cqk_solve_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
     "cqk_solve_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _INFO]),
@@ -210,7 +211,8 @@ def load(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
-    p = path or LIB_PATH
+    # CQK_LIBRARY: another build of the same library (e.g. a tuning variant)
+    p = path or os.environ.get("CQK_LIBRARY") or LIB_PATH
     if not os.path.exists(p):
         raise CqkLibraryMissing(
             f"{p} is not built; run `python -m paper_2603_15910_amd.build` "

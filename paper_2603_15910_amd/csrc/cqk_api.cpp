@@ -316,6 +316,15 @@ cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t
   return CQK_OK;
 }
 
+cqk_status cqk_last_pass_ms(cqk_ctx* ctx, float* ms, int32_t cap, int32_t* count) {
+  if (!ctx || cap < 0 || (cap > 0 && !ms)) return CQK_INVALID_ARG;
+  const int32_t have = (int32_t)ctx->last_pass_ms.size();
+  const int32_t k = cap < have ? cap : have;
+  for (int32_t i = 0; i < k; ++i) ms[i] = ctx->last_pass_ms[i];
+  if (count) *count = have;
+  return CQK_OK;
+}
+
 cqk_status cqk_solve_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
                          const double* b, const double* l, const double* u, double r, double* x,
                          const cqk_opts* opts, cqk_info* info) {

@@ -835,12 +835,14 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     inf->n_after_init = 0;
     inf->finalize_bytes = (double)n * (6.0 * sizeof(TIn));
     inf->pass_launches = npass;
+    ctx->last_pass_ms.clear();
     if (timing) {
       // every grid pass queued; those after the loop stopped returned at once
       for (int i = 2; i + 1 < pass_events; i += 2) {
         float ms = 0.f;
         hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
         inf->pass_ms += ms;
+        ctx->last_pass_ms.push_back(ms);
       }
       float ms = 0.f;
       hipEventElapsedTime(&ms, ctx->events[0], ctx->events[1]);

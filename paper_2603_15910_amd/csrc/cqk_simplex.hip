@@ -1869,6 +1869,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
       if (t.kind == 0 && t.source == 0 && t.compacted)
         info->pass_bytes += sizeof(TIn) * (double)t.n_in * ((sparse ? 0.0 : 1.0) + (warm ? 1.0 : 0.0));
     }
+    ctx->last_pass_ms.clear();
     if (timing) {
       // every grid pass launched (those after the loop stopped return at
       // once); the tail loop runs in one block between them and is not here
@@ -1876,6 +1877,7 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
         float ms = 0.f;
         hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]);
         info->pass_ms += ms;
+        ctx->last_pass_ms.push_back(ms);
       }
       for (int j = 0; j < 2; ++j) {
         float ms = 0.f;
