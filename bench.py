@@ -146,11 +146,12 @@ def pass_table(ctx, in_bytes=40.0):
     rows = []
     for k, t in enumerate(recs):
         per_in = in_bytes if t["source"] == 0 else 32.0
-        nbytes = per_in * t["n_in"] + (32.0 * t["n_out"] if t["compacted"] else 0.0)
+        # n_out: survivors written for both sides of the evaluation
+        nbytes = per_in * t["n_in"] + 32.0 * t["n_out"]
         us = ms[k] * 1e3 if k < len(ms) else None
         rows.append({"kind": {0: "lambda0", 1: "evaluate", 2: "breakpoint"}[t["kind"]],
                      "source": "original" if t["source"] == 0 else "compacted",
-                     "n_in": t["n_in"], "n_out": t["n_out"] if t["compacted"] else 0,
+                     "n_in": t["n_in"], "n_out": t["n_out"], "adopted": bool(t["compacted"]),
                      "bytes": nbytes, "us": us,
                      "gbs": nbytes / (us * 1e-6) / 1e9 if us else None,
                      "frac_of_peak": nbytes / (us * 1e-6) / 1e9 / HBM_PEAK_GBS if us else None})

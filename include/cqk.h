@@ -86,9 +86,15 @@ typedef enum cqk_lambda0_mode {
 
 typedef enum cqk_compaction {
   CQK_COMPACT_OFF = 0,      /* every pass reads all n indices (the paper's GPU form) */
-  CQK_COMPACT_AUTO = 1,     /* compact when the predicted survivors are
-                               <= compact_theta times the current set */
-  CQK_COMPACT_ALWAYS = 2    /* compact whenever the bracket resolves an index */
+  CQK_COMPACT_AUTO = 1,     /* general CQK: every evaluation after the first
+                               writes, for each bracket it can end with
+                               ([lam, hi] or [lo, lam]), the indices that
+                               bracket leaves unresolved, giving a side up
+                               as soon as it would keep more than
+                               compact_theta of the indices read; the next
+                               pass reads the set of the side that happened.
+                               Simplex / l1: compact on y + lam <= 0 */
+  CQK_COMPACT_ALWAYS = 2    /* as AUTO with compact_theta = 1 (every side kept) */
 } cqk_compaction;
 
 typedef enum cqk_accum {
@@ -103,7 +109,7 @@ typedef struct cqk_opts {
   int32_t max_iter;         /* Newton iterations (evaluations of phi); default 100 */
   double tol;               /* <= 0: eps^(3/4) of the working type (Section 5) */
   int32_t compaction;       /* cqk_compaction; default AUTO */
-  double compact_theta;     /* <= 0: library default */
+  double compact_theta;     /* <= 0: library default (0.5) */
   int32_t accum;            /* cqk_accum */
   int32_t sync;             /* 1 (default): wait and fill *info */
   int32_t trace;            /* 1: record one cqk_trace_rec per pass */
@@ -145,14 +151,16 @@ typedef struct cqk_trace_rec {
                                thread's Algorithm 2 (simplex / l1 start, see
                                below).  For kinds 3, 4 and 6, lam is the next
                                iterate, phi and slope those it was taken from. */
-  int32_t compacted;        /* 1 if this pass wrote a compacted set */
-  int32_t source;           /* 0 original arrays, 1/2 compacted buffers */
+  int32_t compacted;        /* 1 if the next pass reads a set this pass wrote */
+  int32_t source;           /* 0 original arrays, 1..3 compacted sets */
   double lam;               /* multiplier evaluated by the pass */
   double phi;               /* phi(lam) */
   double slope;             /* slope used for the step (phi'_+ or phi'_-) */
   double lo, hi;            /* Newton bracket after the pass */
   int64_t n_in;             /* indices read by the pass */
-  int64_t n_out;            /* indices written (compaction survivors) */
+  int64_t n_out;            /* indices written (compaction survivors; general
+                               CQK: of both sides, the next pass's n_in
+                               being the kept side's) */
 } cqk_trace_rec;
 
 typedef struct cqk_ctx cqk_ctx;

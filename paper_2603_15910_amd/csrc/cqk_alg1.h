@@ -16,25 +16,42 @@ namespace {
 
 // Partial record of an evaluation pass: NSUM sums.  A breakpoint pass writes
 // two (key, weight) pairs instead.
+//
+// An evaluation at lam ends with one of two brackets: [lam, hi] when
+// phi(lam) < r (side 0) or [lo, lam] when phi(lam) > r (side 1).  The pass
+// does not know which until its sums are reduced, so it drops the indices
+// each side's bracket resolves into that side's sums and writes each side's
+// survivors to its own compacted set; the update keeps the side that
+// happened.  Per side: D_* below, at P_SIDE + side * D_N.
+enum {
+  D_F = 0,   // bounds of the indices the side's bracket fixes
+  D_AF,      // |bounds| of those
+  D_C0,      // c of the indices free on the side's whole bracket
+  D_C1,      // s of those
+  D_A0,      // sgn * c of those
+  D_A1,      // sgn * s of those
+  D_NOUT,    // survivors written
+  D_DROP,    // waves that gave the side up (more survivors than theta allows)
+  D_N
+};
 enum {
   P_P = 0,     // sum g_i(lam)
   P_A,         // sum |g_i(lam)|
   P_QP,        // phi'_+ part
   P_QM,        // phi'_- part
-  P_DF,        // bounds of indices fixed in this pass
-  P_DAF,       // |bounds| of indices fixed in this pass
-  P_DC0,       // c of indices found free on the bracket
-  P_DC1,       // s of those
-  P_DA0,       // sgn * c of those
-  P_DA1,       // sgn * s of those
-  P_NIN,       // indices read
-  P_NOUT,      // indices written
-  P_PREDLO,    // survivors if lo moves to lam
-  P_PREDHI,    // survivors if hi moves to lam
+  P_SIDE,      // side 0, then side 1 (2 * D_N values)
+  P_NIN = P_SIDE + 2 * D_N,  // indices read
   P_BAD,       // indices failing the input checks
   NSUM
 };
 constexpr int NPART = NSUM;
+
+// Compacted sets: the caller's arrays are source 0, the three compacted sets
+// sources 1..3.  An evaluation reading source `src` writes side k's
+// survivors to side_dst(src, k), the two sets other than src.
+__device__ __host__ __forceinline__ int side_dst(int src, int side) {
+  return (src + side) % 3 + 1;
+}
 
 
 struct Acc {
@@ -61,11 +78,28 @@ __device__ __forceinline__ void to_form(double d, double a, double b, double l, 
   bad += ok ? 0.0 : 1.0;
 }
 
-// One index of an evaluation pass.  Returns true if the index survives
-// compaction (always true when not compacting).
+// Dropped-index sums of one side: fixed at l or at u on the side's whole
+// bracket, or free on it with g keeping one sign (pos: g >= 0 there).
+// Written as selects so the accumulators stay in registers.
+__device__ __forceinline__ void side_sums(Acc& acc, int o, bool at_l, bool at_u, bool fr,
+                                          double bl, double bu, double c, double s, bool pos) {
+  const double fixv = at_l ? bl : (at_u ? bu : 0.0);
+  acc.s[o + D_F] += fixv;
+  acc.s[o + D_AF] += fabs(fixv);
+  const double fc = fr ? c : 0.0, fs = fr ? s : 0.0;
+  const double sg = pos ? 1.0 : -1.0;
+  acc.s[o + D_C0] += fc;
+  acc.s[o + D_C1] += fs;
+  acc.s[o + D_A0] += sg * fc;
+  acc.s[o + D_A1] += sg * fs;
+}
+
+// One index of an evaluation pass at lam with bracket [lo, hi].  With
+// COMPACT, returns which sides keep the index (bit k: side k), after adding
+// it to the sums of the sides that drop it; else returns 0.
 template <bool COMPACT>
-__device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double bl, double bu,
-                                           double lam, double lo, double hi) {
+__device__ __forceinline__ int eval_index(Acc& acc, double c, double s, double bl, double bu,
+                                          double lam, double lo, double hi) {
   const double f = fma(s, lam, c);
   const double g = fmin(fmax(f, bl), bu);
   acc.s[P_P] += g;
@@ -73,30 +107,23 @@ __device__ __forceinline__ bool eval_index(Acc& acc, double c, double s, double 
   const bool ge_l = f >= bl, gt_l = f > bl, lt_u = f < bu, le_u = f <= bu;
   acc.s[P_QP] += (ge_l && lt_u) ? s : 0.0;
   acc.s[P_QM] += (gt_l && le_u) ? s : 0.0;
-  acc.s[P_NIN] += 1.0;
+  if (!COMPACT) return 0;
   const double fl = fma(s, lo, c);
   const double fh = fma(s, hi, c);
-  const bool fix_l = fh <= bl;
-  const bool fix_u = fl >= bu;
-  // resolved under the two brackets the update can produce
-  const bool res_lo_lam = (f <= bl) || fix_u || ((fl >= bl) && le_u && (fl >= 0.0 || f <= 0.0));
-  const bool res_lam_hi = fix_l || (f >= bu) || (ge_l && (fh <= bu) && (f >= 0.0 || fh <= 0.0));
-  acc.s[P_PREDHI] += res_lo_lam ? 0.0 : 1.0;
-  acc.s[P_PREDLO] += res_lam_hi ? 0.0 : 1.0;
-  if (!COMPACT) return true;
-  // fixed at a bound on the whole bracket, else free on the whole bracket
-  // with one sign; written as selects so the accumulators stay in registers
-  const double fixv = fix_l ? bl : (fix_u ? bu : 0.0);
-  acc.s[P_DF] += fixv;
-  acc.s[P_DAF] += fabs(fixv);
-  const bool freeb = !fix_l && !fix_u && (fl >= bl) && (fh <= bu) && (fl >= 0.0 || fh <= 0.0);
-  const double sg = (fl >= 0.0) ? 1.0 : -1.0;
-  const double fc = freeb ? c : 0.0, fs = freeb ? s : 0.0;
-  acc.s[P_DC0] += fc;
-  acc.s[P_DC1] += fs;
-  acc.s[P_DA0] += sg * fc;
-  acc.s[P_DA1] += sg * fs;
-  return !(fix_l || fix_u || freeb);
+  int keep = 0;
+  {  // side 0: [lam, hi]
+    const bool at_l = fh <= bl, at_u = f >= bu;
+    const bool fr = !at_l && !at_u && ge_l && (fh <= bu) && (f >= 0.0 || fh <= 0.0);
+    side_sums(acc, P_SIDE, at_l, at_u, fr, bl, bu, c, s, f >= 0.0);
+    keep |= (at_l || at_u || fr) ? 0 : 1;
+  }
+  {  // side 1: [lo, lam]
+    const bool at_l = f <= bl, at_u = fl >= bu;
+    const bool fr = !at_l && !at_u && (fl >= bl) && le_u && (fl >= 0.0 || f <= 0.0);
+    side_sums(acc, P_SIDE + D_N, at_l, at_u, fr, bl, bu, c, s, fl >= 0.0);
+    keep |= (at_l || at_u || fr) ? 0 : 2;
+  }
+  return keep;
 }
 
 // Closest breakpoints around lam (Algorithm 1, breakpoint steps), with the
@@ -153,7 +180,6 @@ __device__ __forceinline__ void advance(GenState* st, double next) {
 // The scalar part of Algorithm 1, run by one thread after an evaluation pass.
 __device__ __forceinline__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
   const double lam = st->lam;
-  const bool compacted = st->compact_next != 0;
   const int source = st->src;
   st->passes += 1;
   if (t[P_BAD] > 0.0) {
@@ -161,25 +187,31 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     return;
   }
   // algorithmic bytes: the set read (caller's arrays or the 32-byte form) and
-  // the survivors written
-  st->bytes += ((source == 0) ? st->in_bytes : 32.0) * t[P_NIN] + (compacted ? 32.0 * t[P_NOUT] : 0.0);
+  // the survivors written for both sides
+  const double nout = t[P_SIDE + D_NOUT] + t[P_SIDE + D_N + D_NOUT];
+  st->bytes += ((source == 0) ? st->in_bytes : 32.0) * t[P_NIN] + 32.0 * nout;
   const double phi = (st->F + st->C0) + (lam * st->C1 + t[P_P]);
   const double A = (st->AF + st->A0) + (lam * st->A1 + t[P_A]);
   const double Qp = st->C1 + t[P_QP];
   const double Qm = st->C1 + t[P_QM];
+  const double r0 = st->r;
+  // the side the evaluation chose; its compacted set (if every wave kept it)
+  // becomes the source of the next pass
+  const int side = (phi - r0 < 0.0) ? 0 : 1;
+  const int o = P_SIDE + side * D_N;
+  const bool compacted = (st->compaction != CQK_COMPACT_OFF) && (phi != r0) && (t[o + D_DROP] == 0.0);
   if (compacted) {
-    st->F += t[P_DF];
-    st->AF += t[P_DAF];
-    st->C0 += t[P_DC0];
-    st->C1 += t[P_DC1];
-    st->A0 += t[P_DA0];
-    st->A1 += t[P_DA1];
-    st->src = (source == 1) ? 2 : 1;
-    st->n_src = (int64_t)t[P_NOUT];
+    st->F += t[o + D_F];
+    st->AF += t[o + D_AF];
+    st->C0 += t[o + D_C0];
+    st->C1 += t[o + D_C1];
+    st->A0 += t[o + D_A0];
+    st->A1 += t[o + D_A1];
+    st->src = side_dst(source, side);
+    st->n_src = (int64_t)t[o + D_NOUT];
   } else {
     st->n_src = (int64_t)t[P_NIN];
   }
-  st->compact_next = 0;
   const double r = st->r, tol = st->tol;
   const double res = phi - r;
   // selects rather than branches, so the state stays in registers
@@ -191,18 +223,11 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
   st->hi = hi;
   const double slope = (res < 0.0) ? Qp : Qm;
   trace_push(st, tr, 1, compacted ? 1 : 0, source, lam, phi, slope, (int64_t)t[P_NIN],
-             compacted ? (int64_t)t[P_NOUT] : 0);
+             (int64_t)nout);
   st->iter += 1;
   // Section 5 criterion 1 (and the exact stop of Algorithm 1)
   if (res == 0.0) return finish(st, lam, 4);
   if (fabs(res) < tol * (A + fabs(r))) return finish(st, lam, 1);
-  // compaction decision for the next evaluation pass
-  if (st->compaction != CQK_COMPACT_OFF) {
-    const double pred = (res < 0.0) ? t[P_PREDLO] : t[P_PREDHI];
-    const double ncur = (double)st->n_src;
-    st->compact_next = (st->compaction == CQK_COMPACT_ALWAYS) ? (pred < ncur)
-                                                              : (pred <= st->theta * ncur);
-  }
   // criterion 3
   if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, lam, 3);
   double next;

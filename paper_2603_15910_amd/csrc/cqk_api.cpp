@@ -267,11 +267,11 @@ cqk_status cqk_set_stream(cqk_ctx* ctx, void* hip_stream) {
 cqk_status cqk_reserve(cqk_ctx* ctx, int64_t max_n, int32_t max_seg) {
   if (!ctx || max_n < 0 || max_seg < 0) return CQK_INVALID_ARG;
   if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
-  // compaction buffers dominate: 2 x 4 doubles per index (the general
-  // solver's exact layout, padding included), plus slack for the other
-  // paths' partial records
-  const size_t gen = std::max(gen_layout(max_n, ctx->num_cus, 2, true).bytes,
-                              gen_layout(max_n, ctx->num_cus, 4, true).bytes);
+  // compaction buffers dominate: three sets of 4 doubles per index at the
+  // largest theta (COMPACT_ALWAYS; the general solver's exact layout,
+  // padding included), plus slack for the other paths' partial records
+  const size_t gen = std::max(gen_layout(max_n, ctx->num_cus, 2, true, 1.0).bytes,
+                              gen_layout(max_n, ctx->num_cus, 4, true, 1.0).bytes);
   const size_t want = std::max(gen, (size_t)max_n * 64) + (size_t)max_seg * 64 + (4u << 20);
   cqk_status st = ensure_buffer(ctx, ctx->ws, want);
   if (st != CQK_OK) return st;

@@ -22,16 +22,27 @@
 // The host queues passes in batches and reads the state once per batch;
 // a pass queued after the loop has stopped returns at once.
 //
-// Compaction.  Once the Newton bracket [lo, hi] is known, an index whose
-// bound is active on the whole bracket (c + hi s <= b l, or c + lo s >= b u)
-// has the same value at every later iterate; so does an index that is free on
-// the whole bracket, whose contribution is the line c + lam s.  Such indices
-// are dropped from the pass (their contributions kept as a few scalars) and
-// the survivors are written, in the per-index form above, to a ping-pong
+// Compaction.  Within a Newton bracket [lo, hi] an index whose bound is
+// active on the whole bracket (c + hi s <= b l, or c + lo s >= b u) has the
+// same value at every later iterate; so does an index that is free on the
+// whole bracket, whose contribution is the line c + lam s.  Such indices are
+// dropped from later passes (their contributions kept as a few scalars) and
+// the survivors are written, in the per-index form above, to a compacted
 // set: wave w always owns the same pieces of it, so no grid-wide scan is
 // needed and the layout is deterministic.  In exact arithmetic the values of
 // phi and its slopes are unchanged; this is the fixing of Section 2.2 applied
 // through the bracket, plus the free-side analogue.
+//
+// The evaluation at lam_k itself narrows the bracket to [lam_k, hi] or
+// [lo, lam_k], and that narrower bracket resolves far more indices than
+// [lo, hi]; but which of the two it is only follows from the pass's reduced
+// sums.  So an evaluation pass writes both candidate sets (one per side, each
+// with its own dropped-index sums), and the update keeps the side that
+// happened.  A side that would keep more than theta of the indices a wave
+// reads is given up by that wave at once (before it writes), which makes the
+// side unusable for the pass and costs nothing more; sides that resolve
+// little are thus never written.  The first pass of a solve (one-sided
+// bracket) does not compact: gen_first_pass_kernel.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -48,10 +59,11 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
-constexpr int kStage = 256;  // LDS ring per wave and array for compaction
-constexpr int kPieceLog = 7;
+constexpr int kStage = 128;  // LDS ring per wave, side and array for compaction
+constexpr int kPieceLog = 6;
 constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
-static_assert(kPiece == 2 * kWave, "a full flush writes one piece, two values per lane");
+static_assert(kPiece == kWave, "a full flush writes one piece, one value per lane");
+static_assert(kStage >= kPiece + kWave - 1, "the ring holds a piece plus one slot's survivors");
 
 struct GenArgs {
   const void* d;
@@ -63,10 +75,11 @@ struct GenArgs {
   void* x;
   int64_t n;
   int64_t chunk;
-  double* buf[2];   // compacted sets: array j (c, s, bl, bu) of set k is the
-                    // plane buf[k] + j NR chunk, in pieces of kPiece values
-                    // (see piece_pos)
-  int32_t* cnt[2];
+  int64_t region;   // values one wave can keep in a compacted set
+  double* buf[3];   // compacted sets 1..3: array j (c, s, bl, bu) of set k is
+                    // the plane buf[k-1] + j NR region, in pieces of kPiece
+                    // values (see Pieces)
+  int32_t* cnt[3];  // survivors of each wave in each set
   double* partials;
   GenState* st;
   cqk_trace_rec* trace;
@@ -174,57 +187,56 @@ struct SrcForm {
   }
 };
 
-// One wave streams its tiles.  Compaction stages the survivors of slot
-// e of every lane in the wave's slice of LDS (ballot + lane prefix count,
-// slot after slot, so the layout is deterministic and needs no block-wide
-// synchronisation) and writes them out kPiece = 128 at a time: one store per
-// array then fills 1 KB, instead of one partial store per slot.
+// One wave streams its tiles.  With COMPACT each index is also classified
+// for both sides of the evaluation (see eval_index): the survivors of slot e
+// of every lane are staged per side in the wave's slice of LDS (ballot +
+// lane prefix count, slot after slot, so the layout is deterministic and
+// needs no block-wide synchronisation) and written out kPiece = 64 at a
+// time: one 512-byte store per array.  A side is given up for the whole pass
+// (D_DROP) as soon as a flush would leave the wave with more than theta
+// times the indices it has read: such a set would not pay for its writes,
+// and a side given up early writes nothing.  At most theta * read + kPiece
+// survivors are ever written, which bounds the wave's region.
 // The LDS operations of one wave complete in issue order, so a lane reads
 // what another lane staged without a wait; the wave-scope fences only keep
 // the compiler from reordering those accesses.
 template <typename Src, bool COMPACT>
 __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t stride, double lam,
-                          double lo, double hi, double* const* out, Pieces op, int32_t* out_cnt,
-                          Acc& acc, double* stg) {
+                          double lo, double hi, double theta, double* const* out, Pieces op,
+                          int32_t* const* out_cnt, Acc& acc, double* stg) {
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
-  int64_t written = 0;
-  int head = 0, pend = 0;  // staged survivors occupy ring slots head .. head + pend - 1
-  // `written` and `head` are multiples of kPiece at every flush, so a flush
-  // fills (the start of) one piece: a full one with 16 bytes per lane and
-  // array (1 KB per store), the last one value by value; non-temporal, like
-  // the other streams
-  auto flush = [&](int m) {
+  // per side: values written, ring head, values staged, given up
+  int64_t written[2] = {0, 0};
+  int head[2] = {0, 0}, pend[2] = {0, 0};
+  bool drop[2] = {false, false};
+  int64_t seen = 0;  // indices read so far
+  // `written` and `head` are multiples of kPiece at every full flush, so a
+  // flush fills (the start of) one piece: a full one with 8 bytes per lane
+  // and array, the last one value by value; non-temporal, like the other
+  // streams
+  auto flush = [&](int k, int m) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int64_t p0 = op.pos(written);
-    if (m == kPiece) {
-      const int q = (head + 2 * lane) & (kStage - 1);
+    const double* sg = stg + k * 4 * kStage;
+    double* const* o = out + 4 * k;
+    const int64_t p0 = op.pos(written[k]);
+    if (lane < m) {
+      const int q = (head[k] + lane) & (kStage - 1);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const dbl2 v = *reinterpret_cast<const dbl2*>(&stg[j * kStage + q]);
-        __builtin_nontemporal_store(v, reinterpret_cast<dbl2*>(&out[j][p0 + 2 * lane]));
-      }
-    } else {
-      for (int i = lane; i < m; i += kWave) {
-        const int q = (head + i) & (kStage - 1);
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          __builtin_nontemporal_store(stg[j * kStage + q], &out[j][p0 + i]);
-      }
+      for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(sg[j * kStage + q], &o[j][p0 + lane]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    head = (head + m) & (kStage - 1);
-    written += m;
-    pend -= m;
+    head[k] = (head[k] + m) & (kStage - 1);
+    written[k] += m;
+    pend[k] -= m;
   };
   // full tiles take the unguarded path; only the last tile of a region checks
   // its range
   auto tile = [&](int64_t base, auto full_tag) {
     constexpr bool FULL = decltype(full_tag)::value;
     double c[E], s[E], bl[E], bu[E];
-    bool keep[E];
     if (FULL) {
       src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
     } else {
@@ -240,37 +252,53 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
-        keep[e] = false;
-        if (FULL || i + k < count)
-          keep[e] = eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi);
-      }
-    }
-    if (COMPACT) {
+        const bool in = FULL || i + k < count;
+        const int keep = in ? eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi) : 0;
+        seen += FULL ? kWave : __popcll(__ballot(in));
+        if (COMPACT) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const uint64_t m = __ballot(keep[e]);
-        if (keep[e]) {
-          const int q = (head + pend + lane_prefix(m)) & (kStage - 1);
-          stg[q] = c[e];
-          stg[kStage + q] = s[e];
-          stg[2 * kStage + q] = bl[e];
-          stg[3 * kStage + q] = bu[e];
+          for (int side = 0; side < 2; ++side) {
+            if (drop[side]) continue;
+            const bool kp = (keep >> side) & 1;
+            const uint64_t m = __ballot(kp);
+            if (kp) {
+              double* sg = stg + side * 4 * kStage;
+              const int q = (head[side] + pend[side] + lane_prefix(m)) & (kStage - 1);
+              sg[q] = c[e];
+              sg[kStage + q] = s[e];
+              sg[2 * kStage + q] = bl[e];
+              sg[3 * kStage + q] = bu[e];
+            }
+            pend[side] += __popcll(m);
+            // pend < kPiece before this slot, so the ring never holds more
+            // than kPiece + 63 <= kStage values
+            if (pend[side] >= kPiece) {
+              if ((double)(written[side] + kPiece) <= theta * (double)seen) flush(side, kPiece);
+              else drop[side] = true;
+            }
+          }
         }
-        pend += __popcll(m);
-        // pend < kPiece before this slot, so the ring never holds more than
-        // kPiece + 63 < kStage values
-        if (pend >= kPiece) flush(kPiece);
       }
     }
   };
   int64_t base = first;
   for (; base + TILE <= count; base += stride) tile(base, std::true_type{});
   if (base < count) tile(base, std::false_type{});
+  if (lane == 0) acc.s[P_NIN] += (double)seen;
   if (COMPACT) {
-    if (pend > 0) flush(pend);
-    if (lane == 0) {
-      *out_cnt = (int32_t)written;
-      acc.s[P_NOUT] += (double)written;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      if (!drop[side] && pend[side] > 0) {
+        if ((double)(written[side] + pend[side]) <= theta * (double)seen + kPiece)
+          flush(side, pend[side]);
+        else
+          drop[side] = true;
+      }
+      if (lane == 0) {
+        *out_cnt[side] = (int32_t)written[side];
+        acc.s[P_SIDE + side * D_N + D_NOUT] += (double)written[side];
+        acc.s[P_SIDE + side * D_N + D_DROP] += drop[side] ? 1.0 : 0.0;
+      }
     }
   }
 }
@@ -316,56 +344,63 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   if (st->status != kRunning) return;
   const int mode = st->mode;
   const int src = st->src;
-  const bool compact = (mode == kModeEval) && (st->compact_next != 0);
-  const double lam = st->lam, lo = st->lo, hi = st->hi;
+  const bool compact = (mode == kModeEval) && (st->compaction != CQK_COMPACT_OFF);
+  const double lam = st->lam, lo = st->lo, hi = st->hi, theta = st->theta;
   // Passes over the caller's arrays hand tiles to waves grid-stride (tile t
   // to wave t mod NR), so all waves stream through neighbouring addresses;
-  // wave rid keeps its survivors (at most `chunk`) in its pieces of a
+  // wave rid keeps its survivors (at most `region`) in its pieces of a
   // compacted set, and later passes stream those pieces.
   const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
   const int64_t nr = (int64_t)gridDim.x * kWavesPerBlock;
-  const int64_t plane = nr * A.chunk;  // one array of a compacted set
+  const int64_t plane = nr * A.region;  // one array of a compacted set
   const Pieces pc{rid, nr};
 
   __shared__ double lds[NPART * (kBlock / kWave)];
   __shared__ double tot[NPART];
-  __shared__ double stage[kWavesPerBlock * 4 * kStage];
-  double* stg = stage + (threadIdx.x / kWave) * 4 * kStage;
+  __shared__ double stage[kWavesPerBlock * 2 * 4 * kStage];
+  double* stg = stage + (threadIdx.x / kWave) * 2 * 4 * kStage;
 
   Acc acc;
   acc_init(acc);
   KeySum ks[2] = {KeySum{inf_d(), 0.0}, KeySum{inf_d(), 0.0}};
+  // the two sides' output sets and counts
+  double* out[8];
+  int32_t* oc[2];
+  if (compact) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int d = side_dst(src, k) - 1;
+      double* rb = A.buf[d];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) out[4 * k + j] = rb + j * plane;
+      oc[k] = A.cnt[d] + rid;
+    }
+  }
   if (src == 0) {
     SrcOrig<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
                    (const TIn*)A.u};
     constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrig<TIn>::V;
     const int64_t first = (int64_t)rid * T, stride = nr * T;
-    if (mode != kModeEval) {
+    if (mode != kModeEval)
       bkpt_pass(s, A.n, first, stride, lam, ks);
-    } else if (compact) {
-      double* rb = A.buf[0];
-      double* out[4] = {rb, rb + plane, rb + 2 * plane, rb + 3 * plane};
-      eval_pass<SrcOrig<TIn>, true>(s, A.n, first, stride, lam, lo, hi, out, pc, A.cnt[0] + rid,
-                                    acc, stg);
-    } else {
-      eval_pass<SrcOrig<TIn>, false>(s, A.n, first, stride, lam, lo, hi, nullptr, pc, nullptr,
-                                     acc, stg);
-    }
+    else if (compact)
+      eval_pass<SrcOrig<TIn>, true>(s, A.n, first, stride, lam, lo, hi, theta, out, pc, oc, acc,
+                                    stg);
+    else
+      eval_pass<SrcOrig<TIn>, false>(s, A.n, first, stride, lam, lo, hi, theta, nullptr, pc,
+                                     nullptr, acc, stg);
   } else {
-    const int si = src - 1, di = 1 - si;
-    const double* sb = A.buf[si];
+    const double* sb = A.buf[src - 1];
     SrcForm s{sb, sb + plane, sb + 2 * plane, sb + 3 * plane, pc};
     constexpr int64_t T = (int64_t)kWave * kUnroll * SrcForm::V;
-    const int64_t count = A.cnt[si][rid];
-    if (mode != kModeEval) {
+    const int64_t count = A.cnt[src - 1][rid];
+    if (mode != kModeEval)
       bkpt_pass(s, count, 0, T, lam, ks);
-    } else if (compact) {
-      double* rb = A.buf[di];
-      double* out[4] = {rb, rb + plane, rb + 2 * plane, rb + 3 * plane};
-      eval_pass<SrcForm, true>(s, count, 0, T, lam, lo, hi, out, pc, A.cnt[di] + rid, acc, stg);
-    } else {
-      eval_pass<SrcForm, false>(s, count, 0, T, lam, lo, hi, nullptr, pc, nullptr, acc, stg);
-    }
+    else if (compact)
+      eval_pass<SrcForm, true>(s, count, 0, T, lam, lo, hi, theta, out, pc, oc, acc, stg);
+    else
+      eval_pass<SrcForm, false>(s, count, 0, T, lam, lo, hi, theta, nullptr, pc, nullptr, acc,
+                                stg);
   }
 
   if (mode == kModeEval) {
@@ -380,6 +415,76 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
       const double v[4] = {ktot[0].k, ktot[0].w, ktot[1].k, ktot[1].w};
       write_partial(A.partials, v, 4);
     }
+  }
+}
+
+// The first Newton pass of a solve: an evaluation over the caller's arrays.
+// Its bracket is one-sided at best, so each side would keep most indices and
+// nothing is compacted; without the compaction rings and sums the kernel
+// needs far fewer registers and no LDS beyond the block reduction, so more
+// waves stream at once.  Same tiles and partial record as gen_pass_kernel
+// (both sides marked as given up).
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_first_pass_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const double lam = st->lam;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+  const int64_t nr = (int64_t)gridDim.x * kWavesPerBlock;
+  SrcOrig<TIn> src{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
+                   (const TIn*)A.u};
+  constexpr int V = SrcOrig<TIn>::V;
+  constexpr int E = kUnroll * V;
+  constexpr int64_t T = (int64_t)kWave * E;
+  const int64_t count = A.n;
+  Acc acc;
+  acc_init(acc);
+  int64_t seen = 0;
+  auto tile = [&](int64_t base, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    double c[E], s[E], bl[E], bu[E];
+    if (FULL) {
+      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
+    } else {
+#pragma unroll
+      for (int w = 0; w < kUnroll; ++w) {
+        const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+        src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
+      }
+    }
+#pragma unroll
+    for (int w = 0; w < kUnroll; ++w) {
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = w * V + k;
+        if (FULL || i + k < count) eval_index<false>(acc, c[e], s[e], bl[e], bu[e], lam, 0.0, 0.0);
+      }
+    }
+    seen += FULL ? T : std::min<int64_t>(T, count - base);
+  };
+  int64_t base = (int64_t)rid * T;
+  for (; base + T <= count; base += nr * T) tile(base, std::true_type{});
+  if (base < count) tile(base, std::false_type{});
+  double v[6] = {acc.s[P_P], acc.s[P_A], acc.s[P_QP], acc.s[P_QM], acc.s[P_BAD],
+                 lane == 0 ? (double)seen : 0.0};
+  __shared__ double lds[6 * (kBlock / kWave)];
+  __shared__ double tot[6];
+  block_reduce<6, 0, 0, kBlock>(v, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) {
+    double rec[NPART];
+#pragma unroll
+    for (int i = 0; i < NPART; ++i) rec[i] = 0.0;
+    rec[P_P] = tot[0];
+    rec[P_A] = tot[1];
+    rec[P_QP] = tot[2];
+    rec[P_QM] = tot[3];
+    rec[P_BAD] = tot[4];
+    rec[P_NIN] = tot[5];
+    rec[P_SIDE + D_DROP] = 1.0;
+    rec[P_SIDE + D_N + D_DROP] = 1.0;
+    write_partial(A.partials, rec, NPART);
   }
 }
 
@@ -663,29 +768,43 @@ int choose_grid(int64_t n, int num_cus) {
 
 // G blocks of kWavesPerBlock waves.  A pass over the caller's arrays hands its
 // tiles (64 lanes x kUnroll vectors of `vec` values) to the NR waves
-// grid-stride, at most `tpw` tiles each, so a wave region of chunk = tpw
-// tiles holds every survivor a wave can keep.  The primal recovery runs
-// grid-stride on its own grid GF of 4-vector tiles.  Workspace: partials |
-// counts (2 x NR) | buffers (2 x 4 x npad doubles, only with compaction).
-GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction) {
+// grid-stride, at most `tpw` tiles each (chunk = tpw tiles).  A wave keeps
+// at most theta * chunk + kPiece survivors of a side (eval_pass), so its
+// region in a compacted set holds that many values, rounded up to whole
+// pieces.  The primal recovery runs grid-stride on its own grid GF of
+// 4-vector tiles.  Workspace: partials | counts (3 x NR) | three compacted
+// sets (4 planes of NR x region doubles each, only with compaction).
+GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta) {
   GenLayout L{};
   const int64_t T = (int64_t)kWave * kUnroll * vec;
   const int G0 = choose_grid(n, num_cus);
   const int64_t ntiles = (n + T - 1) / T;
   const int64_t tpw = std::max<int64_t>(
       1, (ntiles + (int64_t)G0 * kWavesPerBlock - 1) / ((int64_t)G0 * kWavesPerBlock));
-  L.chunk = tpw * T;  // a multiple of 16: every region array starts a 128-byte line
+  L.chunk = tpw * T;
   const int64_t bchunk = L.chunk * kWavesPerBlock;
   L.G = (int)std::max<int64_t>(1, (n + bchunk - 1) / bchunk);
   L.NR = L.G * kWavesPerBlock;
-  const int64_t npad = (int64_t)L.NR * L.chunk;
+  const double th = std::min(1.0, std::max(0.0, theta));
+  const int64_t keep = (int64_t)std::ceil(th * (double)L.chunk) + kPiece;
+  // a multiple of kPiece (so of 16): every plane starts a 128-byte line
+  L.region = std::min<int64_t>((L.chunk + kPiece - 1) / kPiece * kPiece,
+                               (keep + kPiece - 1) / kPiece * kPiece);
   const int64_t ftile = (int64_t)kBlock * vec * 4;
   L.GF = (int)std::max<int64_t>(1, std::min<int64_t>(4 * (int64_t)L.G, (n + ftile - 1) / ftile));
   L.part_bytes = ((size_t)L.G * NPART * sizeof(double) + 255) / 256 * 256;
-  L.cnt_bytes = ((size_t)2 * L.NR * sizeof(int32_t) + 255) / 256 * 256;
-  const size_t buf_bytes = compaction ? (size_t)8 * npad * sizeof(double) : 0;
+  L.cnt_bytes = ((size_t)3 * L.NR * sizeof(int32_t) + 255) / 256 * 256;
+  const size_t buf_bytes =
+      compaction ? (size_t)3 * 4 * (size_t)L.NR * (size_t)L.region * sizeof(double) : 0;
   L.bytes = L.part_bytes + L.cnt_bytes + buf_bytes;
   return L;
+}
+
+// theta of a call: the library default 0.5 (AUTO) unless the options give
+// one; COMPACT_ALWAYS keeps every side whatever its size
+double gen_theta(const cqk_opts& o) {
+  if (o.compaction == CQK_COMPACT_ALWAYS) return 1.0;
+  return (o.compact_theta > 0.0) ? o.compact_theta : 0.5;
 }
 
 namespace {
@@ -694,10 +813,11 @@ template <typename TIn>
 cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, const TIn* b,
                        const TIn* l, const TIn* u, const TIn* xw, double r, TIn* x,
                        const cqk_opts& o, cqk_info* info) {
-  const GenLayout Lg = gen_layout(n, ctx->num_cus, VecWidth<TIn>::value, o.compaction != CQK_COMPACT_OFF);
+  const bool compaction = o.compaction != CQK_COMPACT_OFF;
+  const double theta = gen_theta(o);
+  const GenLayout Lg = gen_layout(n, ctx->num_cus, VecWidth<TIn>::value, compaction, theta);
   const int G = Lg.G, NR = Lg.NR, GF = Lg.GF;
   const int64_t chunk = Lg.chunk;
-  const bool compaction = o.compaction != CQK_COMPACT_OFF;
   const size_t part_bytes = Lg.part_bytes, cnt_bytes = Lg.cnt_bytes;
   cqk_status stt = ensure_buffer(ctx, ctx->ws, Lg.bytes);
   if (stt != CQK_OK) return stt;
@@ -716,13 +836,14 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   A.x = x;
   A.n = n;
   A.chunk = chunk;
+  A.region = Lg.region;
   A.partials = (double*)ws;
   A.cnt[0] = (int32_t*)(ws + part_bytes);
   A.cnt[1] = A.cnt[0] + NR;
+  A.cnt[2] = A.cnt[1] + NR;
   if (compaction) {
     double* bb = (double*)(ws + part_bytes + cnt_bytes);
-    A.buf[0] = bb;
-    A.buf[1] = bb + (size_t)4 * NR * chunk;
+    for (int k = 0; k < 3; ++k) A.buf[k] = bb + (size_t)k * 4 * NR * Lg.region;
   }
   A.st = (GenState*)ctx->state.ptr;
   A.trace = (cqk_trace_rec*)((char*)ctx->state.ptr + 1024);
@@ -739,7 +860,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.phi_lo = init.phi_hi = __builtin_nan("");
   init.r = r;
   init.tol = (o.tol > 0.0) ? o.tol : std::pow(eps, 0.75);
-  init.theta = (o.compact_theta > 0.0) ? o.compact_theta : 0.5;
+  init.theta = theta;
   init.n_src = n;
   init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
@@ -789,8 +910,15 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;
+  // the first Newton pass always evaluates the caller's arrays without
+  // compaction: the lean kernel; every later pass the general one
+  auto pass = [&]() {
+    if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel);
+    else launch(gen_pass_kernel<TIn>, gen_update_kernel);
+    ++launched;
+  };
   if (deferred) {
-    for (; launched < max_launch; ++launched) launch(gen_pass_kernel<TIn>, gen_update_kernel);
+    while (launched < max_launch) pass();
     finalize();
     if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
   } else {
@@ -798,8 +926,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     int batch = 6;
     while (launched < max_launch) {
       const int k = std::min(batch, max_launch - launched);
-      for (int i = 0; i < k; ++i) launch(gen_pass_kernel<TIn>, gen_update_kernel);
-      launched += k;
+      for (int i = 0; i < k; ++i) pass();
       finalize();
       if (hip_ok(hipGetLastError()) != CQK_OK) return CQK_DEVICE_ERROR;
       if (hip_ok(hipMemcpyAsync(hs, A.st, sizeof(GenState), hipMemcpyDeviceToHost, s)) != CQK_OK)

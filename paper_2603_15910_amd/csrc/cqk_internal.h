@@ -41,10 +41,10 @@ struct GenState {
   double in_bytes;                // bytes per index of the caller's arrays
   int64_t n_src;                  // indices in the current source
   int64_t n_free;                 // finalize: free indices
-  int32_t status, iter, passes, mode, src, compact_next, stop_reason, max_iter;
+  int32_t status, iter, passes, mode, src, stop_reason, max_iter;
   int32_t compaction, trace_cap, ntrace, nblocks;
   uint32_t ticket;
-  int32_t pad_[3];
+  int32_t pad_[4];
 };
 
 // Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).
@@ -140,10 +140,11 @@ void fill_default_opts(cqk_opts* o);
 // 16-byte vector (2: FP64 inputs, 4: FP32 inputs).
 struct GenLayout {
   int G, NR, GF;
-  int64_t chunk;
+  int64_t chunk, region;
   size_t part_bytes, cnt_bytes, bytes;
 };
-GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction);
+// theta: the largest survivor fraction a compacted set may keep (1: any)
+GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta);
 
 // xw: the primal estimate of a warm start, or null (opts.lambda0_mode then
 // chooses the start)
