@@ -199,7 +199,8 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
   // becomes the source of the next pass
   const int side = (phi - r0 < 0.0) ? 0 : 1;
   const int o = P_SIDE + side * D_N;
-  const bool compacted = (st->compaction != CQK_COMPACT_OFF) && (phi != r0) && (t[o + D_DROP] == 0.0);
+  const bool compacted =
+      (st->compaction != CQK_COMPACT_OFF) && (phi != r0) && (t[o + D_DROP] == 0.0);
   if (compacted) {
     st->F += t[o + D_F];
     st->AF += t[o + D_AF];

@@ -59,6 +59,10 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
+constexpr int kPair = 2;  // adjacent tiles a wave reads per step of a pass over the caller's arrays
+// the general pass kernel reads a step's tiles one after the other (its
+// compaction state leaves no registers for both tiles' loads at once)
+constexpr bool kPairUnrollGeneral = false;
 constexpr int kStage = 128;  // LDS ring per wave, side and array for compaction
 constexpr int kPieceLog = 6;
 constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
@@ -187,6 +191,30 @@ struct SrcForm {
   }
 };
 
+// Runs tile(base, full) over one wave's tiles of TILE values in [0, count):
+// steps of P adjacent tiles starting at `first`, `stride` apart; full tiles
+// take the unguarded path, the tiles of the step that reaches `count` the
+// checked one.  Reading P adjacent tiles (4 KB of each array for P = 2 in
+// FP64) per step streams HBM faster than one tile per step.
+template <int P, bool UNROLL, typename F>
+__device__ __forceinline__ void for_tiles(int64_t count, int64_t first, int64_t stride,
+                                          int64_t TILE, F&& tile) {
+  int64_t base = first;
+  for (; base + P * TILE <= count; base += stride) {
+    if constexpr (UNROLL) {
+#pragma unroll
+      for (int p = 0; p < P; ++p) tile(base + p * TILE, std::true_type{});
+    } else {
+#pragma unroll 1
+      for (int p = 0; p < P; ++p) tile(base + p * TILE, std::true_type{});
+    }
+  }
+  for (int64_t b = base; b < count && b < base + P * TILE; b += TILE) {
+    if (b + TILE <= count) tile(b, std::true_type{});
+    else tile(b, std::false_type{});
+  }
+}
+
 // One wave streams its tiles.  With COMPACT each index is also classified
 // for both sides of the evaluation (see eval_index): the survivors of slot e
 // of every lane are staged per side in the wave's slice of LDS (ballot +
@@ -281,9 +309,7 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
       }
     }
   };
-  int64_t base = first;
-  for (; base + TILE <= count; base += stride) tile(base, std::true_type{});
-  if (base < count) tile(base, std::false_type{});
+  for_tiles<kPair, kPairUnrollGeneral>(count, first, stride, TILE, tile);
   if (lane == 0) acc.s[P_NIN] += (double)seen;
   if (COMPACT) {
 #pragma unroll
@@ -310,10 +336,11 @@ __device__ void bkpt_pass(const Src& src, int64_t count, int64_t first, int64_t 
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
-  for (int64_t base = first; base < count; base += stride) {
+  auto tile = [&](int64_t base, auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
     double c[E], s[E], bl[E], bu[E];
     double dummy = 0.0;
-    if (base + TILE <= count) {
+    if (FULL) {
       src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, dummy);
     } else {
 #pragma unroll
@@ -328,10 +355,11 @@ __device__ void bkpt_pass(const Src& src, int64_t count, int64_t first, int64_t 
 #pragma unroll
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
-        if (i + k < count) bkpt_index(ks, c[e], s[e], bl[e], bu[e], lam);
+        if (FULL || i + k < count) bkpt_index(ks, c[e], s[e], bl[e], bu[e], lam);
       }
     }
-  }
+  };
+  for_tiles<kPair, kPairUnrollGeneral>(count, first, stride, TILE, tile);
 }
 
 
@@ -380,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     SrcOrig<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
                    (const TIn*)A.u};
     constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrig<TIn>::V;
-    const int64_t first = (int64_t)rid * T, stride = nr * T;
+    const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
     if (mode != kModeEval)
       bkpt_pass(s, A.n, first, stride, lam, ks);
     else if (compact)
@@ -394,12 +422,14 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     SrcForm s{sb, sb + plane, sb + 2 * plane, sb + 3 * plane, pc};
     constexpr int64_t T = (int64_t)kWave * kUnroll * SrcForm::V;
     const int64_t count = A.cnt[src - 1][rid];
+    // the wave's own region, front to back
+    constexpr int64_t S = kPair * T;
     if (mode != kModeEval)
-      bkpt_pass(s, count, 0, T, lam, ks);
+      bkpt_pass(s, count, 0, S, lam, ks);
     else if (compact)
-      eval_pass<SrcForm, true>(s, count, 0, T, lam, lo, hi, theta, out, pc, oc, acc, stg);
+      eval_pass<SrcForm, true>(s, count, 0, S, lam, lo, hi, theta, out, pc, oc, acc, stg);
     else
-      eval_pass<SrcForm, false>(s, count, 0, T, lam, lo, hi, theta, nullptr, pc, nullptr, acc,
+      eval_pass<SrcForm, false>(s, count, 0, S, lam, lo, hi, theta, nullptr, pc, nullptr, acc,
                                 stg);
   }
 
@@ -464,9 +494,7 @@ __global__ __launch_bounds__(kBlock) void gen_first_pass_kernel(GenArgs A) {
     }
     seen += FULL ? T : std::min<int64_t>(T, count - base);
   };
-  int64_t base = (int64_t)rid * T;
-  for (; base + T <= count; base += nr * T) tile(base, std::true_type{});
-  if (base < count) tile(base, std::false_type{});
+  for_tiles<kPair, true>(count, (int64_t)rid * kPair * T, nr * kPair * T, T, tile);
   double v[6] = {acc.s[P_P], acc.s[P_A], acc.s[P_QP], acc.s[P_QM], acc.s[P_BAD],
                  lane == 0 ? (double)seen : 0.0};
   __shared__ double lds[6 * (kBlock / kWave)];
@@ -766,17 +794,18 @@ int choose_grid(int64_t n, int num_cus) {
 
 }  // namespace
 
-// G blocks of kWavesPerBlock waves.  A pass over the caller's arrays hands its
-// tiles (64 lanes x kUnroll vectors of `vec` values) to the NR waves
-// grid-stride, at most `tpw` tiles each (chunk = tpw tiles).  A wave keeps
-// at most theta * chunk + kPiece survivors of a side (eval_pass), so its
-// region in a compacted set holds that many values, rounded up to whole
-// pieces.  The primal recovery runs grid-stride on its own grid GF of
-// 4-vector tiles.  Workspace: partials | counts (3 x NR) | three compacted
-// sets (4 planes of NR x region doubles each, only with compaction).
+// G blocks of kWavesPerBlock waves.  A pass over the caller's arrays hands
+// its steps (kPair adjacent tiles of 64 lanes x kUnroll vectors of `vec`
+// values) to the NR waves grid-stride, at most `tpw` steps each (chunk = tpw
+// steps).  A wave keeps at most theta * chunk + kPiece survivors of a side
+// (eval_pass), so its region in a compacted set holds that many values,
+// rounded up to whole pieces.  The primal recovery runs grid-stride on its
+// own grid GF of 4-vector tiles.  Workspace: partials | counts (3 x NR) |
+// three compacted sets (4 planes of NR x region doubles each, only with
+// compaction).
 GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta) {
   GenLayout L{};
-  const int64_t T = (int64_t)kWave * kUnroll * vec;
+  const int64_t T = (int64_t)kWave * kUnroll * vec * kPair;
   const int G0 = choose_grid(n, num_cus);
   const int64_t ntiles = (n + T - 1) / T;
   const int64_t tpw = std::max<int64_t>(
