@@ -454,15 +454,22 @@ cqk_status cqk_project_simplex_batched_backward_f32(cqk_ctx* ctx, int32_t nseg,
  * short_first = 1 hands out the one-wave rows before the workgroup rows
  * (which always go longest first). */
 typedef struct cqk_batch_schedule {
-  int32_t small_per;        /* 4 or 8 */
-  int32_t blocks_per_cu;    /* 1 .. 8 */
-  int32_t short_first;      /* 0 or 1 */
-  int32_t reserved;         /* 0 */
+  int32_t small_per;        /* 4 or 8: rows of at most 64 * small_per values are
+                               solved by one wave from its registers */
+  int32_t blocks_per_cu;    /* 1 .. 8: persistent workgroups per compute unit */
+  int32_t short_first;      /* 0 or 1: one-wave rows handed out first */
+  int32_t medium_tiles;     /* 0 .. 64, batched simplex forward only: rows of
+                               at most 1024 * medium_tiles values (and more
+                               than 64 * small_per) are solved by one wave,
+                               tile after tile, four rows per workgroup; 0:
+                               every longer row gets a whole workgroup.
+                               Ignored by the other batched calls. */
 } cqk_batch_schedule;
 
 /* The schedule the context uses for one kind of batched call: which = 0
  * batched simplex forward, 1 its backward, 2 batched general CQK forward,
- * 3 its backward; a new context starts with {8, 4, 0, 0} for each.  Set
+ * 3 its backward; a new context starts with {8, 4, 1, 16} for the batched
+ * simplex forward and {8, 4, 0, 0} for the others.  Set
  * returns INVALID_ARG for a schedule outside the ranges above or another
  * `which`. */
 cqk_status cqk_get_batch_schedule(cqk_ctx* ctx, int32_t which, cqk_batch_schedule* out);
@@ -470,11 +477,12 @@ cqk_status cqk_set_batch_schedule(cqk_ctx* ctx, int32_t which,
                                   const cqk_batch_schedule* sched);
 
 /* Autotuner: runs cqk_project_simplex_batched_f32 on these rows under every
- * candidate schedule (small_per in {4, 8} x blocks_per_cu in {1..4} x
- * short_first in {0, 1}), `repeats` timed runs each after one warm-up, keeps
- * the fastest as the context's forward schedule and returns it with its
- * time in milliseconds (either pointer may be NULL).  x is overwritten.
- * Synchronises the stream; not for use under graph capture. */
+ * candidate schedule (small_per in {4, 8} x blocks_per_cu in {2, 3, 4, 6} x
+ * short_first in {0, 1} x medium_tiles in {0, 4, 8, 16, 32, 64}), `repeats` timed
+ * runs each after one warm-up, keeps the fastest as the context's forward
+ * schedule and returns it with its time in milliseconds (either pointer may
+ * be NULL).  x is overwritten.  Synchronises the stream; not for use under
+ * graph capture. */
 cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                 const float* y, const double* r, double r_scalar, float* x,
                                 int32_t repeats, cqk_batch_schedule* best, double* best_ms);

@@ -618,8 +618,9 @@ class Context:
         return sc.as_dict()
 
     def set_batch_schedule(self, small_per=8, blocks_per_cu=4, short_first=0, backward=False,
-                           general=False):
-        sc = L.cqk_batch_schedule(int(small_per), int(blocks_per_cu), int(short_first), 0)
+                           general=False, medium_tiles=0):
+        sc = L.cqk_batch_schedule(int(small_per), int(blocks_per_cu), int(short_first),
+                                  int(medium_tiles))
         st = cqk_set_batch_schedule(self.handle, (2 if general else 0) + (1 if backward else 0),
                                     sc)
         if st != CQK_OK:

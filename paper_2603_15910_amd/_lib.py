@@ -97,11 +97,11 @@ class cqk_batch_schedule(C.Structure):
         ("small_per", C.c_int32),
         ("blocks_per_cu", C.c_int32),
         ("short_first", C.c_int32),
-        ("reserved", C.c_int32),
+        ("medium_tiles", C.c_int32),
     ]
 
     def as_dict(self):
-        return {f[0]: getattr(self, f[0]) for f in self._fields_ if f[0] != "reserved"}
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
 
 
 class cqk_spg_opts(C.Structure):

@@ -45,7 +45,8 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kK = 16;               // values per lane per wave tile (workgroup rows)
 constexpr int kWTile = kWave * kK;   // 1024
 constexpr int kSurvW = 1024;         // LDS list slots per wave (value + index)
-constexpr int kNB = 24;              // length buckets (bucket 0: wave rows)
+constexpr int kNBW = 24;             // length buckets (bit length) of each row class
+constexpr int kNB = 2 * kNBW;        // wave rows 0 .. kNBW - 1, workgroup rows kNBW .. kNB - 1
 constexpr int kRefine = 8;
 constexpr int kMaxNewton = 100;
 
@@ -53,7 +54,8 @@ enum BatFlags : int32_t { kBadRadius = 1, kBadValue = 2, kInfeasible = 4, kNotCo
 
 struct BatArgs {
   int32_t nseg;
-  int32_t small_max;    // longest wave row
+  int32_t small_max;    // longest row solved from one wave's registers
+  int32_t med_max;      // longest row solved by one wave (tile by tile above small_max)
   int32_t short_first;  // 1: wave rows are handed out first
   const int64_t* off;
   const float* y;
@@ -76,26 +78,41 @@ constexpr int CTR_NLONG = 3 * kNB, CTR_NSHORT = 3 * kNB + 1, CTR_NITEMS = 3 * kN
               CTR_QUEUE = 3 * kNB + 3, CTR_FLAGS = 3 * kNB + 4,
               CTR_SURV = 3 * kNB + 6, CTR_OVER = 3 * kNB + 7, CTR_TOTAL = 3 * kNB + 8;
 
-__device__ __forceinline__ int bucket_of(int64_t L, int small_max) {
-  if (L <= small_max) return 0;
-  int b = 64 - __clzll((unsigned long long)L) - 8;  // bit length - 8
-  b = b < 1 ? 1 : b;
-  return b >= kNB ? kNB - 1 : b;
+// Length bucket of a row of L values: its bit length, in the wave-row range
+// if L <= wave_max, else in the workgroup-row range.
+__device__ __forceinline__ int bucket_of(int64_t L, int wave_max) {
+  int b = 64 - __clzll((unsigned long long)L);
+  b = b >= kNBW ? kNBW - 1 : b;
+  return (L <= wave_max) ? b : kNBW + b;
 }
 
 // Planning: the rows are listed by length bucket (workgroup rows longest
-// bucket first, then the wave rows), in row order inside a bucket, without
-// atomics: each block of kPBlock rows counts its buckets with ballots, then
-// each block places its rows after the rows of its bucket in earlier blocks.
+// bucket first, then the wave rows longest bucket first, so the four wave
+// rows of one work item have about the same length), in row order inside a
+// bucket, without atomics: each block of kPBlock rows counts its buckets
+// with ballots, then each block places its rows after the rows of its bucket
+// in earlier blocks.
 constexpr int kPBlock = 1024;
 constexpr int kPW = kPBlock / kWave;
+
+// Longest row one wave solves: the simplex forward's medium limit, else the
+// register limit.
+template <typename Args>
+__device__ __forceinline__ int wave_row_max(const Args& A) {
+  return A.small_max;
+}
+
+template <>
+__device__ __forceinline__ int wave_row_max<BatArgs>(const BatArgs& A) {
+  return A.med_max;
+}
 
 // length bucket of row s, -1 past the last row.  Args: the simplex or the
 // general form's argument record (both carry nseg, small_max, off and the
 // planning buffers).
 template <typename Args>
 __device__ __forceinline__ int plan_bucket(const Args& A, int s) {
-  return (s < A.nseg) ? bucket_of(A.off[s + 1] - A.off[s], A.small_max) : -1;
+  return (s < A.nseg) ? bucket_of(A.off[s + 1] - A.off[s], wave_row_max(A)) : -1;
 }
 
 template <typename Args>
@@ -130,8 +147,8 @@ __global__ __launch_bounds__(kPBlock) void bat_place_kernel(Args A) {
   const int nblk = gridDim.x;
   // bucket totals over all blocks and over the blocks before this one,
   // 32 threads per bucket
-  if (threadIdx.x < kNB * 32) {
-    const int k = threadIdx.x / 32, sub = threadIdx.x % 32;
+  for (int idx = threadIdx.x; idx < kNB * 32; idx += kPBlock) {
+    const int k = idx / 32, sub = idx % 32;
     int t = 0, p = 0;
     for (int q = sub; q < nblk; q += 32) {
       const int v = A.bhist[(size_t)q * kNB + k];
@@ -170,19 +187,24 @@ __global__ __launch_bounds__(kPBlock) void bat_place_kernel(Args A) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    // workgroup rows, longest bucket first, then the wave rows
+    // workgroup rows, longest bucket first, then the wave rows, longest first
     int acc = 0;
-    for (int k = kNB - 1; k >= 1; --k) {
+    for (int k = kNB - 1; k >= kNBW; --k) {
       const int t = base[k];
       base[k] = acc;
       acc += t;
     }
-    const int nshort = base[0];
-    base[0] = acc;
+    const int nlong = acc;
+    for (int k = kNBW - 1; k >= 0; --k) {
+      const int t = base[k];
+      base[k] = acc;
+      acc += t;
+    }
+    const int nshort = acc - nlong;
     if (blockIdx.x == 0) {
-      A.counters[CTR_NLONG] = acc;
+      A.counters[CTR_NLONG] = nlong;
       A.counters[CTR_NSHORT] = nshort;
-      A.counters[CTR_NITEMS] = acc + (nshort + kWaves - 1) / kWaves;
+      A.counters[CTR_NITEMS] = nlong + (nshort + kWaves - 1) / kWaves;
     }
   }
   __syncthreads();
@@ -336,11 +358,19 @@ __device__ __forceinline__ void load_wtile(const float* p, int64_t t0, int lane,
 #pragma unroll
       for (int k = 0; k < 4; ++k) o[4 * q + k] = r[q][k];
   } else {
+    // a part tile: whole vectors still move 16 bytes, the one that crosses
+    // the end value by value
 #pragma unroll
     for (int q = 0; q < kK / 4; ++q) {
       const int64_t i = t0 + q * kWave * 4 + lane * 4;
+      if (i + 4 <= n) {
+        const flt4u r = ld16(p + i);
 #pragma unroll
-      for (int k = 0; k < 4; ++k) o[4 * q + k] = (i + k < n) ? p[i + k] : 0.f;
+        for (int k = 0; k < 4; ++k) o[4 * q + k] = r[k];
+      } else {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) o[4 * q + k] = (i + k < n) ? p[i + k] : 0.f;
+      }
     }
   }
 }
@@ -402,6 +432,98 @@ __device__ __forceinline__ double wave_newton_lists(const BatLds& L, const int* 
   return lam;
 }
 
+// A wave's running state over its tiles of one row: the values kept so far
+// (count, sum, list length), the smallest bound found (each bound lam_J of
+// some set J, so >= lam*), the largest value and a NaN once a value is NaN
+// or infinite.
+struct WaveRun {
+  double c = 0.0, s = 0.0, lam = inf_d();
+  float vmx = -__builtin_huge_valf();
+  float badf = 0.f;
+  int nw = 0;
+};
+
+// One tile (values t0 .. t0 + 1023) of a row of n values for the calling
+// wave: x = 0 over the tile; on the wave's first tile of the row Algorithm 2
+// per lane with the wave's refinement, on a later one the running bound;
+// the values kept are appended with their positions to the wave's list
+// (sv, si; entries past kSurvW are counted, not stored).
+__device__ __forceinline__ void wave_row_tile(const float* y, float* x, int64_t n, int64_t t0,
+                                              double rd, WaveRun& R, float* sv, int32_t* si) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float v[kK];
+  uint32_t active = 0;
+  load_wtile(y, t0, lane, n, v);
+  if (t0 + kWTile <= n) {
+    // a tile wholly in the row: no per-value range tests
+    const flt4u z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < kK / 4; ++q) st16(x + t0 + q * kWave * 4 + lane * 4, z);
+    active = (1u << kK) - 1u;
+#pragma unroll
+    for (int e = 0; e < kK; ++e) {
+      R.badf += v[e] * 0.f;
+      R.vmx = fmaxf(R.vmx, v[e]);
+    }
+  } else {
+    // x is zero wherever the lists do not write it
+    zero_wtile(x, t0, lane, n);
+#pragma unroll
+    for (int q = 0; q < kK / 4; ++q) {
+      const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (i + k < n) {
+          active |= 1u << (4 * q + k);
+          R.badf += v[4 * q + k] * 0.f;
+          R.vmx = fmaxf(R.vmx, v[4 * q + k]);
+        }
+      }
+    }
+  }
+  // values at or below the wave's best bound so far are zero at the
+  // solution (v <= thr exactly when v + lam <= 0)
+  if (R.lam < inf_d()) {
+    const float thr = float_at_or_below(-R.lam);
+#pragma unroll
+    for (int e = 0; e < kK; ++e)
+      if (!(v[e] > thr)) active &= ~(1u << e);
+  }
+  if (__ballot(active != 0u) == 0) return;
+  double nk = 0.0, ks = 0.0;
+  uint32_t keep = 0;
+  if (R.c > 0.0) {
+    // a later tile: the running bound has already filtered it and every
+    // value left is kept; lam_J of everything kept so far becomes the
+    // bound below (again >= lam*)
+    keep = active;
+#pragma unroll
+    for (int e = 0; e < kK; ++e) {
+      nk += ((active >> e) & 1u) ? 1.0 : 0.0;
+      ks += ((active >> e) & 1u) ? (double)v[e] : 0.0;
+    }
+  } else {
+    keep = wave_tile_alg2(v, active, rd, R.c, R.s, R.lam, nk, ks);
+  }
+  if (__ballot(keep != 0u) == 0) return;
+#pragma unroll
+  for (int e = 0; e < kK; ++e) {
+    const bool kb = (keep >> e) & 1u;
+    const uint64_t m = __ballot(kb);
+    if (kb) {
+      const int pos = R.nw + lane_prefix(m);
+      if (pos < kSurvW) {
+        sv[pos] = v[e];
+        si[pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
+      }
+    }
+    R.nw += __popcll(m);
+  }
+  R.c += wave_sum(nk);
+  R.s += wave_sum(ks);
+  if (R.c > 0.0) R.lam = fmin(R.lam, (rd - R.s) / R.c);
+}
+
 // ---------------------------------------------------------------------------
 // One workgroup row.
 // ---------------------------------------------------------------------------
@@ -420,86 +542,13 @@ __device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n,
     }
     return;
   }
-  // wave-uniform running state: survivors kept, smallest bound found
-  double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
-  float vmx = -__builtin_huge_valf();
-  float badf = 0.f;  // NaN once a value is NaN or infinite
-  int nw = 0;
+  WaveRun R;
   const int64_t ntiles = (n + kWTile - 1) / kWTile;
-  for (int64_t t = wid; t < ntiles; t += kWaves) {
-    const int64_t t0 = t * kWTile;
-    float v[kK];
-    uint32_t active = 0;
-    load_wtile(y, t0, lane, n, v);
-    if (t0 + kWTile <= n) {
-      // a tile wholly in the row: no per-value range tests
-      const flt4u z = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int q = 0; q < kK / 4; ++q) st16(x + t0 + q * kWave * 4 + lane * 4, z);
-      active = (1u << kK) - 1u;
-#pragma unroll
-      for (int e = 0; e < kK; ++e) {
-        badf += v[e] * 0.f;
-        vmx = fmaxf(vmx, v[e]);
-      }
-    } else {
-      // x is zero wherever the lists below do not write it
-      zero_wtile(x, t0, lane, n);
-#pragma unroll
-      for (int q = 0; q < kK / 4; ++q) {
-        const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          if (i + k < n) {
-            active |= 1u << (4 * q + k);
-            badf += v[4 * q + k] * 0.f;
-            vmx = fmaxf(vmx, v[4 * q + k]);
-          }
-        }
-      }
-    }
-    // values at or below the wave's best bound so far are zero at the
-    // solution (v <= thr exactly when v + lam_min <= 0)
-    if (lam_min < inf_d()) {
-      const float thr = float_at_or_below(-lam_min);
-#pragma unroll
-      for (int e = 0; e < kK; ++e)
-        if (!(v[e] > thr)) active &= ~(1u << e);
-    }
-    if (__ballot(active != 0u) == 0) continue;
-    double nk = 0.0, ks = 0.0;
-    uint32_t keep = 0;
-    if (run_c > 0.0) {
-      // a later tile: the running bound has already filtered it and every
-      // value left is kept; lam_J of everything kept so far becomes the
-      // bound below (again >= lam*)
-      keep = active;
-#pragma unroll
-      for (int e = 0; e < kK; ++e) {
-        nk += ((active >> e) & 1u) ? 1.0 : 0.0;
-        ks += ((active >> e) & 1u) ? (double)v[e] : 0.0;
-      }
-    } else {
-      keep = wave_tile_alg2(v, active, rd, run_c, run_s, lam_min, nk, ks);
-    }
-    if (__ballot(keep != 0u) == 0) continue;
-#pragma unroll
-    for (int e = 0; e < kK; ++e) {
-      const bool kb = (keep >> e) & 1u;
-      const uint64_t m = __ballot(kb);
-      if (kb) {
-        const int pos = nw + lane_prefix(m);
-        if (pos < kSurvW) {
-          L.sv[wid][pos] = v[e];
-          L.si[wid][pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
-        }
-      }
-      nw += __popcll(m);
-    }
-    run_c += wave_sum(nk);
-    run_s += wave_sum(ks);
-    if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
-  }
+  for (int64_t t = wid; t < ntiles; t += kWaves)
+    wave_row_tile(y, x, n, t * kWTile, rd, R, L.sv[wid], L.si[wid]);
+  const double run_c = R.c, run_s = R.s, lam_min = R.lam;
+  const float vmx = R.vmx, badf = R.badf;
+  const int nw = R.nw;
   const double wbad = wave_sum((badf == 0.f) ? 0.0 : 1.0);
   const double wmax = wave_max((double)vmx);
   if (lane == 0) {
@@ -599,6 +648,121 @@ __device__ void solve_long_row(const BatArgs& A, int s, int64_t base, int64_t n,
     if (A.lam_out) A.lam_out[s] = lam;
     if (A.nfree_out) A.nfree_out[s] = (int32_t)nft;
     atomicAdd(&A.counters[CTR_SURV], ntot);
+  }
+}
+
+// Algorithm 4 from lam (>= lam*) on one wave's LDS list of n values.
+__device__ __forceinline__ double wave_newton_list(const float* lv, int n, double rd, double lam) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double prev_c = -1.0;
+  for (int it = 0; it < kMaxNewton; ++it) {
+    double cc = 0.0, ss = 0.0, ph = 0.0;
+    for (int i = lane; i < n; i += kWave) {
+      const double v = (double)lv[i];
+      const double z = v + lam;
+      if (z > 0.0) {
+        cc += 1.0;
+        ss += v;
+        ph += z;
+      }
+    }
+    cc = wave_sum(cc);
+    ss = wave_sum(ss);
+    ph = wave_sum(ph);
+    if (cc == prev_c) break;
+    if (it > 0 && ph <= rd) break;
+    if (cc == 0.0) break;
+    const double nl = (rd - ss) / cc;
+    if (!(nl < lam)) break;
+    prev_c = cc;
+    lam = nl;
+  }
+  return lam;
+}
+
+// ---------------------------------------------------------------------------
+// One medium row (64 * SP < n <= med_max): one wave takes every tile of the
+// row, as each wave of a workgroup row takes every fourth, then runs
+// Algorithm 4 on its own list.  No workgroup barrier: the four waves of a
+// work item solve four rows of about the same length at once.
+// ---------------------------------------------------------------------------
+__device__ void solve_medium_row(const BatArgs& A, int s, int64_t base, int64_t n, BatLds& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const double rd = row_radius(A, s);
+  const float* y = A.y + base;
+  float* x = A.x + base;
+  if (!(rd >= 0.0) || !(rd < inf_d())) {
+    for (int64_t i = lane; i < n; i += kWave) x[i] = 0.f;
+    if (lane == 0) {
+      atomicOr(&A.counters[CTR_FLAGS], kBadRadius);
+      if (A.lam_out) A.lam_out[s] = __builtin_nan("");
+      if (A.nfree_out) A.nfree_out[s] = 0;
+    }
+    return;
+  }
+  WaveRun R;
+  const int64_t ntiles = (n + kWTile - 1) / kWTile;
+  for (int64_t t = 0; t < ntiles; ++t)
+    wave_row_tile(y, x, n, t * kWTile, rd, R, L.sv[wid], L.si[wid]);
+  const bool bad = wave_sum((R.badf == 0.f) ? 0.0 : 1.0) > 0.0;
+  if (bad || rd == 0.0) {
+    // x is already zero
+    if (lane == 0) {
+      if (bad) atomicOr(&A.counters[CTR_FLAGS], kBadValue);
+      if (A.lam_out) A.lam_out[s] = bad ? __builtin_nan("") : 0.0;
+      if (A.nfree_out) A.nfree_out[s] = 0;
+    }
+    return;
+  }
+  double lam = (R.c > 0.0) ? fmin((rd - R.s) / R.c, R.lam) : R.lam;
+  double nf = 0.0;
+  const bool over = R.nw > kSurvW;
+  if (over) {
+    // the list overflowed: Algorithm 4 over the row itself (re-read)
+    double prev_c = -1.0;
+    for (int it = 0; it < kMaxNewton; ++it) {
+      double cc = 0.0, ss = 0.0, ph = 0.0;
+      for (int64_t i = lane; i < n; i += kWave) {
+        const double yv = (double)y[i];
+        const double z = yv + lam;
+        if (z > 0.0) {
+          cc += 1.0;
+          ss += yv;
+          ph += z;
+        }
+      }
+      cc = wave_sum(cc);
+      ss = wave_sum(ss);
+      ph = wave_sum(ph);
+      if (cc == prev_c) break;
+      if (it > 0 && ph <= rd) break;
+      if (cc == 0.0) break;
+      const double nl = (rd - ss) / cc;
+      if (!(nl < lam)) break;
+      prev_c = cc;
+      lam = nl;
+    }
+    for (int64_t i = lane; i < n; i += kWave) {
+      const float o = (float)fmax((double)y[i] + lam, 0.0);
+      nf += (o > 0.f) ? 1.0 : 0.0;
+      x[i] = o;
+    }
+  } else {
+    lam = wave_newton_list(L.sv[wid], R.nw, rd, lam);
+    // x for the list; every other x of the row is already zero
+    for (int i = lane; i < R.nw; i += kWave) {
+      const float o = (float)fmax((double)L.sv[wid][i] + lam, 0.0);
+      x[L.si[wid][i]] = o;
+      nf += (o > 0.f) ? 1.0 : 0.0;
+    }
+  }
+  nf = wave_sum(nf);
+  if (lane == 0) {
+    if (A.lam_out) A.lam_out[s] = lam;
+    if (A.nfree_out) A.nfree_out[s] = (int32_t)nf;
+    atomicAdd(&A.counters[CTR_SURV], R.nw);
+    if (over) atomicAdd(&A.counters[CTR_OVER], 1);
   }
 }
 
@@ -759,7 +923,9 @@ __global__ __launch_bounds__(kBlock, 3) void bat_solve_kernel(BatArgs A) {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
       if (k < nshort) {
         const size_t e = (size_t)nlong + k;
-        solve_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+        const int64_t Lr = A.lrow[2 * e + 1];
+        if (Lr <= A.small_max) solve_short_row<SP>(A, A.list[e], A.lrow[2 * e], Lr);
+        else solve_medium_row(A, A.list[e], A.lrow[2 * e], Lr, L);
       }
     }
     __syncthreads();
@@ -1451,14 +1617,17 @@ void plan(cqk_ctx* ctx, const Args& A) {
   hipLaunchKernelGGL(bat_place_kernel<Args>, dim3(gb), dim3(kPBlock), 0, s, A);
 }
 
-void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A) {
+// medium: whether rows above the register limit and up to medium_tiles tiles
+// are solved by one wave (the simplex forward only)
+void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A, bool medium) {
   A->small_max = kWave * sc.small_per;
+  A->med_max = medium ? std::max(A->small_max, sc.medium_tiles * kWTile) : A->small_max;
   A->short_first = sc.short_first;
 }
 
 // Queues one forward call under schedule sc.
 void launch_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
-  apply_schedule(sc, &A);
+  apply_schedule(sc, &A, true);
   plan(ctx, A);
   const dim3 grid(persistent_grid(ctx, sc, A.nseg));
   if (sc.small_per == 4)
@@ -1468,7 +1637,7 @@ void launch_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
 }
 
 void launch_backward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
-  apply_schedule(sc, &A);
+  apply_schedule(sc, &A, false);
   plan(ctx, A);
   const dim3 grid(persistent_grid(ctx, sc, A.nseg));
   if (sc.small_per == 4)
@@ -1513,6 +1682,18 @@ BatArgs backward_args(int32_t nseg, const int64_t* offsets, const float* x, cons
 }
 
 // The candidate schedules the tuner times.
+// The simplex forward's candidates: also the medium-row limit (medium_tiles,
+// in tiles of 1024 values; 0: none).
+int candidate_schedules_fwd(cqk_batch_schedule* out, int cap) {
+  int k = 0;
+  for (int sp : {4, 8})
+    for (int bpc : {2, 3, 4, 6})
+      for (int sf : {0, 1})
+        for (int med : {0, 4, 8, 16, 32, 64})
+          if (k < cap) out[k++] = cqk_batch_schedule{sp, bpc, sf, med};
+  return k;
+}
+
 int candidate_schedules(cqk_batch_schedule* out, int cap) {
   int k = 0;
   for (int sp : {4, 8})
@@ -1780,10 +1961,10 @@ cqk_status tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
 
 bool valid_schedule(const cqk_batch_schedule& sc) {
   return (sc.small_per == 4 || sc.small_per == 8) && sc.blocks_per_cu >= 1 &&
-         sc.blocks_per_cu <= 8 && (sc.short_first == 0 || sc.short_first == 1);
+         sc.blocks_per_cu <= 8 && (sc.short_first == 0 || sc.short_first == 1) &&
+         sc.medium_tiles >= 0 && sc.medium_tiles <= 64;
 }
 
-cqk_batch_schedule default_schedule() { return cqk_batch_schedule{8, 4, 0, 0}; }
 
 // The info record of the last batched forward call from the host copy of its
 // counters.
@@ -1910,8 +2091,8 @@ cqk_status tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets, 
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
   const BatArgs A = forward_args(nseg, offsets, y, r, r_scalar, x, nullptr, nullptr, w);
-  cqk_batch_schedule cand[32];
-  const int nc = candidate_schedules(cand, 32);
+  cqk_batch_schedule cand[128];
+  const int nc = candidate_schedules_fwd(cand, 128);
   int bi = 0;
   double ms = 0.0;
   st = tune(ctx, cand, nc, repeats,
