@@ -458,12 +458,13 @@ typedef struct cqk_batch_schedule {
                                solved by one wave from its registers */
   int32_t blocks_per_cu;    /* 1 .. 8: persistent workgroups per compute unit */
   int32_t short_first;      /* 0 or 1: one-wave rows handed out first */
-  int32_t medium_tiles;     /* 0 .. 64, batched simplex forward only: rows of
-                               at most 1024 * medium_tiles values (and more
-                               than 64 * small_per) are solved by one wave,
-                               tile after tile, four rows per workgroup; 0:
-                               every longer row gets a whole workgroup.
-                               Ignored by the other batched calls. */
+  int32_t medium_tiles;     /* 0 .. 64, batched simplex (forward and
+                               backward) only: rows of at most 1024 *
+                               medium_tiles values (and more than 64 *
+                               small_per) are solved by one wave, tile after
+                               tile, four rows per workgroup; 0: every longer
+                               row gets a whole workgroup.  Ignored by the
+                               batched general CQK. */
 } cqk_batch_schedule;
 
 /* The schedule the context uses for one kind of batched call: which = 0
@@ -487,7 +488,8 @@ cqk_status cqk_tune_batched_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offse
                                 const float* y, const double* r, double r_scalar, float* x,
                                 int32_t repeats, cqk_batch_schedule* best, double* best_ms);
 /* The same for the backward call (x: forward output, g: upstream gradient,
- * grad_y overwritten); sets the context's backward schedule. */
+ * grad_y overwritten; the same candidates); sets the context's backward
+ * schedule. */
 cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* offsets,
                                          const float* x, const float* g, float* grad_y,
                                          int32_t repeats, cqk_batch_schedule* best,

@@ -935,6 +935,49 @@ __global__ __launch_bounds__(kBlock, 3) void bat_solve_kernel(BatArgs A) {
 // ---------------------------------------------------------------------------
 // Backward: grad_y = [x > 0](g - mean_S g), grad_r = mean_S g.
 // ---------------------------------------------------------------------------
+// One tile (values t0 .. t0 + 1023) of a row of n values for the calling
+// wave's VJP: grad_y = 0 over the tile, the support's count and sum of g
+// added to (cnt, sum), its (g, position) pairs appended to the wave's list
+// (sv, si; entries past kSurvW are counted, not stored).
+__device__ __forceinline__ void vjp_row_tile(const float* x, const float* g, float* gy, int64_t n,
+                                             int64_t t0, double& cnt, double& sum, int& nw,
+                                             float* sv, int32_t* si) {
+  const int lane = threadIdx.x & (kWave - 1);
+  float xs[kK], gs[kK];
+  uint32_t sup = 0;
+  load_wtile(x, t0, lane, n, xs);
+  load_wtile(g, t0, lane, n, gs);
+  // grad_y is zero off the support
+  zero_wtile(gy, t0, lane, n);
+#pragma unroll
+  for (int q = 0; q < kK / 4; ++q) {
+    const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = 4 * q + k;
+      if (i + k < n && xs[e] > 0.f) {
+        sup |= 1u << e;
+        cnt += 1.0;
+        sum += (double)gs[e];
+      }
+    }
+  }
+  if (__ballot(sup != 0u) == 0) return;
+#pragma unroll
+  for (int e = 0; e < kK; ++e) {
+    const bool kb = (sup >> e) & 1u;
+    const uint64_t m = __ballot(kb);
+    if (kb) {
+      const int pos = nw + lane_prefix(m);
+      if (pos < kSurvW) {
+        sv[pos] = gs[e];
+        si[pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
+      }
+    }
+    nw += __popcll(m);
+  }
+}
+
 __device__ void vjp_long_row(const BatArgs& A, int s, int64_t base, int64_t n, BatLds& L) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -944,42 +987,8 @@ __device__ void vjp_long_row(const BatArgs& A, int s, int64_t base, int64_t n, B
   double cnt = 0.0, sum = 0.0;
   int nw = 0;
   const int64_t ntiles = (n + kWTile - 1) / kWTile;
-  for (int64_t t = wid; t < ntiles; t += kWaves) {
-    const int64_t t0 = t * kWTile;
-    float xs[kK], gs[kK];
-    uint32_t sup = 0;
-    load_wtile(x, t0, lane, n, xs);
-    load_wtile(g, t0, lane, n, gs);
-    // grad_y is zero off the support
-    zero_wtile(gy, t0, lane, n);
-#pragma unroll
-    for (int q = 0; q < kK / 4; ++q) {
-      const int64_t i = t0 + (int64_t)q * kWave * 4 + (int64_t)lane * 4;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int e = 4 * q + k;
-        if (i + k < n && xs[e] > 0.f) {
-          sup |= 1u << e;
-          cnt += 1.0;
-          sum += (double)gs[e];
-        }
-      }
-    }
-    if (__ballot(sup != 0u) == 0) continue;
-#pragma unroll
-    for (int e = 0; e < kK; ++e) {
-      const bool kb = (sup >> e) & 1u;
-      const uint64_t m = __ballot(kb);
-      if (kb) {
-        const int pos = nw + lane_prefix(m);
-        if (pos < kSurvW) {
-          L.sv[wid][pos] = gs[e];
-          L.si[wid][pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
-        }
-      }
-      nw += __popcll(m);
-    }
-  }
+  for (int64_t t = wid; t < ntiles; t += kWaves)
+    vjp_row_tile(x, g, gy, n, t * kWTile, cnt, sum, nw, L.sv[wid], L.si[wid]);
   cnt = wave_sum(cnt);
   sum = wave_sum(sum);
   if (lane == 0) {
@@ -1006,6 +1015,31 @@ __device__ void vjp_long_row(const BatArgs& A, int s, int64_t base, int64_t n, B
     for (int i = lane; i < nw; i += kWave) gy[L.si[wid][i]] = L.sv[wid][i] - gb;
   }
   if (threadIdx.x == 0 && A.gr) A.gr[s] = gbar;
+}
+
+// A medium row's VJP (64 * SP < n <= med_max) by one wave, tile after tile.
+__device__ void vjp_medium_row(const BatArgs& A, int s, int64_t base, int64_t n, BatLds& L) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const float* x = A.x + base;
+  const float* g = A.g + base;
+  float* gy = A.gy + base;
+  double cnt = 0.0, sum = 0.0;
+  int nw = 0;
+  const int64_t ntiles = (n + kWTile - 1) / kWTile;
+  for (int64_t t = 0; t < ntiles; ++t)
+    vjp_row_tile(x, g, gy, n, t * kWTile, cnt, sum, nw, L.sv[wid], L.si[wid]);
+  const double C = wave_sum(cnt), Sg = wave_sum(sum);
+  const double gbar = (C > 0.0) ? Sg / C : 0.0;
+  const float gb = (float)gbar;
+  if (nw > kSurvW) {
+    // the support did not fit the list: a second pass over the row
+    for (int64_t i = lane; i < n; i += kWave)
+      if (x[i] > 0.f) gy[i] = g[i] - gb;
+  } else {
+    for (int i = lane; i < nw; i += kWave) gy[L.si[wid][i]] = L.sv[wid][i] - gb;
+  }
+  if (lane == 0 && A.gr) A.gr[s] = gbar;
 }
 
 template <int SP>
@@ -1067,7 +1101,9 @@ __global__ __launch_bounds__(kBlock) void bat_vjp_kernel(BatArgs A) {
       const int k = idx * kWaves + (int)(threadIdx.x / kWave);
       if (k < nshort) {
         const size_t e = (size_t)nlong + k;
-        vjp_short_row<SP>(A, A.list[e], A.lrow[2 * e], A.lrow[2 * e + 1]);
+        const int64_t Lr = A.lrow[2 * e + 1];
+        if (Lr <= A.small_max) vjp_short_row<SP>(A, A.list[e], A.lrow[2 * e], Lr);
+        else vjp_medium_row(A, A.list[e], A.lrow[2 * e], Lr, L);
       }
     }
     __syncthreads();
@@ -1617,17 +1653,17 @@ void plan(cqk_ctx* ctx, const Args& A) {
   hipLaunchKernelGGL(bat_place_kernel<Args>, dim3(gb), dim3(kPBlock), 0, s, A);
 }
 
-// medium: whether rows above the register limit and up to medium_tiles tiles
-// are solved by one wave (the simplex forward only)
-void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A, bool medium) {
+// Rows above the register limit and up to medium_tiles tiles are solved by
+// one wave.
+void apply_schedule(const cqk_batch_schedule& sc, BatArgs* A) {
   A->small_max = kWave * sc.small_per;
-  A->med_max = medium ? std::max(A->small_max, sc.medium_tiles * kWTile) : A->small_max;
+  A->med_max = std::max(A->small_max, sc.medium_tiles * kWTile);
   A->short_first = sc.short_first;
 }
 
 // Queues one forward call under schedule sc.
 void launch_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
-  apply_schedule(sc, &A, true);
+  apply_schedule(sc, &A);
   plan(ctx, A);
   const dim3 grid(persistent_grid(ctx, sc, A.nseg));
   if (sc.small_per == 4)
@@ -1637,7 +1673,7 @@ void launch_forward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
 }
 
 void launch_backward(cqk_ctx* ctx, const cqk_batch_schedule& sc, BatArgs A) {
-  apply_schedule(sc, &A, false);
+  apply_schedule(sc, &A);
   plan(ctx, A);
   const dim3 grid(persistent_grid(ctx, sc, A.nseg));
   if (sc.small_per == 4)
@@ -1682,7 +1718,7 @@ BatArgs backward_args(int32_t nseg, const int64_t* offsets, const float* x, cons
 }
 
 // The candidate schedules the tuner times.
-// The simplex forward's candidates: also the medium-row limit (medium_tiles,
+// The batched simplex candidates: also the medium-row limit (medium_tiles,
 // in tiles of 1024 values; 0: none).
 int candidate_schedules_fwd(cqk_batch_schedule* out, int cap) {
   int k = 0;
@@ -2112,8 +2148,8 @@ cqk_status tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* 
   cqk_status st = bat_workspace(ctx, nseg, &w);
   if (st != CQK_OK) return st;
   const BatArgs A = backward_args(nseg, offsets, x, g, grad_y, nullptr, w);
-  cqk_batch_schedule cand[32];
-  const int nc = candidate_schedules(cand, 32);
+  cqk_batch_schedule cand[128];
+  const int nc = candidate_schedules_fwd(cand, 128);
   int bi = 0;
   double ms = 0.0;
   st = tune(ctx, cand, nc, repeats,

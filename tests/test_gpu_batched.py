@@ -297,7 +297,7 @@ def test_medium_rows_match_oracle(ctx, sp, bpc, mt):
     off[1:] = np.cumsum(lens)
     y = (3.0 * W.simplex_input(int(off[-1]), 22, "normal", np.float32)).astype(np.float32)
     ctx.set_batch_schedule(sp, bpc, 0, medium_tiles=mt)
-    ctx.set_batch_schedule(sp, bpc, 0, backward=True)
+    ctx.set_batch_schedule(sp, bpc, 0, backward=True, medium_tiles=mt)
     try:
         x, lam, nf, info = _run(ctx, off, y)
         assert info["status"] == 0, info
