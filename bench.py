@@ -698,7 +698,7 @@ def main():
                    "n": n, "seed": 1},
         "roofline": {
             "bound": "hbm",
-            "kernel": "gen_pass_kernel<double> (evaluation pass)",
+            "kernel": "gen_first_pass_kernel + gen_pass_kernel <double> (evaluation passes)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
