@@ -335,16 +335,16 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   int64_t written = 0;
   bool traced = false;  // this wave has run Algorithm 2 on a tile
   const uint32_t amask = l1 ? 0x7FFFFFFFu : 0xFFFFFFFFu;
+  // -lam_min rounded down into TIn, recomputed only when lam_min moves
+  TIn thr = -(TIn)__builtin_huge_val();
+  double thr_of = 0.0;
+  bool thr_set = false;
   // One tile; `full` (a tile wholly in range) is known at compile time, so
   // the in-range tests of the other tiles cost nothing here.
-  auto tile = [&](const int64_t base, auto full_tag) {
+  // yv: the tile's values, loaded by the caller
+  auto tile = [&](const int64_t base, auto full_tag, const TIn* yv) {
     constexpr bool full = decltype(full_tag)::value;
-    TIn yv[K];
     TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
-    if constexpr (full)
-      load_tile_full<TIn, NL>(y, base, lane, yv);
-    else
-      load_tile<TIn, NL>(y, base, lane, count, yv);
     uint32_t inI = 0xFFFFFFFFu;  // the values Algorithm 2 may use
     if constexpr (WARM) {
       TIn xv[K];
@@ -390,7 +390,13 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     // at the solution: only the rest enters Algorithm 2.  The threshold is
     // rounded down into TIn, so the comparison never drops a value it must
     // keep.
-    const TIn thr = round_down_to<TIn>(-lam_min);
+    if (!thr_set || lam_min != thr_of) {
+      thr = round_down_to<TIn>(-lam_min);
+      thr_of = lam_min;
+      thr_set = true;
+    }
+    // most tiles hold no value above it: one test on the lanes' maxima
+    if (__ballot(tmax > thr) == 0) return;
     uint32_t active = 0;
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -521,11 +527,16 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
     run_s += wave_sum(ks);
     if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
   };
-  for (int64_t base = (int64_t)rid * TILE; base < count; base += nr * TILE) {
-    if (base + TILE <= count)
-      tile(base, std::true_type{});
-    else
-      tile(base, std::false_type{});
+  const int64_t stride = nr * TILE;
+  for (int64_t base = (int64_t)rid * TILE; base < count; base += stride) {
+    TIn ycur[K];
+    if (base + TILE <= count) {
+      load_tile_full<TIn, NL>(y, base, lane, ycur);
+      tile(base, std::true_type{}, ycur);
+    } else {
+      load_tile<TIn, NL>(y, base, lane, count, ycur);
+      tile(base, std::false_type{}, ycur);
+    }
   }
   if (lane == 0) {
     acc[C_CNT] = run_c;
