@@ -80,7 +80,9 @@ typedef enum cqk_lambda0_mode {
   CQK_LAMBDA0_ZERO = 0,     /* lam_0 = 0 */
   CQK_LAMBDA0_FORMULA = 1,  /* lam_0 = (r - s)/q over all indices, eq. (CQKlambda0) */
   CQK_LAMBDA0_CONDAT = 2,   /* simplex / l1 only: Algorithm 2 run per thread
-                               chunk, merged by eq. (lambdaJ) (Section 4) */
+                               chunk on a sample of y, merged by eq. (lambdaJ)
+                               (Section 4), then one pass over y that keeps
+                               the values above the merged bound */
   CQK_LAMBDA0_USER = 3      /* lam_0 = opts->lambda0_user */
 } cqk_lambda0_mode;
 
@@ -191,21 +193,22 @@ cqk_status cqk_ctx_last_info(cqk_ctx* ctx, cqk_info* info);
 /* Copy up to `cap` trace records of the last call into host memory `out`;
  * *count receives the number recorded.
  * A simplex / l1 call with the CONDAT start and opts->trace = 1 writes one
- * kind-7 record first: lane 0 of the first wave ran Algorithm 2 (Section
- * 2.2, the per-chunk form of Section 4) on the values of the tile at index 0
- * it holds, value e (e = 0..15, ascending in y) being y[(e / V) * 64 * V +
+ * kind-7 record first: lane 0 of the first sample wave ran Algorithm 2
+ * (Section 2.2, the per-chunk form of Section 4) on the values of the tile at
+ * index 0 it holds, value e (e = 0..15, ascending in y) being y[(e / V) * 64 * V +
  * e % V] with V = 16 / sizeof(element).  Fields: n_in = mask of the values
  * above the wave's filter (those Algorithm 2 scanned, in order of e), n_out =
  * mask of its final set J, compacted = |J|, phi = sum of J (of |y| for l1),
  * lam = (r - phi) / |J| (Algorithm 2's bound), slope = the filter threshold,
  * lo = the wave's bound after merging and refining, source = mask of the
- * values of J kept as survivors (v + min(lam, lo) > 0; every other value of
- * the tile is fixed at zero), hi = 0 (the tile's index). */
+ * values of J that bound keeps (v + min(lam, lo) > 0; every other value of
+ * the tile is zero at the solution), hi = 0 (the tile's index). */
 cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count);
 /* Kernel time in milliseconds of each grid pass of the last single-instance
  * call made with opts->timing = 1 and sync = 1 (cqk_solve_*,
- * cqk_project_*), in the order the passes were queued: the lambda_0 or
- * Algorithm 2 pass if any, then the Newton passes, including those queued
+ * cqk_project_*), in the order the passes were queued: the lambda_0 pass
+ * or the Algorithm 2 sample and filtering passes if any, then the Newton
+ * passes, including those queued
  * after the loop had stopped, which return at once.  The x-writing pass is
  * not included (info->finalize_ms).  Copies min(cap, count) values; *count
  * receives the number of passes.  The list is refilled whenever a

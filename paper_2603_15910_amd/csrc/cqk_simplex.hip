@@ -18,13 +18,19 @@
 // later passes stream those regions.
 //
 // Kernels:
-//   spx_condat_kernel       one read of y (and x = 0 written over it): on a
-//                           wave's first tile with values above its bound
-//                           every thread runs Algorithm 2 on 16
-//                           register-resident values and the wave merges the
-//                           lanes' sets into lam_J bounds and refines them;
-//                           later tiles keep every value above the running
-//                           bound (wave reductions only, no barriers).
+//   spx_condat_sample_kernel  Algorithm 2 on a sample of up to 1024 tiles
+//                           spread evenly over y: every thread runs it on 16
+//                           register-resident values above the tile's first
+//                           bound, the wave merges the lanes' sets into lam_J
+//                           bounds and refines them; block records of the
+//                           smallest bound and of the kept sets' counts and
+//                           sums.
+//   spx_condat_kernel       one read of y (and x = 0 written over it),
+//                           starting from the sample's bound: each wave keeps
+//                           every value above its running bound, which the
+//                           kept values lower further (wave reductions only,
+//                           no barriers); a tile with no value above it costs
+//                           one test.
 //   spx_condat_merge_kernel lam_0 = the smallest bound any wave found and the
 //                           bound of the union of every surviving set.
 //   spx_pass_kernel<MULTI>  right after the start: the survivors' counts and
@@ -60,7 +66,7 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block kernels (reductions, the tail loop)
 constexpr int kWaves = kBlock / kWave;
 constexpr int kCondatK = 16;   // values per lane per tile in Algorithm 2
-constexpr int kRefine = 8;     // refinement rounds on a wave's first kept tile
+constexpr int kRefine = 8;     // refinement rounds on a sample tile
 constexpr int kTailBytes = 128 * 1024;  // LDS copy of the set the tail loop runs on
 constexpr int kCand = 12;               // start refinement candidates
 
@@ -87,6 +93,12 @@ struct SpxArgs {
   double* partials;
   SpxState* st;
   cqk_trace_rec* trace;
+  // Algorithm 2 sample: samp_waves waves over samp_ntiles tiles of y; its
+  // block records (samp_blocks of them, value-major)
+  double* samp;
+  int64_t samp_ntiles;
+  int32_t samp_waves;
+  int32_t samp_blocks;
   // sparse output (x is null then)
   uint32_t* bm;      // one bit per index, ceil(n/32) words
   int64_t nwords;
@@ -288,18 +300,29 @@ __device__ __forceinline__ void zero_tile(TIn* x, int64_t base, int lane, int64_
   }
 }
 
-// Partial record of the Algorithm 2 kernel.
+// Partial record of the streaming Algorithm 2 kernel.
 // C_CNTI, C_SUMI: the kept values of a warm start's support I.
 enum { C_CNT = 0, C_SUM, C_ABS, C_BAD, C_NOUT, C_CNTI, C_SUMI, C_NSUM };
 constexpr int C_NPART = C_NSUM + 3;  // + min lam, max v, max v over I
+// Block record of the sample kernel (value-major, like the partial records):
+// the smallest bound its waves found, and the count and sum of the sets they
+// kept.
+enum { SM_LAM = 0, SM_CNT, SM_SUM, SM_N };
+constexpr int kSampleWaves = 1024;  // tiles in the sample, at most
 
-// WARM: also the warm start of Section 3.1 from a primal estimate xbar, with
-// I = {xbar > 0} (l1: xbar != 0).  The kernel runs as without it: every bound
-// it finds is lam_J of some non-empty J, so it fixes values at zero whatever
-// J is.  It also sums the kept values of I and takes the largest value of I,
-// from which the merge forms the estimate's lam_J.
-template <typename TIn, typename TA, bool WARM>
-__global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
+// Algorithm 2 on a sample of y (Section 2.2, Section 4).  Wave w of the ns
+// sample waves takes tile floor(w * ntiles / ns), so the sample is spread
+// evenly over y and holds distinct tiles when ntiles >= ns.  The wave's first
+// bound is lam_J of the tile's largest value alone (Algorithm 2's first set);
+// each thread runs Algorithm 2 on its K values above that bound, and the wave
+// merges the lanes' sets into lam_J of their union and refines it with
+//   lam <- lam_J'  with  J' = {j in J : y_j + lam > 0},
+// each step of which can only lower lam (Algorithm 4's step on the tile's own
+// sub-problem).  Every bound is lam_J of a non-empty J, hence >= lam*
+// (eq. (lambdaJ)), and so is lam_J of the union of the waves' final sets,
+// which the streaming kernel forms from the block records.
+template <typename TIn, typename TA>
+__global__ __launch_bounds__(kBlock) void spx_condat_sample_kernel(SpxArgs A) {
   SpxState* st = A.st;
   if (st->status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
@@ -308,6 +331,164 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   constexpr int64_t TILE = (int64_t)kWave * K;
   const bool l1 = st->l1 != 0;
   const TA r = (TA)st->r;
+  const double rd = st->r;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = (int)(threadIdx.x / kWave);
+  const int w = blockIdx.x * kWaves + wid;
+  const int ns = A.samp_waves;
+  const int64_t count = A.n;
+  const uint32_t amask = l1 ? 0x7FFFFFFFu : 0xFFFFFFFFu;
+  __shared__ double lds[SM_N * kWaves];
+
+  double lam_b = inf_d(), nk = 0.0, ks = 0.0;
+  if (w < ns) {
+    const int64_t base = (int64_t)w * A.samp_ntiles / ns * TILE;
+    TIn yv[K];
+    const bool full = base + TILE <= count;
+    if (full)
+      load_tile_full<TIn, NL>((const TIn*)A.y, base, lane, yv);
+    else
+      load_tile<TIn, NL>((const TIn*)A.y, base, lane, count, yv);
+    TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
+    uint32_t inm = 0;
+    TIn tmax = -(TIn)__builtin_huge_val();
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = q * V + k;
+        const bool in = full || (i + k < count);
+        av[e] = abs_if(yv[e], amask);
+        inm |= in ? (1u << e) : 0u;
+        tmax = max(tmax, in ? av[e] : -(TIn)__builtin_huge_val());
+      }
+    }
+    const double m = wave_max((double)tmax);
+    if (m > -inf_d()) {
+      const double lam_first = rd - m;
+      // values at or below -lam_first are zero at the solution; the threshold
+      // is rounded down into TIn so that the test keeps every value it must
+      const TIn thr = round_down_to<TIn>(-lam_first);
+      uint32_t active = 0;
+#pragma unroll
+      for (int e = 0; e < K; ++e) active |= (((inm >> e) & 1u) && av[e] > thr) ? (1u << e) : 0u;
+      double lb = lam_first;
+      if (__ballot(active != 0u) != 0) {
+        TA v[K];
+#pragma unroll
+        for (int e = 0; e < K; ++e) v[e] = (TA)av[e];
+        int c = 0;
+        TA S = TA(0);
+        uint32_t J;
+        if (__ballot(__popc(active) > 1) != 0) {
+          J = condat_thread<K, TA>(v, active, r, l1, c, S);
+        } else {
+          // at most one value per lane: it joins J (l1: if non-zero)
+          J = 0;
+#pragma unroll
+          for (int e = 0; e < K; ++e) {
+            if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
+              J |= 1u << e;
+              c += 1;
+              S += v[e];
+            }
+          }
+        }
+        const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
+        const double ct = wave_sum((double)c);
+        const double skt = wave_sum((double)S);
+        if (ct > 0.0) lb = fmin(lb, (rd - skt) / ct);
+        uint32_t keep = 0;
+        auto select = [&](double bound) {
+          const TA lt = (TA)fmin(lam_t, bound);
+          keep = 0;
+          nk = 0.0;
+          ks = 0.0;
+#pragma unroll
+          for (int e = 0; e < K; ++e) {
+            if (((J >> e) & 1u) && (v[e] + lt > TA(0))) {
+              keep |= 1u << e;
+              nk += 1.0;
+              ks += (double)v[e];
+            }
+          }
+        };
+        for (int it = 0; it < kRefine; ++it) {
+          select(lb);
+          const double kc = wave_sum(nk), kss = wave_sum(ks);
+          if (kc == 0.0) break;
+          const double nl = (rd - kss) / kc;
+          if (!(nl < lb)) break;
+          lb = nl;
+        }
+        select(lb);
+        // with tracing on, lane 0 of the wave on tile 0 records its own
+        // Algorithm 2: the values it saw, J, the thread's bound and the values
+        // the wave's refined bound kept
+        if (w == 0 && lane == 0 && st->trace_cap > 0) {
+          cqk_trace_rec& t = A.trace[0];
+          t.iter = 0;
+          t.kind = 7;
+          t.compacted = c;
+          t.source = (int32_t)keep;
+          t.lam = lam_t;
+          t.phi = (double)S;
+          t.slope = (double)thr;
+          t.lo = lb;
+          t.hi = (double)base;
+          t.n_in = (int64_t)active;
+          t.n_out = (int64_t)J;
+          st->ntrace = 1;
+        }
+      }
+      lam_b = lb;
+    }
+  }
+  const double wc = wave_sum(nk), wsum = wave_sum(ks);
+  if (lane == 0) {
+    lds[SM_LAM * kWaves + wid] = lam_b;
+    lds[SM_CNT * kWaves + wid] = wc;
+    lds[SM_SUM * kWaves + wid] = wsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = lds[SM_LAM * kWaves], b = lds[SM_CNT * kWaves], c = lds[SM_SUM * kWaves];
+    for (int i = 1; i < kWaves; ++i) {
+      a = fmin(a, lds[SM_LAM * kWaves + i]);
+      b += lds[SM_CNT * kWaves + i];
+      c += lds[SM_SUM * kWaves + i];
+    }
+    A.samp[SM_LAM * gridDim.x + blockIdx.x] = a;
+    A.samp[SM_CNT * gridDim.x + blockIdx.x] = b;
+    A.samp[SM_SUM * gridDim.x + blockIdx.x] = c;
+  }
+}
+
+// The streaming pass of the Algorithm 2 start (Section 2.2, Section 4): one
+// read of y, and x = 0 written over it.  Every wave starts from the bound the
+// sample gives (the smallest bound of its waves and lam_J of the union of
+// their sets) and takes tiles grid-stride.  In each tile it keeps every value
+// above its running bound (l1: if non-zero); the kept values join its set J,
+// and the bound becomes min(bound, lam_J): still >= lam*, so the values at or
+// below -bound are zero at the solution.  Most tiles hold no value above the
+// bound and cost one test on the lanes' maxima.
+//
+// WARM: also the warm start of Section 3.1 from a primal estimate xbar, with
+// I = {xbar > 0} (l1: xbar != 0).  The kernel runs as without it: every bound
+// it finds is lam_J of some non-empty J, so it fixes values at zero whatever
+// J is.  It also sums the kept values of I and takes the largest value of I,
+// from which the merge forms the estimate's lam_J.
+template <typename TIn, bool WARM>
+__global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
+  SpxState* st = A.st;
+  if (st->status != kRunning) return;
+  constexpr int V = VecWidth<TIn>::value;
+  constexpr int K = kCondatK;
+  constexpr int NL = K / V;  // vector loads per lane per tile
+  constexpr int64_t TILE = (int64_t)kWave * K;
+  static_assert(K < 32, "a lane's kept count must fit in five bits");
+  const bool l1 = st->l1 != 0;
   const double rd = st->r;
   const int lane = threadIdx.x & (kWave - 1);
   const int rid = blockIdx.x * kWaves + (int)(threadIdx.x / kWave);
@@ -324,8 +505,25 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   __shared__ double lds[C_NPART * (kBlock / kWave)];
   __shared__ double tot[C_NPART];
 
-  // wave-uniform: the survivors this wave kept so far, the smallest bound
-  double run_c = 0.0, run_s = 0.0, lam_min = inf_d();
+  // the sample's bound (every wave forms the same value)
+  double lam_min;
+  {
+    const int g = A.samp_blocks;
+    double sl = inf_d(), sc = 0.0, ss = 0.0;
+    for (int i = lane; i < g; i += kWave) {
+      sl = fmin(sl, A.samp[SM_LAM * g + i]);
+      sc += A.samp[SM_CNT * g + i];
+      ss += A.samp[SM_SUM * g + i];
+    }
+    sl = wave_min(sl);
+    sc = wave_sum(sc);
+    ss = wave_sum(ss);
+    lam_min = (sc > 0.0) ? fmin(sl, (rd - ss) / sc) : sl;
+    // NaN only from invalid data, which the merge reports
+    if (!(lam_min <= inf_d())) lam_min = inf_d();
+  }
+  // wave-uniform: the values this wave kept so far
+  double run_c = 0.0, run_s = 0.0;
   double acc[C_NSUM] = {0, 0, 0, 0, 0, 0, 0};
   double abs_sum = 0.0;            // sum |y| (l1 only)
   double run_ci = 0.0, run_si = 0.0;  // kept values of I (WARM)
@@ -333,7 +531,6 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   TIn vmxI = -(TIn)__builtin_huge_val();
   TIn badacc = TIn(0);             // NaN once any y is NaN or infinite
   int64_t written = 0;
-  bool traced = false;  // this wave has run Algorithm 2 on a tile
   const uint32_t amask = l1 ? 0x7FFFFFFFu : 0xFFFFFFFFu;
   // -lam_min rounded down into TIn, recomputed only when lam_min moves
   TIn thr = -(TIn)__builtin_huge_val();
@@ -344,8 +541,8 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
   // yv: the tile's values, loaded by the caller
   auto tile = [&](const int64_t base, auto full_tag, const TIn* yv) {
     constexpr bool full = decltype(full_tag)::value;
-    TIn av[K];  // the values Algorithm 2 sees: y, or |y| for l1
-    uint32_t inI = 0xFFFFFFFFu;  // the values Algorithm 2 may use
+    TIn av[K];  // y, or |y| for l1
+    uint32_t inI = 0xFFFFFFFFu;  // the values of I (WARM)
     if constexpr (WARM) {
       TIn xv[K];
       load_tile<TIn, NL>((const TIn*)A.xw, base, lane, count, xv);
@@ -354,8 +551,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       for (int e = 0; e < K; ++e) inI |= (l1 ? (xv[e] != TIn(0)) : (xv[e] > TIn(0))) ? (1u << e) : 0u;
     }
     // x_i = 0 for every index (survivors get their value from the scatter at
-    // the end), written while this kernel is busy with Algorithm 2 anyway;
-    // a sparse output has no x
+    // the end); a sparse output has no x
     if (x != nullptr) {
       if constexpr (full)
         zero_tile_full<TIn, NL>(x, base, lane);
@@ -375,29 +571,25 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
         badacc += in ? yv[e] * TIn(0) : TIn(0);
         if (l1) abs_sum += in ? (double)av[e] : 0.0;
         tmax = max(tmax, in ? av[e] : -(TIn)__builtin_huge_val());
-        tmaxI = max(tmaxI, (in && ((inI >> e) & 1u)) ? av[e] : -(TIn)__builtin_huge_val());
+        if constexpr (WARM)
+          tmaxI = max(tmaxI, (in && ((inI >> e) & 1u)) ? av[e] : -(TIn)__builtin_huge_val());
       }
     }
     vmx = max(vmx, tmax);
-    vmxI = max(vmxI, tmaxI);
-    // The first bound: J = {the tile's largest value} gives lam_J = r - max
-    // (Algorithm 2's own first set, with the best single element).
+    if constexpr (WARM) vmxI = max(vmxI, tmaxI);
+    // no bound yet (a sample that found none): lam_J of the tile's largest
+    // value alone
     if (lam_min == inf_d()) {
       const double m = wave_max((double)tmax);
       if (m > -inf_d()) lam_min = rd - m;
     }
-    // Values at or below -lam_min (any lam_J >= lam*, eq. (lambdaJ)) are zero
-    // at the solution: only the rest enters Algorithm 2.  The threshold is
-    // rounded down into TIn, so the comparison never drops a value it must
-    // keep.
     if (!thr_set || lam_min != thr_of) {
       thr = round_down_to<TIn>(-lam_min);
       thr_of = lam_min;
       thr_set = true;
     }
-    // most tiles hold no value above it: one test on the lanes' maxima
     if (__ballot(tmax > thr) == 0) return;
-    uint32_t active = 0;
+    uint32_t keep = 0;
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
       const int64_t i = base + (int64_t)q * kWave * V + (int64_t)lane * V;
@@ -405,101 +597,37 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       for (int k = 0; k < V; ++k) {
         const int e = q * V + k;
         const bool in = full || (i + k < count);
-        active |= (in && av[e] > thr) ? (1u << e) : 0u;
+        keep |= (in && av[e] > thr && (!l1 || av[e] > TIn(0))) ? (1u << e) : 0u;
       }
     }
-    if (__ballot(active != 0u) == 0) return;
-    uint32_t keep = 0;
-    double nk = 0.0, ks = 0.0;
-    if (run_c > 0.0) {
-      // A later tile: the wave's running bound has already filtered it and
-      // every value left is kept (l1: if non-zero); the bound becomes lam_J
-      // of everything kept so far (below), again >= lam*.
+    // this lane's place among the wave's kept values: its count (five bits)
+    // summed over the lanes below it, one bit at a time
+    const int c = __popc(keep);
+    int pre = 0, nt = 0;
 #pragma unroll
-      for (int e = 0; e < K; ++e) {
-        if (((active >> e) & 1u) && (!l1 || av[e] > TIn(0))) {
-          keep |= 1u << e;
-          nk += 1.0;
-          ks += (double)av[e];
-        }
-      }
-    } else {
-      TA v[K];
+    for (int b = 0; b < 5; ++b) {
+      const uint64_t m = __ballot((c >> b) & 1);
+      pre += lane_prefix(m) << b;
+      nt += __popcll(m) << b;
+    }
+    if (nt == 0) return;
+    int64_t pos = written + pre;
+    double ks = 0.0;
 #pragma unroll
-      for (int e = 0; e < K; ++e) v[e] = (TA)av[e];
-      int c = 0;
-      TA S = TA(0);
-      uint32_t J;
-      if (__ballot(__popc(active) > 1) != 0) {
-        J = condat_thread<K, TA>(v, active, r, l1, c, S);
-      } else {
-        // at most one value per lane: it joins J (l1: if non-zero)
-        J = 0;
+    for (int q = 0; q < NL; ++q) {
+      if ((keep >> (q * V)) & ((1u << V) - 1u)) {
 #pragma unroll
-        for (int e = 0; e < K; ++e) {
-          if (((active >> e) & 1u) && (!l1 || v[e] > TA(0))) {
-            J |= 1u << e;
-            c += 1;
-            S += v[e];
+        for (int k = 0; k < V; ++k) {
+          const int e = q * V + k;
+          if ((keep >> e) & 1u) {
+            outv[pos] = yv[e];
+            outi[pos] = (uint32_t)(base + (int64_t)q * kWave * V + (int64_t)lane * V + k);
+            ks += (double)av[e];
+            ++pos;
           }
         }
       }
-      const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
-      // The wave's first kept tile.  Every lam below is lam_J of some
-      // non-empty J, hence >= lam* (Section 2.2): the union of the lanes'
-      // sets and the refinements
-      //   lam <- lam_J'  with  J' = {j in J : y_j + lam > 0},
-      // each of which can only lower lam (it is Algorithm 4's step on the
-      // tile's own sub-problem).
-      const double ct = wave_sum((double)c);
-      const double skt = wave_sum((double)S);
-      double lam_b = (ct > 0.0) ? (rd - skt) / ct : inf_d();
-      lam_b = fmin(lam_b, lam_min);
-      auto select = [&](double lb) {
-        const TA lt = (TA)fmin(lam_t, lb);
-        keep = 0;
-        nk = 0.0;
-        ks = 0.0;
-#pragma unroll
-        for (int e = 0; e < K; ++e) {
-          if (((J >> e) & 1u) && (v[e] + lt > TA(0))) {
-            keep |= 1u << e;
-            nk += 1.0;
-            ks += (double)v[e];
-          }
-        }
-      };
-      for (int it = 0; it < kRefine; ++it) {
-        select(lam_b);
-        const double kc = wave_sum(nk), kss = wave_sum(ks);
-        if (kc == 0.0) break;
-        const double nl = (rd - kss) / kc;
-        if (!(nl < lam_b)) break;
-        lam_b = nl;
-      }
-      select(lam_b);
-      // with tracing on, lane 0 of wave 0 records its own Algorithm 2 on the
-      // wave's first tile (the tile at index 0): the values it saw, J, the
-      // thread's bound and the values the wave's refined bound kept
-      if (rid == 0 && lane == 0 && !traced && st->trace_cap > 0) {
-        cqk_trace_rec& t = A.trace[0];
-        t.iter = 0;
-        t.kind = 7;
-        t.compacted = c;
-        t.source = (int32_t)keep;
-        t.lam = lam_t;
-        t.phi = (double)S;
-        t.slope = (double)thr;
-        t.lo = lam_b;
-        t.hi = (double)base;
-        t.n_in = (int64_t)active;
-        t.n_out = (int64_t)J;
-        st->ntrace = 1;
-      }
-      traced = true;
-      lam_min = fmin(lam_min, lam_b);
     }
-    if (__ballot(keep != 0u) == 0) return;
     if constexpr (WARM) {
       double ci = 0.0, si = 0.0;
 #pragma unroll
@@ -511,21 +639,10 @@ __global__ __launch_bounds__(kBlock) void spx_condat_kernel(SpxArgs A) {
       run_ci += wave_sum(ci);
       run_si += wave_sum(si);
     }
-#pragma unroll
-    for (int e = 0; e < K; ++e) {
-      const bool kb = (keep >> e) & 1u;
-      const uint64_t m = __ballot(kb);
-      if (kb) {
-        const int64_t pos = written + lane_prefix(m);
-        const int q = e / V, k = e % V;
-        outv[pos] = yv[e];
-        outi[pos] = (uint32_t)(base + (int64_t)q * kWave * V + (int64_t)lane * V + k);
-      }
-      written += __popcll(m);
-    }
-    run_c += wave_sum(nk);
+    written += nt;
+    run_c += (double)nt;
     run_s += wave_sum(ks);
-    if (run_c > 0.0) lam_min = fmin(lam_min, (rd - run_s) / run_c);
+    lam_min = fmin(lam_min, (rd - run_s) / run_c);
   };
   const int64_t stride = nr * TILE;
   for (int64_t base = (int64_t)rid * TILE; base < count; base += stride) {
@@ -1620,8 +1737,12 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   const bool condat = warm || o.lambda0_mode == CQK_LAMBDA0_CONDAT;
   const bool formula = !warm && o.lambda0_mode == CQK_LAMBDA0_FORMULA;
 
-  const size_t part_bytes =
-      ((size_t)G0 * (kPassRec + 2 * kCand) * sizeof(double) + 255) / 256 * 256;
+  // the Algorithm 2 sample: one tile per wave, spread evenly over y; its
+  // block records follow the partial records of the grid passes
+  const int ns = (int)std::min<int64_t>(ntiles, kSampleWaves);
+  const int GSm = (ns + kWaves - 1) / kWaves;
+  const size_t prec = (size_t)G0 * (kPassRec + 2 * kCand);
+  const size_t part_bytes = ((prec + (size_t)SM_N * GSm) * sizeof(double) + 255) / 256 * 256;
   const size_t cnt_bytes = ((size_t)2 * NR * sizeof(int32_t) + 255) / 256 * 256;
   const size_t cap = (size_t)G0 * chunk0;
   const size_t val_bytes = (cap * sizeof(TIn) + 255) / 256 * 256;
@@ -1666,6 +1787,10 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   A.n = n;
   A.chunk0 = chunk0;
   A.partials = (double*)ws;
+  A.samp = A.partials + prec;
+  A.samp_ntiles = ntiles;
+  A.samp_waves = ns;
+  A.samp_blocks = GSm;
   A.cnt[0] = (int32_t*)(ws + part_bytes);
   A.cnt[1] = A.cnt[0] + NR;
   A.tidx = (uint32_t*)(ws + part_bytes + cnt_bytes);
@@ -1783,10 +1908,11 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     if (!deferred && wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
   } else {
     if (condat) {
+      launch(spx_condat_sample_kernel<TIn, TA>, GSm);
       if (warm)
-        launch(spx_condat_kernel<TIn, TA, true>, G0);
+        launch(spx_condat_kernel<TIn, true>, G0);
       else
-        launch(spx_condat_kernel<TIn, TA, false>, G0);
+        launch(spx_condat_kernel<TIn, false>, G0);
       reduce(spx_condat_merge_kernel<TIn, TA>, G0);
     } else if (formula) {
       launch(spx_formula_kernel<TIn>, G0);
@@ -1823,10 +1949,16 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
   }
   const int pass_events = ev;
   const int trace_cap = init.trace_cap;
+  // bytes of y the Algorithm 2 sample reads
+  double samp_bytes = 0.0;
+  for (int w = 0; w < ns; ++w) {
+    const int64_t base = (int64_t)w * ntiles / ns * kT;
+    samp_bytes += (double)sizeof(TIn) * (double)std::min<int64_t>(kT, n - base);
+  }
   // Fills an info record from the state copy in hs (the stream synchronised),
   // reading the trace ring too.
   auto report = [ctx, hs, A, trace_cap, n, r, l1, sparse, warm, timing, pass_events, nwords,
-                 npass](cqk_info* info) -> cqk_status {
+                 npass, samp_bytes](cqk_info* info) -> cqk_status {
     const int ntrace = std::min(hs->ntrace, trace_cap);
     ctx->last_trace.resize(ntrace);
     if (ntrace > 0 && hip_ok(hipMemcpy(ctx->last_trace.data(), A.trace,
@@ -1875,10 +2007,12 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
       const double per_in = (t.source == 0) ? (double)sizeof(TIn) : (double)sizeof(TIn) + 4.0;
       const double per_out = (double)sizeof(TIn) + 4.0;
       info->pass_bytes += per_in * (double)t.n_in + per_out * (double)t.n_out;
-      // the Algorithm 2 kernel also writes x = 0 everywhere (not for a
-      // sparse output) and reads the estimate of a warm start
+      // the Algorithm 2 start also reads its sample of y, writes x = 0
+      // everywhere (not for a sparse output) and reads the estimate of a
+      // warm start
       if (t.kind == 0 && t.source == 0 && t.compacted)
-        info->pass_bytes += sizeof(TIn) * (double)t.n_in * ((sparse ? 0.0 : 1.0) + (warm ? 1.0 : 0.0));
+        info->pass_bytes += samp_bytes + sizeof(TIn) * (double)t.n_in *
+                                             ((sparse ? 0.0 : 1.0) + (warm ? 1.0 : 0.0));
     }
     ctx->last_pass_ms.clear();
     if (timing) {
