@@ -447,12 +447,15 @@ struct WaveRun {
 // wave: x = 0 over the tile; on the wave's first tile of the row Algorithm 2
 // per lane with the wave's refinement, on a later one the running bound;
 // the values kept are appended with their positions to the wave's list
-// (sv, si; entries past kSurvW are counted, not stored).
+// (sv, si; entries past kSurvW are counted, not stored).  A tile whose
+// largest value is at or below the running bound costs one test.
 __device__ __forceinline__ void wave_row_tile(const float* y, float* x, int64_t n, int64_t t0,
                                               double rd, WaveRun& R, float* sv, int32_t* si) {
+  static_assert(kK < 32, "a lane's kept count must fit in five bits");
   const int lane = threadIdx.x & (kWave - 1);
   float v[kK];
   uint32_t active = 0;
+  float tmax = -__builtin_huge_valf();
   load_wtile(y, t0, lane, n, v);
   if (t0 + kWTile <= n) {
     // a tile wholly in the row: no per-value range tests
@@ -463,7 +466,7 @@ __device__ __forceinline__ void wave_row_tile(const float* y, float* x, int64_t 
 #pragma unroll
     for (int e = 0; e < kK; ++e) {
       R.badf += v[e] * 0.f;
-      R.vmx = fmaxf(R.vmx, v[e]);
+      tmax = fmaxf(tmax, v[e]);
     }
   } else {
     // x is zero wherever the lists do not write it
@@ -476,52 +479,73 @@ __device__ __forceinline__ void wave_row_tile(const float* y, float* x, int64_t 
         if (i + k < n) {
           active |= 1u << (4 * q + k);
           R.badf += v[4 * q + k] * 0.f;
-          R.vmx = fmaxf(R.vmx, v[4 * q + k]);
+          tmax = fmaxf(tmax, v[4 * q + k]);
         }
       }
     }
+  }
+  R.vmx = fmaxf(R.vmx, tmax);
+  // the first bound of the row: lam_J of the tile's largest value alone
+  // (Algorithm 2's first set), so that Algorithm 2 below only scans the
+  // values above it
+  if (R.lam == inf_d()) {
+    const double m = wave_max((double)tmax);
+    if (m > -inf_d()) R.lam = rd - m;
   }
   // values at or below the wave's best bound so far are zero at the
   // solution (v <= thr exactly when v + lam <= 0)
   if (R.lam < inf_d()) {
     const float thr = float_at_or_below(-R.lam);
+    if (__ballot(tmax > thr) == 0) return;
 #pragma unroll
     for (int e = 0; e < kK; ++e)
       if (!(v[e] > thr)) active &= ~(1u << e);
   }
   if (__ballot(active != 0u) == 0) return;
-  double nk = 0.0, ks = 0.0;
-  uint32_t keep = 0;
+  uint32_t keep;
   if (R.c > 0.0) {
     // a later tile: the running bound has already filtered it and every
     // value left is kept; lam_J of everything kept so far becomes the
     // bound below (again >= lam*)
     keep = active;
-#pragma unroll
-    for (int e = 0; e < kK; ++e) {
-      nk += ((active >> e) & 1u) ? 1.0 : 0.0;
-      ks += ((active >> e) & 1u) ? (double)v[e] : 0.0;
-    }
   } else {
+    double nk, ks;
     keep = wave_tile_alg2(v, active, rd, R.c, R.s, R.lam, nk, ks);
   }
-  if (__ballot(keep != 0u) == 0) return;
+  // this lane's place in the list: its kept count (five bits) summed over
+  // the lanes below it, one bit at a time
+  const int c = __popc(keep);
+  int pre = 0, nt = 0;
 #pragma unroll
-  for (int e = 0; e < kK; ++e) {
-    const bool kb = (keep >> e) & 1u;
-    const uint64_t m = __ballot(kb);
-    if (kb) {
-      const int pos = R.nw + lane_prefix(m);
-      if (pos < kSurvW) {
-        sv[pos] = v[e];
-        si[pos] = (int32_t)(t0 + (e / 4) * kWave * 4 + lane * 4 + (e % 4));
+  for (int b = 0; b < 5; ++b) {
+    const uint64_t m = __ballot((c >> b) & 1);
+    pre += lane_prefix(m) << b;
+    nt += __popcll(m) << b;
+  }
+  if (nt == 0) return;
+  int pos = R.nw + pre;
+  double ks = 0.0;
+#pragma unroll
+  for (int q = 0; q < kK / 4; ++q) {
+    if ((keep >> (4 * q)) & 0xFu) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int e = 4 * q + k;
+        if ((keep >> e) & 1u) {
+          if (pos < kSurvW) {
+            sv[pos] = v[e];
+            si[pos] = (int32_t)(t0 + q * kWave * 4 + lane * 4 + k);
+          }
+          ++pos;
+          ks += (double)v[e];
+        }
       }
     }
-    R.nw += __popcll(m);
   }
-  R.c += wave_sum(nk);
+  R.nw += nt;
+  R.c += (double)nt;
   R.s += wave_sum(ks);
-  if (R.c > 0.0) R.lam = fmin(R.lam, (rd - R.s) / R.c);
+  R.lam = fmin(R.lam, (rd - R.s) / R.c);
 }
 
 // ---------------------------------------------------------------------------
@@ -818,12 +842,23 @@ __device__ void solve_short_row(const BatArgs& A, int s, int64_t base, int64_t L
     return;
   }
   const float r = (float)rd;
+  // Algorithm 2 scans only the values above the first bound, lam_J of the
+  // row's largest value alone
+  float vm = -__builtin_huge_valf();
+#pragma unroll
+  for (int k = 0; k < SP; ++k)
+    if ((active >> k) & 1u) vm = fmaxf(vm, v[k]);
+  const double lam_first = rd - wave_max((double)vm);
+  const float thr = float_at_or_below(-lam_first);
+  uint32_t scan = 0;
+#pragma unroll
+  for (int k = 0; k < SP; ++k) scan |= (((active >> k) & 1u) && v[k] > thr) ? (1u << k) : 0u;
   int c;
   float S;
-  const uint32_t J = alg2<SP>(v, active, r, c, S);
+  const uint32_t J = alg2<SP>(v, scan, r, c, S);
   const double lam_t = (c > 0) ? (rd - (double)S) / (double)c : inf_d();
   const double cw = wave_sum((double)c), sw = wave_sum((double)S);
-  double lam_b = (cw > 0) ? (rd - sw) / cw : inf_d();
+  double lam_b = (cw > 0) ? fmin((rd - sw) / cw, lam_first) : lam_first;
   // refinement on the wave's own sub-problem, then Algorithm 4 on the row
   for (int it = 0; it < kRefine; ++it) {
     const double lt = fmin(lam_t, lam_b);
