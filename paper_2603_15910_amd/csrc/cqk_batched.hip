@@ -69,17 +69,18 @@ struct BatArgs {
   double* gr;           // backward: grad_r
   int32_t* list;        // row ids: workgroup rows by bucket, then wave rows
   int64_t* lrow;        // per list entry: the row's first element and its length
-  int32_t* counters;    // 3kNB: n_long, +1: n_short, +2: n_items, +3: queue, +4: flags,
-                        // +6: survivors total, +7: overflow rows
+  int32_t* counters;    // CTR_* below
   int32_t* bhist;       // planning: rows per length bucket of each block of kPBlock rows
 };
 
-constexpr int CTR_NLONG = 3 * kNB, CTR_NSHORT = 3 * kNB + 1, CTR_NITEMS = 3 * kNB + 2,
-              CTR_QUEUE = 3 * kNB + 3, CTR_FLAGS = 3 * kNB + 4,
-              CTR_SURV = 3 * kNB + 6, CTR_OVER = 3 * kNB + 7, CTR_TOTAL = 3 * kNB + 8;
+// The call's counters: rows of each class, work items, the work queue, the
+// flags, the survivors total and the rows whose lists overflowed.
+constexpr int CTR_NLONG = 0, CTR_NSHORT = 1, CTR_NITEMS = 2, CTR_QUEUE = 3, CTR_FLAGS = 4,
+              CTR_SURV = 6, CTR_OVER = 7, CTR_TOTAL = 8;
 
 // Length bucket of a row of L values: its bit length, in the wave-row range
-// if L <= wave_max, else in the workgroup-row range.
+// if L <= wave_max, else in the workgroup-row range.  (Finer buckets, with
+// the two bits below the leading one, made the solve kernel slower.)
 __device__ __forceinline__ int bucket_of(int64_t L, int wave_max) {
   int b = 64 - __clzll((unsigned long long)L);
   b = b >= kNBW ? kNBW - 1 : b;
@@ -1642,7 +1643,7 @@ constexpr size_t round256(size_t v) { return (v + 255) / 256 * 256; }
 // the counters, the bucket histogram of each planning block and the row
 // extents, each on a 256-byte boundary.
 constexpr size_t bat_ws_bytes(size_t nseg) {
-  return round256(nseg * sizeof(int32_t)) + 256 * sizeof(int32_t) +
+  return round256(nseg * sizeof(int32_t)) + round256(CTR_TOTAL * sizeof(int32_t)) +
          round256((nseg > kPBlock ? (nseg + kPBlock - 1) / kPBlock : 1) * kNB * sizeof(int32_t)) +
          round256(nseg * 2 * sizeof(int64_t));
 }
@@ -1650,7 +1651,7 @@ constexpr size_t bat_ws_bytes(size_t nseg) {
 // Carves the planning buffers out of base (bat_ws_bytes(nseg) bytes).
 void bat_layout(void* base, int32_t nseg, BatWs* w) {
   const size_t list_bytes = round256((size_t)nseg * sizeof(int32_t));
-  const size_t ctr_bytes = 256 * sizeof(int32_t);
+  const size_t ctr_bytes = round256(CTR_TOTAL * sizeof(int32_t));
   const size_t nblk = std::max<size_t>(1, ((size_t)nseg + kPBlock - 1) / kPBlock);
   const size_t hist_bytes = round256(nblk * kNB * sizeof(int32_t));
   char* p = (char*)base;
