@@ -635,6 +635,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # the compaction threshold theta, tuned on this instance (every candidate
+    # solved, the fastest kept in the context for the timed solves)
+    log("bench: tuning theta")
+    theta, theta_ms, theta_sweep = ctx.tune_theta(*t, r, repeats=3, out=x)
+    log(f"bench: theta {theta} ({theta_ms:.3f} ms); sweep {theta_sweep}")
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         ctx.solve(*t, r, out=x)
@@ -709,6 +714,8 @@ def main():
             "avg_launch_bytes": pass_bytes / max(passes, 1),
         },
         "iterations": infos[-1]["iterations"],
+        "theta": {"chosen": theta, "tuned_ms": theta_ms,
+                  "sweep_ms": {str(k): v for k, v in theta_sweep.items()}},
         "passes": passes_tab,
         "passes_after_stop_us": tail_us,
         "finalize_gbs": fin_gbs,

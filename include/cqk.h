@@ -111,7 +111,7 @@ typedef struct cqk_opts {
   int32_t max_iter;         /* Newton iterations (evaluations of phi); default 100 */
   double tol;               /* <= 0: eps^(3/4) of the working type (Section 5) */
   int32_t compaction;       /* cqk_compaction; default AUTO */
-  double compact_theta;     /* <= 0: library default (0.5) */
+  double compact_theta;     /* <= 0: the context's (0.5 unless set or tuned) */
   int32_t accum;            /* cqk_accum */
   int32_t sync;             /* 1 (default): wait and fill *info */
   int32_t trace;            /* 1: record one cqk_trace_rec per pass */
@@ -519,6 +519,36 @@ cqk_status cqk_tune_batched_cqk_f32(cqk_ctx* ctx, int32_t nseg, const int64_t* o
                                     const float* g, float* grad_a, int32_t backward,
                                     int32_t repeats, cqk_batch_schedule* best,
                                     double* best_ms);
+
+/* The compaction threshold theta that AUTO calls of the general CQK use when
+ * opts->compact_theta <= 0 (Section 2.2 variable fixing: a side is written
+ * only while it keeps at most theta of the indices read).  A new context
+ * starts at 0.5; set takes 0 < theta <= 1, else INVALID_ARG. */
+cqk_status cqk_get_compact_theta(cqk_ctx* ctx, double* theta);
+cqk_status cqk_set_compact_theta(cqk_ctx* ctx, double theta);
+
+/* Candidates of the theta tuner, in this order. */
+#define CQK_THETA_CANDIDATES 7   /* 0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 1.0 */
+
+/* Autotuner of theta (Section 2.2; when compaction pays is an empirical
+ * question there): solves this instance with cqk_solve_f64 (_f32: with
+ * cqk_solve_f32) at every candidate theta, with AUTO compaction and the rest
+ * of *opts (NULL: defaults; sync, trace and timing are ignored), `repeats`
+ * timed solves each after one warm-up, keeps the fastest as the context's
+ * theta and returns it with its time in milliseconds (host clock around the
+ * synchronised call, median of the repeats).  times_ms, if not NULL, receives
+ * the CQK_THETA_CANDIDATES times in candidate order.  x is overwritten.  Any
+ * solve that does not return CQK_OK ends the tuning with its status and the
+ * context's theta unchanged.  Synchronises; not under graph capture
+ * (INVALID_ARG). */
+cqk_status cqk_tune_theta_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                              const double* b, const double* l, const double* u, double r,
+                              double* x, const cqk_opts* opts, int32_t repeats,
+                              double* best_theta, double* best_ms, double* times_ms);
+cqk_status cqk_tune_theta_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                              const float* b, const float* l, const float* u, double r,
+                              float* x, const cqk_opts* opts, int32_t repeats,
+                              double* best_theta, double* best_ms, double* times_ms);
 
 #ifdef __cplusplus
 }

@@ -609,6 +609,45 @@ class Context:
         return gy
 
 
+    @property
+    def compact_theta(self):
+        """The compaction threshold AUTO solves use when they give none."""
+        v = C.c_double(0.0)
+        st = _call("cqk_get_compact_theta", C.c_void_p(self.handle), C.byref(v))
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_get_compact_theta")
+        return v.value
+
+    @compact_theta.setter
+    def compact_theta(self, theta):
+        st = _call("cqk_set_compact_theta", C.c_void_p(self.handle), float(theta))
+        if st != CQK_OK:
+            raise CqkError(st, "cqk_set_compact_theta")
+
+    def tune_theta(self, d, a, b, l, u, r, repeats=3, out=None, **kw):
+        """Times the general solve of this instance at every candidate
+        theta (L.THETA_CANDIDATES) and keeps the fastest as the context's;
+        returns (theta, ms, {theta: ms}).  kw: solve options (compaction is
+        AUTO)."""
+        torch = _torch()
+        dt = d.dtype
+        if dt not in (torch.float64, torch.float32):
+            raise TypeError("tune_theta takes float64 or float32 tensors")
+        n = d.numel()
+        x = out if out is not None else torch.empty_like(d)
+        ptrs = [_dev_ptr(t, dt, nm) for t, nm in zip((d, a, b, l, u, x), "dablux")]
+        opts = make_opts(**kw)
+        best, ms = C.c_double(0.0), C.c_double(0.0)
+        times = (C.c_double * L.CQK_THETA_CANDIDATES)()
+        name = "cqk_tune_theta_f64" if dt == torch.float64 else "cqk_tune_theta_f32"
+        self._bind_stream()
+        st = _call(name, C.c_void_p(self.handle), n, *ptrs[:5], float(r), ptrs[5],
+                   C.byref(opts), int(repeats), C.byref(best), C.byref(ms),
+                   C.cast(times, C.c_void_p))
+        if st != CQK_OK:
+            raise CqkError(st, name)
+        return best.value, ms.value, dict(zip(L.THETA_CANDIDATES, list(times)))
+
     def batch_schedule(self, backward=False, general=False):
         """The context's batched schedule as a dict (general: the batched
         general CQK's, else the batched simplex's)."""

@@ -19,6 +19,8 @@ CQK_DEVICE_ERROR = 4
 CQK_NO_MEMORY = 5
 CQK_BUFFER_TOO_SMALL = 6
 CQK_NOALLOC_MAX_SEG = 65536   # rows the no-allocation batched call holds
+CQK_THETA_CANDIDATES = 7      # the theta tuner's candidates
+THETA_CANDIDATES = (0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 1.0)
 STATUS_NAMES = {0: "OK", 1: "INFEASIBLE", 2: "INVALID_ARG", 3: "NOT_CONVERGED",
                 4: "DEVICE_ERROR", 5: "NO_MEMORY", 6: "BUFFER_TOO_SMALL"}
 
@@ -193,6 +195,12 @@ SIGNATURES = {
         C.c_int, [_P, _I32, _P, _P, _P, _D, _P, _P, _P, _OPTS, _INFO]),
     "cqk_project_simplex_batched_backward_f32": (
         C.c_int, [_P, _I32, _P, _P, _P, _P, _P, _OPTS]),
+    "cqk_get_compact_theta": (C.c_int, [_P, C.POINTER(_D)]),
+    "cqk_set_compact_theta": (C.c_int, [_P, _D]),
+    "cqk_tune_theta_f64": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _I32,
+                                     C.POINTER(_D), C.POINTER(_D), _P]),
+    "cqk_tune_theta_f32": (C.c_int, [_P, _I64, _P, _P, _P, _P, _P, _D, _P, _OPTS, _I32,
+                                     C.POINTER(_D), C.POINTER(_D), _P]),
     "cqk_get_batch_schedule": (C.c_int, [_P, _I32, C.POINTER(cqk_batch_schedule)]),
     "cqk_set_batch_schedule": (C.c_int, [_P, _I32, C.POINTER(cqk_batch_schedule)]),
     "cqk_tune_batched_f32": (

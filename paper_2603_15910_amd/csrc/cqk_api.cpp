@@ -3,10 +3,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/cqk.h"
 #include "cqk_internal.h"
@@ -215,6 +217,48 @@ cqk_status sparse_common(cqk_ctx* ctx, int64_t n, const T* y, const T* xbar, dou
   return st;
 }
 
+constexpr double kThetaCands[CQK_THETA_CANDIDATES] = {0.2, 0.3, 0.4, 0.5, 0.6, 0.75, 1.0};
+
+// Times solve_common at every candidate theta (median of `repeats` after a
+// warm-up, host clock around the synchronised call) and keeps the fastest.
+template <typename T>
+cqk_status tune_theta(cqk_ctx* ctx, int64_t n, const T* d, const T* a, const T* b, const T* l,
+                      const T* u, double r, T* x, const cqk_opts* opts, int32_t repeats,
+                      double* best_theta, double* best_ms, double* times_ms) {
+  if (!ctx || n <= 0 || repeats < 1 || repeats > 100) return CQK_INVALID_ARG;
+  cqk_opts o;
+  cqk_status st = check_opts(opts, &o, false);
+  if (st != CQK_OK) return st;
+  if (hipSetDevice(ctx->device) != hipSuccess) return CQK_DEVICE_ERROR;
+  if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
+  o.compaction = CQK_COMPACT_AUTO;
+  o.sync = 1;
+  o.trace = 0;
+  o.timing = 0;
+  double times[CQK_THETA_CANDIDATES];
+  std::vector<double> runs((size_t)repeats);
+  for (int c = 0; c < CQK_THETA_CANDIDATES; ++c) {
+    o.compact_theta = kThetaCands[c];
+    for (int k = -1; k < repeats; ++k) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = solve_common<T>(ctx, n, d, a, b, l, u, nullptr, false, r, x, &o, nullptr);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (st != CQK_OK) return st;
+      if (k >= 0) runs[(size_t)k] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    }
+    std::sort(runs.begin(), runs.end());
+    times[c] = runs[(size_t)repeats / 2];
+  }
+  int best = 0;
+  for (int c = 1; c < CQK_THETA_CANDIDATES; ++c)
+    if (times[c] < times[best]) best = c;
+  ctx->theta = kThetaCands[best];
+  if (best_theta) *best_theta = kThetaCands[best];
+  if (best_ms) *best_ms = times[best];
+  if (times_ms)
+    for (int c = 0; c < CQK_THETA_CANDIDATES; ++c) times_ms[c] = times[c];
+  return CQK_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -701,6 +745,34 @@ cqk_status cqk_tune_batched_backward_f32(cqk_ctx* ctx, int32_t nseg, const int64
   ctx->last = nullptr;
   if (stream_capturing(ctx->stream)) return CQK_INVALID_ARG;  // the tuner synchronises
   return tune_batched_backward_f32(ctx, nseg, offsets, x, g, grad_y, repeats, best, best_ms);
+}
+
+cqk_status cqk_get_compact_theta(cqk_ctx* ctx, double* theta) {
+  if (!ctx || !theta) return CQK_INVALID_ARG;
+  *theta = ctx->theta;
+  return CQK_OK;
+}
+
+cqk_status cqk_set_compact_theta(cqk_ctx* ctx, double theta) {
+  if (!ctx || !(theta > 0.0 && theta <= 1.0)) return CQK_INVALID_ARG;
+  ctx->theta = theta;
+  return CQK_OK;
+}
+
+cqk_status cqk_tune_theta_f64(cqk_ctx* ctx, int64_t n, const double* d, const double* a,
+                              const double* b, const double* l, const double* u, double r,
+                              double* x, const cqk_opts* opts, int32_t repeats,
+                              double* best_theta, double* best_ms, double* times_ms) {
+  return tune_theta<double>(ctx, n, d, a, b, l, u, r, x, opts, repeats, best_theta, best_ms,
+                            times_ms);
+}
+
+cqk_status cqk_tune_theta_f32(cqk_ctx* ctx, int64_t n, const float* d, const float* a,
+                              const float* b, const float* l, const float* u, double r,
+                              float* x, const cqk_opts* opts, int32_t repeats,
+                              double* best_theta, double* best_ms, double* times_ms) {
+  return tune_theta<float>(ctx, n, d, a, b, l, u, r, x, opts, repeats, best_theta, best_ms,
+                           times_ms);
 }
 
 }  // extern "C"

@@ -829,11 +829,11 @@ GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double th
   return L;
 }
 
-// theta of a call: the library default 0.5 (AUTO) unless the options give
-// one; COMPACT_ALWAYS keeps every side whatever its size
-double gen_theta(const cqk_opts& o) {
+// theta of a call: the options' if they give one, else the context's (0.5
+// unless set or tuned); COMPACT_ALWAYS keeps every side whatever its size
+double gen_theta(const cqk_ctx* ctx, const cqk_opts& o) {
   if (o.compaction == CQK_COMPACT_ALWAYS) return 1.0;
-  return (o.compact_theta > 0.0) ? o.compact_theta : 0.5;
+  return (o.compact_theta > 0.0) ? o.compact_theta : ctx->theta;
 }
 
 namespace {
@@ -843,7 +843,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
                        const TIn* l, const TIn* u, const TIn* xw, double r, TIn* x,
                        const cqk_opts& o, cqk_info* info) {
   const bool compaction = o.compaction != CQK_COMPACT_OFF;
-  const double theta = gen_theta(o);
+  const double theta = gen_theta(ctx, o);
   const GenLayout Lg = gen_layout(n, ctx->num_cus, VecWidth<TIn>::value, compaction, theta);
   const int G = Lg.G, NR = Lg.NR, GF = Lg.GF;
   const int64_t chunk = Lg.chunk;

@@ -103,6 +103,7 @@ struct cqk_ctx {
   int32_t last_trace_count = 0;
   std::vector<cqk_trace_rec> last_trace;
   std::vector<float> last_pass_ms;  // kernel time of each grid pass of the last timed call
+  double theta = 0.5;  // compaction threshold of AUTO calls that give none
   cqk_batch_schedule sched_fwd{8, 4, 1, 16};  // batched forward / backward schedules
   cqk_batch_schedule sched_bwd{8, 4, 0, 0};
   cqk_batch_schedule sched_cqk_fwd{8, 4, 0, 0};  // batched general CQK forward / backward

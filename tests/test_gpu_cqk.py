@@ -229,3 +229,32 @@ def test_several_tiles_per_wave(ctx, gen, dtype):
         check_cqk(x, inst, ref, tol)
         if compaction != "off":
             assert any(t["compacted"] for t in ctx.trace())
+
+
+def test_theta_tuner_keeps_the_fastest_candidate(ctx):
+    """The theta tuner solves the instance at every candidate, keeps the
+    fastest in the context, and every candidate solves it exactly."""
+    from paper_2603_15910_amd import _lib as L
+    from paper_2603_15910_amd import CqkError
+    inst = W.cqk_uniform(2_000_003, 31)
+    ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+    t = _dev(inst)
+    assert ctx.compact_theta == 0.5
+    try:
+        theta, ms, times = ctx.tune_theta(*t, inst["r"], repeats=1)
+        assert theta in L.THETA_CANDIDATES and ctx.compact_theta == theta
+        assert sorted(times) == sorted(L.THETA_CANDIDATES)
+        assert ms == times[theta] == min(times.values()) and ms > 0
+        x, info = _solve(ctx, inst)
+        assert info["status"] == 0
+        check_cqk(x, inst, ref, 1e-10)
+        for th in L.THETA_CANDIDATES:
+            x, info = _solve(ctx, inst, theta=th, trace=True)
+            assert info["status"] == 0, (th, info)
+            check_cqk(x, inst, ref, 1e-10)
+        with pytest.raises(CqkError):
+            ctx.compact_theta = 0.0
+        with pytest.raises(CqkError):
+            ctx.compact_theta = 1.5
+    finally:
+        ctx.compact_theta = 0.5
