@@ -196,3 +196,38 @@ def test_tail_loop_capacity_boundary(ctx, dtype, n, start):
         x, info = _run(ctx, y, 1.0, lambda0=start)
         assert info["status"] == 0, info
         check_simplex(x, y, x_ref, lam_ref, 1.0, TOL[dtype])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_condat_start_sample_cases(ctx, dtype):
+    """The Algorithm 2 start bounds lam* from a sample of tiles (one per wave,
+    tile floor(w * ntiles / 1024) of 1024 values) and then filters all of y
+    with it: inputs where the sample sees nothing of the support, ordered
+    inputs, ties, and invalid values inside and outside the sample."""
+    rng = np.random.default_rng(77)
+    n = 3 * 1024 * 1024 + 517          # 3073 tiles: tile 1 is not sampled
+    base = rng.standard_normal(n).astype(dtype)
+    cases = {}
+    spike = base.copy()
+    spike[1024 + 300] = dtype(50.0)      # the whole support in an unsampled tile
+    cases["spike_unsampled"] = (spike, False)
+    neg = base.copy()
+    neg[1024 + 301] = dtype(-60.0)       # l1: the largest |y| is negative, unsampled
+    cases["l1_negative_spike"] = (neg, True)
+    cases["ascending"] = (np.sort(base), False)
+    cases["descending"] = (np.sort(base)[::-1].copy(), False)
+    cases["ties"] = (np.full(n, 0.25, dtype=dtype), False)
+    small = rng.standard_normal(6 * 1024 + 7).astype(dtype)   # fewer tiles than sample waves
+    cases["six_tiles"] = (small, False)
+    for name, (y, l1) in cases.items():
+        x_ref, lam_ref = _ref(y, 1.0, l1)
+        x, info = _run(ctx, y, 1.0, l1=l1, lambda0="condat")
+        assert info["status"] == 0, (name, info)
+        check_simplex(x, y, x_ref, lam_ref, 1.0, TOL[dtype], l1=l1)
+        if not l1:
+            assert info["lambda0"] >= lam_ref - 1e-9 * max(1.0, abs(lam_ref)), (name, info)
+    for pos in (5, 1024 + 5):            # inside tile 0 (sampled), inside tile 1 (not)
+        y = base.copy()
+        y[pos] = np.nan
+        _, info = _run(ctx, y, 1.0, lambda0="condat")
+        assert info["status"] == 2, (pos, info)
