@@ -2,7 +2,8 @@
 
 One step = one whole solve (cqk_solve_f64: the Newton passes with compaction
 of resolved indices, then the x-writing pass) over inputs already resident in
-HBM.  Prints one JSON line: the metric (elements/s = n / ms per solve), the
+HBM, with the compaction threshold theta tuned on the instance first
+(cqk_tune_theta_f64; --theta fixes it instead).  Prints one JSON line: the metric (elements/s = n / ms per solve), the
 roofline of the pass kernel (algorithmic bytes per launch over its average
 launch time from HIP events stamped by its dispatches in the timed region,
 against 8 TB/s, and the measured HBM traffic per launch when the committed
@@ -17,7 +18,7 @@ checked for its status.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--n N]
                     [--no-cpu-baseline] [--no-extras] [--calibrate-copy]
-                    [--oracle-full]
+                    [--oracle-full] [--theta T]
 """
 from __future__ import annotations
 
@@ -598,6 +599,8 @@ def main():
                     help="also run one 1 GiB device copy (reference for HBM counters)")
     ap.add_argument("--only", choices=EXTRA_SECTIONS, default=None,
                     help="run one extra workload alone (for profiling) and print its record")
+    ap.add_argument("--theta", type=float, default=0.0,
+                    help="use this compaction threshold instead of tuning it (profiling runs)")
     ap.add_argument("--no-row-loop", action="store_true",
                     help="skip the per-row loop comparator of the batched workload")
     ap.add_argument("--oracle-full", action="store_true",
@@ -637,9 +640,13 @@ def main():
         del src, dst
     # the compaction threshold theta, tuned on this instance (every candidate
     # solved, the fastest kept in the context for the timed solves)
-    log("bench: tuning theta")
-    theta, theta_ms, theta_sweep = ctx.tune_theta(*t, r, repeats=3, out=x)
-    log(f"bench: theta {theta} ({theta_ms:.3f} ms); sweep {theta_sweep}")
+    if args.theta > 0.0:
+        ctx.compact_theta = args.theta
+        theta, theta_ms, theta_sweep = args.theta, None, {}
+    else:
+        log("bench: tuning theta")
+        theta, theta_ms, theta_sweep = ctx.tune_theta(*t, r, repeats=3, out=x)
+        log(f"bench: theta {theta} ({theta_ms:.3f} ms); sweep {theta_sweep}")
     log(f"bench: warmup {args.warmup}")
     for _ in range(args.warmup):
         ctx.solve(*t, r, out=x)
@@ -714,7 +721,7 @@ def main():
             "avg_launch_bytes": pass_bytes / max(passes, 1),
         },
         "iterations": infos[-1]["iterations"],
-        "theta": {"chosen": theta, "tuned_ms": theta_ms,
+        "theta": {"chosen": theta, "tuned": args.theta <= 0.0, "tuned_ms": theta_ms,
                   "sweep_ms": {str(k): v for k, v in theta_sweep.items()}},
         "passes": passes_tab,
         "passes_after_stop_us": tail_us,
