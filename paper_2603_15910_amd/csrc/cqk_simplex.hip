@@ -321,17 +321,20 @@ constexpr int kSampleWaves = 1024;  // tiles in the sample, at most
 // sub-problem).  Every bound is lam_J of a non-empty J, hence >= lam*
 // (eq. (lambdaJ)), and so is lam_J of the union of the waves' final sets,
 // which the streaming kernel forms from the block records.
+// The kernel also starts the solve: `init` is the solve's initial state,
+// which block 0 stores (no kernel of the call runs before this one).
 template <typename TIn, typename TA>
-__global__ __launch_bounds__(kBlock) void spx_condat_sample_kernel(SpxArgs A) {
+__global__ __launch_bounds__(kBlock) void spx_condat_sample_kernel(SpxArgs A, SpxState init) {
   SpxState* st = A.st;
-  if (st->status != kRunning) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *st = init;
+  if (init.status != kRunning) return;
   constexpr int V = VecWidth<TIn>::value;
   constexpr int K = kCondatK;
   constexpr int NL = K / V;  // vector loads per lane per tile
   constexpr int64_t TILE = (int64_t)kWave * K;
-  const bool l1 = st->l1 != 0;
-  const TA r = (TA)st->r;
-  const double rd = st->r;
+  const bool l1 = init.l1 != 0;
+  const TA r = (TA)init.r;
+  const double rd = init.r;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = (int)(threadIdx.x / kWave);
   const int w = blockIdx.x * kWaves + wid;
@@ -426,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void spx_condat_sample_kernel(SpxArgs A) {
         // with tracing on, lane 0 of the wave on tile 0 records its own
         // Algorithm 2: the values it saw, J, the thread's bound and the values
         // the wave's refined bound kept
-        if (w == 0 && lane == 0 && st->trace_cap > 0) {
+        if (w == 0 && lane == 0 && init.trace_cap > 0) {
           cqk_trace_rec& t = A.trace[0];
           t.iter = 0;
           t.kind = 7;
@@ -1860,7 +1863,9 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     stt = ensure_events(ctx, nev);
     if (stt != CQK_OK) return stt;
   }
-  hipLaunchKernelGGL(spx_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
+  // the Algorithm 2 sample kernel stores the initial state itself
+  const bool init_in_sample = condat && r != 0.0;
+  if (!init_in_sample) hipLaunchKernelGGL(spx_init_kernel, dim3(1), dim3(1), 0, s, A.st, init);
   int ev = 4;
   int npass = 0;  // grid passes queued
   auto launch = [&](auto kern, int grid) {
@@ -1890,8 +1895,18 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
                    GS);
       return;
     }
-    launch_timed(spx_finalize_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
-                 timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
+    // after the Algorithm 2 start of a simplex projection x = 0 is written
+    // and the final set is a compacted one: the finalize would return at
+    // once (l1 may still copy y), so only the scatter runs
+    if (condat && !l1 && r != 0.0) {
+      if (timing) {
+        (void)hipEventRecord(ctx->events[0], s);
+        (void)hipEventRecord(ctx->events[1], s);
+      }
+    } else {
+      launch_timed(spx_finalize_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
+                   timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
+    }
     launch_timed(spx_scatter_kernel<TIn, TA>, dim3(G0), dim3(kBlock), s,
                  timing ? ctx->events[2] : nullptr, timing ? ctx->events[3] : nullptr, A);
     hipLaunchKernelGGL(spx_fin_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, G0);
@@ -1908,7 +1923,14 @@ cqk_status run_simplex(cqk_ctx* ctx, int64_t n, const TIn* y, const TIn* xw, Spa
     if (!deferred && wait_state() != CQK_OK) return CQK_DEVICE_ERROR;
   } else {
     if (condat) {
-      launch(spx_condat_sample_kernel<TIn, TA>, GSm);
+      {
+        const bool rec = timing && ev + 2 <= (int)nev;
+        launch_timed(spx_condat_sample_kernel<TIn, TA>, dim3(GSm), dim3(kBlock), s,
+                     rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A,
+                     init);
+        if (rec) ev += 2;
+        ++npass;
+      }
       if (warm)
         launch(spx_condat_kernel<TIn, true>, G0);
       else
