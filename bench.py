@@ -143,14 +143,16 @@ def pass_table(ctx, in_bytes=40.0):
     """Per grid pass of the last timed, traced general solve: indices read
     (n_k), survivors written, algorithmic bytes, kernel µs and GB/s."""
     ms = ctx.pass_ms()
-    recs = [t for t in ctx.trace() if t["kind"] in (0, 1, 2)]
+    recs = [t for t in ctx.trace() if t["kind"] in (0, 1, 2, 8, 9)]
     rows = []
     for k, t in enumerate(recs):
         per_in = in_bytes if t["source"] == 0 else 32.0
-        # n_out: survivors written for both sides of the evaluation
-        nbytes = per_in * t["n_in"] + 32.0 * t["n_out"]
+        # n_out: survivors written for both sides of the evaluation (the
+        # sample's record: survivors it predicts, nothing written)
+        nbytes = per_in * t["n_in"] + (32.0 * t["n_out"] if t["kind"] in (1, 2) else 0.0)
         us = ms[k] * 1e3 if k < len(ms) else None
-        rows.append({"kind": {0: "lambda0", 1: "evaluate", 2: "breakpoint"}[t["kind"]],
+        rows.append({"kind": {0: "lambda0", 1: "evaluate", 2: "breakpoint",
+                              8: "sample", 9: "sample2"}[t["kind"]],
                      "source": "original" if t["source"] == 0 else "compacted",
                      "n_in": t["n_in"], "n_out": t["n_out"], "adopted": bool(t["compacted"]),
                      "bytes": nbytes, "us": us,

@@ -48,10 +48,13 @@ constexpr int NPART = NSUM;
 
 // Compacted sets: the caller's arrays are source 0, the three compacted sets
 // sources 1..3.  An evaluation reading source `src` writes side k's
-// survivors to side_dst(src, k), the two sets other than src.
+// survivors to side_dst(src, k), the two sets other than src; passes over
+// the caller's arrays leave set 3 alone, which is where the first pass
+// writes the sampled-bracket set.
 __device__ __host__ __forceinline__ int side_dst(int src, int side) {
   return (src + side) % 3 + 1;
 }
+constexpr int kSpecSet = 3;
 
 
 struct Acc {
@@ -126,6 +129,21 @@ __device__ __forceinline__ int eval_index(Acc& acc, double c, double s, double b
   return keep;
 }
 
+// One index of the first evaluation pass classified on a bracket [p, q]
+// estimated from a sample (not yet known to hold lam*): dropped into side 0's
+// sums when its bound is active on all of [p, q] or it is free on all of it
+// with g keeping one sign; returns 1 when kept.  The sums are exact for every
+// lam strictly inside (p, q), wherever lam* is.
+__device__ __forceinline__ int spec_index(Acc& acc, double c, double s, double bl, double bu,
+                                          double p, double q) {
+  const double fp = fma(s, p, c);
+  const double fq = fma(s, q, c);
+  const bool at_l = fq <= bl, at_u = fp >= bu;
+  const bool fr = !at_l && !at_u && (fp >= bl) && (fq <= bu) && (fp >= 0.0 || fq <= 0.0);
+  side_sums(acc, P_SIDE, at_l, at_u, fr, bl, bu, c, s, fp >= 0.0);
+  return (at_l || at_u || fr) ? 0 : 1;
+}
+
 // Closest breakpoints around lam (Algorithm 1, breakpoint steps), with the
 // slope that opens there.  The candidates are chosen with the same predicate
 // the slopes use (an index below its lower bound at lam can only become free
@@ -167,6 +185,51 @@ __device__ __forceinline__ void finish(GenState* st, double lamf, int reason) {
   st->stop_reason = reason;
 }
 
+// A compacted set's dropped-index sums hold on a bracket [vlo, vhi]: for a
+// set made from Algorithm 1's own bracket that bracket holds every later
+// iterate; for the sampled-bracket set it need not.  The next evaluation at
+// `next` keeps the current source only if next lies strictly inside, a
+// breakpoint search only if Algorithm 1's whole bracket does (the breakpoint
+// it looks for lies between the bracket end and lam*); otherwise the next
+// pass reads the caller's arrays again.
+__device__ __forceinline__ void to_caller_arrays(GenState* st) {
+  st->src = 0;
+  st->F = st->AF = st->C0 = st->C1 = st->A0 = st->A1 = 0.0;
+  st->n_src = st->n_all;
+  st->vlo = -inf_d();
+  st->vhi = inf_d();
+}
+__device__ __forceinline__ void check_source_eval(GenState* st, double next) {
+  if (st->src != 0 && !(next > st->vlo && next < st->vhi)) to_caller_arrays(st);
+}
+// Source of an evaluation at `next` once the sampled-bracket set exists: it
+// replaces the caller's arrays, or a larger set just adopted, when next lies
+// strictly inside its bracket.  It waits only while the passes read the
+// caller's arrays (passes over a compacted set may overwrite it).  Returns
+// whether it was taken.
+__device__ __forceinline__ bool take_spec_set(GenState* st, double next) {
+  if (!st->spend) return false;
+  const bool inside = next > st->sp && next < st->sq;
+  const bool take = inside && (st->src == 0 || st->sn < st->n_src);
+  if (take) {
+    st->F = st->sF;
+    st->AF = st->sAF;
+    st->C0 = st->sC0;
+    st->C1 = st->sC1;
+    st->A0 = st->sA0;
+    st->A1 = st->sA1;
+    st->src = kSpecSet;
+    st->n_src = st->sn;
+    st->vlo = st->sp;
+    st->vhi = st->sq;
+  }
+  if (take || st->src != 0) st->spend = 0;
+  return take;
+}
+__device__ __forceinline__ void check_source_bkpt(GenState* st) {
+  if (st->src != 0 && !(st->vlo <= st->lo && st->hi <= st->vhi)) to_caller_arrays(st);
+}
+
 __device__ __forceinline__ void advance(GenState* st, double next) {
   st->lam_prev = st->lam;
   st->lam = next;
@@ -181,10 +244,26 @@ __device__ __forceinline__ void advance(GenState* st, double next) {
 __device__ __forceinline__ void update_after_eval(GenState* st, const double* t, cqk_trace_rec* tr) {
   const double lam = st->lam;
   const int source = st->src;
+  const double lo_in = st->lo, hi_in = st->hi;
+  // the first pass wrote the sampled-bracket set in side 0's slot instead of
+  // the two sides
+  const bool spec = st->spec != 0;
+  st->spec = 0;
   st->passes += 1;
   if (t[P_BAD] > 0.0) {
     st->status = CQK_INVALID_ARG;
     return;
+  }
+  if (spec && t[P_SIDE + D_DROP] == 0.0) {
+    // every wave kept the sampled-bracket set: it waits in set 3
+    st->sF = t[P_SIDE + D_F];
+    st->sAF = t[P_SIDE + D_AF];
+    st->sC0 = t[P_SIDE + D_C0];
+    st->sC1 = t[P_SIDE + D_C1];
+    st->sA0 = t[P_SIDE + D_A0];
+    st->sA1 = t[P_SIDE + D_A1];
+    st->sn = (int64_t)t[P_SIDE + D_NOUT];
+    st->spend = 1;
   }
   // algorithmic bytes: the set read (caller's arrays or the 32-byte form) and
   // the survivors written for both sides
@@ -200,7 +279,7 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
   const int side = (phi - r0 < 0.0) ? 0 : 1;
   const int o = P_SIDE + side * D_N;
   const bool compacted =
-      (st->compaction != CQK_COMPACT_OFF) && (phi != r0) && (t[o + D_DROP] == 0.0);
+      !spec && (st->compaction != CQK_COMPACT_OFF) && (phi != r0) && (t[o + D_DROP] == 0.0);
   if (compacted) {
     st->F += t[o + D_F];
     st->AF += t[o + D_AF];
@@ -210,6 +289,9 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     st->A1 += t[o + D_A1];
     st->src = side_dst(source, side);
     st->n_src = (int64_t)t[o + D_NOUT];
+    // the side's bracket, within the one the source's sums hold on
+    st->vlo = (side == 0) ? lam : fmax(lo_in, st->vlo);
+    st->vhi = (side == 0) ? fmin(hi_in, st->vhi) : lam;
   } else {
     st->n_src = (int64_t)t[P_NIN];
   }
@@ -223,6 +305,7 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
   st->lo = lo;
   st->hi = hi;
   const double slope = (res < 0.0) ? Qp : Qm;
+  const int ti = st->ntrace;
   trace_push(st, tr, 1, compacted ? 1 : 0, source, lam, phi, slope, (int64_t)t[P_NIN],
              (int64_t)nout);
   st->iter += 1;
@@ -239,8 +322,11 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     next = lam - step;
     secant = (res < 0.0) ? !(next < hi) : !(next > lo);
   } else {
-    // slope zero: the closest breakpoint in the needed direction
+    // slope zero: the closest breakpoint in the needed direction (the
+    // sampled-bracket set is not used for it)
     st->mode = (res < 0.0) ? kModeBreakRight : kModeBreakLeft;
+    if (st->src != 0) st->spend = 0;
+    check_source_bkpt(st);
     return;
   }
   int kind = 3;  // the Newton step
@@ -255,6 +341,11 @@ __device__ __forceinline__ void update_after_eval(GenState* st, const double* t,
     }
   }
   if (next == lam) return finish(st, lam, 2);  // criterion 2, lam_{k-1} = lam_k
+  if (take_spec_set(st, next)) {
+    if (tr != nullptr && ti < st->trace_cap) tr[ti].compacted = 1;
+  } else {
+    check_source_eval(st, next);
+  }
   trace_push(st, tr, kind, 0, source, next, phi, slope, 0, 0);
   advance(st, next);
 }
@@ -291,7 +382,11 @@ __device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks
     return;
   }
   if (hi - lo < tol * fmax(fabs(hi), fabs(lo))) return finish(st, bp, 3);
-  if (!(sw > 0.0)) return;  // still flat past bp: search again from bp
+  if (!(sw > 0.0)) {  // still flat past bp: search again from bp
+    if (st->src != 0) st->spend = 0;
+    check_source_bkpt(st);
+    return;
+  }
   const double step = res / sw;
   double next = bp - step;
   if (fabs(step) < tol) return finish(st, fmin(fmax(next, lo), hi), 2);
@@ -306,6 +401,7 @@ __device__ __forceinline__ void update_after_bkpt(GenState* st, const KeySum* ks
   }
   if (next == bp) return finish(st, bp, 2);
   trace_push(st, tr, kind, 0, st->src, next, phi, sw, 0, 0);
+  if (!take_spec_set(st, next)) check_source_eval(st, next);
   advance(st, next);
 }
 

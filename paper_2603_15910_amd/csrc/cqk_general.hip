@@ -68,6 +68,12 @@ constexpr int kPieceLog = 6;
 constexpr int kPiece = 1 << kPieceLog;  // compacted sets are stored in pieces of this many values
 static_assert(kPiece == kWave, "a full flush writes one piece, one value per lane");
 static_assert(kStage >= kPiece + kWave - 1, "the ring holds a piece plus one slot's survivors");
+// The sampled-bracket pass keeps one side: a ring twice as long, written out
+// kSpecFlush pieces at a time (fewer, larger bursts of stores between the
+// loads of the pass)
+constexpr int kStageSpec = 256;
+constexpr int kSpecFlush = 2;
+static_assert(kStageSpec >= kSpecFlush * kPiece + kWave - 1, "ring of the sampled-bracket pass");
 
 struct GenArgs {
   const void* d;
@@ -85,6 +91,7 @@ struct GenArgs {
                     // values (see Pieces)
   int32_t* cnt[3];  // survivors of each wave in each set
   double* partials;
+  float* smp;       // the sample, 4 floats per index (compaction only)
   GenState* st;
   cqk_trace_rec* trace;
 };
@@ -215,7 +222,14 @@ __device__ __forceinline__ void for_tiles(int64_t count, int64_t first, int64_t 
   }
 }
 
-// One wave streams its tiles.  With COMPACT each index is also classified
+// How a pass treats the indices it evaluates.
+enum PassMode {
+  kEvalOnly = 0,   // phi and its slopes only (both sides marked given up)
+  kTwoSides = 1,   // also compact for both brackets the evaluation can end with
+  kSampled = 2     // also compact for the sampled bracket [lo, hi] (side 0 only)
+};
+
+// One wave streams its tiles.  With kTwoSides each index is also classified
 // for both sides of the evaluation (see eval_index): the survivors of slot e
 // of every lane are staged per side in the wave's slice of LDS (ballot +
 // lane prefix count, slot after slot, so the layout is deterministic and
@@ -224,14 +238,21 @@ __device__ __forceinline__ void for_tiles(int64_t count, int64_t first, int64_t 
 // (D_DROP) as soon as a flush would leave the wave with more than theta
 // times the indices it has read: such a set would not pay for its writes,
 // and a side given up early writes nothing.  At most theta * read + kPiece
-// survivors are ever written, which bounds the wave's region.
+// survivors are ever written, which bounds the wave's region.  With
+// kSampled only side 0 exists, classified on [lo, hi] (spec_index), theta is
+// the share the sample allows, and the ring is written kSpecFlush pieces at
+// a time (at most theta * read + kSpecFlush * kPiece survivors).
 // The LDS operations of one wave complete in issue order, so a lane reads
 // what another lane staged without a wait; the wave-scope fences only keep
 // the compiler from reordering those accesses.
-template <typename Src, bool COMPACT>
+template <typename Src, int MODE>
 __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t stride, double lam,
                           double lo, double hi, double theta, double* const* out, Pieces op,
                           int32_t* const* out_cnt, Acc& acc, double* stg) {
+  constexpr bool COMPACT = MODE != kEvalOnly;
+  constexpr int NSIDE = (MODE == kSampled) ? 1 : 2;
+  constexpr int STG = (MODE == kSampled) ? kStageSpec : kStage;  // ring length
+  constexpr int FP = (MODE == kSampled) ? kSpecFlush : 1;        // pieces per flush
   constexpr int V = Src::V;
   constexpr int E = kUnroll * V;
   constexpr int64_t TILE = (int64_t)kWave * E;
@@ -239,7 +260,7 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
   // per side: values written, ring head, values staged, given up
   int64_t written[2] = {0, 0};
   int head[2] = {0, 0}, pend[2] = {0, 0};
-  bool drop[2] = {false, false};
+  bool drop[2] = {false, MODE == kSampled};
   int64_t seen = 0;  // indices read so far
   // `written` and `head` are multiples of kPiece at every full flush, so a
   // flush fills (the start of) one piece: a full one with 8 bytes per lane
@@ -247,16 +268,16 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
   // streams
   auto flush = [&](int k, int m) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const double* sg = stg + k * 4 * kStage;
+    const double* sg = stg + k * 4 * STG;
     double* const* o = out + 4 * k;
     const int64_t p0 = op.pos(written[k]);
     if (lane < m) {
-      const int q = (head[k] + lane) & (kStage - 1);
+      const int q = (head[k] + lane) & (STG - 1);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(sg[j * kStage + q], &o[j][p0 + lane]);
+      for (int j = 0; j < 4; ++j) __builtin_nontemporal_store(sg[j * STG + q], &o[j][p0 + lane]);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    head[k] = (head[k] + m) & (kStage - 1);
+    head[k] = (head[k] + m) & (STG - 1);
     written[k] += m;
     pend[k] -= m;
   };
@@ -281,44 +302,61 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
       for (int k = 0; k < V; ++k) {
         const int e = w * V + k;
         const bool in = FULL || i + k < count;
-        const int keep = in ? eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi) : 0;
+        int keep = 0;
+        if (MODE == kSampled) {
+          if (in) {
+            eval_index<false>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi);
+            keep = spec_index(acc, c[e], s[e], bl[e], bu[e], lo, hi);
+          }
+        } else {
+          keep = in ? eval_index<COMPACT>(acc, c[e], s[e], bl[e], bu[e], lam, lo, hi) : 0;
+        }
         seen += FULL ? kWave : __popcll(__ballot(in));
         if (COMPACT) {
 #pragma unroll
-          for (int side = 0; side < 2; ++side) {
+          for (int side = 0; side < NSIDE; ++side) {
             if (drop[side]) continue;
             const bool kp = (keep >> side) & 1;
             const uint64_t m = __ballot(kp);
             if (kp) {
-              double* sg = stg + side * 4 * kStage;
-              const int q = (head[side] + pend[side] + lane_prefix(m)) & (kStage - 1);
+              double* sg = stg + side * 4 * STG;
+              const int q = (head[side] + pend[side] + lane_prefix(m)) & (STG - 1);
               sg[q] = c[e];
-              sg[kStage + q] = s[e];
-              sg[2 * kStage + q] = bl[e];
-              sg[3 * kStage + q] = bu[e];
+              sg[STG + q] = s[e];
+              sg[2 * STG + q] = bl[e];
+              sg[3 * STG + q] = bu[e];
             }
             pend[side] += __popcll(m);
-            // pend < kPiece before this slot, so the ring never holds more
-            // than kPiece + 63 <= kStage values
-            if (pend[side] >= kPiece) {
-              if ((double)(written[side] + kPiece) <= theta * (double)seen) flush(side, kPiece);
-              else drop[side] = true;
+            // pend < FP * kPiece before this slot, so the ring never holds
+            // more than FP * kPiece + 63 <= STG values
+            if (pend[side] >= FP * kPiece) {
+              if ((double)(written[side] + FP * kPiece) <= theta * (double)seen) {
+#pragma unroll
+                for (int f = 0; f < FP; ++f) flush(side, kPiece);
+              } else {
+                drop[side] = true;
+              }
             }
           }
         }
       }
     }
   };
-  for_tiles<kPair, kPairUnrollGeneral>(count, first, stride, TILE, tile);
+  // one side's ring leaves registers for both tiles' loads at once
+  for_tiles<kPair, (MODE == kSampled) || kPairUnrollGeneral>(count, first, stride, TILE, tile);
   if (lane == 0) acc.s[P_NIN] += (double)seen;
   if (COMPACT) {
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
+    for (int side = 0; side < NSIDE; ++side) {
       if (!drop[side] && pend[side] > 0) {
-        if ((double)(written[side] + pend[side]) <= theta * (double)seen + kPiece)
-          flush(side, pend[side]);
-        else
+        if ((double)(written[side] + pend[side]) <= theta * (double)seen + FP * kPiece) {
+          if constexpr (FP > 1) {
+            while (pend[side] >= kPiece) flush(side, kPiece);
+          }
+          if (pend[side] > 0) flush(side, pend[side]);
+        } else {
           drop[side] = true;
+        }
       }
       if (lane == 0) {
         *out_cnt[side] = (int32_t)written[side];
@@ -326,6 +364,11 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
         acc.s[P_SIDE + side * D_N + D_DROP] += drop[side] ? 1.0 : 0.0;
       }
     }
+  }
+  // sides that were not written count as given up by every wave
+  if (lane == 0) {
+    if (!COMPACT) acc.s[P_SIDE + D_DROP] += 1.0;
+    if (!COMPACT || NSIDE < 2) acc.s[P_SIDE + D_N + D_DROP] += 1.0;
   }
 }
 
@@ -374,6 +417,8 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   const int src = st->src;
   const bool compact = (mode == kModeEval) && (st->compaction != CQK_COMPACT_OFF);
   const double lam = st->lam, lo = st->lo, hi = st->hi, theta = st->theta;
+  // the sides' brackets stay within the one the source's sums hold on
+  const double clo = fmax(lo, st->vlo), chi = fmin(hi, st->vhi);
   // Passes over the caller's arrays hand tiles to waves grid-stride (tile t
   // to wave t mod NR), so all waves stream through neighbouring addresses;
   // wave rid keeps its survivors (at most `region`) in its pieces of a
@@ -412,11 +457,11 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     if (mode != kModeEval)
       bkpt_pass(s, A.n, first, stride, lam, ks);
     else if (compact)
-      eval_pass<SrcOrig<TIn>, true>(s, A.n, first, stride, lam, lo, hi, theta, out, pc, oc, acc,
-                                    stg);
+      eval_pass<SrcOrig<TIn>, kTwoSides>(s, A.n, first, stride, lam, clo, chi, theta, out, pc,
+                                         oc, acc, stg);
     else
-      eval_pass<SrcOrig<TIn>, false>(s, A.n, first, stride, lam, lo, hi, theta, nullptr, pc,
-                                     nullptr, acc, stg);
+      eval_pass<SrcOrig<TIn>, kEvalOnly>(s, A.n, first, stride, lam, lo, hi, theta, nullptr, pc,
+                                         nullptr, acc, stg);
   } else {
     const double* sb = A.buf[src - 1];
     SrcForm s{sb, sb + plane, sb + 2 * plane, sb + 3 * plane, pc};
@@ -427,10 +472,10 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     if (mode != kModeEval)
       bkpt_pass(s, count, 0, S, lam, ks);
     else if (compact)
-      eval_pass<SrcForm, true>(s, count, 0, S, lam, lo, hi, theta, out, pc, oc, acc, stg);
+      eval_pass<SrcForm, kTwoSides>(s, count, 0, S, lam, clo, chi, theta, out, pc, oc, acc, stg);
     else
-      eval_pass<SrcForm, false>(s, count, 0, S, lam, lo, hi, theta, nullptr, pc, nullptr, acc,
-                                stg);
+      eval_pass<SrcForm, kEvalOnly>(s, count, 0, S, lam, lo, hi, theta, nullptr, pc, nullptr,
+                                    acc, stg);
   }
 
   if (mode == kModeEval) {
@@ -513,6 +558,374 @@ __global__ __launch_bounds__(kBlock) void gen_first_pass_kernel(GenArgs A) {
     rec[P_SIDE + D_DROP] = 1.0;
     rec[P_SIDE + D_N + D_DROP] = 1.0;
     write_partial(A.partials, rec, NPART);
+  }
+}
+
+// The first Newton pass with a sampled bracket: the evaluation at lam_0 of
+// gen_first_pass_kernel, and the indices whose breakpoints fall in the
+// bracket [sp, sq] that gen_sample_kernel estimated written to compacted set
+// 3 (kSpecSet), with the others' contributions summed (spec_index).
+// Only one side's LDS ring.  When the sample gave no bracket, the plain
+// evaluation.
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+  const int64_t nr = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t plane = nr * A.region;
+  const Pieces pc{rid, nr};
+  __shared__ double lds[NPART * (kBlock / kWave)];
+  __shared__ double tot[NPART];
+  __shared__ double stage[kWavesPerBlock * 4 * kStageSpec];
+  double* stg = stage + (threadIdx.x / kWave) * 4 * kStageSpec;
+  Acc acc;
+  acc_init(acc);
+  SrcOrig<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
+                 (const TIn*)A.u};
+  constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrig<TIn>::V;
+  const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
+  const double lam = st->lam;
+  if (st->spec != 0) {
+    double* out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = A.buf[kSpecSet - 1] + j * plane;
+    int32_t* oc[1] = {A.cnt[kSpecSet - 1] + rid};
+    eval_pass<SrcOrig<TIn>, kSampled>(s, A.n, first, stride, lam, st->sp, st->sq, st->scap, out,
+                                      pc, oc, acc, stg);
+  } else {
+    eval_pass<SrcOrig<TIn>, kEvalOnly>(s, A.n, first, stride, lam, 0.0, 0.0, 0.0, nullptr, pc,
+                                       nullptr, acc, stg);
+  }
+  block_reduce<NSUM, 0, 0, kBlock>(acc.s, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, NPART);
+}
+
+// Bracket estimate from a sample (a GPU addition to the variable fixing of
+// Section 2.2, which lets the first pass compact; Algorithm 1 itself is
+// unchanged), in two kernels.
+//
+// gen_sample_kernel: kSmpBlocks blocks read kSmpTiles tiles of 64
+// consecutive indices spread evenly over [0, n), one tile per wave, and
+// store them in the per-index form rounded to float; the last block to
+// finish solves the sampled equation
+//     (n/m) sum_{i in sample} g_i(lam) = r
+// by Newton steps safeguarded by bisection.  By the delta method the
+// solution's standard deviation is sd(g) sqrt(m) / sum_{sample, free} s_i,
+// and the bracket is the solution +- kSmpWidth of those; the share of the
+// sample with a breakpoint in it is counted.
+//
+// gen_sample2_kernel: a sample kS2M / kSmpM times larger (kS2Tiles tiles,
+// in FP64) takes one Newton step of the same equation from the first
+// solution (within a few of the first standard deviations of its own, where
+// the sampled phi is close to linear), with the standard deviation and the
+// bracket as above and the share scaled by the bracket's width.  The share,
+// with a margin, caps what the first pass may keep; a bracket that would
+// keep more than half of theta is not used, nor one from a sample with
+// invalid values (the first pass then only evaluates).  Whether lam* lies in
+// the bracket does not matter for correctness: a pass at a multiplier
+// outside reads the caller's arrays.
+constexpr int kSmpThreads = 512;
+constexpr int kSmpWaves = kSmpThreads / kWave;
+constexpr int kSmpPer = 8;     // sampled indices per thread of the solving block
+constexpr int kSmpTiles = kSmpWaves * kSmpPer;
+constexpr int kSmpBlocks = kSmpTiles / kSmpWaves;
+constexpr int64_t kSmpM = (int64_t)kSmpTiles * kWave;  // first sample's size
+constexpr double kSmpWidth = 5.0;
+constexpr int kSmpIter = 48;
+constexpr int kS2Threads = 256;
+constexpr int kS2Waves = kS2Threads / kWave;
+constexpr int kS2PerWave = 4;  // tiles per wave
+constexpr int kS2Blocks = 256;
+constexpr int kS2Tiles = kS2Blocks * kS2Waves * kS2PerWave;
+constexpr int64_t kS2M = (int64_t)kS2Tiles * kWave;    // second sample's size
+constexpr int64_t kSmpMinN = (int64_t)1 << 22;
+static_assert(kSmpMinN >= (int64_t)kS2Tiles * kWave, "every sampled tile lies inside the arrays");
+
+template <typename TIn>
+__global__ __launch_bounds__(kSmpThreads) void gen_sample_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  {
+    // the host launches this for n >= kSmpMinN only, so span >= 64 and
+    // every tile lies inside [0, n)
+    const int64_t span = A.n / kSmpTiles;
+    const int j = blockIdx.x * kSmpWaves + w;
+    const int64_t i = (int64_t)j * span + lane;
+    const TIn* d = (const TIn*)A.d;
+    const TIn* a = (const TIn*)A.a;
+    const TIn* b = (const TIn*)A.b;
+    const TIn* l = (const TIn*)A.l;
+    const TIn* u = (const TIn*)A.u;
+    double fc, fs, fl, fu, bad = 0.0;
+    to_form((double)d[i], (double)a[i], (double)b[i], (double)l[i], (double)u[i], fc, fs, fl, fu,
+            bad);
+    flt4u v;
+    v.x = (float)fc;
+    v.y = (float)fs;
+    v.z = (float)fl;
+    v.w = (float)fu;
+    const bool fin = __builtin_isfinite(v.x) && __builtin_isfinite(v.y) && v.y > 0.0f &&
+                     !__builtin_isnan(v.z) && !__builtin_isnan(v.w);
+    // an entry that cannot be used is marked by s = NaN
+    if (!(bad == 0.0 && fin)) v.y = __builtin_nanf("");
+    *reinterpret_cast<flt4u*>(A.smp + 4 * ((int64_t)j * kWave + lane)) = v;
+  }
+  // the last block to finish reads every block's stores and solves
+  __shared__ int last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = (atomicAdd(&st->ticket, 1u) == (unsigned)(kSmpBlocks - 1));
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  float c[kSmpPer], s[kSmpPer], bl[kSmpPer], bu[kSmpPer];
+  double nbad = 0.0;
+#pragma unroll
+  for (int k = 0; k < kSmpPer; ++k) {
+    const flt4u v = *reinterpret_cast<const flt4u*>(A.smp + 4 * ((int64_t)k * kSmpThreads + threadIdx.x));
+    c[k] = v.x;
+    s[k] = v.y;
+    bl[k] = v.z;
+    bu[k] = v.w;
+    nbad += __builtin_isnan(v.y) ? 1.0 : 0.0;
+  }
+  __shared__ double red[2][kSmpWaves][4];
+  int par = 0;
+  // block sums of four values, the same in every thread (fixed order)
+  auto bsum = [&](double (&v)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = wave_sum(v[q]);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) red[par][w][q] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double t = 0.0;
+      for (int ww = 0; ww < kSmpWaves; ++ww) t += red[par][ww][q];
+      v[q] = t;
+    }
+    par ^= 1;
+  };
+  const double m = (double)kSmpM;
+  const double rs = st->r * (m / (double)A.n);
+  double lam = (double)(float)st->lam, lo = -inf_d(), hi = inf_d();
+  bool found = false;
+  {
+    double v[4] = {nbad, 0.0, 0.0, 0.0};
+    bsum(v);
+    nbad = v[0];
+  }
+  // per-thread sums in float (the sample is float), block sums in double
+  for (int it = 0; it < kSmpIter && nbad == 0.0; ++it) {
+    const float lf = (float)lam;
+    float t4[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kSmpPer; ++k) {
+      const float f = fmaf(s[k], lf, c[k]);
+      const float g = fminf(fmaxf(f, bl[k]), bu[k]);
+      t4[0] += g;
+      t4[1] += fabsf(g);
+      t4[2] += (f >= bl[k] && f < bu[k]) ? s[k] : 0.0f;
+      t4[3] += (f > bl[k] && f <= bu[k]) ? s[k] : 0.0f;
+    }
+    double v[4] = {t4[0], t4[1], t4[2], t4[3]};
+    bsum(v);
+    const double res = v[0] - rs;
+    if (fabs(res) <= 1e-7 * (v[1] + fabs(rs))) {
+      found = true;
+      break;
+    }
+    if (res < 0.0) lo = lam;
+    else hi = lam;
+    const double slope = (res < 0.0) ? v[2] : v[3];
+    double next = (slope > 0.0) ? lam - res / slope : lam;
+    if (!(next > lo && next < hi)) {
+      if (lo > -inf_d() && hi < inf_d()) next = 0.5 * (lo + hi);
+      else next = (res < 0.0) ? lam + (1.0 + fabs(lam)) : lam - (1.0 + fabs(lam));
+    }
+    // the multiplier is kept in float: a step that float cannot resolve ends
+    // the search at the root's float resolution
+    const double nf = (double)(float)next;
+    if (nf == lam) {
+      found = true;
+      break;
+    }
+    lam = nf;
+  }
+  double p = __builtin_nan(""), q = __builtin_nan(""), sdl = 0.0, share = 1.0;
+  if (found) {
+    const float lf = (float)lam;
+    float t3[3] = {0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int k = 0; k < kSmpPer; ++k) {
+      const float f = fmaf(s[k], lf, c[k]);
+      const float g = fminf(fmaxf(f, bl[k]), bu[k]);
+      t3[0] += g;
+      t3[1] += g * g;
+      t3[2] += (f > bl[k] && f < bu[k]) ? s[k] : 0.0f;
+    }
+    double v[4] = {t3[0], t3[1], t3[2], 0.0};
+    bsum(v);
+    const double mean = v[0] / m;
+    const double sdg = sqrt(fmax(v[1] / m - mean * mean, 0.0));
+    sdl = (v[2] > 0.0) ? sdg * sqrt(m) / v[2] : 0.0;
+    const double half = kSmpWidth * sdl;
+    if (half > 0.0 && half < inf_d()) {
+      p = lam - half;
+      q = lam + half;
+      const float pf = (float)p, qf = (float)q;
+      float kept = 0.0f;
+#pragma unroll
+      for (int k = 0; k < kSmpPer; ++k) {
+        const float fp = fmaf(s[k], pf, c[k]);
+        const float fq = fmaf(s[k], qf, c[k]);
+        const bool at_l = fq <= bl[k], at_u = fp >= bu[k];
+        const bool fr = !at_l && !at_u && fp >= bl[k] && fq <= bu[k] && (fp >= 0.0f || fq <= 0.0f);
+        kept += (at_l || at_u || fr) ? 0.0f : 1.0f;
+      }
+      double w4[4] = {kept, 0.0, 0.0, 0.0};
+      bsum(w4);
+      share = w4[0] / m;
+    }
+  }
+  if (threadIdx.x == 0) {
+    st->s1ok = (p < q) ? 1 : 0;
+    st->s1lam = lam;
+    st->s1half = (p < q) ? 0.5 * (q - p) : 0.0;
+    st->s1share = share;
+    st->ticket = 0;
+    st->passes += 1;
+    st->bytes += st->in_bytes * m;
+    if (st->ntrace < st->trace_cap) {
+      cqk_trace_rec& t = A.trace[st->ntrace];
+      t.iter = st->iter;
+      t.kind = 8;
+      t.compacted = 0;
+      t.source = 0;
+      t.lam = lam;
+      t.phi = sdl;
+      t.slope = share;
+      t.lo = p;
+      t.hi = q;
+      t.n_in = kSmpM;
+      t.n_out = (int64_t)(share * (double)A.n);
+    }
+    st->ntrace += 1;
+  }
+}
+
+template <typename TIn>
+__global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const bool ok1 = st->s1ok != 0;
+  // sum g, sum g^2, sum of s over the free indices, invalid entries
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (ok1) {
+    const double lam = st->s1lam;
+    // n >= kSmpMinN: span >= 64, every tile inside [0, n)
+    const int64_t span = A.n / kS2Tiles;
+    const TIn* d = (const TIn*)A.d;
+    const TIn* a = (const TIn*)A.a;
+    const TIn* b = (const TIn*)A.b;
+    const TIn* l = (const TIn*)A.l;
+    const TIn* u = (const TIn*)A.u;
+    TIn vd[kS2PerWave], va[kS2PerWave], vb[kS2PerWave], vl[kS2PerWave], vu[kS2PerWave];
+#pragma unroll
+    for (int k = 0; k < kS2PerWave; ++k) {
+      const int j = (k * kS2Blocks + (int)blockIdx.x) * kS2Waves + w;
+      const int64_t i = (int64_t)j * span + lane;
+      vd[k] = d[i];
+      va[k] = a[i];
+      vb[k] = b[i];
+      vl[k] = l[i];
+      vu[k] = u[i];
+    }
+#pragma unroll
+    for (int k = 0; k < kS2PerWave; ++k) {
+      double c, s, bl, bu, bad = 0.0;
+      to_form((double)vd[k], (double)va[k], (double)vb[k], (double)vl[k], (double)vu[k], c, s,
+              bl, bu, bad);
+      const double f = fma(s, lam, c);
+      const double g = fmin(fmax(f, bl), bu);
+      const bool fin = __builtin_isfinite(g) && __builtin_isfinite(s);
+      v[0] += fin ? g : 0.0;
+      v[1] += fin ? g * g : 0.0;
+      v[2] += (fin && f > bl && f < bu) ? s : 0.0;
+      v[3] += (bad == 0.0 && fin) ? 0.0 : 1.0;
+    }
+  }
+  __shared__ double lds[4 * kS2Waves];
+  __shared__ double tot[4];
+  block_reduce<4, 0, 0, kS2Threads>(v, nullptr, nullptr, lds, tot);
+  // the last block to finish combines the blocks' records in block order
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    write_partial(A.partials, tot, 4);
+    __threadfence();
+    last = (atomicAdd(&st->ticket, 1u) == (unsigned)(kS2Blocks - 1));
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  __shared__ double rl[4 * kS2Waves];
+  __shared__ double all[4];
+  reduce_partials<4, 0, 0, kS2Threads>(A.partials, kS2Blocks, rl, all);
+  if (threadIdx.x == 0) {
+    const double m = (double)kS2M;
+    const double theta = st->theta;
+    double lam = __builtin_nan(""), p = __builtin_nan(""), q = __builtin_nan("");
+    double sdl = 0.0, share = 1.0;
+    bool use = false;
+    if (ok1 && all[3] == 0.0 && all[2] > 0.0) {
+      lam = st->s1lam - (all[0] - st->r * (m / (double)A.n)) / all[2];
+      const double mean = all[0] / m;
+      sdl = sqrt(fmax(all[1] / m - mean * mean, 0.0)) * sqrt(m) / all[2];
+      const double half = kSmpWidth * sdl;
+      // the step stays within the first bracket, where one step is accurate
+      if (half > 0.0 && half < inf_d() && fabs(lam - st->s1lam) < st->s1half) {
+        p = lam - half;
+        q = lam + half;
+        share = st->s1share * (half / st->s1half);
+      }
+    }
+    if (!(p < q) && ok1) {
+      // the first estimate's bracket
+      lam = st->s1lam;
+      p = st->s1lam - st->s1half;
+      q = st->s1lam + st->s1half;
+      share = st->s1share;
+    }
+    use = (p < q) && (share < 0.5 * theta);
+    st->sp = use ? p : __builtin_nan("");
+    st->sq = use ? q : __builtin_nan("");
+    st->scap = use ? fmin(theta, 1.5 * share + 1.0 / 32.0) : 0.0;
+    st->spec = use ? 1 : 0;
+    st->ticket = 0;
+    st->passes += 1;
+    st->bytes += st->in_bytes * m;
+    if (st->ntrace < st->trace_cap) {
+      cqk_trace_rec& t = A.trace[st->ntrace];
+      t.iter = st->iter;
+      t.kind = 9;
+      t.compacted = use ? 1 : 0;
+      t.source = 0;
+      t.lam = lam;
+      t.phi = sdl;
+      t.slope = share;
+      t.lo = p;
+      t.hi = q;
+      t.n_in = kS2M;
+      t.n_out = (int64_t)(share * (double)A.n);
+    }
+    st->ntrace += 1;
   }
 }
 
@@ -797,12 +1210,12 @@ int choose_grid(int64_t n, int num_cus) {
 // G blocks of kWavesPerBlock waves.  A pass over the caller's arrays hands
 // its steps (kPair adjacent tiles of 64 lanes x kUnroll vectors of `vec`
 // values) to the NR waves grid-stride, at most `tpw` steps each (chunk = tpw
-// steps).  A wave keeps at most theta * chunk + kPiece survivors of a side
-// (eval_pass), so its region in a compacted set holds that many values,
+// steps).  A wave keeps at most theta * chunk + kSpecFlush * kPiece survivors
+// of a side (eval_pass), so its region in a compacted set holds that many values,
 // rounded up to whole pieces.  The primal recovery runs grid-stride on its
 // own grid GF of 4-vector tiles.  Workspace: partials | counts (3 x NR) |
-// three compacted sets (4 planes of NR x region doubles each, only with
-// compaction).
+// with compaction: the sample of gen_sample_kernel and three compacted sets
+// (4 planes of NR x region doubles each).
 GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta) {
   GenLayout L{};
   const int64_t T = (int64_t)kWave * kUnroll * vec * kPair;
@@ -815,7 +1228,7 @@ GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double th
   L.G = (int)std::max<int64_t>(1, (n + bchunk - 1) / bchunk);
   L.NR = L.G * kWavesPerBlock;
   const double th = std::min(1.0, std::max(0.0, theta));
-  const int64_t keep = (int64_t)std::ceil(th * (double)L.chunk) + kPiece;
+  const int64_t keep = (int64_t)std::ceil(th * (double)L.chunk) + kSpecFlush * kPiece;
   // a multiple of kPiece (so of 16): every plane starts a 128-byte line
   L.region = std::min<int64_t>((L.chunk + kPiece - 1) / kPiece * kPiece,
                                (keep + kPiece - 1) / kPiece * kPiece);
@@ -825,7 +1238,9 @@ GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double th
   L.cnt_bytes = ((size_t)3 * L.NR * sizeof(int32_t) + 255) / 256 * 256;
   const size_t buf_bytes =
       compaction ? (size_t)3 * 4 * (size_t)L.NR * (size_t)L.region * sizeof(double) : 0;
-  L.bytes = L.part_bytes + L.cnt_bytes + buf_bytes;
+  // the sampled-bracket estimate's sample (4 floats per index)
+  L.smp_bytes = compaction ? (size_t)kSmpM * 4 * sizeof(float) : 0;
+  L.bytes = L.part_bytes + L.cnt_bytes + L.smp_bytes + buf_bytes;
   return L;
 }
 
@@ -871,7 +1286,8 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   A.cnt[1] = A.cnt[0] + NR;
   A.cnt[2] = A.cnt[1] + NR;
   if (compaction) {
-    double* bb = (double*)(ws + part_bytes + cnt_bytes);
+    A.smp = (float*)(ws + part_bytes + cnt_bytes);
+    double* bb = (double*)(ws + part_bytes + cnt_bytes + Lg.smp_bytes);
     for (int k = 0; k < 3; ++k) A.buf[k] = bb + (size_t)k * 4 * NR * Lg.region;
   }
   A.st = (GenState*)ctx->state.ptr;
@@ -891,6 +1307,10 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.tol = (o.tol > 0.0) ? o.tol : std::pow(eps, 0.75);
   init.theta = theta;
   init.n_src = n;
+  init.n_all = n;
+  init.vlo = -__builtin_huge_val();
+  init.vhi = __builtin_huge_val();
+  init.sp = init.sq = __builtin_nan("");
   init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
   init.max_iter = o.max_iter;
@@ -936,13 +1356,31 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   else if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
     launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel);
 
+  // With compaction on large inputs, a bracket estimated from a sample lets
+  // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
+  // kSmpMinN the sample costs more than it saves.
+  // (the second estimate's block records use the partials buffer)
+  const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * 4;
+  if (sampled) {
+    bool rec = timing && ev + 2 <= (int)nev;
+    launch_timed(gen_sample_kernel<TIn>, dim3(kSmpBlocks), dim3(kSmpThreads), s,
+                 rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A);
+    if (rec) ev += 2;
+    rec = timing && ev + 2 <= (int)nev;
+    launch_timed(gen_sample2_kernel<TIn>, dim3(kS2Blocks), dim3(kS2Threads), s,
+                 rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A);
+    if (rec) ev += 2;
+    npass += 2;
+  }
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;
-  // the first Newton pass always evaluates the caller's arrays without
-  // compaction: the lean kernel; every later pass the general one
+  // the first Newton pass evaluates the caller's arrays: with the sampled
+  // bracket it also compacts for it, else the lean kernel runs; every later
+  // pass the general one
   auto pass = [&]() {
-    if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel);
+    if (launched == 0 && sampled) launch(gen_spec_pass_kernel<TIn>, gen_update_kernel);
+    else if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel);
     else launch(gen_pass_kernel<TIn>, gen_update_kernel);
     ++launched;
   };

@@ -39,12 +39,30 @@ struct GenState {
   double res_P, res_A;            // finalize: b^T x and sum |b x|
   double bytes;                   // algorithmic bytes of the grid passes so far
   double in_bytes;                // bytes per index of the caller's arrays
+  // The dropped-index sums of the current source hold for lam in [vlo, vhi]
+  // (the caller's arrays: everywhere); a pass at a multiplier outside it
+  // reads the caller's arrays again.
+  double vlo, vhi;
+  // Bracket [sp, sq] estimated from a sample of the indices, and the share of
+  // indices the first pass may keep for it (sp < sq only when in use); the
+  // dropped-index sums and size of the set the first pass wrote for it,
+  // while that set waits in set 3 for an iterate inside (spend = 1)
+  double sp, sq, scap;
+  double sF, sAF, sC0, sC1, sA0, sA1;
+  int64_t sn;
+  // the first estimate (solution, bracket half-width, share of the sample
+  // inside), refined by the second
+  double s1lam, s1half, s1share;
   int64_t n_src;                  // indices in the current source
+  int64_t n_all;                  // indices of the caller's arrays
   int64_t n_free;                 // finalize: free indices
   int32_t status, iter, passes, mode, src, stop_reason, max_iter;
   int32_t compaction, trace_cap, ntrace, nblocks;
   uint32_t ticket;
-  int32_t pad_[4];
+  int32_t spec;                   // 1: the next evaluation writes the sampled-bracket set
+  int32_t spend;                  // 1: that set waits in set 3
+  int32_t s1ok;                   // 1: the first estimate found a bracket
+  int32_t pad_[1];
 };
 
 // Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).
@@ -142,7 +160,7 @@ void fill_default_opts(cqk_opts* o);
 struct GenLayout {
   int G, NR, GF;
   int64_t chunk, region;
-  size_t part_bytes, cnt_bytes, bytes;
+  size_t part_bytes, cnt_bytes, smp_bytes, bytes;
 };
 // theta: the largest survivor fraction a compacted set may keep (1: any)
 GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta);
