@@ -1,14 +1,16 @@
 """Benchmark: general CQK solve, n = 1e8, FP64, on one MI355X.
 
-One step = one whole solve (cqk_solve_f64: the Newton passes with compaction
-of resolved indices, then the x-writing pass) over inputs already resident in
-HBM, with the compaction threshold theta tuned on the instance first
-(cqk_tune_theta_f64; --theta fixes it instead).  Prints one JSON line: the metric (elements/s = n / ms per solve), the
-roofline of the pass kernel (algorithmic bytes per launch over its average
-launch time from HIP events stamped by its dispatches in the timed region,
-against 8 TB/s, and the measured HBM traffic per launch when the committed
-counter summary matches the kernel source), each pass of one solve (indices
-read, bytes, µs, GB/s), the same solve on seeds 1-3 of both n = 1e8
+One step = one whole solve (cqk_solve_f64: the sampled-bracket estimate, the
+Newton passes with compaction of resolved indices, then the x-writing pass)
+over inputs already resident in HBM, with the compaction threshold theta
+tuned on the instance first (cqk_tune_theta_f64; --theta fixes it instead).
+Prints one JSON line: the metric (elements/s = n / ms per solve), the
+roofline of the first Newton pass and of the x-writing pass (algorithmic
+bytes per launch over the average launch time from HIP events stamped by the
+dispatches in the timed region, against 8 TB/s, and the measured HBM traffic
+per launch when the committed counter summary matches the kernel source),
+each pass of one solve (indices read, bytes, µs, GB/s), the same solve on
+seeds 1-3 of both n = 1e8
 generators, the n = 1e5 latency case (seeds 1-20, median over seeds of the
 best run), the oracle's CPU rate (best of 3 on a 1e7 sample, best of 10 at
 1e5), and "extras": the other workloads (correlated CQK, simplex and l1 at
@@ -38,7 +40,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gen_pass_kernel_cqk_uniform_1e8.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gen_kernels_cqk_uniform_1e8.traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2603_15910_amd", "csrc", "cqk_general.hip")
 
 
@@ -93,9 +95,9 @@ def cpu_baseline(n_sample: int, reps: int = 3, full: bool = False):
     return out
 
 
-def measured_traffic(kernel_sha):
-    """HBM bytes per launch of the pass kernel from the committed counter
-    summary, if it was taken on the current kernel source."""
+def measured_traffic(kernel_sha, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -103,7 +105,7 @@ def measured_traffic(kernel_sha):
         return None
     if rec.get("kernel_source_sha256") != kernel_sha:
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", {}).get(kernel)
 
 
 def timed(fn, reps, sync):
@@ -655,7 +657,7 @@ def main():
     torch.cuda.synchronize()
 
     log(f"bench: timing {args.steps} steps")
-    infos = []
+    infos, per_pass = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -663,6 +665,7 @@ def main():
         # summed on the device (no per-pass trace copied back in here)
         _, info = ctx.solve(*t, r, out=x, timing=True)
         infos.append(info)
+        per_pass.append(ctx.pass_ms())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms = dt * 1e3 / args.steps
@@ -670,15 +673,23 @@ def main():
 
     pass_bytes = sum(i["pass_bytes"] for i in infos)
     pass_ms = sum(i["pass_ms"] for i in infos)
-    # every launch of the pass kernel, as a kernel trace counts them
+    # every launch of the pass kernels, as a kernel trace counts them
     passes = sum(i["pass_launches"] for i in infos)
     achieved = pass_bytes / (pass_ms * 1e-3) / 1e9 if pass_ms > 0 else 0.0
-    fin_gbs = (sum(i["finalize_bytes"] for i in infos) /
-               (sum(i["finalize_ms"] for i in infos) * 1e-3) / 1e9)
+    fin_ms = statistics.mean(i["finalize_ms"] for i in infos)
+    fin_bytes = infos[-1]["finalize_bytes"]
+    fin_gbs = fin_bytes / (fin_ms * 1e-3) / 1e9
     # after the timed region: the per-pass log with each pass's kernel time
     ctx.solve(*t, r, out=x, trace=True, timing=True)
     tr = ctx.trace()
     passes_tab, tail_us = pass_table(ctx)
+    # the first Newton pass (over the caller's arrays, compacting for the
+    # sampled bracket): its algorithmic bytes from the traced solve (the same
+    # in every solve of this instance), its time in each timed solve
+    k_first = next(k for k, p in enumerate(passes_tab) if p["kind"] == "evaluate")
+    first_bytes = passes_tab[k_first]["bytes"]
+    first_ms = statistics.mean(p[k_first] for p in per_pass)
+    first_gbs = first_bytes / (first_ms * 1e-3) / 1e9
     # context beside the headline (not the metric): the eq. (CQKlambda0) start
     # on the same instance, and the device-copy ceiling of this part
     ctx.solve(*t, r, out=x, lambda0="formula")
@@ -712,16 +723,34 @@ def main():
                    "n": n, "seed": 1},
         "roofline": {
             "bound": "hbm",
-            "kernel": "gen_first_pass_kernel + gen_pass_kernel <double> (evaluation passes)",
-            "achieved": achieved,
+            "kernel": "gen_spec_pass_kernel<double> (the first Newton pass)",
+            "achieved": first_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(sha),
-            "launches": passes,
-            "avg_launch_ms": pass_ms / max(passes, 1),
-            "avg_launch_bytes": pass_bytes / max(passes, 1),
+            "frac": first_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(sha, "gen_spec_pass_kernel"),
+            "launches": len(per_pass),
+            "avg_launch_ms": first_ms,
+            "avg_launch_bytes": first_bytes,
         },
+        # the x-writing pass, about as long: 40 B read + 8 B written per index
+        "roofline_finalize": {
+            "bound": "hbm",
+            "kernel": "gen_finalize_kernel<double>",
+            "achieved": fin_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": fin_gbs / HBM_PEAK_GBS,
+            "traffic": measured_traffic(sha, "gen_finalize_kernel"),
+            "launches": len(infos),
+            "avg_launch_ms": fin_ms,
+            "avg_launch_bytes": fin_bytes,
+        },
+        # every pass kernel launch of the timed solves (the sample kernels,
+        # the Newton passes, those queued after the loop stopped)
+        "passes_all": {"achieved": achieved, "frac": achieved / HBM_PEAK_GBS,
+                       "launches": passes, "avg_launch_ms": pass_ms / max(passes, 1),
+                       "avg_launch_bytes": pass_bytes / max(passes, 1)},
         "iterations": infos[-1]["iterations"],
         "theta": {"chosen": theta, "tuned": args.theta <= 0.0, "tuned_ms": theta_ms,
                   "sweep_ms": {str(k): v for k, v in theta_sweep.items()}},

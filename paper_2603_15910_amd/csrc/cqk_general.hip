@@ -603,7 +603,7 @@ __global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
 
 // Bracket estimate from a sample (a GPU addition to the variable fixing of
 // Section 2.2, which lets the first pass compact; Algorithm 1 itself is
-// unchanged), in two kernels.
+// unchanged), in three kernels.
 //
 // gen_sample_kernel: kSmpBlocks blocks read kSmpTiles tiles of 64
 // consecutive indices spread evenly over [0, n), one tile per wave, and
@@ -615,16 +615,18 @@ __global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
 // and the bracket is the solution +- kSmpWidth of those; the share of the
 // sample with a breakpoint in it is counted.
 //
-// gen_sample2_kernel: a sample kS2M / kSmpM times larger (kS2Tiles tiles,
-// in FP64) takes one Newton step of the same equation from the first
-// solution (within a few of the first standard deviations of its own, where
-// the sampled phi is close to linear), with the standard deviation and the
-// bracket as above and the share scaled by the bracket's width.  The share,
-// with a margin, caps what the first pass may keep; a bracket that would
-// keep more than half of theta is not used, nor one from a sample with
-// invalid values (the first pass then only evaluates).  Whether lam* lies in
-// the bracket does not matter for correctness: a pass at a multiplier
-// outside reads the caller's arrays.
+// gen_sample2_kernel and gen_sample2_reduce_kernel: a sample kS2M / kSmpM
+// times larger (kS2Tiles tiles in FP64, summed per block, the block records
+// combined in order by one block) takes one Newton step of the same
+// equation from the first solution (within a few of the first standard
+// deviations of its own, where the sampled phi is close to linear).  The
+// bracket is set as above, widened to take in Algorithm 1's first iterate
+// as the sample predicts it when that is near, and the share is scaled by
+// the bracket's width.  The share, with a margin, caps what the first pass
+// may keep; a bracket that would keep more than half of theta is not used,
+// nor one from a sample with invalid values (the first pass then only
+// evaluates).  Whether lam* lies in the bracket does not matter for
+// correctness: a pass at a multiplier outside reads the caller's arrays.
 constexpr int kSmpThreads = 512;
 constexpr int kSmpWaves = kSmpThreads / kWave;
 constexpr int kSmpPer = 8;     // sampled indices per thread of the solving block
@@ -635,8 +637,10 @@ constexpr double kSmpWidth = 5.0;
 constexpr int kSmpIter = 48;
 constexpr int kS2Threads = 256;
 constexpr int kS2Waves = kS2Threads / kWave;
-constexpr int kS2PerWave = 4;  // tiles per wave
-constexpr int kS2Blocks = 256;
+constexpr int kS2PerWave = 8;  // tiles per wave
+constexpr int kS2Blocks = 512;
+constexpr double kS2Lam1Width = 4.0;
+enum { S2_G = 0, S2_G2, S2_SF, S2_BAD, S2_G0, S2_QP0, S2_QM0, S2_N };
 constexpr int kS2Tiles = kS2Blocks * kS2Waves * kS2PerWave;
 constexpr int64_t kS2M = (int64_t)kS2Tiles * kWave;    // second sample's size
 constexpr int64_t kSmpMinN = (int64_t)1 << 22;
@@ -673,11 +677,15 @@ __global__ __launch_bounds__(kSmpThreads) void gen_sample_kernel(GenArgs A) {
     if (!(bad == 0.0 && fin)) v.y = __builtin_nanf("");
     *reinterpret_cast<flt4u*>(A.smp + 4 * ((int64_t)j * kWave + lane)) = v;
   }
-  // the last block to finish reads every block's stores and solves
+  // the last block to finish reads every block's stores and solves (the
+  // block's stores reach its L2 before the barrier; one device-scope release
+  // by thread 0 then publishes them with the ticket)
   __shared__ int last;
-  __threadfence();
   __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&st->ticket, 1u) == (unsigned)(kSmpBlocks - 1));
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = (atomicAdd(&st->ticket, 1u) == (unsigned)(kSmpBlocks - 1));
+  }
   __syncthreads();
   if (!last) return;
   __threadfence();
@@ -826,10 +834,11 @@ __global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
   const bool ok1 = st->s1ok != 0;
-  // sum g, sum g^2, sum of s over the free indices, invalid entries
-  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  // at the first solution: sum g, sum g^2, sum of s over the free indices;
+  // invalid entries; at lam_0: sum g and the one-sided slope sums
+  double v[S2_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (ok1) {
-    const double lam = st->s1lam;
+    const double lam = st->s1lam, lam0 = st->lam;
     // n >= kSmpMinN: span >= 64, every tile inside [0, n)
     const int64_t span = A.n / kS2Tiles;
     const TIn* d = (const TIn*)A.d;
@@ -855,45 +864,63 @@ __global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
               bl, bu, bad);
       const double f = fma(s, lam, c);
       const double g = fmin(fmax(f, bl), bu);
-      const bool fin = __builtin_isfinite(g) && __builtin_isfinite(s);
-      v[0] += fin ? g : 0.0;
-      v[1] += fin ? g * g : 0.0;
-      v[2] += (fin && f > bl && f < bu) ? s : 0.0;
-      v[3] += (bad == 0.0 && fin) ? 0.0 : 1.0;
+      const double f0 = fma(s, lam0, c);
+      const double g0 = fmin(fmax(f0, bl), bu);
+      const bool fin = __builtin_isfinite(g) && __builtin_isfinite(s) && __builtin_isfinite(g0);
+      v[S2_G] += fin ? g : 0.0;
+      v[S2_G2] += fin ? g * g : 0.0;
+      v[S2_SF] += (fin && f > bl && f < bu) ? s : 0.0;
+      v[S2_BAD] += (bad == 0.0 && fin) ? 0.0 : 1.0;
+      v[S2_G0] += fin ? g0 : 0.0;
+      v[S2_QP0] += (fin && f0 >= bl && f0 < bu) ? s : 0.0;
+      v[S2_QM0] += (fin && f0 > bl && f0 <= bu) ? s : 0.0;
     }
   }
-  __shared__ double lds[4 * kS2Waves];
-  __shared__ double tot[4];
-  block_reduce<4, 0, 0, kS2Threads>(v, nullptr, nullptr, lds, tot);
-  // the last block to finish combines the blocks' records in block order
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    write_partial(A.partials, tot, 4);
-    __threadfence();
-    last = (atomicAdd(&st->ticket, 1u) == (unsigned)(kS2Blocks - 1));
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  __shared__ double rl[4 * kS2Waves];
-  __shared__ double all[4];
-  reduce_partials<4, 0, 0, kS2Threads>(A.partials, kS2Blocks, rl, all);
+  __shared__ double lds[S2_N * kS2Waves];
+  __shared__ double tot[S2_N];
+  block_reduce<S2_N, 0, 0, kS2Threads>(v, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, S2_N);
+}
+
+// Combines gen_sample2_kernel's block records in block order and sets the
+// bracket (one block).
+__global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const bool ok1 = st->s1ok != 0;
+  __shared__ double rl[S2_N * (kRBlock / kWave)];
+  __shared__ double all[S2_N];
+  reduce_partials<S2_N, 0, 0, kRBlock>(A.partials, kS2Blocks, rl, all);
   if (threadIdx.x == 0) {
     const double m = (double)kS2M;
     const double theta = st->theta;
+    const double rs = st->r * (m / (double)A.n);
     double lam = __builtin_nan(""), p = __builtin_nan(""), q = __builtin_nan("");
     double sdl = 0.0, share = 1.0;
     bool use = false;
-    if (ok1 && all[3] == 0.0 && all[2] > 0.0) {
-      lam = st->s1lam - (all[0] - st->r * (m / (double)A.n)) / all[2];
-      const double mean = all[0] / m;
-      sdl = sqrt(fmax(all[1] / m - mean * mean, 0.0)) * sqrt(m) / all[2];
+    if (ok1 && all[S2_BAD] == 0.0 && all[S2_SF] > 0.0) {
+      lam = st->s1lam - (all[S2_G] - rs) / all[S2_SF];
+      const double mean = all[S2_G] / m;
+      sdl = sqrt(fmax(all[S2_G2] / m - mean * mean, 0.0)) * sqrt(m) / all[S2_SF];
       const double half = kSmpWidth * sdl;
       // the step stays within the first bracket, where one step is accurate
       if (half > 0.0 && half < inf_d() && fabs(lam - st->s1lam) < st->s1half) {
         p = lam - half;
         q = lam + half;
-        share = st->s1share * (half / st->s1half);
+        // Algorithm 1's first iterate, predicted from the sample: the
+        // bracket also takes it in (with kS2Lam1Width deviations of margin)
+        // when that at most doubles its width, so that the second pass
+        // already reads the set
+        const double res0 = all[S2_G0] - rs;
+        const double sl0 = (res0 < 0.0) ? all[S2_QP0] : all[S2_QM0];
+        const double lam1 = (sl0 > 0.0) ? st->lam - res0 / sl0 : __builtin_nan("");
+        const double p1 = fmin(p, lam1 - kS2Lam1Width * sdl);
+        const double q1 = fmax(q, lam1 + kS2Lam1Width * sdl);
+        if (q1 - p1 <= 4.0 * half) {
+          p = p1;
+          q = q1;
+        }
+        share = st->s1share * ((q - p) / (2.0 * st->s1half));
       }
     }
     if (!(p < q) && ok1) {
@@ -908,7 +935,6 @@ __global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
     st->sq = use ? q : __builtin_nan("");
     st->scap = use ? fmin(theta, 1.5 * share + 1.0 / 32.0) : 0.0;
     st->spec = use ? 1 : 0;
-    st->ticket = 0;
     st->passes += 1;
     st->bytes += st->in_bytes * m;
     if (st->ntrace < st->trace_cap) {
@@ -1360,7 +1386,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
   // kSmpMinN the sample costs more than it saves.
   // (the second estimate's block records use the partials buffer)
-  const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * 4;
+  const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * S2_N;
   if (sampled) {
     bool rec = timing && ev + 2 <= (int)nev;
     launch_timed(gen_sample_kernel<TIn>, dim3(kSmpBlocks), dim3(kSmpThreads), s,
@@ -1370,6 +1396,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     launch_timed(gen_sample2_kernel<TIn>, dim3(kS2Blocks), dim3(kS2Threads), s,
                  rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
+    hipLaunchKernelGGL(gen_sample2_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A);
     npass += 2;
   }
   GenState* hs = (GenState*)ctx->host_pinned;

@@ -14,8 +14,8 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
-# the two samples: 64 and 4096 tiles of 64 indices spread evenly
-SAMPLE_TILES = (64, 4096)
+# the two samples: 64 and 16384 tiles of 64 indices spread evenly
+SAMPLE_TILES = (64, 16384)
 
 
 @pytest.fixture(scope="module")
@@ -136,14 +136,14 @@ def test_iterate_outside_the_sampled_bracket_reads_the_arrays_again(ctx):
     inst["l"][pos] = -50.0
     inst["u"][pos] = 50.0
     target = 0.0
-    for _ in range(4):
+    for _ in range(12):
         # sampled equation: sum_S (a_i + lam) = r m / n at lam = lam_1
         inst["r"] = float(np.dot(inst["b"], (inst["l"] + inst["u"]) / 2))
         inst["a"][pos] = inst["r"] / n - target + noise
         target = _newton_from_zero(inst)
     inst["r"] = float(np.dot(inst["b"], (inst["l"] + inst["u"]) / 2))
     ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
-    assert abs(ref.lam - target) > 1e-3      # lam* well outside the bracket
+    assert abs(ref.lam - target) > 1e-4      # lam* far outside the bracket (~3e-6)
     x, info, tr = _solve(ctx, inst, compaction="auto")
     assert info["status"] == 0, info
     check_cqk(x, inst, ref, 1e-10)
