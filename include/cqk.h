@@ -123,7 +123,11 @@ typedef struct cqk_opts {
   int32_t accum;            /* cqk_accum */
   int32_t sync;             /* 1 (default): wait and fill *info */
   int32_t trace;            /* 1: record one cqk_trace_rec per pass */
-  int32_t timing;           /* 1: time every pass kernel with HIP events */
+  int32_t timing;           /* 1: time every pass kernel with HIP events;
+                               2 (general CQK): only the first Newton pass
+                               and the x-writing pass, so the others run
+                               without the gaps the runtime leaves around a
+                               timed dispatch (other calls: as 1) */
 } cqk_opts;
 
 typedef struct cqk_info {
@@ -224,14 +228,15 @@ cqk_status cqk_ctx_last_info(cqk_ctx* ctx, cqk_info* info);
 cqk_status cqk_last_trace(cqk_ctx* ctx, cqk_trace_rec* out, int32_t cap, int32_t* count);
 /* Kernel time in milliseconds of each grid pass of the last single-instance
  * call made with opts->timing = 1 and sync = 1 (cqk_solve_*,
- * cqk_project_*), in the order the passes were queued: the lambda_0 pass
- * or the Algorithm 2 sample and filtering passes if any, then the Newton
- * passes, including those queued
- * after the loop had stopped, which return at once.  The x-writing pass is
- * not included (info->finalize_ms).  Copies min(cap, count) values; *count
+ * cqk_project_*), in the order the passes were queued: the lambda_0 pass,
+ * the two sampled-bracket kernels or the Algorithm 2 sample and filtering
+ * passes if any, then the Newton passes, including those queued after the
+ * loop had stopped, which return at once.  With opts->timing = 2 a general
+ * solve lists its first Newton pass only.  The x-writing pass is not
+ * included (info->finalize_ms).  Copies min(cap, count) values; *count
  * receives the number of passes.  The list is refilled whenever a
  * single-instance call's info is filled (sync = 1, or cqk_ctx_last_info) and
- * is empty unless that call had opts->timing = 1 and sync = 1; batched calls
+ * is empty unless that call had opts->timing set and sync = 1; batched calls
  * and the SPG driver leave it as it was. */
 cqk_status cqk_last_pass_ms(cqk_ctx* ctx, float* ms, int32_t cap, int32_t* count);
 

@@ -304,7 +304,8 @@ def make_opts(lambda0=None, lambda0_user=0.0, max_iter=100, tol=0.0, compaction=
     o.accum = L.ACCUM[accum]
     o.sync = 1 if sync else 0
     o.trace = 1 if trace else 0
-    o.timing = 1 if timing else 0
+    # True: every pass kernel; 2: the first Newton pass and the x-writing pass
+    o.timing = int(timing) if not isinstance(timing, bool) else (1 if timing else 0)
     return o
 
 

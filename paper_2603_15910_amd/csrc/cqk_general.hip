@@ -1351,6 +1351,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // back; cqk_ctx_last_info reads the result later.  No per-pass timing then.
   const bool deferred = !o.sync || stream_capturing(s);
   const bool timing = o.timing && !deferred;
+  // timing 2: only the first Newton pass and the recovery carry events (the
+  // runtime leaves a few microseconds around every timed dispatch)
+  const bool timing_all = timing && o.timing != 2;
   // events 0, 1: the finalize of the last batch; then one pair per grid pass
   const size_t nev = (size_t)2 + 2 * (o.max_iter * 2 + 8);
   if (timing) {
@@ -1362,8 +1365,8 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   int ev = 2;
   int npass = 0;  // grid passes queued
   // a grid pass (timed when asked) followed by its one-block reduction
-  auto launch = [&](auto kern, auto reduce) {
-    const bool rec = timing && ev + 2 <= (int)nev;
+  auto launch = [&](auto kern, auto reduce, bool first_newton) {
+    const bool rec = (timing_all || (timing && first_newton)) && ev + 2 <= (int)nev;
     launch_timed(kern, dim3(G), dim3(kBlock), s, rec ? ctx->events[ev] : nullptr,
                  rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
@@ -1378,9 +1381,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, GF);
   };
   if (xw != nullptr)
-    launch(gen_warm_kernel<TIn>, gen_warm_update_kernel);
+    launch(gen_warm_kernel<TIn>, gen_warm_update_kernel, false);
   else if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
-    launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel);
+    launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel, false);
 
   // With compaction on large inputs, a bracket estimated from a sample lets
   // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
@@ -1388,11 +1391,11 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // (the second estimate's block records use the partials buffer)
   const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * S2_N;
   if (sampled) {
-    bool rec = timing && ev + 2 <= (int)nev;
+    bool rec = timing_all && ev + 2 <= (int)nev;
     launch_timed(gen_sample_kernel<TIn>, dim3(kSmpBlocks), dim3(kSmpThreads), s,
                  rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
-    rec = timing && ev + 2 <= (int)nev;
+    rec = timing_all && ev + 2 <= (int)nev;
     launch_timed(gen_sample2_kernel<TIn>, dim3(kS2Blocks), dim3(kS2Threads), s,
                  rec ? ctx->events[ev] : nullptr, rec ? ctx->events[ev + 1] : nullptr, A);
     if (rec) ev += 2;
@@ -1406,9 +1409,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // bracket it also compacts for it, else the lean kernel runs; every later
   // pass the general one
   auto pass = [&]() {
-    if (launched == 0 && sampled) launch(gen_spec_pass_kernel<TIn>, gen_update_kernel);
-    else if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel);
-    else launch(gen_pass_kernel<TIn>, gen_update_kernel);
+    if (launched == 0 && sampled) launch(gen_spec_pass_kernel<TIn>, gen_update_kernel, true);
+    else if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel, true);
+    else launch(gen_pass_kernel<TIn>, gen_update_kernel, false);
     ++launched;
   };
   if (deferred) {
