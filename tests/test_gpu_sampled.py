@@ -196,3 +196,49 @@ def test_sampled_bracket_with_infinite_bounds(ctx):
         assert info["status"] == 0, (compaction, info)
         check_cqk(x, inst, ref, 1e-10)
         _estimates(tr)
+
+
+def test_sampled_bracket_under_graph_capture(ctx):
+    """The two sample estimates and the first pass's set inside a captured
+    graph: every replay estimates again on the data then in the arrays (the
+    estimate's ticket and state are set by the solve's own first kernel), and
+    each replay's x is the oracle's."""
+    import paper_2603_15910_amd as cqk
+    n = 4_400_003
+    inst = W.cqk_uniform(n, 49)
+    inst2 = W.cqk_uniform(n, 50)
+    t = [torch.from_numpy(inst[k]).cuda() for k in "dablu"]
+    x = torch.empty_like(t[0])
+    c = cqk.Context(0)
+    try:
+        c.reserve(n, 0)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(graph, stream=s):
+                c.solve(*t, inst["r"], out=x, check=False, max_iter=12, trace=True)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+        for rep in range(3):
+            x.fill_(float("nan"))
+            torch.cuda.synchronize()
+            graph.replay()
+            st, info = c.ctx_last_info()
+            assert st == cqk.CQK_OK, info
+            check_cqk(x.cpu().numpy(), inst, ref, 1e-10)
+            _, s2 = _estimates(c.trace())
+            assert s2["compacted"] == 1 and s2["lo"] < ref.lam < s2["hi"], s2
+        # other a with the same r (r depends on b, l, u only)
+        t[1].copy_(torch.from_numpy(inst2["a"]))
+        graph.replay()
+        st, info = c.ctx_last_info()
+        assert st == cqk.CQK_OK, info
+        inst3 = dict(inst, a=inst2["a"])
+        ref3 = O.solve_cqk(*[inst3[k] for k in "dablu"], inst["r"])
+        check_cqk(x.cpu().numpy(), inst3, ref3, 1e-10)
+        _, s3 = _estimates(c.trace())
+        assert s3["lo"] < ref3.lam < s3["hi"], (s3, ref3.lam)
+    finally:
+        c.close()
