@@ -230,10 +230,33 @@ __device__ __forceinline__ void check_source_bkpt(GenState* st) {
   if (st->src != 0 && !(st->vlo <= st->lo && st->hi <= st->vhi)) to_caller_arrays(st);
 }
 
+// Sides the next evaluation (at st->lam) need not write.  One the sample's
+// estimate of lam* puts more than kSideSkip standard deviations on the far
+// side of lam* will not happen but for a wrong estimate (which then only
+// costs that pass's compaction).  One whose bracket covers more than
+// kSkipShare * theta of the source's bracket would keep more than theta of
+// a compacted source (its breakpoints taken as spread evenly over that
+// bracket) and be given up, after some of its writes.
+constexpr double kSideSkip = 4.0;
+constexpr double kSkipShare = 1.25;
+__device__ __forceinline__ void plan_sides(GenState* st) {
+  const double lam = st->lam, slam = st->slam, ssd = st->ssd;
+  int skip = ((lam > slam + kSideSkip * ssd) ? 1 : 0) | ((lam < slam - kSideSkip * ssd) ? 2 : 0);
+  const double vw = st->vhi - st->vlo;
+  if (st->src != 0 && vw > 0.0 && vw < inf_d()) {
+    const double clo = fmax(st->lo, st->vlo), chi = fmin(st->hi, st->vhi);
+    const double cap = kSkipShare * st->theta * vw;
+    skip |= ((chi - lam) > cap) ? 1 : 0;
+    skip |= ((lam - clo) > cap) ? 2 : 0;
+  }
+  st->skip = skip;
+}
+
 __device__ __forceinline__ void advance(GenState* st, double next) {
   st->lam_prev = st->lam;
   st->lam = next;
   st->mode = kModeEval;
+  if (st->compaction != CQK_COMPACT_OFF) plan_sides(st);
   if (st->iter >= st->max_iter) {
     st->status = CQK_NOT_CONVERGED;
     st->lam_final = st->lam_prev;

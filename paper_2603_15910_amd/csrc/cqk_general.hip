@@ -248,7 +248,7 @@ enum PassMode {
 template <typename Src, int MODE>
 __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t stride, double lam,
                           double lo, double hi, double theta, double* const* out, Pieces op,
-                          int32_t* const* out_cnt, Acc& acc, double* stg) {
+                          int32_t* const* out_cnt, Acc& acc, double* stg, int skip = 0) {
   constexpr bool COMPACT = MODE != kEvalOnly;
   constexpr int NSIDE = (MODE == kSampled) ? 1 : 2;
   constexpr int STG = (MODE == kSampled) ? kStageSpec : kStage;  // ring length
@@ -260,7 +260,9 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
   // per side: values written, ring head, values staged, given up
   int64_t written[2] = {0, 0};
   int head[2] = {0, 0}, pend[2] = {0, 0};
-  bool drop[2] = {false, MODE == kSampled};
+  // sides given up from the start: skip (bit k: side k), and side 1 of the
+  // sampled-bracket pass
+  bool drop[2] = {(skip & 1) != 0, MODE == kSampled || (skip & 2) != 0};
   int64_t seen = 0;  // indices read so far
   // `written` and `head` are multiples of kPiece at every full flush, so a
   // flush fills (the start of) one piece: a full one with 8 bytes per lane
@@ -419,6 +421,8 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   const double lam = st->lam, lo = st->lo, hi = st->hi, theta = st->theta;
   // the sides' brackets stay within the one the source's sums hold on
   const double clo = fmax(lo, st->vlo), chi = fmin(hi, st->vhi);
+  // sides not to write, chosen by the update before this pass (plan_sides)
+  const int skip = st->skip;
   // Passes over the caller's arrays hand tiles to waves grid-stride (tile t
   // to wave t mod NR), so all waves stream through neighbouring addresses;
   // wave rid keeps its survivors (at most `region`) in its pieces of a
@@ -458,7 +462,7 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
       bkpt_pass(s, A.n, first, stride, lam, ks);
     else if (compact)
       eval_pass<SrcOrig<TIn>, kTwoSides>(s, A.n, first, stride, lam, clo, chi, theta, out, pc,
-                                         oc, acc, stg);
+                                         oc, acc, stg, skip);
     else
       eval_pass<SrcOrig<TIn>, kEvalOnly>(s, A.n, first, stride, lam, lo, hi, theta, nullptr, pc,
                                          nullptr, acc, stg);
@@ -472,7 +476,8 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
     if (mode != kModeEval)
       bkpt_pass(s, count, 0, S, lam, ks);
     else if (compact)
-      eval_pass<SrcForm, kTwoSides>(s, count, 0, S, lam, clo, chi, theta, out, pc, oc, acc, stg);
+      eval_pass<SrcForm, kTwoSides>(s, count, 0, S, lam, clo, chi, theta, out, pc, oc, acc, stg,
+                                    skip);
     else
       eval_pass<SrcForm, kEvalOnly>(s, count, 0, S, lam, lo, hi, theta, nullptr, pc, nullptr,
                                     acc, stg);
@@ -931,6 +936,9 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
       share = st->s1share;
     }
     use = (p < q) && (share < 0.5 * theta);
+    st->slam = (p < q) ? lam : __builtin_nan("");
+    st->ssd = (p < q) ? ((sdl > 0.0 && !(lam == st->s1lam)) ? sdl : st->s1half / kSmpWidth)
+                      : __builtin_nan("");
     st->sp = use ? p : __builtin_nan("");
     st->sq = use ? q : __builtin_nan("");
     st->scap = use ? fmin(theta, 1.5 * share + 1.0 / 32.0) : 0.0;
@@ -1337,6 +1345,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.vlo = -__builtin_huge_val();
   init.vhi = __builtin_huge_val();
   init.sp = init.sq = __builtin_nan("");
+  init.slam = init.ssd = __builtin_nan("");
   init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
   init.max_iter = o.max_iter;

@@ -53,6 +53,8 @@ struct GenState {
   // the first estimate (solution, bracket half-width, share of the sample
   // inside), refined by the second
   double s1lam, s1half, s1share;
+  // the sample's estimate of lam* and its standard deviation (NaN: none)
+  double slam, ssd;
   int64_t n_src;                  // indices in the current source
   int64_t n_all;                  // indices of the caller's arrays
   int64_t n_free;                 // finalize: free indices
@@ -62,7 +64,7 @@ struct GenState {
   int32_t spec;                   // 1: the next evaluation writes the sampled-bracket set
   int32_t spend;                  // 1: that set waits in set 3
   int32_t s1ok;                   // 1: the first estimate found a bracket
-  int32_t pad_[1];
+  int32_t skip;                   // sides the next evaluation does not write (bit k: side k)
 };
 
 // Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).
