@@ -242,3 +242,28 @@ def test_sampled_bracket_under_graph_capture(ctx):
         assert s3["lo"] < ref3.lam < s3["hi"], (s3, ref3.lam)
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("name", ["breakpoint_step_right", "breakpoint_step_left"])
+def test_breakpoint_step_takes_the_waiting_set(ctx, golden, name):
+    """The hand-traced breakpoint examples tiled past 2^22 indices: the
+    sampled bracket around lam* holds no breakpoint (the set the first pass
+    writes is empty), the breakpoint search runs on the caller's arrays while
+    the set waits, and the Newton step after the breakpoint step lands in the
+    bracket and takes the set.  Algorithm 1's iterates are the hand-traced
+    ones, exactly."""
+    ex = next(e for e in golden["alg1_traces"] if e["name"] == name)
+    k = 1_400_003
+    inst = {c: np.tile(np.array([float(v) for v in ex[c]]), k) for c in "dablu"}
+    r = float(ex["r"]) * k
+    inst["r"] = r
+    ref = O.solve_cqk(*[inst[c] for c in "dablu"], r)
+    x, info, tr = _solve(ctx, inst, compaction="auto")
+    assert info["status"] == 0, info
+    np.testing.assert_array_equal(x, ref.x)
+    _, s = _estimates(tr)
+    assert s["compacted"] == 1 and s["lo"] < ex["lam"] < s["hi"], s
+    assert [t["lam"] for t in tr if t["kind"] in (1, 5)] == ex["lams"]
+    ev = _evals(tr)
+    assert ev[0]["n_out"] == 0, ev[0]
+    assert ev[-1]["source"] == 3 and ev[-1]["n_in"] == 0, ev[-1]
