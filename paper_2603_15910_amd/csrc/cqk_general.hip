@@ -144,6 +144,77 @@ struct SrcOrig {
   }
 };
 
+// The caller's arrays and a primal estimate xbar (warm start, end of
+// Section 2.1): loads like SrcOrig and adds each index to the warm start's
+// sums as it goes (wm, WS_* below): free in xbar (l < xbar < u) into the
+// free set J's sums, at or beyond a bound into the fixed sum; a NaN entry
+// of xbar counts nowhere.  xbar is compared with l and u as given.
+enum { WS_SJ = 0, WS_QJ, WS_FIX, WS_NJ, WS_SALL, WS_QALL, WS_N };
+template <typename TIn>
+struct SrcOrigWarm {
+  static constexpr int V = VecWidth<TIn>::value;
+  const TIn *d, *a, *b, *l, *u, *xw;
+  double* wm;  // WS_N sums of the calling thread
+  __device__ __forceinline__ void add(double vl, double vu, double vx, double c, double s,
+                                      double bl, double bu) const {
+    const bool fr = (vx > vl) && (vx < vu);
+    const bool at_l = !fr && (vx <= vl);
+    const bool at_u = !fr && (vx >= vu);
+    wm[WS_SJ] += fr ? c : 0.0;
+    wm[WS_QJ] += fr ? s : 0.0;
+    wm[WS_NJ] += fr ? 1.0 : 0.0;
+    wm[WS_FIX] += at_l ? bl : (at_u ? bu : 0.0);
+    wm[WS_SALL] += c;
+    wm[WS_QALL] += s;
+  }
+  __device__ __forceinline__ void load(int64_t i, int64_t n, double* c, double* s, double* bl,
+                                       double* bu, double& bad) const {
+    double vd[V], va[V], vb[V], vl[V], vu[V], vx[V];
+    Vec<TIn, V>::load(d, i, n, 1.0, vd);
+    Vec<TIn, V>::load(a, i, n, 0.0, va);
+    Vec<TIn, V>::load(b, i, n, 1.0, vb);
+    Vec<TIn, V>::load(l, i, n, 0.0, vl);
+    Vec<TIn, V>::load(u, i, n, 0.0, vu);
+    Vec<TIn, V>::load(xw, i, n, 0.0, vx);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      double tb = 0.0;
+      to_form(vd[k], va[k], vb[k], vl[k], vu[k], c[k], s[k], bl[k], bu[k], tb);
+      if (i + k < n) {
+        bad += tb;
+        add(vl[k], vu[k], vx[k], c[k], s[k], bl[k], bu[k]);
+      }
+    }
+  }
+  template <int U>
+  __device__ __forceinline__ void load_fast(int64_t base, int lane, double* c, double* s,
+                                            double* bl, double* bu, double& bad) const {
+    typename Raw16<TIn>::type rd[U], ra[U], rb[U], rl[U], ru[U], rx[U];
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+      const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
+      rd[w] = ld16(d + i);
+      ra[w] = ld16(a + i);
+      rb[w] = ld16(b + i);
+      rl[w] = ld16(l + i);
+      ru[w] = ld16(u + i);
+      rx[w] = ld16(xw + i);
+    }
+#pragma unroll
+    for (int w = 0; w < U; ++w) {
+#pragma unroll
+      for (int k = 0; k < V; ++k) {
+        const int e = w * V + k;
+        double tb = 0.0;
+        to_form((double)rd[w][k], (double)ra[w][k], (double)rb[w][k], (double)rl[w][k],
+                (double)ru[w][k], c[e], s[e], bl[e], bu[e], tb);
+        bad += tb;
+        add((double)rl[w][k], (double)ru[w][k], (double)rx[w][k], c[e], s[e], bl[e], bu[e]);
+      }
+    }
+  }
+};
+
 // A compacted set is stored in pieces of kPiece values: value j of wave rid
 // lives at piece_pos(j) of each plane, so piece k of every wave sits next to
 // piece k of the others.  Waves write and read their k-th pieces at about the
@@ -606,6 +677,95 @@ __global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
   if (threadIdx.x == 0) write_partial(A.partials, tot, NPART);
 }
 
+// The warm start's pass (end of Section 2.1) with the sampled bracket: the
+// sums of eq. (CQKlambda0) over the estimate's free set (SrcOrigWarm), and
+// the indices with a breakpoint in [sp, sq] written to set 3 as the first
+// Newton pass does without a warm start (gen_spec_pass_kernel), so that the
+// Newton pass at the warm lam_0 can already read that set.  The warm sums
+// travel in side 1's slots of the partial record (side 1 is not used).
+template <typename TIn>
+__global__ __launch_bounds__(kBlock) void gen_warm_spec_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const int rid = blockIdx.x * kWavesPerBlock + (int)(threadIdx.x / kWave);
+  const int64_t nr = (int64_t)gridDim.x * kWavesPerBlock;
+  const int64_t plane = nr * A.region;
+  const Pieces pc{rid, nr};
+  __shared__ double lds[NPART * (kBlock / kWave)];
+  __shared__ double tot[NPART];
+  __shared__ double stage[kWavesPerBlock * 4 * kStageSpec];
+  double* stg = stage + (threadIdx.x / kWave) * 4 * kStageSpec;
+  Acc acc;
+  acc_init(acc);
+  double wm[WS_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  SrcOrigWarm<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
+                     (const TIn*)A.u, (const TIn*)A.xw, wm};
+  constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrigWarm<TIn>::V;
+  const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
+  if (st->spec != 0) {
+    double* out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) out[j] = A.buf[kSpecSet - 1] + j * plane;
+    int32_t* oc[1] = {A.cnt[kSpecSet - 1] + rid};
+    eval_pass<SrcOrigWarm<TIn>, kSampled>(s, A.n, first, stride, 0.0, st->sp, st->sq, st->scap,
+                                          out, pc, oc, acc, stg);
+  } else {
+    eval_pass<SrcOrigWarm<TIn>, kEvalOnly>(s, A.n, first, stride, 0.0, 0.0, 0.0, 0.0, nullptr, pc,
+                                           nullptr, acc, stg);
+  }
+#pragma unroll
+  for (int j = 0; j < WS_N; ++j) acc.s[P_SIDE + D_N + j] = wm[j];
+  block_reduce<NSUM, 0, 0, kBlock>(acc.s, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, NPART);
+}
+static_assert(WS_N < D_DROP, "the warm sums fit side 1's slots below its drop count");
+
+// lam_0 of the warm start from gen_warm_spec_kernel's sums (as
+// gen_warm_update_kernel), the sampled-bracket set kept waiting in set 3,
+// and taken at once when lam_0 lies inside its bracket.
+__global__ __launch_bounds__(kRBlock) void gen_warm_spec_update_kernel(GenArgs A, int G) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  __shared__ double lds[NPART * (kRBlock / kWave)];
+  __shared__ double tot[NPART];
+  reduce_partials<NSUM, 0, 0, kRBlock>(A.partials, G, lds, tot);
+  if (threadIdx.x == 0) {
+    GenState sv = *st;
+    GenState* s = &sv;
+    const double* w = tot + P_SIDE + D_N;
+    const double nout = tot[P_SIDE + D_NOUT];
+    s->passes += 1;
+    s->bytes += (s->in_bytes * 6.0 / 5.0) * (double)A.n + 32.0 * nout;
+    if (tot[P_BAD] > 0.0) {
+      s->status = CQK_INVALID_ARG;
+    } else {
+      const double lam0 = (w[WS_NJ] > 0.0) ? (s->r - w[WS_FIX] - w[WS_SJ]) / w[WS_QJ]
+                                           : (s->r - w[WS_SALL]) / w[WS_QALL];
+      s->lam = lam0;
+      s->lam0 = lam0;
+      if (s->spec != 0 && tot[P_SIDE + D_DROP] == 0.0) {
+        s->sF = tot[P_SIDE + D_F];
+        s->sAF = tot[P_SIDE + D_AF];
+        s->sC0 = tot[P_SIDE + D_C0];
+        s->sC1 = tot[P_SIDE + D_C1];
+        s->sA0 = tot[P_SIDE + D_A0];
+        s->sA1 = tot[P_SIDE + D_A1];
+        s->sn = (int64_t)nout;
+        s->spend = 1;
+      }
+      s->spec = 0;
+      take_spec_set(s, lam0);
+      plan_sides(s);
+      // over the caller's arrays the first Newton pass has a one-sided
+      // bracket at best: neither side is written (as gen_first_pass_kernel)
+      if (s->src == 0) s->skip = 3;
+    }
+    trace_push(s, A.trace, 0, s->src != 0 ? 1 : 0, 0, s->lam, w[WS_SJ], w[WS_QJ], A.n,
+               (int64_t)w[WS_NJ]);
+    *st = sv;
+  }
+}
+
 // Bracket estimate from a sample (a GPU addition to the variable fixing of
 // Section 2.2, which lets the first pass compact; Algorithm 1 itself is
 // unchanged), in three kernels.
@@ -921,7 +1081,8 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
         const double lam1 = (sl0 > 0.0) ? st->lam - res0 / sl0 : __builtin_nan("");
         const double p1 = fmin(p, lam1 - kS2Lam1Width * sdl);
         const double q1 = fmax(q, lam1 + kS2Lam1Width * sdl);
-        if (q1 - p1 <= 4.0 * half) {
+        // (a warm start's lam_0 is not known yet: no first iterate)
+        if (st->warm == 0 && q1 - p1 <= 4.0 * half) {
           p = p1;
           q = q1;
         }
@@ -1346,6 +1507,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.vhi = __builtin_huge_val();
   init.sp = init.sq = __builtin_nan("");
   init.slam = init.ssd = __builtin_nan("");
+  init.warm = (xw != nullptr) ? 1 : 0;
   init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
   init.max_iter = o.max_iter;
@@ -1389,16 +1551,18 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
                  timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, GF);
   };
-  if (xw != nullptr)
-    launch(gen_warm_kernel<TIn>, gen_warm_update_kernel, false);
-  else if (o.lambda0_mode == CQK_LAMBDA0_FORMULA)
-    launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel, false);
-
   // With compaction on large inputs, a bracket estimated from a sample lets
   // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
-  // kSmpMinN the sample costs more than it saves.
+  // kSmpMinN the sample costs more than it saves.  A warm start then runs
+  // its pass after the sample and writes the sampled set itself
+  // (gen_warm_spec_kernel), and the first Newton pass is a general one.
   // (the second estimate's block records use the partials buffer)
   const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * S2_N;
+  const bool warm_spec = sampled && xw != nullptr;
+  if (xw != nullptr && !warm_spec)
+    launch(gen_warm_kernel<TIn>, gen_warm_update_kernel, false);
+  else if (xw == nullptr && o.lambda0_mode == CQK_LAMBDA0_FORMULA)
+    launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel, false);
   if (sampled) {
     bool rec = timing_all && ev + 2 <= (int)nev;
     launch_timed(gen_sample_kernel<TIn>, dim3(kSmpBlocks), dim3(kSmpThreads), s,
@@ -1411,6 +1575,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     hipLaunchKernelGGL(gen_sample2_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A);
     npass += 2;
   }
+  if (warm_spec) launch(gen_warm_spec_kernel<TIn>, gen_warm_spec_update_kernel, false);
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;
@@ -1418,7 +1583,8 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   // bracket it also compacts for it, else the lean kernel runs; every later
   // pass the general one
   auto pass = [&]() {
-    if (launched == 0 && sampled) launch(gen_spec_pass_kernel<TIn>, gen_update_kernel, true);
+    if (launched == 0 && warm_spec) launch(gen_pass_kernel<TIn>, gen_update_kernel, true);
+    else if (launched == 0 && sampled) launch(gen_spec_pass_kernel<TIn>, gen_update_kernel, true);
     else if (launched == 0) launch(gen_first_pass_kernel<TIn>, gen_update_kernel, true);
     else launch(gen_pass_kernel<TIn>, gen_update_kernel, false);
     ++launched;

@@ -267,3 +267,33 @@ def test_breakpoint_step_takes_the_waiting_set(ctx, golden, name):
     ev = _evals(tr)
     assert ev[0]["n_out"] == 0, ev[0]
     assert ev[-1]["source"] == 3 and ev[-1]["n_in"] == 0, ev[-1]
+
+
+@pytest.mark.parametrize("perturb", [0.0, 1e-3])
+def test_warm_start_writes_the_sampled_set(ctx, perturb):
+    """A warm start past 2^22 indices: the sample comes first, the warm
+    start's own pass writes the sampled set beside eq. (CQKlambda0)'s sums
+    over the estimate's free set, and the Newton pass at the warm lam_0 reads
+    that set.  x against the oracle, lam_0 against the oracle's warm start."""
+    import paper_2603_15910_amd as cqk  # noqa: F401
+    n = 4_300_007
+    inst = W.cqk_uniform(n, 51)
+    xbar = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"]).x
+    if perturb:
+        inst = dict(inst, a=inst["a"] + np.random.default_rng(52).uniform(-perturb, perturb, n))
+    ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+    t = [torch.from_numpy(np.asarray(inst[k])).cuda() for k in "dablu"]
+    xb = torch.from_numpy(xbar).cuda()
+    x, info = ctx.solve(*t, inst["r"], xbar=xb, check=False, trace=True)
+    assert info["status"] == 0, info
+    check_cqk(x.cpu().numpy(), inst, ref, 1e-10)
+    lam0_ref = O.cqk_lambda0_warm(*[inst[k] for k in "dablu"], inst["r"], xbar)
+    assert abs(info["lambda0"] - lam0_ref) <= 1e-10 * (1.0 + abs(lam0_ref)), \
+        (info["lambda0"], lam0_ref)
+    tr = ctx.trace()
+    assert [t_["kind"] for t_ in tr[:3]] == [8, 9, 0], tr[:3]
+    s = tr[1]
+    assert s["compacted"] == 1 and s["lo"] < lam0_ref < s["hi"], (s, lam0_ref)
+    assert tr[2]["compacted"] == 1, tr[2]
+    ev = _evals(tr)
+    assert ev[0]["source"] == 3 and 0 < ev[0]["n_in"] < 0.1 * n, ev[0]
