@@ -215,6 +215,36 @@ struct SrcOrigWarm {
   }
 };
 
+// The caller's arrays, adding every index to the sums of eq. (CQKlambda0)
+// over all indices as it loads them (wm[WS_SALL], wm[WS_QALL]).
+template <typename TIn>
+struct SrcOrigSum {
+  static constexpr int V = VecWidth<TIn>::value;
+  SrcOrig<TIn> o;
+  double* wm;
+  __device__ __forceinline__ void load(int64_t i, int64_t n, double* c, double* s, double* bl,
+                                       double* bu, double& bad) const {
+    o.load(i, n, c, s, bl, bu, bad);
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      if (i + k < n) {
+        wm[WS_SALL] += c[k];
+        wm[WS_QALL] += s[k];
+      }
+    }
+  }
+  template <int U>
+  __device__ __forceinline__ void load_fast(int64_t base, int lane, double* c, double* s,
+                                            double* bl, double* bu, double& bad) const {
+    o.template load_fast<U>(base, lane, c, s, bl, bu, bad);
+#pragma unroll
+    for (int e = 0; e < U * V; ++e) {
+      wm[WS_SALL] += c[e];
+      wm[WS_QALL] += s[e];
+    }
+  }
+};
+
 // A compacted set is stored in pieces of kPiece values: value j of wave rid
 // lives at piece_pos(j) of each plane, so piece k of every wave sits next to
 // piece k of the others.  Waves write and read their k-th pieces at about the
@@ -677,13 +707,14 @@ __global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
   if (threadIdx.x == 0) write_partial(A.partials, tot, NPART);
 }
 
-// The warm start's pass (end of Section 2.1) with the sampled bracket: the
-// sums of eq. (CQKlambda0) over the estimate's free set (SrcOrigWarm), and
-// the indices with a breakpoint in [sp, sq] written to set 3 as the first
-// Newton pass does without a warm start (gen_spec_pass_kernel), so that the
-// Newton pass at the warm lam_0 can already read that set.  The warm sums
-// travel in side 1's slots of the partial record (side 1 is not used).
-template <typename TIn>
+// The lam_0 pass with the sampled bracket: the sums of eq. (CQKlambda0) --
+// over a warm start's free set (WARM, end of Section 2.1, SrcOrigWarm) or
+// over all indices (SrcOrigSum) -- and the indices with a breakpoint in
+// [sp, sq] written to set 3 as the first Newton pass does without a lam_0
+// pass (gen_spec_pass_kernel), so that the Newton pass at lam_0 can already
+// read that set.  The sums travel in side 1's slots of the partial record
+// (side 1 is not used).
+template <typename TIn, bool WARM>
 __global__ __launch_bounds__(kBlock) void gen_warm_spec_kernel(GenArgs A) {
   GenState* st = A.st;
   if (st->status != kRunning) return;
@@ -698,20 +729,27 @@ __global__ __launch_bounds__(kBlock) void gen_warm_spec_kernel(GenArgs A) {
   Acc acc;
   acc_init(acc);
   double wm[WS_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-  SrcOrigWarm<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
-                     (const TIn*)A.u, (const TIn*)A.xw, wm};
-  constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrigWarm<TIn>::V;
+  using Src = typename std::conditional<WARM, SrcOrigWarm<TIn>, SrcOrigSum<TIn>>::type;
+  Src s;
+  if constexpr (WARM) {
+    s = Src{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l, (const TIn*)A.u,
+            (const TIn*)A.xw, wm};
+  } else {
+    s = Src{{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l, (const TIn*)A.u},
+            wm};
+  }
+  constexpr int64_t T = (int64_t)kWave * kUnroll * Src::V;
   const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
   if (st->spec != 0) {
     double* out[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) out[j] = A.buf[kSpecSet - 1] + j * plane;
     int32_t* oc[1] = {A.cnt[kSpecSet - 1] + rid};
-    eval_pass<SrcOrigWarm<TIn>, kSampled>(s, A.n, first, stride, 0.0, st->sp, st->sq, st->scap,
-                                          out, pc, oc, acc, stg);
+    eval_pass<Src, kSampled>(s, A.n, first, stride, 0.0, st->sp, st->sq, st->scap, out, pc, oc,
+                             acc, stg);
   } else {
-    eval_pass<SrcOrigWarm<TIn>, kEvalOnly>(s, A.n, first, stride, 0.0, 0.0, 0.0, 0.0, nullptr, pc,
-                                           nullptr, acc, stg);
+    eval_pass<Src, kEvalOnly>(s, A.n, first, stride, 0.0, 0.0, 0.0, 0.0, nullptr, pc, nullptr,
+                              acc, stg);
   }
 #pragma unroll
   for (int j = 0; j < WS_N; ++j) acc.s[P_SIDE + D_N + j] = wm[j];
@@ -720,9 +758,10 @@ __global__ __launch_bounds__(kBlock) void gen_warm_spec_kernel(GenArgs A) {
 }
 static_assert(WS_N < D_DROP, "the warm sums fit side 1's slots below its drop count");
 
-// lam_0 of the warm start from gen_warm_spec_kernel's sums (as
-// gen_warm_update_kernel), the sampled-bracket set kept waiting in set 3,
-// and taken at once when lam_0 lies inside its bracket.
+// lam_0 from gen_warm_spec_kernel's sums (as gen_warm_update_kernel, or
+// gen_lambda0_update_kernel without a warm start), the sampled-bracket set
+// kept waiting in set 3, and taken at once when lam_0 lies inside its
+// bracket.
 __global__ __launch_bounds__(kRBlock) void gen_warm_spec_update_kernel(GenArgs A, int G) {
   GenState* st = A.st;
   if (st->status != kRunning) return;
@@ -734,13 +773,16 @@ __global__ __launch_bounds__(kRBlock) void gen_warm_spec_update_kernel(GenArgs A
     GenState* s = &sv;
     const double* w = tot + P_SIDE + D_N;
     const double nout = tot[P_SIDE + D_NOUT];
+    const bool warm = s->warm != 0;
     s->passes += 1;
-    s->bytes += (s->in_bytes * 6.0 / 5.0) * (double)A.n + 32.0 * nout;
+    s->bytes += (warm ? s->in_bytes * 6.0 / 5.0 : s->in_bytes) * (double)A.n + 32.0 * nout;
     if (tot[P_BAD] > 0.0) {
       s->status = CQK_INVALID_ARG;
     } else {
-      const double lam0 = (w[WS_NJ] > 0.0) ? (s->r - w[WS_FIX] - w[WS_SJ]) / w[WS_QJ]
-                                           : (s->r - w[WS_SALL]) / w[WS_QALL];
+      const double lam0 =
+          (warm && w[WS_NJ] > 0.0) ? (s->r - w[WS_FIX] - w[WS_SJ]) / w[WS_QJ]
+          : (w[WS_QALL] > 0.0)     ? (s->r - w[WS_SALL]) / w[WS_QALL]
+                                   : 0.0;
       s->lam = lam0;
       s->lam0 = lam0;
       if (s->spec != 0 && tot[P_SIDE + D_DROP] == 0.0) {
@@ -760,8 +802,11 @@ __global__ __launch_bounds__(kRBlock) void gen_warm_spec_update_kernel(GenArgs A
       // bracket at best: neither side is written (as gen_first_pass_kernel)
       if (s->src == 0) s->skip = 3;
     }
-    trace_push(s, A.trace, 0, s->src != 0 ? 1 : 0, 0, s->lam, w[WS_SJ], w[WS_QJ], A.n,
-               (int64_t)w[WS_NJ]);
+    if (warm)
+      trace_push(s, A.trace, 0, s->src != 0 ? 1 : 0, 0, s->lam, w[WS_SJ], w[WS_QJ], A.n,
+                 (int64_t)w[WS_NJ]);
+    else
+      trace_push(s, A.trace, 0, s->src != 0 ? 1 : 0, 0, s->lam, w[WS_SALL], w[WS_QALL], A.n, 0);
     *st = sv;
   }
 }
@@ -805,7 +850,7 @@ constexpr int kS2Waves = kS2Threads / kWave;
 constexpr int kS2PerWave = 8;  // tiles per wave
 constexpr int kS2Blocks = 512;
 constexpr double kS2Lam1Width = 4.0;
-enum { S2_G = 0, S2_G2, S2_SF, S2_BAD, S2_G0, S2_QP0, S2_QM0, S2_N };
+enum { S2_G = 0, S2_G2, S2_SF, S2_BAD, S2_G0, S2_QP0, S2_QM0, S2_C, S2_S, S2_N };
 constexpr int kS2Tiles = kS2Blocks * kS2Waves * kS2PerWave;
 constexpr int64_t kS2M = (int64_t)kS2Tiles * kWave;    // second sample's size
 constexpr int64_t kSmpMinN = (int64_t)1 << 22;
@@ -1001,7 +1046,7 @@ __global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
   const bool ok1 = st->s1ok != 0;
   // at the first solution: sum g, sum g^2, sum of s over the free indices;
   // invalid entries; at lam_0: sum g and the one-sided slope sums
-  double v[S2_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double v[S2_N] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   if (ok1) {
     const double lam = st->s1lam, lam0 = st->lam;
     // n >= kSmpMinN: span >= 64, every tile inside [0, n)
@@ -1039,6 +1084,8 @@ __global__ __launch_bounds__(kS2Threads) void gen_sample2_kernel(GenArgs A) {
       v[S2_G0] += fin ? g0 : 0.0;
       v[S2_QP0] += (fin && f0 >= bl && f0 < bu) ? s : 0.0;
       v[S2_QM0] += (fin && f0 > bl && f0 <= bu) ? s : 0.0;
+      v[S2_C] += fin ? c : 0.0;
+      v[S2_S] += fin ? s : 0.0;
     }
   }
   __shared__ double lds[S2_N * kS2Waves];
@@ -1072,17 +1119,23 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
       if (half > 0.0 && half < inf_d() && fabs(lam - st->s1lam) < st->s1half) {
         p = lam - half;
         q = lam + half;
-        // Algorithm 1's first iterate, predicted from the sample: the
-        // bracket also takes it in (with kS2Lam1Width deviations of margin)
-        // when that at most doubles its width, so that the second pass
-        // already reads the set
-        const double res0 = all[S2_G0] - rs;
-        const double sl0 = (res0 < 0.0) ? all[S2_QP0] : all[S2_QM0];
-        const double lam1 = (sl0 > 0.0) ? st->lam - res0 / sl0 : __builtin_nan("");
+        // Algorithm 1's first point outside the sample's reach, predicted
+        // from the sample: the first iterate from a known lam_0, or the
+        // formula start's lam_0 itself (eq. (CQKlambda0) over the sample; a
+        // warm start's is not predicted).  The bracket also takes it in
+        // (with kS2Lam1Width deviations of margin) when that at most doubles
+        // its width, so that the pass at it already reads the set.
+        double lam1 = __builtin_nan("");
+        if (st->lam0_later == 0) {
+          const double res0 = all[S2_G0] - rs;
+          const double sl0 = (res0 < 0.0) ? all[S2_QP0] : all[S2_QM0];
+          if (sl0 > 0.0) lam1 = st->lam - res0 / sl0;
+        } else if (st->warm == 0 && all[S2_S] > 0.0) {
+          lam1 = (rs - all[S2_C]) / all[S2_S];
+        }
         const double p1 = fmin(p, lam1 - kS2Lam1Width * sdl);
         const double q1 = fmax(q, lam1 + kS2Lam1Width * sdl);
-        // (a warm start's lam_0 is not known yet: no first iterate)
-        if (st->warm == 0 && q1 - p1 <= 4.0 * half) {
+        if (q1 - p1 <= 4.0 * half) {
           p = p1;
           q = q1;
         }
@@ -1491,6 +1544,16 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   const bool is_f32 = sizeof(TIn) == 4;
   const double eps = (is_f32 && o.accum == CQK_ACCUM_F32) ? 1.1920928955078125e-07
                                                           : 2.220446049250313e-16;
+  // With compaction on large inputs, a bracket estimated from a sample lets
+  // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
+  // kSmpMinN the sample costs more than it saves.  A warm or formula start
+  // then runs its lam_0 pass after the sample and writes the sampled set
+  // itself (gen_warm_spec_kernel), and the first Newton pass is a general
+  // one.
+  // (the second estimate's block records use the partials buffer)
+  const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * S2_N;
+  const bool formula = xw == nullptr && o.lambda0_mode == CQK_LAMBDA0_FORMULA;
+  const bool warm_spec = sampled && (xw != nullptr || formula);
   GenState init{};
   init.lam = (o.lambda0_mode == CQK_LAMBDA0_USER && xw == nullptr) ? o.lambda0_user : 0.0;
   init.lam0 = init.lam;
@@ -1508,6 +1571,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.sp = init.sq = __builtin_nan("");
   init.slam = init.ssd = __builtin_nan("");
   init.warm = (xw != nullptr) ? 1 : 0;
+  init.lam0_later = warm_spec ? 1 : 0;
   init.in_bytes = 5.0 * sizeof(TIn);
   init.status = kRunning;
   init.max_iter = o.max_iter;
@@ -1551,17 +1615,9 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
                  timing ? ctx->events[0] : nullptr, timing ? ctx->events[1] : nullptr, A);
     hipLaunchKernelGGL(gen_finalize_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A, GF);
   };
-  // With compaction on large inputs, a bracket estimated from a sample lets
-  // the first pass compact (gen_sample_kernel, gen_sample2_kernel); below
-  // kSmpMinN the sample costs more than it saves.  A warm start then runs
-  // its pass after the sample and writes the sampled set itself
-  // (gen_warm_spec_kernel), and the first Newton pass is a general one.
-  // (the second estimate's block records use the partials buffer)
-  const bool sampled = compaction && n >= kSmpMinN && (int64_t)G * NPART >= (int64_t)kS2Blocks * S2_N;
-  const bool warm_spec = sampled && xw != nullptr;
   if (xw != nullptr && !warm_spec)
     launch(gen_warm_kernel<TIn>, gen_warm_update_kernel, false);
-  else if (xw == nullptr && o.lambda0_mode == CQK_LAMBDA0_FORMULA)
+  else if (formula && !warm_spec)
     launch(gen_lambda0_kernel<TIn>, gen_lambda0_update_kernel, false);
   if (sampled) {
     bool rec = timing_all && ev + 2 <= (int)nev;
@@ -1575,7 +1631,10 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     hipLaunchKernelGGL(gen_sample2_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A);
     npass += 2;
   }
-  if (warm_spec) launch(gen_warm_spec_kernel<TIn>, gen_warm_spec_update_kernel, false);
+  if (warm_spec && xw != nullptr)
+    launch(gen_warm_spec_kernel<TIn, true>, gen_warm_spec_update_kernel, false);
+  else if (warm_spec)
+    launch(gen_warm_spec_kernel<TIn, false>, gen_warm_spec_update_kernel, false);
   GenState* hs = (GenState*)ctx->host_pinned;
   int launched = 0;
   const int max_launch = 2 * o.max_iter + 4;

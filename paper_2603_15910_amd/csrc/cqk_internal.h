@@ -66,7 +66,7 @@ struct GenState {
   int32_t s1ok;                   // 1: the first estimate found a bracket
   int32_t skip;                   // sides the next evaluation does not write (bit k: side k)
   int32_t warm;                   // 1: lam_0 comes from a primal estimate
-  int32_t pad_[1];
+  int32_t lam0_later;             // 1: lam_0 is computed after the sample (warm or formula start)
 };
 
 // Run state of the simplex / l1 solver (Algorithm 4 on a compacted set).

@@ -110,12 +110,15 @@ def test_sampled_bracket_compacts_the_first_pass(ctx, gen, dtype):
     _same_iterates(ev, _evals(tr0))
 
 
-def _same_iterates(ev, ev0):
+def _same_iterates(ev, ev0, exact_first=True):
+    """exact_first: lam_0 is the same number on both runs (lam_0 = 0); a
+    formula start sums its terms in another order on the two paths."""
     lam_on = [t["lam"] for t in ev]
     lam_off = [t["lam"] for t in ev0]
     assert abs(len(lam_on) - len(lam_off)) <= 1, (lam_on, lam_off)
     k = min(len(lam_on), len(lam_off))
-    assert lam_on[0] == lam_off[0]
+    if exact_first:
+        assert lam_on[0] == lam_off[0]
     np.testing.assert_allclose(lam_on[:k], lam_off[:k], rtol=1e-9, atol=1e-12)
 
 
@@ -297,3 +300,27 @@ def test_warm_start_writes_the_sampled_set(ctx, perturb):
     assert tr[2]["compacted"] == 1, tr[2]
     ev = _evals(tr)
     assert ev[0]["source"] == 3 and 0 < ev[0]["n_in"] < 0.1 * n, ev[0]
+
+
+@pytest.mark.parametrize("gen", ["uniform", "correlated"])
+def test_formula_start_writes_the_sampled_set(ctx, gen):
+    """The eq. (CQKlambda0) start past 2^22 indices: its pass over all indices
+    also writes the sampled set; lam_0 is the formula's, x the oracle's, and
+    the Newton pass at lam_0 reads the set when lam_0 lies in its bracket."""
+    n = 4_300_007
+    inst = W.cqk_uniform(n, 53) if gen == "uniform" else W.cqk_correlated(n, 53)
+    ref = O.solve_cqk(*[inst[k] for k in "dablu"], inst["r"])
+    x, info, tr = _solve(ctx, inst, lambda0="formula")
+    assert info["status"] == 0, info
+    check_cqk(x, inst, ref, 1e-10)
+    lam0 = O.cqk_lambda0(*[inst[k] for k in "dablu"], inst["r"])
+    assert abs(info["lambda0"] - lam0) <= 1e-12 * (1.0 + abs(lam0)), (info["lambda0"], lam0)
+    assert [t["kind"] for t in tr[:3]] == [8, 9, 0], tr[:3]
+    s, ev = tr[1], _evals(tr)
+    if s["compacted"] == 1 and s["lo"] < info["lambda0"] < s["hi"]:
+        assert tr[2]["compacted"] == 1 and ev[0]["source"] == 3, (tr[2], ev[0])
+    else:
+        assert ev[0]["source"] == 0 and ev[0]["n_out"] == 0, ev[0]
+    # Algorithm 1's iterates are those of the same start without compaction
+    _, _, tr0 = _solve(ctx, inst, lambda0="formula", compaction="off")
+    _same_iterates(ev, _evals(tr0), exact_first=False)
