@@ -18,7 +18,9 @@
 //   gen_update_kernel   one block: reduces the records and runs the scalar
 //                       Algorithm 1 update on the device-resident state;
 //   gen_lambda0_kernel  eq. (CQKlambda0) over all indices, with input checks;
-//   gen_finalize_kernel x(lam*) over all n indices (eq. (xopt)), b^T x.
+//   gen_finalize_kernel x(lam*) over all n indices (eq. (xopt)), b^T x;
+//   gen_sample_kernel, gen_sample2_kernel (+ reduce), gen_spec_pass_kernel,
+//   gen_warm_spec_kernel: the sampled bracket (below).
 // The host queues passes in batches and reads the state once per batch;
 // a pass queued after the loop has stopped returns at once.
 //
@@ -41,8 +43,18 @@
 // happened.  A side that would keep more than theta of the indices a wave
 // reads is given up by that wave at once (before it writes), which makes the
 // side unusable for the pass and costs nothing more; sides that resolve
-// little are thus never written.  The first pass of a solve (one-sided
-// bracket) does not compact: gen_first_pass_kernel.
+// little are thus never written.  The first pass of a solve has a one-sided
+// bracket at best, which resolves little: without more it does not compact
+// (gen_first_pass_kernel).
+//
+// Sampled bracket (a GPU addition).  For large n two small kernels estimate
+// lam* from a sample with a bracket of a few standard deviations, and the
+// first pass (or the lam_0 pass of a warm or formula start) also writes the
+// indices with a breakpoint in that bracket to set 3.  Every compacted set
+// carries the bracket its dropped sums hold on (GenState vlo, vhi) and is
+// read only at a multiplier strictly inside it, so Algorithm 1's iterates do
+// not depend on the estimate; the sampled set waits in set 3 until an
+// iterate falls inside (take_spec_set).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
