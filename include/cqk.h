@@ -95,14 +95,20 @@ typedef enum cqk_compaction {
                                as soon as it would keep more than
                                compact_theta of the indices read; the next
                                pass reads the set of the side that happened.
-                               For n >= 2^22 a bracket estimated from a
-                               sample of 16384 indices (the solution of the
-                               sampled equation +- 5 estimated standard
-                               deviations) lets the first pass compact too;
-                               a set is read only at multipliers strictly
-                               inside the bracket its sums hold on, the
-                               caller's arrays otherwise, so Algorithm 1's
-                               iterates do not depend on the estimate.
+                               For n >= 2^22 a bracket estimated from two
+                               samples (4096 and 1048576 indices: the
+                               solution of the sampled equation +- 5
+                               estimated standard deviations, widened to
+                               the first iterate the sample predicts) lets
+                               the first pass, or the lam_0 pass of a warm
+                               or formula start, compact too; a set is read
+                               only at multipliers strictly inside the
+                               bracket its sums hold on, the caller's
+                               arrays otherwise, so Algorithm 1's iterates
+                               do not depend on the estimate.  Sides an
+                               evaluation will not use (by the estimate, or
+                               by their share of the set's bracket) are not
+                               written.
                                Simplex / l1: compact on y + lam <= 0 */
   CQK_COMPACT_ALWAYS = 2    /* as AUTO with compact_theta = 1 (every side kept) */
 } cqk_compaction;
@@ -163,16 +169,18 @@ typedef struct cqk_trace_rec {
                                5 breakpoint step, 6 bisection (the secant
                                point rounded onto a bracket end), 7 one
                                thread's Algorithm 2 (simplex / l1 start, see
-                               below), 8 sampled bracket (general CQK, see
+                               below), 8 and 9 the first and second
+                               sampled-bracket estimates (general CQK, see
                                CQK_COMPACT_AUTO).  For kinds 3, 4 and 6, lam
                                is the next iterate, phi and slope those it
-                               was taken from.  Kind 8: lam solves the
-                               sampled equation, lo/hi the bracket (NaN when
-                               none), phi the estimated standard deviation
-                               of lam, slope the share of the sample with a
-                               breakpoint in the bracket, compacted 1 when
-                               the first pass compacts for it, n_in the
-                               sample size, n_out the survivors predicted. */
+                               was taken from.  Kinds 8 and 9: lam solves
+                               the sampled equation, lo/hi the bracket (NaN
+                               when none), phi the estimated standard
+                               deviation of lam, slope the share of the
+                               sample with a breakpoint in the bracket,
+                               compacted (kind 9) 1 when the first pass
+                               compacts for it, n_in the sample size, n_out
+                               the survivors predicted. */
   int32_t compacted;        /* 1 if the next pass reads a compacted set this
                                pass adopted (written by this pass, or the
                                sampled-bracket set the first pass wrote) */
