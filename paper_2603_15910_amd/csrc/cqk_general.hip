@@ -1120,7 +1120,7 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
     const double theta = st->theta;
     const double rs = st->r * (m / (double)A.n);
     double lam = __builtin_nan(""), p = __builtin_nan(""), q = __builtin_nan("");
-    double sdl = 0.0, share = 1.0;
+    double sdl = 0.0, share = 1.0, lam1_pred = __builtin_nan("");
     bool use = false;
     if (ok1 && all[S2_BAD] == 0.0 && all[S2_SF] > 0.0) {
       lam = st->s1lam - (all[S2_G] - rs) / all[S2_SF];
@@ -1145,6 +1145,7 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
         } else if (st->warm == 0 && all[S2_S] > 0.0) {
           lam1 = (rs - all[S2_C]) / all[S2_S];
         }
+        lam1_pred = lam1;
         const double p1 = fmin(p, lam1 - kS2Lam1Width * sdl);
         const double q1 = fmax(q, lam1 + kS2Lam1Width * sdl);
         if (q1 - p1 <= 4.0 * half) {
@@ -1169,6 +1170,12 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
     st->sq = use ? q : __builtin_nan("");
     st->scap = use ? fmin(theta, 1.5 * share + 1.0 / 32.0) : 0.0;
     st->spec = use ? 1 : 0;
+    // a predicted first iterate of a known lam_0 left outside: the third
+    // estimate looks at the second
+    st->s2lam1 = (use && st->lam0_later == 0 && __builtin_isfinite(lam1_pred) &&
+                  !(lam1_pred > p && lam1_pred < q))
+                     ? lam1_pred
+                     : __builtin_nan("");
     st->passes += 1;
     st->bytes += st->in_bytes * m;
     if (st->ntrace < st->trace_cap) {
@@ -1186,6 +1193,108 @@ __global__ __launch_bounds__(kRBlock) void gen_sample2_reduce_kernel(GenArgs A) 
       t.n_out = (int64_t)(share * (double)A.n);
     }
     st->ntrace += 1;
+  }
+}
+
+// Third estimate: when Newton's first step from lam_0 lands outside the
+// bracket (the sample predicts lam_1 far from lam*), the pass at lam_1 reads
+// the caller's arrays, and so would the pass at lam_2 if that too lay
+// outside.  gen_sample3_kernel evaluates the sampled phi and its one-sided
+// slopes at the predicted lam_1 (kS3Tiles tiles, FP64, per-block sums);
+// gen_sample3_reduce_kernel takes the Newton step from it and widens the
+// bracket to the predicted lam_2 (+- kS3Width deviations) when that keeps
+// it within kS3MaxWiden times the width of the bracket around lam* and the
+// share allowed.  Both return at once when there is nothing to predict.
+constexpr int kS3Blocks = 256;
+constexpr int kS3Threads = 256;
+constexpr int kS3Waves = kS3Threads / kWave;
+constexpr int kS3PerWave = 4;
+constexpr int kS3Tiles = kS3Blocks * kS3Waves * kS3PerWave;
+constexpr int64_t kS3M = (int64_t)kS3Tiles * kWave;
+constexpr double kS3Width = 6.0;
+constexpr double kS3MaxWiden = 6.0;
+static_assert(kSmpMinN >= (int64_t)kS3Tiles * kWave, "every sampled tile lies inside the arrays");
+enum { S3_G = 0, S3_QP, S3_QM, S3_BAD, S3_N };
+
+template <typename TIn>
+__global__ __launch_bounds__(kS3Threads) void gen_sample3_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const double mu = st->s2lam1;
+  if (!__builtin_isfinite(mu)) return;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int64_t span = A.n / kS3Tiles;  // n >= kSmpMinN: span >= 64
+  const TIn* d = (const TIn*)A.d;
+  const TIn* a = (const TIn*)A.a;
+  const TIn* b = (const TIn*)A.b;
+  const TIn* l = (const TIn*)A.l;
+  const TIn* u = (const TIn*)A.u;
+  TIn vd[kS3PerWave], va[kS3PerWave], vb[kS3PerWave], vl[kS3PerWave], vu[kS3PerWave];
+#pragma unroll
+  for (int k = 0; k < kS3PerWave; ++k) {
+    const int j = (k * kS3Blocks + (int)blockIdx.x) * kS3Waves + w;
+    const int64_t i = (int64_t)j * span + lane;
+    vd[k] = d[i];
+    va[k] = a[i];
+    vb[k] = b[i];
+    vl[k] = l[i];
+    vu[k] = u[i];
+  }
+  double v[S3_N] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < kS3PerWave; ++k) {
+    double c, s, bl, bu, bad = 0.0;
+    to_form((double)vd[k], (double)va[k], (double)vb[k], (double)vl[k], (double)vu[k], c, s, bl,
+            bu, bad);
+    const double f = fma(s, mu, c);
+    const double g = fmin(fmax(f, bl), bu);
+    const bool fin = __builtin_isfinite(g) && __builtin_isfinite(s);
+    v[S3_G] += fin ? g : 0.0;
+    v[S3_QP] += (fin && f >= bl && f < bu) ? s : 0.0;
+    v[S3_QM] += (fin && f > bl && f <= bu) ? s : 0.0;
+    v[S3_BAD] += (bad == 0.0 && fin) ? 0.0 : 1.0;
+  }
+  __shared__ double lds[S3_N * kS3Waves];
+  __shared__ double tot[S3_N];
+  block_reduce<S3_N, 0, 0, kS3Threads>(v, nullptr, nullptr, lds, tot);
+  if (threadIdx.x == 0) write_partial(A.partials, tot, S3_N);
+}
+
+__global__ __launch_bounds__(kRBlock) void gen_sample3_reduce_kernel(GenArgs A) {
+  GenState* st = A.st;
+  if (st->status != kRunning) return;
+  const double mu = st->s2lam1;
+  if (!__builtin_isfinite(mu)) return;
+  __shared__ double rl[S3_N * (kRBlock / kWave)];
+  __shared__ double all[S3_N];
+  reduce_partials<S3_N, 0, 0, kRBlock>(A.partials, kS3Blocks, rl, all);
+  if (threadIdx.x == 0) {
+    const double m = (double)kS3M;
+    const double res = all[S3_G] - st->r * (m / (double)A.n);
+    const double sl = (res < 0.0) ? all[S3_QP] : all[S3_QM];
+    const double p = st->sp, q = st->sq, ssd = st->ssd;
+    if (all[S3_BAD] == 0.0 && sl > 0.0 && p < q) {
+      const double lam2 = mu - res / sl;
+      const double p2 = fmin(p, lam2 - kS3Width * ssd);
+      const double q2 = fmax(q, lam2 + kS3Width * ssd);
+      const double base = 2.0 * kSmpWidth * ssd;
+      const double share = st->s1share * ((q2 - p2) / (2.0 * st->s1half));
+      if (q2 - p2 <= kS3MaxWiden * base && share < 0.5 * st->theta) {
+        st->sp = p2;
+        st->sq = q2;
+        st->scap = fmin(st->theta, 1.5 * share + 1.0 / 32.0);
+        // the second estimate's trace record shows the bracket used
+        const int ti = st->ntrace - 1;
+        if (ti >= 0 && ti < st->trace_cap && A.trace[ti].kind == 9) {
+          A.trace[ti].lo = p2;
+          A.trace[ti].hi = q2;
+          A.trace[ti].slope = share;
+          A.trace[ti].n_out = (int64_t)(share * (double)A.n);
+        }
+      }
+    }
+    st->bytes += st->in_bytes * m;
   }
 }
 
@@ -1581,7 +1690,7 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
   init.vlo = -__builtin_huge_val();
   init.vhi = __builtin_huge_val();
   init.sp = init.sq = __builtin_nan("");
-  init.slam = init.ssd = __builtin_nan("");
+  init.slam = init.ssd = init.s2lam1 = __builtin_nan("");
   init.warm = (xw != nullptr) ? 1 : 0;
   init.lam0_later = warm_spec ? 1 : 0;
   init.in_bytes = 5.0 * sizeof(TIn);
@@ -1642,6 +1751,10 @@ cqk_status run_general(cqk_ctx* ctx, int64_t n, const TIn* d, const TIn* a, cons
     if (rec) ev += 2;
     hipLaunchKernelGGL(gen_sample2_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A);
     npass += 2;
+    if (!warm_spec) {
+      hipLaunchKernelGGL(gen_sample3_kernel<TIn>, dim3(kS3Blocks), dim3(kS3Threads), 0, s, A);
+      hipLaunchKernelGGL(gen_sample3_reduce_kernel, dim3(1), dim3(kRBlock), 0, s, A);
+    }
   }
   if (warm_spec && xw != nullptr)
     launch(gen_warm_spec_kernel<TIn, true>, gen_warm_spec_update_kernel, false);

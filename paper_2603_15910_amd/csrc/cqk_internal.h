@@ -55,6 +55,10 @@ struct GenState {
   double s1lam, s1half, s1share;
   // the sample's estimate of lam* and its standard deviation (NaN: none)
   double slam, ssd;
+  // Algorithm 1's first iterate as the sample predicts it, when it lies
+  // outside the bracket (NaN otherwise): the third estimate predicts the
+  // second iterate from it
+  double s2lam1;
   int64_t n_src;                  // indices in the current source
   int64_t n_all;                  // indices of the caller's arrays
   int64_t n_free;                 // finalize: free indices
