@@ -99,7 +99,9 @@ typedef enum cqk_compaction {
                                samples (4096 and 1048576 indices: the
                                solution of the sampled equation +- 5
                                estimated standard deviations, widened to
-                               the first iterate the sample predicts) lets
+                               the first iterate the sample predicts, or
+                               to the second when the first lies far out)
+                               lets
                                the first pass, or the lam_0 pass of a warm
                                or formula start, compact too; a set is read
                                only at multipliers strictly inside the

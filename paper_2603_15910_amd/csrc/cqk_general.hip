@@ -19,7 +19,8 @@
 //                       Algorithm 1 update on the device-resident state;
 //   gen_lambda0_kernel  eq. (CQKlambda0) over all indices, with input checks;
 //   gen_finalize_kernel x(lam*) over all n indices (eq. (xopt)), b^T x;
-//   gen_sample_kernel, gen_sample2_kernel (+ reduce), gen_spec_pass_kernel,
+//   gen_sample_kernel, gen_sample2_kernel, gen_sample3_kernel (+ reduces),
+//   gen_spec_pass_kernel,
 //   gen_warm_spec_kernel: the sampled bracket (below).
 // The host queues passes in batches and reads the state once per batch;
 // a pass queued after the loop has stopped returns at once.
