@@ -72,6 +72,10 @@ constexpr int kBlock = 256;
 constexpr int kRBlock = 1024;  // one-block reductions of partial records
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kUnroll = 2;
+// values per lane in one tile of a pass: kUnroll 16-byte vectors of FP64,
+// or half as many vectors of FP32, so both element types hold as many
+// values in registers
+constexpr int kTileE = kUnroll * 2;
 constexpr int kPair = 2;  // adjacent tiles a wave reads per step of a pass over the caller's arrays
 // the general pass kernel reads a step's tiles one after the other (its
 // compaction state leaves no registers for both tiles' loads at once)
@@ -368,7 +372,8 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
   constexpr int STG = (MODE == kSampled) ? kStageSpec : kStage;  // ring length
   constexpr int FP = (MODE == kSampled) ? kSpecFlush : 1;        // pieces per flush
   constexpr int V = Src::V;
-  constexpr int E = kUnroll * V;
+  constexpr int U = kTileE / V;  // 16-byte vectors per lane and array
+  constexpr int E = kTileE;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
   // per side: values written, ring head, values staged, given up
@@ -403,16 +408,16 @@ __device__ void eval_pass(const Src& src, int64_t count, int64_t first, int64_t 
     constexpr bool FULL = decltype(full_tag)::value;
     double c[E], s[E], bl[E], bu[E];
     if (FULL) {
-      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
+      src.template load_fast<U>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
     } else {
 #pragma unroll
-      for (int w = 0; w < kUnroll; ++w) {
+      for (int w = 0; w < U; ++w) {
         const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
         src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
       }
     }
 #pragma unroll
-    for (int w = 0; w < kUnroll; ++w) {
+    for (int w = 0; w < U; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
 #pragma unroll
       for (int k = 0; k < V; ++k) {
@@ -492,7 +497,8 @@ template <typename Src>
 __device__ void bkpt_pass(const Src& src, int64_t count, int64_t first, int64_t stride, double lam,
                           KeySum* ks) {
   constexpr int V = Src::V;
-  constexpr int E = kUnroll * V;
+  constexpr int U = kTileE / V;  // 16-byte vectors per lane and array
+  constexpr int E = kTileE;
   constexpr int64_t TILE = (int64_t)kWave * E;
   const int lane = threadIdx.x & (kWave - 1);
   auto tile = [&](int64_t base, auto full_tag) {
@@ -500,16 +506,16 @@ __device__ void bkpt_pass(const Src& src, int64_t count, int64_t first, int64_t 
     double c[E], s[E], bl[E], bu[E];
     double dummy = 0.0;
     if (FULL) {
-      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, dummy);
+      src.template load_fast<U>(base, lane, c, s, bl, bu, dummy);
     } else {
 #pragma unroll
-      for (int w = 0; w < kUnroll; ++w) {
+      for (int w = 0; w < U; ++w) {
         const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
         src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], dummy);
       }
     }
 #pragma unroll
-    for (int w = 0; w < kUnroll; ++w) {
+    for (int w = 0; w < U; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
 #pragma unroll
       for (int k = 0; k < V; ++k) {
@@ -570,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   if (src == 0) {
     SrcOrig<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
                    (const TIn*)A.u};
-    constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrig<TIn>::V;
+    constexpr int64_t T = (int64_t)kWave * kTileE;
     const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
     if (mode != kModeEval)
       bkpt_pass(s, A.n, first, stride, lam, ks);
@@ -583,7 +589,7 @@ __global__ __launch_bounds__(kBlock) void gen_pass_kernel(GenArgs A) {
   } else {
     const double* sb = A.buf[src - 1];
     SrcForm s{sb, sb + plane, sb + 2 * plane, sb + 3 * plane, pc};
-    constexpr int64_t T = (int64_t)kWave * kUnroll * SrcForm::V;
+    constexpr int64_t T = (int64_t)kWave * kTileE;
     const int64_t count = A.cnt[src - 1][rid];
     // the wave's own region, front to back
     constexpr int64_t S = kPair * T;
@@ -629,7 +635,8 @@ __global__ __launch_bounds__(kBlock) void gen_first_pass_kernel(GenArgs A) {
   SrcOrig<TIn> src{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
                    (const TIn*)A.u};
   constexpr int V = SrcOrig<TIn>::V;
-  constexpr int E = kUnroll * V;
+  constexpr int U = kTileE / V;  // 16-byte vectors per lane and array
+  constexpr int E = kTileE;
   constexpr int64_t T = (int64_t)kWave * E;
   const int64_t count = A.n;
   Acc acc;
@@ -639,16 +646,16 @@ __global__ __launch_bounds__(kBlock) void gen_first_pass_kernel(GenArgs A) {
     constexpr bool FULL = decltype(full_tag)::value;
     double c[E], s[E], bl[E], bu[E];
     if (FULL) {
-      src.template load_fast<kUnroll>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
+      src.template load_fast<U>(base, lane, c, s, bl, bu, acc.s[P_BAD]);
     } else {
 #pragma unroll
-      for (int w = 0; w < kUnroll; ++w) {
+      for (int w = 0; w < U; ++w) {
         const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
         src.load(i, count, &c[w * V], &s[w * V], &bl[w * V], &bu[w * V], acc.s[P_BAD]);
       }
     }
 #pragma unroll
-    for (int w = 0; w < kUnroll; ++w) {
+    for (int w = 0; w < U; ++w) {
       const int64_t i = base + (int64_t)w * kWave * V + (int64_t)lane * V;
 #pragma unroll
       for (int k = 0; k < V; ++k) {
@@ -702,7 +709,7 @@ __global__ __launch_bounds__(kBlock) void gen_spec_pass_kernel(GenArgs A) {
   acc_init(acc);
   SrcOrig<TIn> s{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l,
                  (const TIn*)A.u};
-  constexpr int64_t T = (int64_t)kWave * kUnroll * SrcOrig<TIn>::V;
+  constexpr int64_t T = (int64_t)kWave * kTileE;
   const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
   const double lam = st->lam;
   if (st->spec != 0) {
@@ -751,7 +758,7 @@ __global__ __launch_bounds__(kBlock) void gen_warm_spec_kernel(GenArgs A) {
     s = Src{{(const TIn*)A.d, (const TIn*)A.a, (const TIn*)A.b, (const TIn*)A.l, (const TIn*)A.u},
             wm};
   }
-  constexpr int64_t T = (int64_t)kWave * kUnroll * Src::V;
+  constexpr int64_t T = (int64_t)kWave * kTileE;
   const int64_t first = (int64_t)rid * kPair * T, stride = nr * kPair * T;
   if (st->spec != 0) {
     double* out[4];
@@ -1578,8 +1585,7 @@ int choose_grid(int64_t n, int num_cus) {
 }  // namespace
 
 // G blocks of kWavesPerBlock waves.  A pass over the caller's arrays hands
-// its steps (kPair adjacent tiles of 64 lanes x kUnroll vectors of `vec`
-// values) to the NR waves grid-stride, at most `tpw` steps each (chunk = tpw
+// its steps (kPair adjacent tiles of 64 lanes x kTileE values) to the NR waves grid-stride, at most `tpw` steps each (chunk = tpw
 // steps).  A wave keeps at most theta * chunk + kSpecFlush * kPiece survivors
 // of a side (eval_pass), so its region in a compacted set holds that many values,
 // rounded up to whole pieces.  The primal recovery runs grid-stride on its
@@ -1588,7 +1594,7 @@ int choose_grid(int64_t n, int num_cus) {
 // (4 planes of NR x region doubles each).
 GenLayout gen_layout(int64_t n, int num_cus, int vec, bool compaction, double theta) {
   GenLayout L{};
-  const int64_t T = (int64_t)kWave * kUnroll * vec * kPair;
+  const int64_t T = (int64_t)kWave * kTileE * kPair;
   const int G0 = choose_grid(n, num_cus);
   const int64_t ntiles = (n + T - 1) / T;
   const int64_t tpw = std::max<int64_t>(
