@@ -300,6 +300,22 @@ def extra_correlated(ctx, dev, torch):
         "pass_gbs": info["pass_bytes"] / (info["pass_ms"] * 1e-3) / 1e9}
     del t, x
     torch.cuda.empty_cache()
+    # FP32 arrays (FP64 arithmetic), both generators, lambda_0 = 0
+    for gen in ("uniform", "correlated"):
+        inst = W.cqk_uniform(100_000_000, 1) if gen == "uniform" else \
+            W.cqk_correlated(100_000_000, 1)
+        t = [torch.from_numpy(inst[k].astype(np.float32)).to(dev) for k in "dablu"]
+        r = float(inst["r"])
+        del inst
+        x = torch.empty_like(t[0])
+        ctx.solve(*t, r, out=x)
+        ms = timed(lambda: ctx.solve(*t, r, out=x), 5, sync)
+        _, info = ctx.solve(*t, r, out=x)
+        ex[f"cqk_{gen}_1e8_f32in"] = {
+            "ms": ms, "elements_per_s": 1e8 / (ms * 1e-3), "iterations": info["iterations"],
+            "status": info["status_name"]}
+        del t, x
+        torch.cuda.empty_cache()
     return ex
 
 
